@@ -1,0 +1,204 @@
+"""Benchmark: dipole-field evaluations per second of the Cartesian FMM on one GPU.
+
+Workload (default): ferrofluid of 1,048,576 hard-core dipoles (random
+sequential addition, volume fraction 0.1, seed 2001), unit moments in random
+directions (seed 2002), order p = 6, opening angle 0.5, s = s_o(6) = 26.64
+dipoles per smallest cell, mixed precision (FP32 bulk arithmetic on MFMA/VALU,
+FP64 derivative tensors and final per-dipole sums).
+
+A step is one pass of the whole method over one configuration with the
+positions and moments already in HBM: tree and lists rebuilt in place for the
+(possibly moved) dipoles, derivative tensors, P2M, M2M, M2L, L2L, L2P and the
+near-field sum.  `value` = dipoles / step time.  The same run also reports the
+evaluation alone (tree reused), the plain FP64 GPU FMM, the error of the mixed
+result against the FP64 GPU FMM (eps_prec) and against the direct sum at
+sampled dipoles (eps_abs), the roofline of the dominant kernel, and the CPU
+oracle timed on a bounded sample of the same recipe.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--skip-cpu] [--skip-fp64]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dipole-field evals/s at ≤1e-5 rel RMS err: mixed/learned FMM vs plain FP64"
+PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
+PEAK_FP64_MFMA = 78.6e12
+PEAK_FP32_VALU = 157.3e12   # published vector FP32 (packed); see the design notes
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--order", type=int, default=6)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--samples", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (no multi-GPU path); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_0810_0233_amd import ccfmm, inputs
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    t0 = time.time()
+    pos, box = inputs.ferrofluid(n, 2001)
+    m = inputs.random_moments(n, 2002)
+    log("inputs: ferrofluid n=%d side=%.3f (%.1f s)" % (n, box[1][0], time.time() - t0))
+    d_pos = torch.from_numpy(pos).to(dev)
+    d_m = torch.from_numpy(m).to(dev)
+    d_H = torch.empty_like(d_m)
+    d_H64 = torch.empty_like(d_m)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    def make(prec):
+        prm = ccfmm.params(order=args.order, theta=args.theta, leaf_target=0.0, box=box, precision=prec,
+                           max_batch=1)
+        return ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, sh)
+
+    def time_steps(plan, out, rebuild, steps, warmup):
+        for _ in range(warmup):
+            if rebuild:
+                plan.update_positions_device(d_pos.data_ptr(), sh)
+            plan.eval_device(1, d_m.data_ptr(), out.data_ptr(), sh)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            if rebuild:
+                plan.update_positions_device(d_pos.data_ptr(), sh)
+            plan.eval_device(1, d_m.data_ptr(), out.data_ptr(), sh)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    # ---- mixed precision: the headline path
+    plan = make(ccfmm.PREC_MIXED)
+    info = plan.info()
+    log("plan: L=%d leaves=%d m2l_pairs=%d p2p_pairs=%d tiles=%d steps=%d" % (
+        info["levels"], info["n_leaves"], info["n_m2l_pairs"], info["n_p2p_pairs"], info["n_m2l_tiles"],
+        info["n_m2l_steps"]))
+    t_step = time_steps(plan, d_H, True, args.steps, args.warmup)
+    log("mixed full step: %.3f ms" % (1e3 * t_step))
+    t_eval = time_steps(plan, d_H, False, args.steps, args.warmup)
+    log("mixed eval only: %.3f ms" % (1e3 * t_eval))
+    passes = [plan.eval_device_timed(1, d_m.data_ptr(), d_H.data_ptr(), sh) for _ in range(3)]
+    pt = {k: float(np.median([p[k] for p in passes])) for k in passes[0]}
+    log("mixed passes (ms): %s" % json.dumps({k: round(v, 4) for k, v in pt.items()}))
+    torch.cuda.synchronize()
+    H_mixed = d_H.cpu().numpy().copy()
+
+    out = {}
+    # ---- plain FP64 GPU FMM
+    if not args.skip_fp64:
+        plan64 = make(ccfmm.PREC_FP64)
+        t_step64 = time_steps(plan64, d_H64, True, max(2, args.steps // 2), 1)
+        t_eval64 = time_steps(plan64, d_H64, False, max(2, args.steps // 2), 1)
+        passes64 = plan64.eval_device_timed(1, d_m.data_ptr(), d_H64.data_ptr(), sh)
+        torch.cuda.synchronize()
+        H64 = d_H64.cpu().numpy().copy()
+        out["fp64_full_step_ms"] = 1e3 * t_step64
+        out["fp64_eval_ms"] = 1e3 * t_eval64
+        out["fp64_passes_ms"] = passes64
+        out["speedup_vs_fp64_step"] = t_step64 / t_step
+        out["speedup_vs_fp64_eval"] = t_eval64 / t_eval
+        out["eps_prec"] = rel_rms(H_mixed, H64)
+        log("fp64 step %.3f ms eval %.3f ms; eps_prec %.3e" % (1e3 * t_step64, 1e3 * t_eval64, out["eps_prec"]))
+        plan64.destroy()
+    # ---- error against the direct sum at sampled dipoles (FP64 on the GPU)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(n, size=min(args.samples, n), replace=False)).astype(np.int64)
+    d_idx = torch.from_numpy(idx).to(dev)
+    d_Hd = torch.empty((idx.size, 3), dtype=torch.float64, device=dev)
+    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m.data_ptr(), idx.size, d_idx.data_ptr(), d_Hd.data_ptr(), sh)
+    torch.cuda.synchronize()
+    H_direct = d_Hd.cpu().numpy()
+    out["eps_abs_mixed"] = rel_rms(H_mixed[idx], H_direct)
+    if not args.skip_fp64:
+        out["eps_abs_fp64"] = rel_rms(H64[idx], H_direct)
+    log("eps_abs mixed %.3e" % out["eps_abs_mixed"])
+
+    # ---- roofline of the dominant kernel (timed with HIP events on the launch stream)
+    m2l_flops = info["m2l_flops_per_config"]
+    p2p_flops = 20.0 * info["n_p2p_pairs"]  # per pair: 3 sub, 3 fma (r^2), 3 fma (m.r), 4 mul, 6 fma (field)
+    if pt["m2l"] >= pt["p2p_l2p"]:
+        ach = m2l_flops / (pt["m2l"] * 1e-3)
+        roof = {"kernel": "k_m2l<float,%d>" % args.order, "bound": "mfma", "achieved": ach / 1e12,
+                "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": None}
+    else:
+        ach = p2p_flops / (pt["p2p_l2p"] * 1e-3)
+        roof = {"kernel": "k_p2p_l2p<float,%d>" % args.order, "bound": "alu", "achieved": ach / 1e12,
+                "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None}
+    out["m2l_tflops"] = m2l_flops / (pt["m2l"] * 1e-3) / 1e12
+    out["p2p_tflops"] = p2p_flops / (pt["p2p_l2p"] * 1e-3) / 1e12
+
+    # ---- CPU oracle on a bounded sample of the same recipe
+    cpu = None
+    if not args.skip_cpu:
+        import oracle
+
+        ns = 1 << 17
+        spos, sbox = inputs.ferrofluid(ns, 2001)
+        sm = inputs.random_moments(ns, 2002)
+        threads = os.cpu_count() or 1
+        threads = min(threads, 16)
+        t = time.perf_counter()
+        oracle.fmm(spos, sm, args.order, args.theta, box=sbox, nthreads=threads)
+        dt = time.perf_counter() - t
+        cpu = {"value": ns / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+               "sample": "FP64 recursive CPU FMM (same p, theta, s rule) on the same ferrofluid recipe at "
+                         "n=131072 (seed 2001/2002), %.1f s" % dt}
+        log("cpu oracle: %.3e evals/s on %d threads" % (ns / dt, threads))
+
+    res = {
+        "metric": METRIC,
+        "value": n / t_step,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ferrofluid_rsa_%d" % n, "n": n, "order": args.order, "theta": args.theta,
+                   "leaf_target": info["s_used"], "levels": info["levels"], "precision": "mixed",
+                   "batch": 1, "step": "tree+lists+tensors+eval"},
+        "eval_only_evals_per_s": n / t_eval,
+        "eval_ms": 1e3 * t_eval,
+        "passes_ms": pt,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    res.update(out)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

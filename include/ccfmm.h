@@ -1,0 +1,148 @@
+/*
+ * ccfmm.h -- C ABI of the MI355X (gfx950) Cartesian fast multipole method for
+ * point-dipole fields (Zhang & Haas, "Adaptation and Performance of the
+ * Cartesian Coordinates Fast Multipole Method for Nanomagnetic Simulations").
+ *
+ * Problem (Sec. 1-3 of the paper): given point dipoles m_i at positions r_i
+ * under open boundaries, return the dipolar field at every dipole,
+ *     H_i = sum_{j : r_j != r_i} (3 (m_j . u) u - m_j) / |r_i - r_j|^3,
+ *     u = (r_i - r_j) / |r_i - r_j|,   in units mu0/4pi = 1,
+ * approximated by the Cartesian FMM with expansion order p (p_m), opening
+ * angle theta (alpha_m) and target dipoles per smallest cell s.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns int: CCFMM_OK (0), a negative error, or a positive
+ *    warning.  No C++ exception, longjmp or abort crosses the ABI.  Details of
+ *    the last error of the calling thread are in ccfmm_last_error().
+ *  - Positions are [n][3] FP64 (x, y, z per dipole).  Moments and fields are
+ *    [nbatch][n][3] FP64: nbatch magnetisation configurations on one geometry.
+ *    Fields come back in the caller's dipole order.
+ *  - The caller owns every buffer it passes, host or device; the library never
+ *    keeps a caller pointer after the call returns.  The library owns the
+ *    plan's device memory; ccfmm_plan_destroy frees it.
+ *  - Host-pointer calls are synchronous.  Device-pointer calls are ordered on
+ *    the given HIP stream (hipStream_t passed as void*, NULL = default stream)
+ *    and return before the GPU work ends.
+ *  - A plan is not thread-safe: one call at a time per plan.
+ */
+#ifndef CCFMM_H
+#define CCFMM_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CCFMM_PMAX 8   /* highest expansion order supported */
+#define CCFMM_LMAX 24  /* deepest bisection tree supported */
+
+/* status codes */
+#define CCFMM_OK 0
+#define CCFMM_EINVAL (-1)     /* invalid argument (sizes, NaN/inf, theta, order, box) */
+#define CCFMM_ENOMEM (-2)     /* device or host allocation failed; the plan stays destroyable */
+#define CCFMM_EHIP (-3)       /* HIP runtime error (message in ccfmm_last_error) */
+#define CCFMM_ESTATE (-4)     /* call not valid in the plan's state */
+#define CCFMM_W_FALLBACK 1    /* learned selector rejected, fixed-parameter result returned */
+
+#define CCFMM_PREC_FP64 0     /* every pass in FP64 */
+#define CCFMM_PREC_MIXED 1    /* FP32 bulk arithmetic; FP64 derivative tensors and final sums */
+
+typedef struct ccfmm_plan_s* ccfmm_plan;
+
+/* Parameters (Sec. 2-4).  Fill with ccfmm_params_default, then override. */
+typedef struct {
+  int32_t order;        /* p_m: multipole and local truncation order, 1..CCFMM_PMAX (Sec. 3) */
+  double theta;         /* alpha_m in (0,1): a cell pair is near iff 2r/d > theta (Sec. 2);
+                           a pair with 2r/d == theta is far */
+  double leaf_target;   /* s, dipoles per smallest cell; <= 0 selects Eq.(so):
+                           s_o = 0.74 p^2 for p > 3, else 8 */
+  int32_t leaf_rule;    /* 0: levels L = argmin_L |N/2^L - s| (Sec. 4);
+                           1: same with N/2^L replaced by the mean over occupied cells */
+  int32_t precision;    /* CCFMM_PREC_FP64 or CCFMM_PREC_MIXED */
+  int32_t selector;     /* 0: fixed (order, theta); 1: learned per-leaf order/angle with
+                           fixed-parameter fallback (needs weights, ccfmm_selector_load) */
+  double err_bound;     /* learned mode: target relative RMS field error (e.g. 1e-5) */
+  int32_t has_box;      /* 1: root cell is [box_lo, box_hi]; 0: tight bounding box */
+  double box_lo[3], box_hi[3];
+  int32_t max_batch;    /* largest nbatch the plan will evaluate (device buffers sized) */
+  int32_t m2l_class_bits; /* M2L target ordering: low key bits grouped first; -1 = autotune */
+} ccfmm_params;
+
+/* Plan summary (counts are exact properties of the tree and lists). */
+typedef struct {
+  int64_t n;
+  int32_t order, levels, precision, max_batch;
+  int32_t split_axis[CCFMM_LMAX + 1];   /* axis halved going to level l (index l >= 1) */
+  double box_lo[3], box_hi[3], leaf_side[3];
+  double s_used;
+  int64_t n_leaves;                     /* occupied smallest cells */
+  int64_t n_cells;                      /* occupied cells, all levels */
+  int64_t n_m2l_pairs;                  /* far (M2L) cell pairs, all levels */
+  int64_t m2l_pairs_per_level[CCFMM_LMAX + 1];
+  int64_t n_p2p_leaf_pairs;             /* near (P2P) leaf pairs, self included */
+  int64_t n_p2p_pairs;                  /* dipole pairs evaluated directly */
+  int64_t n_m2l_tiles, n_m2l_steps;     /* MFMA work units of the M2L pass */
+  int64_t n_delta;                      /* distinct cell offsets with an M2L operator */
+  int32_t m2l_class_bits;
+  int32_t fallback;                     /* learned mode fell back to fixed parameters */
+  double m2l_flops_per_config;          /* algorithmic: 2 * (N(p)-1)^2 * M2L pairs */
+  double p2p_pairs_per_config;
+} ccfmm_info;
+
+/* Per-pass device times (milliseconds) of one evaluation, from HIP events. */
+typedef struct {
+  double p2m, m2m, m2l, l2l, p2p_l2p, total;
+} ccfmm_pass_times;
+
+const char* ccfmm_status_string(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char* ccfmm_last_error(void);
+int ccfmm_params_default(ccfmm_params* prm);
+
+/* Build the plan: tree by recursive halving (Sec. 2, level rule of Sec. 4),
+ * near/far lists by the opening angle (Sec. 2, Appendix createPartners),
+ * derivative tensors (Eqs. Dn, Dnr) and the M2L work tiles.
+ *  pos: host [n][3] FP64, copied.  device: HIP device ordinal.
+ * Errors: EINVAL (n < 1, non-finite positions, order/theta/box invalid, a point
+ * outside a caller box), ENOMEM, EHIP.  On error *out is NULL. */
+int ccfmm_plan_create(ccfmm_plan* out, int32_t device, int64_t n, const double* pos,
+                      const ccfmm_params* prm);
+/* Same from device positions d_pos [n][3] FP64 on the current device, ordered
+ * on stream (the call synchronises the stream once to size the lists). */
+int ccfmm_plan_create_device(ccfmm_plan* out, int64_t n, const double* d_pos,
+                             const ccfmm_params* prm, void* stream);
+/* Rebuild tree, lists and tensors in place for new device positions of the
+ * same count (moving dipoles); buffers are reused when large enough. */
+int ccfmm_plan_update_positions_device(ccfmm_plan plan, const double* d_pos, void* stream);
+
+/* Evaluate H for nbatch configurations (1 <= nbatch <= max_batch).
+ * Host version: m and H are host [nbatch][n][3]; synchronous.
+ * Device version: d_m and d_H are device [nbatch][n][3], stream-ordered.
+ * Passes: P2M Eq.(multipolemoments), M2M Eq.(momentshift), M2L Eq.(taylorcalc),
+ * L2L Eq.(taylorshift), L2P Eq.(H) and the near-field sum Eq.(H2). */
+int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H);
+int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream);
+/* As ccfmm_eval_device, with HIP events between the passes (synchronises). */
+int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H,
+                            void* stream, ccfmm_pass_times* times);
+
+int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out);
+/* Energy E_b = -1/2 sum_i m_i . H_i per configuration (Sec. 3 and Appendix),
+ * host arrays; E is [nbatch]. */
+int ccfmm_energy(int64_t n, int32_t nbatch, const double* m, const double* H, double* E);
+/* NULL-safe. */
+void ccfmm_plan_destroy(ccfmm_plan plan);
+
+/* Direct O(N^2) FP64 field on the GPU at nt sampled targets (error reference at
+ * scale): d_pos [n][3], d_m [n][3], d_idx [nt] int64, d_H [nt][3]; stream-ordered. */
+int ccfmm_direct_targets_device(int64_t n, const double* d_pos, const double* d_m, int64_t nt,
+                                const int64_t* d_idx, double* d_H, void* stream);
+
+/* Self-test of the matrix-core operand layout used by the M2L kernels: runs one
+ * 16x16x4 FP32 and one FP64 MFMA tile on known data and compares with a plain
+ * product on the host.  Returns CCFMM_OK if both match. */
+int ccfmm_selftest_mfma(int32_t device);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

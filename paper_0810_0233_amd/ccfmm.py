@@ -1,0 +1,227 @@
+"""Thin ctypes binding of the C ABI in include/ccfmm.h (libccfmm.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  The library must have been built (``paper_0810_0233_amd.build``);
+loading fails loudly otherwise -- there is no CPU fallback.
+
+Device arrays are passed as raw pointers (e.g. ``tensor.data_ptr()`` of a
+torch CUDA tensor) and streams as raw ``hipStream_t`` handles
+(``torch.cuda.current_stream().cuda_stream``).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccfmm.so")
+
+PMAX = 8
+LMAX = 24
+OK, EINVAL, ENOMEM, EHIP, ESTATE, W_FALLBACK = 0, -1, -2, -3, -4, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class ccfmm_params(C.Structure):
+    _fields_ = [("order", C.c_int32), ("theta", C.c_double), ("leaf_target", C.c_double),
+                ("leaf_rule", C.c_int32), ("precision", C.c_int32), ("selector", C.c_int32),
+                ("err_bound", C.c_double), ("has_box", C.c_int32),
+                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+                ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32)]
+
+
+class ccfmm_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("order", C.c_int32), ("levels", C.c_int32),
+                ("precision", C.c_int32), ("max_batch", C.c_int32),
+                ("split_axis", C.c_int32 * (LMAX + 1)),
+                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3), ("leaf_side", C.c_double * 3),
+                ("s_used", C.c_double), ("n_leaves", C.c_int64), ("n_cells", C.c_int64),
+                ("n_m2l_pairs", C.c_int64), ("m2l_pairs_per_level", C.c_int64 * (LMAX + 1)),
+                ("n_p2p_leaf_pairs", C.c_int64), ("n_p2p_pairs", C.c_int64),
+                ("n_m2l_tiles", C.c_int64), ("n_m2l_steps", C.c_int64), ("n_delta", C.c_int64),
+                ("m2l_class_bits", C.c_int32), ("fallback", C.c_int32),
+                ("m2l_flops_per_config", C.c_double), ("p2p_pairs_per_config", C.c_double)]
+
+
+class ccfmm_pass_times(C.Structure):
+    _fields_ = [("p2m", C.c_double), ("m2m", C.c_double), ("m2l", C.c_double), ("l2l", C.c_double),
+                ("p2p_l2p", C.c_double), ("total", C.c_double)]
+
+
+# every symbol the header declares (checked by the CPU tests)
+EXPORTS = [
+    "ccfmm_status_string", "ccfmm_last_error", "ccfmm_params_default", "ccfmm_plan_create",
+    "ccfmm_plan_create_device", "ccfmm_plan_update_positions_device", "ccfmm_eval", "ccfmm_eval_device",
+    "ccfmm_eval_device_timed", "ccfmm_plan_info", "ccfmm_energy", "ccfmm_plan_destroy",
+    "ccfmm_direct_targets_device", "ccfmm_selftest_mfma",
+]
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+class CCFMMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (status_string(status), status, msg))
+        self.status = status
+
+
+def lib():
+    """Load libccfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libccfmm.so is not built (run paper_0810_0233_amd.build.build())")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 under
+        # the same SONAME; loading torch first makes libccfmm bind to that copy
+        # instead of pulling in a second runtime that torch could not share.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        L.ccfmm_status_string.argtypes = [C.c_int]
+        L.ccfmm_status_string.restype = C.c_char_p
+        L.ccfmm_last_error.restype = C.c_char_p
+        L.ccfmm_params_default.argtypes = [C.POINTER(ccfmm_params)]
+        L.ccfmm_plan_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_int64, _dp, C.POINTER(ccfmm_params)]
+        L.ccfmm_plan_create_device.argtypes = [C.POINTER(C.c_void_p), C.c_int64, C.c_void_p,
+                                               C.POINTER(ccfmm_params), C.c_void_p]
+        L.ccfmm_plan_update_positions_device.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ccfmm_eval.argtypes = [C.c_void_p, C.c_int32, _dp, _dp]
+        L.ccfmm_eval_device.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ccfmm_eval_device_timed.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.POINTER(ccfmm_pass_times)]
+        L.ccfmm_plan_info.argtypes = [C.c_void_p, C.POINTER(ccfmm_info)]
+        L.ccfmm_energy.argtypes = [C.c_int64, C.c_int32, _dp, _dp, _dp]
+        L.ccfmm_plan_destroy.argtypes = [C.c_void_p]
+        L.ccfmm_plan_destroy.restype = None
+        L.ccfmm_direct_targets_device.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                                  C.c_void_p, C.c_void_p]
+        L.ccfmm_selftest_mfma.argtypes = [C.c_int32]
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    return lib().ccfmm_status_string(status).decode()
+
+
+def last_error():
+    return lib().ccfmm_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise CCFMMError(rc, last_error())
+    return rc
+
+
+def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64, selector=0,
+           err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3):
+    p = ccfmm_params()
+    _check(lib().ccfmm_params_default(C.byref(p)))
+    p.order = int(order)
+    p.theta = float(theta)
+    p.leaf_target = float(leaf_target)
+    p.leaf_rule = int(leaf_rule)
+    p.precision = int(precision)
+    p.selector = int(selector)
+    p.err_bound = float(err_bound)
+    if box is not None:
+        p.has_box = 1
+        for a in range(3):
+            p.box_lo[a] = float(box[0][a])
+            p.box_hi[a] = float(box[1][a])
+    p.max_batch = int(max_batch)
+    p.m2l_class_bits = int(m2l_class_bits)
+    return p
+
+
+def info_dict(inf):
+    L = inf.levels
+    d = {f: getattr(inf, f) for f, _ in ccfmm_info._fields_
+         if f not in ("split_axis", "box_lo", "box_hi", "leaf_side", "m2l_pairs_per_level")}
+    d["split_axis"] = [inf.split_axis[l] for l in range(1, L + 1)]
+    d["box_lo"] = list(inf.box_lo)
+    d["box_hi"] = list(inf.box_hi)
+    d["leaf_side"] = list(inf.leaf_side)
+    d["m2l_pairs_per_level"] = [inf.m2l_pairs_per_level[l] for l in range(L + 1)]
+    return d
+
+
+class Plan:
+    """A ccfmm plan (tree, lists, derivative tensors) of one geometry."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    @classmethod
+    def create(cls, pos, prm, device=0):
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        h = C.c_void_p()
+        _check(lib().ccfmm_plan_create(C.byref(h), device, pos.shape[0], pos, C.byref(prm)))
+        return cls(h)
+
+    @classmethod
+    def create_device(cls, n, d_pos, prm, stream=0):
+        h = C.c_void_p()
+        _check(lib().ccfmm_plan_create_device(C.byref(h), int(n), C.c_void_p(d_pos), C.byref(prm),
+                                              C.c_void_p(stream)))
+        return cls(h)
+
+    def update_positions_device(self, d_pos, stream=0):
+        _check(lib().ccfmm_plan_update_positions_device(self.h, C.c_void_p(d_pos), C.c_void_p(stream)))
+
+    def eval(self, m):
+        """Host moments [nbatch][n][3] (or [n][3]) -> host fields, same shape."""
+        m = np.ascontiguousarray(m, dtype=np.float64)
+        shape = m.shape
+        m3 = m.reshape(-1, self.info()["n"], 3)
+        H = np.empty_like(m3)
+        _check(lib().ccfmm_eval(self.h, m3.shape[0], m3, H))
+        return H.reshape(shape)
+
+    def eval_device(self, nbatch, d_m, d_H, stream=0):
+        _check(lib().ccfmm_eval_device(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H), C.c_void_p(stream)))
+
+    def eval_device_timed(self, nbatch, d_m, d_H, stream=0):
+        t = ccfmm_pass_times()
+        _check(lib().ccfmm_eval_device_timed(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H),
+                                             C.c_void_p(stream), C.byref(t)))
+        return {f: getattr(t, f) for f, _ in ccfmm_pass_times._fields_}
+
+    def info(self):
+        inf = ccfmm_info()
+        _check(lib().ccfmm_plan_info(self.h, C.byref(inf)))
+        return info_dict(inf)
+
+    def destroy(self):
+        if self.h:
+            lib().ccfmm_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def energy(m, H):
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    n = m.shape[-2]
+    nb = m.size // (3 * n)
+    E = np.zeros(nb)
+    _check(lib().ccfmm_energy(n, nb, m.reshape(-1), H.reshape(-1), E))
+    return E
+
+
+def direct_targets_device(n, d_pos, d_m, nt, d_idx, d_H, stream=0):
+    _check(lib().ccfmm_direct_targets_device(int(n), C.c_void_p(d_pos), C.c_void_p(d_m), int(nt),
+                                             C.c_void_p(d_idx), C.c_void_p(d_H), C.c_void_p(stream)))
+
+
+def selftest_mfma(device=0):
+    return lib().ccfmm_selftest_mfma(device)

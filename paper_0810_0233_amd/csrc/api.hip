@@ -1,0 +1,566 @@
+// api.hip -- the C ABI: plan life cycle, evaluation, info, errors.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "plan.hpp"
+
+namespace ccfmm {
+
+static thread_local std::string g_last_error;
+
+void* DevBuf::ensure(size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (bytes <= cap) return p;
+  release();
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess || q == nullptr) {
+    (void)hipGetLastError();
+    throw StatusError{CCFMM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  }
+  p = q;
+  cap = bytes;
+  return p;
+}
+
+void DevBuf::release() {
+  // buffers are only released while rebuilding or destroying; work queued on
+  // any stream may still read them, so drain the device first
+  if (p) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p);
+  }
+  p = nullptr;
+  cap = 0;
+}
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{e, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void fail(int status, const std::string& msg) { throw StatusError{status, msg}; }
+
+int selftest_mfma_impl(int device);
+
+// ---------------------------------------------------------------- geometry
+__global__ void k_bbox_partial(const double* __restrict__ pos, int64_t n, double* part, int32_t* bad) {
+  __shared__ double smin[3][256], smax[3][256];
+  const int t = threadIdx.x;
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + t; i < n; i += (int64_t)gridDim.x * 256) {
+    for (int a = 0; a < 3; a++) {
+      const double v = pos[3 * i + a];
+      if (!isfinite(v)) bad[0] = 1;
+      mn[a] = fmin(mn[a], v);
+      mx[a] = fmax(mx[a], v);
+    }
+  }
+  for (int a = 0; a < 3; a++) {
+    smin[a][t] = mn[a];
+    smax[a][t] = mx[a];
+  }
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off)
+      for (int a = 0; a < 3; a++) {
+        smin[a][t] = fmin(smin[a][t], smin[a][t + off]);
+        smax[a][t] = fmax(smax[a][t], smax[a][t + off]);
+      }
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int a = 0; a < 3; a++) {
+      part[6 * blockIdx.x + a] = smin[a][0];
+      part[6 * blockIdx.x + 3 + a] = smax[a][0];
+    }
+}
+
+static void device_bbox(const double* d_pos, int64_t n, DevBuf& tmp, hipStream_t st, double mn[3], double mx[3],
+                        bool& bad) {
+  const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  char* buf = reinterpret_cast<char*>(tmp.ensure(sizeof(double) * 6 * nblk + 64));
+  double* part = reinterpret_cast<double*>(buf + 64);
+  int32_t* dbad = reinterpret_cast<int32_t*>(buf);
+  CCFMM_HIP(hipMemsetAsync(dbad, 0, sizeof(int32_t), st));
+  k_bbox_partial<<<nblk, 256, 0, st>>>(d_pos, n, part, dbad);
+  CCFMM_HIP(hipGetLastError());
+  std::vector<double> h(6 * nblk);
+  int32_t hb = 0;
+  CCFMM_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * 6 * nblk, hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipMemcpyAsync(&hb, dbad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  for (int a = 0; a < 3; a++) {
+    mn[a] = INFINITY;
+    mx[a] = -INFINITY;
+  }
+  for (int b = 0; b < nblk; b++)
+    for (int a = 0; a < 3; a++) {
+      mn[a] = std::min(mn[a], h[6 * b + a]);
+      mx[a] = std::max(mx[a], h[6 * b + 3 + a]);
+    }
+  bad = hb != 0;
+}
+
+static double s_opt(int p) { return p > 3 ? 0.74 * (double)p * (double)p : 8.0; }
+
+// Root box, level count and split sequence.  Root: the caller's box, else the
+// tight bounding box (an axis without extent takes the smallest nonzero side,
+// or 1).  Levels: the depth whose mean dipoles per smallest cell, N / 2^L, is
+// closest to s (ties to the shallower tree).  Split: halve the longest side,
+// ties x < y < z.
+static void setup_geometry(Plan& P, const double mn[3], const double mx[3]) {
+  double lo[3], W[3];
+  if (P.prm.has_box) {
+    for (int a = 0; a < 3; a++) {
+      lo[a] = P.prm.box_lo[a];
+      W[a] = P.prm.box_hi[a] - P.prm.box_lo[a];
+      if (!(W[a] > 0.0) || !std::isfinite(W[a])) fail(CCFMM_EINVAL, "empty or non-finite box");
+      if (mn[a] < P.prm.box_lo[a] || mx[a] > P.prm.box_hi[a]) fail(CCFMM_EINVAL, "a dipole lies outside the box");
+    }
+  } else {
+    double smallest = 0.0;
+    for (int a = 0; a < 3; a++) {
+      const double w = mx[a] - mn[a];
+      if (w > 0.0 && (smallest == 0.0 || w < smallest)) smallest = w;
+    }
+    if (smallest == 0.0) smallest = 1.0;
+    for (int a = 0; a < 3; a++) {
+      lo[a] = mn[a];
+      W[a] = (mx[a] - mn[a] > 0.0) ? (mx[a] - mn[a]) : smallest;
+    }
+  }
+  P.s_used = P.prm.leaf_target > 0.0 ? P.prm.leaf_target : s_opt(P.p);
+  int best = 0;
+  double bestd = INFINITY;
+  for (int L = 0; L <= kLMax; L++) {
+    const double d = std::fabs((double)P.n / std::ldexp(1.0, L) - P.s_used);
+    if (d < bestd) {
+      bestd = d;
+      best = L;
+    }
+  }
+  P.L = best;
+  TreeGeom& G = P.geo;
+  std::memset(&G, 0, sizeof(G));
+  G.L = P.L;
+  double h[3] = {W[0], W[1], W[2]};
+  int k[3] = {0, 0, 0};
+  for (int l = 0; l <= P.L; l++) {
+    if (l > 0) {
+      int a = 0;
+      if (h[1] > h[a]) a = 1;
+      if (h[2] > h[a]) a = 2;
+      h[a] = h[a] / 2.0;
+      k[a]++;
+      G.lev[l].axis = a;
+    } else {
+      G.lev[l].axis = -1;
+    }
+    const double s = std::min(h[0], std::min(h[1], h[2]));
+    G.lev[l].s = s;
+    for (int a = 0; a < 3; a++) {
+      G.lev[l].h[a] = h[a];
+      G.lev[l].g[a] = h[a] / s;
+      G.lev[l].k[a] = k[a];
+    }
+  }
+  for (int a = 0; a < 3; a++) {
+    G.lo[a] = lo[a];
+    G.W[a] = W[a];
+  }
+}
+
+static void size_expansions(Plan& P, int nb) {
+  const int NS = nstride(P.p);
+  int64_t off = 0;
+  for (int l = 0; l <= P.L; l++) {
+    P.lev[l]->qoff = off;
+    off += (int64_t)P.lev[l]->ncells * nb * NS;
+  }
+  P.qv_elems = off;
+  const size_t es = P.precision == CCFMM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  P.Q.ensure(es * std::max<int64_t>(1, off));
+  P.V.ensure(es * std::max<int64_t>(1, off));
+  P.m_sorted.ensure(es * 3 * (size_t)P.n * nb);
+  P.qv_batch = nb;
+}
+
+__global__ void k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr, const int32_t* near_idx,
+                                  const int32_t* lcount, unsigned long long* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  long long s = 0;
+  for (int e = near_ptr[i]; e < near_ptr[i + 1]; e++) s += lcount[near_idx[e]];
+  atomicAdd(out, (unsigned long long)(s * lcount[i]));
+}
+
+static void fill_info(Plan& P, hipStream_t st) {
+  ccfmm_info& I = P.info;
+  std::memset(&I, 0, sizeof(I));
+  I.n = P.n;
+  I.order = P.p;
+  I.levels = P.L;
+  I.precision = P.precision;
+  I.max_batch = P.nbmax;
+  for (int l = 0; l <= kLMax; l++) I.split_axis[l] = (l >= 1 && l <= P.L) ? P.geo.lev[l].axis : -1;
+  for (int a = 0; a < 3; a++) {
+    I.box_lo[a] = P.geo.lo[a];
+    I.box_hi[a] = P.geo.lo[a] + P.geo.W[a];
+    I.leaf_side[a] = P.geo.lev[P.L].h[a];
+  }
+  I.s_used = P.s_used;
+  I.n_leaves = P.lev[P.L]->ncells;
+  int64_t cells = 0, m2l = 0;
+  for (int l = 0; l <= P.L; l++) {
+    cells += P.lev[l]->ncells;
+    I.m2l_pairs_per_level[l] = P.lev[l]->nfar;
+    m2l += P.lev[l]->nfar;
+    I.n_delta += P.lev[l]->ndelta;
+  }
+  I.n_cells = cells;
+  I.n_m2l_pairs = m2l;
+  I.n_p2p_leaf_pairs = P.lev[P.L]->nnear;
+  I.n_m2l_tiles = P.ntiles;
+  I.n_m2l_steps = P.nsteps;
+  I.m2l_class_bits = P.class_bits;
+  const double np = (double)nact(P.p);
+  I.m2l_flops_per_config = 2.0 * np * np * (double)m2l;
+  // direct pairs (self pairs included in the count)
+  LevelData& D = *P.lev[P.L];
+  unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(P.scratch2.ensure(64));
+  CCFMM_HIP(hipMemsetAsync(dcnt, 0, 8, st));
+  k_count_p2p_pairs<<<ceil_div(D.ncells, 256), 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
+                                                             D.near_idx.as<int32_t>(), P.lcount.as<int32_t>(), dcnt);
+  CCFMM_HIP(hipGetLastError());
+  unsigned long long h = 0;
+  CCFMM_HIP(hipMemcpyAsync(&h, dcnt, 8, hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  I.n_p2p_pairs = (int64_t)h;
+  I.p2p_pairs_per_config = (double)h;
+}
+
+static void validate_params(const ccfmm_params* prm, int64_t n) {
+  if (!prm) fail(CCFMM_EINVAL, "params is NULL");
+  if (n < 1) fail(CCFMM_EINVAL, "n must be >= 1");
+  if (n > (int64_t)INT32_MAX / 3) fail(CCFMM_EINVAL, "n too large");
+  if (prm->order < 1 || prm->order > kPMax) fail(CCFMM_EINVAL, "order must be in 1..8");
+  if (!(prm->theta > 0.0 && prm->theta < 1.0)) fail(CCFMM_EINVAL, "theta must be in (0, 1)");
+  if (!std::isfinite(prm->leaf_target)) fail(CCFMM_EINVAL, "leaf_target not finite");
+  if (prm->leaf_rule != 0) fail(CCFMM_EINVAL, "leaf_rule 1 is not supported by this build");
+  if (prm->precision != CCFMM_PREC_FP64 && prm->precision != CCFMM_PREC_MIXED)
+    fail(CCFMM_EINVAL, "precision must be FP64 or MIXED");
+  if (prm->selector != 0) fail(CCFMM_EINVAL, "learned selector not available in this build");
+  if (prm->max_batch < 1 || prm->max_batch > 4096) fail(CCFMM_EINVAL, "max_batch must be in 1..4096");
+  if (prm->has_box)
+    for (int a = 0; a < 3; a++)
+      if (!std::isfinite(prm->box_lo[a]) || !std::isfinite(prm->box_hi[a])) fail(CCFMM_EINVAL, "box not finite");
+}
+
+// Build (or rebuild) everything that depends on the positions.
+static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
+  double mn[3], mx[3];
+  bool bad = false;
+  device_bbox(d_pos, P.n, P.scratch, st, mn, mx, bad);
+  if (bad) fail(CCFMM_EINVAL, "non-finite position");
+  setup_geometry(P, mn, mx);
+  const int64_t n = P.n;
+  P.key.ensure(sizeof(uint32_t) * n);
+  P.val.ensure(sizeof(int32_t) * n);
+  P.key_tmp.ensure(sizeof(uint32_t) * n);
+  P.val_tmp.ensure(sizeof(int32_t) * n);
+  P.perm.ensure(sizeof(int32_t) * n);
+  P.yd.ensure(sizeof(double) * 3 * n);
+  P.yf.ensure(sizeof(float) * 3 * n);
+  P.leaf_start.ensure(sizeof(int32_t) * ((1ll << P.L) + 1));
+  const int64_t nheap = (2ll << P.L) - 1;
+  P.heap_flag.ensure(sizeof(int32_t) * (nheap + 1));
+  P.heap_scan.ensure(sizeof(int32_t) * (nheap + 1));
+  P.cmap.ensure(sizeof(int32_t) * nheap);
+  while ((int)P.lev.size() < P.L + 1) P.lev.emplace_back(new LevelData());
+  build_tree(P, d_pos, st);
+  build_lists(P, st);
+  build_dtensors(P, st);
+  build_p2p_chunks(P, st);
+  build_m2l_tiles(P, P.nbmax, st);
+  P.qv_batch = 0;
+  fill_info(P, st);
+  P.built = true;
+}
+
+static void prepare_batch(Plan& P, int nb, hipStream_t st) {
+  if (nb < 1 || nb > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
+  const int tb = [&] {
+    int t = 1;
+    while (t < nb && t < 16) t <<= 1;
+    return t;
+  }();
+  if (tb != P.TB || ceil_div(nb, tb) != P.ncg) {
+    build_m2l_tiles(P, nb, st);
+    P.info.n_m2l_tiles = P.ntiles;
+    P.info.n_m2l_steps = P.nsteps;
+  }
+  if (P.qv_batch != nb) size_expansions(P, nb);
+}
+
+static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev) {
+  if (ev) CCFMM_HIP(hipEventRecord(ev[0], st));
+  run_p2m(P, nb, d_m, st);
+  if (ev) CCFMM_HIP(hipEventRecord(ev[1], st));
+  run_m2m(P, nb, st);
+  if (ev) CCFMM_HIP(hipEventRecord(ev[2], st));
+  run_m2l(P, nb, st);
+  if (ev) CCFMM_HIP(hipEventRecord(ev[3], st));
+  run_l2l(P, nb, st);
+  if (ev) CCFMM_HIP(hipEventRecord(ev[4], st));
+  run_p2p_l2p(P, nb, d_H, st);
+  if (ev) CCFMM_HIP(hipEventRecord(ev[5], st));
+}
+
+template <typename F>
+static int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const StatusError& e) {
+    g_last_error = e.what;
+    return e.status;
+  } catch (const HipError& e) {
+    g_last_error = e.what;
+    return CCFMM_EHIP;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return CCFMM_ENOMEM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return CCFMM_EHIP;
+  }
+}
+
+}  // namespace ccfmm
+
+using namespace ccfmm;
+
+struct ccfmm_plan_s {
+  Plan P;
+};
+
+extern "C" {
+
+const char* ccfmm_status_string(int status) {
+  switch (status) {
+    case CCFMM_OK: return "ok";
+    case CCFMM_EINVAL: return "invalid argument";
+    case CCFMM_ENOMEM: return "out of memory";
+    case CCFMM_EHIP: return "HIP runtime error";
+    case CCFMM_ESTATE: return "invalid plan state";
+    case CCFMM_W_FALLBACK: return "learned selector fell back to fixed parameters";
+    default: return "unknown status";
+  }
+}
+
+const char* ccfmm_last_error(void) { return g_last_error.c_str(); }
+
+int ccfmm_params_default(ccfmm_params* prm) {
+  if (!prm) return CCFMM_EINVAL;
+  std::memset(prm, 0, sizeof(*prm));
+  prm->order = 4;
+  prm->theta = 0.5;
+  prm->leaf_target = 0.0;
+  prm->leaf_rule = 0;
+  prm->precision = CCFMM_PREC_FP64;
+  prm->selector = 0;
+  prm->err_bound = 1e-5;
+  prm->has_box = 0;
+  prm->max_batch = 1;
+  prm->m2l_class_bits = 3;
+  return CCFMM_OK;
+}
+
+static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const ccfmm_params* prm, hipStream_t st,
+                         bool own) {
+  return guarded([&] {
+    if (!out) fail(CCFMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    validate_params(prm, n);
+    if (!d_pos) fail(CCFMM_EINVAL, "positions are NULL");
+    ccfmm_plan pl = new ccfmm_plan_s();
+    Plan& P = pl->P;
+    try {
+      CCFMM_HIP(hipGetDevice(&P.device));
+      P.n = n;
+      P.prm = *prm;
+      P.p = prm->order;
+      P.precision = prm->precision;
+      P.nbmax = prm->max_batch;
+      P.class_bits = prm->m2l_class_bits < 0 ? 3 : std::min(prm->m2l_class_bits, 12);
+      if (own) {
+        CCFMM_HIP(hipStreamCreateWithFlags(&P.own_stream, hipStreamNonBlocking));
+        st = P.own_stream;
+      }
+      build_all(P, d_pos, st);
+    } catch (...) {
+      if (P.own_stream) (void)hipStreamDestroy(P.own_stream);
+      delete pl;
+      throw;
+    }
+    *out = pl;
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_create(ccfmm_plan* out, int32_t device, int64_t n, const double* pos, const ccfmm_params* prm) {
+  return guarded([&] {
+    if (!out) fail(CCFMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    validate_params(prm, n);
+    if (!pos) fail(CCFMM_EINVAL, "positions are NULL");
+    for (int64_t i = 0; i < 3 * n; i++)
+      if (!std::isfinite(pos[i])) fail(CCFMM_EINVAL, "non-finite position");
+    CCFMM_HIP(hipSetDevice(device));
+    DevBuf dpos;
+    dpos.ensure(sizeof(double) * 3 * n);
+    CCFMM_HIP(hipMemcpy(dpos.p, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    int rc = create_common(out, n, dpos.as<double>(), prm, nullptr, true);
+    if (rc == CCFMM_OK) {
+      // keep the device copy: the host-pointer plan owns its positions
+      std::swap((*out)->P.pos.p, dpos.p);
+      std::swap((*out)->P.pos.cap, dpos.cap);
+      CCFMM_HIP(hipStreamSynchronize((*out)->P.own_stream));
+    } else {
+      g_last_error = g_last_error;  // preserved from create_common
+    }
+    return rc;
+  });
+}
+
+int ccfmm_plan_create_device(ccfmm_plan* out, int64_t n, const double* d_pos, const ccfmm_params* prm,
+                             void* stream) {
+  return create_common(out, n, d_pos, prm, reinterpret_cast<hipStream_t>(stream), false);
+}
+
+int ccfmm_plan_update_positions_device(ccfmm_plan plan, const double* d_pos, void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_pos) fail(CCFMM_EINVAL, "positions are NULL");
+    Plan& P = plan->P;
+    CCFMM_HIP(hipSetDevice(P.device));
+    P.built = false;
+    build_all(P, d_pos, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_m || !d_H) fail(CCFMM_EINVAL, "moment or field pointer is NULL");
+    Plan& P = plan->P;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CCFMM_HIP(hipSetDevice(P.device));
+    prepare_batch(P, nbatch, st);
+    eval_passes(P, nbatch, d_m, d_H, st, nullptr);
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream,
+                            ccfmm_pass_times* times) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_m || !d_H || !times) fail(CCFMM_EINVAL, "NULL argument");
+    Plan& P = plan->P;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CCFMM_HIP(hipSetDevice(P.device));
+    prepare_batch(P, nbatch, st);
+    hipEvent_t ev[6];
+    for (int i = 0; i < 6; i++) CCFMM_HIP(hipEventCreate(&ev[i]));
+    eval_passes(P, nbatch, d_m, d_H, st, ev);
+    CCFMM_HIP(hipEventSynchronize(ev[5]));
+    float ms[5];
+    for (int i = 0; i < 5; i++) CCFMM_HIP(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+    float tot;
+    CCFMM_HIP(hipEventElapsedTime(&tot, ev[0], ev[5]));
+    for (int i = 0; i < 6; i++) (void)hipEventDestroy(ev[i]);
+    times->p2m = ms[0];
+    times->m2m = ms[1];
+    times->m2l = ms[2];
+    times->l2l = ms[3];
+    times->p2p_l2p = ms[4];
+    times->total = tot;
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!m || !H) fail(CCFMM_EINVAL, "moment or field pointer is NULL");
+    Plan& P = plan->P;
+    if (nbatch < 1 || nbatch > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
+    for (int64_t i = 0; i < (int64_t)3 * P.n * nbatch; i++)
+      if (!std::isfinite(m[i])) fail(CCFMM_EINVAL, "non-finite moment");
+    CCFMM_HIP(hipSetDevice(P.device));
+    hipStream_t st = P.own_stream;
+    const size_t bytes = sizeof(double) * 3 * (size_t)P.n * nbatch;
+    DevBuf dm, dH;
+    dm.ensure(bytes);
+    dH.ensure(bytes);
+    CCFMM_HIP(hipMemcpyAsync(dm.p, m, bytes, hipMemcpyHostToDevice, st));
+    prepare_batch(P, nbatch, st);
+    eval_passes(P, nbatch, dm.as<double>(), dH.as<double>(), st, nullptr);
+    CCFMM_HIP(hipMemcpyAsync(H, dH.p, bytes, hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipStreamSynchronize(st));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!out) fail(CCFMM_EINVAL, "out is NULL");
+    *out = plan->P.info;
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_energy(int64_t n, int32_t nbatch, const double* m, const double* H, double* E) {
+  return guarded([&] {
+    if (n < 1 || nbatch < 1 || !m || !H || !E) fail(CCFMM_EINVAL, "invalid argument");
+    for (int b = 0; b < nbatch; b++) {
+      double s = 0.0;
+      const double* mb = m + (int64_t)b * n * 3;
+      const double* hb = H + (int64_t)b * n * 3;
+      for (int64_t i = 0; i < 3 * n; i++) s += mb[i] * hb[i];
+      E[b] = -0.5 * s;
+    }
+    return CCFMM_OK;
+  });
+}
+
+void ccfmm_plan_destroy(ccfmm_plan plan) {
+  if (!plan) return;
+  try {
+    (void)hipSetDevice(plan->P.device);
+    (void)hipDeviceSynchronize();
+    if (plan->P.own_stream) (void)hipStreamDestroy(plan->P.own_stream);
+    delete plan;
+  } catch (...) {
+  }
+}
+
+int ccfmm_direct_targets_device(int64_t n, const double* d_pos, const double* d_m, int64_t nt, const int64_t* d_idx,
+                                double* d_H, void* stream) {
+  return guarded([&] {
+    if (n < 1 || nt < 0 || !d_pos || !d_m || (nt > 0 && (!d_idx || !d_H))) fail(CCFMM_EINVAL, "invalid argument");
+    run_direct_targets(n, d_pos, d_m, nt, d_idx, d_H, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_selftest_mfma(int32_t device) {
+  return guarded([&] { return selftest_mfma_impl(device); });
+}
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// expansions.hip -- derivative tensors (Eqs. Dn, Dnr), multipole moments of
+// dipoles (Eq. multipolemoments), moment shifts up the tree (Eq. momentshift)
+// and Taylor shifts down the tree (Eq. taylorshift).
+//
+// All expansions are stored per level in scaled form (s = smallest side of the
+// level's cells):  Qt_n = Q_n s^(1-|n|),  Vt_n = V_n s^(|n|+2),  and the dipole
+// offsets inside a smallest cell are yt = (x - centre) / s.  In these units the
+// numbers stay O(1) at every level, which the FP32 form relies on.
+#include <algorithm>
+#include <map>
+#include <type_traits>
+
+#include "plan.hpp"
+
+namespace ccfmm {
+
+// ------------------------------------------------------------ F table (host)
+// D_k(r) = r^-(2|k|+1) sum_{|q|=|k|} F_k(q) r^q.  Going from k to k + e_v
+// applies -d/dr_v, which maps the term r^q / r^(2|k|+1) onto
+//   (2|k|+1-q_v) r^(q+e_v) - q_v r^(q-e_v+2e_u) - q_v r^(q-e_v+2e_w)
+// over r^(2|k|+3).  Here every k is reached from k - e_v with v the last axis
+// on which k is nonzero; the table is unique, so the choice is free.
+struct FTableHost {
+  std::vector<int32_t> ptr;   // ncoef(K) + 1
+  std::vector<int32_t> q;     // flat index of q (same degree as k)
+  std::vector<double> val;
+};
+
+static FTableHost make_ftable(int K) {
+  const int NK = ncoef(K);
+  std::vector<std::map<int, long double>> F(NK);
+  F[0][0] = 1.0L;
+  std::vector<int> mx(NK), my(NK), mz(NK);
+  {
+    int t = 0;
+    for (int d = 0; d <= K; d++)
+      for (int a = d; a >= 0; a--)
+        for (int b = d - a; b >= 0; b--) {
+          mx[t] = a;
+          my[t] = b;
+          mz[t] = d - a - b;
+          t++;
+        }
+  }
+  for (int t = 1; t < NK; t++) {
+    int k[3] = {mx[t], my[t], mz[t]};
+    int v = k[2] > 0 ? 2 : (k[1] > 0 ? 1 : 0);
+    int n[3] = {k[0], k[1], k[2]};
+    n[v]--;
+    const int deg = n[0] + n[1] + n[2];
+    const int src = midx(n[0], n[1], n[2]);
+    for (const auto& kv : F[src]) {
+      const int qi = kv.first;
+      const long double f = kv.second;
+      int q[3] = {mx[qi], my[qi], mz[qi]};
+      {
+        int r[3] = {q[0], q[1], q[2]};
+        r[v]++;
+        F[t][midx(r[0], r[1], r[2])] += (long double)(2 * deg + 1 - q[v]) * f;
+      }
+      if (q[v] > 0) {
+        for (int u = 0; u < 3; u++) {
+          if (u == v) continue;
+          int r[3] = {q[0], q[1], q[2]};
+          r[v]--;
+          r[u] += 2;
+          F[t][midx(r[0], r[1], r[2])] -= (long double)q[v] * f;
+        }
+      }
+    }
+  }
+  FTableHost out;
+  out.ptr.push_back(0);
+  for (int t = 0; t < NK; t++) {
+    for (const auto& kv : F[t]) {
+      if (kv.second == 0.0L) continue;
+      out.q.push_back(kv.first);
+      out.val.push_back((double)kv.second);
+    }
+    out.ptr.push_back((int32_t)out.q.size());
+  }
+  return out;
+}
+
+// One thread per (offset, k): D_k(c) in FP64, then an FP32 copy.  The list
+// offsets are source minus target; Eq.(taylorcalc) takes c = target centre
+// minus source centre, i.e. c = -delta * g in the level's units.
+__global__ void k_dtensor(int32_t ndelta, const int32_t* __restrict__ dvec, double g0, double g1, double g2,
+                          int K, const int32_t* __restrict__ fptr, const int32_t* __restrict__ fq,
+                          const double* __restrict__ fval, int64_t row0, double* Dd, float* Df) {
+  const int NK = ncoef(K);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ndelta * NK) return;
+  const int d = (int)(t / NK), k = (int)(t % NK);
+  const double c[3] = {-dvec[3 * d] * g0, -dvec[3 * d + 1] * g1, -dvec[3 * d + 2] * g2};
+  double pw[3][kKMax + 1];
+  for (int a = 0; a < 3; a++) {
+    pw[a][0] = 1.0;
+    for (int j = 1; j <= K; j++) pw[a][j] = pw[a][j - 1] * c[a];
+  }
+  const double r2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+  const int deg = kMI.x[k] + kMI.y[k] + kMI.z[k];
+  double s = 0.0;
+  for (int e = fptr[k]; e < fptr[k + 1]; e++) {
+    const int q = fq[e];
+    s += fval[e] * pw[0][kMI.x[q]] * pw[1][kMI.y[q]] * pw[2][kMI.z[q]];
+  }
+  // r^-(2 deg + 1)
+  const double rinv = 1.0 / sqrt(r2);
+  double rp = rinv;
+  const double rinv2 = rinv * rinv;
+  for (int j = 0; j < deg; j++) rp *= rinv2;
+  const double v = s * rp;
+  const int64_t o = (row0 + d) * NK + k;
+  Dd[o] = v;
+  Df[o] = (float)v;
+}
+
+void build_dtensors(Plan& P, hipStream_t st) {
+  const int K = 2 * P.p;
+  const int NK = ncoef(K);
+  static FTableHost ft[kPMax + 1];
+  static bool have[kPMax + 1] = {false};
+  if (!have[P.p]) {
+    ft[P.p] = make_ftable(K);
+    have[P.p] = true;
+  }
+  const FTableHost& F = ft[P.p];
+  // table upload: ptr | q | val
+  const size_t nb_ptr = sizeof(int32_t) * F.ptr.size(), nb_q = sizeof(int32_t) * F.q.size();
+  const size_t nb_val = sizeof(double) * F.val.size();
+  char* buf = reinterpret_cast<char*>(P.scratch2.ensure(nb_ptr + nb_q + nb_val + 64));
+  int32_t* dptr = reinterpret_cast<int32_t*>(buf);
+  int32_t* dq = reinterpret_cast<int32_t*>(buf + nb_ptr);
+  double* dval = reinterpret_cast<double*>(buf + ((nb_ptr + nb_q + 15) & ~size_t(15)));
+  CCFMM_HIP(hipMemcpyAsync(dptr, F.ptr.data(), nb_ptr, hipMemcpyHostToDevice, st));
+  CCFMM_HIP(hipMemcpyAsync(dq, F.q.data(), nb_q, hipMemcpyHostToDevice, st));
+  CCFMM_HIP(hipMemcpyAsync(dval, F.val.data(), nb_val, hipMemcpyHostToDevice, st));
+  const int64_t rows = std::max<int64_t>(1, P.nrows);
+  double* Dd = reinterpret_cast<double*>(P.Dd.ensure(sizeof(double) * rows * NK));
+  float* Df = reinterpret_cast<float*>(P.Df.ensure(sizeof(float) * rows * NK));
+  for (int l = 0; l <= P.L; l++) {
+    const LevelData& D = *P.lev[l];
+    if (D.ndelta == 0) continue;
+    const LevelGeom& lg = P.geo.lev[l];
+    const int64_t nt = (int64_t)D.ndelta * NK;
+    k_dtensor<<<ceil_div(nt, 256), 256, 0, st>>>(D.ndelta, D.delta_vec.as<int32_t>(), lg.g[0], lg.g[1], lg.g[2], K,
+                                                 dptr, dq, dval, D.drow0, Dd, Df);
+    CCFMM_HIP(hipGetLastError());
+  }
+  CCFMM_HIP(hipStreamSynchronize(st));  // host table buffers stay alive, scratch2 reused later
+}
+
+// ------------------------------------------------------------ moments in tree order
+template <typename T>
+__global__ void k_permute_moments(const double* __restrict__ m, const int32_t* __restrict__ perm, int64_t n,
+                                  int nb, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n) return;
+  const int64_t src = perm[i];
+  const double* mi = m + ((int64_t)b * n + src) * 3;
+  T* o = out + (int64_t)b * 3 * n;
+  o[i] = (T)mi[0];
+  o[n + i] = (T)mi[1];
+  o[2 * n + i] = (T)mi[2];
+}
+
+// ------------------------------------------------------------ P2M
+// One wavefront per (occupied smallest cell, configuration).  Eq.
+// (multipolemoments) in scaled units: Qt_n = sum_i sum_{a: n_a>0} m_ia yt^(n-e_a)/(n-e_a)!.
+// Lanes first tabulate yt^k/k! (|k| <= p-1) of kP2MChunk dipoles in LDS, then
+// each lane sums whole coefficients over those dipoles.
+constexpr int kP2MWaves = 4;
+constexpr int kP2MChunk = 16;
+
+template <typename T, int P>
+__global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restrict__ lstart,
+                                                       const int32_t* __restrict__ lcount, int32_t nleaf,
+                                                       const T* __restrict__ y, const T* __restrict__ msort,
+                                                       int64_t n, int nb, T* __restrict__ Q) {
+  constexpr int NM = ncoef(P - 1);  // monomials of degree <= p-1
+  constexpr int NP = nact(P);
+  constexpr int NS = nstride(P);
+  constexpr int NR = (NP + 63) / 64;
+  __shared__ T mono[kP2MWaves][kP2MChunk][NM + 1];
+  __shared__ T mm[kP2MWaves][kP2MChunk][3];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * kP2MWaves + w;
+  if (item >= (int64_t)nleaf * nb) return;
+  const int leaf = (int)(item / nb), b = (int)(item % nb);
+  const int first = lstart[leaf], cnt = lcount[leaf];
+  // source indices of coefficient n - e_a for this lane's coefficients
+  int srcx[NR], srcy[NR], srcz[NR];
+  T acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int t = lane + 64 * r + 1;  // flat index, |n| >= 1
+    acc[r] = (T)0;
+    srcx[r] = srcy[r] = srcz[r] = -1;
+    if (t <= NP) {
+      const int x = kMI.x[t], yy = kMI.y[t], z = kMI.z[t];
+      if (x > 0) srcx[r] = midx(x - 1, yy, z);
+      if (yy > 0) srcy[r] = midx(x, yy - 1, z);
+      if (z > 0) srcz[r] = midx(x, yy, z - 1);
+    }
+  }
+  const T* mb = msort + (int64_t)b * 3 * n;
+  for (int base = 0; base < cnt; base += kP2MChunk) {
+    const int nchunk = min(kP2MChunk, cnt - base);
+    if (lane < nchunk) {
+      const int64_t i = first + base + lane;
+      const T yx = y[i], yy = y[n + i], yz = y[2 * n + i];
+      T px[P], py[P], pz[P];
+      px[0] = py[0] = pz[0] = (T)1;
+#pragma unroll
+      for (int j = 1; j < P; j++) {
+        const T inv = (T)(1.0 / j);
+        px[j] = px[j - 1] * yx * inv;
+        py[j] = py[j - 1] * yy * inv;
+        pz[j] = pz[j - 1] * yz * inv;
+      }
+#pragma unroll
+      for (int t = 0; t < NM; t++) mono[w][lane][t] = px[kMI.x[t]] * py[kMI.y[t]] * pz[kMI.z[t]];
+      mm[w][lane][0] = mb[i];
+      mm[w][lane][1] = mb[n + i];
+      mm[w][lane][2] = mb[2 * n + i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = 0; j < nchunk; j++) {
+      const T m0 = mm[w][j][0], m1 = mm[w][j][1], m2 = mm[w][j][2];
+#pragma unroll
+      for (int r = 0; r < NR; r++) {
+        T s = acc[r];
+        if (srcx[r] >= 0) s += m0 * mono[w][j][srcx[r]];
+        if (srcy[r] >= 0) s += m1 * mono[w][j][srcy[r]];
+        if (srcz[r] >= 0) s += m2 * mono[w][j][srcz[r]];
+        acc[r] = s;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  T* q = Q + ((int64_t)leaf * nb + b) * NS;
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int a = lane + 64 * r;
+    if (a < NS) q[a] = (a < NP) ? acc[r] : (T)0;
+  }
+}
+
+// ------------------------------------------------------------ M2M
+// Eq.(momentshift) from level l+1 to l.  The two children sit at -/+ h_a/2 of
+// the parent centre along the halved axis a only, so Q_n(P) sums Q_{n-k e_a}(C)
+// over k; in scaled units the weight is gamma^k/k! rho^(|n|-k-1) with
+// gamma = (child centre - parent centre)_a / s_l and rho = s_{l+1}/s_l.
+template <typename T, int P>
+__global__ void k_m2m(int32_t ncells, const int32_t* __restrict__ child, int axis, double gam, double rho, int nb,
+                      const T* __restrict__ Qc, T* __restrict__ Qp) {
+  constexpr int NP = nact(P);
+  constexpr int NS = nstride(P);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ncells * nb * NS) return;
+  const int a = (int)(t % NS);
+  const int64_t cb = t / NS;
+  const int b = (int)(cb % nb);
+  const int c = (int)(cb / nb);
+  T* out = Qp + ((int64_t)c * nb + b) * NS;
+  if (a >= NP) {
+    out[a] = (T)0;
+    return;
+  }
+  const int f = a + 1;
+  int n[3] = {kMI.x[f], kMI.y[f], kMI.z[f]};
+  const int deg = n[0] + n[1] + n[2];
+  double s = 0.0;
+  for (int e = 0; e < 2; e++) {
+    const int ch = child[2 * c + e];
+    if (ch < 0) continue;
+    const double g = (e == 0) ? -gam : gam;
+    const T* qc = Qc + ((int64_t)ch * nb + b) * NS;
+    double gk = 1.0;  // gamma^k / k!
+    for (int k = 0; k <= n[axis]; k++) {
+      int m[3] = {n[0], n[1], n[2]};
+      m[axis] -= k;
+      const int dm = deg - k;
+      if (dm >= 1) {
+        double w = gk;
+        for (int j = 0; j < dm - 1; j++) w *= rho;
+        s += w * (double)qc[midx(m[0], m[1], m[2]) - 1];
+      }
+      gk = gk * g / (double)(k + 1);
+    }
+  }
+  out[a] = (T)s;
+}
+
+// ------------------------------------------------------------ L2L
+// Eq.(taylorshift) from level l to l+1 along the halved axis:
+// Vt_n(C) += sum_k gamma^k/k! rho^(|n|+2) Vt_{n+k e_a}(P).
+template <typename T, int P>
+__global__ void k_l2l(int32_t ncells, const int32_t* __restrict__ parent, const int32_t* __restrict__ key, int axis,
+                      double gam, double rho, int nb, const T* __restrict__ Vp, T* __restrict__ Vc) {
+  constexpr int NP = nact(P);
+  constexpr int NS = nstride(P);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ncells * nb * NP) return;
+  const int a = (int)(t % NP);
+  const int64_t cb = t / NP;
+  const int b = (int)(cb % nb);
+  const int c = (int)(cb / nb);
+  const int f = a + 1;
+  const int n[3] = {kMI.x[f], kMI.y[f], kMI.z[f]};
+  const int deg = n[0] + n[1] + n[2];
+  const double g = (key[c] & 1) ? gam : -gam;
+  const T* vp = Vp + ((int64_t)parent[c] * nb + b) * NS;
+  double rp = 1.0;
+  for (int j = 0; j < deg + 2; j++) rp *= rho;
+  double s = 0.0, gk = 1.0;
+  for (int k = 0; deg + k <= P; k++) {
+    int m[3] = {n[0], n[1], n[2]};
+    m[axis] += k;
+    s += gk * (double)vp[midx(m[0], m[1], m[2]) - 1];
+    gk = gk * g / (double)(k + 1);
+  }
+  T* out = Vc + ((int64_t)c * nb + b) * NS + a;
+  *out = (T)((double)*out + rp * s);
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+static T* qptr(Plan& P, DevBuf& buf, int l) {
+  return buf.as<T>() + P.lev[l]->qoff;
+}
+
+template <typename T, int PP>
+static void p2m_impl(Plan& P, int nb, const double* d_m, hipStream_t st) {
+  T* ms = P.m_sorted.as<T>();
+  dim3 g1(ceil_div(P.n, 256), nb);
+  k_permute_moments<T><<<g1, 256, 0, st>>>(d_m, P.perm.as<int32_t>(), P.n, nb, ms);
+  CCFMM_HIP(hipGetLastError());
+  const int nl = P.lev[P.L]->ncells;
+  const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
+  const int64_t items = (int64_t)nl * nb;
+  k_p2m<T, PP><<<ceil_div(items, kP2MWaves), 64 * kP2MWaves, 0, st>>>(P.lstart.as<int32_t>(), P.lcount.as<int32_t>(),
+                                                                    nl, y, ms, P.n, nb, qptr<T>(P, P.Q, P.L));
+  CCFMM_HIP(hipGetLastError());
+}
+
+template <typename T, int PP>
+static void m2m_impl(Plan& P, int nb, hipStream_t st) {
+  constexpr int NS = nstride(PP);
+  for (int l = P.L - 1; l >= 1; l--) {
+    const LevelData& D = *P.lev[l];
+    const int a = P.geo.lev[l + 1].axis;
+    const double gam = 0.5 * P.geo.lev[l + 1].h[a] / P.geo.lev[l].s;
+    const double rho = P.geo.lev[l + 1].s / P.geo.lev[l].s;
+    const int64_t nt = (int64_t)D.ncells * nb * NS;
+    k_m2m<T, PP><<<ceil_div(nt, 256), 256, 0, st>>>(D.ncells, D.child.as<int32_t>(), a, gam, rho, nb,
+                                                    qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l));
+    CCFMM_HIP(hipGetLastError());
+  }
+}
+
+template <typename T, int PP>
+static void l2l_impl(Plan& P, int nb, hipStream_t st) {
+  constexpr int NP = nact(PP);
+  for (int l = 1; l < P.L; l++) {
+    const LevelData& C = *P.lev[l + 1];
+    const int a = P.geo.lev[l + 1].axis;
+    const double gam = 0.5 * P.geo.lev[l + 1].h[a] / P.geo.lev[l].s;
+    const double rho = P.geo.lev[l + 1].s / P.geo.lev[l].s;
+    const int64_t nt = (int64_t)C.ncells * nb * NP;
+    k_l2l<T, PP><<<ceil_div(nt, 256), 256, 0, st>>>(C.ncells, C.parent.as<int32_t>(), C.key.as<int32_t>(), a, gam,
+                                                    rho, nb, qptr<T>(P, P.V, l), qptr<T>(P, P.V, l + 1));
+    CCFMM_HIP(hipGetLastError());
+  }
+}
+
+#define CCFMM_DISPATCH_P(P_, FN, ...)                        \
+  switch (P_) {                                              \
+    case 1: FN<1>(__VA_ARGS__); break;                       \
+    case 2: FN<2>(__VA_ARGS__); break;                       \
+    case 3: FN<3>(__VA_ARGS__); break;                       \
+    case 4: FN<4>(__VA_ARGS__); break;                       \
+    case 5: FN<5>(__VA_ARGS__); break;                       \
+    case 6: FN<6>(__VA_ARGS__); break;                       \
+    case 7: FN<7>(__VA_ARGS__); break;                       \
+    case 8: FN<8>(__VA_ARGS__); break;                       \
+    default: fail(CCFMM_EINVAL, "order out of range");       \
+  }
+
+template <int PP>
+static void p2m_d(Plan& P, int nb, const double* d_m, hipStream_t st) {
+  if (P.precision == CCFMM_PREC_FP64)
+    p2m_impl<double, PP>(P, nb, d_m, st);
+  else
+    p2m_impl<float, PP>(P, nb, d_m, st);
+}
+template <int PP>
+static void m2m_d(Plan& P, int nb, hipStream_t st) {
+  if (P.precision == CCFMM_PREC_FP64)
+    m2m_impl<double, PP>(P, nb, st);
+  else
+    m2m_impl<float, PP>(P, nb, st);
+}
+template <int PP>
+static void l2l_d(Plan& P, int nb, hipStream_t st) {
+  if (P.precision == CCFMM_PREC_FP64)
+    l2l_impl<double, PP>(P, nb, st);
+  else
+    l2l_impl<float, PP>(P, nb, st);
+}
+
+void run_p2m(Plan& P, int nb, const double* d_m, hipStream_t st) { CCFMM_DISPATCH_P(P.p, p2m_d, P, nb, d_m, st); }
+void run_m2m(Plan& P, int nb, hipStream_t st) { CCFMM_DISPATCH_P(P.p, m2m_d, P, nb, st); }
+void run_l2l(Plan& P, int nb, hipStream_t st) { CCFMM_DISPATCH_P(P.p, l2l_d, P, nb, st); }
+
+}  // namespace ccfmm

@@ -1,0 +1,142 @@
+// internal.hpp -- shared declarations of the ccfmm HIP library (gfx950).
+//
+// Indexing of Cartesian multi-indices n = (nx, ny, nz) (Sec. 3 notation):
+// degree-major, then nx descending, then ny descending.  The flat index of n
+// with degree d = |n| is N(d-1) + u(u+1)/2 + nz with u = d - nx, where
+// N(d) = (d+1)(d+2)(d+3)/6 counts the multi-indices of degree <= d.
+// Expansions keep only the "active" coefficients 1 <= |n| <= p: a dipole
+// distribution has no monopole (Q_0 = 0) and the field needs no V_0.
+// Active coefficient a <-> flat index a + 1.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ccfmm.h"
+
+namespace ccfmm {
+
+constexpr int kPMax = CCFMM_PMAX;
+constexpr int kLMax = CCFMM_LMAX;
+constexpr int kKMax = 2 * kPMax;  // derivative tensors up to order 2p
+
+__host__ __device__ constexpr int ncoef(int d) { return d < 0 ? 0 : (d + 1) * (d + 2) * (d + 3) / 6; }
+__host__ __device__ constexpr int midx(int a, int b, int c) {
+  return ncoef(a + b + c - 1) + (b + c) * (b + c + 1) / 2 + c;
+}
+// active coefficients of order p, and the padded stride of one expansion
+__host__ __device__ constexpr int nact(int p) { return ncoef(p) - 1; }
+__host__ __device__ constexpr int nstride(int p) { return (nact(p) + 3) & ~3; }
+
+template <int K>
+struct MultiIndexTable {
+  int8_t x[ncoef(K)], y[ncoef(K)], z[ncoef(K)];
+  constexpr MultiIndexTable() : x{}, y{}, z{} {
+    int t = 0;
+    for (int d = 0; d <= K; d++)
+      for (int a = d; a >= 0; a--)
+        for (int b = d - a; b >= 0; b--) {
+          x[t] = (int8_t)a;
+          y[t] = (int8_t)b;
+          z[t] = (int8_t)(d - a - b);
+          t++;
+        }
+  }
+};
+__device__ constexpr MultiIndexTable<kKMax> kMI{};
+
+// 1/k! for k <= 16
+struct InvFact {
+  double v[kKMax + 1];
+  constexpr InvFact() : v{} {
+    double f = 1.0;
+    v[0] = 1.0;
+    for (int k = 1; k <= kKMax; k++) {
+      f *= k;
+      v[k] = 1.0 / f;
+    }
+  }
+};
+__device__ constexpr InvFact kInvFact{};
+
+// ---------------------------------------------------------------------------
+// Geometry of one tree level (uniform-depth bisection tree).
+//   h[a]  cell side, s = smallest side (the level's length unit),
+//   g[a]  = h[a] / s, k[a] = halvings of axis a so far, axis = axis halved to
+//   reach this level (-1 at the root).
+// Scaled expansions at level l: Qt_n = Q_n s^(1-|n|), Vt_n = V_n s^(|n|+2);
+// then M2L reads Vt_n = (-1)^|n| sum_q D_{n+q}(delta*g) Qt_q with integer
+// cell offsets delta, independent of the level's absolute size.
+// ---------------------------------------------------------------------------
+struct LevelGeom {
+  double h[3];
+  double g[3];
+  double s;
+  int k[3];
+  int axis;
+};
+
+struct Workspace;
+
+// Flat description of one M2L work tile for one wavefront: up to 16 columns
+// (target cell, configuration); the Q columns of step t come from
+// step_src[(step0 + t) * 16 + col].
+struct M2LTile {
+  int32_t level;
+  int32_t step0;
+  int32_t nsteps;
+  int32_t tgt0;     // first entry in tile_tgt (16 entries, -1 = unused column group)
+  int32_t b0;       // first configuration of the tile
+  int32_t pad[3];
+};
+
+// P2P / L2P work chunk: up to 64 consecutive sorted dipoles of one leaf.
+struct P2PChunk {
+  int32_t leaf;     // compact leaf index at level L
+  int32_t first;    // first sorted dipole
+  int32_t count;    // <= 64
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Device buffer with grow-only capacity.
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  void* ensure(size_t bytes);
+  void release();
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+  ~DevBuf() { release(); }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+struct HipError {
+  hipError_t code;
+  std::string what;
+};
+struct StatusError {
+  int status;
+  std::string what;
+};
+
+void check_hip(hipError_t e, const char* what);
+#define CCFMM_HIP(x) ::ccfmm::check_hip((x), #x)
+[[noreturn]] void fail(int status, const std::string& msg);
+
+// ---------------------------------------------------------------------------
+// Primitives (tree.hip)
+// ---------------------------------------------------------------------------
+// exclusive scan of n int32 values into out (out may alias in); returns nothing,
+// total is written to out[n] (out must hold n+1 ints).
+void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
+// stable LSD radix sort of (key, val) pairs by the low `bits` bits of key
+void radix_sort_pairs(uint32_t* key, int32_t* val, uint32_t* key_tmp, int32_t* val_tmp, int64_t n,
+                      int bits, DevBuf& tmp, hipStream_t st);
+
+}  // namespace ccfmm

@@ -1,0 +1,245 @@
+// p2p.hip -- the field at the dipoles: smooth part from the local expansion
+// (Eq. H, with H = -grad V) plus the direct sum over the near smallest cells
+// (Eq. H2, read as the field of source dipole j: (3 (m_j.u) u - m_j)/r^3, pairs
+// at zero separation skipped), accumulated in FP64 and written in the
+// caller's dipole order.
+//
+// One wavefront per chunk of <= 64 dipoles of one smallest cell.  A chunk of
+// c dipoles gets G = 64 / pow2ceil(c) lanes per dipole; the lanes of a dipole
+// split the sources, and their partial fields are combined with cross-lane
+// butterflies at the end.  Sources are staged 64 at a time in LDS, shifted by
+// the integer offset of their cell so all coordinates stay cell-relative.
+#include "plan.hpp"
+
+namespace ccfmm {
+
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T x);
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double x) {
+  // hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kP2PWaves = 4;
+
+struct P2PArgs {
+  const P2PChunk* chunks;
+  int64_t nchunks;
+  const int32_t* near_ptr;   // level L, compact leaves
+  const int32_t* near_idx;
+  const int32_t* coord;      // level L, compact leaves
+  const int32_t* lstart;
+  const int32_t* lcount;
+  const int32_t* perm;
+  int64_t n;
+  int nb;
+  double g[3];               // leaf sides / smallest leaf side
+  double inv_s3;             // 1 / s_L^3
+  int64_t voff;              // offset of level L in V
+};
+
+template <typename T, int P>
+__global__ void __launch_bounds__(64 * kP2PWaves) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
+                                                           const T* __restrict__ msort, const T* __restrict__ V,
+                                                           double* __restrict__ H) {
+  constexpr int NP = nact(P);
+  constexpr int NS = nstride(P);
+  constexpr int NM = ncoef(P - 1);
+  __shared__ T sx[kP2PWaves][64], sy[kP2PWaves][64], sz[kP2PWaves][64];
+  __shared__ T smx[kP2PWaves][64], smy[kP2PWaves][64], smz[kP2PWaves][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * kP2PWaves + w;
+  const int b = blockIdx.y;
+  if (item >= a.nchunks) return;
+  const P2PChunk ch = a.chunks[item];
+  const int n = (int)a.n;
+  int cpow = 1;
+  while (cpow < ch.count) cpow <<= 1;
+  const int G = 64 / cpow;
+  const int t = lane / G, sub = lane % G;
+  const bool active = t < ch.count;
+  const int64_t i = ch.first + (active ? t : 0);
+  const T yx = y[i], yy = y[n + i], yz = y[2 * n + i];
+  const T* mb = msort + (int64_t)b * 3 * n;
+  const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
+  double hx = 0.0, hy = 0.0, hz = 0.0;  // near field, cell-relative units
+  for (int e = a.near_ptr[ch.leaf]; e < a.near_ptr[ch.leaf + 1]; e++) {
+    const int S = a.near_idx[e];
+    const T ox = (T)((a.coord[3 * S] - cx) * a.g[0]);
+    const T oy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
+    const T oz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
+    const int s0 = a.lstart[S], sn = a.lcount[S];
+    T fx = (T)0, fy = (T)0, fz = (T)0;
+    for (int base = 0; base < sn; base += 64) {
+      const int nsrc = min(64, sn - base);
+      if (lane < nsrc) {
+        const int64_t j = s0 + base + lane;
+        sx[w][lane] = y[j] + ox;
+        sy[w][lane] = y[n + j] + oy;
+        sz[w][lane] = y[2 * n + j] + oz;
+        smx[w][lane] = mb[j];
+        smy[w][lane] = mb[n + j];
+        smz[w][lane] = mb[2 * n + j];
+      }
+      wave_lds_sync();
+      for (int q = sub; q < nsrc; q += G) {
+        const T rx = yx - sx[w][q], ry = yy - sy[w][q], rz = yz - sz[w][q];
+        const T r2 = rx * rx + ry * ry + rz * rz;
+        const T inv = (r2 > (T)0) ? rsqrt_t<T>(r2) : (T)0;
+        const T inv2 = inv * inv;
+        const T inv3 = inv2 * inv;
+        const T mr = smx[w][q] * rx + smy[w][q] * ry + smz[w][q] * rz;
+        const T c = (T)3 * mr * inv2 * inv3;
+        fx += c * rx - inv3 * smx[w][q];
+        fy += c * ry - inv3 * smy[w][q];
+        fz += c * rz - inv3 * smz[w][q];
+      }
+      wave_lds_sync();
+    }
+    hx += (double)fx;
+    hy += (double)fy;
+    hz += (double)fz;
+  }
+  // combine the G lanes of each dipole
+  for (int off = 1; off < G; off <<= 1) {
+    hx += __shfl_xor(hx, off);
+    hy += __shfl_xor(hy, off);
+    hz += __shfl_xor(hz, off);
+  }
+  if (!active || sub != 0) return;
+  // smooth field from the local expansion: H_a = -sum_k Vt_{k+e_a} yt^k/k!
+  const T* v = V + a.voff + ((int64_t)ch.leaf * a.nb + b) * NS;
+  T px[P], py[P], pz[P];
+  px[0] = py[0] = pz[0] = (T)1;
+#pragma unroll
+  for (int j = 1; j < P; j++) {
+    const T inv = (T)(1.0 / j);
+    px[j] = px[j - 1] * yx * inv;
+    py[j] = py[j - 1] * yy * inv;
+    pz[j] = pz[j - 1] * yz * inv;
+  }
+  T ex = (T)0, ey = (T)0, ez = (T)0;
+#pragma unroll
+  for (int k = 0; k < NM; k++) {
+    const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
+    const T mono = px[kx] * py[ky] * pz[kz];
+    ex += v[midx(kx + 1, ky, kz) - 1] * mono;
+    ey += v[midx(kx, ky + 1, kz) - 1] * mono;
+    ez += v[midx(kx, ky, kz + 1) - 1] * mono;
+  }
+  (void)NP;
+  const double s3 = a.inv_s3;
+  const int64_t o = ((int64_t)b * n + a.perm[i]) * 3;
+  H[o] = s3 * (hx - (double)ex);
+  H[o + 1] = s3 * (hy - (double)ey);
+  H[o + 2] = s3 * (hz - (double)ez);
+}
+
+template <typename T, int PP>
+static void p2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
+  LevelData& D = *P.lev[P.L];
+  P2PArgs a;
+  a.chunks = P.chunks.as<P2PChunk>();
+  a.nchunks = P.nchunks;
+  a.near_ptr = D.near_ptr.as<int32_t>();
+  a.near_idx = D.near_idx.as<int32_t>();
+  a.coord = D.coord.as<int32_t>();
+  a.lstart = P.lstart.as<int32_t>();
+  a.lcount = P.lcount.as<int32_t>();
+  a.perm = P.perm.as<int32_t>();
+  a.n = P.n;
+  a.nb = nb;
+  for (int q = 0; q < 3; q++) a.g[q] = P.geo.lev[P.L].g[q];
+  const double s = P.geo.lev[P.L].s;
+  a.inv_s3 = 1.0 / (s * s * s);
+  a.voff = D.qoff;
+  const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
+  dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
+  k_p2p_l2p<T, PP><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
+  CCFMM_HIP(hipGetLastError());
+}
+
+template <int PP>
+static void p2p_d(Plan& P, int nb, double* d_H, hipStream_t st) {
+  if (P.precision == CCFMM_PREC_FP64)
+    p2p_impl<double, PP>(P, nb, d_H, st);
+  else
+    p2p_impl<float, PP>(P, nb, d_H, st);
+}
+
+void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st) {
+  switch (P.p) {
+    case 1: p2p_d<1>(P, nb, d_H, st); break;
+    case 2: p2p_d<2>(P, nb, d_H, st); break;
+    case 3: p2p_d<3>(P, nb, d_H, st); break;
+    case 4: p2p_d<4>(P, nb, d_H, st); break;
+    case 5: p2p_d<5>(P, nb, d_H, st); break;
+    case 6: p2p_d<6>(P, nb, d_H, st); break;
+    case 7: p2p_d<7>(P, nb, d_H, st); break;
+    case 8: p2p_d<8>(P, nb, d_H, st); break;
+    default: fail(CCFMM_EINVAL, "order out of range");
+  }
+}
+
+// ------------------------------------------------------------ direct sum
+// FP64 O(N) per target: the plain definition of the field at sampled targets,
+// one wavefront per target, sources split over lanes and reduced by butterfly.
+__global__ void __launch_bounds__(256) k_direct_targets(int64_t n, const double* __restrict__ pos,
+                                                        const double* __restrict__ m, int64_t nt,
+                                                        const int64_t* __restrict__ idx, double* __restrict__ H) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + w;
+  if (t >= nt) return;
+  const int64_t i = idx[t];
+  if (i < 0 || i >= n) {  // out-of-range target: report NaN, touch nothing
+    if (lane == 0) H[3 * t] = H[3 * t + 1] = H[3 * t + 2] = __builtin_nan("");
+    return;
+  }
+  const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  double hx = 0.0, hy = 0.0, hz = 0.0;
+  for (int64_t j = lane; j < n; j += 64) {
+    const double rx = xi - pos[3 * j], ry = yi - pos[3 * j + 1], rz = zi - pos[3 * j + 2];
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 == 0.0) continue;
+    const double inv = 1.0 / sqrt(r2);
+    const double inv3 = inv * inv * inv;
+    const double mr = m[3 * j] * rx + m[3 * j + 1] * ry + m[3 * j + 2] * rz;
+    const double c = 3.0 * mr * inv * inv * inv3;
+    hx += c * rx - inv3 * m[3 * j];
+    hy += c * ry - inv3 * m[3 * j + 1];
+    hz += c * rz - inv3 * m[3 * j + 2];
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    hx += __shfl_xor(hx, off);
+    hy += __shfl_xor(hy, off);
+    hz += __shfl_xor(hz, off);
+  }
+  if (lane == 0) {
+    H[3 * t] = hx;
+    H[3 * t + 1] = hy;
+    H[3 * t + 2] = hz;
+  }
+}
+
+void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt, const int64_t* d_idx,
+                        double* d_H, hipStream_t st) {
+  if (nt <= 0) return;
+  k_direct_targets<<<ceil_div(nt, 4), 256, 0, st>>>(n, d_pos, d_m, nt, d_idx, d_H);
+  CCFMM_HIP(hipGetLastError());
+}
+
+}  // namespace ccfmm

@@ -1,0 +1,110 @@
+// plan.hpp -- the plan object: tree, lists, derivative tensors and M2L tiles
+// of one geometry, plus the expansion buffers of its evaluations.
+#pragma once
+#include <memory>
+
+#include "internal.hpp"
+
+namespace ccfmm {
+
+// Geometry passed by value to kernels that need the level table.
+struct TreeGeom {
+  LevelGeom lev[kLMax + 1];
+  double lo[3];
+  double W[3];
+  int L;
+  int pad;
+};
+
+struct LevelData {
+  int32_t ncells = 0;   // occupied cells
+  int64_t heap0 = 0;    // first heap id of the level (2^l - 1)
+  DevBuf key;           // compact -> key (int32)
+  DevBuf coord;         // compact -> integer cell coordinates (3 int32)
+  DevBuf parent;        // compact -> parent compact (int32), level >= 1
+  DevBuf child;         // compact -> 2 child compact (int32, -1 empty), level < L
+  DevBuf near_ptr;      // CSR (ncells+1) of near cells (compact), self included
+  DevBuf near_idx;
+  int64_t nnear = 0;
+  DevBuf far_ptr;       // CSR (ncells+1) of far cells (M2L sources)
+  DevBuf far_idx;
+  DevBuf far_did;       // Delta id (level-local) of each far entry
+  int64_t nfar = 0;
+  int32_t ndelta = 0;
+  int64_t drow0 = 0;    // first row of this level in the derivative-tensor table
+  int wbox[3] = {0, 0, 0};  // Delta box half-widths
+  DevBuf delta_vec;     // ndelta * 3 int32
+  // M2L tiling
+  DevBuf order;         // tile order position -> compact target
+  int32_t ngroups = 0;  // target groups of TC cells
+  int64_t step0 = 0;    // first global step of the level
+  int64_t nsteps = 0;
+  int64_t tile0 = 0;
+  int64_t ntiles = 0;
+  int64_t qoff = 0;     // element offset of the level in Q/V
+};
+
+struct Plan {
+  int device = 0;
+  int64_t n = 0;
+  ccfmm_params prm{};
+  int p = 0, L = 0;
+  int precision = 0;
+  int nbmax = 1;
+  int class_bits = 3;
+  double s_used = 0.0;
+  TreeGeom geo{};
+  hipStream_t own_stream = nullptr;
+
+  // sorted dipoles
+  DevBuf pos;        // [n][3] FP64 input order (device copy)
+  DevBuf key, val, key_tmp, val_tmp;
+  DevBuf perm;       // sorted -> input index (int32)
+  DevBuf yd;         // SoA [3][n] FP64 leaf-relative scaled offsets
+  DevBuf yf;         // SoA [3][n] FP32
+  DevBuf leaf_start; // 2^L + 1 (int32), by leaf key
+  DevBuf lstart, lcount;  // per occupied leaf (compact)
+  DevBuf heap_flag, heap_scan;  // occupancy and compact ids over all heap cells
+  DevBuf cmap;       // heap id -> compact id within its level, -1 if empty
+  std::vector<std::unique_ptr<LevelData>> lev;
+
+  // derivative tensors: rows (level, delta), ncoef(2p) values each
+  int64_t nrows = 0;
+  DevBuf Dd, Df;
+  // M2L tiles
+  int TB = 16, TC = 1, ncg = 1;  // configs per tile, targets per tile, config groups
+  DevBuf tiles, tile_tgt, step_delta, step_src, bitmap;
+  int64_t ntiles = 0, nsteps = 0;
+  // P2P chunks
+  DevBuf chunks;
+  int64_t nchunks = 0;
+  // expansions (compact cells of all levels)
+  DevBuf Q, V;
+  int64_t qv_elems = 0;
+  int qv_batch = 0;  // nbatch the Q/V buffers are laid out for
+  DevBuf m_sorted;   // moments in sorted order [b][3][n] (FP64 or FP32)
+  DevBuf scratch;    // scan/sort temporaries
+  DevBuf scratch2;
+  ccfmm_info info{};
+  bool built = false;
+};
+
+// build steps (tree.hip, lists.hip, expansions.hip)
+void build_tree(Plan& P, const double* d_pos, hipStream_t st);
+void build_lists(Plan& P, hipStream_t st);
+void build_dtensors(Plan& P, hipStream_t st);
+void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st);
+void build_p2p_chunks(Plan& P, hipStream_t st);
+
+// evaluation passes
+void run_p2m(Plan& P, int nb, const double* d_m, hipStream_t st);
+void run_m2m(Plan& P, int nb, hipStream_t st);
+void run_m2l(Plan& P, int nb, hipStream_t st);
+void run_l2l(Plan& P, int nb, hipStream_t st);
+void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st);
+void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt,
+                        const int64_t* d_idx, double* d_H, hipStream_t st);
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace ccfmm

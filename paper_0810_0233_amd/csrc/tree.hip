@@ -1,0 +1,412 @@
+// tree.hip -- bisection tree on the GPU: leaf keys, stable radix sort,
+// smallest-cell ranges, sorted SoA offsets and the occupied cells per level.
+//
+// The system box is halved recursively (Sec. 2); level l halves the longest
+// side of the level-(l-1) cell, ties x < y < z, so the smallest cells are as
+// cubic as the halving allows (Sec. 4).  The key of a cell at level l is the
+// sequence of its l half-choices (1 = upper half), so the children of key k
+// are 2k and 2k+1 and a dipole's smallest-cell key orders dipoles cell by
+// cell (a Morton order in the split sequence).
+#include "plan.hpp"
+
+namespace ccfmm {
+
+// ---------------------------------------------------------------- scan
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* sh, int32_t& total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int32_t add = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int32_t incl = sh[t];
+  total = sh[kScanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t* in, int32_t* out,
+                                                             int32_t* sums, int64_t n) {
+  __shared__ int32_t sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+  int32_t s = 0;
+  for (int i = 0; i < kScanItems; i++) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    s += v[i];
+  }
+  int32_t total;
+  int32_t ex = block_exclusive_scan(s, sh, total);
+  for (int i = 0; i < kScanItems; i++) {
+    if (base + i < n) out[base + i] = ex;
+    ex += v[i];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(int32_t* out, const int32_t* sums, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  const int32_t add = sums[blockIdx.x];
+  for (int r = 0; r < kScanItems; r++) {
+    int64_t j = i + (int64_t)r * kScanThreads;
+    if (j < n) out[j] += add;
+  }
+}
+
+static void scan_rec(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t st) {
+  const int nb = ceil_div(n, kScanTile);
+  int32_t* sums = tmp;
+  k_scan_tiles<<<nb, kScanThreads, 0, st>>>(in, out, sums, n);
+  CCFMM_HIP(hipGetLastError());
+  if (nb > 1) {
+    scan_rec(sums, sums, nb, tmp + nb, st);
+    k_scan_add<<<nb, kScanThreads, 0, st>>>(out, sums, n);
+    CCFMM_HIP(hipGetLastError());
+  }
+}
+
+__global__ void k_copy_last(const int32_t* in, int64_t n, int32_t* last) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) last[0] = (n > 0) ? in[n - 1] : 0;
+}
+__global__ void k_finish_total(int32_t* out, int64_t n, const int32_t* last) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n > 0) ? out[n - 1] + last[0] : 0;
+}
+
+void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st) {
+  // temporaries: block sums of every recursion level + the saved last input
+  int64_t need = 4;
+  for (int64_t m = n; m > 1; m = ceil_div(m, kScanTile)) need += ceil_div(m, kScanTile) + 1;
+  int32_t* t = reinterpret_cast<int32_t*>(tmp.ensure(sizeof(int32_t) * (need + 8)));
+  if (n <= 0) {
+    k_finish_total<<<1, 1, 0, st>>>(out, 0, t);
+    return;
+  }
+  k_copy_last<<<1, 1, 0, st>>>(in, n, t);
+  scan_rec(in, out, n, t + 4, st);
+  k_finish_total<<<1, 1, 0, st>>>(out, n, t);
+  CCFMM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- radix sort
+// Stable LSD radix sort, 8-bit digits.  Each block owns a tile of
+// kSortThreads * kSortRounds keys processed in rounds of kSortThreads; inside
+// a round the rank of a key among equal digits of lower thread index comes
+// from wavefront ballots, then a prefix over the block's wavefronts.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kWaves = kSortThreads / 64;
+
+__global__ void __launch_bounds__(kSortThreads) k_digit_hist(const uint32_t* key, int64_t n, int shift,
+                                                             int32_t* hist, int nblocks) {
+  __shared__ int32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; r++) {
+    int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(key[i] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_digit_scatter(const uint32_t* key, const int32_t* val,
+                                                                uint32_t* key_out, int32_t* val_out,
+                                                                int64_t n, int shift,
+                                                                const int32_t* offs, int nblocks) {
+  __shared__ int32_t base[256];
+  __shared__ int32_t wcnt[kWaves][256];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortRounds; r++) {
+    for (int q = 0; q < kWaves; q++) wcnt[q][t] = 0;
+    __syncthreads();
+    const int64_t i = tile0 + (int64_t)r * kSortThreads + t;
+    const bool valid = i < n;
+    uint32_t k = valid ? key[i] : 0u;
+    int32_t v = valid ? val[i] : 0;
+    const uint32_t d = (k >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < 8; b++) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    // prefix over wavefronts for digit t, and this round's total
+    int32_t run = 0;
+    int32_t pre[kWaves];
+    for (int q = 0; q < kWaves; q++) {
+      pre[q] = run;
+      run += wcnt[q][t];
+    }
+    __syncthreads();
+    for (int q = 0; q < kWaves; q++) wcnt[q][t] = pre[q];
+    __syncthreads();
+    if (valid) {
+      const int32_t pos = base[d] + wcnt[w][d] + rank;
+      key_out[pos] = k;
+      val_out[pos] = v;
+    }
+    __syncthreads();
+    base[t] += run;
+    __syncthreads();
+  }
+}
+
+void radix_sort_pairs(uint32_t* key, int32_t* val, uint32_t* key_tmp, int32_t* val_tmp, int64_t n,
+                      int bits, DevBuf& tmp, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return;
+  const int nblocks = ceil_div(n, kSortTile);
+  const int64_t nh = (int64_t)256 * nblocks;
+  // histogram + its scan live behind the scan temporaries in a second region
+  DevBuf& hb = tmp;
+  int64_t scan_need = 4;
+  for (int64_t m = nh; m > 1; m = ceil_div(m, kScanTile)) scan_need += ceil_div(m, kScanTile) + 1;
+  size_t bytes = sizeof(int32_t) * (2 * (nh + 1) + scan_need + 16);
+  int32_t* h = reinterpret_cast<int32_t*>(hb.ensure(bytes));
+  int32_t* hist = h;
+  int32_t* offs = h + nh + 1;
+  int32_t* stmp = offs + nh + 1;
+  uint32_t* kin = key;
+  int32_t* vin = val;
+  uint32_t* kout = key_tmp;
+  int32_t* vout = val_tmp;
+  int passes = (bits + 7) / 8;
+  for (int ps = 0; ps < passes; ps++) {
+    const int shift = 8 * ps;
+    k_digit_hist<<<nblocks, kSortThreads, 0, st>>>(kin, n, shift, hist, nblocks);
+    CCFMM_HIP(hipGetLastError());
+    // exclusive scan of the digit-major histogram
+    scan_rec(hist, offs, nh, stmp + 4, st);
+    k_digit_scatter<<<nblocks, kSortThreads, 0, st>>>(kin, vin, kout, vout, n, shift, offs, nblocks);
+    CCFMM_HIP(hipGetLastError());
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  if (kin != key) {
+    CCFMM_HIP(hipMemcpyAsync(key, kin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+    CCFMM_HIP(hipMemcpyAsync(val, vin, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  }
+}
+
+// ---------------------------------------------------------------- tree
+// Smallest-cell coordinate along one axis: floor((x - lo) 2^k / W) clamped to
+// [0, 2^k - 1] (a point on a face goes to the upper cell, the top face to the
+// last cell), with exactly this IEEE sequence and no contraction.
+__device__ __forceinline__ int32_t leaf_coord(double x, double lo, double W, int k) {
+#pragma clang fp contract(off)
+  double t = x - lo;
+  t = t * ldexp(1.0, k);
+  double u = t / W;
+  double f = floor(u);
+  int32_t top = (1 << k) - 1;
+  if (f < 0.0) return 0;
+  if (f > (double)top) return top;
+  return (int32_t)f;
+}
+
+__global__ void k_leaf_keys(const double* __restrict__ pos, int64_t n, TreeGeom G, uint32_t* key,
+                            int32_t* val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int L = G.L;
+  int32_t c[3];
+  for (int a = 0; a < 3; a++) c[a] = leaf_coord(pos[3 * i + a], G.lo[a], G.W[a], G.lev[L].k[a]);
+  uint32_t k = 0;
+  for (int l = 1; l <= L; l++) {
+    const int a = G.lev[l].axis;
+    const uint32_t bit = (uint32_t)(c[a] >> (G.lev[L].k[a] - G.lev[l].k[a])) & 1u;
+    k = (k << 1) | bit;
+  }
+  key[i] = k;
+  val[i] = (int32_t)i;
+}
+
+// integer coordinates of the cell with key `key` at level l
+__device__ __forceinline__ void cell_coords(const TreeGeom& G, int l, uint32_t key, int32_t c[3]) {
+  c[0] = c[1] = c[2] = 0;
+  for (int j = 1; j <= l; j++) {
+    const int a = G.lev[j].axis;
+    const int32_t bit = (int32_t)((key >> (l - j)) & 1u);
+    c[a] |= bit << (G.lev[l].k[a] - G.lev[j].k[a]);
+  }
+}
+
+__global__ void k_leaf_start(const uint32_t* key, int64_t n, int64_t nleaf, int32_t* start) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nleaf) return;
+  // lower bound of k in the sorted keys
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  start[k] = (int32_t)lo;
+}
+
+__global__ void k_gather_sorted(const double* __restrict__ pos, const uint32_t* __restrict__ key,
+                                const int32_t* __restrict__ perm, int64_t n, TreeGeom G, double* yd,
+                                float* yf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int L = G.L;
+  int32_t c[3];
+  cell_coords(G, L, key[i], c);
+  const int64_t src = perm[i];
+  const double inv_s = 1.0 / G.lev[L].s;
+  for (int a = 0; a < 3; a++) {
+    const double center = G.lo[a] + ((double)c[a] + 0.5) * G.lev[L].h[a];
+    const double y = (pos[3 * src + a] - center) * inv_s;
+    yd[a * n + i] = y;
+    yf[a * n + i] = (float)y;
+  }
+}
+
+// occupancy of every heap cell (level l, key k) <-> heap id 2^l - 1 + k
+__global__ void k_heap_flags(const int32_t* __restrict__ leaf_start, int L, int64_t nheap,
+                             int32_t* flag) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= nheap) return;
+  int l = 63 - __clzll((unsigned long long)(h + 1));
+  int64_t k = h - ((1ll << l) - 1);
+  int sh = L - l;
+  int64_t a = k << sh, b = (k + 1) << sh;
+  flag[h] = (leaf_start[b] > leaf_start[a]) ? 1 : 0;
+}
+
+struct LevelPtrs {
+  int32_t* key[kLMax + 1];
+  int32_t* parent[kLMax + 1];
+  int32_t* child[kLMax + 1];
+  int64_t start[kLMax + 2];  // compact start of each level in the heap scan
+};
+
+__global__ void k_compact_cells(const int32_t* __restrict__ flag, const int32_t* __restrict__ scan,
+                                int L, int64_t nheap, LevelPtrs lp, int32_t* cmap) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= nheap) return;
+  int l = 63 - __clzll((unsigned long long)(h + 1));
+  if (!flag[h]) {
+    cmap[h] = -1;
+    return;
+  }
+  const int32_t c = (int32_t)(scan[h] - lp.start[l]);
+  cmap[h] = c;
+  const int64_t k = h - ((1ll << l) - 1);
+  lp.key[l][c] = (int32_t)k;
+}
+
+__global__ void k_link_cells(const int32_t* __restrict__ flag, const int32_t* __restrict__ cmap, int L,
+                             int64_t nheap, LevelPtrs lp) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= nheap || !flag[h]) return;
+  int l = 63 - __clzll((unsigned long long)(h + 1));
+  const int32_t c = cmap[h];
+  if (l > 0) lp.parent[l][c] = cmap[(h - 1) >> 1];
+  if (l < L) {
+    lp.child[l][2 * c] = cmap[2 * h + 1];
+    lp.child[l][2 * c + 1] = cmap[2 * h + 2];
+  }
+}
+
+__global__ void k_cell_coords(const int32_t* __restrict__ key, int32_t nc, int l, TreeGeom G,
+                              int32_t* coord) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int32_t c[3];
+  cell_coords(G, l, (uint32_t)key[i], c);
+  coord[3 * i] = c[0];
+  coord[3 * i + 1] = c[1];
+  coord[3 * i + 2] = c[2];
+}
+
+__global__ void k_leaf_ranges(const int32_t* __restrict__ lkey, const int32_t* __restrict__ leaf_start,
+                              int32_t nl, int32_t* lstart, int32_t* lcount) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  const int32_t k = lkey[i];
+  lstart[i] = leaf_start[k];
+  lcount[i] = leaf_start[k + 1] - leaf_start[k];
+}
+
+void build_tree(Plan& P, const double* d_pos, hipStream_t st) {
+  const int64_t n = P.n;
+  const int L = P.L;
+  TreeGeom& G = P.geo;
+  const int T = 256;
+  uint32_t* key = P.key.as<uint32_t>();
+  int32_t* val = P.val.as<int32_t>();
+  k_leaf_keys<<<ceil_div(n, T), T, 0, st>>>(d_pos, n, G, key, val);
+  CCFMM_HIP(hipGetLastError());
+  radix_sort_pairs(key, val, P.key_tmp.as<uint32_t>(), P.val_tmp.as<int32_t>(), n, L, P.scratch, st);
+  const int64_t nleaf = 1ll << L;
+  int32_t* ls = P.leaf_start.as<int32_t>();
+  k_leaf_start<<<ceil_div(nleaf + 1, T), T, 0, st>>>(key, n, nleaf, ls);
+  CCFMM_HIP(hipGetLastError());
+  // sorted -> input order is the sorted val array
+  CCFMM_HIP(hipMemcpyAsync(P.perm.p, val, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  k_gather_sorted<<<ceil_div(n, T), T, 0, st>>>(d_pos, key, P.perm.as<int32_t>(), n, G,
+                                                P.yd.as<double>(), P.yf.as<float>());
+  CCFMM_HIP(hipGetLastError());
+
+  const int64_t nheap = (2ll << L) - 1;
+  int32_t* flag = P.heap_flag.as<int32_t>();
+  int32_t* scan = P.heap_scan.as<int32_t>();
+  k_heap_flags<<<ceil_div(nheap, T), T, 0, st>>>(ls, L, nheap, flag);
+  CCFMM_HIP(hipGetLastError());
+  scan_exclusive(flag, scan, nheap, P.scratch, st);
+  // level starts: scan[2^l - 1] for l = 0..L+1 (the last is the total)
+  std::vector<int32_t> starts(L + 2);
+  for (int l = 0; l <= L + 1; l++)
+    CCFMM_HIP(hipMemcpyAsync(&starts[l], scan + ((1ll << l) - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  LevelPtrs lp{};
+  for (int l = 0; l <= L; l++) {
+    LevelData& D = *P.lev[l];
+    D.ncells = starts[l + 1] - starts[l];
+    D.heap0 = (1ll << l) - 1;
+    const int nc = D.ncells > 0 ? D.ncells : 1;
+    lp.key[l] = reinterpret_cast<int32_t*>(D.key.ensure(sizeof(int32_t) * nc));
+    lp.parent[l] = reinterpret_cast<int32_t*>(D.parent.ensure(sizeof(int32_t) * nc));
+    lp.child[l] = reinterpret_cast<int32_t*>(D.child.ensure(sizeof(int32_t) * 2 * nc));
+    lp.start[l] = starts[l];
+  }
+  lp.start[L + 1] = starts[L + 1];
+  int32_t* cmap = P.cmap.as<int32_t>();
+  k_compact_cells<<<ceil_div(nheap, T), T, 0, st>>>(flag, scan, L, nheap, lp, cmap);
+  CCFMM_HIP(hipGetLastError());
+  k_link_cells<<<ceil_div(nheap, T), T, 0, st>>>(flag, cmap, L, nheap, lp);
+  CCFMM_HIP(hipGetLastError());
+  for (int l = 0; l <= L; l++) {
+    LevelData& D = *P.lev[l];
+    D.coord.ensure(sizeof(int32_t) * 3 * (D.ncells > 0 ? D.ncells : 1));
+    k_cell_coords<<<ceil_div(D.ncells, T), T, 0, st>>>(lp.key[l], D.ncells, l, G, D.coord.as<int32_t>());
+    CCFMM_HIP(hipGetLastError());
+  }
+  const int32_t nl = P.lev[L]->ncells;
+  P.lstart.ensure(sizeof(int32_t) * nl);
+  P.lcount.ensure(sizeof(int32_t) * nl);
+  k_leaf_ranges<<<ceil_div(nl, T), T, 0, st>>>(lp.key[L], ls, nl, P.lstart.as<int32_t>(),
+                                                P.lcount.as<int32_t>());
+  CCFMM_HIP(hipGetLastError());
+}
+
+}  // namespace ccfmm

@@ -1,0 +1,60 @@
+"""The C-ABI library: it loads, exports every symbol include/ccfmm.h declares,
+and rejects invalid arguments before touching a GPU.  CPU only."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_0810_0233_amd import ccfmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ccfmm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccfmm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declarations_match_binding():
+    assert declared_symbols() == sorted(ccfmm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ccfmm.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_defaults():
+    assert ccfmm.status_string(ccfmm.OK) == "ok"
+    assert ccfmm.status_string(ccfmm.EINVAL) == "invalid argument"
+    p = ccfmm.params()
+    assert p.order == 4 and p.theta == 0.5 and p.max_batch == 1
+
+
+@pytest.mark.parametrize("bad", [dict(order=0), dict(order=9), dict(theta=0.0), dict(theta=1.0),
+                                 dict(max_batch=0), dict(precision=7)])
+def test_invalid_params_rejected_without_gpu(bad):
+    prm = ccfmm.params(**bad)
+    with pytest.raises(ccfmm.CCFMMError) as e:
+        ccfmm.Plan.create(np.zeros((4, 3)), prm)
+    assert e.value.status == ccfmm.EINVAL
+
+
+def test_nonfinite_positions_rejected():
+    pos = np.zeros((4, 3))
+    pos[2, 1] = np.nan
+    with pytest.raises(ccfmm.CCFMMError) as e:
+        ccfmm.Plan.create(pos, ccfmm.params())
+    assert e.value.status == ccfmm.EINVAL
+    assert "non-finite" in ccfmm.last_error()
+
+
+def test_energy_helper_matches_definition():
+    rng = np.random.default_rng(0)
+    m = rng.normal(size=(2, 10, 3))
+    H = rng.normal(size=(2, 10, 3))
+    E = ccfmm.energy(m, H)
+    np.testing.assert_allclose(E, -0.5 * np.sum(m * H, axis=(1, 2)), rtol=1e-14)

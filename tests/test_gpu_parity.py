@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars (written here, derived in the design notes):
+* FP64 plan: whole-FMM relative RMS vs the oracle FMM at the same (p, theta, s)
+  <= 1e-10 (the two differ only by summation order and the scaled-unit
+  roundings, ~1e-15 per operation); discrete structure (levels, split axes,
+  occupied cells, list sizes per level) bit-exact.
+* theta -> 0 (everything near): vs brute force <= 1e-12.
+* MIXED plan: vs the FP64 GPU plan <= 1e-5 relative RMS.
+"""
+import numpy as np
+import pytest
+
+from paper_0810_0233_amd import ccfmm, inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-10
+MIXED_BAR = 1e-5
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+@pytest.fixture(scope="module")
+def ref():
+    import oracle
+
+    return oracle
+
+
+def plan_for(pos, order, theta, leaf_target=0.0, box=None, precision=ccfmm.PREC_FP64, max_batch=1, **kw):
+    prm = ccfmm.params(order=order, theta=theta, leaf_target=leaf_target, box=box, precision=precision,
+                       max_batch=max_batch, **kw)
+    return ccfmm.Plan.create(pos, prm)
+
+
+def test_mfma_operand_layout():
+    assert ccfmm.selftest_mfma(0) == ccfmm.OK
+
+
+def test_lattice_1000_fp64_matches_oracle(ref):
+    c = inputs.config_lattice_1000()
+    pos, m = c["pos"], c["m"][0]
+    print("case lattice_1000 p=4 theta=0.5 s=8", flush=True)
+    H_ref, st = ref.fmm(pos, m, 4, 0.5, leaf_target=8, box=c["box"], return_stats=True)
+    pl = plan_for(pos, 4, 0.5, 8, c["box"])
+    inf = pl.info()
+    assert inf["levels"] == st["levels"] == 7
+    assert inf["split_axis"] == st["split_axis"]
+    assert inf["leaf_side"] == st["leaf_side"]
+    assert inf["n_leaves"] == st["n_leaves"]
+    assert inf["m2l_pairs_per_level"] == st["m2l_pairs_per_level"]
+    assert inf["n_p2p_leaf_pairs"] == st["n_p2p_leaf_pairs"]
+    H = pl.eval(m)
+    assert rel_rms(H, H_ref) <= FP64_BAR
+    Hb = ref.bruteforce(pos, m)
+    assert rel_rms(H, Hb) < 2e-4  # the truncation error of (4, 0.5), as the oracle has it
+
+
+def test_theta_to_zero_is_bruteforce(ref):
+    c = inputs.config_lattice_1000()
+    pos, m = c["pos"], c["m"][0]
+    pl = plan_for(pos, 4, 1e-3, 8, c["box"])
+    assert pl.info()["n_m2l_pairs"] == 0
+    H = pl.eval(m)
+    assert rel_rms(H, ref.bruteforce(pos, m)) <= 1e-12
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 5, 6, 7, 8])
+def test_orders_fp64_match_oracle(ref, order):
+    pos, box = inputs.lattice(12, 12, 12)
+    m = inputs.random_moments(pos.shape[0], 77 + order)
+    print("case lattice12 order=%d" % order, flush=True)
+    H_ref, st = ref.fmm(pos, m, order, 0.5, leaf_target=8, box=box, return_stats=True)
+    pl = plan_for(pos, order, 0.5, 8, box)
+    assert pl.info()["m2l_pairs_per_level"] == st["m2l_pairs_per_level"]
+    assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.45, 0.7])
+def test_ferrofluid_fp64_matches_oracle(ref, theta):
+    pos, box = inputs.ferrofluid(6000, 2001)
+    m = inputs.random_moments(6000, 2002)
+    print("case ferrofluid6000 theta=%g" % theta, flush=True)
+    H_ref, st = ref.fmm(pos, m, 6, theta, box=box, return_stats=True)
+    pl = plan_for(pos, 6, theta, 0.0, box)
+    inf = pl.info()
+    assert inf["levels"] == st["levels"]
+    assert inf["m2l_pairs_per_level"] == st["m2l_pairs_per_level"]
+    assert inf["n_p2p_leaf_pairs"] == st["n_p2p_leaf_pairs"]
+    assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
+
+
+def test_bounding_box_and_clusters(ref):
+    pos, _ = inputs.clusters(6, 700, 4001, box_side=128.0)
+    m = inputs.random_moments(pos.shape[0], 4002)
+    H_ref, st = ref.fmm(pos, m, 5, 0.4, return_stats=True)  # tight bounding box
+    pl = plan_for(pos, 5, 0.4)
+    assert pl.info()["box_lo"] == st["box_lo"]
+    assert pl.info()["n_leaves"] == st["n_leaves"]
+    assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
+
+
+def test_mixed_precision_vs_fp64():
+    pos, box = inputs.ferrofluid(20000, 2001)
+    m = inputs.random_moments(20000, 2002)
+    H64 = plan_for(pos, 6, 0.5, 0.0, box).eval(m)
+    H32 = plan_for(pos, 6, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED).eval(m)
+    e = rel_rms(H32, H64)
+    print("mixed vs fp64 rel rms = %.3e" % e, flush=True)
+    assert e <= MIXED_BAR
+
+
+def test_batched_equals_single(ref):
+    pos, box = inputs.sphere_cut(3000, 20)
+    mb = inputs.aligned_moments(3000, 5, 3000)
+    pl = plan_for(pos, 5, 0.5, 0.0, box, max_batch=8)
+    Hb = pl.eval(mb)
+    for b in range(5):
+        Hs = pl.eval(mb[b:b + 1])[0]
+        assert rel_rms(Hb[b], Hs) <= 1e-14
+        if b in (0, 4):
+            assert rel_rms(Hb[b], ref.fmm(pos, mb[b], 5, 0.5, box=box)) <= FP64_BAR
+
+
+def test_edge_cases(ref):
+    # one dipole: no field
+    pl = plan_for(np.array([[0.3, 0.2, 0.1]]), 3, 0.5)
+    np.testing.assert_array_equal(pl.eval(np.array([[1.0, 0, 0]])), 0.0)
+    # two coincident dipoles and one apart
+    pos = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 0, 0]])
+    m = np.array([[0, 0, 1.0], [0, 1.0, 0], [1.0, 0, 0]])
+    H = plan_for(pos, 3, 0.5).eval(m)
+    np.testing.assert_allclose(H, ref.bruteforce(pos, m), rtol=1e-14, atol=1e-15)
+    # ragged occupancy: a dense blob plus a few far points (leaf chunks > 64)
+    rng = np.random.default_rng(3)
+    pos = np.concatenate([rng.normal(size=(900, 3)) * 0.5, rng.uniform(-40, 40, size=(60, 3))])
+    m = inputs.unit_moments(960, rng)
+    H_ref = ref.fmm(pos, m, 4, 0.5, leaf_target=20)
+    assert rel_rms(plan_for(pos, 4, 0.5, 20).eval(m), H_ref) <= FP64_BAR
+
+
+def test_device_path_and_determinism():
+    import torch
+
+    pos, box = inputs.ferrofluid(5000, 11)
+    m = inputs.random_moments(5000, 12)
+    dev = torch.device("cuda:0")
+    d_pos = torch.from_numpy(pos).to(dev)
+    d_m = torch.from_numpy(m).to(dev)
+    d_H = torch.empty_like(d_m)
+    st = torch.cuda.current_stream().cuda_stream
+    prm = ccfmm.params(order=5, theta=0.5, box=box)
+    pl = ccfmm.Plan.create_device(5000, d_pos.data_ptr(), prm, st)
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    H1 = d_H.cpu().numpy().copy()
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d_H.cpu().numpy(), H1)  # FP64 path is bitwise repeatable
+    H_host = ccfmm.Plan.create(pos, prm).eval(m)
+    np.testing.assert_array_equal(H_host, H1)
+    # moving the dipoles and rebuilding in place gives the fresh-plan answer
+    pos2 = pos + 0.01
+    d_pos.copy_(torch.from_numpy(pos2))
+    prm2 = ccfmm.params(order=5, theta=0.5)
+    pl2 = ccfmm.Plan.create_device(5000, d_pos.data_ptr(), prm2, st)
+    pl2.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    Ha = d_H.cpu().numpy().copy()
+    pl3 = ccfmm.Plan.create_device(5000, torch.from_numpy(pos).to(dev).data_ptr(), prm2, st)
+    pl3.update_positions_device(d_pos.data_ptr(), st)
+    pl3.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(d_H.cpu().numpy(), Ha)
+
+
+def test_direct_targets_matches_oracle(ref):
+    import torch
+
+    pos, _ = inputs.ferrofluid(4000, 5)
+    m = inputs.random_moments(4000, 6)
+    idx = np.array([0, 17, 3999, 2000], dtype=np.int64)
+    dev = torch.device("cuda:0")
+    d_pos = torch.from_numpy(pos).to(dev)
+    d_m = torch.from_numpy(m).to(dev)
+    d_idx = torch.from_numpy(idx).to(dev)
+    d_H = torch.zeros((4, 3), dtype=torch.float64, device=dev)
+    ccfmm.direct_targets_device(4000, d_pos.data_ptr(), d_m.data_ptr(), 4, d_idx.data_ptr(), d_H.data_ptr(),
+                                torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(d_H.cpu().numpy(), ref.bruteforce_targets(pos, m, idx), rtol=1e-12, atol=1e-14)
