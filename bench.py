@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--samples", type=int, default=4096)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with one plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); run with --gpus 1",
@@ -197,6 +199,13 @@ def main():
         "cpu_baseline": cpu,
     }
     res.update(out)
+    if args.calib_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        a.copy_(b)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = 256 << 20
     print(json.dumps(res), flush=True)
 
 

@@ -197,6 +197,27 @@ __global__ void k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr, const int
 }
 
 static void fill_info(Plan& P, hipStream_t st) {
+  // list totals, chunk count and error flags come back in one synchronisation
+  const int L = P.L;
+  std::vector<int32_t> tot(2 * (L + 1) + 2, 0);
+  for (int l = 0; l <= L; l++) {
+    LevelData& D = *P.lev[l];
+    CCFMM_HIP(hipMemcpyAsync(&tot[2 * l], D.near_ptr.as<int32_t>() + D.ncells, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipMemcpyAsync(&tot[2 * l + 1], D.far_ptr.as<int32_t>() + D.ncells, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, st));
+  }
+  const int nl = P.lev[L]->ncells;
+  CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1)], P.chunk_cnt.as<int32_t>() + (nl + 1) + nl, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1) + 1], P.flags.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  if (tot[2 * (L + 1) + 1]) fail(CCFMM_EHIP, "internal: a cell list exceeded its bound");
+  for (int l = 0; l <= L; l++) {
+    P.lev[l]->nnear = tot[2 * l];
+    P.lev[l]->nfar = tot[2 * l + 1];
+  }
+  P.nchunks = tot[2 * (L + 1)];
   ccfmm_info& I = P.info;
   std::memset(&I, 0, sizeof(I));
   I.n = P.n;
@@ -217,9 +238,9 @@ static void fill_info(Plan& P, hipStream_t st) {
     cells += P.lev[l]->ncells;
     I.m2l_pairs_per_level[l] = P.lev[l]->nfar;
     m2l += P.lev[l]->nfar;
-    I.n_delta += P.lev[l]->ndelta;
   }
   I.n_cells = cells;
+  I.n_delta = P.nrows;
   I.n_m2l_pairs = m2l;
   I.n_p2p_leaf_pairs = P.lev[P.L]->nnear;
   I.n_m2l_tiles = P.ntiles;
@@ -291,11 +312,7 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
 
 static void prepare_batch(Plan& P, int nb, hipStream_t st) {
   if (nb < 1 || nb > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
-  const int tb = [&] {
-    int t = 1;
-    while (t < nb && t < 16) t <<= 1;
-    return t;
-  }();
+  const int tb = tile_batch(nb);
   if (tb != P.TB || ceil_div(nb, tb) != P.ncg) {
     build_m2l_tiles(P, nb, st);
     P.info.n_m2l_tiles = P.ntiles;

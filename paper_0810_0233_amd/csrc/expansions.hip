@@ -82,28 +82,41 @@ static FTableHost make_ftable(int K) {
   return out;
 }
 
-// One thread per (offset, k): D_k(c) in FP64, then an FP32 copy.  The list
-// offsets are source minus target; Eq.(taylorcalc) takes c = target centre
-// minus source centre, i.e. c = -delta * g in the level's units.
-__global__ void k_dtensor(int32_t ndelta, const int32_t* __restrict__ dvec, double g0, double g1, double g2,
-                          int K, const int32_t* __restrict__ fptr, const int32_t* __restrict__ fq,
+// One thread per (dense offset id, k): D_k(c) in FP64, then an FP32 copy.
+// Dense id d enumerates the offsets delta of the box [-w, w]^3 (source minus
+// target cell); Eq.(taylorcalc) takes c = target minus source centre, i.e.
+// c = -delta * g in the level's units.  The zero offset (never a far pair) is
+// stored as zeros.
+__global__ void k_dtensor(int64_t nbox, int w0, int w1, int w2, double g0, double g1, double g2, int K,
+                          const int32_t* __restrict__ fptr, const int32_t* __restrict__ fq,
                           const double* __restrict__ fval, int64_t row0, double* Dd, float* Df) {
   const int NK = ncoef(K);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)ndelta * NK) return;
-  const int d = (int)(t / NK), k = (int)(t % NK);
-  const double c[3] = {-dvec[3 * d] * g0, -dvec[3 * d + 1] * g1, -dvec[3 * d + 2] * g2};
-  double pw[3][kKMax + 1];
-  for (int a = 0; a < 3; a++) {
-    pw[a][0] = 1.0;
-    for (int j = 1; j <= K; j++) pw[a][j] = pw[a][j - 1] * c[a];
-  }
+  if (t >= nbox * NK) return;
+  const int64_t d = t / NK;
+  const int k = (int)(t % NK);
+  const int nz = 2 * w2 + 1, ny = 2 * w1 + 1;
+  const int dz = (int)(d % nz) - w2;
+  const int dy = (int)((d / nz) % ny) - w1;
+  const int dx = (int)(d / ((int64_t)nz * ny)) - w0;
+  const double c[3] = {-dx * g0, -dy * g1, -dz * g2};
   const double r2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-  const int deg = kMI.x[k] + kMI.y[k] + kMI.z[k];
+  const int64_t o = (row0 + d) * NK + k;
+  if (r2 == 0.0) {
+    Dd[o] = 0.0;
+    Df[o] = 0.0f;
+    return;
+  }
+  const int qx0 = kMI.x[k], qy0 = kMI.y[k], qz0 = kMI.z[k];
+  const int deg = qx0 + qy0 + qz0;
   double s = 0.0;
   for (int e = fptr[k]; e < fptr[k + 1]; e++) {
     const int q = fq[e];
-    s += fval[e] * pw[0][kMI.x[q]] * pw[1][kMI.y[q]] * pw[2][kMI.z[q]];
+    double m = fval[e];
+    for (int j = 0; j < kMI.x[q]; j++) m *= c[0];
+    for (int j = 0; j < kMI.y[q]; j++) m *= c[1];
+    for (int j = 0; j < kMI.z[q]; j++) m *= c[2];
+    s += m;
   }
   // r^-(2 deg + 1)
   const double rinv = 1.0 / sqrt(r2);
@@ -111,14 +124,39 @@ __global__ void k_dtensor(int32_t ndelta, const int32_t* __restrict__ dvec, doub
   const double rinv2 = rinv * rinv;
   for (int j = 0; j < deg; j++) rp *= rinv2;
   const double v = s * rp;
-  const int64_t o = (row0 + d) * NK + k;
   Dd[o] = v;
   Df[o] = (float)v;
 }
 
+// Derivative tensors for every offset of each level's box.  Levels with the
+// same cell shape (g) and box share one table; the tables are kept across
+// rebuilds as long as order, shapes and boxes do not change.
 void build_dtensors(Plan& P, hipStream_t st) {
   const int K = 2 * P.p;
   const int NK = ncoef(K);
+  std::vector<std::array<double, 6>> keys;
+  std::vector<int64_t> key_row, key_nbox;
+  std::vector<int> lev_key(P.L + 1, -1);
+  int64_t rows = 0;
+  for (int l = 1; l <= P.L; l++) {
+    LevelData& D = *P.lev[l];
+    const LevelGeom& lg = P.geo.lev[l];
+    std::array<double, 6> k = {lg.g[0], lg.g[1], lg.g[2], (double)D.wfar[0], (double)D.wfar[1], (double)D.wfar[2]};
+    int found = -1;
+    for (size_t i = 0; i < keys.size(); i++)
+      if (keys[i] == k) found = (int)i;
+    if (found < 0) {
+      found = (int)keys.size();
+      keys.push_back(k);
+      key_row.push_back(rows);
+      key_nbox.push_back(D.nbox);
+      rows += D.nbox;
+    }
+    lev_key[l] = found;
+    D.drow0 = key_row[found];
+  }
+  P.lev[0]->drow0 = 0;
+  if (P.dtab_p == P.p && P.dtab_keys == keys && P.Dd.p) return;  // unchanged: reuse
   static FTableHost ft[kPMax + 1];
   static bool have[kPMax + 1] = {false};
   if (!have[P.p]) {
@@ -126,29 +164,29 @@ void build_dtensors(Plan& P, hipStream_t st) {
     have[P.p] = true;
   }
   const FTableHost& F = ft[P.p];
-  // table upload: ptr | q | val
   const size_t nb_ptr = sizeof(int32_t) * F.ptr.size(), nb_q = sizeof(int32_t) * F.q.size();
   const size_t nb_val = sizeof(double) * F.val.size();
-  char* buf = reinterpret_cast<char*>(P.scratch2.ensure(nb_ptr + nb_q + nb_val + 64));
+  const size_t off_val = (nb_ptr + nb_q + 15) & ~size_t(15);
+  char* buf = reinterpret_cast<char*>(P.scratch2.ensure(off_val + nb_val + 64));
   int32_t* dptr = reinterpret_cast<int32_t*>(buf);
   int32_t* dq = reinterpret_cast<int32_t*>(buf + nb_ptr);
-  double* dval = reinterpret_cast<double*>(buf + ((nb_ptr + nb_q + 15) & ~size_t(15)));
+  double* dval = reinterpret_cast<double*>(buf + off_val);
   CCFMM_HIP(hipMemcpyAsync(dptr, F.ptr.data(), nb_ptr, hipMemcpyHostToDevice, st));
   CCFMM_HIP(hipMemcpyAsync(dq, F.q.data(), nb_q, hipMemcpyHostToDevice, st));
   CCFMM_HIP(hipMemcpyAsync(dval, F.val.data(), nb_val, hipMemcpyHostToDevice, st));
-  const int64_t rows = std::max<int64_t>(1, P.nrows);
-  double* Dd = reinterpret_cast<double*>(P.Dd.ensure(sizeof(double) * rows * NK));
-  float* Df = reinterpret_cast<float*>(P.Df.ensure(sizeof(float) * rows * NK));
-  for (int l = 0; l <= P.L; l++) {
-    const LevelData& D = *P.lev[l];
-    if (D.ndelta == 0) continue;
-    const LevelGeom& lg = P.geo.lev[l];
-    const int64_t nt = (int64_t)D.ndelta * NK;
-    k_dtensor<<<ceil_div(nt, 256), 256, 0, st>>>(D.ndelta, D.delta_vec.as<int32_t>(), lg.g[0], lg.g[1], lg.g[2], K,
-                                                 dptr, dq, dval, D.drow0, Dd, Df);
+  P.nrows = std::max<int64_t>(1, rows);
+  double* Dd = reinterpret_cast<double*>(P.Dd.ensure(sizeof(double) * P.nrows * NK));
+  float* Df = reinterpret_cast<float*>(P.Df.ensure(sizeof(float) * P.nrows * NK));
+  for (size_t i = 0; i < keys.size(); i++) {
+    const auto& k = keys[i];
+    const int64_t nt = key_nbox[i] * NK;
+    k_dtensor<<<ceil_div(nt, 256), 256, 0, st>>>(key_nbox[i], (int)k[3], (int)k[4], (int)k[5], k[0], k[1], k[2], K,
+                                                 dptr, dq, dval, key_row[i], Dd, Df);
     CCFMM_HIP(hipGetLastError());
   }
-  CCFMM_HIP(hipStreamSynchronize(st));  // host table buffers stay alive, scratch2 reused later
+  CCFMM_HIP(hipStreamSynchronize(st));  // the host table copies above must finish before scratch2 is reused
+  P.dtab_p = P.p;
+  P.dtab_keys = keys;
 }
 
 // ------------------------------------------------------------ moments in tree order

@@ -21,6 +21,15 @@ namespace ccfmm {
 constexpr int kPMax = CCFMM_PMAX;
 constexpr int kLMax = CCFMM_LMAX;
 constexpr int kKMax = 2 * kPMax;  // derivative tensors up to order 2p
+constexpr int kTileCols = 64;     // M2L tile: (target cell, configuration) columns per block
+
+// configurations per M2L tile for a batch of nb: the next power of two, at
+// most one tile width
+inline int tile_batch(int nb) {
+  int t = 1;
+  while (t < nb && t < kTileCols) t <<= 1;
+  return t;
+}
 
 __host__ __device__ constexpr int ncoef(int d) { return d < 0 ? 0 : (d + 1) * (d + 2) * (d + 3) / 6; }
 __host__ __device__ constexpr int midx(int a, int b, int c) {

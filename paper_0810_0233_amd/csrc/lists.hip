@@ -1,6 +1,5 @@
 // lists.hip -- near/far cell lists (Sec. 2 and Appendix, createPartners),
-// the distinct cell offsets of the far pairs, the M2L work tiles and the
-// P2P work chunks.
+// the M2L work tiles and the P2P work chunks, all built on the GPU.
 //
 // Level by level, the candidates of a cell are the children of the cells near
 // its parent (the parent itself included, which supplies the sibling).  A
@@ -8,7 +7,13 @@
 // the near-field sum at the smallest cells); otherwise it is far and enters
 // the cell's M2L list.  Empty cells are never created, which leaves every
 // field unchanged (their moments vanish and they hold no field points).
+//
+// One wavefront per cell walks its candidates 64 at a time; ballots give each
+// near/far candidate its slot, so the lists come out in candidate order, the
+// same order a serial walk produces.  Buffers are sized from exact per-cell
+// bounds computed on the host, so no level waits on the host.
 #include <algorithm>
+#include <cmath>
 
 #include "plan.hpp"
 
@@ -18,7 +23,7 @@ namespace ccfmm {
 // and g the cell sides over the smallest side, alpha = |g| / |delta*g|; the
 // pair is far iff theta^2 |delta*g|^2 >= |g|^2 (alpha == theta is far).  The
 // sums run x, y, z with no contraction.
-__device__ __forceinline__ bool is_near(const LevelGeom& lg, double theta2, int dx, int dy, int dz) {
+__host__ __device__ __forceinline__ bool is_near(const LevelGeom& lg, double theta2, int dx, int dy, int dz) {
 #pragma clang fp contract(off)
   const double ax = (double)dx * lg.g[0];
   const double ay = (double)dy * lg.g[1];
@@ -42,87 +47,90 @@ struct ListArgs {
   int32_t ncells;
   int level;
   double theta2;
-  int wbox[3];
+  int wfar[3];
+  int64_t near_cap, far_cap;
 };
 
-__global__ void k_list_count(ListArgs a, TreeGeom G, int32_t* near_cnt, int32_t* far_cnt) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+// Candidate i of cell c: child (i & 1) of the (i >> 1)-th near cell of the parent.
+__global__ void __launch_bounds__(256) k_list_count(ListArgs a, TreeGeom G, int32_t* near_cnt, int32_t* far_cnt) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.ncells) return;
-  const LevelGeom lg = G.lev[a.level];
+  const LevelGeom& lg = G.lev[a.level];
   const int pc = a.parent[c];
+  const int e0 = a.pnear_ptr[pc], ncand = 2 * (a.pnear_ptr[pc + 1] - e0);
   const int cx = a.coord[3 * c], cy = a.coord[3 * c + 1], cz = a.coord[3 * c + 2];
   int nn = 0, nf = 0;
-  for (int e = a.pnear_ptr[pc]; e < a.pnear_ptr[pc + 1]; e++) {
-    const int A = a.pnear_idx[e];
-    for (int s = 0; s < 2; s++) {
-      const int X = a.pchild[2 * A + s];
-      if (X < 0) continue;
-      const int dx = a.coord[3 * X] - cx, dy = a.coord[3 * X + 1] - cy, dz = a.coord[3 * X + 2] - cz;
-      if (is_near(lg, a.theta2, dx, dy, dz))
-        nn++;
-      else
-        nf++;
-    }
-  }
-  near_cnt[c] = nn;
-  far_cnt[c] = nf;
-}
-
-__device__ __forceinline__ int64_t box_index(const int w[3], int dx, int dy, int dz) {
-  return ((int64_t)(dx + w[0]) * (2 * w[1] + 1) + (dy + w[1])) * (2 * w[2] + 1) + (dz + w[2]);
-}
-
-__global__ void k_list_fill(ListArgs a, TreeGeom G, const int32_t* near_ptr, int32_t* near_idx,
-                            const int32_t* far_ptr, int32_t* far_idx, int32_t* far_box, int32_t* box_flag,
-                            int32_t* overflow) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.ncells) return;
-  const LevelGeom lg = G.lev[a.level];
-  const int pc = a.parent[c];
-  const int cx = a.coord[3 * c], cy = a.coord[3 * c + 1], cz = a.coord[3 * c + 2];
-  int jn = near_ptr[c], jf = far_ptr[c];
-  for (int e = a.pnear_ptr[pc]; e < a.pnear_ptr[pc + 1]; e++) {
-    const int A = a.pnear_idx[e];
-    for (int s = 0; s < 2; s++) {
-      const int X = a.pchild[2 * A + s];
-      if (X < 0) continue;
-      const int dx = a.coord[3 * X] - cx, dy = a.coord[3 * X + 1] - cy, dz = a.coord[3 * X + 2] - cz;
-      if (is_near(lg, a.theta2, dx, dy, dz)) {
-        near_idx[jn++] = X;
-      } else {
-        far_idx[jf] = X;
-        if (abs(dx) > a.wbox[0] || abs(dy) > a.wbox[1] || abs(dz) > a.wbox[2]) {
-          overflow[0] = 1;
-          far_box[jf] = 0;
-        } else {
-          const int64_t b = box_index(a.wbox, dx, dy, dz);
-          far_box[jf] = (int32_t)b;
-          box_flag[b] = 1;
-        }
-        jf++;
+  for (int base = 0; base < ncand; base += 64) {
+    const int i = base + lane;
+    bool isn = false, isf = false;
+    if (i < ncand) {
+      const int X = a.pchild[2 * a.pnear_idx[e0 + (i >> 1)] + (i & 1)];
+      if (X >= 0) {
+        const bool nr = is_near(lg, a.theta2, a.coord[3 * X] - cx, a.coord[3 * X + 1] - cy, a.coord[3 * X + 2] - cz);
+        isn = nr;
+        isf = !nr;
       }
     }
+    nn += __popcll(__ballot(isn));
+    nf += __popcll(__ballot(isf));
+  }
+  if (lane == 0) {
+    near_cnt[c] = nn;
+    far_cnt[c] = nf;
   }
 }
 
-__global__ void k_far_did(int64_t nfar, const int32_t* far_box, const int32_t* box_scan, int32_t* far_did) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nfar) return;
-  far_did[e] = box_scan[far_box[e]];
-}
-
-__global__ void k_delta_vecs(int64_t nbox, const int32_t* box_flag, const int32_t* box_scan, int w0, int w1,
-                             int w2, int32_t* dvec) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbox || !box_flag[b]) return;
-  const int nz = 2 * w2 + 1, ny = 2 * w1 + 1;
-  const int dz = (int)(b % nz) - w2;
-  const int dy = (int)((b / nz) % ny) - w1;
-  const int dx = (int)(b / ((int64_t)nz * ny)) - w0;
-  const int id = box_scan[b];
-  dvec[3 * id] = dx;
-  dvec[3 * id + 1] = dy;
-  dvec[3 * id + 2] = dz;
+__global__ void __launch_bounds__(256) k_list_fill(ListArgs a, TreeGeom G, const int32_t* near_ptr, int32_t* near_idx,
+                                                   const int32_t* far_ptr, int32_t* far_idx, int32_t* far_did,
+                                                   int32_t* flags) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= a.ncells) return;
+  const LevelGeom& lg = G.lev[a.level];
+  const int pc = a.parent[c];
+  const int e0 = a.pnear_ptr[pc], ncand = 2 * (a.pnear_ptr[pc + 1] - e0);
+  const int cx = a.coord[3 * c], cy = a.coord[3 * c + 1], cz = a.coord[3 * c + 2];
+  int64_t jn = near_ptr[c], jf = far_ptr[c];
+  const uint64_t lt = lanemask_lt(lane);
+  for (int base = 0; base < ncand; base += 64) {
+    const int i = base + lane;
+    bool isn = false, isf = false;
+    int X = -1, dx = 0, dy = 0, dz = 0;
+    if (i < ncand) {
+      X = a.pchild[2 * a.pnear_idx[e0 + (i >> 1)] + (i & 1)];
+      if (X >= 0) {
+        dx = a.coord[3 * X] - cx;
+        dy = a.coord[3 * X + 1] - cy;
+        dz = a.coord[3 * X + 2] - cz;
+        const bool nr = is_near(lg, a.theta2, dx, dy, dz);
+        isn = nr;
+        isf = !nr;
+      }
+    }
+    const uint64_t mn = __ballot(isn), mf = __ballot(isf);
+    if (isn) {
+      const int64_t at = jn + __popcll(mn & lt);
+      if (at < a.near_cap)
+        near_idx[at] = X;
+      else
+        flags[0] = 1;
+    }
+    if (isf) {
+      const int64_t at = jf + __popcll(mf & lt);
+      const bool inbox = abs(dx) <= a.wfar[0] && abs(dy) <= a.wfar[1] && abs(dz) <= a.wfar[2];
+      if (at < a.far_cap && inbox) {
+        far_idx[at] = X;
+        far_did[at] = (int32_t)box_index(a.wfar, dx, dy, dz);
+      } else {
+        flags[0] = 1;
+      }
+    }
+    jn += __popcll(mn);
+    jf += __popcll(mf);
+  }
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -136,55 +144,71 @@ static void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   CCFMM_HIP(hipGetLastError());
 }
 
-static int32_t read_i32(const int32_t* d, hipStream_t st) {
-  int32_t v = 0;
-  CCFMM_HIP(hipMemcpyAsync(&v, d, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  CCFMM_HIP(hipStreamSynchronize(st));
-  return v;
+// Offset bounds of every level: near offsets satisfy |delta_a g_a| < |g|/theta;
+// candidates are children of near cells of the parent, so their offsets are
+// those of the parent level, doubled (+1) along the axis halved at this level.
+static void level_bounds(Plan& P) {
+  const double th = P.prm.theta;
+  for (int l = 0; l <= P.L; l++) {
+    LevelData& D = *P.lev[l];
+    const LevelGeom& lg = P.geo.lev[l];
+    const double R = lg.g[0] * lg.g[0] + lg.g[1] * lg.g[1] + lg.g[2] * lg.g[2];
+    for (int a = 0; a < 3; a++) {
+      const double grid = std::ldexp(1.0, lg.k[a]) - 1.0;
+      const double w = std::floor(std::sqrt(R) / (th * lg.g[a])) + 1.0;
+      D.wnear[a] = (int)std::min(w, grid);
+      if (l == 0) {
+        D.wfar[a] = 0;
+      } else {
+        const LevelData& U = *P.lev[l - 1];
+        const double wf = (a == lg.axis) ? 2.0 * U.wnear[a] + 1.0 : (double)U.wnear[a];
+        D.wfar[a] = (int)std::min(wf, grid);
+      }
+    }
+    // most near cells of one cell: near offsets counted in the near box, with a
+    // small relative margin so that no tie is under-counted
+    int64_t cn = 0;
+    const double th2 = th * th;
+    for (int dx = -D.wnear[0]; dx <= D.wnear[0]; dx++)
+      for (int dy = -D.wnear[1]; dy <= D.wnear[1]; dy++)
+        for (int dz = -D.wnear[2]; dz <= D.wnear[2]; dz++) {
+          const double ax = dx * lg.g[0], ay = dy * lg.g[1], az = dz * lg.g[2];
+          if (th2 * (ax * ax + ay * ay + az * az) < R * (1.0 + 1e-9)) cn++;
+        }
+    D.cnear = std::max<int64_t>(1, cn);
+    D.nbox = (int64_t)(2 * D.wfar[0] + 1) * (2 * D.wfar[1] + 1) * (2 * D.wfar[2] + 1);
+  }
 }
 
 void build_lists(Plan& P, hipStream_t st) {
   const int L = P.L;
   const int T = 256;
   const double theta2 = P.prm.theta * P.prm.theta;
-  // level 0: the root is near itself
+  level_bounds(P);
+  int32_t* flags = reinterpret_cast<int32_t*>(P.flags.ensure(64));
+  fill_i32(flags, 16, 0, st);
+  // level 0: the root is near itself, no far cells
   {
     LevelData& D = *P.lev[0];
     int32_t* np = reinterpret_cast<int32_t*>(D.near_ptr.ensure(sizeof(int32_t) * 2));
     int32_t* ni = reinterpret_cast<int32_t*>(D.near_idx.ensure(sizeof(int32_t) * 1));
-    const int32_t h_np[2] = {0, 1}, h_ni[1] = {0};
-    CCFMM_HIP(hipMemcpyAsync(np, h_np, sizeof(h_np), hipMemcpyHostToDevice, st));
-    CCFMM_HIP(hipMemcpyAsync(ni, h_ni, sizeof(h_ni), hipMemcpyHostToDevice, st));
-    D.nnear = 1;
     int32_t* fp = reinterpret_cast<int32_t*>(D.far_ptr.ensure(sizeof(int32_t) * 2));
+    fill_i32(np, 1, 0, st);
+    fill_i32(np + 1, 1, 1, st);
+    fill_i32(ni, 1, 0, st);
     fill_i32(fp, 2, 0, st);
-    D.nfar = 0;
-    D.ndelta = 0;
-    CCFMM_HIP(hipStreamSynchronize(st));  // host arrays above go out of scope
   }
-  DevBuf& cnt = P.scratch2;
   for (int l = 1; l <= L; l++) {
     LevelData& D = *P.lev[l];
     LevelData& U = *P.lev[l - 1];
     const int nc = D.ncells;
-    // offset box for the far pairs of this level: a far pair's parents are near
-    // at level l-1, which bounds their offset; the halved axis doubles it
-    const LevelGeom& pg = P.geo.lev[l - 1];
-    const double Rp = pg.g[0] * pg.g[0] + pg.g[1] * pg.g[1] + pg.g[2] * pg.g[2];
-    for (int a = 0; a < 3; a++) {
-      double wp = std::floor(std::sqrt(Rp) / (P.prm.theta * pg.g[a])) + 1.0;
-      double w = (a == P.geo.lev[l].axis) ? 2.0 * wp + 1.0 : wp;
-      double gridmax = (double)((1ll << P.geo.lev[l].k[a]) - 1);
-      D.wbox[a] = (int)std::min(w, gridmax);
-    }
-    const int64_t nbox = (int64_t)(2 * D.wbox[0] + 1) * (2 * D.wbox[1] + 1) * (2 * D.wbox[2] + 1);
-    if (nbox > (1ll << 26)) fail(CCFMM_EINVAL, "opening angle too small for this tree (offset box too large)");
-
-    int32_t* c = reinterpret_cast<int32_t*>(cnt.ensure(sizeof(int32_t) * (2 * (size_t)(nc + 1) + nbox + 1 + 8)));
+    const int64_t near_cap = (int64_t)nc * D.cnear;
+    const int64_t far_cap = (int64_t)nc * std::min<int64_t>(2 * U.cnear, D.nbox);
+    if (near_cap > (1ll << 31) - 1 || far_cap > (1ll << 31) - 1)
+      fail(CCFMM_EINVAL, "opening angle too small for this tree (lists would exceed 2^31 entries)");
+    int32_t* c = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * 2 * (size_t)(nc + 1)));
     int32_t* near_cnt = c;
     int32_t* far_cnt = c + (nc + 1);
-    int32_t* ovf = far_cnt + (nc + 1);
-    int32_t* box_flag = ovf + 8;
     ListArgs a;
     a.parent = D.parent.as<int32_t>();
     a.coord = D.coord.as<int32_t>();
@@ -194,63 +218,34 @@ void build_lists(Plan& P, hipStream_t st) {
     a.ncells = nc;
     a.level = l;
     a.theta2 = theta2;
-    for (int q = 0; q < 3; q++) a.wbox[q] = D.wbox[q];
-    k_list_count<<<ceil_div(nc, T), T, 0, st>>>(a, P.geo, near_cnt, far_cnt);
+    for (int q = 0; q < 3; q++) a.wfar[q] = D.wfar[q];
+    a.near_cap = near_cap;
+    a.far_cap = far_cap;
+    const int nblk = ceil_div(nc, 4);
+    k_list_count<<<nblk, T, 0, st>>>(a, P.geo, near_cnt, far_cnt);
     CCFMM_HIP(hipGetLastError());
     int32_t* nptr = reinterpret_cast<int32_t*>(D.near_ptr.ensure(sizeof(int32_t) * (nc + 1)));
     int32_t* fptr = reinterpret_cast<int32_t*>(D.far_ptr.ensure(sizeof(int32_t) * (nc + 1)));
     scan_exclusive(near_cnt, nptr, nc, P.scratch, st);
     scan_exclusive(far_cnt, fptr, nc, P.scratch, st);
-    int32_t tot[2];
-    CCFMM_HIP(hipMemcpyAsync(&tot[0], nptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    CCFMM_HIP(hipMemcpyAsync(&tot[1], fptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    CCFMM_HIP(hipStreamSynchronize(st));
-    D.nnear = tot[0];
-    D.nfar = tot[1];
-    int32_t* nidx = reinterpret_cast<int32_t*>(D.near_idx.ensure(sizeof(int32_t) * std::max<int64_t>(1, D.nnear)));
-    int32_t* fidx = reinterpret_cast<int32_t*>(D.far_idx.ensure(sizeof(int32_t) * std::max<int64_t>(1, D.nfar)));
-    int32_t* fdid = reinterpret_cast<int32_t*>(D.far_did.ensure(sizeof(int32_t) * std::max<int64_t>(1, D.nfar)));
-    fill_i32(ovf, 1, 0, st);
-    fill_i32(box_flag, nbox, 0, st);
-    // far_did first holds the box index of each far entry
-    k_list_fill<<<ceil_div(nc, T), T, 0, st>>>(a, P.geo, nptr, nidx, fptr, fidx, fdid, box_flag, ovf);
+    int32_t* nidx = reinterpret_cast<int32_t*>(D.near_idx.ensure(sizeof(int32_t) * std::max<int64_t>(1, near_cap)));
+    int32_t* fidx = reinterpret_cast<int32_t*>(D.far_idx.ensure(sizeof(int32_t) * std::max<int64_t>(1, far_cap)));
+    int32_t* fdid = reinterpret_cast<int32_t*>(D.far_did.ensure(sizeof(int32_t) * std::max<int64_t>(1, far_cap)));
+    k_list_fill<<<nblk, T, 0, st>>>(a, P.geo, nptr, nidx, fptr, fidx, fdid, flags);
     CCFMM_HIP(hipGetLastError());
-    if (read_i32(ovf, st)) fail(CCFMM_EINVAL, "internal: far offset outside its bound");
-    // compact the offsets that occur
-    DevBuf& bs = P.scratch;  // scan output must not alias scratch used by scan itself
-    int32_t* box_scan = reinterpret_cast<int32_t*>(P.bitmap.ensure(sizeof(int32_t) * (nbox + 1)));
-    (void)bs;
-    scan_exclusive(box_flag, box_scan, nbox, P.scratch, st);
-    D.ndelta = read_i32(box_scan + nbox, st);
-    int32_t* dvec = reinterpret_cast<int32_t*>(D.delta_vec.ensure(sizeof(int32_t) * 3 * std::max(1, D.ndelta)));
-    k_delta_vecs<<<ceil_div(nbox, T), T, 0, st>>>(nbox, box_flag, box_scan, D.wbox[0], D.wbox[1], D.wbox[2], dvec);
-    CCFMM_HIP(hipGetLastError());
-    if (D.nfar > 0) {
-      k_far_did<<<ceil_div(D.nfar, T), T, 0, st>>>(D.nfar, fdid, box_scan, fdid);
-      CCFMM_HIP(hipGetLastError());
-    }
   }
-  // derivative-tensor rows: levels in order
-  int64_t r = 0;
-  for (int l = 0; l <= L; l++) {
-    P.lev[l]->drow0 = r;
-    r += P.lev[l]->ndelta;
-  }
-  P.nrows = r;
 }
 
 // ---------------------------------------------------------------- M2L tiles
-// Targets of a level are ordered by (low class bits of the key, remaining key
-// bits): cells in the same position inside their ancestors have the same set
-// of far offsets, so a tile of TC such cells shares one list of offsets.  The
-// tile's steps are the union of its cells' offsets; a cell without a source
-// at that offset gets a null column.
-__global__ void k_rot_keys(const int32_t* key, int32_t nc, int l, int cb, uint32_t* rot, int32_t* idx) {
+// Targets of a level are ordered by (low class bits of the key, key): cells in
+// the same position inside their ancestors have the same set of far offsets,
+// so a tile of TC such cells shares one list of offsets.  The tile's steps are
+// the union of its cells' offsets; a cell without a source at that offset
+// gets a null column.
+__global__ void k_class_keys(const int32_t* key, int32_t nc, int cb, uint32_t* cls, int32_t* idx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc) return;
-  const uint32_t k = (uint32_t)key[i];
-  const uint32_t mask = (1u << cb) - 1u;
-  rot[i] = ((k & mask) << (l - cb)) | (k >> cb);
+  cls[i] = (uint32_t)key[i] & ((1u << cb) - 1u);
   idx[i] = i;
 }
 
@@ -259,28 +254,32 @@ __global__ void k_inverse(const int32_t* order, int32_t nc, int32_t* inv) {
   if (i < nc) inv[order[i]] = i;
 }
 
-__global__ void k_group_bitmap(int32_t nc, const int32_t* far_ptr, const int32_t* far_did, const int32_t* inv,
-                               int TC, int words, uint32_t* bitmap) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_group_bitmap(int32_t nc, const int32_t* far_ptr, const int32_t* far_did,
+                                                      const int32_t* inv, int TC, int words, uint32_t* bitmap) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= nc) return;
-  const int gidx = inv[c] / TC;
-  uint32_t* bm = bitmap + (int64_t)gidx * words;
-  for (int e = far_ptr[c]; e < far_ptr[c + 1]; e++) {
+  uint32_t* bm = bitmap + (int64_t)(inv[c] / TC) * words;
+  for (int e = far_ptr[c] + lane; e < far_ptr[c + 1]; e += 64) {
     const int d = far_did[e];
     atomicOr(&bm[d >> 5], 1u << (d & 31));
   }
 }
 
-__global__ void k_group_count(int32_t ng, int words, const uint32_t* bitmap, int32_t* cnt) {
+// per group: exclusive popcount prefix over its words, and its step count
+__global__ void k_group_prefix(int32_t ng, int words, const uint32_t* bitmap, int32_t* wpre, int32_t* cnt) {
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= ng) return;
   int s = 0;
-  for (int w = 0; w < words; w++) s += __popc(bitmap[(int64_t)gi * words + w]);
+  for (int w = 0; w < words; w++) {
+    wpre[(int64_t)gi * words + w] = s;
+    s += __popc(bitmap[(int64_t)gi * words + w]);
+  }
   cnt[gi] = s;
 }
 
-__global__ void k_group_steps(int32_t ng, int words, const uint32_t* bitmap, const int32_t* goff,
-                              int64_t step_base, int64_t drow0, int32_t* step_delta) {
+__global__ void k_group_steps(int32_t ng, int words, const uint32_t* bitmap, const int32_t* goff, int64_t step_base,
+                              int64_t drow0, int32_t* step_delta) {
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= ng) return;
   int64_t s = step_base + goff[gi];
@@ -294,21 +293,20 @@ __global__ void k_group_steps(int32_t ng, int words, const uint32_t* bitmap, con
   }
 }
 
-__global__ void k_step_src(int32_t nc, const int32_t* far_ptr, const int32_t* far_idx, const int32_t* far_did,
-                           const int32_t* inv, int TC, int words, const uint32_t* bitmap, const int32_t* goff,
-                           int64_t step_base, int32_t* step_src) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_step_src(int32_t nc, const int32_t* far_ptr, const int32_t* far_idx,
+                                                  const int32_t* far_did, const int32_t* inv, int TC, int words,
+                                                  const uint32_t* bitmap, const int32_t* wpre, const int32_t* goff,
+                                                  int64_t step_base, int32_t* step_src) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= nc) return;
   const int pos = inv[c];
   const int gi = pos / TC, tc = pos % TC;
-  const uint32_t* bm = bitmap + (int64_t)gi * words;
-  for (int e = far_ptr[c]; e < far_ptr[c + 1]; e++) {
+  const int64_t base = (int64_t)gi * words;
+  for (int e = far_ptr[c] + lane; e < far_ptr[c + 1]; e += 64) {
     const int d = far_did[e];
-    int rank = 0;
-    for (int w = 0; w < (d >> 5); w++) rank += __popc(bm[w]);
-    rank += __popc(bm[d >> 5] & ((1u << (d & 31)) - 1u));
-    const int64_t s = step_base + goff[gi] + rank;
-    step_src[s * TC + tc] = far_idx[e];
+    const int rank = wpre[base + (d >> 5)] + __popc(bitmap[base + (d >> 5)] & ((1u << (d & 31)) - 1u));
+    step_src[(step_base + goff[gi] + rank) * TC + tc] = far_idx[e];
   }
 }
 
@@ -337,28 +335,29 @@ __global__ void k_tile_tgt(int32_t nc, int32_t ng, int TC, const int32_t* order,
 void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   const int L = P.L;
   const int T = 256;
-  // columns of a wavefront tile: TC targets x TB configurations (TC*TB = 16)
-  int tb = 1;
-  while (tb < nbatch && tb < 16) tb <<= 1;
+  const int tb = tile_batch(nbatch);
   P.TB = tb;
-  P.TC = 16 / tb;
+  P.TC = kTileCols / tb;
   P.ncg = ceil_div(nbatch, tb);
   const int TC = P.TC;
   // pass 1: ordering, bitmaps, step counts per target group
-  std::vector<int64_t> bm_off(L + 2, 0), g_off(L + 2, 0);
-  std::vector<int> words(L + 1, 0);
+  int64_t nbm = 0, ngc = 0;
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
     D.ngroups = ceil_div(D.ncells, TC);
-    words[l] = std::max(1, ceil_div(D.ndelta, 32));
-    bm_off[l + 1] = bm_off[l] + (int64_t)D.ngroups * words[l];
-    g_off[l + 1] = g_off[l] + D.ngroups + 1;
+    D.words = std::max(1, ceil_div(D.nbox, 32));
+    D.bm0 = nbm;
+    D.g0 = ngc;
+    nbm += (int64_t)D.ngroups * D.words;
+    ngc += D.ngroups + 1;
   }
-  uint32_t* bitmap = reinterpret_cast<uint32_t*>(P.bitmap.ensure(sizeof(uint32_t) * std::max<int64_t>(1, bm_off[L + 1])));
-  int32_t* gbuf = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * 2 * (g_off[L + 1] + 1)));
+  // bitmap | word prefixes, group counts | group offsets
+  uint32_t* bitmap = reinterpret_cast<uint32_t*>(P.bitmap.ensure(sizeof(uint32_t) * 2 * std::max<int64_t>(1, nbm)));
+  int32_t* wpre = reinterpret_cast<int32_t*>(bitmap + std::max<int64_t>(1, nbm));
+  int32_t* gbuf = reinterpret_cast<int32_t*>(P.gcount.ensure(sizeof(int32_t) * 2 * (ngc + 1)));
   int32_t* gcnt = gbuf;
-  int32_t* goff = gbuf + g_off[L + 1] + 1;
-  fill_i32(reinterpret_cast<int32_t*>(bitmap), bm_off[L + 1], 0, st);
+  int32_t* goff = gbuf + ngc + 1;
+  fill_i32(reinterpret_cast<int32_t*>(bitmap), nbm, 0, st);
   std::vector<int32_t> lsteps(L + 1, 0);
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
@@ -366,21 +365,22 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
     int32_t* order = reinterpret_cast<int32_t*>(D.order.ensure(sizeof(int32_t) * 2 * std::max(1, nc)));
     int32_t* inv = order + std::max(1, nc);
     const int cb = std::min(P.class_bits, l);
-    k_rot_keys<<<ceil_div(nc, T), T, 0, st>>>(D.key.as<int32_t>(), nc, l, cb, P.key_tmp.as<uint32_t>(), order);
+    k_class_keys<<<ceil_div(nc, T), T, 0, st>>>(D.key.as<int32_t>(), nc, cb, P.key_tmp.as<uint32_t>(), order);
     CCFMM_HIP(hipGetLastError());
-    // sort by rotated key (stable; compact order is key order)
-    radix_sort_pairs(P.key_tmp.as<uint32_t>(), order, P.key.as<uint32_t>(), inv, nc, l, P.scratch, st);
+    // stable sort by class: compact order is key order, so this yields (class, key)
+    radix_sort_pairs(P.key_tmp.as<uint32_t>(), order, P.key.as<uint32_t>(), inv, nc, cb, P.scratch, st);
     k_inverse<<<ceil_div(nc, T), T, 0, st>>>(order, nc, inv);
     CCFMM_HIP(hipGetLastError());
-    if (D.nfar > 0) {
-      k_group_bitmap<<<ceil_div(nc, T), T, 0, st>>>(nc, D.far_ptr.as<int32_t>(), D.far_did.as<int32_t>(), inv, TC,
-                                                     words[l], bitmap + bm_off[l]);
+    if (l > 0) {
+      k_group_bitmap<<<ceil_div(nc, 4), T, 0, st>>>(nc, D.far_ptr.as<int32_t>(), D.far_did.as<int32_t>(), inv, TC,
+                                                    D.words, bitmap + D.bm0);
       CCFMM_HIP(hipGetLastError());
     }
-    k_group_count<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, words[l], bitmap + bm_off[l], gcnt + g_off[l]);
+    k_group_prefix<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, D.words, bitmap + D.bm0, wpre + D.bm0,
+                                                         gcnt + D.g0);
     CCFMM_HIP(hipGetLastError());
-    scan_exclusive(gcnt + g_off[l], goff + g_off[l], D.ngroups, P.scratch, st);
-    CCFMM_HIP(hipMemcpyAsync(&lsteps[l], goff + g_off[l] + D.ngroups, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    scan_exclusive(gcnt + D.g0, goff + D.g0, D.ngroups, P.scratch, st);
+    CCFMM_HIP(hipMemcpyAsync(&lsteps[l], goff + D.g0 + D.ngroups, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   }
   CCFMM_HIP(hipStreamSynchronize(st));
   int64_t nsteps = 0, ntiles = 0, ntgt = 0;
@@ -394,8 +394,8 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
     ntiles += D.ntiles;
     ntgt += (int64_t)D.ngroups * TC;
   }
-  // level 0 (the root) never has far cells; it still gets a tile so that its
-  // (zero) local expansion is written like every other cell's
+  // the root gets a tile too, so its (zero) local expansion is written like
+  // every other cell's
   P.nsteps = nsteps;
   P.ntiles = ntiles;
   int32_t* step_delta = reinterpret_cast<int32_t*>(P.step_delta.ensure(sizeof(int32_t) * std::max<int64_t>(1, nsteps)));
@@ -409,49 +409,57 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
     const int nc = D.ncells;
     int32_t* order = D.order.as<int32_t>();
     int32_t* inv = order + std::max(1, nc);
-    k_group_steps<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, words[l], bitmap + bm_off[l], goff + g_off[l],
-                                                          D.step0, D.drow0, step_delta);
+    k_group_steps<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, D.words, bitmap + D.bm0, goff + D.g0, D.step0,
+                                                        D.drow0, step_delta);
     CCFMM_HIP(hipGetLastError());
-    if (D.nfar > 0) {
-      k_step_src<<<ceil_div(nc, T), T, 0, st>>>(nc, D.far_ptr.as<int32_t>(), D.far_idx.as<int32_t>(),
-                                                 D.far_did.as<int32_t>(), inv, TC, words[l], bitmap + bm_off[l],
-                                                 goff + g_off[l], D.step0, step_src);
+    if (l > 0) {
+      k_step_src<<<ceil_div(nc, 4), T, 0, st>>>(nc, D.far_ptr.as<int32_t>(), D.far_idx.as<int32_t>(),
+                                                D.far_did.as<int32_t>(), inv, TC, D.words, bitmap + D.bm0,
+                                                wpre + D.bm0, goff + D.g0, D.step0, step_src);
       CCFMM_HIP(hipGetLastError());
     }
     k_tile_tgt<<<ceil_div((int64_t)D.ngroups * TC, T), T, 0, st>>>(nc, D.ngroups, TC, order, tile_tgt + tgt_base);
     CCFMM_HIP(hipGetLastError());
-    k_tiles<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, l, TC, P.TB, P.ncg, D.step0, tgt_base,
-                                                  goff + g_off[l], tiles, D.tile0);
+    k_tiles<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, l, TC, P.TB, P.ncg, D.step0, tgt_base, goff + D.g0,
+                                                  tiles, D.tile0);
     CCFMM_HIP(hipGetLastError());
     tgt_base += (int64_t)D.ngroups * TC;
   }
-  CCFMM_HIP(hipStreamSynchronize(st));
 }
 
 // ---------------------------------------------------------------- P2P chunks
-void build_p2p_chunks(Plan& P, hipStream_t st) {
-  LevelData& D = *P.lev[P.L];
-  const int nl = D.ncells;
-  std::vector<int32_t> start(nl), count(nl);
-  CCFMM_HIP(hipMemcpyAsync(start.data(), P.lstart.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
-  CCFMM_HIP(hipMemcpyAsync(count.data(), P.lcount.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
-  CCFMM_HIP(hipStreamSynchronize(st));
-  std::vector<P2PChunk> ch;
-  ch.reserve(nl);
-  for (int i = 0; i < nl; i++) {
-    for (int off = 0; off < count[i]; off += 64) {
-      P2PChunk c;
-      c.leaf = i;
-      c.first = start[i] + off;
-      c.count = std::min(64, count[i] - off);
-      c.pad = 0;
-      ch.push_back(c);
-    }
+// Every occupied smallest cell is cut into chunks of at most 64 dipoles; the
+// chunk count stays in device memory (the P2P launch is sized by its bound).
+__global__ void k_chunk_count(int32_t nl, const int32_t* lcount, int32_t* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nl) cnt[i] = (lcount[i] + 63) >> 6;
+}
+
+__global__ void k_chunk_fill(int32_t nl, const int32_t* lstart, const int32_t* lcount, const int32_t* off,
+                             P2PChunk* ch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  for (int k = 0, o = off[i]; k < lcount[i]; k += 64, o++) {
+    P2PChunk c;
+    c.leaf = i;
+    c.first = lstart[i] + k;
+    c.count = min(64, lcount[i] - k);
+    c.pad = 0;
+    ch[o] = c;
   }
-  P.nchunks = (int64_t)ch.size();
-  void* d = P.chunks.ensure(sizeof(P2PChunk) * std::max<size_t>(1, ch.size()));
-  CCFMM_HIP(hipMemcpyAsync(d, ch.data(), sizeof(P2PChunk) * ch.size(), hipMemcpyHostToDevice, st));
-  CCFMM_HIP(hipStreamSynchronize(st));
+}
+
+void build_p2p_chunks(Plan& P, hipStream_t st) {
+  const int nl = P.lev[P.L]->ncells;
+  P.nchunks_cap = (int64_t)nl + P.n / 64 + 1;
+  int32_t* cnt = reinterpret_cast<int32_t*>(P.chunk_cnt.ensure(sizeof(int32_t) * 2 * (nl + 1)));
+  int32_t* off = cnt + nl + 1;
+  k_chunk_count<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lcount.as<int32_t>(), cnt);
+  CCFMM_HIP(hipGetLastError());
+  scan_exclusive(cnt, off, nl, P.scratch, st);  // off[nl] = number of chunks
+  P2PChunk* ch = reinterpret_cast<P2PChunk*>(P.chunks.ensure(sizeof(P2PChunk) * P.nchunks_cap));
+  k_chunk_fill<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), off, ch);
+  CCFMM_HIP(hipGetLastError());
 }
 
 }  // namespace ccfmm

@@ -1,15 +1,19 @@
 // m2l.hip -- the M2L pass, Eq.(taylorcalc), on the matrix cores.
 //
 // For target cell C and source cell A at integer offset delta (same level),
-//   Vt_n(C) += (-1)^|n| sum_q D_{n+q}(delta*g) Qt_q(A),   1 <= |n|, |q| <= p,
-// in the level's scaled units.  The operator depends only on delta, so pairs
-// are grouped by offset: a wavefront owns a tile of 16 columns (target cell,
-// configuration) and walks the tile's offsets; every step is a dense
-// [NP x NP] x [NP x 16] product on the MFMA units with the accumulators kept
-// in registers for the whole walk, so each target column is written once.
-// The [NP x NP] operator of a step is never stored: its entries are gathered
-// from the step's derivative tensor (ncoef(2p) values in LDS) through a
-// per-block index table idx(n+q) (the operator is Hankel-like in n+q).
+//   Vt_n(C) += (-1)^|n| sum_q D_{n+q}(c) Qt_q(A),   1 <= |n|, |q| <= p,
+// in the level's scaled units (c = target minus source centre).  The operator
+// depends only on the offset, so the pairs are grouped by offset: a block of
+// four wavefronts owns a tile of 64 columns (target cell, configuration) whose
+// cells share one list of offsets, and walks that list.  Each step is a dense
+// [NP x NP] x [NP x 64] product on the MFMA units: the step's operator is
+// materialised once in LDS, in MFMA operand order, from the ncoef(2p)
+// derivative-tensor entries (it is Hankel-like: entry (n, q) is D_{n+q}), and
+// all four wavefronts read it conflict-free for their 16 columns each.  The
+// accumulators stay in registers for the whole walk, so each target column is
+// written once and no atomics are needed.
+#include <type_traits>
+
 #include "plan.hpp"
 
 namespace ccfmm {
@@ -47,84 +51,109 @@ __device__ __forceinline__ int acc_row<double>(int kq, int r) {
   return kq + 4 * r;
 }
 
-__device__ __forceinline__ void lds_wave_sync() {
-  // DS instructions of one wavefront execute in issue order; this keeps the
-  // compiler from moving LDS accesses across the point and waits for them.
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 struct LevelOffsets {
   int64_t qoff[kLMax + 1];
 };
 
-// Launch geometry: WPB wavefronts per block, one tile per wavefront.
-template <typename T, int P, int WPB>
-__global__ void __launch_bounds__(64 * WPB) k_m2l(const M2LTile* __restrict__ tiles, int64_t ntiles,
-                                                 const int32_t* __restrict__ tile_tgt,
-                                                 const int32_t* __restrict__ step_delta,
-                                                 const int32_t* __restrict__ step_src, const T* __restrict__ Dtab,
-                                                 const T* __restrict__ Q, T* __restrict__ V, LevelOffsets lo, int nb,
-                                                 int TB, int TC) {
+// Compile-time shape of the M2L kernel for order P and element type T.
+template <typename T, int P>
+struct M2LShape {
+  static constexpr int NP = nact(P);
+  static constexpr int NS = nstride(P);      // K extent (multiple of 4)
+  static constexpr int MB = (NP + 15) / 16;  // 16-row blocks
+  static constexpr int KS = NS / 4;          // k steps of 4
+  static constexpr int ND = ncoef(2 * P);    // derivative-tensor entries
+  static constexpr int QST = 65;             // padded stride of one Q fragment
+  static constexpr int LDS_Q = 4 * KS * QST * (int)sizeof(T);
+  static constexpr int LDS_D = (ND + 1) * (int)sizeof(T);
+  static constexpr int LDS_MB = KS * 64 * (int)sizeof(T);  // one M-block of operator
+  // two blocks per CU when the operator fits in ~76 KB, else one
+  static constexpr int BUDGET = (LDS_Q + LDS_D + LDS_MB <= 76 * 1024) ? 76 * 1024 : 156 * 1024;
+  static constexpr int MBC_FIT = (BUDGET - LDS_Q - LDS_D) / LDS_MB;
+  static constexpr int MBC = MBC_FIT < MB ? MBC_FIT : MB;   // M-blocks per operator chunk
+  static constexpr int NCH = (MB + MBC - 1) / MBC;
+  static constexpr int NT = MBC * KS * 64;                  // operator entries per chunk
+  static constexpr int TR = (NT + 255) / 256;               // per thread per chunk
+  static constexpr int TRA = TR * NCH;                      // per thread, all chunks
+  static constexpr int NQ = 64 * NS;
+  static constexpr int QR = (NQ + 255) / 256;
+  static constexpr int DR = (ND + 255) / 256;
+};
+
+// Flat index of n + q for operator entry (m, k) (active coefficients m, k);
+// ND (a zero entry) for padding rows/columns.
+template <int P>
+__device__ __forceinline__ int op_index(int m, int k) {
   constexpr int NP = nact(P);
-  constexpr int NS = nstride(P);       // K extent, multiple of 4
-  constexpr int MB = (NP + 15) / 16;   // 16-row blocks
-  constexpr int KS = NS / 4;           // k steps
-  constexpr int ND = ncoef(2 * P);     // derivative tensor entries
-  constexpr int NQ = 16 * NS;          // Q tile entries
-  constexpr int LD_ROUNDS = (ND + 63) / 64;
-  constexpr int LQ_ROUNDS = (NQ + 63) / 64;
+  if (m >= NP || k >= NP) return ncoef(2 * P);
+  const int a = m + 1, b = k + 1;
+  return midx(kMI.x[a] + kMI.x[b], kMI.y[a] + kMI.y[b], kMI.z[a] + kMI.z[b]);
+}
 
-  __shared__ uint16_t sidx[MB * 16][NS];   // idx(n+q) (ND = zero entry for padding)
-  __shared__ T sD[WPB][ND + 1];
-  __shared__ T sQ[WPB][16][NS + 1];
+template <typename T, int P>
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && P <= 6) ? 2 : 1) k_m2l(const M2LTile* __restrict__ tiles, int64_t ntiles,
+                                             const int32_t* __restrict__ tile_tgt,
+                                             const int32_t* __restrict__ step_delta,
+                                             const int32_t* __restrict__ step_src, const T* __restrict__ Dtab,
+                                             const T* __restrict__ Q, T* __restrict__ V, LevelOffsets lo, int nb,
+                                             int TB, int TC) {
+  using S = M2LShape<T, P>;
+  constexpr int MB = S::MB, KS = S::KS, NS = S::NS, ND = S::ND, QST = S::QST;
+  constexpr int MBC = S::MBC, NCH = S::NCH, NT = S::NT, TR = S::TR;
+  __shared__ T sD[ND + 1];
+  __shared__ T sT[NT];
+  __shared__ T sQ[4 * KS * QST];
 
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // index table: row m <-> active coefficient m (flat m+1), column k likewise
-  for (int e = threadIdx.x; e < MB * 16 * NS; e += 64 * WPB) {
-    const int m = e / NS, k = e % NS;
-    uint16_t v = (uint16_t)ND;
-    if (m < NP && k < NP) {
-      const int a = m + 1, b = k + 1;
-      v = (uint16_t)midx(kMI.x[a] + kMI.x[b], kMI.y[a] + kMI.y[b], kMI.z[a] + kMI.z[b]);
-    }
-    sidx[m][k] = v;
-  }
-  __syncthreads();
-
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
   // range of tiles so neighbouring tiles (shared sources) share an L2
   const int nblk = gridDim.x;
   const int bid = blockIdx.x;
-  const int lb = (nblk % 8 == 0) ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
-  const int64_t tile = (int64_t)lb * WPB + w;
+  const int64_t tile = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
   if (tile >= ntiles) return;
-
   const M2LTile tl = tiles[tile];
   const T* Ql = Q + lo.qoff[tl.level];
-  T* Vl = V + lo.qoff[tl.level];
+
+  // this thread's operator entries (step independent): (chunk, r) -> index
+  uint32_t myidx[(NCH * TR + 1) / 2];
+#pragma unroll
+  for (int i = 0; i < (NCH * TR + 1) / 2; i++) myidx[i] = 0;
+#pragma unroll
+  for (int ch = 0; ch < NCH; ch++) {
+#pragma unroll
+    for (int r = 0; r < TR; r++) {
+      const int e = t + 256 * r;
+      int v = ND;
+      if (e < NT) {
+        const int mbl = e / (KS * 64), rem = e % (KS * 64);
+        const int ks = rem >> 6, l = rem & 63;
+        const int mb = ch * MBC + mbl;
+        if (mb < MB) v = op_index<P>(16 * mb + (l & 15), 4 * ks + (l >> 4));
+      }
+      const int q = ch * TR + r;
+      myidx[q >> 1] |= (uint32_t)v << (16 * (q & 1));
+    }
+  }
+
   using AccT = typename Acc<T>::type;
   AccT acc[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; mb++) acc[mb] = AccT{0, 0, 0, 0};
 
-  const int col = lane & 15, kq = lane >> 4;
-  // columns handled by this lane when loading Q: entry e = lane + 64 r
-  T rD[LD_ROUNDS], rQ[LQ_ROUNDS];
+  T rD[S::DR], rQ[S::QR];
   auto fetch = [&](int s) {
     const int64_t st = (int64_t)tl.step0 + s;
     const T* drow = Dtab + (int64_t)step_delta[st] * ND;
 #pragma unroll
-    for (int r = 0; r < LD_ROUNDS; r++) {
-      const int e = lane + 64 * r;
+    for (int r = 0; r < S::DR; r++) {
+      const int e = t + 256 * r;
       rD[r] = (e < ND) ? drow[e] : (T)0;
     }
 #pragma unroll
-    for (int r = 0; r < LQ_ROUNDS; r++) {
-      const int e = lane + 64 * r;
+    for (int r = 0; r < S::QR; r++) {
+      const int e = t + 256 * r;
       T v = (T)0;
-      if (e < NQ) {
+      if (e < S::NQ) {
         const int j = e / NS, k = e % NS;
         const int tc = j / TB, b = tl.b0 + (j % TB);
         if (tc < TC && b < nb) {
@@ -137,37 +166,51 @@ __global__ void __launch_bounds__(64 * WPB) k_m2l(const M2LTile* __restrict__ ti
   };
   if (tl.nsteps > 0) fetch(0);
   for (int s = 0; s < tl.nsteps; s++) {
-    // stage this step's operator entries and Q columns
+    // stage the step's derivative tensor and its Q columns (fragment order)
 #pragma unroll
-    for (int r = 0; r < LD_ROUNDS; r++) {
-      const int e = lane + 64 * r;
-      if (e < ND) sD[w][e] = rD[r];
+    for (int r = 0; r < S::DR; r++) {
+      const int e = t + 256 * r;
+      if (e < ND) sD[e] = rD[r];
     }
-    if (lane == 0) sD[w][ND] = (T)0;
+    if (t == 0) sD[ND] = (T)0;
 #pragma unroll
-    for (int r = 0; r < LQ_ROUNDS; r++) {
-      const int e = lane + 64 * r;
-      if (e < NQ) sQ[w][e / NS][e % NS] = rQ[r];
-    }
-    lds_wave_sync();
-    if (s + 1 < tl.nsteps) fetch(s + 1);  // overlap the next step's loads with this step's products
-#pragma unroll
-    for (int ks = 0; ks < KS; ks++) {
-      const T bq = sQ[w][col][4 * ks + kq];
-#pragma unroll
-      for (int mb = 0; mb < MB; mb++) {
-        const T a = sD[w][sidx[16 * mb + col][4 * ks + kq]];
-        acc[mb] = mfma16x16x4(a, bq, acc[mb]);
+    for (int r = 0; r < S::QR; r++) {
+      const int e = t + 256 * r;
+      if (e < S::NQ) {
+        const int j = e / NS, k = e % NS;
+        sQ[((j >> 4) * KS + (k >> 2)) * QST + (j & 15) + 16 * (k & 3)] = rQ[r];
       }
     }
-    lds_wave_sync();
+    if (s + 1 < tl.nsteps) fetch(s + 1);  // next step's loads overlap this step's products
+#pragma unroll
+    for (int ch = 0; ch < NCH; ch++) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < TR; r++) {
+        const int e = t + 256 * r;
+        const int q = ch * TR + r;
+        if (e < NT) sT[e] = sD[(myidx[q >> 1] >> (16 * (q & 1))) & 0xffffu];
+      }
+      __syncthreads();
+#pragma unroll 7
+      for (int ks = 0; ks < KS; ks++) {
+        const T bq = sQ[(w * KS + ks) * QST + lane];
+#pragma unroll
+        for (int mbl = 0; mbl < MBC; mbl++) {
+          const int mb = ch * MBC + mbl;
+          if (mb < MB) acc[mb] = mfma16x16x4(sT[(mbl * KS + ks) * 64 + lane], bq, acc[mb]);
+        }
+      }
+    }
+    __syncthreads();
   }
-  // write: lane holds rows 16 mb + acc_row(kq, r) of column col
+  // write: lane holds rows 16 mb + acc_row(l/16, r) of column 16 w + l % 16
+  const int col = 16 * w + (lane & 15), kq = lane >> 4;
   const int tc = col / TB, b = tl.b0 + (col % TB);
   if (tc < TC && b < nb) {
     const int tgt = tile_tgt[tl.tgt0 + tc];
     if (tgt >= 0) {
-      T* out = Vl + ((int64_t)tgt * nb + b) * NS;
+      T* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + b) * NS;
 #pragma unroll
       for (int mb = 0; mb < MB; mb++) {
 #pragma unroll
@@ -175,7 +218,7 @@ __global__ void __launch_bounds__(64 * WPB) k_m2l(const M2LTile* __restrict__ ti
           const int m = 16 * mb + acc_row<T>(kq, r);
           if (m < NS) {
             T v = (T)0;
-            if (m < NP) {
+            if (m < S::NP) {
               const int f = m + 1;
               const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
               v = (deg & 1) ? -acc[mb][r] : acc[mb][r];
@@ -190,15 +233,13 @@ __global__ void __launch_bounds__(64 * WPB) k_m2l(const M2LTile* __restrict__ ti
 
 template <typename T, int PP>
 static void m2l_impl(Plan& P, int nb, hipStream_t st) {
-  constexpr int WPB = (PP >= 7 && sizeof(T) == 8) ? 2 : 4;
   LevelOffsets lo{};
   for (int l = 0; l <= P.L; l++) lo.qoff[l] = P.lev[l]->qoff;
   const T* D = std::is_same<T, double>::value ? (const T*)P.Dd.p : (const T*)P.Df.p;
-  const int nblk = ceil_div(P.ntiles, WPB);
-  if (nblk == 0) return;
-  k_m2l<T, PP, WPB><<<nblk, 64 * WPB, 0, st>>>(P.tiles.as<M2LTile>(), P.ntiles, P.tile_tgt.as<int32_t>(),
-                                                P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), D,
-                                                P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
+  if (P.ntiles == 0) return;
+  k_m2l<T, PP><<<(unsigned)P.ntiles, 256, 0, st>>>(P.tiles.as<M2LTile>(), P.ntiles, P.tile_tgt.as<int32_t>(),
+                                                   P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), D,
+                                                   P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
   CCFMM_HIP(hipGetLastError());
 }
 
@@ -234,8 +275,8 @@ __global__ void k_mfma_probe(const float* A, const float* B, float* Cf, const do
   f64x4 cd = {0, 0, 0, 0};
   cd = mfma16x16x4(Ad[i * 4 + k], Bd[k * 16 + i], cd);
   for (int r = 0; r < 4; r++) {
-    Cf[(4 * k + r) * 16 + i] = c[r];
-    Cd[(k + 4 * r) * 16 + i] = cd[r];
+    Cf[acc_row<float>(k, r) * 16 + i] = c[r];
+    Cd[acc_row<double>(k, r) * 16 + i] = cd[r];
   }
 }
 

@@ -1,6 +1,7 @@
 // plan.hpp -- the plan object: tree, lists, derivative tensors and M2L tiles
 // of one geometry, plus the expansion buffers of its evaluations.
 #pragma once
+#include <array>
 #include <memory>
 
 #include "internal.hpp"
@@ -28,15 +29,21 @@ struct LevelData {
   int64_t nnear = 0;
   DevBuf far_ptr;       // CSR (ncells+1) of far cells (M2L sources)
   DevBuf far_idx;
-  DevBuf far_did;       // Delta id (level-local) of each far entry
+  DevBuf far_did;       // dense offset id of each far entry (box wfar)
   int64_t nfar = 0;
-  int32_t ndelta = 0;
-  int64_t drow0 = 0;    // first row of this level in the derivative-tensor table
-  int wbox[3] = {0, 0, 0};  // Delta box half-widths
-  DevBuf delta_vec;     // ndelta * 3 int32
+  // offset bounds (host): near offsets lie in [-wnear, wnear], every candidate
+  // (near or far) in [-wfar, wfar]; cnear = most near cells any cell can have
+  int wnear[3] = {0, 0, 0};
+  int wfar[3] = {0, 0, 0};
+  int64_t cnear = 1;
+  int64_t nbox = 1;     // dense offset ids of the level: prod(2 wfar + 1)
+  int64_t drow0 = 0;    // derivative-tensor row of dense id 0
   // M2L tiling
-  DevBuf order;         // tile order position -> compact target
+  DevBuf order;         // tile order position -> compact target, then its inverse
   int32_t ngroups = 0;  // target groups of TC cells
+  int words = 1;        // bitmap words per group
+  int64_t bm0 = 0;      // first bitmap word of the level
+  int64_t g0 = 0;       // first group counter of the level
   int64_t step0 = 0;    // first global step of the level
   int64_t nsteps = 0;
   int64_t tile0 = 0;
@@ -68,16 +75,20 @@ struct Plan {
   DevBuf cmap;       // heap id -> compact id within its level, -1 if empty
   std::vector<std::unique_ptr<LevelData>> lev;
 
-  // derivative tensors: rows (level, delta), ncoef(2p) values each
+  // derivative tensors: one dense table per distinct (g, wfar) of the levels,
+  // kept across rebuilds while the keys do not change
   int64_t nrows = 0;
   DevBuf Dd, Df;
+  int dtab_p = 0;
+  std::vector<std::array<double, 6>> dtab_keys;
   // M2L tiles
-  int TB = 16, TC = 1, ncg = 1;  // configs per tile, targets per tile, config groups
-  DevBuf tiles, tile_tgt, step_delta, step_src, bitmap;
+  int TB = 64, TC = 1, ncg = 1;  // configs per tile, targets per tile, config groups
+  DevBuf tiles, tile_tgt, step_delta, step_src, bitmap, gcount;
   int64_t ntiles = 0, nsteps = 0;
-  // P2P chunks
-  DevBuf chunks;
-  int64_t nchunks = 0;
+  // P2P chunks (built on the device; their count stays in device memory)
+  DevBuf chunks, chunk_cnt;
+  int64_t nchunks_cap = 0;
+  int64_t nchunks = 0;  // filled at info time
   // expansions (compact cells of all levels)
   DevBuf Q, V;
   int64_t qv_elems = 0;
@@ -85,6 +96,7 @@ struct Plan {
   DevBuf m_sorted;   // moments in sorted order [b][3][n] (FP64 or FP32)
   DevBuf scratch;    // scan/sort temporaries
   DevBuf scratch2;
+  DevBuf flags;      // device error flags
   ccfmm_info info{};
   bool built = false;
 };
@@ -106,5 +118,10 @@ void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64
                         const int64_t* d_idx, double* d_H, hipStream_t st);
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// dense offset id of (dx, dy, dz) in the box [-w, w]^3
+__host__ __device__ inline int64_t box_index(const int w[3], int dx, int dy, int dz) {
+  return ((int64_t)(dx + w[0]) * (2 * w[1] + 1) + (dy + w[1])) * (2 * w[2] + 1) + (dz + w[2]);
+}
 
 }  // namespace ccfmm
