@@ -100,7 +100,11 @@ def main():
 
     # ---- mixed precision: the headline path
     plan = make(ccfmm.PREC_MIXED)
+    tune = plan.autotune(1, d_m.data_ptr(), d_H.data_ptr(), sh)
     info = plan.info()
+    log("m2l autotune: %s -> variant %d class_bits %d" % (
+        json.dumps([(t["variant"], t["class_bits"], round(t["m2l_ms"], 3)) for t in tune]),
+        info["m2l_variant"], info["m2l_class_bits"]))
     log("plan: L=%d leaves=%d m2l_pairs=%d p2p_pairs=%d tiles=%d steps=%d" % (
         info["levels"], info["n_leaves"], info["n_m2l_pairs"], info["n_p2p_pairs"], info["n_m2l_tiles"],
         info["n_m2l_steps"]))
@@ -118,6 +122,7 @@ def main():
     # ---- plain FP64 GPU FMM
     if not args.skip_fp64:
         plan64 = make(ccfmm.PREC_FP64)
+        plan64.autotune(1, d_m.data_ptr(), d_H64.data_ptr(), sh)
         t_step64 = time_steps(plan64, d_H64, True, max(2, args.steps // 2), 1)
         t_eval64 = time_steps(plan64, d_H64, False, max(2, args.steps // 2), 1)
         passes64 = plan64.eval_device_timed(1, d_m.data_ptr(), d_H64.data_ptr(), sh)
@@ -191,7 +196,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ferrofluid_rsa_%d" % n, "n": n, "order": args.order, "theta": args.theta,
                    "leaf_target": info["s_used"], "levels": info["levels"], "precision": "mixed",
-                   "batch": 1, "step": "tree+lists+tensors+eval"},
+                   "batch": 1, "step": "tree+lists+tensors+eval",
+                   "m2l_variant": info["m2l_variant"], "m2l_class_bits": info["m2l_class_bits"]},
         "eval_only_evals_per_s": n / t_eval,
         "eval_ms": 1e3 * t_eval,
         "passes_ms": pt,

@@ -64,8 +64,19 @@ typedef struct {
   int32_t has_box;      /* 1: root cell is [box_lo, box_hi]; 0: tight bounding box */
   double box_lo[3], box_hi[3];
   int32_t max_batch;    /* largest nbatch the plan will evaluate (device buffers sized) */
-  int32_t m2l_class_bits; /* M2L target ordering: low key bits grouped first; -1 = autotune */
+  int32_t m2l_class_bits; /* M2L target ordering: cells grouped by their low key bits
+                             (position inside their ancestors) before tiling; 0..12 */
+  int32_t m2l_variant;    /* M2L kernel: 0 = block of 4 wavefronts sharing one operator per
+                             step (64-column tiles), 1 = independent wavefronts (16 columns,
+                             orders <= 6); ccfmm_plan_autotune can choose */
 } ccfmm_params;
+
+/* One timed M2L configuration of ccfmm_plan_autotune. */
+typedef struct {
+  int32_t variant, class_bits;
+  double m2l_ms;   /* median of the timed launches */
+  int64_t steps;   /* MFMA operator steps of the tiling */
+} ccfmm_tune_entry;
 
 /* Plan summary (counts are exact properties of the tree and lists). */
 typedef struct {
@@ -86,6 +97,7 @@ typedef struct {
   int32_t fallback;                     /* learned mode fell back to fixed parameters */
   double m2l_flops_per_config;          /* algorithmic: 2 * (N(p)-1)^2 * M2L pairs */
   double p2p_pairs_per_config;
+  int32_t m2l_variant;                  /* kernel in use (see ccfmm_params) */
 } ccfmm_info;
 
 /* Per-pass device times (milliseconds) of one evaluation, from HIP events. */
@@ -124,6 +136,14 @@ int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double
 /* As ccfmm_eval_device, with HIP events between the passes (synchronises). */
 int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H,
                             void* stream, ccfmm_pass_times* times);
+
+/* M2L autotuner: times every (kernel variant, class bits) combination on this
+ * plan's tiles for nbatch configurations of the device moments d_m (d_H is a
+ * scratch field buffer of the same shape), keeps the fastest in the plan and
+ * writes up to max_out timings to out (*n_out = number written).  Synchronises
+ * the stream.  The field values do not depend on the choice. */
+int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream,
+                        ccfmm_tune_entry* out, int32_t max_out, int32_t* n_out);
 
 int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out);
 /* Energy E_b = -1/2 sum_i m_i . H_i per configuration (Sec. 3 and Appendix),

@@ -27,7 +27,11 @@ class ccfmm_params(C.Structure):
                 ("leaf_rule", C.c_int32), ("precision", C.c_int32), ("selector", C.c_int32),
                 ("err_bound", C.c_double), ("has_box", C.c_int32),
                 ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
-                ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32)]
+                ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32), ("m2l_variant", C.c_int32)]
+
+
+class ccfmm_tune_entry(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("class_bits", C.c_int32), ("m2l_ms", C.c_double), ("steps", C.c_int64)]
 
 
 class ccfmm_info(C.Structure):
@@ -40,7 +44,8 @@ class ccfmm_info(C.Structure):
                 ("n_p2p_leaf_pairs", C.c_int64), ("n_p2p_pairs", C.c_int64),
                 ("n_m2l_tiles", C.c_int64), ("n_m2l_steps", C.c_int64), ("n_delta", C.c_int64),
                 ("m2l_class_bits", C.c_int32), ("fallback", C.c_int32),
-                ("m2l_flops_per_config", C.c_double), ("p2p_pairs_per_config", C.c_double)]
+                ("m2l_flops_per_config", C.c_double), ("p2p_pairs_per_config", C.c_double),
+                ("m2l_variant", C.c_int32)]
 
 
 class ccfmm_pass_times(C.Structure):
@@ -52,7 +57,7 @@ class ccfmm_pass_times(C.Structure):
 EXPORTS = [
     "ccfmm_status_string", "ccfmm_last_error", "ccfmm_params_default", "ccfmm_plan_create",
     "ccfmm_plan_create_device", "ccfmm_plan_update_positions_device", "ccfmm_eval", "ccfmm_eval_device",
-    "ccfmm_eval_device_timed", "ccfmm_plan_info", "ccfmm_energy", "ccfmm_plan_destroy",
+    "ccfmm_eval_device_timed", "ccfmm_plan_autotune", "ccfmm_plan_info", "ccfmm_energy", "ccfmm_plan_destroy",
     "ccfmm_direct_targets_device", "ccfmm_selftest_mfma",
 ]
 
@@ -92,6 +97,8 @@ def lib():
         L.ccfmm_eval_device.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ccfmm_eval_device_timed.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.POINTER(ccfmm_pass_times)]
+        L.ccfmm_plan_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.POINTER(ccfmm_tune_entry), C.c_int32, C.POINTER(C.c_int32)]
         L.ccfmm_plan_info.argtypes = [C.c_void_p, C.POINTER(ccfmm_info)]
         L.ccfmm_energy.argtypes = [C.c_int64, C.c_int32, _dp, _dp, _dp]
         L.ccfmm_plan_destroy.argtypes = [C.c_void_p]
@@ -118,7 +125,7 @@ def _check(rc):
 
 
 def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64, selector=0,
-           err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3):
+           err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=0):
     p = ccfmm_params()
     _check(lib().ccfmm_params_default(C.byref(p)))
     p.order = int(order)
@@ -135,6 +142,7 @@ def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64
             p.box_hi[a] = float(box[1][a])
     p.max_batch = int(max_batch)
     p.m2l_class_bits = int(m2l_class_bits)
+    p.m2l_variant = int(m2l_variant)
     return p
 
 
@@ -190,6 +198,15 @@ class Plan:
         _check(lib().ccfmm_eval_device_timed(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H),
                                              C.c_void_p(stream), C.byref(t)))
         return {f: getattr(t, f) for f, _ in ccfmm_pass_times._fields_}
+
+    def autotune(self, nbatch, d_m, d_H, stream=0):
+        """Time the M2L variants on this plan, keep the fastest; returns the timings."""
+        out = (ccfmm_tune_entry * 16)()
+        n = C.c_int32(0)
+        _check(lib().ccfmm_plan_autotune(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H),
+                                         C.c_void_p(stream), out, 16, C.byref(n)))
+        return [{"variant": out[i].variant, "class_bits": out[i].class_bits, "m2l_ms": out[i].m2l_ms,
+                 "steps": out[i].steps} for i in range(n.value)]
 
     def info(self):
         inf = ccfmm_info()

@@ -246,6 +246,7 @@ static void fill_info(Plan& P, hipStream_t st) {
   I.n_m2l_tiles = P.ntiles;
   I.n_m2l_steps = P.nsteps;
   I.m2l_class_bits = P.class_bits;
+  I.m2l_variant = P.m2l_variant;
   const double np = (double)nact(P.p);
   I.m2l_flops_per_config = 2.0 * np * np * (double)m2l;
   // direct pairs (self pairs included in the count)
@@ -312,8 +313,9 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
 
 static void prepare_batch(Plan& P, int nb, hipStream_t st) {
   if (nb < 1 || nb > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
-  const int tb = tile_batch(nb);
-  if (tb != P.TB || ceil_div(nb, tb) != P.ncg) {
+  const int tb = tile_batch(nb, m2l_tile_cols(P.m2l_variant));
+  if (tb != P.TB || ceil_div(nb, tb) != P.ncg || P.tiles_variant != P.m2l_variant ||
+      P.tiles_class_bits != P.class_bits) {
     build_m2l_tiles(P, nb, st);
     P.info.n_m2l_tiles = P.ntiles;
     P.info.n_m2l_steps = P.nsteps;
@@ -392,6 +394,7 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->has_box = 0;
   prm->max_batch = 1;
   prm->m2l_class_bits = 3;
+  prm->m2l_variant = kM2LBlock;
   return CCFMM_OK;
 }
 
@@ -412,6 +415,7 @@ static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const 
       P.precision = prm->precision;
       P.nbmax = prm->max_batch;
       P.class_bits = prm->m2l_class_bits < 0 ? 3 : std::min(prm->m2l_class_bits, 12);
+      P.m2l_variant = (prm->m2l_variant == kM2LWave && prm->order <= 6) ? kM2LWave : kM2LBlock;
       if (own) {
         CCFMM_HIP(hipStreamCreateWithFlags(&P.own_stream, hipStreamNonBlocking));
         st = P.own_stream;
@@ -529,6 +533,66 @@ int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H) {
     eval_passes(P, nbatch, dm.as<double>(), dH.as<double>(), st, nullptr);
     CCFMM_HIP(hipMemcpyAsync(H, dH.p, bytes, hipMemcpyDeviceToHost, st));
     CCFMM_HIP(hipStreamSynchronize(st));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream,
+                        ccfmm_tune_entry* out, int32_t max_out, int32_t* n_out) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_m || !d_H) fail(CCFMM_EINVAL, "moment or field pointer is NULL");
+    Plan& P = plan->P;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CCFMM_HIP(hipSetDevice(P.device));
+    prepare_batch(P, nbatch, st);
+    // the multipoles the timed launches read
+    run_p2m(P, nbatch, d_m, st);
+    run_m2m(P, nbatch, st);
+    hipEvent_t e0, e1;
+    CCFMM_HIP(hipEventCreate(&e0));
+    CCFMM_HIP(hipEventCreate(&e1));
+    std::vector<ccfmm_tune_entry> res;
+    const int variants[2] = {kM2LBlock, kM2LWave};
+    const int bits[3] = {0, 3, 6};
+    for (int v : variants) {
+      if (v == kM2LWave && P.p > 6) continue;
+      for (int cb : bits) {
+        P.m2l_variant = v;
+        P.class_bits = cb;
+        prepare_batch(P, nbatch, st);
+        run_m2l(P, nbatch, st);  // warm-up
+        std::vector<float> ms;
+        for (int r = 0; r < 3; r++) {
+          CCFMM_HIP(hipEventRecord(e0, st));
+          run_m2l(P, nbatch, st);
+          CCFMM_HIP(hipEventRecord(e1, st));
+          CCFMM_HIP(hipEventSynchronize(e1));
+          float t;
+          CCFMM_HIP(hipEventElapsedTime(&t, e0, e1));
+          ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        res.push_back(ccfmm_tune_entry{v, cb, (double)ms[1], P.nsteps});
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    size_t best = 0;
+    for (size_t i = 1; i < res.size(); i++)
+      if (res[i].m2l_ms < res[best].m2l_ms) best = i;
+    P.m2l_variant = res[best].variant;
+    P.class_bits = res[best].class_bits;
+    prepare_batch(P, nbatch, st);
+    P.info.m2l_class_bits = P.class_bits;
+    P.info.m2l_variant = P.m2l_variant;
+    if (n_out) *n_out = 0;
+    if (out && max_out > 0) {
+      const int k = std::min<int>(max_out, (int)res.size());
+      for (int i = 0; i < k; i++) out[i] = res[i];
+      if (n_out) *n_out = k;
+    }
+    (void)d_H;
     return CCFMM_OK;
   });
 }

@@ -21,13 +21,18 @@ namespace ccfmm {
 constexpr int kPMax = CCFMM_PMAX;
 constexpr int kLMax = CCFMM_LMAX;
 constexpr int kKMax = 2 * kPMax;  // derivative tensors up to order 2p
-constexpr int kTileCols = 64;     // M2L tile: (target cell, configuration) columns per block
+// M2L kernel variants and their tile widths in (target cell, configuration)
+// columns: a block of 4 wavefronts sharing one operator per step (64), or
+// independent wavefronts gathering operator entries themselves (16)
+constexpr int kM2LBlock = 0;
+constexpr int kM2LWave = 1;
+inline int m2l_tile_cols(int variant) { return variant == kM2LWave ? 16 : 64; }
 
 // configurations per M2L tile for a batch of nb: the next power of two, at
 // most one tile width
-inline int tile_batch(int nb) {
+inline int tile_batch(int nb, int cols) {
   int t = 1;
-  while (t < nb && t < kTileCols) t <<= 1;
+  while (t < nb && t < cols) t <<= 1;
   return t;
 }
 

@@ -335,9 +335,12 @@ __global__ void k_tile_tgt(int32_t nc, int32_t ng, int TC, const int32_t* order,
 void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   const int L = P.L;
   const int T = 256;
-  const int tb = tile_batch(nbatch);
+  const int cols = m2l_tile_cols(P.m2l_variant);
+  const int tb = tile_batch(nbatch, cols);
   P.TB = tb;
-  P.TC = kTileCols / tb;
+  P.TC = cols / tb;
+  P.tiles_variant = P.m2l_variant;
+  P.tiles_class_bits = P.class_bits;
   P.ncg = ceil_div(nbatch, tb);
   const int TC = P.TC;
   // pass 1: ordering, bitmaps, step counts per target group

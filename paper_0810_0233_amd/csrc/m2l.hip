@@ -231,12 +231,143 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && P <= 6) ? 2 : 1) k_m2l
   }
 }
 
+// Variant with independent wavefronts: one tile of 16 columns per wavefront,
+// no block synchronisation.  Each lane keeps the derivative-tensor index of
+// its operator entries (row 16 mb + l%16, column 4 ks + l/16) in registers, so
+// every MFMA A operand is a single LDS gather from the step's 455-entry tensor.
+// Used for orders up to 6 (the index registers grow as p^6).
+template <typename T, int P>
+__global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__ tiles, int64_t ntiles,
+                                                  const int32_t* __restrict__ tile_tgt,
+                                                  const int32_t* __restrict__ step_delta,
+                                                  const int32_t* __restrict__ step_src, const T* __restrict__ Dtab,
+                                                  const T* __restrict__ Q, T* __restrict__ V, LevelOffsets lo,
+                                                  int nb, int TB, int TC) {
+  constexpr int NP = nact(P), NS = nstride(P), MB = (NP + 15) / 16, KS = NS / 4, ND = ncoef(2 * P);
+  constexpr int QST = 65;
+  constexpr int NQ = 16 * NS;
+  constexpr int DR = (ND + 63) / 64, QR = (NQ + 63) / 64;
+  constexpr int NI = MB * KS;
+  __shared__ T sD[4][ND + 1];
+  __shared__ T sQ[4][KS * QST];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  const int64_t blk = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  const int64_t tile = blk * 4 + w;
+  // operator index of (ks, mb, lane), read back as 64 consecutive u16 per wave
+  __shared__ uint16_t sIdx[NI * 64];
+  for (int e = threadIdx.x; e < NI * 64; e += 256) {
+    const int l = e & 63, i = e >> 6;
+    const int ks = i / MB, mb = i % MB;
+    sIdx[e] = (uint16_t)op_index<P>(16 * mb + (l & 15), 4 * ks + (l >> 4));
+  }
+  __syncthreads();
+  if (tile >= ntiles) return;
+  const M2LTile tl = tiles[tile];
+  const T* Ql = Q + lo.qoff[tl.level];
+  using AccT = typename Acc<T>::type;
+  AccT acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++) acc[mb] = AccT{0, 0, 0, 0};
+  T rD[DR], rQ[QR];
+  auto fetch = [&](int s) {
+    const int64_t st = (int64_t)tl.step0 + s;
+    const T* drow = Dtab + (int64_t)step_delta[st] * ND;
+#pragma unroll
+    for (int r = 0; r < DR; r++) {
+      const int e = lane + 64 * r;
+      rD[r] = (e < ND) ? drow[e] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < QR; r++) {
+      const int e = lane + 64 * r;
+      T v = (T)0;
+      if (e < NQ) {
+        const int j = e / NS, k = e % NS;
+        const int tc = j / TB, b = tl.b0 + (j % TB);
+        if (tc < TC && b < nb) {
+          const int src = step_src[st * TC + tc];
+          if (src >= 0) v = Ql[((int64_t)src * nb + b) * NS + k];
+        }
+      }
+      rQ[r] = v;
+    }
+  };
+  if (tl.nsteps > 0) fetch(0);
+  for (int s = 0; s < tl.nsteps; s++) {
+#pragma unroll
+    for (int r = 0; r < DR; r++) {
+      const int e = lane + 64 * r;
+      if (e < ND) sD[w][e] = rD[r];
+    }
+    if (lane == 0) sD[w][ND] = (T)0;
+#pragma unroll
+    for (int r = 0; r < QR; r++) {
+      const int e = lane + 64 * r;
+      if (e < NQ) {
+        const int j = e / NS, k = e % NS;
+        sQ[w][(k >> 2) * QST + j + 16 * (k & 3)] = rQ[r];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (s + 1 < tl.nsteps) fetch(s + 1);
+#pragma unroll 3
+    for (int ks = 0; ks < KS; ks++) {
+      const T bq = sQ[w][ks * QST + lane];
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++) {
+        const int ix = sIdx[(ks * MB + mb) * 64 + lane];
+        acc[mb] = mfma16x16x4(sD[w][ix], bq, acc[mb]);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const int col = lane & 15, kq = lane >> 4;
+  const int tc = col / TB, b = tl.b0 + (col % TB);
+  if (tc < TC && b < nb) {
+    const int tgt = tile_tgt[tl.tgt0 + tc];
+    if (tgt >= 0) {
+      T* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + b) * NS;
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int m = 16 * mb + acc_row<T>(kq, r);
+          if (m < NS) {
+            T v = (T)0;
+            if (m < NP) {
+              const int f = m + 1;
+              const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
+              v = (deg & 1) ? -acc[mb][r] : acc[mb][r];
+            }
+            out[m] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int PP>
 static void m2l_impl(Plan& P, int nb, hipStream_t st) {
   LevelOffsets lo{};
   for (int l = 0; l <= P.L; l++) lo.qoff[l] = P.lev[l]->qoff;
   const T* D = std::is_same<T, double>::value ? (const T*)P.Dd.p : (const T*)P.Df.p;
   if (P.ntiles == 0) return;
+  if (P.tiles_variant == kM2LWave) {
+    if constexpr (PP <= 6) {
+      k_m2l_wave<T, PP><<<ceil_div(P.ntiles, 4), 256, 0, st>>>(
+          P.tiles.as<M2LTile>(), P.ntiles, P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),
+          P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
+      CCFMM_HIP(hipGetLastError());
+      return;
+    }
+    fail(CCFMM_EINVAL, "wavefront M2L variant supports orders up to 6");
+  }
   k_m2l<T, PP><<<(unsigned)P.ntiles, 256, 0, st>>>(P.tiles.as<M2LTile>(), P.ntiles, P.tile_tgt.as<int32_t>(),
                                                    P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), D,
                                                    P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);

@@ -83,6 +83,8 @@ struct Plan {
   std::vector<std::array<double, 6>> dtab_keys;
   // M2L tiles
   int TB = 64, TC = 1, ncg = 1;  // configs per tile, targets per tile, config groups
+  int m2l_variant = kM2LBlock;    // kernel used by run_m2l
+  int tiles_variant = -1, tiles_class_bits = -1;  // what the current tiles were built for
   DevBuf tiles, tile_tgt, step_delta, step_src, bitmap, gcount;
   int64_t ntiles = 0, nsteps = 0;
   // P2P chunks (built on the device; their count stays in device memory)

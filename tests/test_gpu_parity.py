@@ -193,3 +193,37 @@ def test_direct_targets_matches_oracle(ref):
                                 torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     np.testing.assert_allclose(d_H.cpu().numpy(), ref.bruteforce_targets(pos, m, idx), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("precision", [ccfmm.PREC_FP64, ccfmm.PREC_MIXED])
+def test_m2l_variants_and_autotune_agree(ref, precision):
+    """Both M2L kernels, every target grouping and the autotuner's pick give the
+    same fields; FP64 matches the oracle."""
+    import torch
+
+    pos, box = inputs.ferrofluid(12000, 21)
+    m = inputs.random_moments(12000, 22)
+    base = None
+    for variant in (0, 1):
+        for cb in (0, 3, 6):
+            H = plan_for(pos, 6, 0.5, 0.0, box, precision=precision, m2l_variant=variant,
+                         m2l_class_bits=cb).eval(m)
+            if base is None:
+                base = H
+            else:
+                assert rel_rms(H, base) <= (1e-14 if precision == ccfmm.PREC_FP64 else 1e-6)
+    if precision == ccfmm.PREC_FP64:
+        assert rel_rms(base, ref.fmm(pos, m, 6, 0.5, box=box)) <= FP64_BAR
+    dev = torch.device("cuda:0")
+    d_m = torch.from_numpy(m).to(dev)
+    d_H = torch.empty_like(d_m)
+    st = torch.cuda.current_stream().cuda_stream
+    pl = plan_for(pos, 6, 0.5, 0.0, box, precision=precision)
+    res = pl.autotune(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    assert len(res) == 6 and all(r["m2l_ms"] > 0 for r in res)
+    inf = pl.info()
+    best = min(res, key=lambda r: r["m2l_ms"])
+    assert (inf["m2l_variant"], inf["m2l_class_bits"]) == (best["variant"], best["class_bits"])
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    assert rel_rms(d_H.cpu().numpy(), base) <= (1e-14 if precision == ccfmm.PREC_FP64 else 1e-6)
