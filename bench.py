@@ -1,21 +1,26 @@
 """Benchmark: dipole-field evaluations per second of the Cartesian FMM on one GPU.
 
-Workload (default): ferrofluid of 1,048,576 hard-core dipoles (random
-sequential addition, volume fraction 0.1, seed 2001), unit moments in random
-directions (seed 2002), order p = 6, opening angle 0.5, s = s_o(6) = 26.64
-dipoles per smallest cell, mixed precision (FP32 bulk arithmetic on MFMA/VALU,
-FP64 derivative tensors and final per-dipole sums).
+Default workload: ferrofluid of 1,048,576 hard-core dipoles (random sequential
+addition, volume fraction 0.1, seed 2001), unit moments in random directions
+(seed 2002), order p = 6, opening angle 0.5, s = s_o(6) = 26.64 dipoles per
+smallest cell, mixed precision (FP32 bulk arithmetic on MFMA/VALU, FP64
+derivative tensors and final per-dipole sums).
 
-A step is one pass of the whole method over one configuration with the
-positions and moments already in HBM: tree and lists rebuilt in place for the
-(possibly moved) dipoles, derivative tensors, P2M, M2M, M2L, L2L, L2P and the
-near-field sum.  `value` = dipoles / step time.  The same run also reports the
-evaluation alone (tree reused), the plain FP64 GPU FMM, the error of the mixed
-result against the FP64 GPU FMM (eps_prec) and against the direct sum at
-sampled dipoles (eps_abs), the roofline of the dominant kernel, and the CPU
-oracle timed on a bounded sample of the same recipe.
+`--workload sphere`: 262,144 lattice sites cut as a sphere from an 80^3 cubic
+lattice, 64 magnetisation configurations (random directions plus 0-50% of
+seeded sites aligned along +z), p = 5, theta = 0.5, evaluated together.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--skip-cpu] [--skip-fp64]
+A step is one pass of the whole method over one batch with the positions and
+moments already in HBM: tree and lists rebuilt in place for the (possibly
+moved) dipoles, derivative tensors, P2M, M2M, M2L, L2L, L2P and the near-field
+sum.  `value` = dipoles x configurations / step time.  The same run reports
+the evaluation alone (tree reused, captured graph replayed), the plain FP64
+GPU FMM, the error of the mixed result against the FP64 GPU FMM (eps_prec) and
+against the direct sum at sampled dipoles (eps_abs), the roofline of the
+dominant kernel, and the CPU oracle timed on a bounded sample of the recipe.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere]
+                       [--skip-cpu] [--skip-fp64] [--calib-copy]
 """
 import argparse
 import json
@@ -43,13 +48,34 @@ def rel_rms(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
+def workload(args, inputs):
+    if args.workload == "ferrofluid":
+        n = args.n or (1 << 20)
+        pos, box = inputs.ferrofluid(n, 2001)
+        m = inputs.random_moments(n, 2002)[None]
+        return dict(name="ferrofluid_rsa_%d" % n, pos=pos, box=box, m=m, order=args.order or 6,
+                    theta=args.theta, sample=lambda k: inputs.ferrofluid(k, 2001)[0],
+                    sample_m=lambda k: inputs.random_moments(k, 2002), sample_n=1 << 17)
+    if args.workload == "sphere":
+        n = args.n or (1 << 18)
+        nb = args.batch or 64
+        pos, box = inputs.sphere_cut(n, 80)
+        m = inputs.aligned_moments(n, nb, 3000)
+        return dict(name="sphere_%d_of_80cube_x%d" % (n, nb), pos=pos, box=box, m=m, order=args.order or 5,
+                    theta=args.theta, sample=lambda k: inputs.sphere_cut(k, 80)[0],
+                    sample_m=lambda k: inputs.aligned_moments(k, 1, 3000)[0], sample_n=1 << 16)
+    raise SystemExit("unknown workload " + args.workload)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--order", type=int, default=6)
+    ap.add_argument("--workload", default="ferrofluid")
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
@@ -67,40 +93,40 @@ def main():
     from paper_0810_0233_amd import ccfmm, inputs
 
     dev = torch.device("cuda:0")
-    n = args.n
     t0 = time.time()
-    pos, box = inputs.ferrofluid(n, 2001)
-    m = inputs.random_moments(n, 2002)
-    log("inputs: ferrofluid n=%d side=%.3f (%.1f s)" % (n, box[1][0], time.time() - t0))
+    W = workload(args, inputs)
+    pos, box, m = W["pos"], W["box"], W["m"]
+    nb, n = m.shape[0], m.shape[1]
+    order, theta = W["order"], W["theta"]
+    log("inputs: %s n=%d batch=%d (%.1f s)" % (W["name"], n, nb, time.time() - t0))
     d_pos = torch.from_numpy(pos).to(dev)
-    d_m = torch.from_numpy(m).to(dev)
+    d_m = torch.from_numpy(np.ascontiguousarray(m)).to(dev)
     d_H = torch.empty_like(d_m)
     d_H64 = torch.empty_like(d_m)
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
 
     def make(prec):
-        prm = ccfmm.params(order=args.order, theta=args.theta, leaf_target=0.0, box=box, precision=prec,
-                           max_batch=1)
+        prm = ccfmm.params(order=order, theta=theta, leaf_target=0.0, box=box, precision=prec, max_batch=nb)
         return ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, sh)
 
     def time_steps(plan, out, rebuild, steps, warmup):
         for _ in range(warmup):
             if rebuild:
                 plan.update_positions_device(d_pos.data_ptr(), sh)
-            plan.eval_device(1, d_m.data_ptr(), out.data_ptr(), sh)
+            plan.eval_device(nb, d_m.data_ptr(), out.data_ptr(), sh)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(steps):
             if rebuild:
                 plan.update_positions_device(d_pos.data_ptr(), sh)
-            plan.eval_device(1, d_m.data_ptr(), out.data_ptr(), sh)
+            plan.eval_device(nb, d_m.data_ptr(), out.data_ptr(), sh)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / steps
 
     # ---- mixed precision: the headline path
     plan = make(ccfmm.PREC_MIXED)
-    tune = plan.autotune(1, d_m.data_ptr(), d_H.data_ptr(), sh)
+    tune = plan.autotune(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
     info = plan.info()
     log("m2l autotune: %s -> variant %d class_bits %d" % (
         json.dumps([(t["variant"], t["class_bits"], round(t["m2l_ms"], 3)) for t in tune]),
@@ -112,7 +138,7 @@ def main():
     log("mixed full step: %.3f ms" % (1e3 * t_step))
     t_eval = time_steps(plan, d_H, False, args.steps, args.warmup)
     log("mixed eval only: %.3f ms" % (1e3 * t_eval))
-    passes = [plan.eval_device_timed(1, d_m.data_ptr(), d_H.data_ptr(), sh) for _ in range(3)]
+    passes = [plan.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), sh) for _ in range(3)]
     pt = {k: float(np.median([p[k] for p in passes])) for k in passes[0]}
     log("mixed passes (ms): %s" % json.dumps({k: round(v, 4) for k, v in pt.items()}))
     torch.cuda.synchronize()
@@ -122,10 +148,10 @@ def main():
     # ---- plain FP64 GPU FMM
     if not args.skip_fp64:
         plan64 = make(ccfmm.PREC_FP64)
-        plan64.autotune(1, d_m.data_ptr(), d_H64.data_ptr(), sh)
+        plan64.autotune(nb, d_m.data_ptr(), d_H64.data_ptr(), sh)
         t_step64 = time_steps(plan64, d_H64, True, max(2, args.steps // 2), 1)
         t_eval64 = time_steps(plan64, d_H64, False, max(2, args.steps // 2), 1)
-        passes64 = plan64.eval_device_timed(1, d_m.data_ptr(), d_H64.data_ptr(), sh)
+        passes64 = plan64.eval_device_timed(nb, d_m.data_ptr(), d_H64.data_ptr(), sh)
         torch.cuda.synchronize()
         H64 = d_H64.cpu().numpy().copy()
         out["fp64_full_step_ms"] = 1e3 * t_step64
@@ -136,30 +162,39 @@ def main():
         out["eps_prec"] = rel_rms(H_mixed, H64)
         log("fp64 step %.3f ms eval %.3f ms; eps_prec %.3e" % (1e3 * t_step64, 1e3 * t_eval64, out["eps_prec"]))
         plan64.destroy()
-    # ---- error against the direct sum at sampled dipoles (FP64 on the GPU)
+    # ---- error against the direct sum at sampled dipoles (FP64 on the GPU), configuration 0
     rng = np.random.default_rng(7)
     idx = np.sort(rng.choice(n, size=min(args.samples, n), replace=False)).astype(np.int64)
     d_idx = torch.from_numpy(idx).to(dev)
     d_Hd = torch.empty((idx.size, 3), dtype=torch.float64, device=dev)
-    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m.data_ptr(), idx.size, d_idx.data_ptr(), d_Hd.data_ptr(), sh)
+    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m[0].data_ptr(), idx.size, d_idx.data_ptr(),
+                                d_Hd.data_ptr(), sh)
     torch.cuda.synchronize()
     H_direct = d_Hd.cpu().numpy()
-    out["eps_abs_mixed"] = rel_rms(H_mixed[idx], H_direct)
+    out["eps_abs_mixed"] = rel_rms(H_mixed[0][idx], H_direct)
     if not args.skip_fp64:
-        out["eps_abs_fp64"] = rel_rms(H64[idx], H_direct)
+        out["eps_abs_fp64"] = rel_rms(H64[0][idx], H_direct)
     log("eps_abs mixed %.3e" % out["eps_abs_mixed"])
 
-    # ---- roofline of the dominant kernel (timed with HIP events on the launch stream)
-    m2l_flops = info["m2l_flops_per_config"]
-    p2p_flops = 20.0 * info["n_p2p_pairs"]  # per pair: 3 sub, 3 fma (r^2), 3 fma (m.r), 4 mul, 6 fma (field)
+    # ---- roofline of the dominant kernel (HIP events on the launch stream)
+    m2l_flops = info["m2l_flops_per_config"] * nb
+    pairs = info["n_p2p_pairs"] * nb
+    batched = nb >= 32
+    # per pair and configuration: 20 flop on the VALU form (3 sub, 3 for r^2,
+    # 3 for m.r, 4 mul, 6 FMA); 18 flop of matrix product on the batched form
+    p2p_flops = (18.0 if batched else 20.0) * pairs
     if pt["m2l"] >= pt["p2p_l2p"]:
         ach = m2l_flops / (pt["m2l"] * 1e-3)
-        roof = {"kernel": "k_m2l<float,%d>" % args.order, "bound": "mfma", "achieved": ach / 1e12,
+        roof = {"kernel": "k_m2l<float,%d>" % order, "bound": "mfma", "achieved": ach / 1e12,
                 "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": None}
     else:
         ach = p2p_flops / (pt["p2p_l2p"] * 1e-3)
-        roof = {"kernel": "k_p2p_l2p<float,%d>" % args.order, "bound": "alu", "achieved": ach / 1e12,
-                "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None}
+        if batched:
+            roof = {"kernel": "k_p2p_batched<float>+k_l2p_batched", "bound": "mfma", "achieved": ach / 1e12,
+                    "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": None}
+        else:
+            roof = {"kernel": "k_p2p_l2p<float,%d>" % order, "bound": "alu", "achieved": ach / 1e12,
+                    "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None}
     out["m2l_tflops"] = m2l_flops / (pt["m2l"] * 1e-3) / 1e12
     out["p2p_tflops"] = p2p_flops / (pt["p2p_l2p"] * 1e-3) / 1e12
 
@@ -168,22 +203,21 @@ def main():
     if not args.skip_cpu:
         import oracle
 
-        ns = 1 << 17
-        spos, sbox = inputs.ferrofluid(ns, 2001)
-        sm = inputs.random_moments(ns, 2002)
-        threads = os.cpu_count() or 1
-        threads = min(threads, 16)
+        ns = W["sample_n"]
+        spos = W["sample"](ns)
+        sm = W["sample_m"](ns)
+        threads = min(os.cpu_count() or 1, 16)
         t = time.perf_counter()
-        oracle.fmm(spos, sm, args.order, args.theta, box=sbox, nthreads=threads)
+        oracle.fmm(spos, sm, order, theta, box=None if args.workload != "sphere" else box, nthreads=threads)
         dt = time.perf_counter() - t
         cpu = {"value": ns / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-               "sample": "FP64 recursive CPU FMM (same p, theta, s rule) on the same ferrofluid recipe at "
-                         "n=131072 (seed 2001/2002), %.1f s" % dt}
+               "sample": "FP64 recursive CPU FMM (same p, theta, s rule), one configuration of the same recipe "
+                         "at n=%d, %.1f s" % (ns, dt)}
         log("cpu oracle: %.3e evals/s on %d threads" % (ns / dt, threads))
 
     res = {
         "metric": METRIC,
-        "value": n / t_step,
+        "value": n * nb / t_step,
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -194,11 +228,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "ferrofluid_rsa_%d" % n, "n": n, "order": args.order, "theta": args.theta,
+        "config": {"workload": W["name"], "n": n, "batch": nb, "order": order, "theta": theta,
                    "leaf_target": info["s_used"], "levels": info["levels"], "precision": "mixed",
-                   "batch": 1, "step": "tree+lists+tensors+eval",
+                   "step": "tree+lists+tensors+eval",
                    "m2l_variant": info["m2l_variant"], "m2l_class_bits": info["m2l_class_bits"]},
-        "eval_only_evals_per_s": n / t_eval,
+        "eval_only_evals_per_s": n * nb / t_eval,
         "eval_ms": 1e3 * t_eval,
         "passes_ms": pt,
         "roofline": roof,

@@ -69,6 +69,8 @@ typedef struct {
   int32_t m2l_variant;    /* M2L kernel: 0 = block of 4 wavefronts sharing one operator per
                              step (64-column tiles), 1 = independent wavefronts (16 columns,
                              orders <= 6); ccfmm_plan_autotune can choose */
+  int32_t use_graph;      /* 1: evaluations are captured once into a HIP graph (per batch size
+                             and buffer pair) and replayed; 0: plain stream launches */
 } ccfmm_params;
 
 /* One timed M2L configuration of ccfmm_plan_autotune. */

@@ -27,7 +27,8 @@ class ccfmm_params(C.Structure):
                 ("leaf_rule", C.c_int32), ("precision", C.c_int32), ("selector", C.c_int32),
                 ("err_bound", C.c_double), ("has_box", C.c_int32),
                 ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
-                ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32), ("m2l_variant", C.c_int32)]
+                ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32), ("m2l_variant", C.c_int32),
+                ("use_graph", C.c_int32)]
 
 
 class ccfmm_tune_entry(C.Structure):
@@ -125,7 +126,7 @@ def _check(rc):
 
 
 def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64, selector=0,
-           err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=0):
+           err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=0, use_graph=1):
     p = ccfmm_params()
     _check(lib().ccfmm_params_default(C.byref(p)))
     p.order = int(order)
@@ -143,6 +144,7 @@ def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64
     p.max_batch = int(max_batch)
     p.m2l_class_bits = int(m2l_class_bits)
     p.m2l_variant = int(m2l_variant)
+    p.use_graph = int(use_graph)
     return p
 
 

@@ -184,6 +184,7 @@ static void size_expansions(Plan& P, int nb) {
   P.Q.ensure(es * std::max<int64_t>(1, off));
   P.V.ensure(es * std::max<int64_t>(1, off));
   P.m_sorted.ensure(es * 3 * (size_t)P.n * nb);
+  if (nb >= P.batched_min) P.m_sorted_t.ensure(es * 3 * (size_t)P.n * nb);
   P.qv_batch = nb;
 }
 
@@ -199,7 +200,7 @@ __global__ void k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr, const int
 static void fill_info(Plan& P, hipStream_t st) {
   // list totals, chunk count and error flags come back in one synchronisation
   const int L = P.L;
-  std::vector<int32_t> tot(2 * (L + 1) + 2, 0);
+  std::vector<int32_t> tot(2 * (L + 1) + 3, 0);
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
     CCFMM_HIP(hipMemcpyAsync(&tot[2 * l], D.near_ptr.as<int32_t>() + D.ncells, sizeof(int32_t),
@@ -211,7 +212,10 @@ static void fill_info(Plan& P, hipStream_t st) {
   CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1)], P.chunk_cnt.as<int32_t>() + (nl + 1) + nl, sizeof(int32_t),
                            hipMemcpyDeviceToHost, st));
   CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1) + 1], P.flags.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1) + 2], P.chunk_cnt.as<int32_t>() + 3 * (nl + 1) + nl, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st));
   CCFMM_HIP(hipStreamSynchronize(st));
+  P.nchunks32 = tot[2 * (L + 1) + 2];
   if (tot[2 * (L + 1) + 1]) fail(CCFMM_EHIP, "internal: a cell list exceeded its bound");
   for (int l = 0; l <= L; l++) {
     P.lev[l]->nnear = tot[2 * l];
@@ -282,6 +286,7 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
 
 // Build (or rebuild) everything that depends on the positions.
 static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
+  P.drop_graph();
   double mn[3], mx[3];
   bool bad = false;
   device_bbox(d_pos, P.n, P.scratch, st, mn, mx, bad);
@@ -316,11 +321,50 @@ static void prepare_batch(Plan& P, int nb, hipStream_t st) {
   const int tb = tile_batch(nb, m2l_tile_cols(P.m2l_variant));
   if (tb != P.TB || ceil_div(nb, tb) != P.ncg || P.tiles_variant != P.m2l_variant ||
       P.tiles_class_bits != P.class_bits) {
+    P.drop_graph();
     build_m2l_tiles(P, nb, st);
     P.info.n_m2l_tiles = P.ntiles;
     P.info.n_m2l_steps = P.nsteps;
   }
-  if (P.qv_batch != nb) size_expansions(P, nb);
+  if (P.qv_batch != nb) {
+    P.drop_graph();
+    size_expansions(P, nb);
+  }
+}
+
+static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev);
+
+// One evaluation.  With graphs on (and a capturable stream), the pass sequence
+// is captured once per (nbatch, moments, fields) and replayed; the capture
+// holds kernel launches only.
+static void eval_run(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st) {
+  prepare_batch(P, nb, st);
+  if (!P.use_graph || st == nullptr) {
+    eval_passes(P, nb, d_m, d_H, st, nullptr);
+    return;
+  }
+  if (!P.gexec || P.g_nb != nb || P.g_m != d_m || P.g_H != d_H) {
+    P.drop_graph();
+    CCFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      eval_passes(P, nb, d_m, d_H, st, nullptr);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(st, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    hipGraph_t g = nullptr;
+    CCFMM_HIP(hipStreamEndCapture(st, &g));
+    hipError_t e = hipGraphInstantiate(&P.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) P.gexec = nullptr;
+    CCFMM_HIP(e);
+    P.g_nb = nb;
+    P.g_m = d_m;
+    P.g_H = d_H;
+  }
+  CCFMM_HIP(hipGraphLaunch(P.gexec, st));
 }
 
 static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev) {
@@ -395,6 +439,7 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->max_batch = 1;
   prm->m2l_class_bits = 3;
   prm->m2l_variant = kM2LBlock;
+  prm->use_graph = 1;
   return CCFMM_OK;
 }
 
@@ -416,6 +461,7 @@ static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const 
       P.nbmax = prm->max_batch;
       P.class_bits = prm->m2l_class_bits < 0 ? 3 : std::min(prm->m2l_class_bits, 12);
       P.m2l_variant = (prm->m2l_variant == kM2LWave && prm->order <= 6) ? kM2LWave : kM2LBlock;
+      P.use_graph = prm->use_graph != 0;
       if (own) {
         CCFMM_HIP(hipStreamCreateWithFlags(&P.own_stream, hipStreamNonBlocking));
         st = P.own_stream;
@@ -480,8 +526,7 @@ int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double
     Plan& P = plan->P;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
-    prepare_batch(P, nbatch, st);
-    eval_passes(P, nbatch, d_m, d_H, st, nullptr);
+    eval_run(P, nbatch, d_m, d_H, st);
     return CCFMM_OK;
   });
 }
@@ -525,13 +570,15 @@ int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H) {
     CCFMM_HIP(hipSetDevice(P.device));
     hipStream_t st = P.own_stream;
     const size_t bytes = sizeof(double) * 3 * (size_t)P.n * nbatch;
-    DevBuf dm, dH;
-    dm.ensure(bytes);
-    dH.ensure(bytes);
-    CCFMM_HIP(hipMemcpyAsync(dm.p, m, bytes, hipMemcpyHostToDevice, st));
-    prepare_batch(P, nbatch, st);
-    eval_passes(P, nbatch, dm.as<double>(), dH.as<double>(), st, nullptr);
-    CCFMM_HIP(hipMemcpyAsync(H, dH.p, bytes, hipMemcpyDeviceToHost, st));
+    // plan-owned staging keeps the device addresses stable across calls, so the
+    // captured graph is reused
+    const size_t cap = sizeof(double) * 3 * (size_t)P.n * P.nbmax;
+    if (P.host_m.cap < cap) P.drop_graph();
+    P.host_m.ensure(cap);
+    P.host_H.ensure(cap);
+    CCFMM_HIP(hipMemcpyAsync(P.host_m.p, m, bytes, hipMemcpyHostToDevice, st));
+    eval_run(P, nbatch, P.host_m.as<double>(), P.host_H.as<double>(), st);
+    CCFMM_HIP(hipMemcpyAsync(H, P.host_H.p, bytes, hipMemcpyDeviceToHost, st));
     CCFMM_HIP(hipStreamSynchronize(st));
     return CCFMM_OK;
   });

@@ -204,6 +204,21 @@ __global__ void k_permute_moments(const double* __restrict__ m, const int32_t* _
   o[2 * n + i] = (T)mi[2];
 }
 
+// configuration-major copy [i][a][b] for the batched near field
+template <typename T>
+__global__ void k_permute_moments_t(const double* __restrict__ m, const int32_t* __restrict__ perm, int64_t n,
+                                    int nb, T* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nb) return;
+  const int64_t i = t / nb;
+  const int b = (int)(t % nb);
+  const double* mi = m + ((int64_t)b * n + perm[i]) * 3;
+  T* o = out + i * 3 * nb + b;
+  o[0] = (T)mi[0];
+  o[nb] = (T)mi[1];
+  o[2 * nb] = (T)mi[2];
+}
+
 // ------------------------------------------------------------ P2M
 // One wavefront per (occupied smallest cell, configuration).  Eq.
 // (multipolemoments) in scaled units: Qt_n = sum_i sum_{a: n_a>0} m_ia yt^(n-e_a)/(n-e_a)!.
@@ -380,6 +395,11 @@ static void p2m_impl(Plan& P, int nb, const double* d_m, hipStream_t st) {
   dim3 g1(ceil_div(P.n, 256), nb);
   k_permute_moments<T><<<g1, 256, 0, st>>>(d_m, P.perm.as<int32_t>(), P.n, nb, ms);
   CCFMM_HIP(hipGetLastError());
+  if (nb >= P.batched_min) {
+    k_permute_moments_t<T><<<ceil_div(P.n * nb, 256), 256, 0, st>>>(d_m, P.perm.as<int32_t>(), P.n, nb,
+                                                                     P.m_sorted_t.as<T>());
+    CCFMM_HIP(hipGetLastError());
+  }
   const int nl = P.lev[P.L]->ncells;
   const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
   const int64_t items = (int64_t)nl * nb;

@@ -452,16 +452,49 @@ __global__ void k_chunk_fill(int32_t nl, const int32_t* lstart, const int32_t* l
   }
 }
 
+// chunks of at most 32 dipoles (batched near field on the matrix cores)
+__global__ void k_chunk_count32(int32_t nl, const int32_t* lcount, int32_t* cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nl) cnt[i] = (lcount[i] + 31) >> 5;
+}
+
+__global__ void k_chunk_fill32(int32_t nl, const int32_t* lstart, const int32_t* lcount, const int32_t* off,
+                               P2PChunk* ch, int32_t* dleaf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  for (int k = 0, o = off[i]; k < lcount[i]; k += 32, o++) {
+    P2PChunk c;
+    c.leaf = i;
+    c.first = lstart[i] + k;
+    c.count = min(32, lcount[i] - k);
+    c.pad = 0;
+    ch[o] = c;
+  }
+  for (int k = 0; k < lcount[i]; k++) dleaf[lstart[i] + k] = i;
+}
+
 void build_p2p_chunks(Plan& P, hipStream_t st) {
   const int nl = P.lev[P.L]->ncells;
   P.nchunks_cap = (int64_t)nl + P.n / 64 + 1;
-  int32_t* cnt = reinterpret_cast<int32_t*>(P.chunk_cnt.ensure(sizeof(int32_t) * 2 * (nl + 1)));
+  // counts | offsets (64-chunks) | counts | offsets (32-chunks)
+  int32_t* cnt = reinterpret_cast<int32_t*>(P.chunk_cnt.ensure(sizeof(int32_t) * 4 * (nl + 1)));
   int32_t* off = cnt + nl + 1;
+  int32_t* cnt32 = off + nl + 1;
+  int32_t* off32 = cnt32 + nl + 1;
   k_chunk_count<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lcount.as<int32_t>(), cnt);
   CCFMM_HIP(hipGetLastError());
   scan_exclusive(cnt, off, nl, P.scratch, st);  // off[nl] = number of chunks
   P2PChunk* ch = reinterpret_cast<P2PChunk*>(P.chunks.ensure(sizeof(P2PChunk) * P.nchunks_cap));
   k_chunk_fill<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), off, ch);
+  CCFMM_HIP(hipGetLastError());
+  k_chunk_count32<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lcount.as<int32_t>(), cnt32);
+  CCFMM_HIP(hipGetLastError());
+  scan_exclusive(cnt32, off32, nl, P.scratch, st);
+  P2PChunk* ch32 =
+      reinterpret_cast<P2PChunk*>(P.chunks32.ensure(sizeof(P2PChunk) * ((int64_t)nl + P.n / 32 + 1)));
+  int32_t* dleaf = reinterpret_cast<int32_t*>(P.dleaf.ensure(sizeof(int32_t) * P.n));
+  k_chunk_fill32<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), off32, ch32,
+                                                    dleaf);
   CCFMM_HIP(hipGetLastError());
 }
 

@@ -9,6 +9,9 @@
 // split the sources, and their partial fields are combined with cross-lane
 // butterflies at the end.  Sources are staged 64 at a time in LDS, shifted by
 // the integer offset of their cell so all coordinates stay cell-relative.
+#include <type_traits>
+
+#include "mfma.hpp"
 #include "plan.hpp"
 
 namespace ccfmm {
@@ -149,8 +152,204 @@ __global__ void __launch_bounds__(64 * kP2PWaves) k_p2p_l2p(P2PArgs a, const T* 
   H[o + 2] = s3 * (hz - (double)ez);
 }
 
+// ------------------------------------------------------------ batched form
+// Smooth field for many configurations: one thread per (dipole, configuration),
+// written (FP64, caller order) before the batched near field adds to it.
+template <typename T, int P>
+__global__ void k_l2p_batched(int64_t n, int nb, const int32_t* __restrict__ dleaf, const int32_t* __restrict__ perm,
+                              const T* __restrict__ y, const T* __restrict__ V, int64_t voff, double inv_s3,
+                              double* __restrict__ H) {
+  constexpr int NS = nstride(P);
+  constexpr int NM = ncoef(P - 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nb) return;
+  const int64_t i = t / nb;
+  const int b = (int)(t % nb);
+  const T yx = y[i], yy = y[n + i], yz = y[2 * n + i];
+  const T* v = V + voff + ((int64_t)dleaf[i] * nb + b) * NS;
+  T px[P], py[P], pz[P];
+  px[0] = py[0] = pz[0] = (T)1;
+#pragma unroll
+  for (int j = 1; j < P; j++) {
+    const T inv = (T)(1.0 / j);
+    px[j] = px[j - 1] * yx * inv;
+    py[j] = py[j - 1] * yy * inv;
+    pz[j] = pz[j - 1] * yz * inv;
+  }
+  T ex = (T)0, ey = (T)0, ez = (T)0;
+#pragma unroll
+  for (int k = 0; k < NM; k++) {
+    const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
+    const T mono = px[kx] * py[ky] * pz[kz];
+    ex += v[midx(kx + 1, ky, kz) - 1] * mono;
+    ey += v[midx(kx, ky + 1, kz) - 1] * mono;
+    ez += v[midx(kx, ky, kz + 1) - 1] * mono;
+  }
+  const int64_t o = ((int64_t)b * n + perm[i]) * 3;
+  H[o] = -inv_s3 * (double)ex;
+  H[o + 1] = -inv_s3 * (double)ey;
+  H[o + 2] = -inv_s3 * (double)ez;
+}
+
+// Near field for many configurations on the matrix cores.  For a chunk of
+// <= 32 target dipoles and a batch of source dipoles the field is a product
+//   H[(t, a)][b] += sum_{(s, c)} K_ts[a][c] m_s[c][b],
+//   K_ts = (3 r r^T / r^2 - I) / r^3,  r = y_t - y_s  (zero for r = 0),
+// with 96 rows (32 targets x 3), 48 inner entries (16 sources x 3) and 64
+// configuration columns per block (16 per wavefront).  The pair geometry is
+// computed once per block and shared by every configuration.  FP32 partial
+// products of one source cell are added into FP64 accumulators.
+constexpr int kBT = 32;  // targets per chunk
+constexpr int kBS = 16;  // sources per step
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* __restrict__ chunks, int64_t nchunks,
+                                                     const T* __restrict__ y, const T* __restrict__ mt,
+                                                     double* __restrict__ H) {
+  constexpr int MB = 3 * kBT / 16;  // 6 row blocks
+  constexpr int KS = 3 * kBS / 4;   // 12 k steps
+  __shared__ T sA[MB * KS * 64];
+  __shared__ T sB[4 * KS * 64];
+  __shared__ T st[kBT][3];
+  __shared__ T ss[kBS][3];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int64_t item = blockIdx.x;
+  if (item >= nchunks) return;
+  const P2PChunk ch = chunks[item];
+  const int nb = a.nb;
+  const int cfg0 = blockIdx.y * 64;
+  const int64_t n = a.n;
+  if (tid < kBT) {
+    const bool ok = tid < ch.count;
+    const int64_t i = ch.first + (ok ? tid : 0);
+    st[tid][0] = y[i];
+    st[tid][1] = y[n + i];
+    st[tid][2] = y[2 * n + i];
+  }
+  using AccT = typename Acc<T>::type;
+  AccT acc[MB];
+  double acc64[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++) {
+    acc[mb] = AccT{0, 0, 0, 0};
+    for (int r = 0; r < 4; r++) acc64[mb][r] = 0.0;
+  }
+  const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
+  for (int e = a.near_ptr[ch.leaf]; e < a.near_ptr[ch.leaf + 1]; e++) {
+    const int S = a.near_idx[e];
+    const T ox = (T)((a.coord[3 * S] - cx) * a.g[0]);
+    const T oy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
+    const T oz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
+    const int s0 = a.lstart[S], sn = a.lcount[S];
+    for (int base = 0; base < sn; base += kBS) {
+      const int ns = min(kBS, sn - base);
+      __syncthreads();  // previous step's operands fully consumed
+      if (tid < kBS) {
+        const int64_t j = s0 + base + (tid < ns ? tid : 0);
+        ss[tid][0] = y[j] + ox;
+        ss[tid][1] = y[n + j] + oy;
+        ss[tid][2] = y[2 * n + j] + oz;
+      }
+      // B: rows (source s, component c), columns configurations
+#pragma unroll
+      for (int r = 0; r < (3 * kBS * 64) / 256; r++) {
+        const int q = tid + 256 * r;
+        const int row = q >> 6, col = q & 63;
+        const int s = row / 3, c = row % 3, b = cfg0 + col;
+        T v = (T)0;
+        if (s < ns && b < nb) v = mt[((int64_t)(s0 + base + s) * 3 + c) * nb + b];
+        sB[((col >> 4) * KS + (row >> 2)) * 64 + (col & 15) + 16 * (row & 3)] = v;
+      }
+      __syncthreads();
+      // A: the 3x3 pair kernels of kBT x kBS pairs, two pairs per thread
+#pragma unroll
+      for (int r = 0; r < (kBT * kBS) / 256; r++) {
+        const int q = tid + 256 * r;
+        const int t = q / kBS, s = q % kBS;
+        const T rx = st[t][0] - ss[s][0], ry = st[t][1] - ss[s][1], rz = st[t][2] - ss[s][2];
+        const T r2 = rx * rx + ry * ry + rz * rz;
+        const bool ok = t < ch.count && s < ns && r2 > (T)0;
+        const T inv = ok ? rsqrt_t<T>(r2) : (T)0;
+        const T inv3 = inv * inv * inv;
+        const T c5 = (T)3 * inv3 * inv * inv;
+        const T rv[3] = {rx, ry, rz};
+#pragma unroll
+        for (int aa = 0; aa < 3; aa++)
+#pragma unroll
+          for (int cc = 0; cc < 3; cc++) {
+            const T kv = c5 * rv[aa] * rv[cc] - (aa == cc ? inv3 : (T)0);
+            const int m = 3 * t + aa, k = 3 * s + cc;
+            sA[((m >> 4) * KS + (k >> 2)) * 64 + (m & 15) + 16 * (k & 3)] = kv;
+          }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) {
+        const T bq = sB[(w * KS + ks) * 64 + lane];
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++) acc[mb] = mfma16x16x4(sA[(mb * KS + ks) * 64 + lane], bq, acc[mb]);
+      }
+    }
+    // fold this source cell's partial products into FP64
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        acc64[mb][r] += (double)acc[mb][r];
+        acc[mb][r] = (T)0;
+      }
+  }
+  const int col = lane & 15, kq = lane >> 4;
+  const int b = cfg0 + 16 * w + col;
+  if (b >= nb) return;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int m = 16 * mb + acc_row<T>(kq, r);
+      const int t = m / 3, aa = m % 3;
+      if (t < ch.count) {
+        const int64_t o = ((int64_t)b * n + a.perm[ch.first + t]) * 3 + aa;
+        H[o] += a.inv_s3 * acc64[mb][r];
+      }
+    }
+}
+
+template <typename T, int PP>
+static void p2p_batched_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
+  LevelData& D = *P.lev[P.L];
+  const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
+  const double s = P.geo.lev[P.L].s;
+  const double inv_s3 = 1.0 / (s * s * s);
+  k_l2p_batched<T, PP><<<ceil_div(P.n * nb, 256), 256, 0, st>>>(P.n, nb, P.dleaf.as<int32_t>(), P.perm.as<int32_t>(),
+                                                                y, P.V.as<T>(), D.qoff, inv_s3, d_H);
+  CCFMM_HIP(hipGetLastError());
+  P2PArgs a;
+  a.chunks = nullptr;
+  a.nchunks = 0;
+  a.near_ptr = D.near_ptr.as<int32_t>();
+  a.near_idx = D.near_idx.as<int32_t>();
+  a.coord = D.coord.as<int32_t>();
+  a.lstart = P.lstart.as<int32_t>();
+  a.lcount = P.lcount.as<int32_t>();
+  a.perm = P.perm.as<int32_t>();
+  a.n = P.n;
+  a.nb = nb;
+  for (int q = 0; q < 3; q++) a.g[q] = P.geo.lev[P.L].g[q];
+  a.inv_s3 = inv_s3;
+  a.voff = D.qoff;
+  if (P.nchunks32 == 0) return;
+  dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
+  k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(), d_H);
+  CCFMM_HIP(hipGetLastError());
+}
+
 template <typename T, int PP>
 static void p2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
+  if (nb >= P.batched_min) {
+    p2p_batched_impl<T, PP>(P, nb, d_H, st);
+    return;
+  }
   LevelData& D = *P.lev[P.L];
   P2PArgs a;
   a.chunks = P.chunks.as<P2PChunk>();

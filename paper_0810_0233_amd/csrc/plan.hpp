@@ -96,11 +96,29 @@ struct Plan {
   int64_t qv_elems = 0;
   int qv_batch = 0;  // nbatch the Q/V buffers are laid out for
   DevBuf m_sorted;   // moments in sorted order [b][3][n] (FP64 or FP32)
+  // batched near field (many configurations): moments [n][3][b] (configuration
+  // fastest), target chunks of <= 32 dipoles, smallest cell of each dipole
+  DevBuf m_sorted_t;
+  DevBuf chunks32, dleaf;
+  int64_t nchunks32 = 0;
+  int batched_min = 32;  // nbatch from which the near field runs on the matrix cores
   DevBuf scratch;    // scan/sort temporaries
   DevBuf scratch2;
   DevBuf flags;      // device error flags
+  // captured evaluation graph, valid for (g_nb, g_m, g_H) until the next rebuild
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  int g_nb = 0;
+  const void* g_m = nullptr;
+  void* g_H = nullptr;
+  DevBuf host_m, host_H;  // staging of the host-pointer evaluation (stable addresses)
   ccfmm_info info{};
   bool built = false;
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+  ~Plan() { drop_graph(); }
 };
 
 // build steps (tree.hip, lists.hip, expansions.hip)

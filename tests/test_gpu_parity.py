@@ -227,3 +227,50 @@ def test_m2l_variants_and_autotune_agree(ref, precision):
     pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
     torch.cuda.synchronize()
     assert rel_rms(d_H.cpu().numpy(), base) <= (1e-14 if precision == ccfmm.PREC_FP64 else 1e-6)
+
+
+@pytest.mark.parametrize("precision", [ccfmm.PREC_FP64, ccfmm.PREC_MIXED])
+def test_batched_matrix_core_near_field(ref, precision):
+    """40 configurations (the matrix-core near field) equal one-at-a-time
+    evaluations, and the FP64 form matches the oracle per configuration."""
+    pos, box = inputs.sphere_cut(4000, 20)
+    nb = 40
+    mb = inputs.aligned_moments(4000, nb, 3000)
+    pl = plan_for(pos, 5, 0.5, 0.0, box, precision=precision, max_batch=nb)
+    Hb = pl.eval(mb)
+    single = plan_for(pos, 5, 0.5, 0.0, box, precision=precision, max_batch=1)
+    for b in (0, 7, 39):
+        Hs = single.eval(mb[b:b + 1])[0]
+        e = rel_rms(Hb[b], Hs)
+        print("batched vs single b=%d: %.3e" % (b, e), flush=True)
+        assert e <= (1e-13 if precision == ccfmm.PREC_FP64 else 2e-6)
+        if precision == ccfmm.PREC_FP64 and b != 7:
+            assert rel_rms(Hb[b], ref.fmm(pos, mb[b], 5, 0.5, box=box)) <= FP64_BAR
+
+
+def test_graph_replays_match_eager():
+    """The captured evaluation, replayed with new moments in the same buffers and
+    eager work in between, equals the uncaptured evaluation every time."""
+    import torch
+
+    pos, box = inputs.ferrofluid(8000, 31)
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    d_pos = torch.from_numpy(pos).to(dev)
+    nb = 3
+    d_m = torch.empty((nb, 8000, 3), dtype=torch.float64, device=dev)
+    d_H = torch.empty_like(d_m)
+    d_Hr = torch.empty_like(d_m)
+    graphed = ccfmm.Plan.create_device(8000, d_pos.data_ptr(), ccfmm.params(order=5, theta=0.5, box=box,
+                                                                              max_batch=nb, use_graph=1), st)
+    eager = ccfmm.Plan.create_device(8000, d_pos.data_ptr(), ccfmm.params(order=5, theta=0.5, box=box,
+                                                                            max_batch=nb, use_graph=0), st)
+    for rep in range(4):
+        m = np.stack([inputs.random_moments(8000, 100 * rep + b) for b in range(nb)])
+        d_m.copy_(torch.from_numpy(m))
+        junk = torch.randn(1 << 20, device=dev).sum()  # unrelated eager work between replays
+        graphed.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
+        eager.eval_device(nb, d_m.data_ptr(), d_Hr.data_ptr(), st)
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        np.testing.assert_array_equal(d_H.cpu().numpy(), d_Hr.cpu().numpy())
