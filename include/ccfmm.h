@@ -154,6 +154,68 @@ int ccfmm_energy(int64_t n, int32_t nbatch, const double* m, const double* H, do
 /* NULL-safe. */
 void ccfmm_plan_destroy(ccfmm_plan plan);
 
+/* ---------------------------------------------------------------------------
+ * Per-smallest-cell parameters and the learned selector.
+ *
+ * Extends the paper's parameter choice (Sec. 4: one (p_m, alpha_m) for the
+ * whole system, chosen from timings and the estimate [alpha/(2-alpha)]^p) to a
+ * choice per smallest cell.  The levels above the smallest cells keep the
+ * plan's (order, theta).  A smallest cell with its own theta_l re-splits its
+ * own candidates (children of the cells near its parent) into near and far
+ * cells by 2r/d > theta_l; its own p_l <= order truncates its local expansion
+ * before L2P.  Cells are in "compact leaf order": occupied smallest cells by
+ * increasing bisection key (ccfmm_plan_leaf_ids gives each dipole's cell).
+ * ------------------------------------------------------------------------- */
+#define CCFMM_MLP_IN 8       /* features per cell */
+#define CCFMM_MLP_HIDDEN 64  /* two hidden layers of this width, ReLU */
+#define CCFMM_MLP_OUT 25     /* predicted log10 error for p in {2..6} x theta in {.3,.4,.5,.6,.7},
+                                output index (p-2)*5 + theta index */
+/* number of packed FP32 parameters: W1[64][8] b1[64] W2[64][64] b2[64] W3[25][64] b3[25] */
+#define CCFMM_MLP_PARAMS (64 * 8 + 64 + 64 * 64 + 64 + 25 * 64 + 25)
+
+typedef struct {
+  int32_t n_leaves;
+  int32_t hist[CCFMM_MLP_OUT];  /* cells per chosen (p, theta), index as the network output */
+  double judge_err;             /* relative RMS of the learned vs the fixed-parameter field */
+  int32_t fallback;             /* 1: learned choice rejected, plan back on fixed parameters */
+} ccfmm_select_info;
+
+/* Set (d_p, d_theta: device arrays of n_leaves int32 / FP64, compact leaf
+ * order) or clear (both NULL) the per-cell parameters; rebuilds the lists.
+ * EINVAL if a p is outside 1..order or a theta outside (0,1). */
+int ccfmm_plan_set_leaf_params(ccfmm_plan plan, const int32_t* d_p, const double* d_theta, void* stream);
+/* Current per-cell parameters into host arrays of n_leaves (p, theta); with no
+ * per-cell parameters set, every cell reports (order, theta).  *n_leaves may be
+ * queried with NULL arrays. */
+int ccfmm_plan_get_leaf_params(ccfmm_plan plan, int32_t* h_p, double* h_theta, int32_t* n_leaves);
+/* Compact leaf index of every dipole, input order: d_out [n] int32. */
+int ccfmm_plan_leaf_ids(ccfmm_plan plan, int32_t* d_out, void* stream);
+/* The selector's 8 features of every cell from device moments [nbatch][n][3]
+ * (on the plan's fixed-parameter lists): d_feat [n_leaves][8] FP32. */
+int ccfmm_plan_leaf_features(ccfmm_plan plan, int32_t nbatch, const double* d_m, float* d_feat, void* stream);
+/* Per cell: sum over its dipoles and configurations of |H - Href|^2 (d_num)
+ * and |Href|^2 (d_den), FP64 [n_leaves]; H, Href are [nbatch][n][3]. */
+int ccfmm_plan_leaf_errors(ccfmm_plan plan, int32_t nbatch, const double* d_H, const double* d_Href,
+                           double* d_num, double* d_den, void* stream);
+/* Selector network (FP32, device arrays): forward pass of rows x [8] -> [25]. */
+int ccfmm_mlp_forward(const float* d_params, int64_t rows, const float* d_x, float* d_y, void* stream);
+/* Loss 0.5 sum mask (y - t)^2 / max(1, sum mask) and its gradient (d_grad
+ * [CCFMM_MLP_PARAMS]); d_loss (1 float) may be NULL.  Deterministic. */
+int ccfmm_mlp_loss_grad(const float* d_params, int64_t rows, const float* d_x, const float* d_t,
+                        const float* d_mask, float* d_grad, float* d_loss, void* stream);
+/* One Adam step (beta 0.9 / 0.999, bias-corrected; step counts from 1). */
+int ccfmm_mlp_adam(float* d_params, const float* d_grad, float* d_m1, float* d_m2, int32_t step, float lr,
+                   void* stream);
+/* Learned selection: features of the current moments -> network -> for every
+ * cell the cheapest (p, theta) whose predicted log10 error is at most
+ * log10(err_bound) - margin (cost = own dipoles x near source dipoles +
+ * cost_far x far cells), then set as the plan's per-cell parameters.  With
+ * judge != 0 the learned field of these moments is compared with the
+ * fixed-parameter field; above err_bound the plan returns to fixed parameters
+ * and the call returns CCFMM_W_FALLBACK.  Synchronises the stream. */
+int ccfmm_plan_select(ccfmm_plan plan, const float* d_params, double err_bound, double margin, double cost_far,
+                      int32_t nbatch, const double* d_m, int32_t judge, void* stream, ccfmm_select_info* out);
+
 /* Direct O(N^2) FP64 field on the GPU at nt sampled targets (error reference at
  * scale): d_pos [n][3], d_m [n][3], d_idx [nt] int64, d_H [nt][3]; stream-ordered. */
 int ccfmm_direct_targets_device(int64_t n, const double* d_pos, const double* d_m, int64_t nt,

@@ -463,6 +463,10 @@ typedef struct {
   int64_t m2l_pairs[CCREF_LMAX + 1];
   int64_t p2p_leaf_pairs;
   int64_t nleaves;
+  /* optional per-smallest-cell parameters, given per dipole (all dipoles of a
+   * smallest cell carry the same values): local order and opening angle */
+  const int32_t* leaf_p;
+  const double* leaf_theta;
 } tree;
 
 /* Eq.(so): optimal dipoles per smallest cell. */
@@ -668,7 +672,13 @@ static int near_pair(const tree* T, const cell* A, const cell* C) {
   double R = g[0] * g[0];
   R = R + g[1] * g[1];
   R = R + g[2] * g[2];
-  int far = (T->theta2 * D >= R);
+  double th2 = T->theta2;
+  if (T->leaf_theta && C->is_leaf && C->count > 0) {
+    /* a smallest cell re-splits its candidates with its own opening angle */
+    double th = T->leaf_theta[C->idx[0]];
+    th2 = th * th;
+  }
+  int far = (th2 * D >= R);
   return !far;
 }
 
@@ -770,7 +780,20 @@ static double update_field(tree* T, cell* c) {
       const double* x = &T->pos[3 * d];
       double y[3] = {x[0] - c->center[0], x[1] - c->center[1], x[2] - c->center[2]};
       double h[3];
-      l2p(T->p, c->V, y, h);
+      if (T->leaf_p) {
+        /* the smallest cell's local expansion truncated at its own order */
+        int pl = T->leaf_p[c->idx[0]];
+        if (pl > T->p) pl = T->p;
+        int side = T->p + 1;
+        double* Vt = (double*)calloc((size_t)side * side * side, sizeof(double));
+        for (int nx = 0; nx <= pl; nx++)
+          for (int ny = 0; nx + ny <= pl; ny++)
+            for (int nz = 0; nx + ny + nz <= pl; nz++) Vt[cidx(nx, ny, nz, T->p)] = c->V[cidx(nx, ny, nz, T->p)];
+        l2p(T->p, Vt, y, h);
+        free(Vt);
+      } else {
+        l2p(T->p, c->V, y, h);
+      }
       for (int64_t u = 0; u < c->near.n; u++) {
         cell* A = c->near.v[u];
         for (int64_t s = 0; s < A->count; s++) {
@@ -853,9 +876,20 @@ int ccref_tree_shape(int64_t n, const double* pos, const ccref_params* prm, ccre
 
 int ccref_fmm(int64_t n, const double* pos, const double* m, const ccref_params* prm, double* H,
               ccref_stats* stats) {
+  return ccref_fmm_leaf(n, pos, m, prm, NULL, NULL, H, stats);
+}
+
+int ccref_fmm_leaf(int64_t n, const double* pos, const double* m, const ccref_params* prm, const int32_t* leaf_p,
+                   const double* leaf_theta, double* H, ccref_stats* stats) {
   if (check_params(n, pos, prm)) return -1;
   for (int64_t i = 0; i < 3 * n; i++)
     if (!isfinite(m[i])) return -1;
+  if (leaf_p)
+    for (int64_t i = 0; i < n; i++)
+      if (leaf_p[i] < 1 || leaf_p[i] > prm->order) return -1;
+  if (leaf_theta)
+    for (int64_t i = 0; i < n; i++)
+      if (!(leaf_theta[i] > 0.0 && leaf_theta[i] < 1.0)) return -1;
   build_ftable();
   set_threads(prm->nthreads);
   tree T;
@@ -863,6 +897,8 @@ int ccref_fmm(int64_t n, const double* pos, const double* m, const ccref_params*
   if (setup_tree(&T, n, pos, prm, &s)) return -1;
   T.m = m;
   T.H = H;
+  T.leaf_p = leaf_p;
+  T.leaf_theta = leaf_theta;
 
   double t0 = now_s();
   int64_t* leafc = (int64_t*)malloc(sizeof(int64_t) * 3 * n);

@@ -59,6 +59,13 @@ int ccref_bruteforce_targets(int64_t n, const double* pos, const double* m, int6
 /* The paper's recursive FMM (three passes); H is [n][3] in input order. stats may be NULL. */
 int ccref_fmm(int64_t n, const double* pos, const double* m, const ccref_params* prm, double* H,
               ccref_stats* stats);
+/* Same with per-smallest-cell parameters, given per dipole (every dipole of a
+ * smallest cell carries its cell's values; NULL = the fixed parameters):
+ * leaf_p in 1..order truncates the cell's local expansion before L2P, and
+ * leaf_theta in (0,1) is the opening angle with which the cell re-splits its
+ * own candidates into near and far cells (the levels above keep theta). */
+int ccref_fmm_leaf(int64_t n, const double* pos, const double* m, const ccref_params* prm,
+                   const int32_t* leaf_p, const double* leaf_theta, double* H, ccref_stats* stats);
 /* Level count and split sequence only (the rule of Sec. 4); fills stats->levels, split_axis,
  * box, leaf_side, s_used.  No lists are built. */
 int ccref_tree_shape(int64_t n, const double* pos, const ccref_params* prm, ccref_stats* stats);

@@ -59,6 +59,8 @@ def lib():
         L.ccref_bruteforce.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_int32]
         L.ccref_bruteforce_targets.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _ip, _dp, C.c_int32]
         L.ccref_fmm.argtypes = [C.c_int64, _dp, _dp, C.POINTER(Params), _dp, C.POINTER(Stats)]
+        L.ccref_fmm_leaf.argtypes = [C.c_int64, _dp, _dp, C.POINTER(Params), C.c_void_p, C.c_void_p, _dp,
+                                     C.POINTER(Stats)]
         L.ccref_tree_shape.argtypes = [C.c_int64, _dp, C.POINTER(Params), C.POINTER(Stats)]
         L.ccref_energy.argtypes = [C.c_int64, _dp, _dp]
         L.ccref_energy.restype = C.c_double
@@ -151,6 +153,26 @@ def fmm(pos, m, order, theta, leaf_target=0.0, leaf_rule=0, box=None, nthreads=0
     rc = lib().ccref_fmm(pos.shape[0], pos, m, C.byref(prm), H, C.byref(st))
     if rc:
         raise ValueError("ccref_fmm: invalid input")
+    if return_stats:
+        return H, _stats_dict(st)
+    return H
+
+
+def fmm_leaf(pos, m, order, theta, leaf_p=None, leaf_theta=None, leaf_target=0.0, leaf_rule=0, box=None,
+             nthreads=0, return_stats=False):
+    """The FMM with per-smallest-cell order / opening angle, given per dipole."""
+    pos = _f64(pos, (-1, 3))
+    m = _f64(m, (-1, 3))
+    H = np.zeros_like(pos)
+    st = Stats()
+    prm = make_params(order, theta, leaf_target, leaf_rule, box, nthreads)
+    lp = None if leaf_p is None else np.ascontiguousarray(leaf_p, dtype=np.int32)
+    lt = None if leaf_theta is None else np.ascontiguousarray(leaf_theta, dtype=np.float64)
+    rc = lib().ccref_fmm_leaf(pos.shape[0], pos, m, C.byref(prm),
+                              None if lp is None else lp.ctypes.data_as(C.c_void_p),
+                              None if lt is None else lt.ctypes.data_as(C.c_void_p), H, C.byref(st))
+    if rc:
+        raise ValueError("ccref_fmm_leaf: invalid input")
     if return_stats:
         return H, _stats_dict(st)
     return H

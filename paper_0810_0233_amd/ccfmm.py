@@ -60,7 +60,19 @@ EXPORTS = [
     "ccfmm_plan_create_device", "ccfmm_plan_update_positions_device", "ccfmm_eval", "ccfmm_eval_device",
     "ccfmm_eval_device_timed", "ccfmm_plan_autotune", "ccfmm_plan_info", "ccfmm_energy", "ccfmm_plan_destroy",
     "ccfmm_direct_targets_device", "ccfmm_selftest_mfma",
+    "ccfmm_plan_set_leaf_params", "ccfmm_plan_get_leaf_params", "ccfmm_plan_leaf_ids", "ccfmm_plan_leaf_features",
+    "ccfmm_plan_leaf_errors", "ccfmm_mlp_forward", "ccfmm_mlp_loss_grad", "ccfmm_mlp_adam", "ccfmm_plan_select",
 ]
+
+MLP_IN, MLP_HIDDEN, MLP_OUT = 8, 64, 25
+MLP_PARAMS = 64 * 8 + 64 + 64 * 64 + 64 + 25 * 64 + 25
+SEL_P = (2, 3, 4, 5, 6)
+SEL_THETA = (0.3, 0.4, 0.5, 0.6, 0.7)
+
+
+class ccfmm_select_info(C.Structure):
+    _fields_ = [("n_leaves", C.c_int32), ("hist", C.c_int32 * MLP_OUT), ("judge_err", C.c_double),
+                ("fallback", C.c_int32)]
 
 _lib = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -107,6 +119,17 @@ def lib():
         L.ccfmm_direct_targets_device.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                                   C.c_void_p, C.c_void_p]
         L.ccfmm_selftest_mfma.argtypes = [C.c_int32]
+        vp = C.c_void_p
+        L.ccfmm_plan_set_leaf_params.argtypes = [vp, vp, vp, vp]
+        L.ccfmm_plan_get_leaf_params.argtypes = [vp, vp, vp, C.POINTER(C.c_int32)]
+        L.ccfmm_plan_leaf_ids.argtypes = [vp, vp, vp]
+        L.ccfmm_plan_leaf_features.argtypes = [vp, C.c_int32, vp, vp, vp]
+        L.ccfmm_plan_leaf_errors.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
+        L.ccfmm_mlp_forward.argtypes = [vp, C.c_int64, vp, vp, vp]
+        L.ccfmm_mlp_loss_grad.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.ccfmm_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, vp]
+        L.ccfmm_plan_select.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_int32, vp, C.c_int32, vp,
+                                        C.POINTER(ccfmm_select_info)]
         _lib = L
     return _lib
 
@@ -210,6 +233,40 @@ class Plan:
         return [{"variant": out[i].variant, "class_bits": out[i].class_bits, "m2l_ms": out[i].m2l_ms,
                  "steps": out[i].steps} for i in range(n.value)]
 
+    def set_leaf_params(self, d_p, d_theta, stream=0):
+        """Per-cell (order, theta) from device arrays (compact leaf order); 0/None clears."""
+        _check(lib().ccfmm_plan_set_leaf_params(self.h, C.c_void_p(d_p or None), C.c_void_p(d_theta or None),
+                                                C.c_void_p(stream)))
+
+    def get_leaf_params(self):
+        nl = C.c_int32(0)
+        _check(lib().ccfmm_plan_get_leaf_params(self.h, None, None, C.byref(nl)))
+        p = np.zeros(nl.value, dtype=np.int32)
+        th = np.zeros(nl.value)
+        _check(lib().ccfmm_plan_get_leaf_params(self.h, p.ctypes.data_as(C.c_void_p), th.ctypes.data_as(C.c_void_p),
+                                                C.byref(nl)))
+        return p, th
+
+    def leaf_ids(self, d_out, stream=0):
+        _check(lib().ccfmm_plan_leaf_ids(self.h, C.c_void_p(d_out), C.c_void_p(stream)))
+
+    def leaf_features(self, nbatch, d_m, d_feat, stream=0):
+        _check(lib().ccfmm_plan_leaf_features(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_feat),
+                                              C.c_void_p(stream)))
+
+    def leaf_errors(self, nbatch, d_H, d_Href, d_num, d_den, stream=0):
+        _check(lib().ccfmm_plan_leaf_errors(self.h, int(nbatch), C.c_void_p(d_H), C.c_void_p(d_Href),
+                                            C.c_void_p(d_num), C.c_void_p(d_den), C.c_void_p(stream)))
+
+    def select(self, d_params, err_bound, margin, cost_far, nbatch, d_m, judge=True, stream=0):
+        """Learned per-cell (p, theta); returns (status, info dict).  status 1 = fell back."""
+        out = ccfmm_select_info()
+        rc = _check(lib().ccfmm_plan_select(self.h, C.c_void_p(d_params), float(err_bound), float(margin),
+                                            float(cost_far), int(nbatch), C.c_void_p(d_m), int(bool(judge)),
+                                            C.c_void_p(stream), C.byref(out)))
+        return rc, {"n_leaves": out.n_leaves, "hist": list(out.hist), "judge_err": out.judge_err,
+                    "fallback": out.fallback}
+
     def info(self):
         inf = ccfmm_info()
         _check(lib().ccfmm_plan_info(self.h, C.byref(inf)))
@@ -240,6 +297,22 @@ def energy(m, H):
 def direct_targets_device(n, d_pos, d_m, nt, d_idx, d_H, stream=0):
     _check(lib().ccfmm_direct_targets_device(int(n), C.c_void_p(d_pos), C.c_void_p(d_m), int(nt),
                                              C.c_void_p(d_idx), C.c_void_p(d_H), C.c_void_p(stream)))
+
+
+def mlp_forward(d_params, rows, d_x, d_y, stream=0):
+    _check(lib().ccfmm_mlp_forward(C.c_void_p(d_params), int(rows), C.c_void_p(d_x), C.c_void_p(d_y),
+                                   C.c_void_p(stream)))
+
+
+def mlp_loss_grad(d_params, rows, d_x, d_t, d_mask, d_grad, d_loss=None, stream=0):
+    _check(lib().ccfmm_mlp_loss_grad(C.c_void_p(d_params), int(rows), C.c_void_p(d_x), C.c_void_p(d_t),
+                                     C.c_void_p(d_mask), C.c_void_p(d_grad), C.c_void_p(d_loss),
+                                     C.c_void_p(stream)))
+
+
+def mlp_adam(d_params, d_grad, d_m1, d_m2, step, lr, stream=0):
+    _check(lib().ccfmm_mlp_adam(C.c_void_p(d_params), C.c_void_p(d_grad), C.c_void_p(d_m1), C.c_void_p(d_m2),
+                                int(step), float(lr), C.c_void_p(stream)))
 
 
 def selftest_mfma(device=0):

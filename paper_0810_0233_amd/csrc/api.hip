@@ -287,6 +287,7 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
 // Build (or rebuild) everything that depends on the positions.
 static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
   P.drop_graph();
+  P.has_leaf = false;  // per-cell parameters belong to the previous cells
   double mn[3], mx[3];
   bool bad = false;
   device_bbox(d_pos, P.n, P.scratch, st, mn, mx, bad);
@@ -676,6 +677,206 @@ void ccfmm_plan_destroy(ccfmm_plan plan) {
     delete plan;
   } catch (...) {
   }
+}
+
+}  // extern "C"
+
+namespace ccfmm {
+// Install (or clear) per-cell parameters given on the host and rebuild every
+// list, tile and count that depends on them (the tree is unchanged).
+static void apply_leaf_params(Plan& P, const int32_t* hp, const double* hth, hipStream_t st) {
+  const int nl = P.lev[P.L]->ncells;
+  if (hp && hth) {
+    std::vector<double> th2(nl);
+    double tmin = 1.0;
+    for (int i = 0; i < nl; i++) {
+      if (hp[i] < 1 || hp[i] > P.p) fail(CCFMM_EINVAL, "per-cell order outside 1..order");
+      if (!(hth[i] > 0.0 && hth[i] < 1.0)) fail(CCFMM_EINVAL, "per-cell theta outside (0,1)");
+      th2[i] = hth[i] * hth[i];
+      tmin = std::min(tmin, hth[i]);
+    }
+    P.h_leaf_p.assign(hp, hp + nl);
+    P.h_leaf_theta.assign(hth, hth + nl);
+    P.leaf_p.ensure(sizeof(int32_t) * nl);
+    P.leaf_th2.ensure(sizeof(double) * nl);
+    CCFMM_HIP(hipMemcpyAsync(P.leaf_p.p, hp, sizeof(int32_t) * nl, hipMemcpyHostToDevice, st));
+    CCFMM_HIP(hipMemcpyAsync(P.leaf_th2.p, th2.data(), sizeof(double) * nl, hipMemcpyHostToDevice, st));
+    CCFMM_HIP(hipStreamSynchronize(st));
+    P.has_leaf = true;
+    P.leaf_theta_min = tmin;
+  } else {
+    P.has_leaf = false;
+    P.h_leaf_p.clear();
+    P.h_leaf_theta.clear();
+  }
+  P.drop_graph();
+  build_lists(P, st);
+  build_dtensors(P, st);
+  build_m2l_tiles(P, P.tiles_nb, st);
+  fill_info(P, st);
+}
+}  // namespace ccfmm
+
+extern "C" {
+
+int ccfmm_plan_set_leaf_params(ccfmm_plan plan, const int32_t* d_p, const double* d_theta, void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if ((d_p == nullptr) != (d_theta == nullptr)) fail(CCFMM_EINVAL, "give both per-cell arrays or neither");
+    Plan& P = plan->P;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CCFMM_HIP(hipSetDevice(P.device));
+    if (!d_p) {
+      apply_leaf_params(P, nullptr, nullptr, st);
+      return CCFMM_OK;
+    }
+    const int nl = P.lev[P.L]->ncells;
+    std::vector<int32_t> hp(nl);
+    std::vector<double> ht(nl);
+    CCFMM_HIP(hipMemcpyAsync(hp.data(), d_p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipMemcpyAsync(ht.data(), d_theta, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipStreamSynchronize(st));
+    apply_leaf_params(P, hp.data(), ht.data(), st);
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_get_leaf_params(ccfmm_plan plan, int32_t* h_p, double* h_theta, int32_t* n_leaves) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    Plan& P = plan->P;
+    const int nl = P.lev[P.L]->ncells;
+    if (n_leaves) *n_leaves = nl;
+    for (int i = 0; i < nl; i++) {
+      if (h_p) h_p[i] = P.has_leaf ? P.h_leaf_p[i] : P.p;
+      if (h_theta) h_theta[i] = P.has_leaf ? P.h_leaf_theta[i] : P.prm.theta;
+    }
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_leaf_ids(ccfmm_plan plan, int32_t* d_out, void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_out) fail(CCFMM_EINVAL, "output is NULL");
+    CCFMM_HIP(hipSetDevice(plan->P.device));
+    run_leaf_ids(plan->P, d_out, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_leaf_features(ccfmm_plan plan, int32_t nbatch, const double* d_m, float* d_feat, void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_m || !d_feat || nbatch < 1) fail(CCFMM_EINVAL, "invalid argument");
+    Plan& P = plan->P;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CCFMM_HIP(hipSetDevice(P.device));
+    if (P.has_leaf) apply_leaf_params(P, nullptr, nullptr, st);  // features use the fixed lists
+    run_leaf_features(P, nbatch, d_m, d_feat, st);
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_leaf_errors(ccfmm_plan plan, int32_t nbatch, const double* d_H, const double* d_Href, double* d_num,
+                           double* d_den, void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_H || !d_Href || !d_num || !d_den || nbatch < 1) fail(CCFMM_EINVAL, "invalid argument");
+    CCFMM_HIP(hipSetDevice(plan->P.device));
+    run_leaf_errors(plan->P, nbatch, d_H, d_Href, d_num, d_den, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_mlp_forward(const float* d_params, int64_t rows, const float* d_x, float* d_y, void* stream) {
+  return guarded([&] {
+    if (!d_params || rows < 0 || (rows > 0 && (!d_x || !d_y))) fail(CCFMM_EINVAL, "invalid argument");
+    run_mlp_forward(d_params, rows, d_x, d_y, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+// gradient partials (one training loop at a time per process); never freed, so
+// nothing touches the runtime during process teardown
+static DevBuf& mlp_tmp() {
+  static DevBuf* b = new DevBuf();
+  return *b;
+}
+
+int ccfmm_mlp_loss_grad(const float* d_params, int64_t rows, const float* d_x, const float* d_t, const float* d_mask,
+                        float* d_grad, float* d_loss, void* stream) {
+  return guarded([&] {
+    if (!d_params || !d_grad || rows < 1 || !d_x || !d_t || !d_mask) fail(CCFMM_EINVAL, "invalid argument");
+    run_mlp_loss_grad(d_params, rows, d_x, d_t, d_mask, d_grad, d_loss, mlp_tmp(),
+                      reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_mlp_adam(float* d_params, const float* d_grad, float* d_m1, float* d_m2, int32_t step, float lr,
+                   void* stream) {
+  return guarded([&] {
+    if (!d_params || !d_grad || !d_m1 || !d_m2 || step < 1 || !(lr > 0.f)) fail(CCFMM_EINVAL, "invalid argument");
+    run_mlp_adam(d_params, d_grad, d_m1, d_m2, step, lr, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_plan_select(ccfmm_plan plan, const float* d_params, double err_bound, double margin, double cost_far,
+                      int32_t nbatch, const double* d_m, int32_t judge, void* stream, ccfmm_select_info* out) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_params || !d_m || !(err_bound > 0.0) || !(cost_far >= 0.0)) fail(CCFMM_EINVAL, "invalid argument");
+    Plan& P = plan->P;
+    if (nbatch < 1 || nbatch > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CCFMM_HIP(hipSetDevice(P.device));
+    if (P.has_leaf) apply_leaf_params(P, nullptr, nullptr, st);
+    const int nl = P.lev[P.L]->ncells;
+    DevBuf dp, dt;
+    dp.ensure(sizeof(int32_t) * nl);
+    dt.ensure(sizeof(double) * nl);
+    std::vector<int32_t> hist;
+    run_select(P, d_params, std::log10(err_bound) - margin, cost_far, nbatch, d_m, dp.as<int32_t>(),
+               dt.as<double>(), hist, st);
+    std::vector<int32_t> hp(nl);
+    std::vector<double> ht(nl);
+    CCFMM_HIP(hipMemcpyAsync(hp.data(), dp.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipMemcpyAsync(ht.data(), dt.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipStreamSynchronize(st));
+    int rc = CCFMM_OK;
+    double jerr = 0.0;
+    int fb = 0;
+    if (judge) {
+      // fixed-parameter field, then the learned one, on these moments
+      const size_t bytes = sizeof(double) * 3 * (size_t)P.n * nbatch;
+      double* Hf = reinterpret_cast<double*>(P.judge_a.ensure(bytes));
+      double* Hl = reinterpret_cast<double*>(P.judge_b.ensure(bytes));
+      prepare_batch(P, nbatch, st);
+      eval_passes(P, nbatch, d_m, Hf, st, nullptr);
+      apply_leaf_params(P, hp.data(), ht.data(), st);
+      prepare_batch(P, nbatch, st);
+      eval_passes(P, nbatch, d_m, Hl, st, nullptr);
+      jerr = run_rel_rms(Hl, Hf, (int64_t)3 * P.n * nbatch, P.scratch, st);
+      if (!(jerr <= err_bound)) {
+        apply_leaf_params(P, nullptr, nullptr, st);
+        fb = 1;
+        rc = CCFMM_W_FALLBACK;
+      }
+    } else {
+      apply_leaf_params(P, hp.data(), ht.data(), st);
+    }
+    P.info.fallback = fb;
+    if (out) {
+      std::memset(out, 0, sizeof(*out));
+      out->n_leaves = nl;
+      for (int i = 0; i < CCFMM_MLP_OUT && i < (int)hist.size(); i++) out->hist[i] = hist[i];
+      out->judge_err = jerr;
+      out->fallback = fb;
+    }
+    return rc;
+  });
 }
 
 int ccfmm_direct_targets_device(int64_t n, const double* d_pos, const double* d_m, int64_t nt, const int64_t* d_idx,

@@ -44,6 +44,7 @@ struct ListArgs {
   const int32_t* pnear_ptr;   // level l-1
   const int32_t* pnear_idx;
   const int32_t* pchild;      // level l-1
+  const double* cell_th2;     // per-cell squared opening angle (smallest cells), or null
   int32_t ncells;
   int level;
   double theta2;
@@ -62,6 +63,7 @@ __global__ void __launch_bounds__(256) k_list_count(ListArgs a, TreeGeom G, int3
   const int pc = a.parent[c];
   const int e0 = a.pnear_ptr[pc], ncand = 2 * (a.pnear_ptr[pc + 1] - e0);
   const int cx = a.coord[3 * c], cy = a.coord[3 * c + 1], cz = a.coord[3 * c + 2];
+  const double th2 = a.cell_th2 ? a.cell_th2[c] : a.theta2;  // a smallest cell may use its own angle
   int nn = 0, nf = 0;
   for (int base = 0; base < ncand; base += 64) {
     const int i = base + lane;
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(256) k_list_count(ListArgs a, TreeGeom G, int3
     if (i < ncand) {
       const int X = a.pchild[2 * a.pnear_idx[e0 + (i >> 1)] + (i & 1)];
       if (X >= 0) {
-        const bool nr = is_near(lg, a.theta2, a.coord[3 * X] - cx, a.coord[3 * X + 1] - cy, a.coord[3 * X + 2] - cz);
+        const bool nr = is_near(lg, th2,a.coord[3 * X] - cx, a.coord[3 * X + 1] - cy, a.coord[3 * X + 2] - cz);
         isn = nr;
         isf = !nr;
       }
@@ -93,6 +95,7 @@ __global__ void __launch_bounds__(256) k_list_fill(ListArgs a, TreeGeom G, const
   const int pc = a.parent[c];
   const int e0 = a.pnear_ptr[pc], ncand = 2 * (a.pnear_ptr[pc + 1] - e0);
   const int cx = a.coord[3 * c], cy = a.coord[3 * c + 1], cz = a.coord[3 * c + 2];
+  const double th2 = a.cell_th2 ? a.cell_th2[c] : a.theta2;  // a smallest cell may use its own angle
   int64_t jn = near_ptr[c], jf = far_ptr[c];
   const uint64_t lt = lanemask_lt(lane);
   for (int base = 0; base < ncand; base += 64) {
@@ -105,7 +108,7 @@ __global__ void __launch_bounds__(256) k_list_fill(ListArgs a, TreeGeom G, const
         dx = a.coord[3 * X] - cx;
         dy = a.coord[3 * X + 1] - cy;
         dz = a.coord[3 * X + 2] - cz;
-        const bool nr = is_near(lg, a.theta2, dx, dy, dz);
+        const bool nr = is_near(lg, th2,dx, dy, dz);
         isn = nr;
         isf = !nr;
       }
@@ -148,8 +151,9 @@ static void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
 // candidates are children of near cells of the parent, so their offsets are
 // those of the parent level, doubled (+1) along the axis halved at this level.
 static void level_bounds(Plan& P) {
-  const double th = P.prm.theta;
   for (int l = 0; l <= P.L; l++) {
+    // smallest cells with their own angles are bounded by the smallest of them
+    const double th = (l == P.L && P.has_leaf) ? std::min(P.prm.theta, P.leaf_theta_min) : P.prm.theta;
     LevelData& D = *P.lev[l];
     const LevelGeom& lg = P.geo.lev[l];
     const double R = lg.g[0] * lg.g[0] + lg.g[1] * lg.g[1] + lg.g[2] * lg.g[2];
@@ -218,6 +222,7 @@ void build_lists(Plan& P, hipStream_t st) {
     a.ncells = nc;
     a.level = l;
     a.theta2 = theta2;
+    a.cell_th2 = (l == L && P.has_leaf) ? P.leaf_th2.as<double>() : nullptr;
     for (int q = 0; q < 3; q++) a.wfar[q] = D.wfar[q];
     a.near_cap = near_cap;
     a.far_cap = far_cap;
@@ -341,6 +346,7 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   P.TC = cols / tb;
   P.tiles_variant = P.m2l_variant;
   P.tiles_class_bits = P.class_bits;
+  P.tiles_nb = nbatch;
   P.ncg = ceil_div(nbatch, tb);
   const int TC = P.TC;
   // pass 1: ordering, bitmaps, step counts per target group

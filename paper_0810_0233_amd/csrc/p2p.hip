@@ -53,6 +53,7 @@ struct P2PArgs {
   double g[3];               // leaf sides / smallest leaf side
   double inv_s3;             // 1 / s_L^3
   int64_t voff;              // offset of level L in V
+  const int32_t* leaf_p;     // per-cell local order (compact leaves), or null
 };
 
 template <typename T, int P>
@@ -135,11 +136,13 @@ __global__ void __launch_bounds__(64 * kP2PWaves) k_p2p_l2p(P2PArgs a, const T* 
     py[j] = py[j - 1] * yy * inv;
     pz[j] = pz[j - 1] * yz * inv;
   }
+  // a smallest cell with its own order p_l keeps |n| <= p_l, i.e. |k| <= p_l - 1
+  const int pl = a.leaf_p ? a.leaf_p[ch.leaf] : P;
   T ex = (T)0, ey = (T)0, ez = (T)0;
 #pragma unroll
   for (int k = 0; k < NM; k++) {
     const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
-    const T mono = px[kx] * py[ky] * pz[kz];
+    const T mono = (kx + ky + kz < pl) ? px[kx] * py[ky] * pz[kz] : (T)0;
     ex += v[midx(kx + 1, ky, kz) - 1] * mono;
     ey += v[midx(kx, ky + 1, kz) - 1] * mono;
     ez += v[midx(kx, ky, kz + 1) - 1] * mono;
@@ -158,7 +161,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves) k_p2p_l2p(P2PArgs a, const T* 
 template <typename T, int P>
 __global__ void k_l2p_batched(int64_t n, int nb, const int32_t* __restrict__ dleaf, const int32_t* __restrict__ perm,
                               const T* __restrict__ y, const T* __restrict__ V, int64_t voff, double inv_s3,
-                              double* __restrict__ H) {
+                              const int32_t* __restrict__ leaf_p, double* __restrict__ H) {
   constexpr int NS = nstride(P);
   constexpr int NM = ncoef(P - 1);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,11 +179,12 @@ __global__ void k_l2p_batched(int64_t n, int nb, const int32_t* __restrict__ dle
     py[j] = py[j - 1] * yy * inv;
     pz[j] = pz[j - 1] * yz * inv;
   }
+  const int pl = leaf_p ? leaf_p[dleaf[i]] : P;
   T ex = (T)0, ey = (T)0, ez = (T)0;
 #pragma unroll
   for (int k = 0; k < NM; k++) {
     const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
-    const T mono = px[kx] * py[ky] * pz[kz];
+    const T mono = (kx + ky + kz < pl) ? px[kx] * py[ky] * pz[kz] : (T)0;
     ex += v[midx(kx + 1, ky, kz) - 1] * mono;
     ey += v[midx(kx, ky + 1, kz) - 1] * mono;
     ez += v[midx(kx, ky, kz + 1) - 1] * mono;
@@ -322,7 +326,8 @@ static void p2p_batched_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const double s = P.geo.lev[P.L].s;
   const double inv_s3 = 1.0 / (s * s * s);
   k_l2p_batched<T, PP><<<ceil_div(P.n * nb, 256), 256, 0, st>>>(P.n, nb, P.dleaf.as<int32_t>(), P.perm.as<int32_t>(),
-                                                                y, P.V.as<T>(), D.qoff, inv_s3, d_H);
+                                                                y, P.V.as<T>(), D.qoff, inv_s3,
+                                                                P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr, d_H);
   CCFMM_HIP(hipGetLastError());
   P2PArgs a;
   a.chunks = nullptr;
@@ -338,6 +343,7 @@ static void p2p_batched_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   for (int q = 0; q < 3; q++) a.g[q] = P.geo.lev[P.L].g[q];
   a.inv_s3 = inv_s3;
   a.voff = D.qoff;
+  a.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
   if (P.nchunks32 == 0) return;
   dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
   k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(), d_H);
@@ -366,6 +372,7 @@ static void p2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const double s = P.geo.lev[P.L].s;
   a.inv_s3 = 1.0 / (s * s * s);
   a.voff = D.qoff;
+  a.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
   const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
   dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
   k_p2p_l2p<T, PP><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);

@@ -105,6 +105,15 @@ struct Plan {
   DevBuf scratch;    // scan/sort temporaries
   DevBuf scratch2;
   DevBuf flags;      // device error flags
+  // per-smallest-cell order and opening angle (compact leaf order); the levels
+  // above keep (p, theta).  theta is stored squared, as the list test uses it.
+  bool has_leaf = false;
+  DevBuf leaf_p, leaf_th2;
+  std::vector<int32_t> h_leaf_p;    // host copies of the per-cell parameters
+  std::vector<double> h_leaf_theta;
+  double leaf_theta_min = 1.0;
+  int tiles_nb = 1;                 // nbatch the M2L tiles were built for
+  DevBuf judge_a, judge_b;          // field buffers of the selector's judge
   // captured evaluation graph, valid for (g_nb, g_m, g_H) until the next rebuild
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
@@ -136,6 +145,20 @@ void run_l2l(Plan& P, int nb, hipStream_t st);
 void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st);
 void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt,
                         const int64_t* d_idx, double* d_H, hipStream_t st);
+
+// learned selector and per-cell data (selector.hip)
+void run_leaf_ids(Plan& P, int32_t* d_out, hipStream_t st);
+void run_leaf_errors(Plan& P, int nb, const double* d_H, const double* d_Href, double* d_num, double* d_den,
+                     hipStream_t st);
+void run_leaf_features(Plan& P, int nb, const double* d_m, float* d_feat, hipStream_t st);
+void run_mlp_forward(const float* d_params, int64_t rows, const float* d_x, float* d_y, hipStream_t st);
+void run_mlp_loss_grad(const float* d_params, int64_t rows, const float* d_x, const float* d_t, const float* d_mask,
+                       float* d_grad, float* d_loss, DevBuf& tmp, hipStream_t st);
+void run_mlp_adam(float* d_params, const float* d_grad, float* d_m1, float* d_m2, int step, float lr,
+                  hipStream_t st);
+void run_select(Plan& P, const float* d_params, double log_bound, double cost_far, int nb, const double* d_m,
+                int32_t* d_p, double* d_theta, std::vector<int32_t>& hist, hipStream_t st);
+double run_rel_rms(const double* d_A, const double* d_B, int64_t count, DevBuf& tmp, hipStream_t st);
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

@@ -1,0 +1,465 @@
+// selector.hip -- learned per-smallest-cell choice of local order and opening
+// angle, and the pieces it is trained from.
+//
+// The paper chooses (p_m, alpha_m) once for a whole system from timing and the
+// error estimate [alpha/(2-alpha)]^p (Sec. 4).  Here a small MLP predicts, for
+// every smallest cell, log10 of the relative RMS field error of that cell for
+// each candidate pair (p, theta) in {2..6} x {0.3..0.7}; the cheapest pair
+// whose prediction meets the bound (with a margin) is used for that cell.  The
+// levels above keep the plan's fixed (p, theta); a cell's theta re-splits its
+// own candidates into near and far cells and its p truncates its local
+// expansion.  Features, network forward/backward, optimiser and selection all
+// run in the kernels below.
+#include <algorithm>
+#include <cmath>
+
+#include "plan.hpp"
+
+namespace ccfmm {
+
+constexpr int kIn = CCFMM_MLP_IN, kH = CCFMM_MLP_HIDDEN, kOut = CCFMM_MLP_OUT;
+constexpr int kParams = kH * kIn + kH + kH * kH + kH + kOut * kH + kOut;
+// packed parameter offsets: W1 [kH][kIn], b1, W2 [kH][kH], b2, W3 [kOut][kH], b3
+constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+              ob3 = oW3 + kOut * kH;
+static_assert(ob3 + kOut == kParams, "parameter packing");
+
+__device__ constexpr double kThetaSet[5] = {0.3, 0.4, 0.5, 0.6, 0.7};
+
+// ---------------------------------------------------------------- per-cell data
+__global__ void k_leaf_ids(int64_t n, const int32_t* __restrict__ dleaf, const int32_t* __restrict__ perm,
+                           int32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[perm[i]] = dleaf[i];
+}
+
+// per cell: sum over its dipoles and the configurations of |H - Href|^2 and |Href|^2
+__global__ void k_leaf_err(int32_t nl, int64_t n, int nb, const int32_t* __restrict__ lstart,
+                           const int32_t* __restrict__ lcount, const int32_t* __restrict__ perm,
+                           const double* __restrict__ H, const double* __restrict__ Href, double* num, double* den) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  double a = 0.0, b2 = 0.0;
+  for (int k = 0; k < lcount[l]; k++) {
+    const int64_t i = perm[lstart[l] + k];
+    for (int b = 0; b < nb; b++) {
+      const int64_t o = ((int64_t)b * n + i) * 3;
+      for (int c = 0; c < 3; c++) {
+        const double d = H[o + c] - Href[o + c];
+        a += d * d;
+        b2 += Href[o + c] * Href[o + c];
+      }
+    }
+  }
+  num[l] = a;
+  den[l] = b2;
+}
+
+// Eight features of a smallest cell (computed on the fixed-parameter lists):
+// log2(1+count), log2(1+near sources), near cells/64, far cells/64, |mean m|,
+// moment variance, log2 of count over mean near occupancy, level/16.
+__global__ void k_leaf_features(int32_t nl, int64_t n, int nb, int L, const int32_t* __restrict__ lstart,
+                                const int32_t* __restrict__ lcount, const int32_t* __restrict__ near_ptr,
+                                const int32_t* __restrict__ near_idx, const int32_t* __restrict__ far_ptr,
+                                const int32_t* __restrict__ perm, const double* __restrict__ m, float* feat) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  const int c = lcount[l];
+  int64_t nsrc = 0;
+  const int nnear = near_ptr[l + 1] - near_ptr[l];
+  for (int e = near_ptr[l]; e < near_ptr[l + 1]; e++) nsrc += lcount[near_idx[e]];
+  const int nfar = far_ptr[l + 1] - far_ptr[l];
+  double sx = 0, sy = 0, sz = 0, s2 = 0;
+  for (int k = 0; k < c; k++) {
+    const int64_t i = perm[lstart[l] + k];
+    for (int b = 0; b < nb; b++) {
+      const double* mi = m + ((int64_t)b * n + i) * 3;
+      sx += mi[0];
+      sy += mi[1];
+      sz += mi[2];
+      s2 += mi[0] * mi[0] + mi[1] * mi[1] + mi[2] * mi[2];
+    }
+  }
+  const double cnt = (double)c * nb;
+  const double mx = sx / cnt, my = sy / cnt, mz = sz / cnt;
+  const double mm = sqrt(mx * mx + my * my + mz * mz);
+  const double var = s2 / cnt - mm * mm;
+  const double mean_near = (double)nsrc / (double)max(1, nnear);
+  float* f = feat + (int64_t)l * kIn;
+  f[0] = (float)log2(1.0 + c);
+  f[1] = (float)log2(1.0 + (double)nsrc);
+  f[2] = (float)(nnear / 64.0);
+  f[3] = (float)(nfar / 64.0);
+  f[4] = (float)mm;
+  f[5] = (float)var;
+  f[6] = (float)(log2(1.0 + c) - log2(1.0 + mean_near));
+  f[7] = (float)(L / 16.0);
+}
+
+// ---------------------------------------------------------------- MLP
+__device__ __forceinline__ void mlp_row(const float* __restrict__ P, const float* x, float* a1, float* a2, float* y) {
+  for (int j = 0; j < kH; j++) {
+    float s = P[ob1 + j];
+    for (int i = 0; i < kIn; i++) s += P[oW1 + j * kIn + i] * x[i];
+    a1[j] = s > 0.f ? s : 0.f;
+  }
+  for (int j = 0; j < kH; j++) {
+    float s = P[ob2 + j];
+    for (int i = 0; i < kH; i++) s += P[oW2 + j * kH + i] * a1[i];
+    a2[j] = s > 0.f ? s : 0.f;
+  }
+  for (int o = 0; o < kOut; o++) {
+    float s = P[ob3 + o];
+    for (int i = 0; i < kH; i++) s += P[oW3 + o * kH + i] * a2[i];
+    y[o] = s;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ params, int64_t rows,
+                                                    const float* __restrict__ x, float* __restrict__ y) {
+  __shared__ float P[kParams];
+  for (int q = threadIdx.x; q < kParams; q += blockDim.x) P[q] = params[q];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float a1[kH], a2[kH], xr[kIn];
+  for (int i = 0; i < kIn; i++) xr[i] = x[r * kIn + i];
+  mlp_row(P, xr, a1, a2, y + r * kOut);
+}
+
+// Masked squared error: loss = sum mask (y - t)^2 / 2 / max(1, sum mask).
+// Each block of 64 rows stores, per row, the forward activations and the
+// back-propagated deltas in LDS, then all threads form the block's share of
+// every parameter gradient; a second kernel sums the blocks in a fixed order.
+constexpr int kGR = 64;  // rows per gradient block
+
+__global__ void k_mask_sum(int64_t count, const float* __restrict__ mask, double* out) {
+  __shared__ double s[256];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) v += mask[i];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0] > 1.0 ? s[0] : 1.0;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_grad_part(const float* __restrict__ params, int64_t rows,
+                                                       const float* __restrict__ x, const float* __restrict__ t,
+                                                       const float* __restrict__ mask, const double* __restrict__ norm,
+                                                       float* __restrict__ part, double* __restrict__ loss_part) {
+  // rows padded by one word: phase one walks a row per thread
+  __shared__ float sx[kGR][kIn + 1], sa1[kGR][kH + 1], sa2[kGR][kH + 1], sd1[kGR][kH + 1], sd2[kGR][kH + 1],
+      sdy[kGR][kOut];
+  __shared__ double sl[kGR];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kGR;
+  const float inv = (float)(1.0 / norm[0]);
+  if (tid < kGR) {
+    const int64_t r = r0 + tid;
+    float xr[kIn], a1[kH], a2[kH], y[kOut], d2[kH];
+    double l = 0.0;
+    if (r < rows) {
+      for (int i = 0; i < kIn; i++) xr[i] = x[r * kIn + i];
+      mlp_row(params, xr, a1, a2, y);
+      for (int o = 0; o < kOut; o++) {
+        const float e = y[o] - t[r * kOut + o];
+        const float w = mask[r * kOut + o];
+        l += 0.5 * (double)w * (double)e * (double)e;
+        sdy[tid][o] = w * e * inv;
+      }
+    } else {
+      for (int i = 0; i < kIn; i++) xr[i] = 0.f;
+      for (int j = 0; j < kH; j++) a1[j] = a2[j] = 0.f;
+      for (int o = 0; o < kOut; o++) sdy[tid][o] = 0.f;
+    }
+    sl[tid] = l;
+    for (int i = 0; i < kIn; i++) sx[tid][i] = xr[i];
+    for (int j = 0; j < kH; j++) {
+      sa1[tid][j] = a1[j];
+      sa2[tid][j] = a2[j];
+    }
+    for (int i = 0; i < kH; i++) {
+      float s = 0.f;
+      for (int o = 0; o < kOut; o++) s += params[oW3 + o * kH + i] * sdy[tid][o];
+      d2[i] = a2[i] > 0.f ? s : 0.f;
+      sd2[tid][i] = d2[i];
+    }
+    for (int i = 0; i < kH; i++) {
+      float s = 0.f;
+      for (int j = 0; j < kH; j++) s += params[oW2 + j * kH + i] * d2[j];
+      sd1[tid][i] = a1[i] > 0.f ? s : 0.f;
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < kParams; q += 256) {
+    float g = 0.f;
+    if (q < ob1) {  // W1[j][i]
+      const int j = q / kIn, i = q % kIn;
+      for (int r = 0; r < kGR; r++) g += sd1[r][j] * sx[r][i];
+    } else if (q < oW2) {
+      const int j = q - ob1;
+      for (int r = 0; r < kGR; r++) g += sd1[r][j];
+    } else if (q < ob2) {  // W2[j][i]
+      const int j = (q - oW2) / kH, i = (q - oW2) % kH;
+      for (int r = 0; r < kGR; r++) g += sd2[r][j] * sa1[r][i];
+    } else if (q < oW3) {
+      const int j = q - ob2;
+      for (int r = 0; r < kGR; r++) g += sd2[r][j];
+    } else if (q < ob3) {  // W3[o][i]
+      const int o = (q - oW3) / kH, i = (q - oW3) % kH;
+      for (int r = 0; r < kGR; r++) g += sdy[r][o] * sa2[r][i];
+    } else {
+      const int o = q - ob3;
+      for (int r = 0; r < kGR; r++) g += sdy[r][o];
+    }
+    part[(int64_t)blockIdx.x * kParams + q] = g;
+  }
+  if (tid == 0) {
+    double s = 0.0;
+    for (int r = 0; r < kGR; r++) s += sl[r];
+    loss_part[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_mlp_grad_sum(int nblk, const float* __restrict__ part, const double* __restrict__ loss_part,
+                               const double* __restrict__ norm, float* __restrict__ grad, float* __restrict__ loss) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < kParams) {
+    float g = 0.f;
+    for (int b = 0; b < nblk; b++) g += part[(int64_t)b * kParams + q];
+    grad[q] = g;
+  }
+  if (q == 0 && loss) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; b++) s += loss_part[b];
+    loss[0] = (float)(s / norm[0]);
+  }
+}
+
+// Adam step (bias-corrected), one thread per parameter.
+__global__ void k_adam(float* __restrict__ params, const float* __restrict__ grad, float* __restrict__ m1,
+                       float* __restrict__ m2, int step, float lr, float b1, float b2, float eps) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= kParams) return;
+  const float g = grad[q];
+  const float a = b1 * m1[q] + (1.f - b1) * g;
+  const float v = b2 * m2[q] + (1.f - b2) * g * g;
+  m1[q] = a;
+  m2[q] = v;
+  const float ah = a / (1.f - powf(b1, (float)step));
+  const float vh = v / (1.f - powf(b2, (float)step));
+  params[q] -= lr * ah / (sqrtf(vh) + eps);
+}
+
+// ---------------------------------------------------------------- selection
+struct SelectArgs {
+  const int32_t* parent;      // smallest level
+  const int32_t* coord;
+  const int32_t* pnear_ptr;   // level above
+  const int32_t* pnear_idx;
+  const int32_t* pchild;
+  const int32_t* lcount;      // smallest cells
+  int32_t nl;
+  int L;
+  double log_bound;           // log10(err_bound) - margin
+  double cost_far;            // cost of one far (M2L) cell relative to one dipole pair
+  int pmax;
+};
+
+__device__ __forceinline__ bool near_test(const LevelGeom& lg, double th2, int dx, int dy, int dz) {
+#pragma clang fp contract(off)
+  const double ax = (double)dx * lg.g[0];
+  const double ay = (double)dy * lg.g[1];
+  const double az = (double)dz * lg.g[2];
+  double D = ax * ax;
+  D = D + ay * ay;
+  D = D + az * az;
+  double R = lg.g[0] * lg.g[0];
+  R = R + lg.g[1] * lg.g[1];
+  R = R + lg.g[2] * lg.g[2];
+  return !(th2 * D >= R);
+}
+
+// Per cell: cost of each candidate angle (its own dipoles x near source
+// dipoles + cost_far x far cells, counted over the cell's candidates), then
+// the cheapest (p, theta) whose predicted log10 error meets the bound; ties
+// go to the higher order.  If none does, the most accurate pair (pmax, 0.3).
+__global__ void k_select(SelectArgs a, TreeGeom G, const float* __restrict__ pred, int32_t* out_p, double* out_theta,
+                         int32_t* hist) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.nl) return;
+  const LevelGeom& lg = G.lev[a.L];
+  double th2[5];
+  for (int q = 0; q < 5; q++) th2[q] = kThetaSet[q] * kThetaSet[q];
+  double near_src[5] = {0, 0, 0, 0, 0}, far_cells[5] = {0, 0, 0, 0, 0};
+  const int pc = a.parent[c];
+  const int cx = a.coord[3 * c], cy = a.coord[3 * c + 1], cz = a.coord[3 * c + 2];
+  for (int e = a.pnear_ptr[pc]; e < a.pnear_ptr[pc + 1]; e++) {
+    for (int s = 0; s < 2; s++) {
+      const int X = a.pchild[2 * a.pnear_idx[e] + s];
+      if (X < 0) continue;
+      const int dx = a.coord[3 * X] - cx, dy = a.coord[3 * X + 1] - cy, dz = a.coord[3 * X + 2] - cz;
+      for (int q = 0; q < 5; q++) {
+        if (near_test(lg, th2[q], dx, dy, dz))
+          near_src[q] += a.lcount[X];
+        else
+          far_cells[q] += 1.0;
+      }
+    }
+  }
+  const double own = a.lcount[c];
+  int best_p = a.pmax, best_t = 0;
+  double best_cost = INFINITY;
+  bool found = false;
+  for (int q = 0; q < 5; q++) {
+    const double cost = own * near_src[q] + a.cost_far * far_cells[q];
+    for (int p = 6; p >= 2; p--) {
+      if (p > a.pmax) continue;
+      const float y = pred[(int64_t)c * kOut + (p - 2) * 5 + q];
+      if (y <= a.log_bound && (cost < best_cost || (cost == best_cost && p > best_p))) {
+        best_cost = cost;
+        best_p = p;
+        best_t = q;
+        found = true;
+      }
+    }
+  }
+  if (!found) {
+    best_p = a.pmax < 6 ? a.pmax : 6;
+    best_t = 0;
+  }
+  out_p[c] = best_p;
+  out_theta[c] = kThetaSet[best_t];
+  atomicAdd(&hist[(best_p - 2) * 5 + best_t], 1);
+}
+
+__global__ void k_diff_sums(int64_t count, const double* __restrict__ A, const double* __restrict__ B, double* part) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
+    const double d = A[i] - B[i];
+    a += d * d;
+    b += B[i] * B[i];
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s1[threadIdx.x] += s1[threadIdx.x + off];
+      s2[threadIdx.x] += s2[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1[0];
+    part[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+void run_leaf_ids(Plan& P, int32_t* d_out, hipStream_t st) {
+  k_leaf_ids<<<ceil_div(P.n, 256), 256, 0, st>>>(P.n, P.dleaf.as<int32_t>(), P.perm.as<int32_t>(), d_out);
+  CCFMM_HIP(hipGetLastError());
+}
+
+void run_leaf_errors(Plan& P, int nb, const double* d_H, const double* d_Href, double* d_num, double* d_den,
+                     hipStream_t st) {
+  const int nl = P.lev[P.L]->ncells;
+  k_leaf_err<<<ceil_div(nl, 128), 128, 0, st>>>(nl, P.n, nb, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(),
+                                                 P.perm.as<int32_t>(), d_H, d_Href, d_num, d_den);
+  CCFMM_HIP(hipGetLastError());
+}
+
+void run_leaf_features(Plan& P, int nb, const double* d_m, float* d_feat, hipStream_t st) {
+  LevelData& D = *P.lev[P.L];
+  const int nl = D.ncells;
+  k_leaf_features<<<ceil_div(nl, 128), 128, 0, st>>>(nl, P.n, nb, P.L, P.lstart.as<int32_t>(),
+                                                     P.lcount.as<int32_t>(), D.near_ptr.as<int32_t>(),
+                                                     D.near_idx.as<int32_t>(), D.far_ptr.as<int32_t>(),
+                                                     P.perm.as<int32_t>(), d_m, d_feat);
+  CCFMM_HIP(hipGetLastError());
+}
+
+void run_mlp_forward(const float* d_params, int64_t rows, const float* d_x, float* d_y, hipStream_t st) {
+  if (rows <= 0) return;
+  k_mlp_forward<<<ceil_div(rows, 64), 64, 0, st>>>(d_params, rows, d_x, d_y);
+  CCFMM_HIP(hipGetLastError());
+}
+
+void run_mlp_loss_grad(const float* d_params, int64_t rows, const float* d_x, const float* d_t, const float* d_mask,
+                       float* d_grad, float* d_loss, DevBuf& tmp, hipStream_t st) {
+  const int nblk = std::max(1, ceil_div(rows, kGR));
+  const size_t bytes = sizeof(float) * (size_t)nblk * kParams + sizeof(double) * (nblk + 8);
+  char* buf = reinterpret_cast<char*>(tmp.ensure(bytes + 64));
+  double* norm = reinterpret_cast<double*>(buf);
+  double* lpart = norm + 8;
+  float* part = reinterpret_cast<float*>(lpart + nblk);
+  k_mask_sum<<<1, 256, 0, st>>>(rows * kOut, d_mask, norm);
+  CCFMM_HIP(hipGetLastError());
+  k_mlp_grad_part<<<nblk, 256, 0, st>>>(d_params, rows, d_x, d_t, d_mask, norm, part, lpart);
+  CCFMM_HIP(hipGetLastError());
+  k_mlp_grad_sum<<<ceil_div(kParams, 256), 256, 0, st>>>(nblk, part, lpart, norm, d_grad, d_loss);
+  CCFMM_HIP(hipGetLastError());
+}
+
+void run_mlp_adam(float* d_params, const float* d_grad, float* d_m1, float* d_m2, int step, float lr,
+                  hipStream_t st) {
+  k_adam<<<ceil_div(kParams, 256), 256, 0, st>>>(d_params, d_grad, d_m1, d_m2, step, lr, 0.9f, 0.999f, 1e-8f);
+  CCFMM_HIP(hipGetLastError());
+}
+
+// features -> network -> per-cell choice; returns the choice histogram
+void run_select(Plan& P, const float* d_params, double log_bound, double cost_far, int nb, const double* d_m,
+                int32_t* d_p, double* d_theta, std::vector<int32_t>& hist, hipStream_t st) {
+  LevelData& D = *P.lev[P.L];
+  LevelData& U = *P.lev[P.L > 0 ? P.L - 1 : 0];
+  const int nl = D.ncells;
+  char* buf = reinterpret_cast<char*>(P.scratch2.ensure(sizeof(float) * (size_t)nl * (kIn + kOut) + 256));
+  float* feat = reinterpret_cast<float*>(buf);
+  float* pred = feat + (size_t)nl * kIn;
+  P.flags.ensure(256);  // flags, then the 25 choice counters
+  int32_t* dh = reinterpret_cast<int32_t*>(P.flags.as<char>() + 64);
+  CCFMM_HIP(hipMemsetAsync(dh, 0, sizeof(int32_t) * kOut, st));
+  run_leaf_features(P, nb, d_m, feat, st);
+  run_mlp_forward(d_params, nl, feat, pred, st);
+  if (P.L == 0) fail(CCFMM_EINVAL, "the tree has a single cell: nothing to select");
+  SelectArgs a;
+  a.parent = D.parent.as<int32_t>();
+  a.coord = D.coord.as<int32_t>();
+  a.pnear_ptr = U.near_ptr.as<int32_t>();
+  a.pnear_idx = U.near_idx.as<int32_t>();
+  a.pchild = U.child.as<int32_t>();
+  a.lcount = P.lcount.as<int32_t>();
+  a.nl = nl;
+  a.L = P.L;
+  a.log_bound = log_bound;
+  a.cost_far = cost_far;
+  a.pmax = P.p;
+  k_select<<<ceil_div(nl, 128), 128, 0, st>>>(a, P.geo, pred, d_p, d_theta, dh);
+  CCFMM_HIP(hipGetLastError());
+  hist.assign(kOut, 0);
+  CCFMM_HIP(hipMemcpyAsync(hist.data(), dh, sizeof(int32_t) * kOut, hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+}
+
+double run_rel_rms(const double* d_A, const double* d_B, int64_t count, DevBuf& tmp, hipStream_t st) {
+  const int nblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, count / 256));
+  double* part = reinterpret_cast<double*>(tmp.ensure(sizeof(double) * 2 * nblk));
+  k_diff_sums<<<nblk, 256, 0, st>>>(count, d_A, d_B, part);
+  CCFMM_HIP(hipGetLastError());
+  std::vector<double> h(2 * nblk);
+  CCFMM_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * nblk, hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nblk; i++) {
+    a += h[2 * i];
+    b += h[2 * i + 1];
+  }
+  return b > 0.0 ? std::sqrt(a / b) : 0.0;
+}
+
+}  // namespace ccfmm

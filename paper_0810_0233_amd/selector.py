@@ -1,0 +1,121 @@
+"""Learned per-cell selector: data generation, training and use.
+
+Orchestration only -- every number is produced by the library's kernels
+(features, FMM evaluations with per-cell parameters, per-cell errors, the
+FP64 direct sum, the network's forward/backward pass and its Adam update).
+
+Labels: for every smallest cell and every candidate (p, theta) in
+{2..6} x {0.3..0.7}, log10 of the cell's relative RMS field error
+sqrt(sum |H - H_direct|^2 / sum |H_direct|^2) when all cells use that pair
+(the levels above keep the plan's fixed order and angle).  The network
+learns these 25 numbers from 8 cell features; at use time the cheapest pair
+predicted to meet the bound is taken per cell, and the fixed-parameter FMM
+judges the result (fallback if the learned field differs from it by more
+than the bound).
+"""
+import numpy as np
+
+from . import ccfmm
+
+SEL_P = ccfmm.SEL_P
+SEL_THETA = ccfmm.SEL_THETA
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def init_params(seed):
+    """He-normal initial weights (seeded), packed as the library expects."""
+    rng = np.random.default_rng(seed)
+    i, h, o = ccfmm.MLP_IN, ccfmm.MLP_HIDDEN, ccfmm.MLP_OUT
+    w1 = rng.normal(size=(h, i)) * np.sqrt(2.0 / i)
+    w2 = rng.normal(size=(h, h)) * np.sqrt(2.0 / h)
+    w3 = rng.normal(size=(o, h)) * np.sqrt(1.0 / h)
+    b3 = np.full(o, -5.0)  # log10 errors sit around -5
+    return np.concatenate([w1.ravel(), np.zeros(h), w2.ravel(), np.zeros(h), w3.ravel(), b3]).astype(np.float32)
+
+
+def direct_field(pos, m, dev):
+    """FP64 direct sum at every dipole, on the GPU (one configuration)."""
+    torch = _torch()
+    n = pos.shape[0]
+    d_pos = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+    d_m = torch.from_numpy(np.ascontiguousarray(m)).to(dev)
+    d_idx = torch.arange(n, dtype=torch.int64, device=dev)
+    d_H = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m.data_ptr(), n, d_idx.data_ptr(), d_H.data_ptr(), st)
+    return d_H
+
+
+def cell_labels(pos, box, m, order=6, theta=0.4, precision=ccfmm.PREC_MIXED, dev="cuda:0", H_direct=None):
+    """Features [cells][8] and labels/mask [cells][25] of one geometry."""
+    torch = _torch()
+    dev = torch.device(dev)
+    st = torch.cuda.current_stream().cuda_stream
+    n = pos.shape[0]
+    prm = ccfmm.params(order=order, theta=theta, box=box, precision=precision, max_batch=1)
+    plan = ccfmm.Plan.create(pos, prm)
+    nl = plan.info()["n_leaves"]
+    d_m = torch.from_numpy(np.ascontiguousarray(m)).to(dev)
+    d_feat = torch.empty((nl, ccfmm.MLP_IN), dtype=torch.float32, device=dev)
+    plan.leaf_features(1, d_m.data_ptr(), d_feat.data_ptr(), st)
+    d_ref = H_direct if H_direct is not None else direct_field(pos, m, dev)
+    d_H = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    num = torch.empty(nl, dtype=torch.float64, device=dev)
+    den = torch.empty(nl, dtype=torch.float64, device=dev)
+    labels = np.zeros((nl, ccfmm.MLP_OUT), dtype=np.float32)
+    mask = np.zeros((nl, ccfmm.MLP_OUT), dtype=np.float32)
+    for pi, p in enumerate(SEL_P):
+        for ti, th in enumerate(SEL_THETA):
+            d_p = torch.full((nl,), min(p, order), dtype=torch.int32, device=dev)
+            d_t = torch.full((nl,), th, dtype=torch.float64, device=dev)
+            plan.set_leaf_params(d_p.data_ptr(), d_t.data_ptr(), st)
+            plan.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+            plan.leaf_errors(1, d_H.data_ptr(), d_ref.data_ptr(), num.data_ptr(), den.data_ptr(), st)
+            torch.cuda.synchronize()
+            nn_, dd = num.cpu().numpy(), den.cpu().numpy()
+            ok = (dd > 0) & (nn_ > 0)
+            col = pi * len(SEL_THETA) + ti
+            labels[ok, col] = np.log10(np.sqrt(nn_[ok] / dd[ok]))
+            mask[ok, col] = 1.0
+    plan.destroy()
+    return d_feat.cpu().numpy(), labels, mask
+
+
+def train(features, labels, mask, steps=400, lr=3e-3, seed=0, dev="cuda:0", log_every=0):
+    """Adam on the masked squared error, all on the GPU.  Returns (params, losses)."""
+    torch = _torch()
+    dev = torch.device(dev)
+    st = torch.cuda.current_stream().cuda_stream
+    x = torch.from_numpy(np.ascontiguousarray(features, dtype=np.float32)).to(dev)
+    t = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.float32)).to(dev)
+    mk = torch.from_numpy(np.ascontiguousarray(mask, dtype=np.float32)).to(dev)
+    P = torch.from_numpy(init_params(seed)).to(dev)
+    g = torch.zeros_like(P)
+    m1 = torch.zeros_like(P)
+    m2 = torch.zeros_like(P)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    rows = x.shape[0]
+    losses = []
+    for k in range(1, steps + 1):
+        ccfmm.mlp_loss_grad(P.data_ptr(), rows, x.data_ptr(), t.data_ptr(), mk.data_ptr(), g.data_ptr(),
+                            loss.data_ptr(), st)
+        ccfmm.mlp_adam(P.data_ptr(), g.data_ptr(), m1.data_ptr(), m2.data_ptr(), k, lr, st)
+        if k == 1 or k == steps or (log_every and k % log_every == 0):
+            losses.append((k, float(loss.item())))
+    return P.cpu().numpy(), losses
+
+
+def save(path, params):
+    np.save(path, np.asarray(params, dtype=np.float32), allow_pickle=False)
+
+
+def load(path):
+    p = np.load(path, allow_pickle=False)
+    if p.dtype != np.float32 or p.size != ccfmm.MLP_PARAMS:
+        raise ValueError("not a selector weight file")
+    return p
