@@ -405,3 +405,60 @@ def test_invalid_inputs(ref):
         ref.fmm(np.array([[np.nan, 0, 0]]), np.zeros((1, 3)), 3, 0.5)
     with pytest.raises(ValueError):
         ref.fmm(np.array([[2.0, 0, 0]]), np.zeros((1, 3)), 3, 0.5, box=([0, 0, 0], [1, 1, 1]))
+
+
+def _bar_case(seed=21, n=64):
+    """Dipoles in the box [0,4]x[0,1]x[0,1] with s = 16: two levels, both
+    splits along x, so the smallest cells are the unit cubes [k, k+1) x ..."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 1, size=(n, 3)) * np.array([4.0, 1.0, 1.0])
+    m = inputs.unit_moments(n, rng)
+    return pos, m, ([0.0, 0.0, 0.0], [4.0, 1.0, 1.0]), np.floor(pos[:, 0]).astype(int)
+
+
+def test_fmm_leaf_uniform_equals_fixed(ref):
+    pos, m, box, cell = _bar_case()
+    H, st = ref.fmm(pos, m, 5, 0.6, leaf_target=16, box=box, return_stats=True)
+    assert st["levels"] == 2 and st["split_axis"] == [0, 0]
+    n = pos.shape[0]
+    H2 = ref.fmm_leaf(pos, m, 5, 0.6, leaf_p=np.full(n, 5), leaf_theta=np.full(n, 0.6), leaf_target=16, box=box)
+    assert np.array_equal(H, H2)
+
+
+def test_fmm_leaf_angle_and_order_act_on_own_cell(ref):
+    """A smallest cell's angle decides which of the candidate cells are far for
+    its own dipoles only: cell 0 sees cell 3 at offset 3 (far iff
+    9 theta^2 >= 3, unit cubes), cell 2 at offset 2 (never far for theta < 1).
+    With theta = 0.3 everything is near -> cell 0 gets the direct sum; with 0.7
+    cell 3 is far -> truncation error that falls with the cell's own order."""
+    pos, m, box, cell = _bar_case()
+    n = pos.shape[0]
+    Hb = ref.bruteforce(pos, m)
+    in0 = cell == 0
+    base_p, base_t = np.full(n, 4), np.full(n, 0.7)
+
+    t = base_t.copy()
+    t[in0] = 0.3
+    H = ref.fmm_leaf(pos, m, 4, 0.7, leaf_p=base_p, leaf_theta=t, leaf_target=16, box=box)
+    assert ref.rel_rms(H[in0], Hb[in0]) < 1e-13
+    H_fixed = ref.fmm(pos, m, 4, 0.7, leaf_target=16, box=box)
+    assert np.array_equal(H[~in0], H_fixed[~in0])  # the other cells are untouched
+    assert ref.rel_rms(H_fixed[in0], Hb[in0]) > 1e-8  # at 0.7 cell 3 is far for cell 0
+
+    errs = []
+    for p in (1, 2, 4):
+        pp = base_p.copy()
+        pp[in0] = p
+        Hp = ref.fmm_leaf(pos, m, 4, 0.7, leaf_p=pp, leaf_theta=base_t, leaf_target=16, box=box)
+        assert np.array_equal(Hp[~in0], H_fixed[~in0])
+        errs.append(ref.rel_rms(Hp[in0], Hb[in0]))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] == ref.rel_rms(H_fixed[in0], Hb[in0])
+
+
+def test_fmm_leaf_rejects_bad_parameters(ref):
+    pos, m, box, _ = _bar_case()
+    n = pos.shape[0]
+    for lp, lt in [(np.full(n, 5), None), (np.full(n, 0), None), (None, np.full(n, 1.0)), (None, np.zeros(n))]:
+        with pytest.raises(ValueError):
+            ref.fmm_leaf(pos, m, 4, 0.5, leaf_p=lp, leaf_theta=lt, leaf_target=16, box=box)
