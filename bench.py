@@ -17,7 +17,7 @@ sum.  `value` = dipoles x configurations / step time.  The same run reports
 the evaluation alone (tree reused, captured graph replayed), the plain FP64
 GPU FMM, the error of the mixed result against the FP64 GPU FMM (eps_prec) and
 against the direct sum at sampled dipoles (eps_abs), the roofline of the
-dominant kernel, and the CPU oracle timed on a bounded sample of the recipe.
+dominant kernel, and the CPU oracle timed on the same workload (configuration 0).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere]
                        [--skip-cpu] [--skip-fp64] [--calib-copy]
@@ -54,17 +54,83 @@ def workload(args, inputs):
         pos, box = inputs.ferrofluid(n, 2001)
         m = inputs.random_moments(n, 2002)[None]
         return dict(name="ferrofluid_rsa_%d" % n, pos=pos, box=box, m=m, order=args.order or 6,
-                    theta=args.theta, sample=lambda k: inputs.ferrofluid(k, 2001)[0],
-                    sample_m=lambda k: inputs.random_moments(k, 2002), sample_n=1 << 17)
+                    theta=args.theta)
     if args.workload == "sphere":
         n = args.n or (1 << 18)
         nb = args.batch or 64
         pos, box = inputs.sphere_cut(n, 80)
         m = inputs.aligned_moments(n, nb, 3000)
         return dict(name="sphere_%d_of_80cube_x%d" % (n, nb), pos=pos, box=box, m=m, order=args.order or 5,
-                    theta=args.theta, sample=lambda k: inputs.sphere_cut(k, 80)[0],
-                    sample_m=lambda k: inputs.aligned_moments(k, 1, 3000)[0], sample_n=1 << 16)
+                    theta=args.theta)
     raise SystemExit("unknown workload " + args.workload)
+
+
+# Algorithmic work per pass (what the method must read, write and compute,
+# not what the kernels happen to move):
+#  p2m      m (FP64, 24 B) + position (FP32 leaf-relative, 12 B) per dipole
+#           and configuration; write Q (4 B x NS) per leaf and configuration;
+#           2 * 3 * NP flop per dipole and configuration
+#  m2m/l2l  read and write one expansion (4 B x NS) per cell and configuration
+#  m2l      read Q and write V once per cell and configuration, one FP32
+#           derivative tensor per distinct offset is ignored (< 1 %);
+#           2 NP^2 flop per (pair, configuration)
+#  p2p_l2p  position 12 B + moment 12 B per dipole (sources counted once),
+#           V per leaf, FP64 field 24 B written per dipole and configuration;
+#           30 flop per (pair, configuration) on the VALU form: 3 differences,
+#           5 for r^2, 1 reciprocal square root, 2 for r^-2 and r^-3, 5 for
+#           m.r, 2 for 3 (m.r) r^-2, 12 for the three components (FMA = 2);
+#           18 per (pair, configuration) on the batched matrix-core form
+def pass_work(info, n, nb, order):
+    NP = (order + 1) * (order + 2) * (order + 3) // 6 - 1
+    NS = (NP + 3) // 4 * 4
+    leaves, cells = info["n_leaves"], info["n_cells"]
+    pairs = info["n_p2p_pairs"]
+    batched = nb >= 32
+    exp_b = 4.0 * NS * nb
+    out = {
+        "p2m": {"kernel": "k_permute_moments+k_p2m<float,%d>" % order, "bound": "hbm",
+                "bytes": n * nb * 24.0 + n * 12.0 + leaves * exp_b, "flops": 6.0 * NP * n * nb},
+        "m2m": {"kernel": "k_m2m<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
+        "m2l": {"kernel": "k_m2l<float,%d>" % order if info["m2l_variant"] == 0 else "k_m2l_wave<float,%d>" % order,
+                "bound": "mfma", "bytes": 2.0 * cells * exp_b, "flops": info["m2l_flops_per_config"] * nb},
+        "l2l": {"kernel": "k_l2l<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
+        "p2p_l2p": {"kernel": ("k_p2p_batched<float>+k_l2p_batched" if batched else "k_p2p_l2p<float,%d>" % order),
+                    "bound": "mfma" if batched else "alu",
+                    "bytes": n * 24.0 + leaves * exp_b + n * nb * 24.0,
+                    "flops": (18.0 if batched else 30.0) * pairs * nb},
+    }
+    for v in out.values():
+        v["peak"] = PEAK_FP32_MFMA if v["bound"] == "mfma" else PEAK_FP32_VALU
+    return out
+
+
+def csrc_digest():
+    """SHA-256 over the kernel sources (names and bytes, sorted)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_0810_0233_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(kernel, workload_name):
+    """HBM bytes per launch from the committed counter record, or None when
+    the record is missing, is for another workload, or the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("workload") != workload_name or rec.get("csrc_sha256") != csrc_digest():
+        return None
+    return k.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -176,43 +242,39 @@ def main():
         out["eps_abs_fp64"] = rel_rms(H64[0][idx], H_direct)
     log("eps_abs mixed %.3e" % out["eps_abs_mixed"])
 
-    # ---- roofline of the dominant kernel (HIP events on the launch stream)
-    m2l_flops = info["m2l_flops_per_config"] * nb
-    pairs = info["n_p2p_pairs"] * nb
-    batched = nb >= 32
-    # per pair and configuration: 20 flop on the VALU form (3 sub, 3 for r^2,
-    # 3 for m.r, 4 mul, 6 FMA); 18 flop of matrix product on the batched form
-    p2p_flops = (18.0 if batched else 20.0) * pairs
-    if pt["m2l"] >= pt["p2p_l2p"]:
-        ach = m2l_flops / (pt["m2l"] * 1e-3)
-        roof = {"kernel": "k_m2l<float,%d>" % order, "bound": "mfma", "achieved": ach / 1e12,
-                "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": None}
-    else:
-        ach = p2p_flops / (pt["p2p_l2p"] * 1e-3)
-        if batched:
-            roof = {"kernel": "k_p2p_batched<float>+k_l2p_batched", "bound": "mfma", "achieved": ach / 1e12,
-                    "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": None}
-        else:
-            roof = {"kernel": "k_p2p_l2p<float,%d>" % order, "bound": "alu", "achieved": ach / 1e12,
-                    "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VALU, "traffic": None}
-    out["m2l_tflops"] = m2l_flops / (pt["m2l"] * 1e-3) / 1e12
-    out["p2p_tflops"] = p2p_flops / (pt["p2p_l2p"] * 1e-3) / 1e12
+    # ---- per-pass algorithmic work and the roofline of the dominant kernel
+    # (times: HIP events recorded by the library on the launch stream)
+    kern = pass_work(info, n, nb, order)
+    for k, v in kern.items():
+        sec = pt[k] * 1e-3
+        v["ms"] = pt[k]
+        v["gb_s"] = v["bytes"] / sec / 1e9
+        v["hbm_frac"] = v["bytes"] / sec / PEAK_HBM
+        if v["flops"]:
+            v["tflop_s"] = v["flops"] / sec / 1e12
+            v["flop_frac"] = v["flops"] / sec / v["peak"]
+    dom = "m2l" if pt["m2l"] >= pt["p2p_l2p"] else "p2p_l2p"
+    d = kern[dom]
+    ach = d["flops"] / (pt[dom] * 1e-3)
+    roof = {"kernel": d["kernel"], "bound": d["bound"], "achieved": ach / 1e12, "peak": d["peak"] / 1e12,
+            "unit": "TFLOP/s", "frac": ach / d["peak"],
+            "traffic": counted_traffic(d["kernel"], W["name"])}
+    out["kernels"] = {k: {q: v[q] for q in v if q != "peak"} for k, v in kern.items()}
 
-    # ---- CPU oracle on a bounded sample of the same recipe
+    # ---- CPU oracle on the same workload (one configuration)
     cpu = None
     if not args.skip_cpu:
         import oracle
 
-        ns = W["sample_n"]
-        spos = W["sample"](ns)
-        sm = W["sample_m"](ns)
+        # the whole workload, configuration 0 (about 10-15 s of CPU work at p = 6)
+        ns = n
         threads = min(os.cpu_count() or 1, 16)
         t = time.perf_counter()
-        oracle.fmm(spos, sm, order, theta, box=None if args.workload != "sphere" else box, nthreads=threads)
+        oracle.fmm(pos, m[0], order, theta, box=box, nthreads=threads)
         dt = time.perf_counter() - t
         cpu = {"value": ns / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-               "sample": "FP64 recursive CPU FMM (same p, theta, s rule), one configuration of the same recipe "
-                         "at n=%d, %.1f s" % (ns, dt)}
+               "sample": "FP64 recursive CPU FMM (same p, theta, s rule and root box) on the whole workload, "
+                         "configuration 0 only (n=%d), %.1f s" % (ns, dt)}
         log("cpu oracle: %.3e evals/s on %d threads" % (ns / dt, threads))
 
     res = {
