@@ -4,11 +4,15 @@
 // at zero separation skipped), accumulated in FP64 and written in the
 // caller's dipole order.
 //
-// One wavefront per chunk of <= 64 dipoles of one smallest cell.  A chunk of
-// c dipoles gets G = 64 / pow2ceil(c) lanes per dipole; the lanes of a dipole
-// split the sources, and their partial fields are combined with cross-lane
-// butterflies at the end.  Sources are staged 64 at a time in LDS, shifted by
-// the integer offset of their cell so all coordinates stay cell-relative.
+// One wavefront per chunk of <= 64 dipoles of one smallest cell.  The c
+// dipoles of a chunk are split as c = a + b (a the largest power of two <= c):
+// the first a get G1 = 64/a lanes each, the other b get G2 = 64/pow2ceil(b)
+// lanes each, so every lane works in both roles whatever c is.  The lanes of
+// a dipole split the sources, and their partial fields are combined with
+// cross-lane butterflies at the end.  Sources are staged 64 at a time in LDS
+// (shifted by the integer offset of their cell so all coordinates stay
+// cell-relative), padded with null sources (zero moment, far away) that add
+// exactly zero, so every lane runs the same trip count.
 #include <type_traits>
 
 #include "mfma.hpp"
@@ -56,77 +60,66 @@ struct P2PArgs {
   const int32_t* leaf_p;     // per-cell local order (compact leaves), or null
 };
 
+// One staged source: position (cell-relative, shifted to the target cell) and
+// moment, padded to 8 elements so a lane reads it with two 16-byte loads.
+template <typename T>
+struct alignas(8 * sizeof(T)) P2PSrc {
+  T x, y, z, mx, my, mz, p0, p1;
+};
+
+// One source on one target: f += (3 (m.r) r / r^2 - m) / r^3, written as
+// inv3 * (k r - m) with k = 3 (m.r) / r^2.  Only the target's own cell can
+// hold a source at zero separation (a position determines its cell), so only
+// that cell pays for the test.
+template <typename T, bool kSelf>
+__device__ __forceinline__ void p2p_pair(const P2PSrc<T>& s, T tx, T ty, T tz, T& fx, T& fy, T& fz) {
+  const T rx = tx - s.x, ry = ty - s.y, rz = tz - s.z;
+  const T r2 = rx * rx + ry * ry + rz * rz;
+  T inv = rsqrt_t<T>(r2);
+  if (kSelf) inv = (r2 > (T)0) ? inv : (T)0;
+  const T inv2 = inv * inv;
+  const T inv3 = inv2 * inv;
+  const T mr = s.mx * rx + s.my * ry + s.mz * rz;
+  const T k = ((T)3 * inv2) * mr;
+  fx += inv3 * (k * rx - s.mx);
+  fy += inv3 * (k * ry - s.my);
+  fz += inv3 * (k * rz - s.mz);
+}
+
+// K sources q = sub, sub + G, ... of the staged batch for one target.
+template <typename T, int G, bool kSelf>
+__device__ __forceinline__ void p2p_run(const P2PSrc<T>* __restrict__ src, int sub, int K, T tx, T ty, T tz, T& fx,
+                                        T& fy, T& fz) {
+  const P2PSrc<T>* q = src + sub;
+  int k = 0;
+  for (; k + 4 <= K; k += 4, q += 4 * G) {
+#pragma unroll
+    for (int u = 0; u < 4; u++) p2p_pair<T, kSelf>(q[u * G], tx, ty, tz, fx, fy, fz);
+  }
+  for (; k < K; k++, q += G) p2p_pair<T, kSelf>(q[0], tx, ty, tz, fx, fy, fz);
+}
+
+template <typename T, bool kSelf>
+__device__ __forceinline__ void p2p_role(const P2PSrc<T>* __restrict__ src, int G, int sub, int nsrc, T tx, T ty,
+                                         T tz, T& fx, T& fy, T& fz) {
+  const int K = (nsrc + G - 1) / G;
+  switch (G) {
+    case 1: p2p_run<T, 1, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+    case 2: p2p_run<T, 2, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+    case 4: p2p_run<T, 4, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+    case 8: p2p_run<T, 8, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+    case 16: p2p_run<T, 16, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+    case 32: p2p_run<T, 32, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+    default: p2p_run<T, 64, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+  }
+}
+
+// Smooth field of one dipole from its cell's local expansion,
+// H_a = -sum_{|k| <= pl-1} Vt_{k+e_a} yt^k / k!, plus the near field.
 template <typename T, int P>
-__global__ void __launch_bounds__(64 * kP2PWaves) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
-                                                           const T* __restrict__ msort, const T* __restrict__ V,
-                                                           double* __restrict__ H) {
-  constexpr int NP = nact(P);
-  constexpr int NS = nstride(P);
+__device__ __forceinline__ void l2p_write(const T* __restrict__ v, int pl, T yx, T yy, T yz, double hx, double hy,
+                                          double hz, double s3, double* __restrict__ Ho) {
   constexpr int NM = ncoef(P - 1);
-  __shared__ T sx[kP2PWaves][64], sy[kP2PWaves][64], sz[kP2PWaves][64];
-  __shared__ T smx[kP2PWaves][64], smy[kP2PWaves][64], smz[kP2PWaves][64];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * kP2PWaves + w;
-  const int b = blockIdx.y;
-  if (item >= a.nchunks) return;
-  const P2PChunk ch = a.chunks[item];
-  const int n = (int)a.n;
-  int cpow = 1;
-  while (cpow < ch.count) cpow <<= 1;
-  const int G = 64 / cpow;
-  const int t = lane / G, sub = lane % G;
-  const bool active = t < ch.count;
-  const int64_t i = ch.first + (active ? t : 0);
-  const T yx = y[i], yy = y[n + i], yz = y[2 * n + i];
-  const T* mb = msort + (int64_t)b * 3 * n;
-  const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
-  double hx = 0.0, hy = 0.0, hz = 0.0;  // near field, cell-relative units
-  for (int e = a.near_ptr[ch.leaf]; e < a.near_ptr[ch.leaf + 1]; e++) {
-    const int S = a.near_idx[e];
-    const T ox = (T)((a.coord[3 * S] - cx) * a.g[0]);
-    const T oy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
-    const T oz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
-    const int s0 = a.lstart[S], sn = a.lcount[S];
-    T fx = (T)0, fy = (T)0, fz = (T)0;
-    for (int base = 0; base < sn; base += 64) {
-      const int nsrc = min(64, sn - base);
-      if (lane < nsrc) {
-        const int64_t j = s0 + base + lane;
-        sx[w][lane] = y[j] + ox;
-        sy[w][lane] = y[n + j] + oy;
-        sz[w][lane] = y[2 * n + j] + oz;
-        smx[w][lane] = mb[j];
-        smy[w][lane] = mb[n + j];
-        smz[w][lane] = mb[2 * n + j];
-      }
-      wave_lds_sync();
-      for (int q = sub; q < nsrc; q += G) {
-        const T rx = yx - sx[w][q], ry = yy - sy[w][q], rz = yz - sz[w][q];
-        const T r2 = rx * rx + ry * ry + rz * rz;
-        const T inv = (r2 > (T)0) ? rsqrt_t<T>(r2) : (T)0;
-        const T inv2 = inv * inv;
-        const T inv3 = inv2 * inv;
-        const T mr = smx[w][q] * rx + smy[w][q] * ry + smz[w][q] * rz;
-        const T c = (T)3 * mr * inv2 * inv3;
-        fx += c * rx - inv3 * smx[w][q];
-        fy += c * ry - inv3 * smy[w][q];
-        fz += c * rz - inv3 * smz[w][q];
-      }
-      wave_lds_sync();
-    }
-    hx += (double)fx;
-    hy += (double)fy;
-    hz += (double)fz;
-  }
-  // combine the G lanes of each dipole
-  for (int off = 1; off < G; off <<= 1) {
-    hx += __shfl_xor(hx, off);
-    hy += __shfl_xor(hy, off);
-    hz += __shfl_xor(hz, off);
-  }
-  if (!active || sub != 0) return;
-  // smooth field from the local expansion: H_a = -sum_k Vt_{k+e_a} yt^k/k!
-  const T* v = V + a.voff + ((int64_t)ch.leaf * a.nb + b) * NS;
   T px[P], py[P], pz[P];
   px[0] = py[0] = pz[0] = (T)1;
 #pragma unroll
@@ -136,23 +129,115 @@ __global__ void __launch_bounds__(64 * kP2PWaves) k_p2p_l2p(P2PArgs a, const T* 
     py[j] = py[j - 1] * yy * inv;
     pz[j] = pz[j - 1] * yz * inv;
   }
-  // a smallest cell with its own order p_l keeps |n| <= p_l, i.e. |k| <= p_l - 1
-  const int pl = a.leaf_p ? a.leaf_p[ch.leaf] : P;
   T ex = (T)0, ey = (T)0, ez = (T)0;
-#pragma unroll
+#pragma unroll 4
   for (int k = 0; k < NM; k++) {
     const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
+    // a smallest cell with its own order pl keeps |n| <= pl, i.e. |k| <= pl - 1
     const T mono = (kx + ky + kz < pl) ? px[kx] * py[ky] * pz[kz] : (T)0;
     ex += v[midx(kx + 1, ky, kz) - 1] * mono;
     ey += v[midx(kx, ky + 1, kz) - 1] * mono;
     ez += v[midx(kx, ky, kz + 1) - 1] * mono;
   }
-  (void)NP;
+  Ho[0] = s3 * (hx - (double)ex);
+  Ho[1] = s3 * (hy - (double)ey);
+  Ho[2] = s3 * (hz - (double)ez);
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
+                                                           const T* __restrict__ msort, const T* __restrict__ V,
+                                                           double* __restrict__ H) {
+  constexpr int NS = nstride(P);
+  __shared__ P2PSrc<T> sS[kP2PWaves][64];
+  // the wave index is uniform: say so, so chunk data, counts and loop bounds
+  // live in scalar registers and branch on scalar conditions
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+  // range of chunks, so neighbouring cells (shared sources) share an L2
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  const int64_t blk = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  const int64_t item = blk * kP2PWaves + w;
+  const int b = blockIdx.y;
+  if (item >= a.nchunks) return;
+  const P2PChunk ch = a.chunks[item];
+  const int n = (int)a.n;
+  const int c = ch.count;
+  int A = 1;
+  while (2 * A <= c) A <<= 1;
+  const int B = c - A;
+  int bp = 1;
+  while (bp < B) bp <<= 1;
+  const int G1 = 64 / A, G2 = 64 / bp;
+  const int t1 = lane / G1, sub1 = lane % G1;
+  const int t2 = A + lane / G2, sub2 = lane % G2;
+  const bool act2 = B > 0 && t2 < c;
+  const int64_t i1 = ch.first + t1, i2 = ch.first + (act2 ? t2 : 0);
+  const T x1 = y[i1], y1 = y[n + i1], z1 = y[2 * n + i1];
+  const T x2 = y[i2], y2 = y[n + i2], z2 = y[2 * n + i2];
+  const T* mb = msort + (int64_t)b * 3 * n;
+  const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
+  P2PSrc<T>* src = sS[w];
+  double hx1 = 0.0, hy1 = 0.0, hz1 = 0.0, hx2 = 0.0, hy2 = 0.0, hz2 = 0.0;  // near field, cell-relative units
+  for (int e = a.near_ptr[ch.leaf]; e < a.near_ptr[ch.leaf + 1]; e++) {
+    const int S = a.near_idx[e];
+    const bool self = S == ch.leaf;
+    const T ox = (T)((a.coord[3 * S] - cx) * a.g[0]);
+    const T oy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
+    const T oz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
+    const int s0 = a.lstart[S], sn = a.lcount[S];
+    T fx1 = (T)0, fy1 = (T)0, fz1 = (T)0, fx2 = (T)0, fy2 = (T)0, fz2 = (T)0;
+    for (int base = 0; base < sn; base += 64) {
+      const int nsrc = min(64, sn - base);
+      P2PSrc<T> q;
+      if (lane < nsrc) {
+        const int64_t j = s0 + base + lane;
+        q.x = y[j] + ox;
+        q.y = y[n + j] + oy;
+        q.z = y[2 * n + j] + oz;
+        q.mx = mb[j];
+        q.my = mb[n + j];
+        q.mz = mb[2 * n + j];
+      } else {  // null source: zero moment, far from every target
+        q.x = q.y = q.z = (T)1e4;
+        q.mx = q.my = q.mz = (T)0;
+      }
+      q.p0 = q.p1 = (T)0;
+      src[lane] = q;
+      wave_lds_sync();
+      if (self) {
+        p2p_role<T, true>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
+        if (B > 0) p2p_role<T, true>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
+      } else {
+        p2p_role<T, false>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
+        if (B > 0) p2p_role<T, false>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
+      }
+      wave_lds_sync();
+    }
+    hx1 += (double)fx1;
+    hy1 += (double)fy1;
+    hz1 += (double)fz1;
+    hx2 += (double)fx2;
+    hy2 += (double)fy2;
+    hz2 += (double)fz2;
+  }
+  // combine the lanes of each dipole (they are contiguous: lane = t G + sub)
+  for (int off = 1; off < G1; off <<= 1) {
+    hx1 += __shfl_xor(hx1, off);
+    hy1 += __shfl_xor(hy1, off);
+    hz1 += __shfl_xor(hz1, off);
+  }
+  for (int off = 1; off < G2; off <<= 1) {
+    hx2 += __shfl_xor(hx2, off);
+    hy2 += __shfl_xor(hy2, off);
+    hz2 += __shfl_xor(hz2, off);
+  }
+  const T* v = V + a.voff + ((int64_t)ch.leaf * a.nb + b) * NS;
+  const int pl = a.leaf_p ? a.leaf_p[ch.leaf] : P;
   const double s3 = a.inv_s3;
-  const int64_t o = ((int64_t)b * n + a.perm[i]) * 3;
-  H[o] = s3 * (hx - (double)ex);
-  H[o + 1] = s3 * (hy - (double)ey);
-  H[o + 2] = s3 * (hz - (double)ez);
+  if (sub1 == 0) l2p_write<T, P>(v, pl, x1, y1, z1, hx1, hy1, hz1, s3, H + ((int64_t)b * n + a.perm[i1]) * 3);
+  if (act2 && sub2 == 0)
+    l2p_write<T, P>(v, pl, x2, y2, z2, hx2, hy2, hz2, s3, H + ((int64_t)b * n + a.perm[i2]) * 3);
 }
 
 // ------------------------------------------------------------ batched form
