@@ -461,7 +461,9 @@ static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const 
       P.precision = prm->precision;
       P.nbmax = prm->max_batch;
       P.class_bits = prm->m2l_class_bits < 0 ? 3 : std::min(prm->m2l_class_bits, 12);
-      P.m2l_variant = (prm->m2l_variant == kM2LWave && prm->order <= 6) ? kM2LWave : kM2LBlock;
+      P.m2l_variant = m2l_variant_ok(prm->m2l_variant, prm->order, prm->precision == CCFMM_PREC_FP64)
+                          ? prm->m2l_variant
+                          : kM2LBlock;
       P.use_graph = prm->use_graph != 0;
       if (own) {
         CCFMM_HIP(hipStreamCreateWithFlags(&P.own_stream, hipStreamNonBlocking));
@@ -601,10 +603,10 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
     CCFMM_HIP(hipEventCreate(&e0));
     CCFMM_HIP(hipEventCreate(&e1));
     std::vector<ccfmm_tune_entry> res;
-    const int variants[2] = {kM2LBlock, kM2LWave};
+    const int variants[4] = {kM2LBlock, kM2LWave, kM2LWide4, kM2LWide2};
     const int bits[3] = {0, 3, 6};
     for (int v : variants) {
-      if (v == kM2LWave && P.p > 6) continue;
+      if (!m2l_variant_ok(v, P.p, P.precision == CCFMM_PREC_FP64)) continue;
       for (int cb : bits) {
         P.m2l_variant = v;
         P.class_bits = cb;

@@ -26,7 +26,18 @@ constexpr int kKMax = 2 * kPMax;  // derivative tensors up to order 2p
 // independent wavefronts gathering operator entries themselves (16)
 constexpr int kM2LBlock = 0;
 constexpr int kM2LWave = 1;
-inline int m2l_tile_cols(int variant) { return variant == kM2LWave ? 16 : 64; }
+constexpr int kM2LWide4 = 2;  // FP32, 256-column tiles
+constexpr int kM2LWide2 = 3;  // FP32, 128-column tiles
+inline int m2l_tile_cols(int variant) {
+  return variant == kM2LWave ? 16 : variant == kM2LWide4 ? 256 : variant == kM2LWide2 ? 128 : 64;
+}
+// whether an M2L kernel variant exists for this order and precision
+inline bool m2l_variant_ok(int variant, int order, bool fp64) {
+  if (variant == kM2LBlock) return true;
+  if (variant == kM2LWave) return order <= 6;
+  if (variant == kM2LWide4 || variant == kM2LWide2) return order <= 6 && !fp64;
+  return false;
+}
 
 // configurations per M2L tile for a batch of nb: the next power of two, at
 // most one tile width

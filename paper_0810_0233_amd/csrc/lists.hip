@@ -337,6 +337,13 @@ __global__ void k_tile_tgt(int32_t nc, int32_t ng, int TC, const int32_t* order,
   tgt[i] = (i < nc) ? order[i] : -1;
 }
 
+__global__ void k_tile_keys(int64_t ntiles, const M2LTile* tiles, uint32_t* key, int32_t* ord) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntiles) return;
+  key[i] = 0xffffu - (uint32_t)min(tiles[i].nsteps, 0xffff);
+  ord[i] = (int32_t)i;
+}
+
 void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   const int L = P.L;
   const int T = 256;
@@ -433,6 +440,17 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
                                                   tiles, D.tile0);
     CCFMM_HIP(hipGetLastError());
     tgt_base += (int64_t)D.ngroups * TC;
+  }
+  // launch order: longest step lists first, so the dispatcher's greedy,
+  // round-robin placement balances the XCDs and their compute units
+  if (ntiles > 0) {
+    int32_t* ord = reinterpret_cast<int32_t*>(P.tile_order.ensure(sizeof(int32_t) * 4 * ntiles));
+    uint32_t* key = reinterpret_cast<uint32_t*>(ord + ntiles);
+    int32_t* ord2 = ord + 2 * ntiles;
+    uint32_t* key2 = reinterpret_cast<uint32_t*>(ord + 3 * ntiles);
+    k_tile_keys<<<ceil_div(ntiles, T), T, 0, st>>>(ntiles, tiles, key, ord);
+    CCFMM_HIP(hipGetLastError());
+    radix_sort_pairs(key, ord, key2, ord2, ntiles, 16, P.scratch, st);
   }
 }
 

@@ -59,7 +59,7 @@ __device__ __forceinline__ int op_index(int m, int k) {
 }
 
 template <typename T, int P>
-__global__ void __launch_bounds__(256, (sizeof(T) == 4 && P <= 6) ? 2 : 1) k_m2l(const M2LTile* __restrict__ tiles, int64_t ntiles,
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && P <= 6) ? 2 : 1) k_m2l(const M2LTile* __restrict__ tiles, const int32_t* __restrict__ tile_order, int64_t ntiles,
                                              const int32_t* __restrict__ tile_tgt,
                                              const int32_t* __restrict__ step_delta,
                                              const int32_t* __restrict__ step_src, const T* __restrict__ Dtab,
@@ -73,13 +73,9 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && P <= 6) ? 2 : 1) k_m2l
   __shared__ T sQ[4 * KS * QST];
 
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-  // range of tiles so neighbouring tiles (shared sources) share an L2
-  const int nblk = gridDim.x;
-  const int bid = blockIdx.x;
-  const int64_t tile = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
-  if (tile >= ntiles) return;
-  const M2LTile tl = tiles[tile];
+  // tiles are launched longest first (greedy balance over the compute units)
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const M2LTile tl = tiles[tile_order[blockIdx.x]];
   const T* Ql = Q + lo.qoff[tl.level];
 
   // this thread's operator entries (step independent): (chunk, r) -> index
@@ -205,7 +201,8 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && P <= 6) ? 2 : 1) k_m2l
 // every MFMA A operand is a single LDS gather from the step's 455-entry tensor.
 // Used for orders up to 6 (the index registers grow as p^6).
 template <typename T, int P>
-__global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__ tiles, int64_t ntiles,
+__global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__ tiles,
+                                                  const int32_t* __restrict__ tile_order, int64_t ntiles,
                                                   const int32_t* __restrict__ tile_tgt,
                                                   const int32_t* __restrict__ step_delta,
                                                   const int32_t* __restrict__ step_src, const T* __restrict__ Dtab,
@@ -219,9 +216,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
   __shared__ T sD[4][ND + 1];
   __shared__ T sQ[4][KS * QST];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nblk = gridDim.x, bid = blockIdx.x;
-  const int64_t blk = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
-  const int64_t tile = blk * 4 + w;
+  const int64_t slot = (int64_t)blockIdx.x * 4 + w;
   // operator index of (ks, mb, lane), read back as 64 consecutive u16 per wave
   __shared__ uint16_t sIdx[NI * 64];
   for (int e = threadIdx.x; e < NI * 64; e += 256) {
@@ -230,8 +225,8 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
     sIdx[e] = (uint16_t)op_index<P>(16 * mb + (l & 15), 4 * ks + (l >> 4));
   }
   __syncthreads();
-  if (tile >= ntiles) return;
-  const M2LTile tl = tiles[tile];
+  if (slot >= ntiles) return;
+  const M2LTile tl = tiles[tile_order[slot]];
   const T* Ql = Q + lo.qoff[tl.level];
   using AccT = typename Acc<T>::type;
   AccT acc[MB];
@@ -320,23 +315,207 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
   }
 }
 
+// Wide variant (FP32, orders <= 6): a block of four wavefronts owns a tile of
+// 4 x 16 CB columns (16 CB per wavefront); each wavefront keeps MB x CB accumulator blocks, so every
+// operator fragment it reads from LDS feeds CB matrix products.  The contraction
+// index is permuted so lane group kq = lane / 16 holds k = kq KS + ks: a lane's
+// B fragments for one column are then KS consecutive words of Q, loaded
+// straight from memory into registers one step ahead.  The operator of the next
+// step is gathered from the derivative tensor in memory straight into the other
+// half of a double-buffered LDS array (global-to-LDS loads, no registers) while
+// the current step's products run, so each step needs a single block barrier
+// and two blocks fit on a compute unit.
+// Zeros read by empty columns and padding operator entries: selecting an
+// address instead of a loaded value keeps the loads free of consumers until
+// the products that need them.
+__device__ const float g_zero_row[128] = {};
+
+template <int P>
+__device__ __forceinline__ int op_index_kperm(int m, int kq, int ks) {
+  constexpr int KS = nstride(P) / 4;
+  return op_index<P>(m, kq * KS + ks);
+}
+
+template <int P, int CB>
+__global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile* __restrict__ tiles,
+                                                   const int32_t* __restrict__ tile_order, int64_t ntiles,
+                                                   const int32_t* __restrict__ tile_tgt,
+                                                   const int32_t* __restrict__ step_delta,
+                                                   const int32_t* __restrict__ step_src,
+                                                   const float* __restrict__ Dtab, const float* __restrict__ Q,
+                                                   float* __restrict__ V, LevelOffsets lo, int nb, int TB, int TC) {
+  constexpr int NP = nact(P), NS = nstride(P), KS = NS / 4, MB = (NP + 15) / 16, ND = ncoef(2 * P);
+  constexpr int NE = MB * KS * 64;       // operator entries in fragment order
+  constexpr int ER = (NE + 255) / 256;   // per thread
+  __shared__ float sT[2][ER * 256];  // padded so every thread stores unconditionally
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  // tiles are launched longest first (greedy balance over the compute units)
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const M2LTile tl = tiles[tile_order[blockIdx.x]];
+  const float* Ql = Q + lo.qoff[tl.level];
+  const int nsteps = tl.nsteps;
+
+  // this thread's operator entries e = t + 256 r: derivative-tensor index or ND (zero)
+  uint32_t eidx[(ER + 1) / 2];  // two 16-bit indices per register
+#pragma unroll
+  for (int r = 0; r < (ER + 1) / 2; r++) eidx[r] = 0;
+#pragma unroll
+  for (int r = 0; r < ER; r++) {
+    const int e = t + 256 * r;
+    int v = ND;
+    if (e < NE) {
+      const int mb = e / (KS * 64), ks = (e / 64) % KS, l = e % 64;
+      v = op_index_kperm<P>(16 * mb + (l & 15), l >> 4, ks);
+    }
+    eidx[r >> 1] |= (uint32_t)v << (16 * (r & 1));
+  }
+  // this lane's columns: 16 CB w + 16 cb + lane % 16, fragment rows kq KS .. kq KS + KS - 1
+  const int kq = lane >> 4;
+  int ctc[CB], cb_b[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; cb++) {
+    const int col = 16 * CB * w + 16 * cb + (lane & 15);
+    ctc[cb] = col / TB;
+    cb_b[cb] = tl.b0 + col % TB;
+    if (!(ctc[cb] < TC && cb_b[cb] < nb)) ctc[cb] = -1;
+  }
+  // Loads are unconditional: an empty column or a padding operator entry reads
+  // g_zero_row through a selected address, so no loaded value has a consumer
+  // before the products that need it and the loads stay in flight meanwhile.
+  auto load_src = [&](int s, int (&src)[CB]) {
+    const int64_t st = (int64_t)tl.step0 + s;
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) src[cb] = step_src[st * TC + (ctc[cb] >= 0 ? ctc[cb] : 0)];
+  };
+  auto load_b = [&](const int (&src)[CB], float (&B)[CB][KS]) {
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) {
+      const bool ok = ctc[cb] >= 0 && src[cb] >= 0;
+      const float* q = ok ? Ql + ((int64_t)src[cb] * nb + cb_b[cb]) * NS + kq * KS : g_zero_row;
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) B[cb][ks] = q[ks];
+    }
+  };
+  // the operator of step s goes from memory straight into sT[buf] (no
+  // registers): lane l of wavefront w writes entry 256 r + 64 w + l
+  auto load_op = [&](int s, int buf) {
+    const float* drow = Dtab + (int64_t)step_delta[tl.step0 + s] * ND;
+#pragma unroll
+    for (int r = 0; r < ER; r++) {
+      const int ix = (eidx[r >> 1] >> (16 * (r & 1))) & 0xffff;
+      const float* g = ix < ND ? drow + ix : g_zero_row;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                       (__attribute__((address_space(3))) void*)&sT[buf][256 * r + 64 * w], 4, 0,
+                                       0);
+    }
+  };
+  // all of this wavefront's memory loads have landed (vmcnt = 0)
+  auto wait_loads = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
+
+  f32x4 acc[MB][CB];
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) acc[mb][cb] = f32x4{0, 0, 0, 0};
+
+  float B0[CB][KS], B1[CB][KS];
+  int srcA[CB], srcB[CB];
+  if (nsteps > 0) {
+    load_op(0, 0);
+    load_src(0, srcA);
+    load_b(srcA, B0);
+    if (nsteps > 1) load_src(1, srcB);
+  }
+  wait_loads();
+  __syncthreads();
+  // one step: products on sT[cur] x Bc while the next operator and B arrive
+  auto step = [&](int s, int cur, float (&Bc)[CB][KS], float (&Bn)[CB][KS], int (&srcN)[CB], int (&srcN2)[CB]) {
+    const bool more = s + 1 < nsteps;
+    if (more) {
+      load_op(s + 1, cur ^ 1);
+      load_b(srcN, Bn);
+      if (s + 2 < nsteps) load_src(s + 2, srcN2);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // issue the loads before the products
+    const float* T0 = sT[cur];
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++) {
+        const float a = T0[(mb * KS + ks) * 64 + lane];
+#pragma unroll
+        for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(a, Bc[cb][ks], acc[mb][cb]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    wait_loads();  // next operator in LDS, next B in registers
+    __syncthreads();
+  };
+  for (int s = 0; s < nsteps; s += 2) {
+    step(s, 0, B0, B1, srcB, srcA);
+    if (s + 1 < nsteps) step(s + 1, 1, B1, B0, srcA, srcB);
+  }
+  // write: lane holds rows 16 mb + 4 kq + r of column 16 CB w + 16 cb + lane % 16
+#pragma unroll
+  for (int cb = 0; cb < CB; cb++) {
+    if (ctc[cb] < 0) continue;
+    const int tgt = tile_tgt[tl.tgt0 + ctc[cb]];
+    if (tgt < 0) continue;
+    float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NS;
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int m = 16 * mb + acc_row<float>(kq, r);
+        if (m < NS) {
+          float v = 0.f;
+          if (m < NP) {
+            const int f = m + 1;
+            const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
+            v = (deg & 1) ? -acc[mb][cb][r] : acc[mb][cb][r];
+          }
+          out[m] = v;
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int PP>
 static void m2l_impl(Plan& P, int nb, hipStream_t st) {
   LevelOffsets lo{};
   for (int l = 0; l <= P.L; l++) lo.qoff[l] = P.lev[l]->qoff;
   const T* D = std::is_same<T, double>::value ? (const T*)P.Dd.p : (const T*)P.Df.p;
   if (P.ntiles == 0) return;
+  if constexpr (std::is_same<T, float>::value && PP <= 6) {
+    if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2) {
+      const int64_t nblk = P.ntiles;
+      if (P.tiles_variant == kM2LWide4)
+        k_m2l_wide<PP, 4><<<(unsigned)nblk, 256, 0, st>>>(
+            P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),
+            P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
+      else
+        k_m2l_wide<PP, 2><<<(unsigned)nblk, 256, 0, st>>>(
+            P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),
+            P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
+      CCFMM_HIP(hipGetLastError());
+      return;
+    }
+  }
+  if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2)
+    fail(CCFMM_EINVAL, "wide M2L variants need mixed precision and order <= 6");
   if (P.tiles_variant == kM2LWave) {
     if constexpr (PP <= 6) {
       k_m2l_wave<T, PP><<<ceil_div(P.ntiles, 4), 256, 0, st>>>(
-          P.tiles.as<M2LTile>(), P.ntiles, P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),
+          P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),
           P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
       CCFMM_HIP(hipGetLastError());
       return;
     }
     fail(CCFMM_EINVAL, "wavefront M2L variant supports orders up to 6");
   }
-  k_m2l<T, PP><<<(unsigned)P.ntiles, 256, 0, st>>>(P.tiles.as<M2LTile>(), P.ntiles, P.tile_tgt.as<int32_t>(),
+  k_m2l<T, PP><<<(unsigned)P.ntiles, 256, 0, st>>>(P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(),
                                                    P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), D,
                                                    P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
   CCFMM_HIP(hipGetLastError());

@@ -86,6 +86,7 @@ struct Plan {
   int m2l_variant = kM2LBlock;    // kernel used by run_m2l
   int tiles_variant = -1, tiles_class_bits = -1;  // what the current tiles were built for
   DevBuf tiles, tile_tgt, step_delta, step_src, bitmap, gcount;
+  DevBuf tile_order;  // launch order of the M2L tiles: longest step list first (+ sort temporaries)
   int64_t ntiles = 0, nsteps = 0;
   // P2P chunks (built on the device; their count stays in device memory)
   DevBuf chunks, chunk_cnt;

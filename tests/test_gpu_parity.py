@@ -204,7 +204,8 @@ def test_m2l_variants_and_autotune_agree(ref, precision):
     pos, box = inputs.ferrofluid(12000, 21)
     m = inputs.random_moments(12000, 22)
     base = None
-    for variant in (0, 1):
+    variants = (0, 1) if precision == ccfmm.PREC_FP64 else (0, 1, 2, 3)
+    for variant in variants:
         for cb in (0, 3, 6):
             H = plan_for(pos, 6, 0.5, 0.0, box, precision=precision, m2l_variant=variant,
                          m2l_class_bits=cb).eval(m)
@@ -220,13 +221,39 @@ def test_m2l_variants_and_autotune_agree(ref, precision):
     st = torch.cuda.current_stream().cuda_stream
     pl = plan_for(pos, 6, 0.5, 0.0, box, precision=precision)
     res = pl.autotune(1, d_m.data_ptr(), d_H.data_ptr(), st)
-    assert len(res) == 6 and all(r["m2l_ms"] > 0 for r in res)
+    assert len(res) == 3 * len(variants) and all(r["m2l_ms"] > 0 for r in res)
     inf = pl.info()
     best = min(res, key=lambda r: r["m2l_ms"])
     assert (inf["m2l_variant"], inf["m2l_class_bits"]) == (best["variant"], best["class_bits"])
     pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
     torch.cuda.synchronize()
     assert rel_rms(d_H.cpu().numpy(), base) <= (1e-14 if precision == ccfmm.PREC_FP64 else 1e-6)
+
+
+@pytest.mark.parametrize("order", [2, 4, 5, 6])
+def test_wide_m2l_variants(order):
+    """The wide FP32 M2L kernels (128- and 256-column tiles, permuted
+    contraction order) equal the block kernel for several orders and a batch
+    that splits tiles into (cell, configuration) columns; an FP64 plan asking
+    for them gets the block kernel."""
+    pos, box = inputs.ferrofluid(9000, 31 + order)
+    nb = 3
+    m = np.stack([inputs.random_moments(9000, 40 + order + b) for b in range(nb)])
+    H = {}
+    for variant in (0, 2, 3):
+        pl = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=nb, m2l_variant=variant,
+                      m2l_class_bits=3)
+        assert pl.info()["m2l_variant"] == variant
+        H[variant] = pl.eval(m)
+        pl.destroy()
+    errs = {v: rel_rms(H[v], H[0]) for v in (2, 3)}
+    print("order %d wide-vs-block %s" % (order, errs), flush=True)
+    for variant in (2, 3):
+        assert errs[variant] <= 1e-6
+    p64 = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_FP64, max_batch=nb, m2l_variant=2)
+    assert p64.info()["m2l_variant"] == 0
+    assert rel_rms(H[2], p64.eval(m)) <= MIXED_BAR
+    p64.destroy()
 
 
 @pytest.mark.parametrize("precision", [ccfmm.PREC_FP64, ccfmm.PREC_MIXED])
