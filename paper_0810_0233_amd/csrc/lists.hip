@@ -246,95 +246,177 @@ void build_lists(Plan& P, hipStream_t st) {
 // the same position inside their ancestors have the same set of far offsets,
 // so a tile of TC such cells shares one list of offsets.  The tile's steps are
 // the union of its cells' offsets; a cell without a source at that offset
-// gets a null column.
-__global__ void k_class_keys(const int32_t* key, int32_t nc, int cb, uint32_t* cls, int32_t* idx) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  cls[i] = (uint32_t)key[i] & ((1u << cb) - 1u);
-  idx[i] = i;
+// gets a null column.  All levels are tiled together: cells and target groups
+// are numbered globally (level by level), each kernel below runs once for
+// the whole tree and finds a cell's or a group's level in a small table.
+struct TileLevel {
+  const int32_t* key;       // compact -> key
+  const int32_t* far_ptr;   // far lists (null at the root level)
+  const int32_t* far_idx;
+  const int32_t* far_did;
+  int64_t cell0;            // first global cell of the level
+  int64_t g0;               // first global target group
+  int64_t bm0;              // first bitmap word
+  int64_t drow0;            // derivative-tensor row of dense offset id 0
+  int32_t nc;
+  int32_t words;            // bitmap words per group
+};
+struct TileLevels {
+  TileLevel lv[kLMax + 1];
+  int32_t nlev;
+  int32_t TC;
+};
+
+__device__ __forceinline__ int level_of_cell(const TileLevels& T, int64_t i) {
+  int l = 0;
+  while (l + 1 < T.nlev && i >= T.lv[l + 1].cell0) l++;
+  return l;
+}
+__device__ __forceinline__ int level_of_group(const TileLevels& T, int64_t b) {
+  int l = 0;
+  while (l + 1 < T.nlev && b >= T.lv[l + 1].g0) l++;
+  return l;
 }
 
-__global__ void k_inverse(const int32_t* order, int32_t nc, int32_t* inv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nc) inv[order[i]] = i;
+// sort key (level, low class bits of the cell key); the value is the global cell
+__global__ void k_tile_class_keys(TileLevels T, int64_t ncell, int cb, uint32_t* key, int32_t* val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const int l = level_of_cell(T, i);
+  const int cbl = min(cb, l);
+  const uint32_t cls = (uint32_t)T.lv[l].key[i - T.lv[l].cell0] & ((1u << cbl) - 1u);
+  key[i] = ((uint32_t)l << cb) | cls;
+  val[i] = (int32_t)i;
 }
 
-__global__ void __launch_bounds__(256) k_group_bitmap(int32_t nc, const int32_t* far_ptr, const int32_t* far_did,
-                                                      const int32_t* inv, int TC, int words, uint32_t* bitmap) {
-  const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= nc) return;
-  uint32_t* bm = bitmap + (int64_t)(inv[c] / TC) * words;
-  for (int e = far_ptr[c] + lane; e < far_ptr[c + 1]; e += 64) {
-    const int d = far_did[e];
-    atomicOr(&bm[d >> 5], 1u << (d & 31));
+__global__ void k_tile_inverse(const int32_t* sorted, int64_t ncell, int32_t* inv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncell) inv[sorted[i]] = (int32_t)i;
+}
+
+// One block per target group: the union of its cells' far offsets as a bitmap
+// over the level's offset box (built in LDS), the exclusive popcount prefix
+// over its words (a step's rank) and its step count.
+__global__ void __launch_bounds__(256) k_group_bits(TileLevels T, const int32_t* sorted, uint32_t* bitmap,
+                                                    int32_t* wpre, int32_t* cnt) {
+  extern __shared__ uint32_t sb[];
+  __shared__ int32_t ssum[256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t b = blockIdx.x;
+  const int l = level_of_group(T, b);
+  const TileLevel& lv = T.lv[l];
+  const int words = lv.words;
+  const int64_t gi = b - lv.g0;
+  for (int w = t; w < words; w += 256) sb[w] = 0u;
+  __syncthreads();
+  if (lv.far_ptr) {
+    const int64_t p0 = gi * T.TC, p1 = min((int64_t)lv.nc, p0 + T.TC);
+    for (int64_t p = p0 + wv; p < p1; p += 4) {
+      const int c = sorted[lv.cell0 + p] - (int32_t)lv.cell0;
+      for (int e = lv.far_ptr[c] + lane; e < lv.far_ptr[c + 1]; e += 64) {
+        const int d = lv.far_did[e];
+        atomicOr(&sb[d >> 5], 1u << (d & 31));
+      }
+    }
   }
-}
-
-// per group: exclusive popcount prefix over its words, and its step count
-__global__ void k_group_prefix(int32_t ng, int words, const uint32_t* bitmap, int32_t* wpre, int32_t* cnt) {
-  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= ng) return;
+  __syncthreads();
+  // thread t owns words [t per, (t + 1) per)
+  const int per = (words + 255) / 256;
   int s = 0;
-  for (int w = 0; w < words; w++) {
-    wpre[(int64_t)gi * words + w] = s;
-    s += __popc(bitmap[(int64_t)gi * words + w]);
+  for (int i = 0; i < per; i++) {
+    const int w = t * per + i;
+    if (w < words) s += __popc(sb[w]);
   }
-  cnt[gi] = s;
+  ssum[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int32_t add = (t >= off) ? ssum[t - off] : 0;
+    __syncthreads();
+    ssum[t] += add;
+    __syncthreads();
+  }
+  int ex = ssum[t] - s;
+  const int64_t base = lv.bm0 + gi * words;
+  for (int i = 0; i < per; i++) {
+    const int w = t * per + i;
+    if (w < words) {
+      const uint32_t m = sb[w];
+      bitmap[base + w] = m;
+      wpre[base + w] = ex;
+      ex += __popc(m);
+    }
+  }
+  if (t == 255) cnt[b] = ssum[255];
 }
 
-__global__ void k_group_steps(int32_t ng, int words, const uint32_t* bitmap, const int32_t* goff, int64_t step_base,
-                              int64_t drow0, int32_t* step_delta) {
-  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= ng) return;
-  int64_t s = step_base + goff[gi];
-  for (int w = 0; w < words; w++) {
-    uint32_t m = bitmap[(int64_t)gi * words + w];
+// one wavefront per group: the derivative-tensor row of every step, in
+// offset-id order (word w, bit k has rank wpre[w] + popcount of lower bits)
+__global__ void __launch_bounds__(256) k_group_steps(TileLevels T, int64_t ngroups, const uint32_t* bitmap,
+                                                     const int32_t* wpre, const int32_t* goff,
+                                                     int32_t* step_delta) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= ngroups) return;
+  const TileLevel& lv = T.lv[level_of_group(T, b)];
+  const int64_t base = lv.bm0 + (b - lv.g0) * lv.words;
+  for (int w = lane; w < lv.words; w += 64) {
+    uint32_t m = bitmap[base + w];
+    int64_t s = (int64_t)goff[b] + wpre[base + w];
     while (m) {
-      const int b = __ffs(m) - 1;
+      const int k = __ffs(m) - 1;
       m &= m - 1;
-      step_delta[s++] = (int32_t)(drow0 + 32 * w + b);
+      step_delta[s++] = (int32_t)(lv.drow0 + 32 * w + k);
     }
   }
 }
 
-__global__ void __launch_bounds__(256) k_step_src(int32_t nc, const int32_t* far_ptr, const int32_t* far_idx,
-                                                  const int32_t* far_did, const int32_t* inv, int TC, int words,
+// one wavefront per cell: each far entry becomes the source of its column at
+// the rank of its offset within the group's steps
+__global__ void __launch_bounds__(256) k_step_src(TileLevels T, int64_t ncell, const int32_t* inv,
                                                   const uint32_t* bitmap, const int32_t* wpre, const int32_t* goff,
-                                                  int64_t step_base, int32_t* step_src) {
+                                                  int32_t* step_src) {
   const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= nc) return;
-  const int pos = inv[c];
-  const int gi = pos / TC, tc = pos % TC;
-  const int64_t base = (int64_t)gi * words;
-  for (int e = far_ptr[c] + lane; e < far_ptr[c + 1]; e += 64) {
-    const int d = far_did[e];
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= ncell) return;
+  const TileLevel& lv = T.lv[level_of_cell(T, i)];
+  if (!lv.far_ptr) return;
+  const int c = (int)(i - lv.cell0);
+  const int64_t pos = inv[i] - lv.cell0;
+  const int64_t gi = pos / T.TC, tc = pos % T.TC;
+  const int64_t b = lv.g0 + gi;
+  const int64_t base = lv.bm0 + gi * lv.words;
+  for (int e = lv.far_ptr[c] + lane; e < lv.far_ptr[c + 1]; e += 64) {
+    const int d = lv.far_did[e];
     const int rank = wpre[base + (d >> 5)] + __popc(bitmap[base + (d >> 5)] & ((1u << (d & 31)) - 1u));
-    step_src[(step_base + goff[gi] + rank) * TC + tc] = far_idx[e];
+    step_src[((int64_t)goff[b] + rank) * T.TC + tc] = lv.far_idx[e];
   }
 }
 
-__global__ void k_tiles(int32_t ng, int level, int TC, int TB, int ncg, int64_t step_base, int64_t tgt_base,
-                        const int32_t* goff, M2LTile* tiles, int64_t tile_base) {
-  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= ng) return;
+// column targets (compact cell of the level, -1 past the level's cells) and
+// the tiles: one per group and configuration group
+__global__ void k_tile_tgt(TileLevels T, int64_t ncol, const int32_t* sorted, int32_t* tgt) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ncol) return;
+  const int64_t b = j / T.TC;
+  const TileLevel& lv = T.lv[level_of_group(T, b)];
+  const int64_t pos = (b - lv.g0) * T.TC + j % T.TC;
+  tgt[j] = pos < lv.nc ? sorted[lv.cell0 + pos] - (int32_t)lv.cell0 : -1;
+}
+
+__global__ void k_tiles(TileLevels T, int64_t ngroups, int TB, int ncg, const int32_t* goff, M2LTile* tiles) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= ngroups) return;
+  const int l = level_of_group(T, b);
   for (int cg = 0; cg < ncg; cg++) {
     M2LTile t;
-    t.level = level;
-    t.step0 = (int32_t)(step_base + goff[gi]);
-    t.nsteps = goff[gi + 1] - goff[gi];
-    t.tgt0 = (int32_t)(tgt_base + (int64_t)gi * TC);
+    t.level = l;
+    t.step0 = goff[b];
+    t.nsteps = goff[b + 1] - goff[b];
+    t.tgt0 = (int32_t)(b * T.TC);
     t.b0 = cg * TB;
     t.pad[0] = t.pad[1] = t.pad[2] = 0;
-    tiles[tile_base + (int64_t)gi * ncg + cg] = t;
+    tiles[b * ncg + cg] = t;
   }
-}
-
-__global__ void k_tile_tgt(int32_t nc, int32_t ng, int TC, const int32_t* order, int32_t* tgt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ng * TC) return;
-  tgt[i] = (i < nc) ? order[i] : -1;
 }
 
 __global__ void k_tile_keys(int64_t ntiles, const M2LTile* tiles, uint32_t* key, int32_t* ord) {
@@ -356,91 +438,76 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   P.tiles_nb = nbatch;
   P.ncg = ceil_div(nbatch, tb);
   const int TC = P.TC;
-  // pass 1: ordering, bitmaps, step counts per target group
-  int64_t nbm = 0, ngc = 0;
+  TileLevels TL{};
+  TL.nlev = L + 1;
+  TL.TC = TC;
+  int64_t ncell = 0, ngroups = 0, nbm = 0;
+  int maxwords = 1;
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
-    D.ngroups = ceil_div(D.ncells, TC);
-    D.words = std::max(1, ceil_div(D.nbox, 32));
-    D.bm0 = nbm;
-    D.g0 = ngc;
-    nbm += (int64_t)D.ngroups * D.words;
-    ngc += D.ngroups + 1;
+    TileLevel& v = TL.lv[l];
+    v.key = D.key.as<int32_t>();
+    v.far_ptr = l > 0 ? D.far_ptr.as<int32_t>() : nullptr;
+    v.far_idx = l > 0 ? D.far_idx.as<int32_t>() : nullptr;
+    v.far_did = l > 0 ? D.far_did.as<int32_t>() : nullptr;
+    v.cell0 = ncell;
+    v.g0 = ngroups;
+    v.bm0 = nbm;
+    v.drow0 = D.drow0;
+    v.nc = D.ncells;
+    v.words = (int)std::max<int64_t>(1, ceil_div(D.nbox, 32));
+    maxwords = std::max(maxwords, v.words);
+    const int64_t ng = ceil_div(D.ncells, TC);
+    ncell += D.ncells;
+    ngroups += ng;
+    nbm += ng * v.words;
   }
-  // bitmap | word prefixes, group counts | group offsets
+  if (sizeof(uint32_t) * (size_t)maxwords > 60 * 1024)
+    fail(CCFMM_EINVAL, "opening angle too small for the M2L tiling (offset box too large)");
+  // target order: (level, class, key) by one stable sort of all cells
+  const int cb = std::min(P.class_bits, 11);
+  int lbits = 1;
+  while ((1 << lbits) <= L) lbits++;
+  int32_t* sbuf = reinterpret_cast<int32_t*>(P.tile_sort.ensure(sizeof(int32_t) * 5 * ncell));
+  uint32_t* skey = reinterpret_cast<uint32_t*>(sbuf);
+  int32_t* sorted = sbuf + ncell;
+  uint32_t* skey2 = reinterpret_cast<uint32_t*>(sbuf + 2 * ncell);
+  int32_t* sval2 = sbuf + 3 * ncell;
+  int32_t* inv = sbuf + 4 * ncell;
+  k_tile_class_keys<<<ceil_div(ncell, T), T, 0, st>>>(TL, ncell, cb, skey, sorted);
+  CCFMM_HIP(hipGetLastError());
+  radix_sort_pairs(skey, sorted, skey2, sval2, ncell, cb + lbits, P.scratch, st);
+  k_tile_inverse<<<ceil_div(ncell, T), T, 0, st>>>(sorted, ncell, inv);
+  CCFMM_HIP(hipGetLastError());
+  // bitmaps, ranks and step counts of every group; global step offsets
   uint32_t* bitmap = reinterpret_cast<uint32_t*>(P.bitmap.ensure(sizeof(uint32_t) * 2 * std::max<int64_t>(1, nbm)));
   int32_t* wpre = reinterpret_cast<int32_t*>(bitmap + std::max<int64_t>(1, nbm));
-  int32_t* gbuf = reinterpret_cast<int32_t*>(P.gcount.ensure(sizeof(int32_t) * 2 * (ngc + 1)));
+  int32_t* gbuf = reinterpret_cast<int32_t*>(P.gcount.ensure(sizeof(int32_t) * 2 * (ngroups + 1)));
   int32_t* gcnt = gbuf;
-  int32_t* goff = gbuf + ngc + 1;
-  fill_i32(reinterpret_cast<int32_t*>(bitmap), nbm, 0, st);
-  std::vector<int32_t> lsteps(L + 1, 0);
-  for (int l = 0; l <= L; l++) {
-    LevelData& D = *P.lev[l];
-    const int nc = D.ncells;
-    int32_t* order = reinterpret_cast<int32_t*>(D.order.ensure(sizeof(int32_t) * 2 * std::max(1, nc)));
-    int32_t* inv = order + std::max(1, nc);
-    const int cb = std::min(P.class_bits, l);
-    k_class_keys<<<ceil_div(nc, T), T, 0, st>>>(D.key.as<int32_t>(), nc, cb, P.key_tmp.as<uint32_t>(), order);
-    CCFMM_HIP(hipGetLastError());
-    // stable sort by class: compact order is key order, so this yields (class, key)
-    radix_sort_pairs(P.key_tmp.as<uint32_t>(), order, P.key.as<uint32_t>(), inv, nc, cb, P.scratch, st);
-    k_inverse<<<ceil_div(nc, T), T, 0, st>>>(order, nc, inv);
-    CCFMM_HIP(hipGetLastError());
-    if (l > 0) {
-      k_group_bitmap<<<ceil_div(nc, 4), T, 0, st>>>(nc, D.far_ptr.as<int32_t>(), D.far_did.as<int32_t>(), inv, TC,
-                                                    D.words, bitmap + D.bm0);
-      CCFMM_HIP(hipGetLastError());
-    }
-    k_group_prefix<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, D.words, bitmap + D.bm0, wpre + D.bm0,
-                                                         gcnt + D.g0);
-    CCFMM_HIP(hipGetLastError());
-    scan_exclusive(gcnt + D.g0, goff + D.g0, D.ngroups, P.scratch, st);
-    CCFMM_HIP(hipMemcpyAsync(&lsteps[l], goff + D.g0 + D.ngroups, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  }
+  int32_t* goff = gbuf + ngroups + 1;
+  k_group_bits<<<(unsigned)ngroups, T, sizeof(uint32_t) * maxwords, st>>>(TL, sorted, bitmap, wpre, gcnt);
+  CCFMM_HIP(hipGetLastError());
+  scan_exclusive(gcnt, goff, ngroups, P.scratch, st);
+  int32_t total = 0;
+  CCFMM_HIP(hipMemcpyAsync(&total, goff + ngroups, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CCFMM_HIP(hipStreamSynchronize(st));
-  int64_t nsteps = 0, ntiles = 0, ntgt = 0;
-  for (int l = 0; l <= L; l++) {
-    LevelData& D = *P.lev[l];
-    D.step0 = nsteps;
-    D.nsteps = lsteps[l];
-    D.tile0 = ntiles;
-    D.ntiles = (int64_t)D.ngroups * P.ncg;
-    nsteps += D.nsteps;
-    ntiles += D.ntiles;
-    ntgt += (int64_t)D.ngroups * TC;
-  }
-  // the root gets a tile too, so its (zero) local expansion is written like
-  // every other cell's
+  const int64_t nsteps = total;
+  const int64_t ntiles = ngroups * P.ncg;
   P.nsteps = nsteps;
   P.ntiles = ntiles;
   int32_t* step_delta = reinterpret_cast<int32_t*>(P.step_delta.ensure(sizeof(int32_t) * std::max<int64_t>(1, nsteps)));
   int32_t* step_src = reinterpret_cast<int32_t*>(P.step_src.ensure(sizeof(int32_t) * std::max<int64_t>(1, nsteps * TC)));
-  int32_t* tile_tgt = reinterpret_cast<int32_t*>(P.tile_tgt.ensure(sizeof(int32_t) * std::max<int64_t>(1, ntgt)));
+  int32_t* tile_tgt = reinterpret_cast<int32_t*>(P.tile_tgt.ensure(sizeof(int32_t) * std::max<int64_t>(1, ngroups * TC)));
   M2LTile* tiles = reinterpret_cast<M2LTile*>(P.tiles.ensure(sizeof(M2LTile) * std::max<int64_t>(1, ntiles)));
   fill_i32(step_src, nsteps * TC, -1, st);
-  int64_t tgt_base = 0;
-  for (int l = 0; l <= L; l++) {
-    LevelData& D = *P.lev[l];
-    const int nc = D.ncells;
-    int32_t* order = D.order.as<int32_t>();
-    int32_t* inv = order + std::max(1, nc);
-    k_group_steps<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, D.words, bitmap + D.bm0, goff + D.g0, D.step0,
-                                                        D.drow0, step_delta);
-    CCFMM_HIP(hipGetLastError());
-    if (l > 0) {
-      k_step_src<<<ceil_div(nc, 4), T, 0, st>>>(nc, D.far_ptr.as<int32_t>(), D.far_idx.as<int32_t>(),
-                                                D.far_did.as<int32_t>(), inv, TC, D.words, bitmap + D.bm0,
-                                                wpre + D.bm0, goff + D.g0, D.step0, step_src);
-      CCFMM_HIP(hipGetLastError());
-    }
-    k_tile_tgt<<<ceil_div((int64_t)D.ngroups * TC, T), T, 0, st>>>(nc, D.ngroups, TC, order, tile_tgt + tgt_base);
-    CCFMM_HIP(hipGetLastError());
-    k_tiles<<<ceil_div(D.ngroups, T), T, 0, st>>>(D.ngroups, l, TC, P.TB, P.ncg, D.step0, tgt_base, goff + D.g0,
-                                                  tiles, D.tile0);
-    CCFMM_HIP(hipGetLastError());
-    tgt_base += (int64_t)D.ngroups * TC;
-  }
+  k_group_steps<<<ceil_div(ngroups, 4), T, 0, st>>>(TL, ngroups, bitmap, wpre, goff, step_delta);
+  CCFMM_HIP(hipGetLastError());
+  k_step_src<<<ceil_div(ncell, 4), T, 0, st>>>(TL, ncell, inv, bitmap, wpre, goff, step_src);
+  CCFMM_HIP(hipGetLastError());
+  k_tile_tgt<<<ceil_div(ngroups * TC, T), T, 0, st>>>(TL, ngroups * TC, sorted, tile_tgt);
+  CCFMM_HIP(hipGetLastError());
+  k_tiles<<<ceil_div(ngroups, T), T, 0, st>>>(TL, ngroups, P.TB, P.ncg, goff, tiles);
+  CCFMM_HIP(hipGetLastError());
   // launch order: longest step lists first, so the dispatcher's greedy,
   // round-robin placement balances the XCDs and their compute units
   if (ntiles > 0) {

@@ -38,16 +38,6 @@ struct LevelData {
   int64_t cnear = 1;
   int64_t nbox = 1;     // dense offset ids of the level: prod(2 wfar + 1)
   int64_t drow0 = 0;    // derivative-tensor row of dense id 0
-  // M2L tiling
-  DevBuf order;         // tile order position -> compact target, then its inverse
-  int32_t ngroups = 0;  // target groups of TC cells
-  int words = 1;        // bitmap words per group
-  int64_t bm0 = 0;      // first bitmap word of the level
-  int64_t g0 = 0;       // first group counter of the level
-  int64_t step0 = 0;    // first global step of the level
-  int64_t nsteps = 0;
-  int64_t tile0 = 0;
-  int64_t ntiles = 0;
   int64_t qoff = 0;     // element offset of the level in Q/V
 };
 
@@ -87,6 +77,7 @@ struct Plan {
   int tiles_variant = -1, tiles_class_bits = -1;  // what the current tiles were built for
   DevBuf tiles, tile_tgt, step_delta, step_src, bitmap, gcount;
   DevBuf tile_order;  // launch order of the M2L tiles: longest step list first (+ sort temporaries)
+  DevBuf tile_sort;   // target ordering of all levels (keys, order, temporaries, inverse)
   int64_t ntiles = 0, nsteps = 0;
   // P2P chunks (built on the device; their count stays in device memory)
   DevBuf chunks, chunk_cnt;

@@ -79,7 +79,45 @@ __global__ void k_finish_total(int32_t* out, int64_t n, const int32_t* last) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n > 0) ? out[n - 1] + last[0] : 0;
 }
 
+// One block scans up to kScanSingleMax values in a single launch: each of
+// 1024 threads owns a contiguous run, the run sums are scanned in LDS, and the
+// total lands in out[n] (out may alias in).
+constexpr int kScanSingleThreads = 1024;
+constexpr int64_t kScanSingleMax = 64 * kScanSingleThreads;
+
+__global__ void __launch_bounds__(kScanSingleThreads) k_scan_single(const int32_t* in, int32_t* out, int64_t n) {
+  __shared__ int32_t sh[kScanSingleThreads];
+  const int t = threadIdx.x;
+  const int per = (int)((n + kScanSingleThreads - 1) / kScanSingleThreads);
+  const int64_t b = (int64_t)t * per;
+  int32_t s = 0;
+  for (int i = 0; i < per; i++)
+    if (b + i < n) s += in[b + i];
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanSingleThreads; off <<= 1) {
+    const int32_t add = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int32_t ex = sh[t] - s;
+  for (int i = 0; i < per; i++) {
+    if (b + i < n) {
+      const int32_t v = in[b + i];
+      out[b + i] = ex;
+      ex += v;
+    }
+  }
+  if (t == kScanSingleThreads - 1) out[n] = sh[t];
+}
+
 void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st) {
+  if (n <= kScanSingleMax) {
+    k_scan_single<<<1, kScanSingleThreads, 0, st>>>(in, out, n < 0 ? 0 : n);
+    CCFMM_HIP(hipGetLastError());
+    return;
+  }
   // temporaries: block sums of every recursion level + the saved last input
   int64_t need = 4;
   for (int64_t m = n; m > 1; m = ceil_div(m, kScanTile)) need += ceil_div(m, kScanTile) + 1;
@@ -347,6 +385,12 @@ __global__ void k_leaf_ranges(const int32_t* __restrict__ lkey, const int32_t* _
   lcount[i] = leaf_start[k + 1] - leaf_start[k];
 }
 
+// level starts in the heap scan: scan[2^l - 1], l = 0..L+1
+__global__ void k_level_starts(const int32_t* scan, int L, int32_t* out) {
+  const int l = threadIdx.x;
+  if (l <= L + 1) out[l] = scan[(1ll << l) - 1];
+}
+
 void build_tree(Plan& P, const double* d_pos, hipStream_t st) {
   const int64_t n = P.n;
   const int L = P.L;
@@ -375,9 +419,13 @@ void build_tree(Plan& P, const double* d_pos, hipStream_t st) {
   scan_exclusive(flag, scan, nheap, P.scratch, st);
   // level starts: scan[2^l - 1] for l = 0..L+1 (the last is the total)
   std::vector<int32_t> starts(L + 2);
-  for (int l = 0; l <= L + 1; l++)
-    CCFMM_HIP(hipMemcpyAsync(&starts[l], scan + ((1ll << l) - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  CCFMM_HIP(hipStreamSynchronize(st));
+  {
+    int32_t* g = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * (L + 2)));
+    k_level_starts<<<1, 64, 0, st>>>(scan, L, g);
+    CCFMM_HIP(hipGetLastError());
+    CCFMM_HIP(hipMemcpyAsync(starts.data(), g, sizeof(int32_t) * (L + 2), hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipStreamSynchronize(st));
+  }
   LevelPtrs lp{};
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
