@@ -197,24 +197,50 @@ __global__ void k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr, const int
   atomicAdd(out, (unsigned long long)(s * lcount[i]));
 }
 
+// scattered device counters gathered into one small array (one copy back);
+// the last two words are cleared for the direct-pair count
+struct InfoSources {
+  const int32_t* at[2 * (kLMax + 1) + 3];
+  int32_t n;
+};
+__global__ void k_info_gather(InfoSources src, int cidx, int32_t* out) {
+  const int i = threadIdx.x;
+  if (i < src.n) out[i] = *src.at[i];
+  if (i == 0) out[cidx] = out[cidx + 1] = 0;
+}
+
 static void fill_info(Plan& P, hipStream_t st) {
-  // list totals, chunk count and error flags come back in one synchronisation
+  // list totals, chunk counts, error flags and the direct-pair count come
+  // back in one copy and one synchronisation
   const int L = P.L;
-  std::vector<int32_t> tot(2 * (L + 1) + 3, 0);
+  const int nl = P.lev[L]->ncells;
+  InfoSources src{};
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
-    CCFMM_HIP(hipMemcpyAsync(&tot[2 * l], D.near_ptr.as<int32_t>() + D.ncells, sizeof(int32_t),
-                             hipMemcpyDeviceToHost, st));
-    CCFMM_HIP(hipMemcpyAsync(&tot[2 * l + 1], D.far_ptr.as<int32_t>() + D.ncells, sizeof(int32_t),
-                             hipMemcpyDeviceToHost, st));
+    src.at[2 * l] = D.near_ptr.as<int32_t>() + D.ncells;
+    src.at[2 * l + 1] = D.far_ptr.as<int32_t>() + D.ncells;
   }
-  const int nl = P.lev[L]->ncells;
-  CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1)], P.chunk_cnt.as<int32_t>() + (nl + 1) + nl, sizeof(int32_t),
-                           hipMemcpyDeviceToHost, st));
-  CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1) + 1], P.flags.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  CCFMM_HIP(hipMemcpyAsync(&tot[2 * (L + 1) + 2], P.chunk_cnt.as<int32_t>() + 3 * (nl + 1) + nl, sizeof(int32_t),
-                           hipMemcpyDeviceToHost, st));
+  src.at[2 * (L + 1)] = P.chunk_cnt.as<int32_t>() + (nl + 1) + nl;
+  src.at[2 * (L + 1) + 1] = P.flags.as<int32_t>();
+  src.at[2 * (L + 1) + 2] = P.chunk_cnt.as<int32_t>() + 3 * (nl + 1) + nl;
+  src.n = 2 * (L + 1) + 3;
+  const int cidx = (src.n + 1) & ~1;  // the 64-bit pair count, 8-byte aligned
+  const int nw = cidx + 2;
+  int32_t* dbuf = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * (nw + 2)));
+  k_info_gather<<<1, 64, 0, st>>>(src, cidx, dbuf);
+  CCFMM_HIP(hipGetLastError());
+  {
+    LevelData& D = *P.lev[L];
+    unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(dbuf + cidx);
+    k_count_p2p_pairs<<<ceil_div(D.ncells, 256), 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
+                                                               D.near_idx.as<int32_t>(), P.lcount.as<int32_t>(), dcnt);
+    CCFMM_HIP(hipGetLastError());
+  }
+  std::vector<int32_t> tot(nw, 0);
+  CCFMM_HIP(hipMemcpyAsync(tot.data(), dbuf, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, st));
   CCFMM_HIP(hipStreamSynchronize(st));
+  unsigned long long npairs = 0;
+  std::memcpy(&npairs, &tot[cidx], sizeof(npairs));
   P.nchunks32 = tot[2 * (L + 1) + 2];
   if (tot[2 * (L + 1) + 1]) fail(CCFMM_EHIP, "internal: a cell list exceeded its bound");
   for (int l = 0; l <= L; l++) {
@@ -254,17 +280,8 @@ static void fill_info(Plan& P, hipStream_t st) {
   const double np = (double)nact(P.p);
   I.m2l_flops_per_config = 2.0 * np * np * (double)m2l;
   // direct pairs (self pairs included in the count)
-  LevelData& D = *P.lev[P.L];
-  unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(P.scratch2.ensure(64));
-  CCFMM_HIP(hipMemsetAsync(dcnt, 0, 8, st));
-  k_count_p2p_pairs<<<ceil_div(D.ncells, 256), 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
-                                                             D.near_idx.as<int32_t>(), P.lcount.as<int32_t>(), dcnt);
-  CCFMM_HIP(hipGetLastError());
-  unsigned long long h = 0;
-  CCFMM_HIP(hipMemcpyAsync(&h, dcnt, 8, hipMemcpyDeviceToHost, st));
-  CCFMM_HIP(hipStreamSynchronize(st));
-  I.n_p2p_pairs = (int64_t)h;
-  I.p2p_pairs_per_config = (double)h;
+  I.n_p2p_pairs = (int64_t)npairs;
+  I.p2p_pairs_per_config = (double)npairs;
 }
 
 static void validate_params(const ccfmm_params* prm, int64_t n) {

@@ -160,6 +160,9 @@ void check_hip(hipError_t e, const char* what);
 // exclusive scan of n int32 values into out (out may alias in); returns nothing,
 // total is written to out[n] (out must hold n+1 ints).
 void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
+// two independent scans of n values each (one launch when n is small)
+void scan_exclusive2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1, int64_t n, DevBuf& tmp,
+                     hipStream_t st);
 // stable LSD radix sort of (key, val) pairs by the low `bits` bits of key
 void radix_sort_pairs(uint32_t* key, int32_t* val, uint32_t* key_tmp, int32_t* val_tmp, int64_t n,
                       int bits, DevBuf& tmp, hipStream_t st);

@@ -231,8 +231,7 @@ void build_lists(Plan& P, hipStream_t st) {
     CCFMM_HIP(hipGetLastError());
     int32_t* nptr = reinterpret_cast<int32_t*>(D.near_ptr.ensure(sizeof(int32_t) * (nc + 1)));
     int32_t* fptr = reinterpret_cast<int32_t*>(D.far_ptr.ensure(sizeof(int32_t) * (nc + 1)));
-    scan_exclusive(near_cnt, nptr, nc, P.scratch, st);
-    scan_exclusive(far_cnt, fptr, nc, P.scratch, st);
+    scan_exclusive2(near_cnt, nptr, far_cnt, fptr, nc, P.scratch, st);
     int32_t* nidx = reinterpret_cast<int32_t*>(D.near_idx.ensure(sizeof(int32_t) * std::max<int64_t>(1, near_cap)));
     int32_t* fidx = reinterpret_cast<int32_t*>(D.far_idx.ensure(sizeof(int32_t) * std::max<int64_t>(1, far_cap)));
     int32_t* fdid = reinterpret_cast<int32_t*>(D.far_did.ensure(sizeof(int32_t) * std::max<int64_t>(1, far_cap)));

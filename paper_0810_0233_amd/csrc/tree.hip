@@ -112,6 +112,48 @@ __global__ void __launch_bounds__(kScanSingleThreads) k_scan_single(const int32_
   if (t == kScanSingleThreads - 1) out[n] = sh[t];
 }
 
+// two arrays of the same length scanned in one launch (two blocks)
+__global__ void __launch_bounds__(kScanSingleThreads) k_scan_single2(const int32_t* in0, int32_t* out0,
+                                                                     const int32_t* in1, int32_t* out1, int64_t n) {
+  __shared__ int32_t sh[kScanSingleThreads];
+  const int32_t* in = blockIdx.x ? in1 : in0;
+  int32_t* out = blockIdx.x ? out1 : out0;
+  const int t = threadIdx.x;
+  const int per = (int)((n + kScanSingleThreads - 1) / kScanSingleThreads);
+  const int64_t b = (int64_t)t * per;
+  int32_t s = 0;
+  for (int i = 0; i < per; i++)
+    if (b + i < n) s += in[b + i];
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanSingleThreads; off <<= 1) {
+    const int32_t add = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int32_t ex = sh[t] - s;
+  for (int i = 0; i < per; i++) {
+    if (b + i < n) {
+      const int32_t v = in[b + i];
+      out[b + i] = ex;
+      ex += v;
+    }
+  }
+  if (t == kScanSingleThreads - 1) out[n] = sh[t];
+}
+
+void scan_exclusive2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1, int64_t n, DevBuf& tmp,
+                     hipStream_t st) {
+  if (n <= kScanSingleMax) {
+    k_scan_single2<<<2, kScanSingleThreads, 0, st>>>(in0, out0, in1, out1, n < 0 ? 0 : n);
+    CCFMM_HIP(hipGetLastError());
+    return;
+  }
+  scan_exclusive(in0, out0, n, tmp, st);
+  scan_exclusive(in1, out1, n, tmp, st);
+}
+
 void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st) {
   if (n <= kScanSingleMax) {
     k_scan_single<<<1, kScanSingleThreads, 0, st>>>(in, out, n < 0 ? 0 : n);
@@ -365,15 +407,22 @@ __global__ void k_link_cells(const int32_t* __restrict__ flag, const int32_t* __
   }
 }
 
-__global__ void k_cell_coords(const int32_t* __restrict__ key, int32_t nc, int l, TreeGeom G,
-                              int32_t* coord) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  int32_t c[3];
-  cell_coords(G, l, (uint32_t)key[i], c);
-  coord[3 * i] = c[0];
-  coord[3 * i + 1] = c[1];
-  coord[3 * i + 2] = c[2];
+// integer coordinates of every cell of every level (global index = compact
+// start of the level + compact index)
+struct LevelCoords {
+  int32_t* coord[kLMax + 1];
+};
+__global__ void k_cell_coords(LevelPtrs lp, LevelCoords lc, int L, TreeGeom G) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= lp.start[L + 1]) return;
+  int l = 0;
+  while (l < L && i >= lp.start[l + 1]) l++;
+  const int64_t c = i - lp.start[l];
+  int32_t x[3];
+  cell_coords(G, l, (uint32_t)lp.key[l][c], x);
+  lc.coord[l][3 * c] = x[0];
+  lc.coord[l][3 * c + 1] = x[1];
+  lc.coord[l][3 * c + 2] = x[2];
 }
 
 __global__ void k_leaf_ranges(const int32_t* __restrict__ lkey, const int32_t* __restrict__ leaf_start,
@@ -443,12 +492,13 @@ void build_tree(Plan& P, const double* d_pos, hipStream_t st) {
   CCFMM_HIP(hipGetLastError());
   k_link_cells<<<ceil_div(nheap, T), T, 0, st>>>(flag, cmap, L, nheap, lp);
   CCFMM_HIP(hipGetLastError());
+  LevelCoords lc{};
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
-    D.coord.ensure(sizeof(int32_t) * 3 * (D.ncells > 0 ? D.ncells : 1));
-    k_cell_coords<<<ceil_div(D.ncells, T), T, 0, st>>>(lp.key[l], D.ncells, l, G, D.coord.as<int32_t>());
-    CCFMM_HIP(hipGetLastError());
+    lc.coord[l] = reinterpret_cast<int32_t*>(D.coord.ensure(sizeof(int32_t) * 3 * (D.ncells > 0 ? D.ncells : 1)));
   }
+  k_cell_coords<<<ceil_div(lp.start[L + 1], T), T, 0, st>>>(lp, lc, L, G);
+  CCFMM_HIP(hipGetLastError());
   const int32_t nl = P.lev[L]->ncells;
   P.lstart.ensure(sizeof(int32_t) * nl);
   P.lcount.ensure(sizeof(int32_t) * nl);
