@@ -9,10 +9,11 @@
 // the first a get G1 = 64/a lanes each, the other b get G2 = 64/pow2ceil(b)
 // lanes each, so every lane works in both roles whatever c is.  The lanes of
 // a dipole split the sources, and their partial fields are combined with
-// cross-lane butterflies at the end.  Sources are staged 64 at a time in LDS
-// (shifted by the integer offset of their cell so all coordinates stay
-// cell-relative), padded with null sources (zero moment, far away) that add
-// exactly zero, so every lane runs the same trip count.
+// cross-lane butterflies at the end.  Sources are staged 64 at a time in LDS,
+// packed from consecutive near cells (each shifted by the integer offset of its
+// cell so all coordinates stay cell-relative) and padded with null sources
+// (zero moment, far away) that add exactly zero, so every lane runs the same
+// trip count; the next batch is loaded while the current one is summed.
 #include <type_traits>
 
 #include "mfma.hpp"
@@ -59,6 +60,17 @@ struct P2PArgs {
   int64_t voff;              // offset of level L in V
   const int32_t* leaf_p;     // per-cell local order (compact leaves), or null
 };
+
+// readlane of a float or double held as bits
+__device__ __forceinline__ uint32_t readlane_t(float v, int k) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint32_t, v), k);
+}
+__device__ __forceinline__ uint64_t readlane_t(double v, int k) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
+  return ((uint64_t)hi << 32) | lo;
+}
 
 // One staged source: position (cell-relative, shifted to the target cell) and
 // moment, padded to 8 elements so a lane reads it with two 16-byte loads.
@@ -178,48 +190,113 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
   const T* mb = msort + (int64_t)b * 3 * n;
   const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
   P2PSrc<T>* src = sS[w];
-  double hx1 = 0.0, hy1 = 0.0, hz1 = 0.0, hx2 = 0.0, hy2 = 0.0, hz2 = 0.0;  // near field, cell-relative units
-  for (int e = a.near_ptr[ch.leaf]; e < a.near_ptr[ch.leaf + 1]; e++) {
-    const int S = a.near_idx[e];
-    const bool self = S == ch.leaf;
-    const T ox = (T)((a.coord[3 * S] - cx) * a.g[0]);
-    const T oy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
-    const T oz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
-    const int s0 = a.lstart[S], sn = a.lcount[S];
-    T fx1 = (T)0, fy1 = (T)0, fz1 = (T)0, fx2 = (T)0, fy2 = (T)0, fz2 = (T)0;
-    for (int base = 0; base < sn; base += 64) {
-      const int nsrc = min(64, sn - base);
-      P2PSrc<T> q;
-      if (lane < nsrc) {
-        const int64_t j = s0 + base + lane;
-        q.x = y[j] + ox;
-        q.y = y[n + j] + oy;
-        q.z = y[2 * n + j] + oz;
-        q.mx = mb[j];
-        q.my = mb[n + j];
-        q.mz = mb[2 * n + j];
-      } else {  // null source: zero moment, far from every target
-        q.x = q.y = q.z = (T)1e4;
-        q.mx = q.my = q.mz = (T)0;
-      }
-      q.p0 = q.p1 = (T)0;
-      src[lane] = q;
-      wave_lds_sync();
-      if (self) {
-        p2p_role<T, true>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
-        if (B > 0) p2p_role<T, true>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
-      } else {
-        p2p_role<T, false>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
-        if (B > 0) p2p_role<T, false>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
-      }
-      wave_lds_sync();
+  const int e0 = a.near_ptr[ch.leaf], e1 = a.near_ptr[ch.leaf + 1];
+  // Near-list metadata, 64 entries at a time, one entry per lane: first sorted
+  // dipole, count, and the cell offset in cell-relative units.  The batch
+  // builder below reads it back with readlane (no dependent loads per cell).
+  int wb = e0;
+  int mstart = 0, mcnt = 0, mself = 0;
+  T mox = (T)0, moy = (T)0, moz = (T)0;
+  auto load_meta = [&](int base) {
+    const int e = base + lane;
+    mcnt = 0;
+    mself = 0;
+    if (e < e1) {
+      const int S = a.near_idx[e];
+      mstart = a.lstart[S];
+      mcnt = a.lcount[S];
+      mself = S == ch.leaf;
+      mox = (T)((a.coord[3 * S] - cx) * a.g[0]);
+      moy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
+      moz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
     }
+  };
+  load_meta(wb);
+  // Batches of up to 64 sources drawn from consecutive near cells (a cell
+  // may be split between batches); (e, off) is the cursor.
+  int e = e0, off = 0;
+  struct Batch {
+    int filled;
+    bool self;
+    bool valid;  // this lane's slot holds a source
+    int64_t j;   // its sorted index
+    T ox, oy, oz;
+  };
+  auto next_batch = [&](Batch& bt) {
+    bt.filled = 0;
+    bt.self = false;
+    bt.valid = false;
+    bt.j = 0;
+    bt.ox = bt.oy = bt.oz = (T)0;
+    while (bt.filled < 64 && e < e1) {
+      if (e - wb >= 64) {
+        wb = e;
+        load_meta(wb);
+      }
+      const int k = e - wb;
+      const int cnt = __builtin_amdgcn_readlane(mcnt, k);
+      const int st = __builtin_amdgcn_readlane(mstart, k);
+      const int take = min(64 - bt.filled, cnt - off);
+      if (lane >= bt.filled && lane < bt.filled + take) {
+        bt.valid = true;
+        bt.j = st + off + (lane - bt.filled);
+        bt.ox = __builtin_bit_cast(T, readlane_t(mox, k));
+        bt.oy = __builtin_bit_cast(T, readlane_t(moy, k));
+        bt.oz = __builtin_bit_cast(T, readlane_t(moz, k));
+      }
+      bt.self = bt.self || __builtin_amdgcn_readlane(mself, k);
+      bt.filled += take;
+      off += take;
+      if (off == cnt) {
+        e++;
+        off = 0;
+      }
+    }
+  };
+  auto load_src = [&](const Batch& bt, P2PSrc<T>& q) {
+    if (bt.valid) {
+      const int64_t j = bt.j;
+      q.x = y[j] + bt.ox;
+      q.y = y[n + j] + bt.oy;
+      q.z = y[2 * n + j] + bt.oz;
+      q.mx = mb[j];
+      q.my = mb[n + j];
+      q.mz = mb[2 * n + j];
+    } else {  // null source: zero moment, far from every target
+      q.x = q.y = q.z = (T)1e4;
+      q.mx = q.my = q.mz = (T)0;
+    }
+    q.p0 = q.p1 = (T)0;
+  };
+  double hx1 = 0.0, hy1 = 0.0, hz1 = 0.0, hx2 = 0.0, hy2 = 0.0, hz2 = 0.0;  // near field, cell-relative units
+  Batch cur, nxt;
+  P2PSrc<T> qc, qn;
+  next_batch(cur);
+  load_src(cur, qc);
+  while (cur.filled > 0) {
+    src[lane] = qc;
+    wave_lds_sync();
+    // the next batch's loads fly while this one is summed
+    next_batch(nxt);
+    load_src(nxt, qn);
+    const int nsrc = cur.filled;
+    T fx1 = (T)0, fy1 = (T)0, fz1 = (T)0, fx2 = (T)0, fy2 = (T)0, fz2 = (T)0;
+    if (cur.self) {
+      p2p_role<T, true>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
+      if (B > 0) p2p_role<T, true>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
+    } else {
+      p2p_role<T, false>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
+      if (B > 0) p2p_role<T, false>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
+    }
+    wave_lds_sync();
     hx1 += (double)fx1;
     hy1 += (double)fy1;
     hz1 += (double)fz1;
     hx2 += (double)fx2;
     hy2 += (double)fy2;
     hz2 += (double)fz2;
+    cur = nxt;
+    qc = qn;
   }
   // combine the lanes of each dipole (they are contiguous: lane = t G + sub)
   for (int off = 1; off < G1; off <<= 1) {
