@@ -462,3 +462,73 @@ def test_fmm_leaf_rejects_bad_parameters(ref):
     for lp, lt in [(np.full(n, 5), None), (np.full(n, 0), None), (None, np.full(n, 1.0)), (None, np.zeros(n))]:
         with pytest.raises(ValueError):
             ref.fmm_leaf(pos, m, 4, 0.5, leaf_p=lp, leaf_theta=lt, leaf_target=16, box=box)
+
+
+MLP_DIMS = (8, 64, 64, 25)
+
+
+def _mlp_unpack(P):
+    i, h1, h2, o = MLP_DIMS
+    k = 0
+    out = []
+    for shape in [(h1, i), (h1,), (h2, h1), (h2,), (o, h2), (o,)]:
+        size = int(np.prod(shape))
+        out.append(P[k:k + size].reshape(shape))
+        k += size
+    return out
+
+
+def test_mlp_reference_special_cases(ref):
+    """The selector network (not in the paper): with positive weights and
+    inputs no ReLU clips, so the network is the plain product chain; with
+    negative pre-activations in both hidden layers only the last bias
+    survives; the masked loss is the squared error over the masked entries."""
+    rng = np.random.default_rng(5)
+    n = ref.mlp_param_count(*MLP_DIMS)
+    P = rng.uniform(0.0, 0.1, n)
+    W1, b1, W2, b2, W3, b3 = _mlp_unpack(P)
+    x = rng.uniform(0.0, 1.0, (7, MLP_DIMS[0]))
+    y = ref.mlp_forward(P, x, *MLP_DIMS)
+    y_lin = ((x @ W1.T + b1) @ W2.T + b2) @ W3.T + b3
+    assert np.allclose(y, y_lin, rtol=1e-13, atol=0)
+    Pn = P.copy()
+    W1n, b1n, _, b2n = _mlp_unpack(Pn)[:4]
+    W1n[...] = -np.abs(W1n)
+    b1n[...] = -1.0  # every first hidden unit clipped ...
+    b2n[...] = -1.0  # ... so the second layer sees only its (negative) bias
+    yn = ref.mlp_forward(Pn, x, *MLP_DIMS)
+    assert np.array_equal(yn, np.broadcast_to(_mlp_unpack(Pn)[5], yn.shape))
+    # loss: zero at the targets, zero with an empty mask, one entry -> (y - t)^2 / 2
+    t = y.copy()
+    mask = np.ones_like(y)
+    loss, g = ref.mlp_loss_grad(P, x, t, mask, *MLP_DIMS)
+    assert loss == 0.0 and not np.any(g)
+    t2 = y + 1.0
+    loss0, g0 = ref.mlp_loss_grad(P, x, t2, np.zeros_like(y), *MLP_DIMS)
+    assert loss0 == 0.0 and not np.any(g0)
+    m1 = np.zeros_like(y)
+    m1[3, 7] = 1.0
+    t3 = y.copy()
+    t3[3, 7] -= 0.25
+    loss1, _ = ref.mlp_loss_grad(P, x, t3, m1, *MLP_DIMS)
+    assert abs(loss1 - 0.25 ** 2 / 2) < 1e-15
+
+
+def test_mlp_reference_gradient_finite_differences(ref):
+    rng = np.random.default_rng(9)
+    n = ref.mlp_param_count(*MLP_DIMS)
+    P = rng.normal(0.0, 0.3, n)
+    x = rng.normal(size=(11, MLP_DIMS[0]))
+    t = rng.normal(size=(11, MLP_DIMS[3]))
+    mask = (rng.random((11, MLP_DIMS[3])) < 0.6).astype(float)
+    _, g = ref.mlp_loss_grad(P, x, t, mask, *MLP_DIMS)
+    h = 1e-6
+    idx = rng.choice(n, 60, replace=False)
+    for k in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[k] += h
+        Pm[k] -= h
+        lp, _ = ref.mlp_loss_grad(Pp, x, t, mask, *MLP_DIMS)
+        lm, _ = ref.mlp_loss_grad(Pm, x, t, mask, *MLP_DIMS)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
