@@ -19,7 +19,11 @@ GPU FMM, the error of the mixed result against the FP64 GPU FMM (eps_prec) and
 against the direct sum at sampled dipoles (eps_abs), the roofline of the
 dominant kernel, and the CPU oracle timed on the same workload (configuration 0).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere]
+`--workload clusters`: 2^21 dipoles in 256 Gaussian clusters with learned per-cell
+(p, theta) for a 1e-5 bound against fixed p = 6, theta = 0.4 (the network is
+trained on the GPU first, from two training geometries of the same recipe).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters]
                        [--skip-cpu] [--skip-fp64] [--calib-copy]
 """
 import argparse
@@ -133,6 +137,138 @@ def counted_traffic(kernel, workload_name):
     return k.get("hbm_bytes_per_launch")
 
 
+def bench_clusters(args, torch, ccfmm, inputs):
+    """Learned per-cell parameters on 2^21 dipoles in 256 Gaussian clusters
+    (sigma 8, box 512^3), error bound 1e-5, against fixed p = 6, theta = 0.4.
+    The network is trained first (two training geometries of the same recipe,
+    seeds 4101 and 4102; GPU labels and GPU training, timed apart).  A learned
+    step rebuilds the tree for the positions, selects per-cell parameters
+    (features, network, choice, list rebuild) and evaluates."""
+    from paper_0810_0233_amd import selector
+
+    dev = torch.device("cuda:0")
+    sh = torch.cuda.current_stream().cuda_stream
+    t0 = time.time()
+    params, losses, ncells = selector.train_on([inputs.config_clusters_training(4101),
+                                                inputs.config_clusters_training(4102)], steps=600)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log("selector trained on %d cells in %.1f s, loss %s" % (ncells, t_train, losses))
+    c = inputs.config_clusters()
+    pos, box, m = c["pos"], c["box"], c["m"]
+    n, nb = pos.shape[0], 1
+    bound = 1e-5
+    d_pos = torch.from_numpy(pos).to(dev)
+    d_m = torch.from_numpy(np.ascontiguousarray(m)).to(dev)
+    d_H = torch.empty_like(d_m)
+    d_P = torch.from_numpy(params).to(dev)
+
+    def make(prec):
+        prm = ccfmm.params(order=6, theta=0.4, leaf_target=0.0, box=box, precision=prec, max_batch=1)
+        return ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, sh)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    plan = make(ccfmm.PREC_MIXED)
+    plan.autotune(1, d_m.data_ptr(), d_H.data_ptr(), sh)
+    cf = selector.cost_ratio(plan, d_m.data_ptr(), d_H.data_ptr(), sh)
+    fixed_info = plan.info()
+
+    def fixed_step():
+        plan.update_positions_device(d_pos.data_ptr(), sh)
+        plan.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), sh)
+
+    t_fixed = timed(fixed_step, args.steps, args.warmup)
+    H_fixed = d_H.cpu().numpy().copy()
+
+    def learned_step():
+        plan.update_positions_device(d_pos.data_ptr(), sh)
+        plan.select(d_P.data_ptr(), bound, 0.3, cf, 1, d_m.data_ptr(), judge=False, stream=sh)
+        plan.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), sh)
+
+    t_learned = timed(learned_step, args.steps, args.warmup)
+    H_learned = d_H.cpu().numpy().copy()
+    t_learned_eval = timed(lambda: plan.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), sh), args.steps, 1)
+    passes = plan.eval_device_timed(1, d_m.data_ptr(), d_H.data_ptr(), sh)
+    learned_info = plan.info()
+    # the judge's verdict on these moments (fixed-parameter FMM vs learned)
+    rc, si = plan.select(d_P.data_ptr(), bound, 0.3, cf, 1, d_m.data_ptr(), judge=True, stream=sh)
+    log("fixed step %.3f ms, learned step %.3f ms (eval %.3f ms), judge %.3e rc %d" % (
+        1e3 * t_fixed, 1e3 * t_learned, 1e3 * t_learned_eval, si["judge_err"], rc))
+    out = {}
+    if not args.skip_fp64:
+        p64 = make(ccfmm.PREC_FP64)
+        p64.autotune(1, d_m.data_ptr(), d_H.data_ptr(), sh)
+
+        def fp64_step():
+            p64.update_positions_device(d_pos.data_ptr(), sh)
+            p64.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), sh)
+
+        t64 = timed(fp64_step, max(2, args.steps // 2), 1)
+        H64 = d_H.cpu().numpy().copy()
+        out["fp64_full_step_ms"] = 1e3 * t64
+        out["speedup_vs_fp64_step"] = t64 / t_learned
+        out["eps_prec_fixed_mixed"] = rel_rms(H_fixed[0], H64[0])
+        out["eps_learned_vs_fp64_fixed"] = rel_rms(H_learned[0], H64[0])
+        p64.destroy()
+    # error against the FP64 direct sum at sampled dipoles (GPU)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(n, size=min(args.samples, n), replace=False)).astype(np.int64)
+    d_idx = torch.from_numpy(idx).to(dev)
+    d_Hd = torch.empty((idx.size, 3), dtype=torch.float64, device=dev)
+    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m[0].data_ptr(), idx.size, d_idx.data_ptr(),
+                                d_Hd.data_ptr(), sh)
+    torch.cuda.synchronize()
+    Hd = d_Hd.cpu().numpy()
+    out["eps_abs_fixed"] = rel_rms(H_fixed[0][idx], Hd)
+    out["eps_abs_learned"] = rel_rms(H_learned[0][idx], Hd)
+    kern = pass_work(learned_info, n, nb, 6)
+    dom = "m2l" if passes["m2l"] >= passes["p2p_l2p"] else "p2p_l2p"
+    ach = kern[dom]["flops"] / (passes[dom] * 1e-3)
+    roof = {"kernel": kern[dom]["kernel"], "bound": kern[dom]["bound"], "achieved": ach / 1e12,
+            "peak": kern[dom]["peak"] / 1e12, "unit": "TFLOP/s", "frac": ach / kern[dom]["peak"],
+            "traffic": counted_traffic(kern[dom]["kernel"], c["name"])}
+    res = {
+        "metric": METRIC,
+        "value": n * nb / t_learned,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_learned,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": c["name"], "n": n, "batch": nb, "order": 6, "theta": 0.4, "precision": "mixed",
+                   "selector": "learned", "err_bound": bound, "step": "tree+lists+select+eval"},
+        "fixed_full_step_ms": 1e3 * t_fixed,
+        "speedup_learned_vs_fixed_step": t_fixed / t_learned,
+        "learned_eval_ms": 1e3 * t_learned_eval,
+        "passes_ms": passes,
+        "cost_ratio_m2l_over_p2p_pair": cf,
+        "selection_hist": si["hist"],
+        "judge_err": si["judge_err"],
+        "fallback": si["fallback"],
+        "p2p_pairs": {"fixed": fixed_info["p2p_pairs_per_config"], "learned": learned_info["p2p_pairs_per_config"]},
+        "m2l_pairs": {"fixed": fixed_info["n_m2l_pairs"], "learned": learned_info["n_m2l_pairs"]},
+        "selector_training_s": t_train,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    res.update(out)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +294,9 @@ def main():
 
     from paper_0810_0233_amd import ccfmm, inputs
 
+    if args.workload == "clusters":
+        bench_clusters(args, torch, ccfmm, inputs)
+        return
     dev = torch.device("cuda:0")
     t0 = time.time()
     W = workload(args, inputs)

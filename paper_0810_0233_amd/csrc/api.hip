@@ -317,7 +317,7 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
   P.val_tmp.ensure(sizeof(int32_t) * n);
   P.perm.ensure(sizeof(int32_t) * n);
   P.yd.ensure(sizeof(double) * 3 * n);
-  P.yf.ensure(sizeof(float) * 3 * n);
+  P.yf.ensure(sizeof(float) * 6 * n);
   P.leaf_start.ensure(sizeof(int32_t) * ((1ll << P.L) + 1));
   const int64_t nheap = (2ll << P.L) - 1;
   P.heap_flag.ensure(sizeof(int32_t) * (nheap + 1));

@@ -147,6 +147,36 @@ static void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   CCFMM_HIP(hipGetLastError());
 }
 
+// Smallest level: each cell's near list reordered so that the cell itself and
+// its face/edge/corner neighbours come first (stable within both parts).  Only
+// those cells can hold dipoles arbitrarily close to the cell's own, so the
+// near-field sum gives them its exact-separation path and packs them into its
+// first batches.  One wavefront per cell; ballots give the slots.
+__global__ void __launch_bounds__(256) k_near_adjacent_first(int32_t nc, const int32_t* near_ptr,
+                                                             const int32_t* near_idx, const int32_t* coord,
+                                                             int32_t* out) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= nc) return;
+  const int cx = coord[3 * c], cy = coord[3 * c + 1], cz = coord[3 * c + 2];
+  const int base = near_ptr[c], cnt = near_ptr[c + 1] - base;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int w = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    for (int k0 = 0; k0 < cnt; k0 += 64) {
+      const int k = k0 + lane;
+      const bool valid = k < cnt;
+      const int S = valid ? near_idx[base + k] : 0;
+      const bool adj = valid && abs(coord[3 * S] - cx) <= 1 && abs(coord[3 * S + 1] - cy) <= 1 &&
+                       abs(coord[3 * S + 2] - cz) <= 1;
+      const bool take = valid && (pass == 0 ? adj : !adj);
+      const uint64_t m = __ballot(take);
+      if (take) out[base + w + __popcll(m & lt)] = S;
+      w += __popcll(m);
+    }
+  }
+}
+
 // Offset bounds of every level: near offsets satisfy |delta_a g_a| < |g|/theta;
 // candidates are children of near cells of the parent, so their offsets are
 // those of the parent level, doubled (+1) along the axis halved at this level.
@@ -237,6 +267,13 @@ void build_lists(Plan& P, hipStream_t st) {
     int32_t* fdid = reinterpret_cast<int32_t*>(D.far_did.ensure(sizeof(int32_t) * std::max<int64_t>(1, far_cap)));
     k_list_fill<<<nblk, T, 0, st>>>(a, P.geo, nptr, nidx, fptr, fidx, fdid, flags);
     CCFMM_HIP(hipGetLastError());
+    if (l == L) {
+      int32_t* reord = reinterpret_cast<int32_t*>(P.near_tmp.ensure(sizeof(int32_t) * std::max<int64_t>(1, near_cap)));
+      k_near_adjacent_first<<<nblk, T, 0, st>>>(nc, nptr, nidx, D.coord.as<int32_t>(), reord);
+      CCFMM_HIP(hipGetLastError());
+      std::swap(D.near_idx.p, P.near_tmp.p);
+      std::swap(D.near_idx.cap, P.near_tmp.cap);
+    }
   }
 }
 

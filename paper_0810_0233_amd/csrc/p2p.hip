@@ -59,6 +59,7 @@ struct P2PArgs {
   double inv_s3;             // 1 / s_L^3
   int64_t voff;              // offset of level L in V
   const int32_t* leaf_p;     // per-cell local order (compact leaves), or null
+  const float* ylo;          // FP32 residuals of the positions (SoA [3][n]); null in FP64
 };
 
 // readlane of a float or double held as bits
@@ -78,14 +79,34 @@ template <typename T>
 struct alignas(8 * sizeof(T)) P2PSrc {
   T x, y, z, mx, my, mz, p0, p1;
 };
+// FP32 residuals of a staged position (exact position = x + lx, ...)
+template <typename T>
+struct alignas(4 * sizeof(T)) P2PLo {
+  T x, y, z, p;
+};
+// A target dipole: position and its residual (zero in FP64)
+template <typename T>
+struct P2PTgt {
+  T x, y, z, lx, ly, lz;
+};
 
 // One source on one target: f += (3 (m.r) r / r^2 - m) / r^3, written as
 // inv3 * (k r - m) with k = 3 (m.r) / r^2.  Only the target's own cell can
 // hold a source at zero separation (a position determines its cell), so only
-// that cell pays for the test.
-template <typename T, bool kSelf>
-__device__ __forceinline__ void p2p_pair(const P2PSrc<T>& s, T tx, T ty, T tz, T& fx, T& fy, T& fz) {
-  const T rx = tx - s.x, ry = ty - s.y, rz = tz - s.z;
+// that cell pays for the test.  With kAcc the separation is formed as
+// (hi_t - hi_s) + (lo_t - lo_s): the first difference is exact for close
+// points, so r keeps its digits however close the pair (own and adjacent
+// cells only; elsewhere r is at least a cell side).
+template <typename T, bool kSelf, bool kAcc>
+__device__ __forceinline__ void p2p_pair(const P2PSrc<T>& s, const P2PLo<T>* l, const P2PTgt<T>& t, T& fx, T& fy,
+                                         T& fz) {
+  T rx = t.x - s.x, ry = t.y - s.y, rz = t.z - s.z;
+  if (kAcc) {
+    const P2PLo<T> q = *l;
+    rx += t.lx - q.x;
+    ry += t.ly - q.y;
+    rz += t.lz - q.z;
+  }
   const T r2 = rx * rx + ry * ry + rz * rz;
   T inv = rsqrt_t<T>(r2);
   if (kSelf) inv = (r2 > (T)0) ? inv : (T)0;
@@ -99,30 +120,31 @@ __device__ __forceinline__ void p2p_pair(const P2PSrc<T>& s, T tx, T ty, T tz, T
 }
 
 // K sources q = sub, sub + G, ... of the staged batch for one target.
-template <typename T, int G, bool kSelf>
-__device__ __forceinline__ void p2p_run(const P2PSrc<T>* __restrict__ src, int sub, int K, T tx, T ty, T tz, T& fx,
-                                        T& fy, T& fz) {
+template <typename T, int G, bool kSelf, bool kAcc>
+__device__ __forceinline__ void p2p_run(const P2PSrc<T>* __restrict__ src, const P2PLo<T>* __restrict__ lo, int sub,
+                                        int K, const P2PTgt<T>& t, T& fx, T& fy, T& fz) {
   const P2PSrc<T>* q = src + sub;
+  const P2PLo<T>* ql = lo + sub;
   int k = 0;
-  for (; k + 4 <= K; k += 4, q += 4 * G) {
+  for (; k + 4 <= K; k += 4, q += 4 * G, ql += 4 * G) {
 #pragma unroll
-    for (int u = 0; u < 4; u++) p2p_pair<T, kSelf>(q[u * G], tx, ty, tz, fx, fy, fz);
+    for (int u = 0; u < 4; u++) p2p_pair<T, kSelf, kAcc>(q[u * G], ql + u * G, t, fx, fy, fz);
   }
-  for (; k < K; k++, q += G) p2p_pair<T, kSelf>(q[0], tx, ty, tz, fx, fy, fz);
+  for (; k < K; k++, q += G, ql += G) p2p_pair<T, kSelf, kAcc>(q[0], ql, t, fx, fy, fz);
 }
 
-template <typename T, bool kSelf>
-__device__ __forceinline__ void p2p_role(const P2PSrc<T>* __restrict__ src, int G, int sub, int nsrc, T tx, T ty,
-                                         T tz, T& fx, T& fy, T& fz) {
+template <typename T, bool kSelf, bool kAcc>
+__device__ __forceinline__ void p2p_role(const P2PSrc<T>* __restrict__ src, const P2PLo<T>* __restrict__ lo, int G,
+                                         int sub, int nsrc, const P2PTgt<T>& t, T& fx, T& fy, T& fz) {
   const int K = (nsrc + G - 1) / G;
   switch (G) {
-    case 1: p2p_run<T, 1, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
-    case 2: p2p_run<T, 2, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
-    case 4: p2p_run<T, 4, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
-    case 8: p2p_run<T, 8, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
-    case 16: p2p_run<T, 16, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
-    case 32: p2p_run<T, 32, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
-    default: p2p_run<T, 64, kSelf>(src, sub, K, tx, ty, tz, fx, fy, fz); break;
+    case 1: p2p_run<T, 1, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 2: p2p_run<T, 2, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 4: p2p_run<T, 4, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 8: p2p_run<T, 8, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 16: p2p_run<T, 16, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 32: p2p_run<T, 32, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    default: p2p_run<T, 64, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
   }
 }
 
@@ -157,11 +179,12 @@ __device__ __forceinline__ void l2p_write(const T* __restrict__ v, int pl, T yx,
 }
 
 template <typename T, int P>
-__global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
+__global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
                                                            const T* __restrict__ msort, const T* __restrict__ V,
                                                            double* __restrict__ H) {
   constexpr int NS = nstride(P);
   __shared__ P2PSrc<T> sS[kP2PWaves][64];
+  __shared__ P2PLo<T> sL[kP2PWaves][64];
   // the wave index is uniform: say so, so chunk data, counts and loop bounds
   // live in scalar registers and branch on scalar conditions
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -187,25 +210,38 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
   const int64_t i1 = ch.first + t1, i2 = ch.first + (act2 ? t2 : 0);
   const T x1 = y[i1], y1 = y[n + i1], z1 = y[2 * n + i1];
   const T x2 = y[i2], y2 = y[n + i2], z2 = y[2 * n + i2];
+  constexpr bool kLo = std::is_same<T, float>::value;  // FP32 keeps residuals for close pairs
+  P2PTgt<T> tg1{x1, y1, z1, (T)0, (T)0, (T)0}, tg2{x2, y2, z2, (T)0, (T)0, (T)0};
+  if constexpr (kLo) {
+    tg1.lx = (T)a.ylo[i1];
+    tg1.ly = (T)a.ylo[n + i1];
+    tg1.lz = (T)a.ylo[2 * n + i1];
+    tg2.lx = (T)a.ylo[i2];
+    tg2.ly = (T)a.ylo[n + i2];
+    tg2.lz = (T)a.ylo[2 * n + i2];
+  }
   const T* mb = msort + (int64_t)b * 3 * n;
   const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
   P2PSrc<T>* src = sS[w];
+  P2PLo<T>* srclo = sL[w];
   const int e0 = a.near_ptr[ch.leaf], e1 = a.near_ptr[ch.leaf + 1];
   // Near-list metadata, 64 entries at a time, one entry per lane: first sorted
   // dipole, count, and the cell offset in cell-relative units.  The batch
   // builder below reads it back with readlane (no dependent loads per cell).
   int wb = e0;
-  int mstart = 0, mcnt = 0, mself = 0;
+  int mstart = 0, mcnt = 0, mself = 0, madj = 0;
   T mox = (T)0, moy = (T)0, moz = (T)0;
   auto load_meta = [&](int base) {
     const int e = base + lane;
     mcnt = 0;
     mself = 0;
+    madj = 0;
     if (e < e1) {
       const int S = a.near_idx[e];
       mstart = a.lstart[S];
       mcnt = a.lcount[S];
       mself = S == ch.leaf;
+      madj = abs(a.coord[3 * S] - cx) <= 1 && abs(a.coord[3 * S + 1] - cy) <= 1 && abs(a.coord[3 * S + 2] - cz) <= 1;
       mox = (T)((a.coord[3 * S] - cx) * a.g[0]);
       moy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
       moz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
@@ -218,6 +254,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
   struct Batch {
     int filled;
     bool self;
+    bool adj;    // holds the target cell or a neighbour of it (close pairs possible)
     bool valid;  // this lane's slot holds a source
     int64_t j;   // its sorted index
     T ox, oy, oz;
@@ -225,6 +262,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
   auto next_batch = [&](Batch& bt) {
     bt.filled = 0;
     bt.self = false;
+    bt.adj = false;
     bt.valid = false;
     bt.j = 0;
     bt.ox = bt.oy = bt.oz = (T)0;
@@ -245,6 +283,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
         bt.oz = __builtin_bit_cast(T, readlane_t(moz, k));
       }
       bt.self = bt.self || __builtin_amdgcn_readlane(mself, k);
+      bt.adj = bt.adj || __builtin_amdgcn_readlane(madj, k);
       bt.filled += take;
       off += take;
       if (off == cnt) {
@@ -253,12 +292,26 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
       }
     }
   };
-  auto load_src = [&](const Batch& bt, P2PSrc<T>& q) {
+  // the shifted position hi + o is rounded; with |o| >= |hi| (o a nonzero
+  // multiple of the cell side, |hi| at most half of it) its error is exactly
+  // hi - ((hi + o) - o), which joins the stored residual
+  auto shifted = [](T hi, T o, T& out, T& err) {
+    out = hi + o;
+    err = hi - (out - o);
+  };
+  auto load_src = [&](const Batch& bt, P2PSrc<T>& q, P2PLo<T>& ql) {
+    ql.x = ql.y = ql.z = ql.p = (T)0;
     if (bt.valid) {
       const int64_t j = bt.j;
-      q.x = y[j] + bt.ox;
-      q.y = y[n + j] + bt.oy;
-      q.z = y[2 * n + j] + bt.oz;
+      T ex, ey, ez;
+      shifted(y[j], bt.ox, q.x, ex);
+      shifted(y[n + j], bt.oy, q.y, ey);
+      shifted(y[2 * n + j], bt.oz, q.z, ez);
+      if (kLo && bt.adj) {
+        ql.x = ex + (T)a.ylo[j];
+        ql.y = ey + (T)a.ylo[n + j];
+        ql.z = ez + (T)a.ylo[2 * n + j];
+      }
       q.mx = mb[j];
       q.my = mb[n + j];
       q.mz = mb[2 * n + j];
@@ -271,22 +324,27 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
   double hx1 = 0.0, hy1 = 0.0, hz1 = 0.0, hx2 = 0.0, hy2 = 0.0, hz2 = 0.0;  // near field, cell-relative units
   Batch cur, nxt;
   P2PSrc<T> qc, qn;
+  P2PLo<T> lc, ln;
   next_batch(cur);
-  load_src(cur, qc);
+  load_src(cur, qc, lc);
   while (cur.filled > 0) {
     src[lane] = qc;
+    if (kLo && cur.adj) srclo[lane] = lc;
     wave_lds_sync();
     // the next batch's loads fly while this one is summed
     next_batch(nxt);
-    load_src(nxt, qn);
+    load_src(nxt, qn, ln);
     const int nsrc = cur.filled;
     T fx1 = (T)0, fy1 = (T)0, fz1 = (T)0, fx2 = (T)0, fy2 = (T)0, fz2 = (T)0;
     if (cur.self) {
-      p2p_role<T, true>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
-      if (B > 0) p2p_role<T, true>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
+      p2p_role<T, true, kLo>(src, srclo, G1, sub1, nsrc, tg1, fx1, fy1, fz1);
+      if (B > 0) p2p_role<T, true, kLo>(src, srclo, G2, sub2, nsrc, tg2, fx2, fy2, fz2);
+    } else if (kLo && cur.adj) {
+      p2p_role<T, false, kLo>(src, srclo, G1, sub1, nsrc, tg1, fx1, fy1, fz1);
+      if (B > 0) p2p_role<T, false, kLo>(src, srclo, G2, sub2, nsrc, tg2, fx2, fy2, fz2);
     } else {
-      p2p_role<T, false>(src, G1, sub1, nsrc, x1, y1, z1, fx1, fy1, fz1);
-      if (B > 0) p2p_role<T, false>(src, G2, sub2, nsrc, x2, y2, z2, fx2, fy2, fz2);
+      p2p_role<T, false, false>(src, srclo, G1, sub1, nsrc, tg1, fx1, fy1, fz1);
+      if (B > 0) p2p_role<T, false, false>(src, srclo, G2, sub2, nsrc, tg2, fx2, fy2, fz2);
     }
     wave_lds_sync();
     hx1 += (double)fx1;
@@ -297,6 +355,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 4 : 2) k_p2p_
     hz2 += (double)fz2;
     cur = nxt;
     qc = qn;
+    lc = ln;
   }
   // combine the lanes of each dipole (they are contiguous: lane = t G + sub)
   for (int off = 1; off < G1; off <<= 1) {
@@ -506,6 +565,7 @@ static void p2p_batched_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   a.inv_s3 = inv_s3;
   a.voff = D.qoff;
   a.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
+  a.ylo = nullptr;
   if (P.nchunks32 == 0) return;
   dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
   k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(), d_H);
@@ -535,6 +595,7 @@ static void p2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   a.inv_s3 = 1.0 / (s * s * s);
   a.voff = D.qoff;
   a.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
+  a.ylo = std::is_same<T, double>::value ? nullptr : P.yf.as<float>() + 3 * P.n;
   const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
   dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
   k_p2p_l2p<T, PP><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);

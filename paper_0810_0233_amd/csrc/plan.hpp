@@ -58,7 +58,7 @@ struct Plan {
   DevBuf key, val, key_tmp, val_tmp;
   DevBuf perm;       // sorted -> input index (int32)
   DevBuf yd;         // SoA [3][n] FP64 leaf-relative scaled offsets
-  DevBuf yf;         // SoA [3][n] FP32
+  DevBuf yf;         // SoA [3][n] FP32, then [3][n] FP32 residuals (yd - yf)
   DevBuf leaf_start; // 2^L + 1 (int32), by leaf key
   DevBuf lstart, lcount;  // per occupied leaf (compact)
   DevBuf heap_flag, heap_scan;  // occupancy and compact ids over all heap cells
@@ -78,6 +78,7 @@ struct Plan {
   DevBuf tiles, tile_tgt, step_delta, step_src, bitmap, gcount;
   DevBuf tile_order;  // launch order of the M2L tiles: longest step list first (+ sort temporaries)
   DevBuf tile_sort;   // target ordering of all levels (keys, order, temporaries, inverse)
+  DevBuf near_tmp;    // reordering buffer of the smallest level's near lists
   int64_t ntiles = 0, nsteps = 0;
   // P2P chunks (built on the device; their count stays in device memory)
   DevBuf chunks, chunk_cnt;

@@ -356,7 +356,9 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const uint32_t* 
     const double center = G.lo[a] + ((double)c[a] + 0.5) * G.lev[L].h[a];
     const double y = (pos[3 * src + a] - center) * inv_s;
     yd[a * n + i] = y;
-    yf[a * n + i] = (float)y;
+    const float hi = (float)y;
+    yf[a * n + i] = hi;
+    yf[(3 + a) * n + i] = (float)(y - (double)hi);  // residual: y = hi + lo to ~1e-16
   }
 }
 

@@ -231,3 +231,14 @@ def config_film(nx=1024, ny=1024, nz=16, nholes=16, hole_seed=5001, mom_seed_bas
     m = np.stack([random_moments(n, mom_seed_base + b) for b in range(nbatch)])
     return dict(name="film_%dx%dx%d_holes%d_x%d" % (nx, ny, nz, nholes, nbatch), pos=pos, box=box,
                 m=m, order=6, theta=0.4, leaf_target=0.0)
+
+
+def config_clusters_training(seed, nclusters=32, per_cluster=8192, box_side=256.0):
+    """Training geometry for the learned selector: the cluster recipe on a box
+    of half the side with 1/8 of the clusters.  The smallest cells then have
+    the same shape (8 x 16 x 16 at s = s_o(6)) and the clusters the same
+    density as in the 2^21-dipole geometry."""
+    pos, box = clusters(nclusters, per_cluster, seed, box_side=box_side)
+    m = random_moments(pos.shape[0], seed + 1)
+    return dict(name="clusters_train_%d" % seed, pos=pos, box=box, m=m[None], order=6, theta=0.4,
+                leaf_target=0.0)

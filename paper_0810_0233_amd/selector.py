@@ -110,6 +110,32 @@ def train(features, labels, mask, steps=400, lr=3e-3, seed=0, dev="cuda:0", log_
     return P.cpu().numpy(), losses
 
 
+def cost_ratio(plan, d_m, d_H, stream, repeats=3):
+    """Cost of one M2L pair relative to one near-field dipole pair, from the
+    plan's own timed passes (median of a few evaluations)."""
+    inf = plan.info()
+    t = [plan.eval_device_timed(1, d_m, d_H, stream) for _ in range(repeats)]
+    m2l = float(np.median([x["m2l"] for x in t]))
+    p2p = float(np.median([x["p2p_l2p"] for x in t]))
+    per_m2l = m2l / max(1, inf["n_m2l_pairs"])
+    per_p2p = p2p / max(1.0, inf["p2p_pairs_per_config"])
+    return per_m2l / per_p2p
+
+
+def train_on(configs, order=6, theta=0.4, steps=600, lr=3e-3, seed=1, dev="cuda:0", log_every=0):
+    """Labels from every training configuration (each a dict with pos, box and
+    m[0]), then training; returns (params, losses, number of cells)."""
+    feats, labs, masks = [], [], []
+    for c in configs:
+        f, y, k = cell_labels(c["pos"], c["box"], c["m"][0], order=order, theta=theta, dev=dev)
+        feats.append(f)
+        labs.append(y)
+        masks.append(k)
+    F, Y, K = np.concatenate(feats), np.concatenate(labs), np.concatenate(masks)
+    params, losses = train(F, Y, K, steps=steps, lr=lr, seed=seed, dev=dev, log_every=log_every)
+    return params, losses, F.shape[0]
+
+
 def save(path, params):
     np.save(path, np.asarray(params, dtype=np.float32), allow_pickle=False)
 

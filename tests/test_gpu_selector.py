@@ -282,3 +282,46 @@ def test_trained_selector_beats_fixed_parameters():
     assert err_learned <= bound
     assert cost(li) < 0.8 * cost(fi)
     fixed.destroy()
+
+
+def test_selector_clusters_full_scale(ref):
+    """2^21 dipoles in 256 Gaussian clusters (sigma 8, box 512^3): a network
+    trained on the GPU on two training geometries of the same recipe (seeds
+    4101, 4102) picks per-cell (p, theta) for a 1e-5 bound; the fixed
+    (6, 0.4) FMM judges it.  Against the oracle's direct sum at sampled
+    dipoles the learned field meets the bound, at a lower modelled cost
+    (near pairs + measured M2L/P2P cost ratio x M2L pairs) than the fixed one."""
+    torch = torch_mod()
+    st = stream()
+    train = [inputs.config_clusters_training(4101), inputs.config_clusters_training(4102)]
+    params, losses, ncells = selector.train_on(train, steps=600, log_every=200)
+    print("trained on %d cells, loss %s" % (ncells, losses), flush=True)
+    c = inputs.config_clusters()
+    pos, box, m = c["pos"], c["box"], c["m"][0]
+    n = pos.shape[0]
+    pl = plan_for(pos, 6, 0.4, box, precision=ccfmm.PREC_MIXED)
+    dm = dev_t(m)
+    dH = torch.empty_like(dm)
+    pl.autotune(1, dm.data_ptr(), dH.data_ptr(), st)
+    cf = selector.cost_ratio(pl, dm.data_ptr(), dH.data_ptr(), st)
+    fi = pl.info()
+    t_fixed = pl.eval_device_timed(1, dm.data_ptr(), dH.data_ptr(), st)["total"]
+    torch.cuda.synchronize()
+    H_fixed = dH.cpu().numpy()
+    idx = np.sort(np.random.default_rng(11).choice(n, 512, replace=False)).astype(np.int64)
+    Hd = ref.bruteforce_targets(pos, m, idx)
+    err_fixed = rel_rms(H_fixed[idx], Hd)
+    dP = dev_t(params)
+    rc, si = pl.select(dP.data_ptr(), 1e-5, 0.3, cf, 1, dm.data_ptr(), judge=True, stream=st)
+    li = pl.info()
+    t_learned = pl.eval_device_timed(1, dm.data_ptr(), dH.data_ptr(), st)["total"]
+    torch.cuda.synchronize()
+    err_learned = rel_rms(dH.cpu().numpy()[idx], Hd)
+    cost = lambda inf: inf["p2p_pairs_per_config"] + cf * inf["n_m2l_pairs"]  # noqa: E731
+    print("n=%d cells=%d cost ratio %.1f | fixed: err %.3e cost %.4e eval %.2f ms | learned: err %.3e cost %.4e "
+          "eval %.2f ms judge %.3e rc %d hist %s" % (n, fi["n_leaves"], cf, err_fixed, cost(fi), t_fixed, err_learned,
+                                                     cost(li), t_learned, si["judge_err"], rc, si["hist"]), flush=True)
+    assert rc == ccfmm.OK
+    assert err_learned <= 1e-5
+    assert cost(li) < cost(fi)
+    pl.destroy()
