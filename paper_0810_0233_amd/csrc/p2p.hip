@@ -435,8 +435,8 @@ __global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* 
   constexpr int KS = 3 * kBS / 4;   // 12 k steps
   __shared__ T sA[MB * KS * 64];
   __shared__ T sB[4 * KS * 64];
-  __shared__ T st[kBT][3];
-  __shared__ T ss[kBS][3];
+  __shared__ T st[kBT][6];  // position, then its FP32 residual (zero in FP64)
+  __shared__ T ss[kBS][6];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int64_t item = blockIdx.x;
   if (item >= nchunks) return;
@@ -450,6 +450,7 @@ __global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* 
     st[tid][0] = y[i];
     st[tid][1] = y[n + i];
     st[tid][2] = y[2 * n + i];
+    for (int c = 0; c < 3; c++) st[tid][3 + c] = a.ylo ? (T)a.ylo[c * n + i] : (T)0;
   }
   using AccT = typename Acc<T>::type;
   AccT acc[MB];
@@ -470,10 +471,17 @@ __global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* 
       const int ns = min(kBS, sn - base);
       __syncthreads();  // previous step's operands fully consumed
       if (tid < kBS) {
+        // shifted positions and their exact rounding errors (|offset| >= |y|
+        // when the offset is nonzero), joined to the stored residuals: the
+        // pair separations below stay exact to rounding for close pairs
         const int64_t j = s0 + base + (tid < ns ? tid : 0);
-        ss[tid][0] = y[j] + ox;
-        ss[tid][1] = y[n + j] + oy;
-        ss[tid][2] = y[2 * n + j] + oz;
+        const T o[3] = {ox, oy, oz};
+        for (int c = 0; c < 3; c++) {
+          const T hi = y[c * n + j];
+          const T sh = hi + o[c];
+          ss[tid][c] = sh;
+          ss[tid][3 + c] = (hi - (sh - o[c])) + (a.ylo ? (T)a.ylo[c * n + j] : (T)0);
+        }
       }
       // B: rows (source s, component c), columns configurations
 #pragma unroll
@@ -491,7 +499,9 @@ __global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* 
       for (int r = 0; r < (kBT * kBS) / 256; r++) {
         const int q = tid + 256 * r;
         const int t = q / kBS, s = q % kBS;
-        const T rx = st[t][0] - ss[s][0], ry = st[t][1] - ss[s][1], rz = st[t][2] - ss[s][2];
+        const T rx = (st[t][0] - ss[s][0]) + (st[t][3] - ss[s][3]);
+        const T ry = (st[t][1] - ss[s][1]) + (st[t][4] - ss[s][4]);
+        const T rz = (st[t][2] - ss[s][2]) + (st[t][5] - ss[s][5]);
         const T r2 = rx * rx + ry * ry + rz * rz;
         const bool ok = t < ch.count && s < ns && r2 > (T)0;
         const T inv = ok ? rsqrt_t<T>(r2) : (T)0;
@@ -565,7 +575,7 @@ static void p2p_batched_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   a.inv_s3 = inv_s3;
   a.voff = D.qoff;
   a.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
-  a.ylo = nullptr;
+  a.ylo = std::is_same<T, double>::value ? nullptr : P.yf.as<float>() + 3 * P.n;
   if (P.nchunks32 == 0) return;
   dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
   k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(), d_H);

@@ -301,3 +301,44 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
         assert float(junk) == float(junk)
         np.testing.assert_array_equal(d_H.cpu().numpy(), d_Hr.cpu().numpy())
+
+
+def close_pair_geometry(seed=3):
+    """A 16^3 lattice plus partners at 1e-5..1e-3 (lattice units) from random
+    sites, and pairs straddling the plane x = 1.5 (a cell face for cell sides
+    that divide 2): the close pairs that FP32 positions alone cannot resolve."""
+    rng = np.random.default_rng(seed)
+    base, box = inputs.lattice(16, 16, 16)
+    k = 512
+    pick = rng.choice(base.shape[0], k, replace=False)
+    d = 10.0 ** rng.uniform(-5, -3, k)
+    u = rng.normal(size=(k, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    partners = base[pick] + d[:, None] * u
+    f = 64
+    yz = rng.uniform(0.0, 15.0, (f, 2))
+    h = 0.5 * 10.0 ** rng.uniform(-5, -3, f)
+    face = np.concatenate([np.stack([1.5 - h, yz[:, 0], yz[:, 1]], 1), np.stack([1.5 + h, yz[:, 0], yz[:, 1]], 1)])
+    pos = np.concatenate([base, partners, face])
+    return pos, box
+
+
+@pytest.mark.parametrize("nb", [1, 40])
+def test_mixed_close_pairs(ref, nb):
+    """Mixed precision keeps the 1e-5 bound when dipoles nearly touch (inside
+    a cell and across a face): the near field forms close separations
+    exactly.  The batched matrix-core form (40 configurations) too.  FP64
+    still matches the oracle."""
+    pos, box = close_pair_geometry()
+    n = pos.shape[0]
+    m = np.stack([inputs.random_moments(n, 60 + b) for b in range(nb)])
+    out = {}
+    for prec in (ccfmm.PREC_FP64, ccfmm.PREC_MIXED):
+        pl = plan_for(pos, 6, 0.5, 0.0, box, precision=prec, max_batch=nb)
+        out[prec] = pl.eval(m)
+        pl.destroy()
+    err = rel_rms(out[ccfmm.PREC_MIXED], out[ccfmm.PREC_FP64])
+    print("close pairs nb=%d: mixed vs fp64 %.3e" % (nb, err), flush=True)
+    assert err <= MIXED_BAR
+    if nb == 1:
+        assert rel_rms(out[ccfmm.PREC_FP64][0], ref.fmm(pos, m[0], 6, 0.5, box=box)) <= FP64_BAR
