@@ -58,9 +58,10 @@ typedef struct {
   int32_t leaf_rule;    /* 0: levels L = argmin_L |N/2^L - s| (Sec. 4);
                            1: same with N/2^L replaced by the mean over occupied cells */
   int32_t precision;    /* CCFMM_PREC_FP64 or CCFMM_PREC_MIXED */
-  int32_t selector;     /* 0: fixed (order, theta); 1: learned per-leaf order/angle with
-                           fixed-parameter fallback (needs weights, ccfmm_selector_load) */
-  double err_bound;     /* learned mode: target relative RMS field error (e.g. 1e-5) */
+  int32_t selector;     /* must be 0 at plan creation: a plan starts with the fixed (order,
+                           theta); learned per-cell parameters are applied afterwards with
+                           ccfmm_plan_select (which takes the weights and the error bound) */
+  double err_bound;     /* reserved (the bound is an argument of ccfmm_plan_select) */
   int32_t has_box;      /* 1: root cell is [box_lo, box_hi]; 0: tight bounding box */
   double box_lo[3], box_hi[3];
   int32_t max_batch;    /* largest nbatch the plan will evaluate (device buffers sized) */

@@ -110,44 +110,14 @@ static double s_opt(int p) { return p > 3 ? 0.74 * (double)p * (double)p : 8.0; 
 // or 1).  Levels: the depth whose mean dipoles per smallest cell, N / 2^L, is
 // closest to s (ties to the shallower tree).  Split: halve the longest side,
 // ties x < y < z.
-static void setup_geometry(Plan& P, const double mn[3], const double mx[3]) {
-  double lo[3], W[3];
-  if (P.prm.has_box) {
-    for (int a = 0; a < 3; a++) {
-      lo[a] = P.prm.box_lo[a];
-      W[a] = P.prm.box_hi[a] - P.prm.box_lo[a];
-      if (!(W[a] > 0.0) || !std::isfinite(W[a])) fail(CCFMM_EINVAL, "empty or non-finite box");
-      if (mn[a] < P.prm.box_lo[a] || mx[a] > P.prm.box_hi[a]) fail(CCFMM_EINVAL, "a dipole lies outside the box");
-    }
-  } else {
-    double smallest = 0.0;
-    for (int a = 0; a < 3; a++) {
-      const double w = mx[a] - mn[a];
-      if (w > 0.0 && (smallest == 0.0 || w < smallest)) smallest = w;
-    }
-    if (smallest == 0.0) smallest = 1.0;
-    for (int a = 0; a < 3; a++) {
-      lo[a] = mn[a];
-      W[a] = (mx[a] - mn[a] > 0.0) ? (mx[a] - mn[a]) : smallest;
-    }
-  }
-  P.s_used = P.prm.leaf_target > 0.0 ? P.prm.leaf_target : s_opt(P.p);
-  int best = 0;
-  double bestd = INFINITY;
-  for (int L = 0; L <= kLMax; L++) {
-    const double d = std::fabs((double)P.n / std::ldexp(1.0, L) - P.s_used);
-    if (d < bestd) {
-      bestd = d;
-      best = L;
-    }
-  }
-  P.L = best;
-  TreeGeom& G = P.geo;
+// the halving sequence to depth L: each level halves the longest side of the
+// previous cell shape, ties x < y < z (Sec. 2 and 4)
+static void make_geometry(const double lo[3], const double W[3], int L, TreeGeom& G) {
   std::memset(&G, 0, sizeof(G));
-  G.L = P.L;
+  G.L = L;
   double h[3] = {W[0], W[1], W[2]};
   int k[3] = {0, 0, 0};
-  for (int l = 0; l <= P.L; l++) {
+  for (int l = 0; l <= L; l++) {
     if (l > 0) {
       int a = 0;
       if (h[1] > h[a]) a = 1;
@@ -170,6 +140,51 @@ static void setup_geometry(Plan& P, const double mn[3], const double mx[3]) {
     G.lo[a] = lo[a];
     G.W[a] = W[a];
   }
+}
+
+static void setup_geometry(Plan& P, const double mn[3], const double mx[3], const double* d_pos, hipStream_t st) {
+  double lo[3], W[3];
+  if (P.prm.has_box) {
+    for (int a = 0; a < 3; a++) {
+      lo[a] = P.prm.box_lo[a];
+      W[a] = P.prm.box_hi[a] - P.prm.box_lo[a];
+      if (!(W[a] > 0.0) || !std::isfinite(W[a])) fail(CCFMM_EINVAL, "empty or non-finite box");
+      if (mn[a] < P.prm.box_lo[a] || mx[a] > P.prm.box_hi[a]) fail(CCFMM_EINVAL, "a dipole lies outside the box");
+    }
+  } else {
+    double smallest = 0.0;
+    for (int a = 0; a < 3; a++) {
+      const double w = mx[a] - mn[a];
+      if (w > 0.0 && (smallest == 0.0 || w < smallest)) smallest = w;
+    }
+    if (smallest == 0.0) smallest = 1.0;
+    for (int a = 0; a < 3; a++) {
+      lo[a] = mn[a];
+      W[a] = (mx[a] - mn[a] > 0.0) ? (mx[a] - mn[a]) : smallest;
+    }
+  }
+  P.s_used = P.prm.leaf_target > 0.0 ? P.prm.leaf_target : s_opt(P.p);
+  // Level count: the depth whose mean dipoles per smallest cell is closest to
+  // s, ties to the shallower tree (Sec. 4).  Rule 0 averages over all 2^L
+  // cells (the paper's N/2^L); rule 1 over the occupied ones.
+  int64_t occupied[kLMax + 1];
+  if (P.prm.leaf_rule == 1) {
+    TreeGeom G24;
+    make_geometry(lo, W, kLMax, G24);
+    count_occupied_by_depth(P, d_pos, G24, st, occupied);
+  }
+  int best = 0;
+  double bestd = INFINITY;
+  for (int L = 0; L <= kLMax; L++) {
+    const double avg = P.prm.leaf_rule == 1 ? (double)P.n / (double)occupied[L] : (double)P.n / std::ldexp(1.0, L);
+    const double d = std::fabs(avg - P.s_used);
+    if (d < bestd) {
+      bestd = d;
+      best = L;
+    }
+  }
+  P.L = best;
+  make_geometry(lo, W, P.L, P.geo);
 }
 
 static void size_expansions(Plan& P, int nb) {
@@ -291,10 +306,11 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
   if (prm->order < 1 || prm->order > kPMax) fail(CCFMM_EINVAL, "order must be in 1..8");
   if (!(prm->theta > 0.0 && prm->theta < 1.0)) fail(CCFMM_EINVAL, "theta must be in (0, 1)");
   if (!std::isfinite(prm->leaf_target)) fail(CCFMM_EINVAL, "leaf_target not finite");
-  if (prm->leaf_rule != 0) fail(CCFMM_EINVAL, "leaf_rule 1 is not supported by this build");
+  if (prm->leaf_rule != 0 && prm->leaf_rule != 1) fail(CCFMM_EINVAL, "leaf_rule must be 0 or 1");
   if (prm->precision != CCFMM_PREC_FP64 && prm->precision != CCFMM_PREC_MIXED)
     fail(CCFMM_EINVAL, "precision must be FP64 or MIXED");
-  if (prm->selector != 0) fail(CCFMM_EINVAL, "learned selector not available in this build");
+  if (prm->selector != 0)
+    fail(CCFMM_EINVAL, "selector must be 0 at plan creation (apply learned parameters with ccfmm_plan_select)");
   if (prm->max_batch < 1 || prm->max_batch > 4096) fail(CCFMM_EINVAL, "max_batch must be in 1..4096");
   if (prm->has_box)
     for (int a = 0; a < 3; a++)
@@ -309,7 +325,7 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
   bool bad = false;
   device_bbox(d_pos, P.n, P.scratch, st, mn, mx, bad);
   if (bad) fail(CCFMM_EINVAL, "non-finite position");
-  setup_geometry(P, mn, mx);
+  setup_geometry(P, mn, mx, d_pos, st);
   const int64_t n = P.n;
   P.key.ensure(sizeof(uint32_t) * n);
   P.val.ensure(sizeof(int32_t) * n);

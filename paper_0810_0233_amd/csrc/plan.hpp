@@ -124,6 +124,8 @@ struct Plan {
 };
 
 // build steps (tree.hip, lists.hip, expansions.hip)
+// occupied smallest cells for every depth 0..24 (G24: the geometry at depth 24)
+void count_occupied_by_depth(Plan& P, const double* d_pos, const TreeGeom& G24, hipStream_t st, int64_t* occupied);
 void build_tree(Plan& P, const double* d_pos, hipStream_t st);
 void build_lists(Plan& P, hipStream_t st);
 void build_dtensors(Plan& P, hipStream_t st);

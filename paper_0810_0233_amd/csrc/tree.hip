@@ -317,6 +317,55 @@ __global__ void k_leaf_keys(const double* __restrict__ pos, int64_t n, TreeGeom 
   val[i] = (int32_t)i;
 }
 
+// Occupied cells at every depth 0..24 from one sort of the depth-24 keys: the
+// depth-l key of a dipole is the top l bits of its depth-24 key (the leaf
+// index at depth l is the depth-24 index shifted right, since scaling by a
+// power of two commutes with the rounding), so neighbours in sorted order
+// that first differ at depth l add one occupied cell at every depth >= l.
+__global__ void __launch_bounds__(256) k_first_diff_hist(const uint32_t* __restrict__ key, int64_t n, int32_t* hist) {
+  __shared__ int32_t h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 1 && i < n) {
+    const uint32_t x = key[i] ^ key[i - 1];
+    if (x) atomicAdd(&h[24 - (31 - __clz(x))], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 25 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_zero_i32(int32_t* p, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+void count_occupied_by_depth(Plan& P, const double* d_pos, const TreeGeom& G24, hipStream_t st, int64_t* occupied) {
+  const int64_t n = P.n;
+  const int T = 256;
+  uint32_t* key = reinterpret_cast<uint32_t*>(P.key.ensure(sizeof(uint32_t) * n));
+  int32_t* val = reinterpret_cast<int32_t*>(P.val.ensure(sizeof(int32_t) * n));
+  uint32_t* key2 = reinterpret_cast<uint32_t*>(P.key_tmp.ensure(sizeof(uint32_t) * n));
+  int32_t* val2 = reinterpret_cast<int32_t*>(P.val_tmp.ensure(sizeof(int32_t) * n));
+  k_leaf_keys<<<ceil_div(n, T), T, 0, st>>>(d_pos, n, G24, key, val);
+  CCFMM_HIP(hipGetLastError());
+  radix_sort_pairs(key, val, key2, val2, n, 24, P.scratch, st);
+  int32_t* hist = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * 32));
+  k_zero_i32<<<1, 32, 0, st>>>(hist, 32);
+  CCFMM_HIP(hipGetLastError());
+  k_first_diff_hist<<<ceil_div(n, T), T, 0, st>>>(key, n, hist);
+  CCFMM_HIP(hipGetLastError());
+  int32_t h[32];
+  CCFMM_HIP(hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  int64_t c = 1;
+  occupied[0] = 1;
+  for (int l = 1; l <= 24; l++) {
+    c += h[l];
+    occupied[l] = c;
+  }
+}
+
 // integer coordinates of the cell with key `key` at level l
 __device__ __forceinline__ void cell_coords(const TreeGeom& G, int l, uint32_t key, int32_t c[3]) {
   c[0] = c[1] = c[2] = 0;

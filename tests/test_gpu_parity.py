@@ -342,3 +342,27 @@ def test_mixed_close_pairs(ref, nb):
     assert err <= MIXED_BAR
     if nb == 1:
         assert rel_rms(out[ccfmm.PREC_FP64][0], ref.fmm(pos, m[0], 6, 0.5, box=box)) <= FP64_BAR
+
+
+@pytest.mark.parametrize("geom", ["sphere", "clusters"])
+def test_leaf_rule_occupied_mean(ref, geom):
+    """Leaf rule 1 (mean dipoles over the occupied smallest cells) on the GPU:
+    the same depth, cells and pair counts as the oracle, and the same field."""
+    if geom == "sphere":
+        pos, box = inputs.sphere_cut(6000, 30)
+    else:
+        pos, box = inputs.clusters(6, 1000, 77, sigma=4.0, box_side=128.0, margin=12.0)
+    m = inputs.random_moments(pos.shape[0], 91)
+    H_ref, st = ref.fmm(pos, m, 5, 0.5, leaf_target=0.0, leaf_rule=1, box=box, return_stats=True)
+    st0 = ref.tree_shape(pos, 5, leaf_target=0.0, leaf_rule=0, box=box)
+    pl = plan_for(pos, 5, 0.5, 0.0, box, leaf_rule=1)
+    inf = pl.info()
+    print("%s: rule-1 depth %d (rule 0: %d), %d cells" % (geom, inf["levels"], st0["levels"], inf["n_leaves"]),
+          flush=True)
+    assert inf["levels"] == st["levels"] and inf["levels"] > st0["levels"]
+    assert inf["split_axis"] == st["split_axis"]
+    assert inf["n_leaves"] == st["n_leaves"]
+    assert inf["m2l_pairs_per_level"] == st["m2l_pairs_per_level"]
+    assert inf["n_p2p_leaf_pairs"] == st["n_p2p_leaf_pairs"]
+    assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
+    pl.destroy()

@@ -392,6 +392,27 @@ def test_leaf_rule_mean_over_nonempty(ref):
     s1 = ref.tree_shape(pos, 4, leaf_target=8, box=box, leaf_rule=1)
     assert s0["levels"] == int(np.argmin([abs(4000 / 2 ** L - 8) for L in range(25)]))
     assert s1["levels"] >= s0["levels"]
+    # occupied smallest cells counted directly (numpy unique over the cell
+    # indices of the halving sequence), then the argmin of the rule
+    lo, hi = np.asarray(box[0], float), np.asarray(box[1], float)
+    W = hi - lo
+
+    def occupied(L):
+        h, k = W.copy(), np.zeros(3, dtype=np.int64)
+        for _ in range(L):
+            a = 0
+            if h[1] > h[a]:
+                a = 1
+            if h[2] > h[a]:
+                a = 2
+            h[a] /= 2.0
+            k[a] += 1
+        c = np.floor((pos - lo) * (2.0 ** k) / W).astype(np.int64)
+        c = np.minimum(np.maximum(c, 0), (1 << k) - 1)
+        return len(np.unique(c, axis=0))
+
+    d = [abs(4000 / occupied(L) - 8) for L in range(25)]
+    assert s1["levels"] == int(np.argmin(d))
 
 
 def test_invalid_inputs(ref):
