@@ -69,8 +69,8 @@ typedef struct {
                              (position inside their ancestors) before tiling; 0..12 */
   int32_t m2l_variant;    /* M2L kernel: 0 = block of 4 wavefronts sharing one operator per
                              step (64-column tiles), 1 = independent wavefronts (16 columns,
-                             orders <= 6), 2 / 3 = wide blocks with a double-buffered
-                             operator (256 / 128 columns; mixed precision, orders <= 6).
+                             orders <= 6), 2 / 3 / 4 = wide blocks with a double-buffered
+                             operator (256 / 128 / 64 columns; mixed precision, orders <= 6).
                              A variant the order or precision cannot use falls back to 0;
                              ccfmm_plan_autotune can choose */
   int32_t use_graph;      /* 1: evaluations are captured once into a HIP graph (per batch size

@@ -636,7 +636,7 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
     CCFMM_HIP(hipEventCreate(&e0));
     CCFMM_HIP(hipEventCreate(&e1));
     std::vector<ccfmm_tune_entry> res;
-    const int variants[4] = {kM2LBlock, kM2LWave, kM2LWide4, kM2LWide2};
+    const int variants[5] = {kM2LBlock, kM2LWave, kM2LWide4, kM2LWide2, kM2LWide1};
     const int bits[3] = {0, 3, 6};
     for (int v : variants) {
       if (!m2l_variant_ok(v, P.p, P.precision == CCFMM_PREC_FP64)) continue;

@@ -28,6 +28,7 @@ constexpr int kM2LBlock = 0;
 constexpr int kM2LWave = 1;
 constexpr int kM2LWide4 = 2;  // FP32, 256-column tiles
 constexpr int kM2LWide2 = 3;  // FP32, 128-column tiles
+constexpr int kM2LWide1 = 4;  // FP32, 64-column tiles
 inline int m2l_tile_cols(int variant) {
   return variant == kM2LWave ? 16 : variant == kM2LWide4 ? 256 : variant == kM2LWide2 ? 128 : 64;
 }
@@ -35,7 +36,7 @@ inline int m2l_tile_cols(int variant) {
 inline bool m2l_variant_ok(int variant, int order, bool fp64) {
   if (variant == kM2LBlock) return true;
   if (variant == kM2LWave) return order <= 6;
-  if (variant == kM2LWide4 || variant == kM2LWide2) return order <= 6 && !fp64;
+  if (variant == kM2LWide4 || variant == kM2LWide2 || variant == kM2LWide1) return order <= 6 && !fp64;
   return false;
 }
 

@@ -314,14 +314,34 @@ __device__ __forceinline__ int level_of_group(const TileLevels& T, int64_t b) {
   return l;
 }
 
-// sort key (level, low class bits of the cell key); the value is the global cell
-__global__ void k_tile_class_keys(TileLevels T, int64_t ncell, int cb, uint32_t* key, int32_t* val) {
+// sort key (level, low class bits of the cell key, 16-bit signature of the
+// cell's set of far offsets); the value is the global cell.  The signature is
+// an order-free hash (a sum of mixed offset ids), so cells with the same set
+// of offsets -- interior cells of one class, and boundary cells cut the same
+// way -- sort next to each other and share tiles without empty columns.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__global__ void k_tile_class_keys(TileLevels T, int64_t ncell, int cb, int sigbits, uint32_t* key, int32_t* val) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ncell) return;
   const int l = level_of_cell(T, i);
+  const TileLevel& lv = T.lv[l];
+  const int c = (int)(i - lv.cell0);
   const int cbl = min(cb, l);
-  const uint32_t cls = (uint32_t)T.lv[l].key[i - T.lv[l].cell0] & ((1u << cbl) - 1u);
-  key[i] = ((uint32_t)l << cb) | cls;
+  const uint32_t cls = (uint32_t)lv.key[c] & ((1u << cbl) - 1u);
+  uint32_t sig = 0;
+  if (sigbits && lv.far_ptr) {
+    uint32_t h = 0;
+    for (int e = lv.far_ptr[c]; e < lv.far_ptr[c + 1]; e++) h += mix32((uint32_t)lv.far_did[e] + 1u);
+    sig = h >> (32 - sigbits);
+  }
+  key[i] = ((((uint32_t)l << cb) | cls) << sigbits) | sig;
   val[i] = (int32_t)i;
 }
 
@@ -510,9 +530,10 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   uint32_t* skey2 = reinterpret_cast<uint32_t*>(sbuf + 2 * ncell);
   int32_t* sval2 = sbuf + 3 * ncell;
   int32_t* inv = sbuf + 4 * ncell;
-  k_tile_class_keys<<<ceil_div(ncell, T), T, 0, st>>>(TL, ncell, cb, skey, sorted);
+  const int sigbits = P.tile_signature ? 16 : 0;
+  k_tile_class_keys<<<ceil_div(ncell, T), T, 0, st>>>(TL, ncell, cb, sigbits, skey, sorted);
   CCFMM_HIP(hipGetLastError());
-  radix_sort_pairs(skey, sorted, skey2, sval2, ncell, cb + lbits, P.scratch, st);
+  radix_sort_pairs(skey, sorted, skey2, sval2, ncell, cb + lbits + sigbits, P.scratch, st);
   k_tile_inverse<<<ceil_div(ncell, T), T, 0, st>>>(sorted, ncell, inv);
   CCFMM_HIP(hipGetLastError());
   // bitmaps, ranks and step counts of every group; global step offsets

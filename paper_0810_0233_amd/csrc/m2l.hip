@@ -489,21 +489,24 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
   const T* D = std::is_same<T, double>::value ? (const T*)P.Dd.p : (const T*)P.Df.p;
   if (P.ntiles == 0) return;
   if constexpr (std::is_same<T, float>::value && PP <= 6) {
-    if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2) {
-      const int64_t nblk = P.ntiles;
+    if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1) {
+      const unsigned nblk = (unsigned)P.ntiles;
+#define CCFMM_WIDE(CB)                                                                                               \
+  k_m2l_wide<PP, CB><<<nblk, 256, 0, st>>>(P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles,            \
+                                           P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),                    \
+                                           P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC)
       if (P.tiles_variant == kM2LWide4)
-        k_m2l_wide<PP, 4><<<(unsigned)nblk, 256, 0, st>>>(
-            P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),
-            P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
+        CCFMM_WIDE(4);
+      else if (P.tiles_variant == kM2LWide2)
+        CCFMM_WIDE(2);
       else
-        k_m2l_wide<PP, 2><<<(unsigned)nblk, 256, 0, st>>>(
-            P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),
-            P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC);
+        CCFMM_WIDE(1);
+#undef CCFMM_WIDE
       CCFMM_HIP(hipGetLastError());
       return;
     }
   }
-  if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2)
+  if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1)
     fail(CCFMM_EINVAL, "wide M2L variants need mixed precision and order <= 6");
   if (P.tiles_variant == kM2LWave) {
     if constexpr (PP <= 6) {

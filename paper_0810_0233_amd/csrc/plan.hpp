@@ -79,6 +79,7 @@ struct Plan {
   DevBuf tile_order;  // launch order of the M2L tiles: longest step list first (+ sort temporaries)
   DevBuf tile_sort;   // target ordering of all levels (keys, order, temporaries, inverse)
   DevBuf near_tmp;    // reordering buffer of the smallest level's near lists
+  bool tile_signature = true;  // M2L targets also grouped by their set of far offsets
   int64_t ntiles = 0, nsteps = 0;
   // P2P chunks (built on the device; their count stays in device memory)
   DevBuf chunks, chunk_cnt;

@@ -204,7 +204,7 @@ def test_m2l_variants_and_autotune_agree(ref, precision):
     pos, box = inputs.ferrofluid(12000, 21)
     m = inputs.random_moments(12000, 22)
     base = None
-    variants = (0, 1) if precision == ccfmm.PREC_FP64 else (0, 1, 2, 3)
+    variants = (0, 1) if precision == ccfmm.PREC_FP64 else (0, 1, 2, 3, 4)
     for variant in variants:
         for cb in (0, 3, 6):
             H = plan_for(pos, 6, 0.5, 0.0, box, precision=precision, m2l_variant=variant,
@@ -240,15 +240,15 @@ def test_wide_m2l_variants(order):
     nb = 3
     m = np.stack([inputs.random_moments(9000, 40 + order + b) for b in range(nb)])
     H = {}
-    for variant in (0, 2, 3):
+    for variant in (0, 2, 3, 4):
         pl = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=nb, m2l_variant=variant,
                       m2l_class_bits=3)
         assert pl.info()["m2l_variant"] == variant
         H[variant] = pl.eval(m)
         pl.destroy()
-    errs = {v: rel_rms(H[v], H[0]) for v in (2, 3)}
+    errs = {v: rel_rms(H[v], H[0]) for v in (2, 3, 4)}
     print("order %d wide-vs-block %s" % (order, errs), flush=True)
-    for variant in (2, 3):
+    for variant in (2, 3, 4):
         assert errs[variant] <= 1e-6
     p64 = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_FP64, max_batch=nb, m2l_variant=2)
     assert p64.info()["m2l_variant"] == 0
