@@ -75,6 +75,9 @@ typedef struct {
                              ccfmm_plan_autotune can choose */
   int32_t use_graph;      /* 1: evaluations are captured once into a HIP graph (per batch size
                              and buffer pair) and replayed; 0: plain stream launches */
+  int32_t overlap_near;   /* 1 (default): the near field runs on a plan-owned second stream
+                             (default priority) beside P2M..L2L, joined before L2P;
+                             0: everything on the caller's stream, near field and L2P fused */
 } ccfmm_params;
 
 /* One timed M2L configuration of ccfmm_plan_autotune. */
@@ -106,9 +109,12 @@ typedef struct {
   int32_t m2l_variant;                  /* kernel in use (see ccfmm_params) */
 } ccfmm_info;
 
-/* Per-pass device times (milliseconds) of one evaluation, from HIP events. */
+/* Per-pass device times (milliseconds) of one evaluation, from HIP events.
+ * p2m includes the moment permutation; p2p is the near field (on the plan's
+ * side stream when overlap_near is on, so it overlaps m2m..l2l); l2p adds the
+ * smooth field (0 when fused into p2p); total spans the whole evaluation. */
 typedef struct {
-  double p2m, m2m, m2l, l2l, p2p_l2p, total;
+  double p2m, m2m, m2l, l2l, p2p, l2p, total;
 } ccfmm_pass_times;
 
 const char* ccfmm_status_string(int status);

@@ -203,13 +203,17 @@ static void size_expansions(Plan& P, int nb) {
   P.qv_batch = nb;
 }
 
-__global__ void k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr, const int32_t* near_idx,
-                                  const int32_t* lcount, unsigned long long* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per smallest cell: its dipoles times the dipoles of its near cells
+__global__ void __launch_bounds__(256) k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr,
+                                                         const int32_t* near_idx, const int32_t* lcount,
+                                                         unsigned long long* out) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= nl) return;
   long long s = 0;
-  for (int e = near_ptr[i]; e < near_ptr[i + 1]; e++) s += lcount[near_idx[e]];
-  atomicAdd(out, (unsigned long long)(s * lcount[i]));
+  for (int e = near_ptr[i] + lane; e < near_ptr[i + 1]; e += 64) s += lcount[near_idx[e]];
+  for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off);
+  if (lane == 0) atomicAdd(out, (unsigned long long)(s * lcount[i]));
 }
 
 // scattered device counters gathered into one small array (one copy back);
@@ -247,7 +251,7 @@ static void fill_info(Plan& P, hipStream_t st) {
   {
     LevelData& D = *P.lev[L];
     unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(dbuf + cidx);
-    k_count_p2p_pairs<<<ceil_div(D.ncells, 256), 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
+    k_count_p2p_pairs<<<ceil_div(D.ncells, 4), 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
                                                                D.near_idx.as<int32_t>(), P.lcount.as<int32_t>(), dcnt);
     CCFMM_HIP(hipGetLastError());
   }
@@ -401,8 +405,31 @@ static void eval_run(Plan& P, int nb, const double* d_m, double* d_H, hipStream_
   CCFMM_HIP(hipGraphLaunch(P.gexec, st));
 }
 
+static void ensure_side_stream(Plan& P) {
+  if (P.side) return;
+  CCFMM_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+  CCFMM_HIP(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming));
+  CCFMM_HIP(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming));
+}
+
+// The passes of one evaluation.  With overlap, the near field (VALU-bound)
+// runs on the plan's side stream while P2M, M2M, M2L (MFMA-bound) and L2L run
+// on the caller's stream; the smooth field is added after the join.  Timing
+// events (ev, 9 of them): [0] start, [1] after P2M, [2] after M2M, [3] after
+// M2L, [4] after L2L, [8] L2P start, [5] end, all on the caller's stream;
+// [6], [7] around the near field.
 static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev) {
   if (ev) CCFMM_HIP(hipEventRecord(ev[0], st));
+  run_permute(P, nb, d_m, st);
+  if (P.overlap) {
+    ensure_side_stream(P);
+    CCFMM_HIP(hipEventRecord(P.ev_fork, st));
+    CCFMM_HIP(hipStreamWaitEvent(P.side, P.ev_fork, 0));
+    if (ev) CCFMM_HIP(hipEventRecord(ev[6], P.side));
+    run_near(P, nb, d_H, P.side);
+    if (ev) CCFMM_HIP(hipEventRecord(ev[7], P.side));
+    CCFMM_HIP(hipEventRecord(P.ev_join, P.side));
+  }
   run_p2m(P, nb, d_m, st);
   if (ev) CCFMM_HIP(hipEventRecord(ev[1], st));
   run_m2m(P, nb, st);
@@ -411,7 +438,18 @@ static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStre
   if (ev) CCFMM_HIP(hipEventRecord(ev[3], st));
   run_l2l(P, nb, st);
   if (ev) CCFMM_HIP(hipEventRecord(ev[4], st));
-  run_p2p_l2p(P, nb, d_H, st);
+  if (P.overlap) {
+    CCFMM_HIP(hipStreamWaitEvent(st, P.ev_join, 0));
+    if (ev) CCFMM_HIP(hipEventRecord(ev[8], st));
+    run_l2p(P, nb, d_H, st);
+  } else {
+    if (ev) CCFMM_HIP(hipEventRecord(ev[6], st));
+    run_p2p_l2p(P, nb, d_H, st);
+    if (ev) {
+      CCFMM_HIP(hipEventRecord(ev[7], st));
+      CCFMM_HIP(hipEventRecord(ev[8], st));
+    }
+  }
   if (ev) CCFMM_HIP(hipEventRecord(ev[5], st));
 }
 
@@ -469,6 +507,7 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->precision = CCFMM_PREC_FP64;
   prm->selector = 0;
   prm->err_bound = 1e-5;
+  prm->overlap_near = 1;
   prm->has_box = 0;
   prm->max_batch = 1;
   prm->m2l_class_bits = 3;
@@ -498,6 +537,7 @@ static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const 
                           ? prm->m2l_variant
                           : kM2LBlock;
       P.use_graph = prm->use_graph != 0;
+      P.overlap = prm->overlap_near != 0;
       if (own) {
         CCFMM_HIP(hipStreamCreateWithFlags(&P.own_stream, hipStreamNonBlocking));
         st = P.own_stream;
@@ -576,20 +616,23 @@ int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
     prepare_batch(P, nbatch, st);
-    hipEvent_t ev[6];
-    for (int i = 0; i < 6; i++) CCFMM_HIP(hipEventCreate(&ev[i]));
+    hipEvent_t ev[9];
+    for (int i = 0; i < 9; i++) CCFMM_HIP(hipEventCreate(&ev[i]));
     eval_passes(P, nbatch, d_m, d_H, st, ev);
     CCFMM_HIP(hipEventSynchronize(ev[5]));
-    float ms[5];
-    for (int i = 0; i < 5; i++) CCFMM_HIP(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
-    float tot;
+    CCFMM_HIP(hipEventSynchronize(ev[7]));
+    float ms[4], near, l2p, tot;
+    for (int i = 0; i < 4; i++) CCFMM_HIP(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+    CCFMM_HIP(hipEventElapsedTime(&near, ev[6], ev[7]));
+    CCFMM_HIP(hipEventElapsedTime(&l2p, ev[8], ev[5]));
     CCFMM_HIP(hipEventElapsedTime(&tot, ev[0], ev[5]));
-    for (int i = 0; i < 6; i++) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 9; i++) (void)hipEventDestroy(ev[i]);
     times->p2m = ms[0];
     times->m2m = ms[1];
     times->m2l = ms[2];
     times->l2l = ms[3];
-    times->p2p_l2p = ms[4];
+    times->p2p = near;
+    times->l2p = l2p;
     times->total = tot;
     return CCFMM_OK;
   });
@@ -630,6 +673,7 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
     CCFMM_HIP(hipSetDevice(P.device));
     prepare_batch(P, nbatch, st);
     // the multipoles the timed launches read
+    run_permute(P, nbatch, d_m, st);
     run_p2m(P, nbatch, d_m, st);
     run_m2m(P, nbatch, st);
     hipEvent_t e0, e1;

@@ -391,15 +391,8 @@ static T* qptr(Plan& P, DevBuf& buf, int l) {
 
 template <typename T, int PP>
 static void p2m_impl(Plan& P, int nb, const double* d_m, hipStream_t st) {
+  (void)d_m;
   T* ms = P.m_sorted.as<T>();
-  dim3 g1(ceil_div(P.n, 256), nb);
-  k_permute_moments<T><<<g1, 256, 0, st>>>(d_m, P.perm.as<int32_t>(), P.n, nb, ms);
-  CCFMM_HIP(hipGetLastError());
-  if (nb >= P.batched_min) {
-    k_permute_moments_t<T><<<ceil_div(P.n * nb, 256), 256, 0, st>>>(d_m, P.perm.as<int32_t>(), P.n, nb,
-                                                                     P.m_sorted_t.as<T>());
-    CCFMM_HIP(hipGetLastError());
-  }
   const int nl = P.lev[P.L]->ncells;
   const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
   const int64_t items = (int64_t)nl * nb;
@@ -471,6 +464,27 @@ static void l2l_d(Plan& P, int nb, hipStream_t st) {
     l2l_impl<double, PP>(P, nb, st);
   else
     l2l_impl<float, PP>(P, nb, st);
+}
+
+// moments in sorted order (FP64 or FP32 per the plan): [config][3][n], plus
+// [n][3][config] for the batched near field
+template <typename T>
+static void permute_impl(Plan& P, int nb, const double* d_m, hipStream_t st) {
+  dim3 g1(ceil_div(P.n, 256), nb);
+  k_permute_moments<T><<<g1, 256, 0, st>>>(d_m, P.perm.as<int32_t>(), P.n, nb, P.m_sorted.as<T>());
+  CCFMM_HIP(hipGetLastError());
+  if (nb >= P.batched_min) {
+    k_permute_moments_t<T><<<ceil_div(P.n * nb, 256), 256, 0, st>>>(d_m, P.perm.as<int32_t>(), P.n, nb,
+                                                                     P.m_sorted_t.as<T>());
+    CCFMM_HIP(hipGetLastError());
+  }
+}
+
+void run_permute(Plan& P, int nb, const double* d_m, hipStream_t st) {
+  if (P.precision == CCFMM_PREC_FP64)
+    permute_impl<double>(P, nb, d_m, st);
+  else
+    permute_impl<float>(P, nb, d_m, st);
 }
 
 void run_p2m(Plan& P, int nb, const double* d_m, hipStream_t st) { CCFMM_DISPATCH_P(P.p, p2m_d, P, nb, d_m, st); }

@@ -327,22 +327,27 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
-__global__ void k_tile_class_keys(TileLevels T, int64_t ncell, int cb, int sigbits, uint32_t* key, int32_t* val) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per cell: the far list is read coalesced and the hash summed
+// across the lanes
+__global__ void __launch_bounds__(256) k_tile_class_keys(TileLevels T, int64_t ncell, int cb, int sigbits,
+                                                         uint32_t* key, int32_t* val) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= ncell) return;
   const int l = level_of_cell(T, i);
   const TileLevel& lv = T.lv[l];
   const int c = (int)(i - lv.cell0);
-  const int cbl = min(cb, l);
-  const uint32_t cls = (uint32_t)lv.key[c] & ((1u << cbl) - 1u);
-  uint32_t sig = 0;
-  if (sigbits && lv.far_ptr) {
-    uint32_t h = 0;
-    for (int e = lv.far_ptr[c]; e < lv.far_ptr[c + 1]; e++) h += mix32((uint32_t)lv.far_did[e] + 1u);
-    sig = h >> (32 - sigbits);
+  uint32_t h = 0;
+  if (sigbits && lv.far_ptr)
+    for (int e = lv.far_ptr[c] + lane; e < lv.far_ptr[c + 1]; e += 64) h += mix32((uint32_t)lv.far_did[e] + 1u);
+  for (int off = 1; off < 64; off <<= 1) h += (uint32_t)__shfl_xor((int)h, off);
+  if (lane == 0) {
+    const int cbl = min(cb, l);
+    const uint32_t cls = (uint32_t)lv.key[c] & ((1u << cbl) - 1u);
+    const uint32_t sig = sigbits ? h >> (32 - sigbits) : 0u;
+    key[i] = ((((uint32_t)l << cb) | cls) << sigbits) | sig;
+    val[i] = (int32_t)i;
   }
-  key[i] = ((((uint32_t)l << cb) | cls) << sigbits) | sig;
-  val[i] = (int32_t)i;
 }
 
 __global__ void k_tile_inverse(const int32_t* sorted, int64_t ncell, int32_t* inv) {
@@ -531,7 +536,7 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   int32_t* sval2 = sbuf + 3 * ncell;
   int32_t* inv = sbuf + 4 * ncell;
   const int sigbits = P.tile_signature ? 16 : 0;
-  k_tile_class_keys<<<ceil_div(ncell, T), T, 0, st>>>(TL, ncell, cb, sigbits, skey, sorted);
+  k_tile_class_keys<<<ceil_div(ncell, 4), T, 0, st>>>(TL, ncell, cb, sigbits, skey, sorted);
   CCFMM_HIP(hipGetLastError());
   radix_sort_pairs(skey, sorted, skey2, sval2, ncell, cb + lbits + sigbits, P.scratch, st);
   k_tile_inverse<<<ceil_div(ncell, T), T, 0, st>>>(sorted, ncell, inv);

@@ -178,7 +178,10 @@ __device__ __forceinline__ void l2p_write(const T* __restrict__ v, int pl, T yx,
   Ho[2] = s3 * (hz - (double)ez);
 }
 
-template <typename T, int P>
+// kL2P: also add the smooth field of the cell's local expansion (one pass);
+// without it the kernel writes the near field alone and the smooth part is
+// added later by k_l2p_batched (so the near field can run beside M2L).
+template <typename T, int P, bool kL2P>
 __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
                                                            const T* __restrict__ msort, const T* __restrict__ V,
                                                            double* __restrict__ H) {
@@ -368,18 +371,35 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
     hy2 += __shfl_xor(hy2, off);
     hz2 += __shfl_xor(hz2, off);
   }
-  const T* v = V + a.voff + ((int64_t)ch.leaf * a.nb + b) * NS;
-  const int pl = a.leaf_p ? a.leaf_p[ch.leaf] : P;
   const double s3 = a.inv_s3;
-  if (sub1 == 0) l2p_write<T, P>(v, pl, x1, y1, z1, hx1, hy1, hz1, s3, H + ((int64_t)b * n + a.perm[i1]) * 3);
-  if (act2 && sub2 == 0)
-    l2p_write<T, P>(v, pl, x2, y2, z2, hx2, hy2, hz2, s3, H + ((int64_t)b * n + a.perm[i2]) * 3);
+  if constexpr (kL2P) {
+    const T* v = V + a.voff + ((int64_t)ch.leaf * a.nb + b) * NS;
+    const int pl = a.leaf_p ? a.leaf_p[ch.leaf] : P;
+    if (sub1 == 0) l2p_write<T, P>(v, pl, x1, y1, z1, hx1, hy1, hz1, s3, H + ((int64_t)b * n + a.perm[i1]) * 3);
+    if (act2 && sub2 == 0)
+      l2p_write<T, P>(v, pl, x2, y2, z2, hx2, hy2, hz2, s3, H + ((int64_t)b * n + a.perm[i2]) * 3);
+  } else {
+    (void)V;
+    (void)NS;
+    if (sub1 == 0) {
+      double* o = H + ((int64_t)b * n + a.perm[i1]) * 3;
+      o[0] = s3 * hx1;
+      o[1] = s3 * hy1;
+      o[2] = s3 * hz1;
+    }
+    if (act2 && sub2 == 0) {
+      double* o = H + ((int64_t)b * n + a.perm[i2]) * 3;
+      o[0] = s3 * hx2;
+      o[1] = s3 * hy2;
+      o[2] = s3 * hz2;
+    }
+  }
 }
 
 // ------------------------------------------------------------ batched form
 // Smooth field for many configurations: one thread per (dipole, configuration),
 // written (FP64, caller order) before the batched near field adds to it.
-template <typename T, int P>
+template <typename T, int P, bool kAdd>
 __global__ void k_l2p_batched(int64_t n, int nb, const int32_t* __restrict__ dleaf, const int32_t* __restrict__ perm,
                               const T* __restrict__ y, const T* __restrict__ V, int64_t voff, double inv_s3,
                               const int32_t* __restrict__ leaf_p, double* __restrict__ H) {
@@ -411,9 +431,15 @@ __global__ void k_l2p_batched(int64_t n, int nb, const int32_t* __restrict__ dle
     ez += v[midx(kx, ky, kz + 1) - 1] * mono;
   }
   const int64_t o = ((int64_t)b * n + perm[i]) * 3;
-  H[o] = -inv_s3 * (double)ex;
-  H[o + 1] = -inv_s3 * (double)ey;
-  H[o + 2] = -inv_s3 * (double)ez;
+  if (kAdd) {  // the near field is already there
+    H[o] -= inv_s3 * (double)ex;
+    H[o + 1] -= inv_s3 * (double)ey;
+    H[o + 2] -= inv_s3 * (double)ez;
+  } else {
+    H[o] = -inv_s3 * (double)ex;
+    H[o + 1] = -inv_s3 * (double)ey;
+    H[o + 2] = -inv_s3 * (double)ez;
+  }
 }
 
 // Near field for many configurations on the matrix cores.  For a chunk of
@@ -545,49 +571,12 @@ __global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* 
       const int t = m / 3, aa = m % 3;
       if (t < ch.count) {
         const int64_t o = ((int64_t)b * n + a.perm[ch.first + t]) * 3 + aa;
-        H[o] += a.inv_s3 * acc64[mb][r];
+        H[o] = a.inv_s3 * acc64[mb][r];  // first writer: the smooth part is added afterwards
       }
     }
 }
 
-template <typename T, int PP>
-static void p2p_batched_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
-  LevelData& D = *P.lev[P.L];
-  const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
-  const double s = P.geo.lev[P.L].s;
-  const double inv_s3 = 1.0 / (s * s * s);
-  k_l2p_batched<T, PP><<<ceil_div(P.n * nb, 256), 256, 0, st>>>(P.n, nb, P.dleaf.as<int32_t>(), P.perm.as<int32_t>(),
-                                                                y, P.V.as<T>(), D.qoff, inv_s3,
-                                                                P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr, d_H);
-  CCFMM_HIP(hipGetLastError());
-  P2PArgs a;
-  a.chunks = nullptr;
-  a.nchunks = 0;
-  a.near_ptr = D.near_ptr.as<int32_t>();
-  a.near_idx = D.near_idx.as<int32_t>();
-  a.coord = D.coord.as<int32_t>();
-  a.lstart = P.lstart.as<int32_t>();
-  a.lcount = P.lcount.as<int32_t>();
-  a.perm = P.perm.as<int32_t>();
-  a.n = P.n;
-  a.nb = nb;
-  for (int q = 0; q < 3; q++) a.g[q] = P.geo.lev[P.L].g[q];
-  a.inv_s3 = inv_s3;
-  a.voff = D.qoff;
-  a.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
-  a.ylo = std::is_same<T, double>::value ? nullptr : P.yf.as<float>() + 3 * P.n;
-  if (P.nchunks32 == 0) return;
-  dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
-  k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(), d_H);
-  CCFMM_HIP(hipGetLastError());
-}
-
-template <typename T, int PP>
-static void p2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
-  if (nb >= P.batched_min) {
-    p2p_batched_impl<T, PP>(P, nb, d_H, st);
-    return;
-  }
+static P2PArgs p2p_args(Plan& P, int nb, bool fp64) {
   LevelData& D = *P.lev[P.L];
   P2PArgs a;
   a.chunks = P.chunks.as<P2PChunk>();
@@ -605,34 +594,93 @@ static void p2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   a.inv_s3 = 1.0 / (s * s * s);
   a.voff = D.qoff;
   a.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
-  a.ylo = std::is_same<T, double>::value ? nullptr : P.yf.as<float>() + 3 * P.n;
+  a.ylo = fp64 ? nullptr : P.yf.as<float>() + 3 * P.n;
+  return a;
+}
+
+// near field alone: written (not added) to H in the caller's order
+template <typename T, int PP>
+static void near_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
+  const bool fp64 = std::is_same<T, double>::value;
+  const T* y = fp64 ? (const T*)P.yd.p : (const T*)P.yf.p;
+  P2PArgs a = p2p_args(P, nb, fp64);
+  if (nb >= P.batched_min) {
+    if (P.nchunks32 == 0) return;
+    dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
+    k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(), d_H);
+  } else {
+    dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
+    k_p2p_l2p<T, PP, false><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
+  }
+  CCFMM_HIP(hipGetLastError());
+}
+
+// smooth field of the local expansions, added to the near field in H
+template <typename T, int PP>
+static void l2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
+  const double s = P.geo.lev[P.L].s;
+  k_l2p_batched<T, PP, true><<<ceil_div(P.n * nb, 256), 256, 0, st>>>(
+      P.n, nb, P.dleaf.as<int32_t>(), P.perm.as<int32_t>(), y, P.V.as<T>(), P.lev[P.L]->qoff, 1.0 / (s * s * s),
+      P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr, d_H);
+  CCFMM_HIP(hipGetLastError());
+}
+
+// both in one pass (single stream, one configuration at a time)
+template <typename T, int PP>
+static void fused_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
+  if (nb >= P.batched_min) {
+    near_impl<T, PP>(P, nb, d_H, st);
+    l2p_impl<T, PP>(P, nb, d_H, st);
+    return;
+  }
+  const bool fp64 = std::is_same<T, double>::value;
+  const T* y = fp64 ? (const T*)P.yd.p : (const T*)P.yf.p;
+  P2PArgs a = p2p_args(P, nb, fp64);
   dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
-  k_p2p_l2p<T, PP><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
+  k_p2p_l2p<T, PP, true><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
   CCFMM_HIP(hipGetLastError());
 }
 
 template <int PP>
-static void p2p_d(Plan& P, int nb, double* d_H, hipStream_t st) {
+static void near_d(Plan& P, int nb, double* d_H, hipStream_t st) {
   if (P.precision == CCFMM_PREC_FP64)
-    p2p_impl<double, PP>(P, nb, d_H, st);
+    near_impl<double, PP>(P, nb, d_H, st);
   else
-    p2p_impl<float, PP>(P, nb, d_H, st);
+    near_impl<float, PP>(P, nb, d_H, st);
+}
+template <int PP>
+static void l2p_d(Plan& P, int nb, double* d_H, hipStream_t st) {
+  if (P.precision == CCFMM_PREC_FP64)
+    l2p_impl<double, PP>(P, nb, d_H, st);
+  else
+    l2p_impl<float, PP>(P, nb, d_H, st);
+}
+template <int PP>
+static void fused_d(Plan& P, int nb, double* d_H, hipStream_t st) {
+  if (P.precision == CCFMM_PREC_FP64)
+    fused_impl<double, PP>(P, nb, d_H, st);
+  else
+    fused_impl<float, PP>(P, nb, d_H, st);
 }
 
-void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st) {
-  switch (P.p) {
-    case 1: p2p_d<1>(P, nb, d_H, st); break;
-    case 2: p2p_d<2>(P, nb, d_H, st); break;
-    case 3: p2p_d<3>(P, nb, d_H, st); break;
-    case 4: p2p_d<4>(P, nb, d_H, st); break;
-    case 5: p2p_d<5>(P, nb, d_H, st); break;
-    case 6: p2p_d<6>(P, nb, d_H, st); break;
-    case 7: p2p_d<7>(P, nb, d_H, st); break;
-    case 8: p2p_d<8>(P, nb, d_H, st); break;
-    default: fail(CCFMM_EINVAL, "order out of range");
+#define CCFMM_P2P_DISPATCH(FN)                                \
+  switch (P.p) {                                              \
+    case 1: FN<1>(P, nb, d_H, st); break;                     \
+    case 2: FN<2>(P, nb, d_H, st); break;                     \
+    case 3: FN<3>(P, nb, d_H, st); break;                     \
+    case 4: FN<4>(P, nb, d_H, st); break;                     \
+    case 5: FN<5>(P, nb, d_H, st); break;                     \
+    case 6: FN<6>(P, nb, d_H, st); break;                     \
+    case 7: FN<7>(P, nb, d_H, st); break;                     \
+    case 8: FN<8>(P, nb, d_H, st); break;                     \
+    default: fail(CCFMM_EINVAL, "order out of range");        \
   }
-}
+
+void run_near(Plan& P, int nb, double* d_H, hipStream_t st) { CCFMM_P2P_DISPATCH(near_d) }
+void run_l2p(Plan& P, int nb, double* d_H, hipStream_t st) { CCFMM_P2P_DISPATCH(l2p_d) }
+void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st) { CCFMM_P2P_DISPATCH(fused_d) }
+#undef CCFMM_P2P_DISPATCH
 
 // ------------------------------------------------------------ direct sum
 // FP64 O(N) per target: the plain definition of the field at sampled targets,

@@ -52,6 +52,11 @@ struct Plan {
   double s_used = 0.0;
   TreeGeom geo{};
   hipStream_t own_stream = nullptr;
+  // the near field runs on a second stream beside the expansion passes
+  // (forked after the moment permutation, joined before L2P)
+  bool overlap = true;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // sorted dipoles
   DevBuf pos;        // [n][3] FP64 input order (device copy)
@@ -121,7 +126,12 @@ struct Plan {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     gexec = nullptr;
   }
-  ~Plan() { drop_graph(); }
+  ~Plan() {
+    drop_graph();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 // build steps (tree.hip, lists.hip, expansions.hip)
@@ -138,7 +148,10 @@ void run_p2m(Plan& P, int nb, const double* d_m, hipStream_t st);
 void run_m2m(Plan& P, int nb, hipStream_t st);
 void run_m2l(Plan& P, int nb, hipStream_t st);
 void run_l2l(Plan& P, int nb, hipStream_t st);
-void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st);
+void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st);  // near + smooth field, one stream
+void run_near(Plan& P, int nb, double* d_H, hipStream_t st);     // near field written to H
+void run_l2p(Plan& P, int nb, double* d_H, hipStream_t st);      // smooth field added to H
+void run_permute(Plan& P, int nb, const double* d_m, hipStream_t st);
 void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt,
                         const int64_t* d_idx, double* d_H, hipStream_t st);
 

@@ -79,68 +79,57 @@ __global__ void k_finish_total(int32_t* out, int64_t n, const int32_t* last) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n > 0) ? out[n - 1] + last[0] : 0;
 }
 
-// One block scans up to kScanSingleMax values in a single launch: each of
-// 1024 threads owns a contiguous run, the run sums are scanned in LDS, and the
-// total lands in out[n] (out may alias in).
+// One block scans up to kScanSingleMax values in a single launch, in chunks of
+// 4096: each of 1024 threads loads 4 consecutive values (coalesced across the
+// block), the 1024 partial sums are scanned in LDS, and a running carry links
+// the chunks.  The total lands in out[n] (out may alias in).
 constexpr int kScanSingleThreads = 1024;
 constexpr int64_t kScanSingleMax = 64 * kScanSingleThreads;
 
-__global__ void __launch_bounds__(kScanSingleThreads) k_scan_single(const int32_t* in, int32_t* out, int64_t n) {
+__device__ __forceinline__ void scan_single_block(const int32_t* in, int32_t* out, int64_t n) {
   __shared__ int32_t sh[kScanSingleThreads];
+  __shared__ int32_t carry_sh;
   const int t = threadIdx.x;
-  const int per = (int)((n + kScanSingleThreads - 1) / kScanSingleThreads);
-  const int64_t b = (int64_t)t * per;
-  int32_t s = 0;
-  for (int i = 0; i < per; i++)
-    if (b + i < n) s += in[b + i];
-  sh[t] = s;
-  __syncthreads();
-  for (int off = 1; off < kScanSingleThreads; off <<= 1) {
-    const int32_t add = (t >= off) ? sh[t - off] : 0;
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += 4 * kScanSingleThreads) {
+    const int64_t b = c0 + 4 * t;
+    int32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) v[i] = (b + i < n) ? in[b + i] : 0;
+    const int32_t s = v[0] + v[1] + v[2] + v[3];
+    sh[t] = s;
     __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  int32_t ex = sh[t] - s;
-  for (int i = 0; i < per; i++) {
-    if (b + i < n) {
-      const int32_t v = in[b + i];
-      out[b + i] = ex;
-      ex += v;
+    for (int off = 1; off < kScanSingleThreads; off <<= 1) {
+      const int32_t add = (t >= off) ? sh[t - off] : 0;
+      __syncthreads();
+      sh[t] += add;
+      __syncthreads();
     }
+    int32_t ex = carry + sh[t] - s;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      if (b + i < n) out[b + i] = ex;
+      ex += v[i];
+    }
+    if (t == kScanSingleThreads - 1) carry_sh = carry + sh[t];
+    __syncthreads();
+    carry = carry_sh;
+    __syncthreads();
   }
-  if (t == kScanSingleThreads - 1) out[n] = sh[t];
+  if (t == 0) out[n] = carry;
 }
 
-// two arrays of the same length scanned in one launch (two blocks)
+__global__ void __launch_bounds__(kScanSingleThreads) k_scan_single(const int32_t* in, int32_t* out, int64_t n) {
+  scan_single_block(in, out, n);
+}
+
+// two arrays of the same length scanned in one launch (one block each)
 __global__ void __launch_bounds__(kScanSingleThreads) k_scan_single2(const int32_t* in0, int32_t* out0,
                                                                      const int32_t* in1, int32_t* out1, int64_t n) {
-  __shared__ int32_t sh[kScanSingleThreads];
-  const int32_t* in = blockIdx.x ? in1 : in0;
-  int32_t* out = blockIdx.x ? out1 : out0;
-  const int t = threadIdx.x;
-  const int per = (int)((n + kScanSingleThreads - 1) / kScanSingleThreads);
-  const int64_t b = (int64_t)t * per;
-  int32_t s = 0;
-  for (int i = 0; i < per; i++)
-    if (b + i < n) s += in[b + i];
-  sh[t] = s;
-  __syncthreads();
-  for (int off = 1; off < kScanSingleThreads; off <<= 1) {
-    const int32_t add = (t >= off) ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  int32_t ex = sh[t] - s;
-  for (int i = 0; i < per; i++) {
-    if (b + i < n) {
-      const int32_t v = in[b + i];
-      out[b + i] = ex;
-      ex += v;
-    }
-  }
-  if (t == kScanSingleThreads - 1) out[n] = sh[t];
+  if (blockIdx.x == 0)
+    scan_single_block(in0, out0, n);
+  else
+    scan_single_block(in1, out1, n);
 }
 
 void scan_exclusive2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1, int64_t n, DevBuf& tmp,

@@ -116,7 +116,7 @@ def cost_ratio(plan, d_m, d_H, stream, repeats=3):
     inf = plan.info()
     t = [plan.eval_device_timed(1, d_m, d_H, stream) for _ in range(repeats)]
     m2l = float(np.median([x["m2l"] for x in t]))
-    p2p = float(np.median([x["p2p_l2p"] for x in t]))
+    p2p = float(np.median([x["p2p"] for x in t]))
     per_m2l = m2l / max(1, inf["n_m2l_pairs"])
     per_p2p = p2p / max(1.0, inf["p2p_pairs_per_config"])
     return per_m2l / per_p2p

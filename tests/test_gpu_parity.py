@@ -366,3 +366,32 @@ def test_leaf_rule_occupied_mean(ref, geom):
     assert inf["n_p2p_leaf_pairs"] == st["n_p2p_leaf_pairs"]
     assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
     pl.destroy()
+
+
+@pytest.mark.parametrize("nb", [1, 40])
+def test_overlapped_near_field_equals_single_stream(nb):
+    """The near field on the side stream beside the expansion passes (joined
+    before the smooth part is added) gives the field of the single-stream
+    evaluation, through graph replays too, for one and for many configurations."""
+    import torch
+
+    pos, box = inputs.ferrofluid(8000, 41)
+    m = np.stack([inputs.random_moments(8000, 300 + b) for b in range(nb)])
+    out = {}
+    for ov in (0, 1):
+        pl = plan_for(pos, 5, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=nb, overlap_near=ov)
+        dev = torch.device("cuda:0")
+        st = torch.cuda.current_stream().cuda_stream
+        d_m = torch.from_numpy(m).to(dev)
+        d_H = torch.empty_like(d_m)
+        res = []
+        for _ in range(3):
+            pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
+            torch.cuda.synchronize()
+            res.append(d_H.cpu().numpy().copy())
+        t = pl.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), st)
+        assert t["p2p"] > 0 and t["total"] > 0
+        assert all(np.array_equal(r, res[0]) for r in res[1:])
+        out[ov] = res[0]
+        pl.destroy()
+    assert rel_rms(out[1], out[0]) <= 1e-12
