@@ -101,7 +101,7 @@ def pass_work(info, n, nb, order):
         "m2l": {"kernel": "k_m2l<float,%d>" % order if info["m2l_variant"] == 0 else "k_m2l_wave<float,%d>" % order,
                 "bound": "mfma", "bytes": 2.0 * cells * exp_b, "flops": info["m2l_flops_per_config"] * nb},
         "l2l": {"kernel": "k_l2l<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
-        "p2p": {"kernel": ("k_p2p_batched<float>" if batched else "k_p2p_l2p<float,%d,false>" % order),
+        "p2p": {"kernel": ("k_p2p_batched<float>" if batched else "k_p2p_l2p<float,%d,true>" % order),
                 "bound": "mfma" if batched else "alu",
                 "bytes": n * 24.0 + n * nb * 24.0,
                 "flops": (18.0 if batched else 30.0) * pairs * nb},
@@ -169,8 +169,8 @@ def bench_clusters(args, torch, ccfmm, inputs):
     d_H = torch.empty_like(d_m)
     d_P = torch.from_numpy(params).to(dev)
 
-    def make(prec):
-        prm = ccfmm.params(order=6, theta=0.4, leaf_target=0.0, box=box, precision=prec, max_batch=1)
+    def make(prec, **kw):
+        prm = ccfmm.params(order=6, theta=0.4, leaf_target=0.0, box=box, precision=prec, max_batch=1, **kw)
         return ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, sh)
 
     def timed(fn, steps, warmup):
@@ -211,7 +211,7 @@ def bench_clusters(args, torch, ccfmm, inputs):
         1e3 * t_fixed, 1e3 * t_learned, 1e3 * t_learned_eval, si["judge_err"], rc))
     out = {}
     if not args.skip_fp64:
-        p64 = make(ccfmm.PREC_FP64)
+        p64 = make(ccfmm.PREC_FP64, overlap_near=0)  # the plain form: one stream
         p64.autotune(1, d_m.data_ptr(), d_H.data_ptr(), sh)
 
         def fp64_step():
@@ -237,6 +237,7 @@ def bench_clusters(args, torch, ccfmm, inputs):
     out["eps_abs_fixed"] = rel_rms(H_fixed[0][idx], Hd)
     out["eps_abs_learned"] = rel_rms(H_learned[0][idx], Hd)
     kern = pass_work(learned_info, n, nb, 6)
+    kern["p2p"]["kernel"] = "k_p2p_l2p<float,6,false>"  # near field alone (overlapped evaluation)
     dom = "m2l" if passes["m2l"] >= passes["p2p"] else "p2p"
     ach = kern[dom]["flops"] / (passes[dom] * 1e-3)
     roof = {"kernel": kern[dom]["kernel"], "bound": kern[dom]["bound"], "achieved": ach / 1e12,
@@ -317,8 +318,8 @@ def main():
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
 
-    def make(prec):
-        prm = ccfmm.params(order=order, theta=theta, leaf_target=0.0, box=box, precision=prec, max_batch=nb)
+    def make(prec, **kw):
+        prm = ccfmm.params(order=order, theta=theta, leaf_target=0.0, box=box, precision=prec, max_batch=nb, **kw)
         return ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, sh)
 
     def time_steps(plan, out, rebuild, steps, warmup):
@@ -349,16 +350,24 @@ def main():
     log("mixed full step: %.3f ms" % (1e3 * t_step))
     t_eval = time_steps(plan, d_H, False, args.steps, args.warmup)
     log("mixed eval only: %.3f ms" % (1e3 * t_eval))
-    passes = [plan.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), sh) for _ in range(3)]
-    pt = {k: float(np.median([p[k] for p in passes])) for k in passes[0]}
-    log("mixed passes (ms): %s" % json.dumps({k: round(v, 4) for k, v in pt.items()}))
+    overlapped = plan.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
     torch.cuda.synchronize()
     H_mixed = d_H.cpu().numpy().copy()
+    # per-pass times of every kernel on its own: the same tiles and kernel
+    # variant, one stream, the near field and the smooth part fused
+    iso = make(ccfmm.PREC_MIXED, overlap_near=0, m2l_variant=info["m2l_variant"],
+               m2l_class_bits=info["m2l_class_bits"])
+    iso.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
+    passes = [iso.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), sh) for _ in range(3)]
+    pt = {k: float(np.median([p[k] for p in passes])) for k in passes[0]}
+    iso.destroy()
+    log("mixed passes, one stream (ms): %s" % json.dumps({k: round(v, 4) for k, v in pt.items()}))
+    log("mixed passes, near field overlapped (ms): %s" % json.dumps({k: round(v, 4) for k, v in overlapped.items()}))
 
     out = {}
     # ---- plain FP64 GPU FMM
     if not args.skip_fp64:
-        plan64 = make(ccfmm.PREC_FP64)
+        plan64 = make(ccfmm.PREC_FP64, overlap_near=0)  # the plain form: one stream
         plan64.autotune(nb, d_m.data_ptr(), d_H64.data_ptr(), sh)
         t_step64 = time_steps(plan64, d_H64, True, max(2, args.steps // 2), 1)
         t_eval64 = time_steps(plan64, d_H64, False, max(2, args.steps // 2), 1)
@@ -444,6 +453,7 @@ def main():
         "eval_only_evals_per_s": n * nb / t_eval,
         "eval_ms": 1e3 * t_eval,
         "passes_ms": pt,
+        "passes_overlapped_ms": overlapped,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
