@@ -262,7 +262,8 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
     int64_t j;   // its sorted index
     T ox, oy, oz;
   };
-  auto next_batch = [&](Batch& bt) {
+  auto next_batch = [&]() -> Batch {
+    Batch bt;
     bt.filled = 0;
     bt.self = false;
     bt.adj = false;
@@ -294,27 +295,19 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
         off = 0;
       }
     }
+    return bt;
   };
-  // the shifted position hi + o is rounded; with |o| >= |hi| (o a nonzero
-  // multiple of the cell side, |hi| at most half of it) its error is exactly
-  // hi - ((hi + o) - o), which joins the stored residual
-  auto shifted = [](T hi, T o, T& out, T& err) {
-    out = hi + o;
-    err = hi - (out - o);
-  };
-  auto load_src = [&](const Batch& bt, P2PSrc<T>& q, P2PLo<T>& ql) {
-    ql.x = ql.y = ql.z = ql.p = (T)0;
+  // A source shifted into the target cell's frame: hi + o is rounded; with
+  // |o| >= |hi| (o a nonzero multiple of the cell side, |hi| at most half of
+  // it) the rounding error is exactly hi - ((hi + o) - o), which joins the
+  // stored residual.  Returned by value (no address-taken temporaries).
+  auto load_src = [&](const Batch& bt) -> P2PSrc<T> {
+    P2PSrc<T> q;
     if (bt.valid) {
       const int64_t j = bt.j;
-      T ex, ey, ez;
-      shifted(y[j], bt.ox, q.x, ex);
-      shifted(y[n + j], bt.oy, q.y, ey);
-      shifted(y[2 * n + j], bt.oz, q.z, ez);
-      if (kLo && bt.adj) {
-        ql.x = ex + (T)a.ylo[j];
-        ql.y = ey + (T)a.ylo[n + j];
-        ql.z = ez + (T)a.ylo[2 * n + j];
-      }
+      q.x = y[j] + bt.ox;
+      q.y = y[n + j] + bt.oy;
+      q.z = y[2 * n + j] + bt.oz;
       q.mx = mb[j];
       q.my = mb[n + j];
       q.mz = mb[2 * n + j];
@@ -323,20 +316,31 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
       q.mx = q.my = q.mz = (T)0;
     }
     q.p0 = q.p1 = (T)0;
+    return q;
+  };
+  auto load_lo = [&](const Batch& bt, const P2PSrc<T>& q) -> P2PLo<T> {
+    P2PLo<T> l;
+    l.x = l.y = l.z = l.p = (T)0;
+    if (kLo && bt.adj && bt.valid) {
+      const int64_t j = bt.j;
+      l.x = (y[j] - (q.x - bt.ox)) + (T)a.ylo[j];
+      l.y = (y[n + j] - (q.y - bt.oy)) + (T)a.ylo[n + j];
+      l.z = (y[2 * n + j] - (q.z - bt.oz)) + (T)a.ylo[2 * n + j];
+    }
+    return l;
   };
   double hx1 = 0.0, hy1 = 0.0, hz1 = 0.0, hx2 = 0.0, hy2 = 0.0, hz2 = 0.0;  // near field, cell-relative units
-  Batch cur, nxt;
-  P2PSrc<T> qc, qn;
-  P2PLo<T> lc, ln;
-  next_batch(cur);
-  load_src(cur, qc, lc);
+  Batch cur = next_batch();
+  P2PSrc<T> qc = load_src(cur);
+  P2PLo<T> lc = load_lo(cur, qc);
   while (cur.filled > 0) {
     src[lane] = qc;
     if (kLo && cur.adj) srclo[lane] = lc;
     wave_lds_sync();
     // the next batch's loads fly while this one is summed
-    next_batch(nxt);
-    load_src(nxt, qn, ln);
+    const Batch nxt = next_batch();
+    const P2PSrc<T> qn = load_src(nxt);
+    const P2PLo<T> ln = load_lo(nxt, qn);
     const int nsrc = cur.filled;
     T fx1 = (T)0, fy1 = (T)0, fz1 = (T)0, fx2 = (T)0, fy2 = (T)0, fz2 = (T)0;
     if (cur.self) {
