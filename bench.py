@@ -101,7 +101,7 @@ def pass_work(info, n, nb, order):
         "m2l": {"kernel": "k_m2l<float,%d>" % order if info["m2l_variant"] == 0 else "k_m2l_wave<float,%d>" % order,
                 "bound": "mfma", "bytes": 2.0 * cells * exp_b, "flops": info["m2l_flops_per_config"] * nb},
         "l2l": {"kernel": "k_l2l<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
-        "p2p": {"kernel": ("k_p2p_batched<float>" if batched else "k_p2p_l2p<float,%d,true>" % order),
+        "p2p": {"kernel": ("k_p2p_mfma" if batched else "k_p2p_l2p<float,%d,true>" % order),
                 "bound": "mfma" if batched else "alu",
                 "bytes": n * 24.0 + n * nb * 24.0,
                 "flops": (18.0 if batched else 30.0) * pairs * nb},

@@ -580,6 +580,328 @@ __global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* 
     }
 }
 
+// FP32 form of the same product with the pair geometry off the critical path.
+// A chunk of <= 32 targets (96 rows) meets blocks of 32 source dipoles (96
+// contraction entries) packed from consecutive near cells and padded with null
+// sources (zero kernel), so a cell of 28 dipoles does not leave a ragged block.
+// Each wavefront owns 16 of the block's 64 configuration columns.  The pair
+// kernels of block i+1 are written by all four wavefronts into the other half
+// of a double-buffered LDS operator while the matrix cores multiply block i,
+// and the moments of block i+1 are loaded into registers meanwhile, so a block
+// costs a single barrier.  Separations always take the exact form
+// (hi_t - hi_s) + (lo_t - lo_s), whatever the cells.  Block products are added
+// into FP64 accumulators.
+//
+// Contraction order: in matrix step ks (0..23) lane group kq = lane / 16 holds
+// source s = 8 kq + ks / 3, component ks % 3.  Operator layout per buffer: the
+// fragment of row block mb, steps 4 k4 .. 4 k4 + 3 is one float4 per lane at
+// ((mb * 6 + k4) * 64 + lane) * 4.  The pair (t, s) is built by the lane with
+// t % 16 = lane % 16 of wavefront s / 8, whose 64 lanes then write 64 distinct
+// banks per store.
+constexpr int kMT = 32;  // target dipoles per chunk
+constexpr int kMS = 32;  // source dipoles per block
+
+// a slot of a source block (lane % 32 holds slot lane % 32): sorted index
+// (-1: null source) and the offset of its cell from the target cell
+struct MSlot {
+  int j;
+  float ox, oy, oz;
+};
+struct MBlock {
+  int filled;
+  MSlot s;
+};
+// one source of a thread's pairs as loaded: position, residual, cell offset
+struct MSrc {
+  float x, y, z, lx, ly, lz, ox, oy, oz;
+  int ok;
+};
+
+constexpr int kMK4 = 3 * kMS / 16;              // float4 groups of matrix steps (6)
+constexpr int kMNA = (3 * kMT / 16) * kMK4 * 256;  // operator words per buffer
+
+// One chunk with MBU of its six 16-row blocks in use (rows 3 count .. 95 hold
+// no target and are skipped).
+template <int MBU>
+__device__ __forceinline__ void p2p_mfma_chunk(const P2PArgs& a, const P2PChunk& ch, const float* __restrict__ y,
+                                               const float* __restrict__ mt, double* __restrict__ H,
+                                               float (*__restrict__ sA)[kMNA]) {
+  constexpr int KS = 3 * kMS / 4;  // 24 matrix steps per block
+  constexpr int K4 = kMK4;
+  constexpr int MB = MBU;
+  constexpr bool kHi = MBU > 3;    // second target (t0 + 16, rows >= 48) in use
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t n = a.n;
+  const int nb = a.nb;
+  const float* __restrict__ ylo = a.ylo;
+
+  // targets of this thread's pairs (t0 and t0 + 16) and their store offsets
+  const int t0 = lane & 15, sq = lane >> 4;
+  float tx[2], ty[2], tz[2], tlx[2], tly[2], tlz[2];
+  int rowoff[2][3], coloff[2][3];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int t = t0 + 16 * h;
+    const int64_t i = ch.first + (t < ch.count ? t : 0);
+    tx[h] = y[i];
+    ty[h] = y[n + i];
+    tz[h] = y[2 * n + i];
+    tlx[h] = ylo[i];
+    tly[h] = ylo[n + i];
+    tlz[h] = ylo[2 * n + i];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const int m = 3 * t + c;
+      rowoff[h][c] = ((m >> 4) * K4 * 64 + (m & 15)) * 4;
+      const int ks = 3 * (sq + 4 * h) + c;  // this thread's sources: 8 w + sq + 4 h
+      coloff[h][c] = ((ks >> 2) * 64 + 16 * w) * 4 + (ks & 3);
+    }
+  }
+  // this lane's configuration column and fragment rows
+  const int kq = lane >> 4;
+  const int b = blockIdx.y * 64 + 16 * w + (lane & 15);
+  const int bcl = b < nb ? b : nb - 1;
+
+  // near-list metadata, 64 entries at a time, one per lane (read by readlane)
+  const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
+  const int e1 = a.near_ptr[ch.leaf + 1];
+  int e = a.near_ptr[ch.leaf], off = 0, wb = e;
+  int mstart = 0, mcnt = 0;
+  float mox = 0.f, moy = 0.f, moz = 0.f;
+  auto load_meta = [&](int base) {
+    const int q = base + lane;
+    mcnt = 0;
+    if (q < e1) {
+      const int S = a.near_idx[q];
+      mstart = a.lstart[S];
+      mcnt = a.lcount[S];
+      mox = (float)((a.coord[3 * S] - cx) * a.g[0]);
+      moy = (float)((a.coord[3 * S + 1] - cy) * a.g[1]);
+      moz = (float)((a.coord[3 * S + 2] - cz) * a.g[2]);
+    }
+  };
+  load_meta(wb);
+  const int slot = lane & 31;
+  // next block of up to 32 sources from consecutive near cells; (e, off) is
+  // the cursor, identical in all wavefronts (same data, same steps)
+  auto next_block = [&]() -> MBlock {
+    MBlock bk;
+    bk.filled = 0;
+    bk.s.j = -1;
+    bk.s.ox = bk.s.oy = bk.s.oz = 0.f;
+    while (bk.filled < kMS && e < e1) {
+      if (e - wb >= 64) {
+        wb = e;
+        load_meta(wb);
+      }
+      const int k = e - wb;
+      const int cnt = __builtin_amdgcn_readlane(mcnt, k);
+      const int st = __builtin_amdgcn_readlane(mstart, k);
+      const int take = min(kMS - bk.filled, cnt - off);
+      if (slot >= bk.filled && slot < bk.filled + take) {
+        bk.s.j = st + off + slot - bk.filled;
+        bk.s.ox = __builtin_bit_cast(float, readlane_t(mox, k));
+        bk.s.oy = __builtin_bit_cast(float, readlane_t(moy, k));
+        bk.s.oz = __builtin_bit_cast(float, readlane_t(moz, k));
+      }
+      bk.filled += take;
+      off += take;
+      if (off == cnt) {
+        e++;
+        off = 0;
+      }
+    }
+    return bk;
+  };
+  // source 8 w + sq + 4 h of a block, as this thread's pairs need it
+  auto fetch = [&](const MSlot& S, int h) -> MSrc {
+    const int s = 8 * w + sq + 4 * h;
+    MSrc q;
+    const int j = __shfl(S.j, s);
+    q.ok = j >= 0;
+    const int64_t jj = j >= 0 ? j : 0;
+    q.ox = __shfl(S.ox, s);
+    q.oy = __shfl(S.oy, s);
+    q.oz = __shfl(S.oz, s);
+    q.x = y[jj];
+    q.y = y[n + jj];
+    q.z = y[2 * n + jj];
+    q.lx = ylo[jj];
+    q.ly = ylo[n + jj];
+    q.lz = ylo[2 * n + jj];
+    return q;
+  };
+  // moments of a block, fragment rows of this lane (null sources read dipole 0:
+  // their operator entries are zero)
+  auto load_b = [&](const MSlot& S, float (&B)[KS]) {
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const int j = __shfl(S.j, 8 * kq + q);
+      const float* p = mt + (int64_t)(j >= 0 ? j : 0) * 3 * nb + bcl;
+#pragma unroll
+      for (int c = 0; c < 3; c++) B[3 * q + c] = p[c * nb];
+    }
+  };
+  // pair kernels of one source with this thread's two targets, into buffer dst.
+  // The shifted source is rounded; with |offset| >= |position| (a nonzero
+  // offset is a multiple of the cell side) the rounding error is exactly
+  // x - ((x + o) - o), which joins the stored residual.
+  auto gen = [&](float* __restrict__ dst, const MSrc& q, int h) {
+    const float sx = q.x + q.ox, sy = q.y + q.oy, sz = q.z + q.oz;
+    const float slx = (q.x - (sx - q.ox)) + q.lx;
+    const float sly = (q.y - (sy - q.oy)) + q.ly;
+    const float slz = (q.z - (sz - q.oz)) + q.lz;
+#pragma unroll
+    for (int tt = 0; tt < (kHi ? 2 : 1); tt++) {
+      const float rx = (tx[tt] - sx) + (tlx[tt] - slx);
+      const float ry = (ty[tt] - sy) + (tly[tt] - sly);
+      const float rz = (tz[tt] - sz) + (tlz[tt] - slz);
+      const float r2 = rx * rx + ry * ry + rz * rz;
+      const bool ok = q.ok != 0 && r2 > 0.f;
+      const float inv = ok ? rsqrt_t<float>(r2) : 0.f;
+      const float inv2 = inv * inv;
+      const float inv3 = inv2 * inv;
+      const float c5 = 3.f * inv3 * inv2;
+      const float ux = c5 * rx, uy = c5 * ry, uz = c5 * rz;
+      const float kxy = ux * ry, kxz = ux * rz, kyz = uy * rz;
+      const int* ro = rowoff[tt];
+      const int* co = coloff[h];
+      dst[ro[0] + co[0]] = ux * rx - inv3;
+      dst[ro[0] + co[1]] = kxy;
+      dst[ro[0] + co[2]] = kxz;
+      dst[ro[1] + co[0]] = kxy;
+      dst[ro[1] + co[1]] = uy * ry - inv3;
+      dst[ro[1] + co[2]] = kyz;
+      dst[ro[2] + co[0]] = kxz;
+      dst[ro[2] + co[1]] = kyz;
+      dst[ro[2] + co[2]] = uz * rz - inv3;
+    }
+  };
+  f32x4 acc[MB];
+  double acc64[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) acc64[mb][r] = 0.0;
+  auto products = [&](const float* __restrict__ A, const float (&B)[KS]) {
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k4 = 0; k4 < K4; k4++) {
+      f32x4 av[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++) av[mb] = *reinterpret_cast<const f32x4*>(A + ((mb * K4 + k4) * 64 + lane) * 4);
+#pragma unroll
+      for (int ku = 0; ku < 4; ku++)
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++) acc[mb] = mfma16x16x4(av[mb][ku], B[4 * k4 + ku], acc[mb]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) acc64[mb][r] += (double)acc[mb][r];
+  };
+
+  // all of this wavefront's memory loads have landed (vmcnt = 0)
+  auto wait_loads = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
+  // Loads from read-only memory may otherwise be sunk below the barrier to
+  // their first use in the next step, where they would stall the products:
+  // an empty consumer holds each value here, where the wait is anyway.
+  auto hold = [](float v) { asm volatile("" ::"v"(v)); };
+  auto hold_b = [&](const float (&B)[KS]) {
+#pragma unroll
+    for (int k = 0; k < KS; k++) hold(B[k]);
+  };
+  auto hold_r = [&](const MSrc (&R)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      hold(R[h].x);
+      hold(R[h].y);
+      hold(R[h].z);
+      hold(R[h].lx);
+      hold(R[h].ly);
+      hold(R[h].lz);
+    }
+  };
+  // prologue: block 0 built into buffer 0 with its moments loaded, block 1 fetched
+  const MBlock b0 = next_block();
+  MBlock bn = next_block();
+  float B0[KS], B1[KS];
+  MSrc RA[2], RB[2];
+  int fc = b0.filled;
+  RB[0] = fetch(b0.s, 0);
+  RB[1] = fetch(b0.s, 1);
+  load_b(b0.s, B0);
+  RA[0] = fetch(bn.s, 0);
+  RA[1] = fetch(bn.s, 1);
+  gen(sA[0], RB[0], 0);
+  gen(sA[0], RB[1], 1);
+  wait_loads();
+  hold_b(B0);
+  hold_r(RA);
+  __syncthreads();
+  // one block: the builder runs while no load is in flight; then the moments
+  // of block i+1 and the sources of block i+2 are requested, and the products
+  // of buffer cur run beside the construction of block i+1 in the other one.
+  // Loads are unconditional (an empty block reads dipole 0 and builds zeros).
+  auto step = [&](int cur, float (&Bc)[KS], float (&Bn)[KS], MSrc (&Rc)[2], MSrc (&Rn)[2]) {
+    const MBlock b2 = next_block();
+    load_b(bn.s, Bn);
+    Rn[0] = fetch(b2.s, 0);
+    Rn[1] = fetch(b2.s, 1);
+    __builtin_amdgcn_sched_barrier(0);  // issue the loads before the products
+    products(sA[cur], Bc);
+    gen(sA[cur ^ 1], Rc[0], 0);
+    gen(sA[cur ^ 1], Rc[1], 1);
+    __builtin_amdgcn_sched_barrier(0);
+    wait_loads();
+    hold_b(Bn);
+    hold_r(Rn);
+    __syncthreads();
+    fc = bn.filled;
+    bn = b2;
+  };
+  while (fc > 0) {
+    step(0, B0, B1, RA, RB);
+    if (fc == 0) break;
+    step(1, B1, B0, RB, RA);
+  }
+
+  // write: lane holds rows 16 mb + 4 kq + r of column b
+  if (b >= nb) return;
+#pragma unroll
+  for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int m = 16 * mb + acc_row<float>(kq, r);
+      const int t = m / 3, aa = m % 3;
+      if (t < ch.count) {
+        const int64_t o = ((int64_t)b * n + a.perm[ch.first + t]) * 3 + aa;
+        H[o] = a.inv_s3 * acc64[mb][r];  // first writer: the smooth part is added afterwards
+      }
+    }
+}
+
+__global__ void __launch_bounds__(256, 2) k_p2p_mfma(P2PArgs a, const P2PChunk* __restrict__ chunks,
+                                                     int64_t nchunks, const float* __restrict__ y,
+                                                     const float* __restrict__ mt, double* __restrict__ H) {
+  __shared__ __attribute__((aligned(16))) float sA[2][kMNA];
+  // blocks are dealt round-robin to the 8 XCDs: give each a contiguous range
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  const int64_t item = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  if (item >= nchunks) return;
+  const P2PChunk ch = chunks[item];
+  switch ((3 * ch.count + 15) / 16) {  // row blocks in use (uniform over the block)
+    case 1: p2p_mfma_chunk<1>(a, ch, y, mt, H, sA); break;
+    case 2: p2p_mfma_chunk<2>(a, ch, y, mt, H, sA); break;
+    case 3: p2p_mfma_chunk<3>(a, ch, y, mt, H, sA); break;
+    case 4: p2p_mfma_chunk<4>(a, ch, y, mt, H, sA); break;
+    case 5: p2p_mfma_chunk<5>(a, ch, y, mt, H, sA); break;
+    default: p2p_mfma_chunk<6>(a, ch, y, mt, H, sA); break;
+  }
+}
+
 static P2PArgs p2p_args(Plan& P, int nb, bool fp64) {
   LevelData& D = *P.lev[P.L];
   P2PArgs a;
@@ -611,7 +933,11 @@ static void near_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   if (nb >= P.batched_min) {
     if (P.nchunks32 == 0) return;
     dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
-    k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(), d_H);
+    if constexpr (std::is_same<T, float>::value)
+      k_p2p_mfma<<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<float>(), d_H);
+    else
+      k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(),
+                                             d_H);
   } else {
     dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
     k_p2p_l2p<T, PP, false><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);

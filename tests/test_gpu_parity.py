@@ -275,6 +275,35 @@ def test_batched_matrix_core_near_field(ref, precision):
             assert rel_rms(Hb[b], ref.fmm(pos, mb[b], 5, 0.5, box=box)) <= FP64_BAR
 
 
+@pytest.mark.parametrize("leaf_target", [0.0, 90.0])
+def test_matrix_core_near_field_ragged(ref, leaf_target):
+    """The FP32 matrix-core near field with 70 configurations (a full and a
+    partial 64-column block) and, with about 90 dipoles per smallest cell,
+    cells split into several 32-target chunks and source blocks that straddle
+    cells: every configuration equals its one-at-a-time evaluation, and the
+    batch is within the mixed bar of the FP64 batch, which matches the oracle."""
+    pos, box = inputs.sphere_cut(6000, 24)
+    nb = 70
+    mb = inputs.aligned_moments(6000, nb, 3100)
+    print("case sphere_cut 6000 nb=70 leaf_target=%g" % leaf_target, flush=True)
+    pm = plan_for(pos, 4, 0.5, leaf_target, box, precision=ccfmm.PREC_MIXED, max_batch=nb)
+    Hm = pm.eval(mb)
+    info = pm.info()
+    pm.destroy()
+    p64 = plan_for(pos, 4, 0.5, leaf_target, box, precision=ccfmm.PREC_FP64, max_batch=nb)
+    H64 = p64.eval(mb)
+    p64.destroy()
+    single = plan_for(pos, 4, 0.5, leaf_target, box, precision=ccfmm.PREC_MIXED, max_batch=1)
+    for b in (0, 33, 63, 64, 69):
+        e = rel_rms(Hm[b], single.eval(mb[b:b + 1])[0])
+        print("leaves %d, b=%d batched vs single %.3e" % (info["n_leaves"], b, e), flush=True)
+        assert e <= 2e-6
+    single.destroy()
+    assert rel_rms(Hm, H64) <= MIXED_BAR
+    for b in (0, 69):
+        assert rel_rms(H64[b], ref.fmm(pos, mb[b], 4, 0.5, box=box, leaf_target=leaf_target)) <= FP64_BAR
+
+
 def test_graph_replays_match_eager():
     """The captured evaluation, replayed with new moments in the same buffers and
     eager work in between, equals the uncaptured evaluation every time."""
