@@ -203,17 +203,26 @@ static void size_expansions(Plan& P, int nb) {
   P.qv_batch = nb;
 }
 
-// one wavefront per smallest cell: its dipoles times the dipoles of its near cells
+// sum over smallest cells of (its dipoles) x (the dipoles of its near cells):
+// wavefronts stride over the cells, each block adds its total once (an
+// integer sum: exact in any order, and a few hundred atomics instead of one
+// per cell)
+constexpr int kPairCountBlocks = 512;
 __global__ void __launch_bounds__(256) k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr,
                                                          const int32_t* near_idx, const int32_t* lcount,
                                                          unsigned long long* out) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= nl) return;
+  __shared__ long long part[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   long long s = 0;
-  for (int e = near_ptr[i] + lane; e < near_ptr[i + 1]; e += 64) s += lcount[near_idx[e]];
+  for (int i = blockIdx.x * 4 + w; i < nl; i += gridDim.x * 4) {
+    long long c = 0;
+    for (int e = near_ptr[i] + lane; e < near_ptr[i + 1]; e += 64) c += lcount[near_idx[e]];
+    s += c * lcount[i];
+  }
   for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off);
-  if (lane == 0) atomicAdd(out, (unsigned long long)(s * lcount[i]));
+  if (lane == 0) part[w] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)(part[0] + part[1] + part[2] + part[3]));
 }
 
 // scattered device counters gathered into one small array (one copy back);
@@ -251,7 +260,8 @@ static void fill_info(Plan& P, hipStream_t st) {
   {
     LevelData& D = *P.lev[L];
     unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(dbuf + cidx);
-    k_count_p2p_pairs<<<ceil_div(D.ncells, 4), 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
+    const int nblk = (int)std::min<int64_t>(kPairCountBlocks, std::max<int64_t>(1, ceil_div(D.ncells, 4)));
+    k_count_p2p_pairs<<<nblk, 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
                                                                D.near_idx.as<int32_t>(), P.lcount.as<int32_t>(), dcnt);
     CCFMM_HIP(hipGetLastError());
   }

@@ -80,41 +80,54 @@ __global__ void k_finish_total(int32_t* out, int64_t n, const int32_t* last) {
 }
 
 // One block scans up to kScanSingleMax values in a single launch, in chunks of
-// 4096: each of 1024 threads loads 4 consecutive values (coalesced across the
-// block), the 1024 partial sums are scanned in LDS, and a running carry links
-// the chunks.  The total lands in out[n] (out may alias in).
+// 8192: each of 1024 threads sums 8 consecutive values, the thread sums are
+// scanned inside each wavefront by shuffles, the 16 wavefront totals by the
+// first wavefront, and a running carry links the chunks (three barriers per
+// chunk).  The total lands in out[n] (out may alias in).
 constexpr int kScanSingleThreads = 1024;
+constexpr int kScanSingleV = 8;
 constexpr int64_t kScanSingleMax = 64 * kScanSingleThreads;
 
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
 __device__ __forceinline__ void scan_single_block(const int32_t* in, int32_t* out, int64_t n) {
-  __shared__ int32_t sh[kScanSingleThreads];
-  __shared__ int32_t carry_sh;
-  const int t = threadIdx.x;
+  constexpr int NW = kScanSingleThreads / 64;
+  __shared__ int32_t wsum[NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int32_t carry = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += 4 * kScanSingleThreads) {
-    const int64_t b = c0 + 4 * t;
-    int32_t v[4];
+  for (int64_t c0 = 0; c0 < n; c0 += kScanSingleV * kScanSingleThreads) {
+    const int64_t b = c0 + kScanSingleV * t;
+    int32_t v[kScanSingleV];
+    int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < 4; i++) v[i] = (b + i < n) ? in[b + i] : 0;
-    const int32_t s = v[0] + v[1] + v[2] + v[3];
-    sh[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanSingleThreads; off <<= 1) {
-      const int32_t add = (t >= off) ? sh[t - off] : 0;
-      __syncthreads();
-      sh[t] += add;
-      __syncthreads();
+    for (int i = 0; i < kScanSingleV; i++) {
+      v[i] = (b + i < n) ? in[b + i] : 0;
+      s += v[i];
     }
-    int32_t ex = carry + sh[t] - s;
+    const int32_t incl = wave_incl_scan(s, lane);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+      int32_t x = lane < NW ? wsum[lane] : 0;
+      x = wave_incl_scan(x, lane);
+      if (lane < NW) wsum[lane] = x;
+    }
+    __syncthreads();
+    int32_t ex = carry + (w > 0 ? wsum[w - 1] : 0) + incl - s;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < kScanSingleV; i++) {
       if (b + i < n) out[b + i] = ex;
       ex += v[i];
     }
-    if (t == kScanSingleThreads - 1) carry_sh = carry + sh[t];
-    __syncthreads();
-    carry = carry_sh;
-    __syncthreads();
+    carry += wsum[NW - 1];
+    __syncthreads();  // wsum is rewritten by the next chunk
   }
   if (t == 0) out[n] = carry;
 }
