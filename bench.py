@@ -98,14 +98,17 @@ def pass_work(info, n, nb, order):
         "p2m": {"kernel": "k_permute_moments+k_p2m<float,%d>" % order, "bound": "hbm",
                 "bytes": n * nb * 24.0 + n * 12.0 + leaves * exp_b, "flops": 6.0 * NP * n * nb},
         "m2m": {"kernel": "k_m2m<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
-        "m2l": {"kernel": "k_m2l<float,%d>" % order if info["m2l_variant"] == 0 else "k_m2l_wave<float,%d>" % order,
+        "m2l": {"kernel": m2l_kernel_name(info["m2l_variant"], order),
                 "bound": "mfma", "bytes": 2.0 * cells * exp_b, "flops": info["m2l_flops_per_config"] * nb},
         "l2l": {"kernel": "k_l2l<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
+        # each input read once: FP32 position and residual (24 B), moment (12 B per configuration), caller
+        # index (4 B), the smallest cells' local expansions when L2P is fused; FP64 field written (24 B)
         "p2p": {"kernel": ("k_p2p_mfma" if batched else "k_p2p_l2p<float,%d,true>" % order),
                 "bound": "mfma" if batched else "alu",
-                "bytes": n * 24.0 + n * nb * 24.0,
+                "bytes": n * 28.0 + n * nb * 36.0 + (0.0 if batched else leaves * exp_b),
                 "flops": (18.0 if batched else 30.0) * pairs * nb},
-        "l2p": {"kernel": "k_l2p_batched<float,%d,true>" % order, "bound": "hbm",
+        "l2p": {"kernel": ("k_l2p_batched<float,%d,true>" % order if batched
+                           else "fused into k_p2p_l2p<float,%d,true>" % order), "bound": "hbm",
                 "bytes": leaves * exp_b + n * 12.0 + n * nb * 48.0,
                 "flops": 6.0 * (order * (order + 1) * (order + 2) // 6) * n * nb},
     }
@@ -114,13 +117,27 @@ def pass_work(info, n, nb, order):
     return out
 
 
-def csrc_digest():
-    """SHA-256 over the kernel sources (names and bytes, sorted)."""
+def m2l_kernel_name(variant, order):
+    """The M2L kernel a plan's variant launches (FP32)."""
+    return {0: "k_m2l<float,%d>" % order, 1: "k_m2l_wave<float,%d>" % order, 2: "k_m2l_wide<%d,4>" % order,
+            3: "k_m2l_wide<%d,2>" % order, 4: "k_m2l_wide<%d,1>" % order}[variant]
+
+
+# the source file that defines each kernel family
+KERNEL_SRC = (("k_p2p", "p2p.hip"), ("k_l2p", "p2p.hip"), ("k_m2l", "m2l.hip"), ("k_p2m", "expansions.hip"),
+              ("k_m2m", "expansions.hip"), ("k_l2l", "expansions.hip"), ("k_permute", "expansions.hip"))
+
+
+def kernel_digest(kernel):
+    """SHA-256 over the source file that defines the kernel and the shared
+    headers (names and bytes, sorted): what the kernel's machine code is built
+    from."""
     import hashlib
 
-    h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_0810_0233_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    own = sorted({f for prefix, f in KERNEL_SRC if kernel.startswith(prefix)})
+    h = hashlib.sha256()
+    for f in own + sorted(x for x in os.listdir(d) if x.endswith(".hpp")):
         h.update(f.encode())
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
@@ -138,7 +155,7 @@ def counted_traffic(kernel, workload_name):
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    if not k or rec.get("workload") != workload_name or rec.get("csrc_sha256") != csrc_digest():
+    if not k or rec.get("workload") != workload_name or k.get("src_sha256") != kernel_digest(kernel):
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -399,6 +416,8 @@ def main():
     # ---- per-pass algorithmic work and the roofline of the dominant kernel
     # (times: HIP events recorded by the library on the launch stream)
     kern = pass_work(info, n, nb, order)
+    if nb < 32:
+        pt["l2p"] = 0.0  # fused into the near-field kernel (the timer brackets nothing)
     for k, v in kern.items():
         v["ms"] = pt[k]
         if pt[k] <= 0.0:  # a pass fused into another
