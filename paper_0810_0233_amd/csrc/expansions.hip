@@ -90,19 +90,19 @@ static FTableHost make_ftable(int K) {
 __global__ void k_dtensor(int64_t nbox, int w0, int w1, int w2, double g0, double g1, double g2, int K,
                           const int32_t* __restrict__ fptr, const int32_t* __restrict__ fq,
                           const double* __restrict__ fval, int64_t row0, double* Dd, float* Df) {
-  const int NK = ncoef(K);
+  const int NK = ncoef(K), NR = NK + 1;  // row: NK entries, then a zero
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nbox * NK) return;
-  const int64_t d = t / NK;
-  const int k = (int)(t % NK);
+  if (t >= nbox * NR) return;
+  const int64_t d = t / NR;
+  const int k = (int)(t % NR);
   const int nz = 2 * w2 + 1, ny = 2 * w1 + 1;
   const int dz = (int)(d % nz) - w2;
   const int dy = (int)((d / nz) % ny) - w1;
   const int dx = (int)(d / ((int64_t)nz * ny)) - w0;
   const double c[3] = {-dx * g0, -dy * g1, -dz * g2};
   const double r2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-  const int64_t o = (row0 + d) * NK + k;
-  if (r2 == 0.0) {
+  const int64_t o = (row0 + d) * NR + k;
+  if (r2 == 0.0 || k == NK) {
     Dd[o] = 0.0;
     Df[o] = 0.0f;
     return;
@@ -175,11 +175,12 @@ void build_dtensors(Plan& P, hipStream_t st) {
   CCFMM_HIP(hipMemcpyAsync(dq, F.q.data(), nb_q, hipMemcpyHostToDevice, st));
   CCFMM_HIP(hipMemcpyAsync(dval, F.val.data(), nb_val, hipMemcpyHostToDevice, st));
   P.nrows = std::max<int64_t>(1, rows);
-  double* Dd = reinterpret_cast<double*>(P.Dd.ensure(sizeof(double) * P.nrows * NK));
-  float* Df = reinterpret_cast<float*>(P.Df.ensure(sizeof(float) * P.nrows * NK));
+  const int NR = drow_stride(P.p);
+  double* Dd = reinterpret_cast<double*>(P.Dd.ensure(sizeof(double) * P.nrows * NR));
+  float* Df = reinterpret_cast<float*>(P.Df.ensure(sizeof(float) * P.nrows * NR));
   for (size_t i = 0; i < keys.size(); i++) {
     const auto& k = keys[i];
-    const int64_t nt = key_nbox[i] * NK;
+    const int64_t nt = key_nbox[i] * NR;
     k_dtensor<<<ceil_div(nt, 256), 256, 0, st>>>(key_nbox[i], (int)k[3], (int)k[4], (int)k[5], k[0], k[1], k[2], K,
                                                  dptr, dq, dval, key_row[i], Dd, Df);
     CCFMM_HIP(hipGetLastError());

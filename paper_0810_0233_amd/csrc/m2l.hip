@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && P <= 6) ? 2 : 1) k_m2l
   T rD[S::DR], rQ[S::QR];
   auto fetch = [&](int s) {
     const int64_t st = (int64_t)tl.step0 + s;
-    const T* drow = Dtab + (int64_t)step_delta[st] * ND;
+    const T* drow = Dtab + (int64_t)step_delta[st] * drow_stride(P);
 #pragma unroll
     for (int r = 0; r < S::DR; r++) {
       const int e = t + 256 * r;
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
   T rD[DR], rQ[QR];
   auto fetch = [&](int s) {
     const int64_t st = (int64_t)tl.step0 + s;
-    const T* drow = Dtab + (int64_t)step_delta[st] * ND;
+    const T* drow = Dtab + (int64_t)step_delta[st] * drow_stride(P);
 #pragma unroll
     for (int r = 0; r < DR; r++) {
       const int e = lane + 64 * r;
@@ -325,9 +325,8 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
 // half of a double-buffered LDS array (global-to-LDS loads, no registers) while
 // the current step's products run, so each step needs a single block barrier
 // and two blocks fit on a compute unit.
-// Zeros read by empty columns and padding operator entries: selecting an
-// address instead of a loaded value keeps the loads free of consumers until
-// the products that need them.
+// Zeros read by empty columns: selecting an address instead of a loaded value
+// keeps the loads free of consumers until the products that need them.
 __device__ const float g_zero_row[128] = {};
 
 template <int P>
@@ -347,7 +346,10 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   constexpr int NP = nact(P), NS = nstride(P), KS = NS / 4, MB = (NP + 15) / 16, ND = ncoef(2 * P);
   constexpr int NE = MB * KS * 64;       // operator entries in fragment order
   constexpr int ER = (NE + 255) / 256;   // per thread
-  __shared__ float sT[2][ER * 256];  // padded so every thread stores unconditionally
+  constexpr int K4 = KS / 4, KT = KS % 4;  // full groups of 4 steps, steps left over
+  static_assert(4 * ND < 65536, "operator byte offsets are kept in 16 bits");
+  // padded so every thread stores unconditionally; fragments read as float4
+  __shared__ __attribute__((aligned(16))) float sT[2][ER * 256];
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   // tiles are launched longest first (greedy balance over the compute units)
@@ -356,8 +358,9 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   const float* Ql = Q + lo.qoff[tl.level];
   const int nsteps = tl.nsteps;
 
-  // this thread's operator entries e = t + 256 r: derivative-tensor index or ND (zero)
-  uint32_t eidx[(ER + 1) / 2];  // two 16-bit indices per register
+  // this thread's operator entries e = t + 256 r: byte offset of the
+  // derivative-tensor entry in its row (ND: the row's trailing zero)
+  uint32_t eidx[(ER + 1) / 2];  // two 16-bit offsets per register
 #pragma unroll
   for (int r = 0; r < (ER + 1) / 2; r++) eidx[r] = 0;
 #pragma unroll
@@ -365,10 +368,21 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     const int e = t + 256 * r;
     int v = ND;
     if (e < NE) {
-      const int mb = e / (KS * 64), ks = (e / 64) % KS, l = e % 64;
+      // LDS slot e of row block mb: steps 4 k4 .. 4 k4 + 3 of lane l are the
+      // float4 at k4 * 256 + 4 l; the KT steps past the last full group follow
+      // as one word per lane each
+      const int mb = e / (KS * 64), r0 = e % (KS * 64);
+      int ks, l;
+      if (r0 < K4 * 256) {
+        ks = 4 * (r0 / 256) + (r0 & 3);
+        l = (r0 % 256) >> 2;
+      } else {
+        ks = 4 * K4 + (r0 - K4 * 256) / 64;
+        l = r0 & 63;
+      }
       v = op_index_kperm<P>(16 * mb + (l & 15), l >> 4, ks);
     }
-    eidx[r >> 1] |= (uint32_t)v << (16 * (r & 1));
+    eidx[r >> 1] |= (uint32_t)(4 * v) << (16 * (r & 1));  // byte offset; ND is the row's zero
   }
   // this lane's columns: 16 CB w + 16 cb + lane % 16, fragment rows kq KS .. kq KS + KS - 1
   const int kq = lane >> 4;
@@ -380,9 +394,10 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     cb_b[cb] = tl.b0 + col % TB;
     if (!(ctc[cb] < TC && cb_b[cb] < nb)) ctc[cb] = -1;
   }
-  // Loads are unconditional: an empty column or a padding operator entry reads
-  // g_zero_row through a selected address, so no loaded value has a consumer
-  // before the products that need it and the loads stay in flight meanwhile.
+  // Loads are unconditional: an empty column reads g_zero_row through a
+  // selected address and a padding operator entry reads the zero that ends
+  // every derivative-table row, so no loaded value has a consumer before the
+  // products that need it and the loads stay in flight meanwhile.
   auto load_src = [&](int s, int (&src)[CB]) {
     const int64_t st = (int64_t)tl.step0 + s;
 #pragma unroll
@@ -392,7 +407,11 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
 #pragma unroll
     for (int cb = 0; cb < CB; cb++) {
       const bool ok = ctc[cb] >= 0 && src[cb] >= 0;
-      const float* q = ok ? Ql + ((int64_t)src[cb] * nb + cb_b[cb]) * NS + kq * KS : g_zero_row;
+      // both candidates in the global address space: a generic pointer would
+      // make these flat loads, which the LDS wait counter also tracks, so
+      // every wait for an operator fragment would wait for them too
+      typedef const __attribute__((address_space(1))) float* gptr;
+      const gptr q = ok ? (gptr)(Ql + ((int64_t)src[cb] * nb + cb_b[cb]) * NS + kq * KS) : (gptr)g_zero_row;
 #pragma unroll
       for (int ks = 0; ks < KS; ks++) B[cb][ks] = q[ks];
     }
@@ -400,11 +419,11 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   // the operator of step s goes from memory straight into sT[buf] (no
   // registers): lane l of wavefront w writes entry 256 r + 64 w + l
   auto load_op = [&](int s, int buf) {
-    const float* drow = Dtab + (int64_t)step_delta[tl.step0 + s] * ND;
+    const char* drow = reinterpret_cast<const char*>(Dtab + (int64_t)step_delta[tl.step0 + s] * drow_stride(P));
 #pragma unroll
     for (int r = 0; r < ER; r++) {
-      const int ix = (eidx[r >> 1] >> (16 * (r & 1))) & 0xffff;
-      const float* g = ix < ND ? drow + ix : g_zero_row;
+      const uint32_t off = (eidx[r >> 1] >> (16 * (r & 1))) & 0xffffu;  // byte offset in the row
+      const char* g = drow + off;
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
                                        (__attribute__((address_space(3))) void*)&sT[buf][256 * r + 64 * w], 4, 0,
                                        0);
@@ -440,12 +459,25 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     __builtin_amdgcn_sched_barrier(0);  // issue the loads before the products
     const float* T0 = sT[cur];
 #pragma unroll
-    for (int ks = 0; ks < KS; ks++) {
+    for (int k4 = 0; k4 < K4; k4++) {
+      f32x4 av[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; mb++)
+        av[mb] = *reinterpret_cast<const f32x4*>(T0 + mb * KS * 64 + k4 * 256 + 4 * lane);
+#pragma unroll
+      for (int ku = 0; ku < 4; ku++)
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+          for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(av[mb][ku], Bc[cb][4 * k4 + ku], acc[mb][cb]);
+    }
+#pragma unroll
+    for (int t = 0; t < KT; t++) {
 #pragma unroll
       for (int mb = 0; mb < MB; mb++) {
-        const float a = T0[(mb * KS + ks) * 64 + lane];
+        const float a = T0[mb * KS * 64 + K4 * 256 + t * 64 + lane];
 #pragma unroll
-        for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(a, Bc[cb][ks], acc[mb][cb]);
+        for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(a, Bc[cb][4 * K4 + t], acc[mb][cb]);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
