@@ -350,10 +350,6 @@ __global__ void __launch_bounds__(256) k_tile_class_keys(TileLevels T, int64_t n
   }
 }
 
-__global__ void k_tile_inverse(const int32_t* sorted, int64_t ncell, int32_t* inv) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ncell) inv[sorted[i]] = (int32_t)i;
-}
 
 // One block per target group: the union of its cells' far offsets as a bitmap
 // over the level's offset box (built in LDS), the exclusive popcount prefix
@@ -431,25 +427,62 @@ __global__ void __launch_bounds__(256) k_group_steps(TileLevels T, int64_t ngrou
   }
 }
 
-// one wavefront per cell: each far entry becomes the source of its column at
-// the rank of its offset within the group's steps
-__global__ void __launch_bounds__(256) k_step_src(TileLevels T, int64_t ncell, const int32_t* inv,
-                                                  const uint32_t* bitmap, const int32_t* wpre, const int32_t* goff,
-                                                  int32_t* step_src) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= ncell) return;
-  const TileLevel& lv = T.lv[level_of_cell(T, i)];
-  if (!lv.far_ptr) return;
-  const int c = (int)(i - lv.cell0);
-  const int64_t pos = inv[i] - lv.cell0;
-  const int64_t gi = pos / T.TC, tc = pos % T.TC;
-  const int64_t b = lv.g0 + gi;
+// One block of 16 wavefronts per group: the group's rows of the column-source
+// table are filled in LDS, a band of rows at a time (-1 where a column has no
+// source at that step), and stored contiguously, so the table is written once
+// with whole-line stores (a far entry's row is the rank of its offset among
+// the group's steps; its column is its cell's place in the group).  A
+// wavefront takes every 16th column, each lane four far entries per round so
+// their loads are in flight together.
+constexpr int kStepSrcThreads = 1024;
+constexpr int kStepSrcLdsBytes = 64 * 1024;
+
+__global__ void __launch_bounds__(kStepSrcThreads) k_step_src(TileLevels T, const int32_t* sorted,
+                                                              const uint32_t* bitmap, const int32_t* wpre,
+                                                              const int32_t* goff, int32_t* step_src) {
+  extern __shared__ int32_t sband[];
+  const int TC = T.TC;
+  const int band_rows = kStepSrcLdsBytes / (int)sizeof(int32_t) / TC;
+  const int64_t b = blockIdx.x;
+  const TileLevel& lv = T.lv[level_of_group(T, b)];
+  const int64_t gi = b - lv.g0;
   const int64_t base = lv.bm0 + gi * lv.words;
-  for (int e = lv.far_ptr[c] + lane; e < lv.far_ptr[c + 1]; e += 64) {
-    const int d = lv.far_did[e];
-    const int rank = wpre[base + (d >> 5)] + __popc(bitmap[base + (d >> 5)] & ((1u << (d & 31)) - 1u));
-    step_src[((int64_t)goff[b] + rank) * T.TC + tc] = lv.far_idx[e];
+  const int64_t s0 = goff[b], ns = goff[b + 1] - s0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int NW = kStepSrcThreads / 64;
+  for (int64_t r0 = 0; r0 < ns; r0 += band_rows) {
+    const int rows = (int)min((int64_t)band_rows, ns - r0);
+    for (int k = threadIdx.x; k < rows * TC; k += kStepSrcThreads) sband[k] = -1;
+    __syncthreads();
+    if (lv.far_ptr) {
+      for (int tc = wv; tc < TC; tc += NW) {
+        const int64_t pos = gi * TC + tc;
+        if (pos >= lv.nc) break;
+        const int c = sorted[lv.cell0 + pos] - (int32_t)lv.cell0;
+        const int e0 = lv.far_ptr[c], e1 = lv.far_ptr[c + 1];
+        for (int e = e0 + lane; e < e1; e += 256) {
+          int d[4], src[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int eu = e + 64 * u;
+            d[u] = eu < e1 ? lv.far_did[eu] : -1;
+            src[u] = eu < e1 ? lv.far_idx[eu] : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            if (d[u] < 0) continue;
+            const int rank = wpre[base + (d[u] >> 5)] +
+                             __popc(bitmap[base + (d[u] >> 5)] & ((1u << (d[u] & 31)) - 1u));
+            const int64_t r = rank - r0;
+            if (r >= 0 && r < rows) sband[r * TC + tc] = src[u];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    int32_t* out = step_src + (s0 + r0) * TC;
+    for (int k = threadIdx.x; k < rows * TC; k += kStepSrcThreads) out[k] = sband[k];
+    __syncthreads();
   }
 }
 
@@ -529,18 +562,15 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   const int cb = std::min(P.class_bits, 11);
   int lbits = 1;
   while ((1 << lbits) <= L) lbits++;
-  int32_t* sbuf = reinterpret_cast<int32_t*>(P.tile_sort.ensure(sizeof(int32_t) * 5 * ncell));
+  int32_t* sbuf = reinterpret_cast<int32_t*>(P.tile_sort.ensure(sizeof(int32_t) * 4 * ncell));
   uint32_t* skey = reinterpret_cast<uint32_t*>(sbuf);
   int32_t* sorted = sbuf + ncell;
   uint32_t* skey2 = reinterpret_cast<uint32_t*>(sbuf + 2 * ncell);
   int32_t* sval2 = sbuf + 3 * ncell;
-  int32_t* inv = sbuf + 4 * ncell;
   const int sigbits = P.tile_signature ? 16 : 0;
   k_tile_class_keys<<<ceil_div(ncell, 4), T, 0, st>>>(TL, ncell, cb, sigbits, skey, sorted);
   CCFMM_HIP(hipGetLastError());
   radix_sort_pairs(skey, sorted, skey2, sval2, ncell, cb + lbits + sigbits, P.scratch, st);
-  k_tile_inverse<<<ceil_div(ncell, T), T, 0, st>>>(sorted, ncell, inv);
-  CCFMM_HIP(hipGetLastError());
   // bitmaps, ranks and step counts of every group; global step offsets
   uint32_t* bitmap = reinterpret_cast<uint32_t*>(P.bitmap.ensure(sizeof(uint32_t) * 2 * std::max<int64_t>(1, nbm)));
   int32_t* wpre = reinterpret_cast<int32_t*>(bitmap + std::max<int64_t>(1, nbm));
@@ -561,11 +591,14 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   int32_t* step_src = reinterpret_cast<int32_t*>(P.step_src.ensure(sizeof(int32_t) * std::max<int64_t>(1, nsteps * TC)));
   int32_t* tile_tgt = reinterpret_cast<int32_t*>(P.tile_tgt.ensure(sizeof(int32_t) * std::max<int64_t>(1, ngroups * TC)));
   M2LTile* tiles = reinterpret_cast<M2LTile*>(P.tiles.ensure(sizeof(M2LTile) * std::max<int64_t>(1, ntiles)));
-  fill_i32(step_src, nsteps * TC, -1, st);
   k_group_steps<<<ceil_div(ngroups, 4), T, 0, st>>>(TL, ngroups, bitmap, wpre, goff, step_delta);
   CCFMM_HIP(hipGetLastError());
-  k_step_src<<<ceil_div(ncell, 4), T, 0, st>>>(TL, ncell, inv, bitmap, wpre, goff, step_src);
-  CCFMM_HIP(hipGetLastError());
+  if (ngroups > 0) {
+    if (kStepSrcLdsBytes / (int)sizeof(int32_t) / TC < 1) fail(CCFMM_EINVAL, "M2L tile too wide");
+    k_step_src<<<(unsigned)ngroups, kStepSrcThreads, kStepSrcLdsBytes, st>>>(TL, sorted, bitmap, wpre, goff,
+                                                                           step_src);
+    CCFMM_HIP(hipGetLastError());
+  }
   k_tile_tgt<<<ceil_div(ngroups * TC, T), T, 0, st>>>(TL, ngroups * TC, sorted, tile_tgt);
   CCFMM_HIP(hipGetLastError());
   k_tiles<<<ceil_div(ngroups, T), T, 0, st>>>(TL, ngroups, P.TB, P.ncg, goff, tiles);

@@ -80,12 +80,15 @@ __global__ void k_finish_total(int32_t* out, int64_t n, const int32_t* last) {
 }
 
 // One block scans up to kScanSingleMax values in a single launch, in chunks of
-// 8192: each of 1024 threads sums 8 consecutive values, the thread sums are
-// scanned inside each wavefront by shuffles, the 16 wavefront totals by the
-// first wavefront, and a running carry links the chunks (three barriers per
-// chunk).  The total lands in out[n] (out may alias in).
+// 16384 values: wavefront w owns the 16 rows of 64 consecutive values from
+// 1024 w, and lane l holds column l of each row, so every load and store
+// covers 64 consecutive words.  Each row is scanned by shuffles and offset by
+// the rows before it; the 16 wavefront totals are scanned by the first
+// wavefront, and a carry links the chunks.  All loads of a chunk are issued
+// before any is used.  The total lands in out[n] (out may alias in: each
+// value is read before it is written, by the same lane).
 constexpr int kScanSingleThreads = 1024;
-constexpr int kScanSingleV = 8;
+constexpr int kScanSingleRows = 16;
 constexpr int64_t kScanSingleMax = 64 * kScanSingleThreads;
 
 __device__ __forceinline__ int32_t wave_incl_scan(int32_t x, int lane) {
@@ -99,20 +102,27 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t x, int lane) {
 
 __device__ __forceinline__ void scan_single_block(const int32_t* in, int32_t* out, int64_t n) {
   constexpr int NW = kScanSingleThreads / 64;
+  constexpr int R = kScanSingleRows;
+  constexpr int CH = R * kScanSingleThreads;
   __shared__ int32_t wsum[NW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int32_t carry = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += kScanSingleV * kScanSingleThreads) {
-    const int64_t b = c0 + kScanSingleV * t;
-    int32_t v[kScanSingleV];
-    int32_t s = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += CH) {
+    const int64_t m = min((int64_t)CH, n - c0);
+    const int32_t base = w * (R * 64) + lane;  // row i of this wavefront: base + 64 i
+    const int32_t* src = in + c0;
+    int32_t v[R];
 #pragma unroll
-    for (int i = 0; i < kScanSingleV; i++) {
-      v[i] = (b + i < n) ? in[b + i] : 0;
-      s += v[i];
+    for (int i = 0; i < R; i++) v[i] = (base + 64 * i < m) ? src[base + 64 * i] : 0;
+    int32_t rowoff = 0;  // sum of this wavefront's rows before row i
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+      const int32_t x = wave_incl_scan(v[i], lane);
+      const int32_t ex = rowoff + x - v[i];
+      rowoff += __builtin_amdgcn_readlane(x, 63);
+      v[i] = ex;  // exclusive prefix inside the wavefront's segment
     }
-    const int32_t incl = wave_incl_scan(s, lane);
-    if (lane == 63) wsum[w] = incl;
+    if (lane == 0) wsum[w] = rowoff;
     __syncthreads();
     if (w == 0) {
       int32_t x = lane < NW ? wsum[lane] : 0;
@@ -120,12 +130,11 @@ __device__ __forceinline__ void scan_single_block(const int32_t* in, int32_t* ou
       if (lane < NW) wsum[lane] = x;
     }
     __syncthreads();
-    int32_t ex = carry + (w > 0 ? wsum[w - 1] : 0) + incl - s;
+    const int32_t add = carry + (w > 0 ? wsum[w - 1] : 0);
+    int32_t* dst = out + c0;
 #pragma unroll
-    for (int i = 0; i < kScanSingleV; i++) {
-      if (b + i < n) out[b + i] = ex;
-      ex += v[i];
-    }
+    for (int i = 0; i < R; i++)
+      if (base + 64 * i < m) dst[base + 64 * i] = add + v[i];
     carry += wsum[NW - 1];
     __syncthreads();  // wsum is rewritten by the next chunk
   }
