@@ -205,9 +205,9 @@ static void size_expansions(Plan& P, int nb) {
 
 // sum over smallest cells of (its dipoles) x (the dipoles of its near cells):
 // wavefronts stride over the cells, each block adds its total once (an
-// integer sum: exact in any order, and a few hundred atomics instead of one
+// integer sum: exact in any order, and a few thousand atomics instead of one
 // per cell)
-constexpr int kPairCountBlocks = 512;
+constexpr int kPairCountBlocks = 2048;
 __global__ void __launch_bounds__(256) k_count_p2p_pairs(int32_t nl, const int32_t* near_ptr,
                                                          const int32_t* near_idx, const int32_t* lcount,
                                                          unsigned long long* out) {
@@ -589,10 +589,8 @@ int ccfmm_plan_create(ccfmm_plan* out, int32_t device, int64_t n, const double* 
       std::swap((*out)->P.pos.p, dpos.p);
       std::swap((*out)->P.pos.cap, dpos.cap);
       CCFMM_HIP(hipStreamSynchronize((*out)->P.own_stream));
-    } else {
-      g_last_error = g_last_error;  // preserved from create_common
     }
-    return rc;
+    return rc;  // on failure the message set by create_common stands
   });
 }
 

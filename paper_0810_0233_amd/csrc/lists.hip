@@ -8,7 +8,8 @@
 // the cell's M2L list.  Empty cells are never created, which leaves every
 // field unchanged (their moments vanish and they hold no field points).
 //
-// One wavefront per cell walks its candidates 64 at a time; ballots give each
+// One wavefront per cell walks its candidates 256 at a time (four ballot
+// rounds whose loads are in flight together); ballots give each
 // near/far candidate its slot, so the lists come out in candidate order, the
 // same order a serial walk produces.  Buffers are sized from exact per-cell
 // bounds computed on the host, so no level waits on the host.
@@ -55,6 +56,33 @@ struct ListArgs {
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
 // Candidate i of cell c: child (i & 1) of the (i >> 1)-th near cell of the parent.
+// A lane takes candidates i, i + 64, i + 128, i + 192 (kCandRounds rounds of
+// a wavefront) and issues their dependent loads together; X = -1: none.
+constexpr int kCandRounds = 4;
+struct Cands {
+  int X[kCandRounds];
+  int d[kCandRounds][3];  // candidate minus cell, integer offset
+};
+__device__ __forceinline__ Cands load_cands(const ListArgs& a, int e0, int ncand, int i0, int cx, int cy, int cz) {
+  Cands q;
+  int pn[kCandRounds];
+#pragma unroll
+  for (int u = 0; u < kCandRounds; u++) {
+    const int i = i0 + 64 * u;
+    pn[u] = i < ncand ? a.pnear_idx[e0 + (i >> 1)] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kCandRounds; u++) q.X[u] = pn[u] >= 0 ? a.pchild[2 * pn[u] + ((i0 + 64 * u) & 1)] : -1;
+#pragma unroll
+  for (int u = 0; u < kCandRounds; u++) {
+    const int X = q.X[u] >= 0 ? q.X[u] : 0;
+    q.d[u][0] = a.coord[3 * X] - cx;
+    q.d[u][1] = a.coord[3 * X + 1] - cy;
+    q.d[u][2] = a.coord[3 * X + 2] - cz;
+  }
+  return q;
+}
+
 __global__ void __launch_bounds__(256) k_list_count(ListArgs a, TreeGeom G, int32_t* near_cnt, int32_t* far_cnt) {
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -65,19 +93,19 @@ __global__ void __launch_bounds__(256) k_list_count(ListArgs a, TreeGeom G, int3
   const int cx = a.coord[3 * c], cy = a.coord[3 * c + 1], cz = a.coord[3 * c + 2];
   const double th2 = a.cell_th2 ? a.cell_th2[c] : a.theta2;  // a smallest cell may use its own angle
   int nn = 0, nf = 0;
-  for (int base = 0; base < ncand; base += 64) {
-    const int i = base + lane;
-    bool isn = false, isf = false;
-    if (i < ncand) {
-      const int X = a.pchild[2 * a.pnear_idx[e0 + (i >> 1)] + (i & 1)];
-      if (X >= 0) {
-        const bool nr = is_near(lg, th2,a.coord[3 * X] - cx, a.coord[3 * X + 1] - cy, a.coord[3 * X + 2] - cz);
+  for (int base = 0; base < ncand; base += 64 * kCandRounds) {
+    const Cands q = load_cands(a, e0, ncand, base + lane, cx, cy, cz);
+#pragma unroll
+    for (int u = 0; u < kCandRounds; u++) {
+      bool isn = false, isf = false;
+      if (q.X[u] >= 0) {
+        const bool nr = is_near(lg, th2, q.d[u][0], q.d[u][1], q.d[u][2]);
         isn = nr;
         isf = !nr;
       }
+      nn += __popcll(__ballot(isn));
+      nf += __popcll(__ballot(isf));
     }
-    nn += __popcll(__ballot(isn));
-    nf += __popcll(__ballot(isf));
   }
   if (lane == 0) {
     near_cnt[c] = nn;
@@ -98,41 +126,38 @@ __global__ void __launch_bounds__(256) k_list_fill(ListArgs a, TreeGeom G, const
   const double th2 = a.cell_th2 ? a.cell_th2[c] : a.theta2;  // a smallest cell may use its own angle
   int64_t jn = near_ptr[c], jf = far_ptr[c];
   const uint64_t lt = lanemask_lt(lane);
-  for (int base = 0; base < ncand; base += 64) {
-    const int i = base + lane;
-    bool isn = false, isf = false;
-    int X = -1, dx = 0, dy = 0, dz = 0;
-    if (i < ncand) {
-      X = a.pchild[2 * a.pnear_idx[e0 + (i >> 1)] + (i & 1)];
+  for (int base = 0; base < ncand; base += 64 * kCandRounds) {
+    const Cands q = load_cands(a, e0, ncand, base + lane, cx, cy, cz);
+#pragma unroll
+    for (int u = 0; u < kCandRounds; u++) {
+      bool isn = false, isf = false;
+      const int X = q.X[u], dx = q.d[u][0], dy = q.d[u][1], dz = q.d[u][2];
       if (X >= 0) {
-        dx = a.coord[3 * X] - cx;
-        dy = a.coord[3 * X + 1] - cy;
-        dz = a.coord[3 * X + 2] - cz;
-        const bool nr = is_near(lg, th2,dx, dy, dz);
+        const bool nr = is_near(lg, th2, dx, dy, dz);
         isn = nr;
         isf = !nr;
       }
-    }
-    const uint64_t mn = __ballot(isn), mf = __ballot(isf);
-    if (isn) {
-      const int64_t at = jn + __popcll(mn & lt);
-      if (at < a.near_cap)
-        near_idx[at] = X;
-      else
-        flags[0] = 1;
-    }
-    if (isf) {
-      const int64_t at = jf + __popcll(mf & lt);
-      const bool inbox = abs(dx) <= a.wfar[0] && abs(dy) <= a.wfar[1] && abs(dz) <= a.wfar[2];
-      if (at < a.far_cap && inbox) {
-        far_idx[at] = X;
-        far_did[at] = (int32_t)box_index(a.wfar, dx, dy, dz);
-      } else {
-        flags[0] = 1;
+      const uint64_t mn = __ballot(isn), mf = __ballot(isf);
+      if (isn) {
+        const int64_t at = jn + __popcll(mn & lt);
+        if (at < a.near_cap)
+          near_idx[at] = X;
+        else
+          flags[0] = 1;
       }
+      if (isf) {
+        const int64_t at = jf + __popcll(mf & lt);
+        const bool inbox = abs(dx) <= a.wfar[0] && abs(dy) <= a.wfar[1] && abs(dz) <= a.wfar[2];
+        if (at < a.far_cap && inbox) {
+          far_idx[at] = X;
+          far_did[at] = (int32_t)box_index(a.wfar, dx, dy, dz);
+        } else {
+          flags[0] = 1;
+        }
+      }
+      jn += __popcll(mn);
+      jf += __popcll(mf);
     }
-    jn += __popcll(mn);
-    jf += __popcll(mf);
   }
 }
 
@@ -162,6 +187,28 @@ __global__ void __launch_bounds__(256) k_near_adjacent_first(int32_t nc, const i
   const int base = near_ptr[c], cnt = near_ptr[c + 1] - base;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   int w = 0;
+  if (cnt <= 256) {  // the usual case: every entry loaded once, four per lane in flight
+    int S[4];
+    bool adj[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) S[u] = lane + 64 * u < cnt ? near_idx[base + lane + 64 * u] : -1;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int X = S[u] >= 0 ? S[u] : 0;
+      adj[u] = S[u] >= 0 && abs(coord[3 * X] - cx) <= 1 && abs(coord[3 * X + 1] - cy) <= 1 &&
+               abs(coord[3 * X + 2] - cz) <= 1;
+    }
+    for (int pass = 0; pass < 2; pass++) {
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const bool take = S[u] >= 0 && (pass == 0 ? adj[u] : !adj[u]);
+        const uint64_t m = __ballot(take);
+        if (take) out[base + w + __popcll(m & lt)] = S[u];
+        w += __popcll(m);
+      }
+    }
+    return;
+  }
   for (int pass = 0; pass < 2; pass++) {
     for (int k0 = 0; k0 < cnt; k0 += 64) {
       const int k = k0 + lane;
@@ -338,8 +385,17 @@ __global__ void __launch_bounds__(256) k_tile_class_keys(TileLevels T, int64_t n
   const TileLevel& lv = T.lv[l];
   const int c = (int)(i - lv.cell0);
   uint32_t h = 0;
-  if (sigbits && lv.far_ptr)
-    for (int e = lv.far_ptr[c] + lane; e < lv.far_ptr[c + 1]; e += 64) h += mix32((uint32_t)lv.far_did[e] + 1u);
+  if (sigbits && lv.far_ptr) {
+    const int e1 = lv.far_ptr[c + 1];
+    for (int e = lv.far_ptr[c] + lane; e < e1; e += 256) {  // four loads in flight per lane
+      int d[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) d[u] = e + 64 * u < e1 ? lv.far_did[e + 64 * u] : -1;
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        if (d[u] >= 0) h += mix32((uint32_t)d[u] + 1u);
+    }
+  }
   for (int off = 1; off < 64; off <<= 1) h += (uint32_t)__shfl_xor((int)h, off);
   if (lane == 0) {
     const int cbl = min(cb, l);
@@ -352,46 +408,57 @@ __global__ void __launch_bounds__(256) k_tile_class_keys(TileLevels T, int64_t n
 
 
 // One block per target group: the union of its cells' far offsets as a bitmap
-// over the level's offset box (built in LDS), the exclusive popcount prefix
-// over its words (a step's rank) and its step count.
-__global__ void __launch_bounds__(256) k_group_bits(TileLevels T, const int32_t* sorted, uint32_t* bitmap,
-                                                    int32_t* wpre, int32_t* cnt) {
+// over the level's offset box (built in LDS by 16 wavefronts, each lane with
+// four far entries in flight), the exclusive popcount prefix over its words
+// (a step's rank, by the first 256 threads) and its step count.
+constexpr int kGroupBitsThreads = 1024;
+__global__ void __launch_bounds__(kGroupBitsThreads) k_group_bits(TileLevels T, const int32_t* sorted,
+                                                                  uint32_t* bitmap, int32_t* wpre, int32_t* cnt) {
   extern __shared__ uint32_t sb[];
   __shared__ int32_t ssum[256];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int NW = kGroupBitsThreads / 64;
   const int64_t b = blockIdx.x;
   const int l = level_of_group(T, b);
   const TileLevel& lv = T.lv[l];
   const int words = lv.words;
   const int64_t gi = b - lv.g0;
-  for (int w = t; w < words; w += 256) sb[w] = 0u;
+  for (int w = t; w < words; w += kGroupBitsThreads) sb[w] = 0u;
   __syncthreads();
   if (lv.far_ptr) {
     const int64_t p0 = gi * T.TC, p1 = min((int64_t)lv.nc, p0 + T.TC);
-    for (int64_t p = p0 + wv; p < p1; p += 4) {
+    for (int64_t p = p0 + wv; p < p1; p += NW) {
       const int c = sorted[lv.cell0 + p] - (int32_t)lv.cell0;
-      for (int e = lv.far_ptr[c] + lane; e < lv.far_ptr[c + 1]; e += 64) {
-        const int d = lv.far_did[e];
-        atomicOr(&sb[d >> 5], 1u << (d & 31));
+      const int e1 = lv.far_ptr[c + 1];
+      for (int e = lv.far_ptr[c] + lane; e < e1; e += 256) {
+        int d[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) d[u] = e + 64 * u < e1 ? lv.far_did[e + 64 * u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+          if (d[u] >= 0) atomicOr(&sb[d[u] >> 5], 1u << (d[u] & 31));
       }
     }
   }
   __syncthreads();
-  // thread t owns words [t per, (t + 1) per)
+  // thread t < 256 owns words [t per, (t + 1) per)
+  const bool own = t < 256;
   const int per = (words + 255) / 256;
   int s = 0;
-  for (int i = 0; i < per; i++) {
-    const int w = t * per + i;
-    if (w < words) s += __popc(sb[w]);
-  }
-  ssum[t] = s;
+  if (own)
+    for (int i = 0; i < per; i++) {
+      const int w = t * per + i;
+      if (w < words) s += __popc(sb[w]);
+    }
+  if (own) ssum[t] = s;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
-    const int32_t add = (t >= off) ? ssum[t - off] : 0;
+    const int32_t add = (own && t >= off) ? ssum[t - off] : 0;
     __syncthreads();
-    ssum[t] += add;
+    if (own) ssum[t] += add;
     __syncthreads();
   }
+  if (!own) return;
   int ex = ssum[t] - s;
   const int64_t base = lv.bm0 + gi * words;
   for (int i = 0; i < per; i++) {
@@ -577,7 +644,8 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   int32_t* gbuf = reinterpret_cast<int32_t*>(P.gcount.ensure(sizeof(int32_t) * 2 * (ngroups + 1)));
   int32_t* gcnt = gbuf;
   int32_t* goff = gbuf + ngroups + 1;
-  k_group_bits<<<(unsigned)ngroups, T, sizeof(uint32_t) * maxwords, st>>>(TL, sorted, bitmap, wpre, gcnt);
+  k_group_bits<<<(unsigned)ngroups, kGroupBitsThreads, sizeof(uint32_t) * maxwords, st>>>(TL, sorted, bitmap, wpre,
+                                                                                         gcnt);
   CCFMM_HIP(hipGetLastError());
   scan_exclusive(gcnt, goff, ngroups, P.scratch, st);
   int32_t total = 0;

@@ -110,6 +110,8 @@ __device__ __forceinline__ void scan_single_block(const int32_t* in, int32_t* ou
   for (int64_t c0 = 0; c0 < n; c0 += CH) {
     const int64_t m = min((int64_t)CH, n - c0);
     const int32_t base = w * (R * 64) + lane;  // row i of this wavefront: base + 64 i
+    // rows of this wavefront that hold values (the rest are zero and skipped)
+    const int rows = (int)max((int64_t)0, min((int64_t)R, (m - (int64_t)w * R * 64 + 63) / 64));
     const int32_t* src = in + c0;
     int32_t v[R];
 #pragma unroll
@@ -117,6 +119,7 @@ __device__ __forceinline__ void scan_single_block(const int32_t* in, int32_t* ou
     int32_t rowoff = 0;  // sum of this wavefront's rows before row i
 #pragma unroll
     for (int i = 0; i < R; i++) {
+      if (i >= rows) break;
       const int32_t x = wave_incl_scan(v[i], lane);
       const int32_t ex = rowoff + x - v[i];
       rowoff += __builtin_amdgcn_readlane(x, 63);
