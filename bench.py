@@ -23,7 +23,11 @@ dominant kernel, and the CPU oracle timed on the same workload (configuration 0)
 (p, theta) for a 1e-5 bound against fixed p = 6, theta = 0.4 (the network is
 trained on the GPU first, from two training geometries of the same recipe).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters]
+`--workload dynamics`: the ferrofluid geometry in a time-stepping loop: one plan,
+its captured evaluation replayed after every in-place precession step of the
+moments, the energy taken on the GPU every step (and the same loop in FP64).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|dynamics]
                        [--skip-cpu] [--skip-fp64] [--calib-copy]
 """
 import argparse
@@ -293,6 +297,69 @@ def bench_clusters(args, torch, ccfmm, inputs):
     print(json.dumps(res), flush=True)
 
 
+def bench_dynamics(args, torch, ccfmm, inputs):
+    """Repeated evaluation as the moments evolve, on the ferrofluid geometry
+    (2^20 dipoles, p = 6, theta = 0.5, mixed precision): one plan, its captured
+    evaluation replayed after every in-place precession step of the moments,
+    and the energy on the GPU every step.  A step = evaluation + energy +
+    moment update; value = dipoles / step time.  The same loop on an FP64 plan
+    gives the energy the mixed loop is compared with."""
+    from paper_0810_0233_amd import dynamics
+
+    dev = torch.device("cuda:0")
+    c = inputs.config_ferrofluid()
+    pos, box = c["pos"], c["box"]
+    n = pos.shape[0]
+    st = torch.cuda.current_stream().cuda_stream
+    d_pos = torch.from_numpy(pos).to(dev)
+    dt = 0.02
+
+    def run(prec, steps):
+        prm = ccfmm.params(order=c["order"], theta=c["theta"], leaf_target=0.0, box=box, precision=prec,
+                           max_batch=1, m2l_variant=4 if prec == ccfmm.PREC_MIXED else 0)
+        pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+        d_m = torch.from_numpy(np.ascontiguousarray(c["m"][:1])).to(dev)
+        d_H = torch.empty_like(d_m)
+        d_E = torch.empty(steps, dtype=torch.float64, device=dev)
+        if prec == ccfmm.PREC_MIXED:
+            pl.autotune(1, d_m.data_ptr(), d_H.data_ptr(), st)
+            d_m.copy_(torch.from_numpy(np.ascontiguousarray(c["m"][:1])))
+        pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)  # capture
+        d_m.copy_(torch.from_numpy(np.ascontiguousarray(c["m"][:1])))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+            pl.energy_device(1, d_m.data_ptr(), d_H.data_ptr(), d_E[k:k + 1].data_ptr(), st)
+            dynamics.precession_step_(d_m, d_H, dt)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        pl.destroy()
+        return t, d_E.cpu().numpy()
+
+    steps = max(args.steps, 5)
+    run(ccfmm.PREC_MIXED, 2)  # warm-up (first-use allocations)
+    t_mx, E_mx = run(ccfmm.PREC_MIXED, steps)
+    out = {}
+    if not args.skip_fp64:
+        t_64, E_64 = run(ccfmm.PREC_FP64, steps)
+        out = {"fp64_step_ms": 1e3 * t_64, "speedup_vs_fp64_step": t_64 / t_mx,
+               "energy_fp64": [float(x) for x in E_64],
+               "energy_rel_diff_max": float(np.max(np.abs(E_mx - E_64) / np.abs(E_64)))}
+    res = {
+        "metric": METRIC, "value": n / t_mx, "unit": "evals/s", "n_gpus": 1, "steps": steps, "warmup": 2,
+        "ms_per_step": 1e3 * t_mx, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ferrofluid_rsa_1048576_precession", "n": n, "batch": 1, "order": c["order"],
+                   "theta": c["theta"], "precision": "mixed", "dt": dt,
+                   "step": "captured evaluation + energy + moment update (plan reused)"},
+        "energy_mixed": [float(x) for x in E_mx],
+        "roofline": None, "cpu_baseline": None,
+    }
+    res.update(out)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +387,9 @@ def main():
 
     if args.workload == "clusters":
         bench_clusters(args, torch, ccfmm, inputs)
+        return
+    if args.workload == "dynamics":
+        bench_dynamics(args, torch, ccfmm, inputs)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()

@@ -161,6 +161,14 @@ int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out);
 /* Energy E_b = -1/2 sum_i m_i . H_i per configuration (Sec. 3 and Appendix),
  * host arrays; E is [nbatch]. */
 int ccfmm_energy(int64_t n, int32_t nbatch, const double* m, const double* H, double* E);
+/* The same energy on the GPU for device arrays d_m and d_H of the plan's n
+ * dipoles, [nbatch][n][3] each (any order of the dipoles, the same in both);
+ * d_E is [nbatch] FP64, caller-owned.  FP64 sums in an order that depends on n
+ * only (the same result on every call).  Stream-ordered; the partial sums live
+ * in a plan-owned buffer (allocated on the first call for a larger nbatch), so
+ * calls on one plan must not overlap. */
+int ccfmm_plan_energy_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, const double* d_H, double* d_E,
+                             void* stream);
 /* NULL-safe. */
 void ccfmm_plan_destroy(ccfmm_plan plan);
 

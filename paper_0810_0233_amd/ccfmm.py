@@ -58,7 +58,7 @@ class ccfmm_pass_times(C.Structure):
 EXPORTS = [
     "ccfmm_status_string", "ccfmm_last_error", "ccfmm_params_default", "ccfmm_plan_create",
     "ccfmm_plan_create_device", "ccfmm_plan_update_positions_device", "ccfmm_eval", "ccfmm_eval_device",
-    "ccfmm_eval_device_timed", "ccfmm_plan_autotune", "ccfmm_plan_info", "ccfmm_energy", "ccfmm_plan_destroy",
+    "ccfmm_eval_device_timed", "ccfmm_plan_autotune", "ccfmm_plan_info", "ccfmm_energy", "ccfmm_plan_energy_device", "ccfmm_plan_destroy",
     "ccfmm_direct_targets_device", "ccfmm_selftest_mfma",
     "ccfmm_plan_set_leaf_params", "ccfmm_plan_get_leaf_params", "ccfmm_plan_leaf_ids", "ccfmm_plan_leaf_features",
     "ccfmm_plan_leaf_errors", "ccfmm_mlp_forward", "ccfmm_mlp_loss_grad", "ccfmm_mlp_adam", "ccfmm_plan_select",
@@ -114,6 +114,8 @@ def lib():
                                           C.POINTER(ccfmm_tune_entry), C.c_int32, C.POINTER(C.c_int32)]
         L.ccfmm_plan_info.argtypes = [C.c_void_p, C.POINTER(ccfmm_info)]
         L.ccfmm_energy.argtypes = [C.c_int64, C.c_int32, _dp, _dp, _dp]
+        L.ccfmm_plan_energy_device.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.c_void_p]
         L.ccfmm_plan_destroy.argtypes = [C.c_void_p]
         L.ccfmm_plan_destroy.restype = None
         L.ccfmm_direct_targets_device.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
@@ -218,6 +220,11 @@ class Plan:
 
     def eval_device(self, nbatch, d_m, d_H, stream=0):
         _check(lib().ccfmm_eval_device(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H), C.c_void_p(stream)))
+
+    def energy_device(self, nbatch, d_m, d_H, d_E, stream=0):
+        """E_b = -1/2 sum_i m_i . H_i on the GPU into d_E [nbatch] (FP64)."""
+        _check(lib().ccfmm_plan_energy_device(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H), C.c_void_p(d_E),
+                                              C.c_void_p(stream)))
 
     def eval_device_timed(self, nbatch, d_m, d_H, stream=0):
         t = ccfmm_pass_times()

@@ -974,6 +974,18 @@ int ccfmm_plan_select(ccfmm_plan plan, const float* d_params, double err_bound, 
   });
 }
 
+int ccfmm_plan_energy_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, const double* d_H, double* d_E,
+                             void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (nbatch < 1 || !d_m || !d_H || !d_E) fail(CCFMM_EINVAL, "invalid argument");
+    Plan& P = plan->P;
+    CCFMM_HIP(hipSetDevice(P.device));
+    run_energy(P, nbatch, d_m, d_H, d_E, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
 int ccfmm_direct_targets_device(int64_t n, const double* d_pos, const double* d_m, int64_t nt, const int64_t* d_idx,
                                 double* d_H, void* stream) {
   return guarded([&] {

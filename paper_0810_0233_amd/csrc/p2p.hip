@@ -1052,6 +1052,56 @@ __global__ void __launch_bounds__(256) k_direct_targets(int64_t n, const double*
   }
 }
 
+// ------------------------------------------------------------ energy
+// E_b = -1/2 sum_i m_i . H_i (Sec. 3 with the Appendix's factor 1/2) per
+// configuration, FP64.  A fixed grid of kEnergyBlocks blocks per
+// configuration each sums a contiguous range of the 3n products (threads
+// strided, then a tree in LDS); one block per configuration adds the partial
+// sums in block order.  The order of every addition depends on n only, so
+// the result is the same on every call.
+constexpr int kEnergyBlocks = 256;
+
+__global__ void __launch_bounds__(256) k_energy_part(int64_t n3, const double* __restrict__ m,
+                                                     const double* __restrict__ H, double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int b = blockIdx.y, g = blockIdx.x, t = threadIdx.x;
+  const int64_t chunk = (n3 + kEnergyBlocks - 1) / kEnergyBlocks;
+  const int64_t lo = (int64_t)g * chunk, hi = min(n3, lo + chunk);
+  const double* mb = m + (int64_t)b * n3;
+  const double* hb = H + (int64_t)b * n3;
+  double s = 0.0;
+  for (int64_t i = lo + t; i < hi; i += 256) s += mb[i] * hb[i];
+  sh[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) part[(int64_t)b * kEnergyBlocks + g] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_energy_final(const double* __restrict__ part, double* __restrict__ E) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  double s = 0.0;
+  for (int g = t; g < kEnergyBlocks; g += 256) s += part[(int64_t)b * kEnergyBlocks + g];
+  sh[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) E[b] = -0.5 * sh[0];
+}
+
+void run_energy(Plan& P, int nb, const double* d_m, const double* d_H, double* d_E, hipStream_t st) {
+  double* part = reinterpret_cast<double*>(P.energy_part.ensure(sizeof(double) * (size_t)kEnergyBlocks * nb));
+  k_energy_part<<<dim3(kEnergyBlocks, nb), 256, 0, st>>>(3 * P.n, d_m, d_H, part);
+  CCFMM_HIP(hipGetLastError());
+  k_energy_final<<<nb, 256, 0, st>>>(part, d_E);
+  CCFMM_HIP(hipGetLastError());
+}
+
 void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt, const int64_t* d_idx,
                         double* d_H, hipStream_t st) {
   if (nt <= 0) return;

@@ -120,6 +120,7 @@ struct Plan {
   const void* g_m = nullptr;
   void* g_H = nullptr;
   DevBuf host_m, host_H;  // staging of the host-pointer evaluation (stable addresses)
+  DevBuf energy_part;     // per-block partial sums of the energy (nbatch x kEnergyBlocks)
   ccfmm_info info{};
   bool built = false;
   void drop_graph() {
@@ -152,6 +153,7 @@ void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st);  // near + smoot
 void run_near(Plan& P, int nb, double* d_H, hipStream_t st);     // near field written to H
 void run_l2p(Plan& P, int nb, double* d_H, hipStream_t st);      // smooth field added to H
 void run_permute(Plan& P, int nb, const double* d_m, hipStream_t st);
+void run_energy(Plan& P, int nb, const double* d_m, const double* d_H, double* d_E, hipStream_t st);
 void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt,
                         const int64_t* d_idx, double* d_H, hipStream_t st);
 
