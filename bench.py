@@ -27,7 +27,11 @@ trained on the GPU first, from two training geometries of the same recipe).
 its captured evaluation replayed after every in-place precession step of the
 moments, the energy taken on the GPU every step (and the same loop in FP64).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|dynamics]
+`--workload leafsweep`: the paper's leaf-size study (Table I, Eq. (so)) redone on
+the GPU path: trees two levels either side of s_o(p) for Table II's (p, alpha)
+pairs, on 32^3 and 128^3 lattices and the ferrofluid.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|dynamics|leafsweep]
                        [--skip-cpu] [--skip-fp64] [--calib-copy]
 """
 import argparse
@@ -360,6 +364,41 @@ def bench_dynamics(args, torch, ccfmm, inputs):
     print(json.dumps(res), flush=True)
 
 
+def bench_leafsweep(args, torch, ccfmm, inputs):
+    """GPU re-study of the paper's leaf-size choice (Table I, Eq. (so)): trees two
+    levels either side of the paper's s_o(p) for Table II's (p, alpha) pairs on
+    the paper's 32^3 lattice and on a 128^3 lattice, and for the ferrofluid at
+    (6, 0.5); mixed precision.  One JSON line with every swept point; value =
+    ferrofluid evals/s (full step) at the fastest tree of the sweep."""
+    from paper_0810_0233_amd import study
+
+    pairs = [(2, 0.36), (3, 0.54), (4, 0.64), (5, 0.71), (6, 0.76)]
+    res = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "steps": 7, "warmup": 1}
+    studies = {}
+    for side in (32, 128):
+        pos, box = inputs.lattice(side, side, side)
+        m = inputs.random_moments(pos.shape[0], 6000 + side)
+        log("leaf sweep: %d^3 lattice" % side)
+        recs = study.leaf_sweep(pos, box, m, pairs, progress=log)
+        for r in recs:
+            log("  p=%d theta=%.2f paper s=%.2f (L=%d): best L=%d, s_opt %.1f, %.2fx vs paper" % (
+                r["order"], r["theta"], r["paper_s"], r["paper_levels"], r["best_levels"], r["s_opt"],
+                r["speedup_best_vs_paper"]))
+        studies["lattice_%d" % side] = {"records": recs, "c_fit": study.fit_c(recs)}
+    c = inputs.config_ferrofluid()
+    log("leaf sweep: ferrofluid")
+    recs = study.leaf_sweep(c["pos"], c["box"], c["m"][0], [(6, 0.5)], progress=log)
+    studies["ferrofluid_rsa_1048576"] = {"records": recs}
+    best = min(recs[0]["points"], key=lambda r: r["step_ms"])
+    n = c["pos"].shape[0]
+    res.update({"value": n / (best["step_ms"] * 1e-3), "ms_per_step": best["step_ms"],
+                "config": {"workload": "leafsweep", "ferrofluid_best_levels": best["levels"],
+                           "ferrofluid_paper_levels": recs[0]["paper_levels"]},
+                "study": studies, "roofline": None, "cpu_baseline": None})
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +429,9 @@ def main():
         return
     if args.workload == "dynamics":
         bench_dynamics(args, torch, ccfmm, inputs)
+        return
+    if args.workload == "leafsweep":
+        bench_leafsweep(args, torch, ccfmm, inputs)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()

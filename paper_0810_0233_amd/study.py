@@ -1,0 +1,125 @@
+"""GPU re-study of the paper's leaf-size choice (Sec. 4, Table I and Eq. (so)).
+
+The paper times its CPU code against the mean number s of dipoles per smallest
+cell and fits the optimal s_o(p) = 0.74 p^2 (p > 3; 8 below).  Here the same
+sweep runs on the GPU path unchanged: for each (p, theta) the number of levels
+L is stepped around the paper's choice (s = N / 2^L selects exactly L), and
+each tree is timed (one full step: rebuild for the positions plus the
+evaluation; and the captured evaluation alone) and its error measured against
+the FP64 direct sum at sampled dipoles.  The GPU-optimal s per order comes
+from a parabola through the three fastest levels in log2 s, and c in
+s_o = c p^2 from a least-squares fit over the orders above 3.
+"""
+import time
+
+import numpy as np
+
+
+def paper_s(p):
+    """Eq. (so): s_o = 0.74 p^2 for p > 3, else 8."""
+    return 0.74 * p * p if p > 3 else 8.0
+
+
+def paper_levels(n, s):
+    """The paper's level rule: L = argmin |N / 2^L - s| (ties: the smaller L)."""
+    return int(np.argmin([abs(n / 2.0 ** L - s) for L in range(40)]))
+
+
+def _timed(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def leaf_sweep(pos, box, m, pairs, dL=(-2, -1, 0, 1, 2), precision=None, reps=7, samples=1024, seed=11,
+               progress=None):
+    """Sweep the number of levels for each (p, theta) in pairs.
+
+    pos [n][3], m [n][3] FP64 host arrays; box (lo, hi) or None.  Returns a list
+    of records, one per (p, theta), with the swept points and the fitted
+    optimum.  progress(str), if given, is called after every point."""
+    import torch
+
+    from paper_0810_0233_amd import ccfmm
+
+    if precision is None:
+        precision = ccfmm.PREC_MIXED
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    n = pos.shape[0]
+    d_pos = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+    d_m = torch.from_numpy(np.ascontiguousarray(m[None])).to(dev)
+    d_H = torch.empty_like(d_m)
+    idx = np.sort(np.random.default_rng(seed).choice(n, size=min(samples, n), replace=False)).astype(np.int64)
+    d_idx = torch.from_numpy(idx).to(dev)
+    d_Hd = torch.empty((idx.size, 3), dtype=torch.float64, device=dev)
+    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m[0].data_ptr(), idx.size, d_idx.data_ptr(), d_Hd.data_ptr(),
+                                st)
+    torch.cuda.synchronize()
+    Hd = d_Hd.cpu().numpy()
+    out = []
+    for p, th in pairs:
+        L0 = paper_levels(n, paper_s(p))
+        pts = []
+        for d in dL:
+            L = L0 + d
+            if L < 1:
+                continue
+            prm = ccfmm.params(order=p, theta=th, leaf_target=n / 2.0 ** L, box=box, precision=precision,
+                               max_batch=1)
+            pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+            if precision == ccfmm.PREC_MIXED:
+                pl.autotune(1, d_m.data_ptr(), d_H.data_ptr(), st)
+            t_eval = _timed(lambda: pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st), reps, torch)
+
+            def step():
+                pl.update_positions_device(d_pos.data_ptr(), st)
+                pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+
+            t_step = _timed(step, reps, torch)
+            H = d_H[0].cpu().numpy()
+            err = float(np.sqrt(np.sum((H[idx] - Hd) ** 2) / np.sum(Hd ** 2)))
+            inf = pl.info()
+            pl.destroy()
+            pts.append({"levels": L, "s": n / 2.0 ** L, "eval_ms": 1e3 * t_eval, "step_ms": 1e3 * t_step,
+                        "eps_abs": err, "m2l_pairs": inf["n_m2l_pairs"], "p2p_pairs": inf["n_p2p_pairs"]})
+            if progress:
+                progress("p=%d theta=%.2f L=%d s=%.2f: step %.3f ms, eval %.3f ms, eps_abs %.2e" % (
+                    p, th, L, n / 2.0 ** L, 1e3 * t_step, 1e3 * t_eval, err))
+        best = min(pts, key=lambda r: r["step_ms"])
+        out.append({"order": p, "theta": th, "paper_s": paper_s(p), "paper_levels": L0, "points": pts,
+                    "best_levels": best["levels"], "s_opt": optimum_s(pts, "step_ms"),
+                    "s_opt_eval": optimum_s(pts, "eval_ms"),
+                    "speedup_best_vs_paper": next(r["step_ms"] for r in pts if r["levels"] == L0) / best["step_ms"]})
+    return out
+
+
+def optimum_s(pts, key):
+    """s at the minimum of a parabola through the fastest point and its two
+    neighbours in log2 s (the fastest point itself at an end of the sweep)."""
+    pts = sorted(pts, key=lambda r: r["s"])
+    k = min(range(len(pts)), key=lambda i: pts[i][key])
+    if k == 0 or k == len(pts) - 1:
+        return pts[k]["s"]
+    x = np.log2([pts[k - 1]["s"], pts[k]["s"], pts[k + 1]["s"]])
+    y = np.array([pts[k - 1][key], pts[k][key], pts[k + 1][key]])
+    a, b, _ = np.polyfit(x, y, 2)
+    if a <= 0:
+        return pts[k]["s"]
+    return float(2.0 ** np.clip(-b / (2 * a), x[0], x[2]))
+
+
+def fit_c(records):
+    """Least-squares c in s_opt = c p^2 over the orders above 3 (Eq. (so)'s form)."""
+    rs = [r for r in records if r["order"] > 3]
+    if not rs:
+        return None
+    p2 = np.array([r["order"] ** 2 for r in rs], dtype=float)
+    s = np.array([r["s_opt"] for r in rs], dtype=float)
+    return float(np.dot(p2, s) / np.dot(p2, p2))

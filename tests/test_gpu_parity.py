@@ -492,3 +492,26 @@ def test_time_stepping_with_plan_reuse(ref):
         c = mc + dt * np.cross(mc, H)
         mc = c / np.linalg.norm(c, axis=1, keepdims=True)
 
+
+@pytest.mark.parametrize("order,theta", [(3, 0.54), (6, 0.76)])
+@pytest.mark.parametrize("dl", [-2, 2])
+def test_leaf_sweep_points_match_oracle(ref, order, theta, dl):
+    """The leaf-size study runs the path unchanged at trees two levels above and
+    below the paper's choice (Table II's (p, alpha) pairs): there too the FP64
+    GPU field equals the oracle FMM and the tree structure is the same."""
+    from paper_0810_0233_amd import study
+
+    pos, box = inputs.lattice(16, 16, 16)
+    n = pos.shape[0]
+    m = inputs.random_moments(n, 120 + order)
+    L = study.paper_levels(n, study.paper_s(order)) + dl
+    s = n / 2.0 ** L
+    H_ref, st = ref.fmm(pos, m, order, theta, leaf_target=s, box=box, return_stats=True)
+    pl = plan_for(pos, order, theta, s, box)
+    inf = pl.info()
+    assert inf["levels"] == st["levels"] == L
+    assert inf["m2l_pairs_per_level"] == st["m2l_pairs_per_level"]
+    assert inf["n_p2p_leaf_pairs"] == st["n_p2p_leaf_pairs"]
+    assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
+    pl.destroy()
+
