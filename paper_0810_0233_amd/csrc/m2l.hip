@@ -335,21 +335,82 @@ __device__ __forceinline__ int op_index_kperm(int m, int kq, int ks) {
   return op_index<P>(m, kq * KS + ks);
 }
 
+// Operator layout of the wide kernels: slot e of row block mb holds, for
+// steps 4 k4 .. 4 k4 + 3 of lane l, the float4 at k4 * 256 + 4 l (so a lane
+// reads four steps' fragments at once); the KT steps past the last full
+// group follow as one word per lane each.  Row length padded to a multiple
+// of 1024 words (whole 16-byte loads of four wavefronts).
+template <int P>
+struct WideOp {
+  static constexpr int NP = nact(P), NS = nstride(P), KS = NS / 4, MB = (NP + 15) / 16, ND = ncoef(2 * P);
+  static constexpr int K4 = KS / 4, KT = KS % 4;
+  static constexpr int NE = MB * KS * 64;                 // operator entries
+  static constexpr int NEP = (NE + 1023) / 1024 * 1024;  // padded row length
+};
+
+// derivative-tensor index of slot e (ND, the row's trailing zero, for padding)
+template <int P>
+__device__ __forceinline__ int wide_slot_dindex(int e) {
+  using W = WideOp<P>;
+  if (e >= W::NE) return W::ND;
+  const int mb = e / (W::KS * 64), r0 = e % (W::KS * 64);
+  int ks, l;
+  if (r0 < W::K4 * 256) {
+    ks = 4 * (r0 / 256) + (r0 & 3);
+    l = (r0 % 256) >> 2;
+  } else {
+    ks = 4 * W::K4 + (r0 - W::K4 * 256) / 64;
+    l = r0 & 63;
+  }
+  return op_index_kperm<P>(16 * mb + (l & 15), l >> 4, ks);
+}
+
+// Every derivative-table row expanded into that layout (FP32), once per
+// table: a step's operator is then one contiguous block of memory.
+template <int P>
+__global__ void k_expand_ops(int64_t nrows, const float* __restrict__ Df, float* __restrict__ Dx) {
+  using W = WideOp<P>;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * W::NEP) return;
+  const int64_t r = t / W::NEP;
+  const int e = (int)(t % W::NEP);
+  Dx[t] = Df[r * drow_stride(P) + wide_slot_dindex<P>(e)];
+}
+
+template <int P>
+static void expand_ops_impl(Plan& P_, hipStream_t st) {
+  using W = WideOp<P>;
+  float* Dx = reinterpret_cast<float*>(P_.Dx.ensure(sizeof(float) * (size_t)P_.nrows * W::NEP));
+  const int64_t nt = P_.nrows * W::NEP;
+  k_expand_ops<P><<<ceil_div(nt, 256), 256, 0, st>>>(P_.nrows, P_.Df.as<float>(), Dx);
+  CCFMM_HIP(hipGetLastError());
+}
+
+void build_wide_ops(Plan& P, hipStream_t st) {
+  switch (P.p) {
+    case 1: expand_ops_impl<1>(P, st); break;
+    case 2: expand_ops_impl<2>(P, st); break;
+    case 3: expand_ops_impl<3>(P, st); break;
+    case 4: expand_ops_impl<4>(P, st); break;
+    case 5: expand_ops_impl<5>(P, st); break;
+    case 6: expand_ops_impl<6>(P, st); break;
+    default: break;  // the wide kernels serve orders up to 6
+  }
+}
+
 template <int P, int CB>
 __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile* __restrict__ tiles,
                                                    const int32_t* __restrict__ tile_order, int64_t ntiles,
                                                    const int32_t* __restrict__ tile_tgt,
                                                    const int32_t* __restrict__ step_delta,
                                                    const int32_t* __restrict__ step_src,
-                                                   const float* __restrict__ Dtab, const float* __restrict__ Q,
+                                                   const float* __restrict__ Dop, const float* __restrict__ Q,
                                                    float* __restrict__ V, LevelOffsets lo, int nb, int TB, int TC) {
-  constexpr int NP = nact(P), NS = nstride(P), KS = NS / 4, MB = (NP + 15) / 16, ND = ncoef(2 * P);
-  constexpr int NE = MB * KS * 64;       // operator entries in fragment order
-  constexpr int ER = (NE + 255) / 256;   // per thread
-  constexpr int K4 = KS / 4, KT = KS % 4;  // full groups of 4 steps, steps left over
-  static_assert(4 * ND < 65536, "operator byte offsets are kept in 16 bits");
-  // padded so every thread stores unconditionally; fragments read as float4
-  __shared__ __attribute__((aligned(16))) float sT[2][ER * 256];
+  using W = WideOp<P>;
+  constexpr int NS = W::NS, KS = W::KS, MB = W::MB, NP = W::NP;
+  constexpr int K4 = W::K4, KT = W::KT;  // full groups of 4 steps, steps left over
+  constexpr int NEP = W::NEP;             // operator words per step (padded)
+  __shared__ __attribute__((aligned(16))) float sT[2][NEP];
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   // tiles are launched longest first (greedy balance over the compute units)
@@ -358,32 +419,6 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   const float* Ql = Q + lo.qoff[tl.level];
   const int nsteps = tl.nsteps;
 
-  // this thread's operator entries e = t + 256 r: byte offset of the
-  // derivative-tensor entry in its row (ND: the row's trailing zero)
-  uint32_t eidx[(ER + 1) / 2];  // two 16-bit offsets per register
-#pragma unroll
-  for (int r = 0; r < (ER + 1) / 2; r++) eidx[r] = 0;
-#pragma unroll
-  for (int r = 0; r < ER; r++) {
-    const int e = t + 256 * r;
-    int v = ND;
-    if (e < NE) {
-      // LDS slot e of row block mb: steps 4 k4 .. 4 k4 + 3 of lane l are the
-      // float4 at k4 * 256 + 4 l; the KT steps past the last full group follow
-      // as one word per lane each
-      const int mb = e / (KS * 64), r0 = e % (KS * 64);
-      int ks, l;
-      if (r0 < K4 * 256) {
-        ks = 4 * (r0 / 256) + (r0 & 3);
-        l = (r0 % 256) >> 2;
-      } else {
-        ks = 4 * K4 + (r0 - K4 * 256) / 64;
-        l = r0 & 63;
-      }
-      v = op_index_kperm<P>(16 * mb + (l & 15), l >> 4, ks);
-    }
-    eidx[r >> 1] |= (uint32_t)(4 * v) << (16 * (r & 1));  // byte offset; ND is the row's zero
-  }
   // this lane's columns: 16 CB w + 16 cb + lane % 16, fragment rows kq KS .. kq KS + KS - 1
   const int kq = lane >> 4;
   int ctc[CB], cb_b[CB];
@@ -395,9 +430,8 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     if (!(ctc[cb] < TC && cb_b[cb] < nb)) ctc[cb] = -1;
   }
   // Loads are unconditional: an empty column reads g_zero_row through a
-  // selected address and a padding operator entry reads the zero that ends
-  // every derivative-table row, so no loaded value has a consumer before the
-  // products that need it and the loads stay in flight meanwhile.
+  // selected address, so no loaded value has a consumer before the products
+  // that need it and the loads stay in flight meanwhile.
   auto load_src = [&](int s, int (&src)[CB]) {
     const int64_t st = (int64_t)tl.step0 + s;
 #pragma unroll
@@ -416,17 +450,16 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
       for (int ks = 0; ks < KS; ks++) B[cb][ks] = q[ks];
     }
   };
-  // the operator of step s goes from memory straight into sT[buf] (no
-  // registers): lane l of wavefront w writes entry 256 r + 64 w + l
+  // the operator of step s (its expanded row, already in LDS order) goes from
+  // memory straight into sT[buf] (no registers): 16-byte loads, lane l of
+  // wavefront w covering words 1024 r + 256 w + 4 l .. + 3
   auto load_op = [&](int s, int buf) {
-    const char* drow = reinterpret_cast<const char*>(Dtab + (int64_t)step_delta[tl.step0 + s] * drow_stride(P));
+    const float* orow = Dop + (int64_t)step_delta[tl.step0 + s] * NEP;
 #pragma unroll
-    for (int r = 0; r < ER; r++) {
-      const uint32_t off = (eidx[r >> 1] >> (16 * (r & 1))) & 0xffffu;  // byte offset in the row
-      const char* g = drow + off;
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
-                                       (__attribute__((address_space(3))) void*)&sT[buf][256 * r + 64 * w], 4, 0,
-                                       0);
+    for (int r = 0; r < NEP / 1024; r++) {
+      const int o = 1024 * r + 256 * w;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(orow + o + 4 * lane),
+                                       (__attribute__((address_space(3))) void*)&sT[buf][o], 16, 0, 0);
     }
   };
   // all of this wavefront's memory loads have landed (vmcnt = 0)
@@ -526,7 +559,8 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
 #define CCFMM_WIDE(CB)                                                                                               \
   k_m2l_wide<PP, CB><<<nblk, 256, 0, st>>>(P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles,            \
                                            P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),                    \
-                                           P.step_src.as<int32_t>(), D, P.Q.as<T>(), P.V.as<T>(), lo, nb, P.TB, P.TC)
+                                           P.step_src.as<int32_t>(), P.Dx.as<float>(), P.Q.as<T>(), P.V.as<T>(), lo,   \
+                                           nb, P.TB, P.TC)
       if (P.tiles_variant == kM2LWide4)
         CCFMM_WIDE(4);
       else if (P.tiles_variant == kM2LWide2)

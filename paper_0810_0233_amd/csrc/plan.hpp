@@ -74,6 +74,7 @@ struct Plan {
   // kept across rebuilds while the keys do not change
   int64_t nrows = 0;
   DevBuf Dd, Df;
+  DevBuf Dx;  // FP32 rows expanded into the wide M2L kernels' LDS order (mixed precision, p <= 6)
   int dtab_p = 0;
   std::vector<std::array<double, 6>> dtab_keys;
   // M2L tiles
@@ -153,6 +154,7 @@ void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st);  // near + smoot
 void run_near(Plan& P, int nb, double* d_H, hipStream_t st);     // near field written to H
 void run_l2p(Plan& P, int nb, double* d_H, hipStream_t st);      // smooth field added to H
 void run_permute(Plan& P, int nb, const double* d_m, hipStream_t st);
+void build_wide_ops(Plan& P, hipStream_t st);  // expanded operator rows (Dx) from Df
 void run_energy(Plan& P, int nb, const double* d_m, const double* d_H, double* d_E, hipStream_t st);
 void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt,
                         const int64_t* d_idx, double* d_H, hipStream_t st);
