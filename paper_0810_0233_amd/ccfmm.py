@@ -234,10 +234,10 @@ class Plan:
 
     def autotune(self, nbatch, d_m, d_H, stream=0):
         """Time the M2L variants on this plan, keep the fastest; returns the timings."""
-        out = (ccfmm_tune_entry * 16)()
+        out = (ccfmm_tune_entry * 32)()
         n = C.c_int32(0)
         _check(lib().ccfmm_plan_autotune(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H),
-                                         C.c_void_p(stream), out, 16, C.byref(n)))
+                                         C.c_void_p(stream), out, 32, C.byref(n)))
         return [{"variant": out[i].variant, "class_bits": out[i].class_bits, "m2l_ms": out[i].m2l_ms,
                  "steps": out[i].steps} for i in range(n.value)]
 
