@@ -6,10 +6,10 @@
 //
 // One wavefront per chunk of <= 64 dipoles of one smallest cell.  The c
 // dipoles of a chunk are split as c = a + b (a the largest power of two <= c):
-// the first a get G1 = 64/a lanes each, the other b get G2 = 64/pow2ceil(b)
-// lanes each, so every lane works in both roles whatever c is.  The lanes of
-// a dipole split the sources, and their partial fields are combined with
-// cross-lane butterflies at the end.  Sources are staged 64 at a time in LDS,
+// the first a get G1 = 64/a lanes each, the other b get G2 = floor(64/b)
+// lanes each, so nearly every lane works in both roles whatever c is.  The
+// lanes of a dipole split the sources, and their partial fields are combined
+// at the end (butterflies in the first role, a segmented tree in the second).  Sources are staged 64 at a time in LDS,
 // packed from consecutive near cells (each shifted by the integer offset of its
 // cell so all coordinates stay cell-relative) and padded with null sources
 // (zero moment, far away) that add exactly zero, so every lane runs the same
@@ -133,6 +133,12 @@ __device__ __forceinline__ void p2p_run(const P2PSrc<T>* __restrict__ src, const
   for (; k < K; k++, q += G, ql += G) p2p_pair<T, kSelf, kAcc>(q[0], ql, t, fx, fy, fz);
 }
 
+// G lanes per target: a power of two (first role) or floor(64 / b) for the b
+// targets of the second role.  A lane reads slots sub + k G < K G, which can
+// pass the 64 staged sources by up to 20 (G = 21): those slots hold null
+// sources.
+constexpr int kP2PPad = 24;
+
 template <typename T, bool kSelf, bool kAcc>
 __device__ __forceinline__ void p2p_role(const P2PSrc<T>* __restrict__ src, const P2PLo<T>* __restrict__ lo, int G,
                                          int sub, int nsrc, const P2PTgt<T>& t, T& fx, T& fy, T& fz) {
@@ -140,9 +146,17 @@ __device__ __forceinline__ void p2p_role(const P2PSrc<T>* __restrict__ src, cons
   switch (G) {
     case 1: p2p_run<T, 1, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
     case 2: p2p_run<T, 2, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 3: p2p_run<T, 3, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
     case 4: p2p_run<T, 4, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 5: p2p_run<T, 5, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 6: p2p_run<T, 6, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 7: p2p_run<T, 7, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
     case 8: p2p_run<T, 8, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 9: p2p_run<T, 9, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 10: p2p_run<T, 10, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 12: p2p_run<T, 12, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
     case 16: p2p_run<T, 16, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
+    case 21: p2p_run<T, 21, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
     case 32: p2p_run<T, 32, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
     default: p2p_run<T, 64, kSelf, kAcc>(src, lo, sub, K, t, fx, fy, fz); break;
   }
@@ -186,8 +200,8 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
                                                            const T* __restrict__ msort, const T* __restrict__ V,
                                                            double* __restrict__ H) {
   constexpr int NS = nstride(P);
-  __shared__ P2PSrc<T> sS[kP2PWaves][64];
-  __shared__ P2PLo<T> sL[kP2PWaves][64];
+  __shared__ P2PSrc<T> sS[kP2PWaves][64 + kP2PPad];
+  __shared__ P2PLo<T> sL[kP2PWaves][64 + kP2PPad];
   // the wave index is uniform: say so, so chunk data, counts and loop bounds
   // live in scalar registers and branch on scalar conditions
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -204,9 +218,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
   int A = 1;
   while (2 * A <= c) A <<= 1;
   const int B = c - A;
-  int bp = 1;
-  while (bp < B) bp <<= 1;
-  const int G1 = 64 / A, G2 = 64 / bp;
+  const int G1 = 64 / A, G2 = B > 0 ? 64 / B : 64;  // G2 in {1..10, 12, 16, 21, 32, 64}
   const int t1 = lane / G1, sub1 = lane % G1;
   const int t2 = A + lane / G2, sub2 = lane % G2;
   const bool act2 = B > 0 && t2 < c;
@@ -227,6 +239,15 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
   const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
   P2PSrc<T>* src = sS[w];
   P2PLo<T>* srclo = sL[w];
+  if (lane < kP2PPad) {  // null sources past the batch (read by strides that do not divide 64)
+    P2PSrc<T> z;
+    z.x = z.y = z.z = (T)1e4;
+    z.mx = z.my = z.mz = z.p0 = z.p1 = (T)0;
+    src[64 + lane] = z;
+    P2PLo<T> zl;
+    zl.x = zl.y = zl.z = zl.p = (T)0;
+    srclo[64 + lane] = zl;
+  }
   const int e0 = a.near_ptr[ch.leaf], e1 = a.near_ptr[ch.leaf + 1];
   // Near-list metadata, 64 entries at a time, one entry per lane: first sorted
   // dipole, count, and the cell offset in cell-relative units.  The batch
@@ -370,10 +391,15 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
     hy1 += __shfl_xor(hy1, off);
     hz1 += __shfl_xor(hz1, off);
   }
+  // second role: G2 need not be a power of two; a segmented tree leaves each
+  // dipole's sum in its first lane (sub2 = 0, the one that writes)
   for (int off = 1; off < G2; off <<= 1) {
-    hx2 += __shfl_xor(hx2, off);
-    hy2 += __shfl_xor(hy2, off);
-    hz2 += __shfl_xor(hz2, off);
+    const double ox = __shfl_down(hx2, off), oy = __shfl_down(hy2, off), oz = __shfl_down(hz2, off);
+    if (sub2 + off < G2) {
+      hx2 += ox;
+      hy2 += oy;
+      hz2 += oz;
+    }
   }
   const double s3 = a.inv_s3;
   if constexpr (kL2P) {
