@@ -11,9 +11,12 @@ lattice, 64 magnetisation configurations (random directions plus 0-50% of
 seeded sites aligned along +z), p = 5, theta = 0.5, evaluated together.
 
 A step is one pass of the whole method over one batch with the positions and
-moments already in HBM: tree and lists rebuilt in place for the (possibly
-moved) dipoles, derivative tensors, P2M, M2M, M2L, L2L, L2P and the near-field
-sum.  `value` = dipoles x configurations / step time.  The same run reports
+moments already in HBM: tree rebuilt in place for moved dipoles (the steps
+alternate between the configuration's positions and a copy displaced by
+N(0, 0.01^2) per coordinate), cell lists and M2L tiles rebuilt unless the
+same cells stay occupied (then they are provably unchanged and kept),
+derivative tensors, P2M, M2M, M2L, L2L, L2P and the near-field sum.  The step
+with every list and tile rebuilt is reported beside it.  `value` = dipoles x configurations / step time.  The same run reports
 the evaluation alone (tree reused, captured graph replayed), the plain FP64
 GPU FMM, the error of the mixed result against the FP64 GPU FMM (eps_prec) and
 against the direct sum at sampled dipoles (eps_abs), the roofline of the
@@ -441,6 +444,10 @@ def main():
     order, theta = W["order"], W["theta"]
     log("inputs: %s n=%d batch=%d (%.1f s)" % (W["name"], n, nb, time.time() - t0))
     d_pos = torch.from_numpy(pos).to(dev)
+    # the moved copy for time steps: displaced by N(0, 0.01^2) per coordinate, kept inside the root box
+    lo_b, hi_b = np.asarray(box[0], float), np.asarray(box[1], float)
+    pos_b = np.clip(pos + 0.01 * np.random.default_rng(17).normal(size=pos.shape), lo_b + 1e-9, hi_b - 1e-9)
+    d_pos_b = torch.from_numpy(pos_b).to(dev)
     d_m = torch.from_numpy(np.ascontiguousarray(m)).to(dev)
     d_H = torch.empty_like(d_m)
     d_H64 = torch.empty_like(d_m)
@@ -452,18 +459,25 @@ def main():
         return ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, sh)
 
     def time_steps(plan, out, rebuild, steps, warmup):
-        for _ in range(warmup):
+        """Mean step time; with rebuild, every step first moves the dipoles
+        (alternating the two position sets); the plan ends on the original."""
+        sets = (d_pos_b, d_pos)
+        for k in range(warmup):
             if rebuild:
-                plan.update_positions_device(d_pos.data_ptr(), sh)
+                plan.update_positions_device(sets[k % 2].data_ptr(), sh)
             plan.eval_device(nb, d_m.data_ptr(), out.data_ptr(), sh)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
+        for k in range(steps):
             if rebuild:
-                plan.update_positions_device(d_pos.data_ptr(), sh)
+                plan.update_positions_device(sets[k % 2].data_ptr(), sh)
             plan.eval_device(nb, d_m.data_ptr(), out.data_ptr(), sh)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / steps
+        t = (time.perf_counter() - t) / steps
+        if rebuild:
+            plan.update_positions_device(d_pos.data_ptr(), sh)
+            torch.cuda.synchronize()
+        return t
 
     # ---- mixed precision: the headline path
     plan = make(ccfmm.PREC_MIXED)
@@ -475,8 +489,16 @@ def main():
     log("plan: L=%d leaves=%d m2l_pairs=%d p2p_pairs=%d tiles=%d steps=%d" % (
         info["levels"], info["n_leaves"], info["n_m2l_pairs"], info["n_p2p_pairs"], info["n_m2l_tiles"],
         info["n_m2l_steps"]))
+    kept0 = plan.info()["n_rebuilds_kept"]
     t_step = time_steps(plan, d_H, True, args.steps, args.warmup)
-    log("mixed full step: %.3f ms" % (1e3 * t_step))
+    kept = plan.info()["n_rebuilds_kept"] - kept0
+    log("mixed full step: %.3f ms (%d of %d rebuilds kept the lists)" % (1e3 * t_step, kept,
+                                                                          args.steps + args.warmup + 1))
+    planr = make(ccfmm.PREC_MIXED, keep_lists=0, m2l_variant=info["m2l_variant"],
+                 m2l_class_bits=info["m2l_class_bits"])
+    t_step_full = time_steps(planr, d_H, True, args.steps, args.warmup)
+    planr.destroy()
+    log("mixed step, lists and tiles always rebuilt: %.3f ms" % (1e3 * t_step_full))
     t_eval = time_steps(plan, d_H, False, args.steps, args.warmup)
     log("mixed eval only: %.3f ms" % (1e3 * t_eval))
     overlapped = plan.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
@@ -579,8 +601,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": W["name"], "n": n, "batch": nb, "order": order, "theta": theta,
                    "leaf_target": info["s_used"], "levels": info["levels"], "precision": "mixed",
-                   "step": "tree+lists+tensors+eval",
+                   "step": "rebuild for moved dipoles (tree; lists and tiles unless the occupied cells are the "
+                           "same) + eval",
                    "m2l_variant": info["m2l_variant"], "m2l_class_bits": info["m2l_class_bits"]},
+        "rebuilds_keeping_lists": kept,
+        "step_lists_always_rebuilt_ms": 1e3 * t_step_full,
         "eval_only_evals_per_s": n * nb / t_eval,
         "eval_ms": 1e3 * t_eval,
         "passes_ms": pt,

@@ -78,6 +78,10 @@ typedef struct {
   int32_t overlap_near;   /* 1 (default): the near field runs on a plan-owned second stream
                              (default priority) beside P2M..L2L, joined before L2P;
                              0: everything on the caller's stream, near field and L2P fused */
+  int32_t keep_lists;     /* 1 (default): a position update with the same geometry and the same
+                             occupied cells keeps the cell lists, M2L tiles and captured
+                             evaluation (exactly what a full rebuild would produce);
+                             0: every update rebuilds everything */
 } ccfmm_params;
 
 /* One timed M2L configuration of ccfmm_plan_autotune. */
@@ -107,6 +111,9 @@ typedef struct {
   double m2l_flops_per_config;          /* algorithmic: 2 * (N(p)-1)^2 * M2L pairs */
   double p2p_pairs_per_config;
   int32_t m2l_variant;                  /* kernel in use (see ccfmm_params) */
+  int64_t n_rebuilds_kept;              /* position updates that kept the cell lists, M2L tiles and the
+                                           captured evaluation's structure: same geometry and the same
+                                           occupied cells at every level (only the dipoles moved) */
 } ccfmm_info;
 
 /* Per-pass device times (milliseconds) of one evaluation, from HIP events.

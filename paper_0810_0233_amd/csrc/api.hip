@@ -1,5 +1,6 @@
 // api.hip -- the C ABI: plan life cycle, evaluation, info, errors.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -10,10 +11,16 @@ namespace ccfmm {
 
 static thread_local std::string g_last_error;
 
+// device allocations made so far (a captured evaluation stays valid only while
+// none of the buffers it reads is reallocated)
+static std::atomic<uint64_t> g_devbuf_allocs{0};
+uint64_t devbuf_allocs() { return g_devbuf_allocs.load(); }
+
 void* DevBuf::ensure(size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (bytes <= cap) return p;
   release();
+  g_devbuf_allocs.fetch_add(1);
   void* q = nullptr;
   hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess || q == nullptr) {
@@ -306,6 +313,7 @@ static void fill_info(Plan& P, hipStream_t st) {
   I.n_m2l_steps = P.nsteps;
   I.m2l_class_bits = P.class_bits;
   I.m2l_variant = P.m2l_variant;
+  I.n_rebuilds_kept = P.n_rebuilds_kept;
   const double np = (double)nact(P.p);
   I.m2l_flops_per_config = 2.0 * np * np * (double)m2l;
   // direct pairs (self pairs included in the count)
@@ -332,14 +340,26 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
 }
 
 // Build (or rebuild) everything that depends on the positions.
-static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
-  P.drop_graph();
+// With the same geometry and the same occupied cells at every level, the cell
+// lists, the M2L tiles and the derivative tables depend on nothing that
+// moved: a rebuild then redoes the tree (keys, sort, dipole ranges) and the
+// near-field chunks only, and keeps the captured evaluation if no buffer it
+// reads was reallocated and its launch sizes stand.  This is the usual case
+// of a time step in a dense system (dipoles move, cells stay occupied).
+static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_built = false) {
+  // the current lists were built for the fixed (order, theta)
+  const bool prev_fixed = was_built && !P.has_leaf && P.prm.keep_lists != 0;
   P.has_leaf = false;  // per-cell parameters belong to the previous cells
+  const TreeGeom geo0 = P.geo;
+  const int L0 = P.L;
+  const uint64_t allocs0 = devbuf_allocs();
+  const int64_t nch0 = P.nchunks, nch32_0 = P.nchunks32;
   double mn[3], mx[3];
   bool bad = false;
   device_bbox(d_pos, P.n, P.scratch, st, mn, mx, bad);
   if (bad) fail(CCFMM_EINVAL, "non-finite position");
   setup_geometry(P, mn, mx, d_pos, st);
+  const bool same_geo = prev_fixed && P.L == L0 && std::memcmp(&geo0, &P.geo, sizeof(TreeGeom)) == 0;
   const int64_t n = P.n;
   P.key.ensure(sizeof(uint32_t) * n);
   P.val.ensure(sizeof(int32_t) * n);
@@ -354,7 +374,17 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st) {
   P.heap_scan.ensure(sizeof(int32_t) * (nheap + 1));
   P.cmap.ensure(sizeof(int32_t) * nheap);
   while ((int)P.lev.size() < P.L + 1) P.lev.emplace_back(new LevelData());
-  build_tree(P, d_pos, st);
+  bool same_cells = false;
+  build_tree(P, d_pos, st, same_geo ? &same_cells : nullptr);
+  if (same_geo && same_cells) {
+    build_p2p_chunks(P, st);
+    P.n_rebuilds_kept++;
+    fill_info(P, st);
+    if (devbuf_allocs() != allocs0 || P.nchunks != nch0 || P.nchunks32 != nch32_0) P.drop_graph();
+    P.built = true;
+    return;
+  }
+  P.drop_graph();
   build_lists(P, st);
   build_dtensors(P, st);
   build_p2p_chunks(P, st);
@@ -528,6 +558,7 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->selector = 0;
   prm->err_bound = 1e-5;
   prm->overlap_near = 1;
+  prm->keep_lists = 1;
   prm->has_box = 0;
   prm->max_batch = 1;
   prm->m2l_class_bits = 3;
@@ -607,8 +638,8 @@ int ccfmm_plan_update_positions_device(ccfmm_plan plan, const double* d_pos, voi
     if (!d_pos) fail(CCFMM_EINVAL, "positions are NULL");
     Plan& P = plan->P;
     CCFMM_HIP(hipSetDevice(P.device));
-    P.built = false;
-    build_all(P, d_pos, reinterpret_cast<hipStream_t>(stream));
+    P.built = false;  // stays false if the rebuild fails
+    build_all(P, d_pos, reinterpret_cast<hipStream_t>(stream), true);
     return CCFMM_OK;
   });
 }

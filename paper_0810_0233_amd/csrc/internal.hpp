@@ -155,6 +155,7 @@ struct StatusError {
 };
 
 void check_hip(hipError_t e, const char* what);
+uint64_t devbuf_allocs();  // device allocations made so far (DevBuf::ensure)
 #define CCFMM_HIP(x) ::ccfmm::check_hip((x), #x)
 [[noreturn]] void fail(int status, const std::string& msg);
 

@@ -55,6 +55,8 @@ struct Plan {
   // the near field runs on a second stream beside the expansion passes
   // (forked after the moment permutation, joined before L2P)
   bool overlap = true;
+  DevBuf heap_flag_prev;       // occupancy of every heap cell at the previous build
+  int64_t n_rebuilds_kept = 0;  // rebuilds that kept lists and tiles (same geometry and occupied cells)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
@@ -139,7 +141,7 @@ struct Plan {
 // build steps (tree.hip, lists.hip, expansions.hip)
 // occupied smallest cells for every depth 0..24 (G24: the geometry at depth 24)
 void count_occupied_by_depth(Plan& P, const double* d_pos, const TreeGeom& G24, hipStream_t st, int64_t* occupied);
-void build_tree(Plan& P, const double* d_pos, hipStream_t st);
+void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells = nullptr);
 void build_lists(Plan& P, hipStream_t st);
 void build_dtensors(Plan& P, hipStream_t st);
 void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st);

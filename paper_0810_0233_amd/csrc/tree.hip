@@ -505,7 +505,16 @@ __global__ void k_level_starts(const int32_t* scan, int L, int32_t* out) {
   if (l <= L + 1) out[l] = scan[(1ll << l) - 1];
 }
 
-void build_tree(Plan& P, const double* d_pos, hipStream_t st) {
+// 1 into *diff if the occupancy of any heap cell differs from the previous build's
+__global__ void k_flags_differ(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n,
+                               int32_t* diff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && a[i] != b[i]) *diff = 1;  // every writer stores the same value
+}
+
+// same_cells (optional): set to whether every heap cell's occupancy equals the
+// previous build's (read back with the level sizes, no extra wait)
+void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells) {
   const int64_t n = P.n;
   const int L = P.L;
   TreeGeom& G = P.geo;
@@ -530,16 +539,27 @@ void build_tree(Plan& P, const double* d_pos, hipStream_t st) {
   int32_t* scan = P.heap_scan.as<int32_t>();
   k_heap_flags<<<ceil_div(nheap, T), T, 0, st>>>(ls, L, nheap, flag);
   CCFMM_HIP(hipGetLastError());
+  int32_t* g = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * (L + 3)));
+  const bool compare = same_cells && P.heap_flag_prev.cap >= sizeof(int32_t) * (size_t)nheap;
+  if (compare) {
+    k_zero_i32<<<1, 64, 0, st>>>(g + L + 2, 1);
+    k_flags_differ<<<ceil_div(nheap, T), T, 0, st>>>(flag, P.heap_flag_prev.as<int32_t>(), nheap, g + L + 2);
+    CCFMM_HIP(hipGetLastError());
+  }
+  int32_t* prev = reinterpret_cast<int32_t*>(P.heap_flag_prev.ensure(sizeof(int32_t) * nheap));
+  CCFMM_HIP(hipMemcpyAsync(prev, flag, sizeof(int32_t) * nheap, hipMemcpyDeviceToDevice, st));
   scan_exclusive(flag, scan, nheap, P.scratch, st);
-  // level starts: scan[2^l - 1] for l = 0..L+1 (the last is the total)
-  std::vector<int32_t> starts(L + 2);
+  // level starts: scan[2^l - 1] for l = 0..L+1 (the last is the total), then
+  // the occupancy-changed word
+  std::vector<int32_t> starts(L + 3, 1);
   {
-    int32_t* g = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * (L + 2)));
     k_level_starts<<<1, 64, 0, st>>>(scan, L, g);
     CCFMM_HIP(hipGetLastError());
-    CCFMM_HIP(hipMemcpyAsync(starts.data(), g, sizeof(int32_t) * (L + 2), hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipMemcpyAsync(starts.data(), g, sizeof(int32_t) * (compare ? L + 3 : L + 2), hipMemcpyDeviceToHost,
+                             st));
     CCFMM_HIP(hipStreamSynchronize(st));
   }
+  if (same_cells) *same_cells = compare && starts[L + 2] == 0;
   LevelPtrs lp{};
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];

@@ -515,3 +515,64 @@ def test_leaf_sweep_points_match_oracle(ref, order, theta, dl):
     assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
     pl.destroy()
 
+
+@pytest.mark.parametrize("precision", [ccfmm.PREC_FP64, ccfmm.PREC_MIXED])
+def test_rebuild_keeps_lists_when_cells_stay_occupied(precision):
+    """A position update that moves dipoles without emptying or filling any
+    cell (same geometry, same occupied cells at every level) keeps the cell
+    lists, the M2L tiles and the captured evaluation; the replayed evaluation
+    then equals that of a new plan on the new positions.  An update that
+    changes the occupied cells rebuilds everything, with the same result."""
+    import torch
+
+    n = 20000
+    pos0, box = inputs.ferrofluid(n, 51)
+    lo, hi = np.asarray(box[0], float), np.asarray(box[1], float)
+    rng = np.random.default_rng(52)
+    pos1 = np.clip(pos0 + 0.05 * rng.normal(size=pos0.shape), lo + 1e-9, hi - 1e-9)
+    pos2 = pos1.copy()
+    W = hi - lo
+    slab = pos2[:, 0] < lo[0] + 0.25 * W[0]
+    pos2[slab, 0] += 0.5 * W[0]  # the slab x < 1/4 emptied: its cells are no longer occupied
+    m = inputs.random_moments(n, 53)[None]
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    d_m = torch.from_numpy(m).to(dev)
+
+    def fresh(pos):
+        d_pos = torch.from_numpy(pos).to(dev)
+        prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1)
+        pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+        d_H = torch.empty_like(d_m)
+        pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+        torch.cuda.synchronize()
+        pl.destroy()
+        return d_H.cpu().numpy()
+
+    d_pos = torch.from_numpy(pos0.copy()).to(dev)
+    prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1)
+    pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+    d_H = torch.empty_like(d_m)
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)  # captured
+    tol = 1e-13 if precision == ccfmm.PREC_FP64 else 1e-6
+    for k, (pos, kept) in enumerate([(pos1, 1), (pos1, 2), (pos2, 2), (pos0, 2)]):
+        print("case rebuild %d, kept so far %d" % (k, kept), flush=True)
+        d_pos.copy_(torch.from_numpy(pos))
+        pl.update_positions_device(d_pos.data_ptr(), st)
+        assert pl.info()["n_rebuilds_kept"] == kept
+        pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+        torch.cuda.synchronize()
+        assert rel_rms(d_H.cpu().numpy(), fresh(pos)) <= tol
+    pl.destroy()
+    # keep_lists = 0: every update rebuilds everything, with the same field
+    d_pos.copy_(torch.from_numpy(pos0))
+    prm0 = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1, keep_lists=0)
+    p0 = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm0, st)
+    d_pos.copy_(torch.from_numpy(pos1))
+    p0.update_positions_device(d_pos.data_ptr(), st)
+    assert p0.info()["n_rebuilds_kept"] == 0
+    p0.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    assert rel_rms(d_H.cpu().numpy(), fresh(pos1)) <= tol
+    p0.destroy()
+
