@@ -338,14 +338,28 @@ __device__ __forceinline__ int op_index_kperm(int m, int kq, int ks) {
 // Operator layout of the wide kernels: slot e of row block mb holds, for
 // steps 4 k4 .. 4 k4 + 3 of lane l, the float4 at k4 * 256 + 4 l (so a lane
 // reads four steps' fragments at once); the KT steps past the last full
-// group follow as one word per lane each.  Row length padded to a multiple
-// of 1024 words (whole 16-byte loads of four wavefronts).
+// group follow as one word per lane each.
+// Rows past the last full block of 16 (RV of them, when there are at most 8
+// and at least one full block) are not padded to a matrix-core block: they
+// are summed on the vector units, and follow the matrix fragments as four
+// runs of KSTR words, one per lane group kq, each holding T[16 MB + j][kq KS +
+// ks] at ks RV + j (read as broadcast float4s; KSTR is an odd number of
+// float4s so the four groups sit in different banks).
+// Row length padded to a multiple of 256 words (whole 16-byte loads of one
+// wavefront).
 template <int P>
 struct WideOp {
-  static constexpr int NP = nact(P), NS = nstride(P), KS = NS / 4, MB = (NP + 15) / 16, ND = ncoef(2 * P);
+  static constexpr int NP = nact(P), NS = nstride(P), KS = NS / 4, ND = ncoef(2 * P);
+  static constexpr int MF = NP / 16, RF = NP % 16;
+  static constexpr bool VROWS = MF >= 1 && RF > 0 && RF <= 8;
+  static constexpr int MB = VROWS ? MF : (NP + 15) / 16;  // matrix-core row blocks
+  static constexpr int RV = VROWS ? RF : 0;               // rows on the vector units
   static constexpr int K4 = KS / 4, KT = KS % 4;
-  static constexpr int NE = MB * KS * 64;                 // operator entries
-  static constexpr int NEP = (NE + 1023) / 1024 * 1024;  // padded row length
+  static constexpr int KSTR0 = (RV * KS + 3) / 4 * 4;
+  static constexpr int KSTR = (KSTR0 / 4) % 2 == 0 && RV > 0 ? KSTR0 + 4 : KSTR0;
+  static constexpr int NEM = MB * KS * 64;               // matrix-core operator entries
+  static constexpr int NE = NEM + 4 * KSTR;              // all operator entries
+  static constexpr int NEP = (NE + 255) / 256 * 256;     // padded row length
 };
 
 // derivative-tensor index of slot e (ND, the row's trailing zero, for padding)
@@ -353,6 +367,11 @@ template <int P>
 __device__ __forceinline__ int wide_slot_dindex(int e) {
   using W = WideOp<P>;
   if (e >= W::NE) return W::ND;
+  if (e >= W::NEM) {
+    const int kq = (e - W::NEM) / W::KSTR, r = (e - W::NEM) % W::KSTR;
+    if (r >= W::RV * W::KS) return W::ND;
+    return op_index_kperm<P>(16 * W::MB + r % W::RV, kq, r / W::RV);
+  }
   const int mb = e / (W::KS * 64), r0 = e % (W::KS * 64);
   int ks, l;
   if (r0 < W::K4 * 256) {
@@ -407,7 +426,7 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
                                                    const float* __restrict__ Dop, const float* __restrict__ Q,
                                                    float* __restrict__ V, LevelOffsets lo, int nb, int TB, int TC) {
   using W = WideOp<P>;
-  constexpr int NS = W::NS, KS = W::KS, MB = W::MB, NP = W::NP;
+  constexpr int NS = W::NS, KS = W::KS, MB = W::MB, NP = W::NP, RV = W::RV;
   constexpr int K4 = W::K4, KT = W::KT;  // full groups of 4 steps, steps left over
   constexpr int NEP = W::NEP;             // operator words per step (padded)
   __shared__ __attribute__((aligned(16))) float sT[2][NEP];
@@ -456,10 +475,11 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   auto load_op = [&](int s, int buf) {
     const float* orow = Dop + (int64_t)step_delta[tl.step0 + s] * NEP;
 #pragma unroll
-    for (int r = 0; r < NEP / 1024; r++) {
+    for (int r = 0; r < (NEP + 1023) / 1024; r++) {
       const int o = 1024 * r + 256 * w;
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(orow + o + 4 * lane),
-                                       (__attribute__((address_space(3))) void*)&sT[buf][o], 16, 0, 0);
+      if (NEP % 1024 == 0 || o < NEP)  // uniform over the wavefront
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(orow + o + 4 * lane),
+                                         (__attribute__((address_space(3))) void*)&sT[buf][o], 16, 0, 0);
     }
   };
   // all of this wavefront's memory loads have landed (vmcnt = 0)
@@ -470,6 +490,12 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   for (int mb = 0; mb < MB; mb++)
 #pragma unroll
     for (int cb = 0; cb < CB; cb++) acc[mb][cb] = f32x4{0, 0, 0, 0};
+  // vector-unit rows: this lane's partial sums over its lane group's k range
+  float pv[CB][RV > 0 ? RV : 1];
+#pragma unroll
+  for (int cb = 0; cb < CB; cb++)
+#pragma unroll
+    for (int j = 0; j < (RV > 0 ? RV : 1); j++) pv[cb][j] = 0.f;
 
   float B0[CB][KS], B1[CB][KS];
   int srcA[CB], srcB[CB];
@@ -513,6 +539,21 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
         for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(a, Bc[cb][4 * K4 + t], acc[mb][cb]);
       }
     }
+    if constexpr (RV > 0) {
+      const float* Tv = T0 + W::NEM + kq * W::KSTR;
+#pragma unroll
+      for (int i = 0; i < W::KSTR / 4; i++) {
+        const f32x4 tv = *reinterpret_cast<const f32x4*>(Tv + 4 * i);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int r = 4 * i + u;
+          if (r < RV * KS) {
+#pragma unroll
+            for (int cb = 0; cb < CB; cb++) pv[cb][r % RV] = fmaf(tv[u], Bc[cb][r / RV], pv[cb][r % RV]);
+          }
+        }
+      }
+    }
     __builtin_amdgcn_sched_barrier(0);
     wait_loads();  // next operator in LDS, next B in registers
     __syncthreads();
@@ -541,6 +582,40 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
             v = (deg & 1) ? -acc[mb][cb][r] : acc[mb][cb][r];
           }
           out[m] = v;
+        }
+      }
+    }
+  }
+  if constexpr (RV > 0) {
+    // vector-unit rows: sum the four lane groups' partial sums; lane group kq
+    // writes rows 16 MB + kq, + 4, ... (the stride's padding rows as zeros)
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) {
+#pragma unroll
+      for (int j = 0; j < RV; j++) {
+        pv[cb][j] += __shfl_xor(pv[cb][j], 16);
+        pv[cb][j] += __shfl_xor(pv[cb][j], 32);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; cb++) {
+      if (ctc[cb] < 0) continue;
+      const int tgt = tile_tgt[tl.tgt0 + ctc[cb]];
+      if (tgt < 0) continue;
+      float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NS;
+#pragma unroll
+      for (int j0 = 0; j0 < NS - 16 * MB; j0 += 4) {
+        const int j = j0 + kq;
+        if (j < NS - 16 * MB) {
+          float v = 0.f;
+#pragma unroll
+          for (int jj = 0; jj < RV; jj++)
+            if (jj == j) {
+              const int f = 16 * MB + jj + 1;
+              const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
+              v = (deg & 1) ? -pv[cb][jj] : pv[cb][jj];
+            }
+          out[16 * MB + j] = v;
         }
       }
     }
