@@ -325,3 +325,125 @@ def test_selector_clusters_full_scale(ref):
     assert err_learned <= 1e-5
     assert cost(li) < cost(fi)
     pl.destroy()
+
+
+def brute_leaf_lists(cc, axes, h_leaf, theta):
+    """Near and far cells of every occupied smallest cell, from the definition:
+    a cell's candidates are the occupied children of its parent's near cells
+    (the root is near itself); a candidate A is near c unless
+    fl(theta^2) * sum_a (delta_a h_a)^2 >= sum_a h_a^2 at that level, else far.
+    cc: integer smallest-cell coordinates per dipole; axes: split axis of
+    levels 1..L; h_leaf: smallest-cell sides (every level's sides are
+    h_leaf times powers of two, so these sums are exact in FP64)."""
+    L = len(axes)
+    kL = np.bincount(np.asarray(axes, dtype=np.int64), minlength=3)
+    th2 = theta * theta
+    near = {(0, 0, 0): [(0, 0, 0)]}
+    far = {}
+    k = np.zeros(3, dtype=np.int64)
+    for lev in range(1, L + 1):
+        k[axes[lev - 1]] += 1
+        h = np.asarray(h_leaf) * (2.0 ** (kL - k))
+        occ = {tuple(r) for r in np.unique(cc >> (kL - k), axis=0)}
+        children = {}
+        for c in occ:
+            par = list(c)
+            par[axes[lev - 1]] >>= 1
+            children.setdefault(tuple(par), []).append(c)
+        R = float(np.sum(h * h))
+        nxt, fr = {}, {}
+        for c in occ:
+            par = list(c)
+            par[axes[lev - 1]] >>= 1
+            nr, fa = [], []
+            for A in near[tuple(par)]:
+                for ch in children.get(A, []):
+                    d = (np.asarray(ch) - np.asarray(c)) * h
+                    (fa if th2 * float(np.sum(d * d)) >= R else nr).append(ch)
+            nxt[c], fr[c] = nr, fa
+        near, far = nxt, fr
+    return near, far
+
+
+def test_leaf_features_match_definition():
+    """The selector's eight features per smallest cell over a batch of three
+    configurations, against the same quantities computed here from the
+    bisection rule and the near/far definition (FP32 features, 1e-6)."""
+    torch = torch_mod()
+    pos, box, m0 = cluster_case(731, ncl=12, per=500)
+    n = pos.shape[0]
+    nb = 3
+    m = np.stack([m0, inputs.random_moments(n, 732), inputs.aligned_moments(n, 2, 733)[1]])  # half aligned along +z
+    theta = 0.5
+    prm = ccfmm.params(order=6, theta=theta, box=box, precision=ccfmm.PREC_MIXED, max_batch=nb)
+    pl = ccfmm.Plan.create(pos, prm)
+    inf = pl.info()
+    nl, L = inf["n_leaves"], inf["levels"]
+    dm = dev_t(m)
+    dF = torch.empty((nl, ccfmm.MLP_IN), dtype=torch.float32, device="cuda:0")
+    pl.leaf_features(nb, dm.data_ptr(), dF.data_ptr(), stream())
+    ids = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    pl.leaf_ids(ids.data_ptr(), stream())
+    torch.cuda.synchronize()
+    F, ids = dF.cpu().numpy().astype(np.float64), ids.cpu().numpy()
+    axes = inf["split_axis"]
+    kL = np.bincount(np.asarray(axes, dtype=np.int64), minlength=3)
+    lo, hi = np.asarray(inf["box_lo"]), np.asarray(inf["box_hi"])
+    W = hi - lo
+    cc = np.floor((pos - lo) * (2.0 ** kL) / W).astype(np.int64)
+    cc = np.minimum(np.maximum(cc, 0), (1 << kL) - 1)
+    near, far = brute_leaf_lists(cc, axes, W / 2.0 ** kL, theta)
+    assert len(near) == nl
+    key = {}
+    for i in range(n):
+        key.setdefault(tuple(cc[i]), set()).add(int(ids[i]))
+    assert all(len(s) == 1 for s in key.values())
+    count = {c: 0 for c in near}
+    for c in map(tuple, cc):
+        count[c] += 1
+    print("case clusters n=%d nb=%d L=%d cells=%d" % (n, nb, L, nl), flush=True)
+    for c, nr in near.items():
+        leaf = next(iter(key[c]))
+        sel = np.all(cc == np.asarray(c), axis=1)
+        mc = m[:, sel, :].reshape(-1, 3)
+        mean = mc.mean(axis=0)
+        mm = float(np.sqrt(np.sum(mean * mean)))
+        var = float(np.mean(np.sum(mc * mc, axis=1))) - mm * mm
+        nsrc = sum(count[a] for a in nr)
+        want = np.array([np.log2(1.0 + count[c]), np.log2(1.0 + nsrc), len(nr) / 64.0, len(far[c]) / 64.0, mm, var,
+                         np.log2(1.0 + count[c]) - np.log2(1.0 + nsrc / len(nr)), L / 16.0])
+        assert np.allclose(F[leaf], want, rtol=1e-6, atol=1e-6), (c, F[leaf], want)
+    pl.destroy()
+
+
+def test_batched_select_judges_every_configuration():
+    """Learned selection over a batch of three configurations: the features
+    pool the batch, one choice serves all three, and the judge's error is the
+    relative RMS of the learned against the fixed field over the whole batch
+    (checked here from separate evaluations of both)."""
+    pos, box, m0 = cluster_case(741, ncl=8, per=400)
+    n = pos.shape[0]
+    nb = 3
+    m = np.stack([m0, inputs.random_moments(n, 742), inputs.random_moments(n, 743)])
+    prm = ccfmm.params(order=6, theta=0.4, box=box, precision=ccfmm.PREC_FP64, max_batch=nb)
+    pl = ccfmm.Plan.create(pos, prm)
+    H_fixed = pl.eval(m)
+    dm = dev_t(m)
+    # a loose bound with no far cost: every cell takes the widest angle
+    dP = dev_t(constant_net(-20.0))
+    rc, si = pl.select(dP.data_ptr(), 1e-2, 0.0, 0.0, nb, dm.data_ptr(), judge=True, stream=stream())
+    assert rc == ccfmm.OK and si["fallback"] == 0
+    p, th = pl.get_leaf_params()
+    assert np.all(th == 0.7)
+    H_learned = pl.eval(m)
+    want = rel_rms(H_learned, H_fixed)
+    print("batched judge %.6e, separate %.6e" % (si["judge_err"], want), flush=True)
+    assert want > 0 and abs(si["judge_err"] - want) <= 1e-9 * want
+    # the same choice applied one configuration at a time gives the same fields
+    for b in range(nb):
+        assert rel_rms(pl.eval(m[b]), H_learned[b]) <= 1e-13
+    # a bound below the batch's error rejects, restoring the fixed fields bit for bit
+    rc, si = pl.select(dP.data_ptr(), 0.5 * want, 0.0, 0.0, nb, dm.data_ptr(), judge=True, stream=stream())
+    assert rc == ccfmm.W_FALLBACK and si["fallback"] == 1
+    assert np.array_equal(pl.eval(m), H_fixed)
+    pl.destroy()
