@@ -152,7 +152,10 @@ int ccfmm_plan_update_positions_device(ccfmm_plan plan, const double* d_pos, voi
  * L2L Eq.(taylorshift), L2P Eq.(H) and the near-field sum Eq.(H2). */
 int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H);
 int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream);
-/* As ccfmm_eval_device, with HIP events between the passes (synchronises). */
+/* As ccfmm_eval_device, with HIP events between the passes (synchronises).
+ * The passes run one after another on the caller's stream whatever the
+ * plan's overlap_near, so each time is that pass alone; below the batched
+ * size the near field and L2P are one fused kernel (timed as p2p, l2p 0). */
 int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H,
                             void* stream, ccfmm_pass_times* times);
 

@@ -667,7 +667,17 @@ int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, 
     prepare_batch(P, nbatch, st);
     hipEvent_t ev[9];
     for (int i = 0; i < 9; i++) CCFMM_HIP(hipEventCreate(&ev[i]));
-    eval_passes(P, nbatch, d_m, d_H, st, ev);
+    // every pass alone on the caller's stream (the near field fused with L2P
+    // below the batched size), so each time is that pass's own cost
+    const bool overlap = P.overlap;
+    P.overlap = false;
+    try {
+      eval_passes(P, nbatch, d_m, d_H, st, ev);
+    } catch (...) {
+      P.overlap = overlap;
+      throw;
+    }
+    P.overlap = overlap;
     CCFMM_HIP(hipEventSynchronize(ev[5]));
     CCFMM_HIP(hipEventSynchronize(ev[7]));
     float ms[4], near, l2p, tot;

@@ -233,6 +233,16 @@ def config_film(nx=1024, ny=1024, nz=16, nholes=16, hole_seed=5001, mom_seed_bas
                 m=m, order=6, theta=0.4, leaf_target=0.0)
 
 
+def config_film_training(seed, nx=1024, ny=1024, nz=16, nholes=16):
+    """Training geometry for the learned selector on films: the film recipe at
+    full size with other seeds (holes from `seed`, moments from seed + 1), so
+    its tree has the same depth and smallest-cell shape (2 x 4 x 4 sites) as
+    the film it serves; it is labelled on a sample of its cells."""
+    pos, box = film_with_holes(nx, ny, nz, nholes, seed)
+    m = random_moments(pos.shape[0], seed + 1)
+    return dict(name="film_train_%d" % seed, pos=pos, box=box, m=m[None], order=6, theta=0.4, leaf_target=0.0)
+
+
 def config_clusters_training(seed, nclusters=32, per_cluster=8192, box_side=256.0):
     """Training geometry for the learned selector: the cluster recipe on a box
     of half the side with 1/8 of the clusters.  The smallest cells then have

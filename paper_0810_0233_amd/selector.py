@@ -51,8 +51,14 @@ def direct_field(pos, m, dev):
     return d_H
 
 
-def cell_labels(pos, box, m, order=6, theta=0.4, precision=ccfmm.PREC_MIXED, dev="cuda:0", H_direct=None):
-    """Features [cells][8] and labels/mask [cells][25] of one geometry."""
+def cell_labels(pos, box, m, order=6, theta=0.4, precision=ccfmm.PREC_MIXED, dev="cuda:0", H_direct=None,
+                sample_cells=0, seed=0):
+    """Features [cells][8] and labels/mask [cells][25] of one geometry.
+
+    sample_cells > 0 labels only that many smallest cells (seeded choice): the
+    direct sum is then taken at their dipoles only, so geometries of the size
+    (and tree depth) the selector will serve can be labelled.  The rows
+    returned are those cells'."""
     torch = _torch()
     dev = torch.device(dev)
     st = torch.cuda.current_stream().cuda_stream
@@ -63,27 +69,47 @@ def cell_labels(pos, box, m, order=6, theta=0.4, precision=ccfmm.PREC_MIXED, dev
     d_m = torch.from_numpy(np.ascontiguousarray(m)).to(dev)
     d_feat = torch.empty((nl, ccfmm.MLP_IN), dtype=torch.float32, device=dev)
     plan.leaf_features(1, d_m.data_ptr(), d_feat.data_ptr(), st)
-    d_ref = H_direct if H_direct is not None else direct_field(pos, m, dev)
+    d_idx = None
+    if sample_cells and sample_cells < nl:
+        cells = np.sort(np.random.default_rng(seed).choice(nl, sample_cells, replace=False))
+        ids = torch.empty(n, dtype=torch.int32, device=dev)
+        plan.leaf_ids(ids.data_ptr(), st)
+        torch.cuda.synchronize()
+        idx = np.nonzero(np.isin(ids.cpu().numpy(), cells))[0].astype(np.int64)
+        d_idx = torch.from_numpy(idx).to(dev)
+        d_pos = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+        d_Hd = torch.empty((idx.size, 3), dtype=torch.float64, device=dev)
+        ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m.data_ptr(), idx.size, d_idx.data_ptr(),
+                                    d_Hd.data_ptr(), st)
+        d_ref = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    else:
+        cells = np.arange(nl)
+        d_ref = H_direct if H_direct is not None else direct_field(pos, m, dev)
     d_H = torch.empty((n, 3), dtype=torch.float64, device=dev)
     num = torch.empty(nl, dtype=torch.float64, device=dev)
     den = torch.empty(nl, dtype=torch.float64, device=dev)
-    labels = np.zeros((nl, ccfmm.MLP_OUT), dtype=np.float32)
-    mask = np.zeros((nl, ccfmm.MLP_OUT), dtype=np.float32)
+    labels = np.zeros((cells.size, ccfmm.MLP_OUT), dtype=np.float32)
+    mask = np.zeros((cells.size, ccfmm.MLP_OUT), dtype=np.float32)
     for pi, p in enumerate(SEL_P):
         for ti, th in enumerate(SEL_THETA):
             d_p = torch.full((nl,), min(p, order), dtype=torch.int32, device=dev)
             d_t = torch.full((nl,), th, dtype=torch.float64, device=dev)
             plan.set_leaf_params(d_p.data_ptr(), d_t.data_ptr(), st)
             plan.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+            if d_idx is not None:
+                # reference: the direct sum at the sampled cells' dipoles (the
+                # other cells' rows are not used)
+                d_ref.copy_(d_H)
+                d_ref[d_idx] = d_Hd
             plan.leaf_errors(1, d_H.data_ptr(), d_ref.data_ptr(), num.data_ptr(), den.data_ptr(), st)
             torch.cuda.synchronize()
-            nn_, dd = num.cpu().numpy(), den.cpu().numpy()
+            nn_, dd = num.cpu().numpy()[cells], den.cpu().numpy()[cells]
             ok = (dd > 0) & (nn_ > 0)
             col = pi * len(SEL_THETA) + ti
             labels[ok, col] = np.log10(np.sqrt(nn_[ok] / dd[ok]))
             mask[ok, col] = 1.0
     plan.destroy()
-    return d_feat.cpu().numpy(), labels, mask
+    return d_feat.cpu().numpy()[cells], labels, mask
 
 
 def train(features, labels, mask, steps=400, lr=3e-3, seed=0, dev="cuda:0", log_every=0):
@@ -110,11 +136,12 @@ def train(features, labels, mask, steps=400, lr=3e-3, seed=0, dev="cuda:0", log_
     return P.cpu().numpy(), losses
 
 
-def cost_ratio(plan, d_m, d_H, stream, repeats=3):
+def cost_ratio(plan, d_m, d_H, stream, repeats=3, nbatch=1):
     """Cost of one M2L pair relative to one near-field dipole pair, from the
-    plan's own timed passes (median of a few evaluations)."""
+    plan's own timed passes over nbatch configurations (median of a few
+    evaluations)."""
     inf = plan.info()
-    t = [plan.eval_device_timed(1, d_m, d_H, stream) for _ in range(repeats)]
+    t = [plan.eval_device_timed(nbatch, d_m, d_H, stream) for _ in range(repeats)]
     m2l = float(np.median([x["m2l"] for x in t]))
     p2p = float(np.median([x["p2p"] for x in t]))
     per_m2l = m2l / max(1, inf["n_m2l_pairs"])
@@ -122,12 +149,14 @@ def cost_ratio(plan, d_m, d_H, stream, repeats=3):
     return per_m2l / per_p2p
 
 
-def train_on(configs, order=6, theta=0.4, steps=600, lr=3e-3, seed=1, dev="cuda:0", log_every=0):
+def train_on(configs, order=6, theta=0.4, steps=600, lr=3e-3, seed=1, dev="cuda:0", log_every=0, sample_cells=0):
     """Labels from every training configuration (each a dict with pos, box and
-    m[0]), then training; returns (params, losses, number of cells)."""
+    m[0]; all cells, or sample_cells of each), then training; returns (params,
+    losses, number of cells)."""
     feats, labs, masks = [], [], []
-    for c in configs:
-        f, y, k = cell_labels(c["pos"], c["box"], c["m"][0], order=order, theta=theta, dev=dev)
+    for i, c in enumerate(configs):
+        f, y, k = cell_labels(c["pos"], c["box"], c["m"][0], order=order, theta=theta, dev=dev,
+                              sample_cells=sample_cells, seed=seed + i)
         feats.append(f)
         labs.append(y)
         masks.append(k)

@@ -418,8 +418,15 @@ def test_overlapped_near_field_equals_single_stream(nb):
             pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
             torch.cuda.synchronize()
             res.append(d_H.cpu().numpy().copy())
+        # the timed evaluation runs every pass alone on one stream, with the same field
         t = pl.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), st)
+        torch.cuda.synchronize()
         assert t["p2p"] > 0 and t["total"] > 0
+        assert rel_rms(d_H.cpu().numpy(), res[0]) <= 1e-12
+        # and leaves the plan's own (overlapped, graph-replayed) evaluation as it was
+        pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
+        torch.cuda.synchronize()
+        res.append(d_H.cpu().numpy().copy())
         assert all(np.array_equal(r, res[0]) for r in res[1:])
         out[ov] = res[0]
         pl.destroy()
