@@ -142,7 +142,13 @@ int ccfmm_plan_create(ccfmm_plan* out, int32_t device, int64_t n, const double* 
 int ccfmm_plan_create_device(ccfmm_plan* out, int64_t n, const double* d_pos,
                              const ccfmm_params* prm, void* stream);
 /* Rebuild tree, lists and tensors in place for new device positions of the
- * same count (moving dipoles); buffers are reused when large enough. */
+ * same count (moving dipoles); buffers are reused when large enough.  With
+ * keep_lists, an update that leaves the geometry and the occupied cells as
+ * they were keeps the lists, tiles and captured evaluation.  With a caller
+ * box, the positions are checked against it on the device (CCFMM_EINVAL for a
+ * non-finite coordinate or a dipole outside).  After a failed update the plan
+ * evaluates nothing (CCFMM_ESTATE) until an update succeeds, which then
+ * rebuilds everything. */
 int ccfmm_plan_update_positions_device(ccfmm_plan plan, const double* d_pos, void* stream);
 
 /* Evaluate H for nbatch configurations (1 <= nbatch <= max_batch).

@@ -110,6 +110,21 @@ static void device_bbox(const double* d_pos, int64_t n, DevBuf& tmp, hipStream_t
   bad = hb != 0;
 }
 
+// Positions against the caller's box, on the device: [0] = 1 if a coordinate
+// is not finite, [1] = 1 if one lies outside [lo, hi] (every writer stores the
+// same value)
+struct BoxBounds {
+  double lo[3], hi[3];
+};
+__global__ void k_check_in_box(const double* __restrict__ pos, int64_t n, BoxBounds b, int32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  const int a = (int)(i % 3);
+  const double v = pos[i];
+  if (!isfinite(v)) bad[0] = 1;
+  else if (v < b.lo[a] || v > b.hi[a]) bad[1] = 1;
+}
+
 static double s_opt(int p) { return p > 3 ? 0.74 * (double)p * (double)p : 8.0; }
 
 // Root box, level count and split sequence.  Root: the caller's box, else the
@@ -244,7 +259,18 @@ __global__ void k_info_gather(InfoSources src, int cidx, int32_t* out) {
   if (i == 0) out[cidx] = out[cidx + 1] = 0;
 }
 
-static void fill_info(Plan& P, hipStream_t st) {
+// direct-pair count of the current cells and lists into *dcnt (cleared by the caller)
+static void launch_pair_count(Plan& P, unsigned long long* dcnt, hipStream_t st) {
+  LevelData& D = *P.lev[P.L];
+  const int nblk = (int)std::min<int64_t>(kPairCountBlocks, std::max<int64_t>(1, ceil_div(D.ncells, 4)));
+  k_count_p2p_pairs<<<nblk, 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(), D.near_idx.as<int32_t>(),
+                                          P.lcount.as<int32_t>(), dcnt);
+  CCFMM_HIP(hipGetLastError());
+}
+
+// count_pairs = false (an update that kept the lists) leaves the direct-pair
+// count, a statistic only, to the next ccfmm_plan_info
+static void fill_info(Plan& P, hipStream_t st, bool count_pairs = true) {
   // list totals, chunk counts, error flags and the direct-pair count come
   // back in one copy and one synchronisation
   const int L = P.L;
@@ -264,14 +290,8 @@ static void fill_info(Plan& P, hipStream_t st) {
   int32_t* dbuf = reinterpret_cast<int32_t*>(P.scratch2.ensure(sizeof(int32_t) * (nw + 2)));
   k_info_gather<<<1, 64, 0, st>>>(src, cidx, dbuf);
   CCFMM_HIP(hipGetLastError());
-  {
-    LevelData& D = *P.lev[L];
-    unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(dbuf + cidx);
-    const int nblk = (int)std::min<int64_t>(kPairCountBlocks, std::max<int64_t>(1, ceil_div(D.ncells, 4)));
-    k_count_p2p_pairs<<<nblk, 256, 0, st>>>(D.ncells, D.near_ptr.as<int32_t>(),
-                                                               D.near_idx.as<int32_t>(), P.lcount.as<int32_t>(), dcnt);
-    CCFMM_HIP(hipGetLastError());
-  }
+  if (count_pairs) launch_pair_count(P, reinterpret_cast<unsigned long long*>(dbuf + cidx), st);
+  P.pairs_stale = !count_pairs;
   std::vector<int32_t> tot(nw, 0);
   CCFMM_HIP(hipMemcpyAsync(tot.data(), dbuf, sizeof(int32_t) * nw, hipMemcpyDeviceToHost, st));
   CCFMM_HIP(hipStreamSynchronize(st));
@@ -355,9 +375,27 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
   const uint64_t allocs0 = devbuf_allocs();
   const int64_t nch0 = P.nchunks, nch32_0 = P.nchunks32;
   double mn[3], mx[3];
-  bool bad = false;
-  device_bbox(d_pos, P.n, P.scratch, st, mn, mx, bad);
-  if (bad) fail(CCFMM_EINVAL, "non-finite position");
+  // With the caller's box and the paper's level rule the bounds are only a
+  // check: it runs on the device and comes back with the level sizes (the
+  // tree kernels clamp any coordinate into the box, so nothing they index
+  // depends on it), saving a wait.  Otherwise the bounds set the root cell.
+  const bool check_later = P.prm.has_box && P.prm.leaf_rule == 0;
+  int32_t check[2] = {0, 0};
+  if (check_later) {
+    int32_t* dchk = reinterpret_cast<int32_t*>(P.pos_check.ensure(sizeof(int32_t) * 2));
+    CCFMM_HIP(hipMemsetAsync(dchk, 0, sizeof(int32_t) * 2, st));  // not captured: an update runs eagerly
+    BoxBounds bb;
+    for (int a = 0; a < 3; a++) {
+      bb.lo[a] = mn[a] = P.prm.box_lo[a];
+      bb.hi[a] = mx[a] = P.prm.box_hi[a];
+    }
+    k_check_in_box<<<ceil_div(3 * P.n, 256), 256, 0, st>>>(d_pos, P.n, bb, dchk);
+    CCFMM_HIP(hipGetLastError());
+  } else {
+    bool bad = false;
+    device_bbox(d_pos, P.n, P.scratch, st, mn, mx, bad);
+    if (bad) fail(CCFMM_EINVAL, "non-finite position");
+  }
   setup_geometry(P, mn, mx, d_pos, st);
   const bool same_geo = prev_fixed && P.L == L0 && std::memcmp(&geo0, &P.geo, sizeof(TreeGeom)) == 0;
   const int64_t n = P.n;
@@ -375,13 +413,16 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
   P.cmap.ensure(sizeof(int32_t) * nheap);
   while ((int)P.lev.size() < P.L + 1) P.lev.emplace_back(new LevelData());
   bool same_cells = false;
-  build_tree(P, d_pos, st, same_geo ? &same_cells : nullptr);
+  build_tree(P, d_pos, st, same_geo ? &same_cells : nullptr, check_later ? P.pos_check.as<int32_t>() : nullptr,
+             check);
+  if (check[0]) fail(CCFMM_EINVAL, "non-finite position");
+  if (check[1]) fail(CCFMM_EINVAL, "a dipole lies outside the box");
   if (same_geo && same_cells) {
     build_p2p_chunks(P, st);
     P.n_rebuilds_kept++;
-    fill_info(P, st);
+    fill_info(P, st, false);
     if (devbuf_allocs() != allocs0 || P.nchunks != nch0 || P.nchunks32 != nch32_0) P.drop_graph();
-    P.built = true;
+    P.built = P.ever_built = true;
     return;
   }
   P.drop_graph();
@@ -391,7 +432,7 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
   build_m2l_tiles(P, P.nbmax, st);
   P.qv_batch = 0;
   fill_info(P, st);
-  P.built = true;
+  P.built = P.ever_built = true;
 }
 
 static void prepare_batch(Plan& P, int nb, hipStream_t st) {
@@ -634,12 +675,14 @@ int ccfmm_plan_create_device(ccfmm_plan* out, int64_t n, const double* d_pos, co
 
 int ccfmm_plan_update_positions_device(ccfmm_plan plan, const double* d_pos, void* stream) {
   return guarded([&] {
-    if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
+    if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_pos) fail(CCFMM_EINVAL, "positions are NULL");
     Plan& P = plan->P;
     CCFMM_HIP(hipSetDevice(P.device));
+    // after a failed update only a full rebuild is trusted
+    const bool was_built = P.built;
     P.built = false;  // stays false if the rebuild fails
-    build_all(P, d_pos, reinterpret_cast<hipStream_t>(stream), true);
+    build_all(P, d_pos, reinterpret_cast<hipStream_t>(stream), was_built);
     return CCFMM_OK;
   });
 }
@@ -787,7 +830,22 @@ int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out) {
   return guarded([&] {
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!out) fail(CCFMM_EINVAL, "out is NULL");
-    *out = plan->P.info;
+    Plan& P = plan->P;
+    if (P.pairs_stale) {
+      // the direct-pair count after an update that kept the lists: taken now,
+      // once every stream's work on the plan has finished
+      CCFMM_HIP(hipSetDevice(P.device));
+      CCFMM_HIP(hipDeviceSynchronize());
+      unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(P.scratch2.ensure(64));
+      CCFMM_HIP(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long), nullptr));
+      launch_pair_count(P, dcnt, nullptr);
+      unsigned long long npairs = 0;
+      CCFMM_HIP(hipMemcpy(&npairs, dcnt, sizeof(npairs), hipMemcpyDeviceToHost));
+      P.info.n_p2p_pairs = (int64_t)npairs;
+      P.info.p2p_pairs_per_config = (double)npairs;
+      P.pairs_stale = false;
+    }
+    *out = P.info;
     return CCFMM_OK;
   });
 }

@@ -56,6 +56,9 @@ struct Plan {
   // (forked after the moment permutation, joined before L2P)
   bool overlap = true;
   DevBuf heap_flag_prev;       // occupancy of every heap cell at the previous build
+  DevBuf pos_check;            // [0] a position is not finite, [1] one lies outside the caller's box
+  bool pairs_stale = false;    // info's direct-pair count not yet taken for the current cells
+  bool ever_built = false;     // a build succeeded once (buffers and parameters in place)
   int64_t n_rebuilds_kept = 0;  // rebuilds that kept lists and tiles (same geometry and occupied cells)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -141,7 +144,8 @@ struct Plan {
 // build steps (tree.hip, lists.hip, expansions.hip)
 // occupied smallest cells for every depth 0..24 (G24: the geometry at depth 24)
 void count_occupied_by_depth(Plan& P, const double* d_pos, const TreeGeom& G24, hipStream_t st, int64_t* occupied);
-void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells = nullptr);
+void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells = nullptr,
+                const int32_t* d_check = nullptr, int32_t* h_check = nullptr);
 void build_lists(Plan& P, hipStream_t st);
 void build_dtensors(Plan& P, hipStream_t st);
 void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st);

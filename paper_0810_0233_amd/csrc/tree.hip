@@ -309,7 +309,7 @@ __device__ __forceinline__ int32_t leaf_coord(double x, double lo, double W, int
   double u = t / W;
   double f = floor(u);
   int32_t top = (1 << k) - 1;
-  if (f < 0.0) return 0;
+  if (!(f >= 0.0)) return 0;  // below the box, or not a number
   if (f > (double)top) return top;
   return (int32_t)f;
 }
@@ -513,8 +513,10 @@ __global__ void k_flags_differ(const int32_t* __restrict__ a, const int32_t* __r
 }
 
 // same_cells (optional): set to whether every heap cell's occupancy equals the
-// previous build's (read back with the level sizes, no extra wait)
-void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells) {
+// previous build's (read back with the level sizes, no extra wait).
+// d_check (optional): two device words copied to h_check in the same wait.
+void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells, const int32_t* d_check,
+                int32_t* h_check) {
   const int64_t n = P.n;
   const int L = P.L;
   TreeGeom& G = P.geo;
@@ -557,6 +559,7 @@ void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells) 
     CCFMM_HIP(hipGetLastError());
     CCFMM_HIP(hipMemcpyAsync(starts.data(), g, sizeof(int32_t) * (compare ? L + 3 : L + 2), hipMemcpyDeviceToHost,
                              st));
+    if (d_check) CCFMM_HIP(hipMemcpyAsync(h_check, d_check, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st));
     CCFMM_HIP(hipStreamSynchronize(st));
   }
   if (same_cells) *same_cells = compare && starts[L + 2] == 0;

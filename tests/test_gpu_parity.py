@@ -546,15 +546,16 @@ def test_rebuild_keeps_lists_when_cells_stay_occupied(precision):
     st = torch.cuda.current_stream().cuda_stream
     d_m = torch.from_numpy(m).to(dev)
 
-    def fresh(pos):
+    def fresh(pos, with_info=False):
         d_pos = torch.from_numpy(pos).to(dev)
         prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1)
         pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
         d_H = torch.empty_like(d_m)
         pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
         torch.cuda.synchronize()
+        inf = pl.info()
         pl.destroy()
-        return d_H.cpu().numpy()
+        return (d_H.cpu().numpy(), inf) if with_info else d_H.cpu().numpy()
 
     d_pos = torch.from_numpy(pos0.copy()).to(dev)
     prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1)
@@ -566,10 +567,14 @@ def test_rebuild_keeps_lists_when_cells_stay_occupied(precision):
         print("case rebuild %d, kept so far %d" % (k, kept), flush=True)
         d_pos.copy_(torch.from_numpy(pos))
         pl.update_positions_device(d_pos.data_ptr(), st)
-        assert pl.info()["n_rebuilds_kept"] == kept
         pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
         torch.cuda.synchronize()
-        assert rel_rms(d_H.cpu().numpy(), fresh(pos)) <= tol
+        H_new, inf_new = fresh(pos, with_info=True)
+        inf = pl.info()  # the direct-pair count of a kept update is taken here
+        assert inf["n_rebuilds_kept"] == kept
+        for key in ("n_leaves", "n_cells", "n_m2l_pairs", "n_p2p_leaf_pairs", "n_p2p_pairs"):
+            assert inf[key] == inf_new[key], key
+        assert rel_rms(d_H.cpu().numpy(), H_new) <= tol
     pl.destroy()
     # keep_lists = 0: every update rebuilds everything, with the same field
     d_pos.copy_(torch.from_numpy(pos0))
@@ -583,3 +588,51 @@ def test_rebuild_keeps_lists_when_cells_stay_occupied(precision):
     assert rel_rms(d_H.cpu().numpy(), fresh(pos1)) <= tol
     p0.destroy()
 
+
+
+def test_positions_checked_against_the_box_on_the_device():
+    """With the caller's box the bounds check runs on the device and reports
+    with the level sizes: a non-finite coordinate or a dipole outside the box
+    is rejected at creation and at update, and a rejected update leaves the
+    plan usable after a valid one (same field as a new plan)."""
+    import torch
+
+    n = 5000
+    pos0, box = inputs.ferrofluid(n, 61)
+    m = inputs.random_moments(n, 62)[None]
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    prm = ccfmm.params(order=4, theta=0.5, box=box, precision=ccfmm.PREC_FP64, max_batch=1)
+    d_m = torch.from_numpy(m).to(dev)
+    d_H = torch.empty_like(d_m)
+    hi = np.asarray(box[1], float)
+    bad_nan = pos0.copy()
+    bad_nan[17, 2] = np.nan
+    bad_out = pos0.copy()
+    bad_out[4321, 0] = hi[0] + 1e-6
+    for bad, msg in ((bad_nan, "non-finite"), (bad_out, "outside the box")):
+        d_bad = torch.from_numpy(bad).to(dev)
+        with pytest.raises(ccfmm.CCFMMError) as e:
+            ccfmm.Plan.create_device(n, d_bad.data_ptr(), prm, st)
+        assert e.value.status == ccfmm.EINVAL and msg in ccfmm.last_error()
+    d_pos = torch.from_numpy(pos0.copy()).to(dev)
+    pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    for bad, msg in ((bad_out, "outside the box"), (bad_nan, "non-finite")):
+        d_pos.copy_(torch.from_numpy(bad))
+        with pytest.raises(ccfmm.CCFMMError) as e:
+            pl.update_positions_device(d_pos.data_ptr(), st)
+        assert e.value.status == ccfmm.EINVAL and msg in ccfmm.last_error()
+    pos1 = pos0.copy()
+    pos1[:, 1] = np.minimum(pos1[:, 1] + 0.01, hi[1])
+    d_pos.copy_(torch.from_numpy(pos1))
+    pl.update_positions_device(d_pos.data_ptr(), st)
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    H = d_H.cpu().numpy().copy()
+    pl.destroy()
+    p2 = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+    p2.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    assert rel_rms(H, d_H.cpu().numpy()) <= 1e-13
+    p2.destroy()
