@@ -6,7 +6,8 @@
  *
  * Readings of passages where the paper is silent or garbled (all documented in
  * the design notes of the repository):
- *  - truncation: multipoles |q| <= p, locals |n| <= p, D up to order 2p;
+ *  - truncation: multipoles |q| <= p, locals |n| <= p, D up to order 2p
+ *    (params.truncation = 1 selects the other reading, |n| + |q| <= p);
  *  - near/far tie alpha == alpha_m counts as far, evaluated exactly with
  *    squared, per-level normalised distances (see near_pair);
  *  - a point on a cell face belongs to the upper cell; the top face is clamped
@@ -277,32 +278,39 @@ int ccref_l2l(int32_t p, const double c[3], const double* Vparent, double* Vchil
 }
 
 /* Eq.(taylorcalc): V_n += (-1)^|n| sum_q D_{n+q}(c) Q_q, c = target center -
- * source center; |n| <= p, |q| <= p, so D is needed up to order 2p.  D is the
- * caller's scratch of side 2p+1. */
-static void m2l(int p, const double c[3], const double* Q, double* V, double* D) {
+ * source center; |n| <= p, |q| <= p, so D is needed up to order 2p.  With
+ * total != 0 only the terms with |n| + |q| <= p are kept (the other reading
+ * of "truncate after the p-th order").  D is the caller's scratch of side
+ * 2p+1. */
+static void m2l(int p, const double c[3], const double* Q, double* V, double* D, int total) {
   int K = 2 * p;
   dtensor(K, c, D);
   for (int nx = 0; nx <= p; nx++)
     for (int ny = 0; nx + ny <= p; ny++)
       for (int nz = 0; nx + ny + nz <= p; nz++) {
+        const int qmax = total ? p - (nx + ny + nz) : p;
         double s = 0.0;
-        for (int qx = 0; qx <= p; qx++)
-          for (int qy = 0; qx + qy <= p; qy++)
-            for (int qz = 0; qx + qy + qz <= p; qz++)
+        for (int qx = 0; qx <= qmax; qx++)
+          for (int qy = 0; qx + qy <= qmax; qy++)
+            for (int qz = 0; qx + qy + qz <= qmax; qz++)
               s += D[cidx(nx + qx, ny + qy, nz + qz, K)] * Q[cidx(qx, qy, qz, p)];
         double sign = ((nx + ny + nz) & 1) ? -1.0 : 1.0;
         V[cidx(nx, ny, nz, p)] += sign * s;
       }
 }
 
-int ccref_m2l(int32_t p, const double c[3], const double* Q, double* V) {
+static int m2l_call(int32_t p, const double c[3], const double* Q, double* V, int total) {
   if (p < 0 || p > CCREF_PMAX) return -1;
   build_ftable();
   double* D = (double*)malloc(sizeof(double) * CUBE(2 * p));
-  m2l(p, c, Q, V, D);
+  m2l(p, c, Q, V, D, total);
   free(D);
   return 0;
 }
+
+int ccref_m2l(int32_t p, const double c[3], const double* Q, double* V) { return m2l_call(p, c, Q, V, 0); }
+
+int ccref_m2l_total(int32_t p, const double c[3], const double* Q, double* V) { return m2l_call(p, c, Q, V, 1); }
 
 /* Eq.(H) with the sign of H = -grad V: H_a = -sum_n V_n n_a y^(n-e_a) / n!. */
 static void l2p(int p, const double* V, const double y[3], double H[3]) {
@@ -467,6 +475,7 @@ typedef struct {
    * smallest cell carry the same values): local order and opening angle */
   const int32_t* leaf_p;
   const double* leaf_theta;
+  int total; /* M2L keeps only |n| + |q| <= p */
 } tree;
 
 /* Eq.(so): optimal dipoles per smallest cell. */
@@ -760,7 +769,7 @@ static double update_field(tree* T, cell* c) {
       cell* A = c->partners.v[t];
       double cc[3] = {c->center[0] - A->center[0], c->center[1] - A->center[1],
                       c->center[2] - A->center[2]};
-      m2l(T->p, cc, A->Q, c->V, D);
+      m2l(T->p, cc, A->Q, c->V, D, T->total);
     }
     free(D);
   }
@@ -834,6 +843,7 @@ static int check_params(int64_t n, const double* pos, const ccref_params* prm) {
   if (!prm || n < 1) return -1;
   if (prm->order < 1 || prm->order > CCREF_PMAX) return -1;
   if (!(prm->theta > 0.0 && prm->theta < 1.0)) return -1;
+  if (prm->truncation != 0 && prm->truncation != 1) return -1;
   for (int64_t i = 0; i < 3 * n; i++)
     if (!isfinite(pos[i])) return -1;
   return 0;
@@ -899,6 +909,7 @@ int ccref_fmm_leaf(int64_t n, const double* pos, const double* m, const ccref_pa
   T.H = H;
   T.leaf_p = leaf_p;
   T.leaf_theta = leaf_theta;
+  T.total = prm->truncation == 1;
 
   double t0 = now_s();
   int64_t* leafc = (int64_t*)malloc(sizeof(int64_t) * 3 * n);

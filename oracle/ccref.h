@@ -35,6 +35,8 @@ typedef struct {
   int32_t has_box;      /* 1: root cell is [box_lo, box_hi]; 0: bounding box */
   double box_lo[3], box_hi[3];
   int32_t nthreads;     /* OpenMP threads (<= 0: library default) */
+  int32_t truncation;   /* 0: multipoles and locals each to order p (the reading of Sec. 3);
+                           1: total degree, only terms with |n| + |q| <= p in M2L */
 } ccref_params;
 
 typedef struct {
@@ -89,6 +91,8 @@ int ccref_m2m(int32_t p, const double c[3], const double* Qchild, double* Qparen
 int ccref_l2l(int32_t p, const double c[3], const double* Vparent, double* Vchild);
 /* Eq.(taylorcalc): V += M2L(Q), c = target center - source center. */
 int ccref_m2l(int32_t p, const double c[3], const double* Q, double* V);
+/* The same keeping only the terms of total degree |n| + |q| <= p. */
+int ccref_m2l_total(int32_t p, const double c[3], const double* Q, double* V);
 /* Eq.(H) with H = -grad V: field at offset y from the expansion center. */
 int ccref_l2p(int32_t p, const double* V, const double y[3], double H[3]);
 /* Potential of a multipole expansion at x (relative to its center), Eq.(Vm): sum_n D_n(x) Q_n. */

@@ -32,7 +32,8 @@ def build(force=True):
 class Params(C.Structure):
     _fields_ = [("order", C.c_int32), ("theta", C.c_double), ("leaf_target", C.c_double),
                 ("leaf_rule", C.c_int32), ("has_box", C.c_int32),
-                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3), ("nthreads", C.c_int32)]
+                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3), ("nthreads", C.c_int32),
+                ("truncation", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -72,6 +73,7 @@ def lib():
         L.ccref_m2m.argtypes = [C.c_int32, _dp, _dp, _dp]
         L.ccref_l2l.argtypes = [C.c_int32, _dp, _dp, _dp]
         L.ccref_m2l.argtypes = [C.c_int32, _dp, _dp, _dp]
+        L.ccref_m2l_total.argtypes = [C.c_int32, _dp, _dp, _dp]
         L.ccref_l2p.argtypes = [C.c_int32, _dp, _dp, _dp]
         L.ccref_multipole_potential.argtypes = [C.c_int32, _dp, _dp]
         L.ccref_multipole_potential.restype = C.c_double
@@ -91,7 +93,9 @@ def _f64(a, shape=None):
     return a
 
 
-def make_params(order, theta, leaf_target=0.0, leaf_rule=0, box=None, nthreads=0):
+def make_params(order, theta, leaf_target=0.0, leaf_rule=0, box=None, nthreads=0, truncation=0):
+    """truncation 0: multipoles and locals each to order p; 1: M2L terms of
+    total degree |n| + |q| <= p only."""
     p = Params()
     p.order = int(order)
     p.theta = float(theta)
@@ -105,6 +109,7 @@ def make_params(order, theta, leaf_target=0.0, leaf_rule=0, box=None, nthreads=0
     else:
         p.has_box = 0
     p.nthreads = int(nthreads)
+    p.truncation = int(truncation)
     return p
 
 
@@ -144,12 +149,13 @@ def _stats_dict(st):
     }
 
 
-def fmm(pos, m, order, theta, leaf_target=0.0, leaf_rule=0, box=None, nthreads=0, return_stats=False):
+def fmm(pos, m, order, theta, leaf_target=0.0, leaf_rule=0, box=None, nthreads=0, return_stats=False,
+        truncation=0):
     pos = _f64(pos, (-1, 3))
     m = _f64(m, (-1, 3))
     H = np.zeros_like(pos)
     st = Stats()
-    prm = make_params(order, theta, leaf_target, leaf_rule, box, nthreads)
+    prm = make_params(order, theta, leaf_target, leaf_rule, box, nthreads, truncation)
     rc = lib().ccref_fmm(pos.shape[0], pos, m, C.byref(prm), H, C.byref(st))
     if rc:
         raise ValueError("ccref_fmm: invalid input")
@@ -232,9 +238,9 @@ def l2l(p, c, Vparent):
     return Vc
 
 
-def m2l(p, c, Q, V=None):
+def m2l(p, c, Q, V=None, total=False):
     Vo = np.zeros((p + 1,) * 3) if V is None else _f64(V).copy()
-    lib().ccref_m2l(p, _f64(c), _f64(Q), Vo)
+    (lib().ccref_m2l_total if total else lib().ccref_m2l)(p, _f64(c), _f64(Q), Vo)
     return Vo
 
 

@@ -553,3 +553,51 @@ def test_mlp_reference_gradient_finite_differences(ref):
         lm, _ = ref.mlp_loss_grad(Pm, x, t, mask, *MLP_DIMS)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
+
+
+# ------------------------------------------------------- total-degree truncation
+def test_total_degree_m2l_is_the_legendre_series(ref):
+    """M2L keeping only |n| + |q| <= p, then the local expansion, gives the
+    potential of a unit charge at x (source cell) at y (target cell) as the
+    Taylor polynomial of 1/|c + w| in w = y - x of degree p, i.e. the Legendre
+    series sum_{j<=p} |w|^j P_j(-c.w/(|c||w|)) / |c|^(j+1) (generating
+    function of the Legendre polynomials).  The separate truncation (each
+    index to p) is not this polynomial."""
+    from numpy.polynomial import legendre
+
+    rng = np.random.default_rng(31)
+    for p in (2, 4, 6, 8):
+        for _ in range(3):
+            src, tgt = np.zeros(3), np.array([3.0, -2.0, 1.5])
+            x = rng.uniform(-0.5, 0.5, 3)
+            y = rng.uniform(-0.5, 0.5, 3)
+            c = tgt - src
+            Q = ref.charge_moments(p, src, x[None], np.array([1.0]))
+            V = ref.m2l(p, c, Q, total=True)
+            got = ref.local_potential(p, V, y)
+            w = y - x
+            cw = -np.dot(c, w) / (np.linalg.norm(c) * np.linalg.norm(w))
+            want = sum(np.linalg.norm(w) ** j / np.linalg.norm(c) ** (j + 1) * legendre.legval(cw, [0] * j + [1])
+                       for j in range(p + 1))
+            assert got == pytest.approx(want, rel=1e-13), p
+            # the separate form keeps some terms of degree p+1..2p: it differs
+            # from the polynomial by a fair share of the truncation error
+            exact = 1.0 / np.linalg.norm(c + w)
+            sep = ref.local_potential(p, ref.m2l(p, c, Q), y)
+            assert abs(sep - want) > 1e-2 * abs(exact - want)
+            assert abs(got - exact) < 2 * (np.linalg.norm(w) / np.linalg.norm(c)) ** (p + 1) / np.linalg.norm(c)
+
+
+def test_total_degree_fmm_converges_to_bruteforce(ref):
+    """Whole FMM with total-degree truncation: theta -> 0 is the direct sum,
+    and the error against the direct sum falls as p rises."""
+    c = inputs.config_lattice_1000()
+    pos, box, m = c["pos"], c["box"], c["m"][0]
+    Hd = ref.bruteforce(pos, m)
+    H0 = ref.fmm(pos, m, 4, 1e-3, leaf_target=8, box=box, truncation=1)
+    assert ref.rel_rms(H0, Hd) <= 1e-13
+    errs = [ref.rel_rms(ref.fmm(pos, m, p, 0.5, leaf_target=8, box=box, truncation=1), Hd) for p in (2, 4, 6, 8)]
+    assert all(errs[i + 1] < errs[i] for i in range(3)), errs
+    # at the same order the total-degree form keeps fewer terms: never more accurate here
+    e_sep = ref.rel_rms(ref.fmm(pos, m, 4, 0.5, leaf_target=8, box=box), Hd)
+    assert errs[1] > e_sep
