@@ -35,11 +35,15 @@ network trained on two smaller films of the same recipe).
 its captured evaluation replayed after every in-place precession step of the
 moments, the energy taken on the GPU every step (and the same loop in FP64).
 
+`--workload truncation`: both readings of the paper's truncation (each index to
+order p, or total degree |n| + |q| <= p): errors against the direct sum, energy
+errors and times on the 32^3 lattice and the ferrofluid.
+
 `--workload leafsweep`: the paper's leaf-size study (Table I, Eq. (so)) redone on
 the GPU path: trees two levels either side of s_o(p) for Table II's (p, alpha)
 pairs, on 32^3 and 128^3 lattices and the ferrofluid.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|film|dynamics|leafsweep]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|film|dynamics|leafsweep|truncation]
                        [--skip-cpu] [--skip-fp64] [--calib-copy]
 """
 import argparse
@@ -428,6 +432,37 @@ def bench_leafsweep(args, torch, ccfmm, inputs):
     print(json.dumps(res), flush=True)
 
 
+def bench_truncation(args, torch, ccfmm, inputs):
+    """Both readings of the paper's truncation (Sec. 3) on the GPU path: each
+    index to order p (the default) against total degree |n| + |q| <= p.  On the
+    paper's 32^3 lattice (FP64) at Table II's (p, alpha) pairs, at (6, 0.48)
+    and at theta = 0.5: field error against the direct sum at every dipole,
+    energy error, evaluation time, next to the paper's estimate
+    [theta/(2-theta)]^p; and the ferrofluid at (6, 0.5) in mixed precision.
+    One JSON line; value = ferrofluid evals/s of the evaluation with the
+    default truncation."""
+    from paper_0810_0233_amd import study
+
+    res = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "steps": 5, "warmup": 1}
+    pos, box = inputs.lattice(32, 32, 32)
+    m = inputs.random_moments(pos.shape[0], 6032)
+    settings = [(2, 0.36), (3, 0.54), (4, 0.64), (5, 0.71), (6, 0.76), (7, 0.79), (8, 0.81), (6, 0.48)]
+    settings += [(p, 0.5) for p in range(2, 9)]
+    log("truncation study: 32^3 lattice, FP64")
+    lat = study.truncation_study(pos, box, m, settings, progress=log)
+    c = inputs.config_ferrofluid()
+    log("truncation study: ferrofluid, mixed")
+    ff = study.truncation_study(c["pos"], c["box"], c["m"][0], [(6, 0.5)], precision=ccfmm.PREC_MIXED,
+                                samples=args.samples, progress=log)
+    n = c["pos"].shape[0]
+    t0 = next(r for r in ff if r["truncation"] == 0)
+    res.update({"value": n / (t0["eval_ms"] * 1e-3), "ms_per_step": t0["eval_ms"],
+                "config": {"workload": "truncation", "step": "eval"},
+                "study": {"lattice_32": lat, "ferrofluid_rsa_1048576": ff}, "roofline": None, "cpu_baseline": None})
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,6 +496,9 @@ def main():
         return
     if args.workload == "leafsweep":
         bench_leafsweep(args, torch, ccfmm, inputs)
+        return
+    if args.workload == "truncation":
+        bench_truncation(args, torch, ccfmm, inputs)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()

@@ -82,6 +82,9 @@ typedef struct {
                              occupied cells keeps the cell lists, M2L tiles and captured
                              evaluation (exactly what a full rebuild would produce);
                              0: every update rebuilds everything */
+  int32_t truncation;     /* 0 (default): multipoles and locals each to order p, M2L with D up to
+                             order 2p (the reading of Sec. 3); 1: total degree, M2L keeps only the
+                             terms with |n| + |q| <= p (D_k = 0 for |k| > p) */
 } ccfmm_params;
 
 /* One timed M2L configuration of ccfmm_plan_autotune. */

@@ -354,6 +354,7 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
   if (prm->selector != 0)
     fail(CCFMM_EINVAL, "selector must be 0 at plan creation (apply learned parameters with ccfmm_plan_select)");
   if (prm->max_batch < 1 || prm->max_batch > 4096) fail(CCFMM_EINVAL, "max_batch must be in 1..4096");
+  if (prm->truncation != 0 && prm->truncation != 1) fail(CCFMM_EINVAL, "truncation must be 0 or 1");
   if (prm->has_box)
     for (int a = 0; a < 3; a++)
       if (!std::isfinite(prm->box_lo[a]) || !std::isfinite(prm->box_hi[a])) fail(CCFMM_EINVAL, "box not finite");
@@ -600,6 +601,7 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->err_bound = 1e-5;
   prm->overlap_near = 1;
   prm->keep_lists = 1;
+  prm->truncation = 0;
   prm->has_box = 0;
   prm->max_batch = 1;
   prm->m2l_class_bits = 3;

@@ -87,7 +87,7 @@ static FTableHost make_ftable(int K) {
 // target cell); Eq.(taylorcalc) takes c = target minus source centre, i.e.
 // c = -delta * g in the level's units.  The zero offset (never a far pair) is
 // stored as zeros.
-__global__ void k_dtensor(int64_t nbox, int w0, int w1, int w2, double g0, double g1, double g2, int K,
+__global__ void k_dtensor(int64_t nbox, int w0, int w1, int w2, double g0, double g1, double g2, int K, int kmax,
                           const int32_t* __restrict__ fptr, const int32_t* __restrict__ fq,
                           const double* __restrict__ fval, int64_t row0, double* Dd, float* Df) {
   const int NK = ncoef(K), NR = NK + 1;  // row: NK entries, then a zero
@@ -102,7 +102,8 @@ __global__ void k_dtensor(int64_t nbox, int w0, int w1, int w2, double g0, doubl
   const double c[3] = {-dx * g0, -dy * g1, -dz * g2};
   const double r2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
   const int64_t o = (row0 + d) * NR + k;
-  if (r2 == 0.0 || k == NK) {
+  // |k| > kmax: total-degree truncation keeps only |n| + |q| = |n + q| <= p
+  if (r2 == 0.0 || k == NK || kMI.x[k] + kMI.y[k] + kMI.z[k] > kmax) {
     Dd[o] = 0.0;
     Df[o] = 0.0f;
     return;
@@ -182,7 +183,8 @@ void build_dtensors(Plan& P, hipStream_t st) {
     const auto& k = keys[i];
     const int64_t nt = key_nbox[i] * NR;
     k_dtensor<<<ceil_div(nt, 256), 256, 0, st>>>(key_nbox[i], (int)k[3], (int)k[4], (int)k[5], k[0], k[1], k[2], K,
-                                                 dptr, dq, dval, key_row[i], Dd, Df);
+                                                 P.prm.truncation == 1 ? P.p : K, dptr, dq, dval, key_row[i], Dd,
+                                                 Df);
     CCFMM_HIP(hipGetLastError());
   }
   if (P.precision != CCFMM_PREC_FP64 && P.p <= 6) build_wide_ops(P, st);

@@ -123,3 +123,59 @@ def fit_c(records):
     p2 = np.array([r["order"] ** 2 for r in rs], dtype=float)
     s = np.array([r["s_opt"] for r in rs], dtype=float)
     return float(np.dot(p2, s) / np.dot(p2, p2))
+
+
+def paper_error_estimate(p, theta):
+    """Sec. 3: the truncation error of a multipole expansion of order p at
+    opening angle theta is of order e = [theta / (2 - theta)]^p."""
+    return (theta / (2.0 - theta)) ** p
+
+
+def truncation_study(pos, box, m, settings, precision=None, reps=5, samples=0, seed=13, progress=None):
+    """Both readings of Sec. 3's truncation on the GPU path: for every (p,
+    theta) in settings and truncation 0 (multipoles and locals each to order
+    p) and 1 (total degree |n| + |q| <= p), the field error against the FP64
+    direct sum (at every dipole, or at `samples` seeded dipoles), the relative
+    energy error (every dipole only), the evaluation time (median of reps) and
+    the M2L pass time (M2L kernel autotuned per plan).  One configuration m
+    [n][3]."""
+    import torch
+
+    from . import ccfmm
+
+    precision = ccfmm.PREC_FP64 if precision is None else precision
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    n = pos.shape[0]
+    d_pos = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+    d_m = torch.from_numpy(np.ascontiguousarray(m)).to(dev)
+    d_H = torch.empty_like(d_m)
+    idx = np.arange(n) if not samples or samples >= n else np.sort(
+        np.random.default_rng(seed).choice(n, samples, replace=False))
+    d_idx = torch.from_numpy(idx.astype(np.int64)).to(dev)
+    d_Hd = torch.empty((idx.size, 3), dtype=torch.float64, device=dev)
+    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m.data_ptr(), idx.size, d_idx.data_ptr(), d_Hd.data_ptr(), st)
+    torch.cuda.synchronize()
+    E_d = float(-0.5 * torch.sum(d_m * d_Hd)) if idx.size == n else None
+    out = []
+    for p, theta in settings:
+        for trunc in (0, 1):
+            prm = ccfmm.params(order=p, theta=theta, box=box, precision=precision, max_batch=1, truncation=trunc)
+            pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+            pl.autotune(1, d_m.data_ptr(), d_H.data_ptr(), st)
+            t = _timed(lambda: pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st), reps, torch)
+            H = d_H[d_idx]
+            err = float(torch.sqrt(torch.sum((H - d_Hd) ** 2) / torch.sum(d_Hd ** 2)))
+            rec = {"order": p, "theta": theta, "truncation": trunc, "eps_abs": err,
+                   "e_paper": paper_error_estimate(p, theta), "eval_ms": 1e3 * t,
+                   "m2l_ms": pl.eval_device_timed(1, d_m.data_ptr(), d_H.data_ptr(), st)["m2l"],
+                   "levels": pl.info()["levels"]}
+            if E_d is not None:
+                E = float(-0.5 * torch.sum(d_m * d_H))
+                rec["energy_rel_err"] = abs(E - E_d) / abs(E_d)
+            pl.destroy()
+            out.append(rec)
+            if progress:
+                progress("  p=%d theta=%.2f truncation=%d: eps_abs %.3e (paper e %.3e) eval %.3f ms m2l %.3f ms" % (
+                    p, theta, trunc, rec["eps_abs"], rec["e_paper"], rec["eval_ms"], rec["m2l_ms"]))
+    return out

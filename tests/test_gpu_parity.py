@@ -636,3 +636,31 @@ def test_positions_checked_against_the_box_on_the_device():
     torch.cuda.synchronize()
     assert rel_rms(H, d_H.cpu().numpy()) <= 1e-13
     p2.destroy()
+
+
+@pytest.mark.parametrize("order", [3, 6, 8])
+def test_total_degree_truncation_matches_oracle(ref, order):
+    """truncation = 1 (M2L keeps |n| + |q| <= p): the FP64 GPU FMM equals the
+    oracle FMM of the same reading to the 1e-10 bar on the 10^3 lattice and a
+    ragged ferrofluid, and differs from the separate truncation; mixed
+    precision stays within 1e-5 of FP64 through every M2L kernel the order
+    allows."""
+    c = inputs.config_lattice_1000()
+    pos, box, m = c["pos"], c["box"], c["m"][0]
+    print("case lattice p=%d total degree" % order, flush=True)
+    H_ref = ref.fmm(pos, m, order, 0.5, leaf_target=8, box=box, truncation=1)
+    H = plan_for(pos, order, 0.5, 8, box, truncation=1).eval(m)
+    assert rel_rms(H, H_ref) <= FP64_BAR
+    H_sep = plan_for(pos, order, 0.5, 8, box).eval(m)
+    assert rel_rms(H_sep, H) > 1e3 * FP64_BAR
+    pos2, box2 = inputs.ferrofluid(6000, 77)
+    m2 = inputs.random_moments(6000, 78)
+    print("case ferrofluid n=6000 p=%d total degree" % order, flush=True)
+    H_ref2 = ref.fmm(pos2, m2, order, 0.5, box=box2, truncation=1)
+    H64 = plan_for(pos2, order, 0.5, 0.0, box2, truncation=1).eval(m2)
+    assert rel_rms(H64, H_ref2) <= FP64_BAR
+    variants = [0, 1, 2, 3, 4] if order <= 6 else [0]
+    for v in variants:
+        Hm = plan_for(pos2, order, 0.5, 0.0, box2, precision=ccfmm.PREC_MIXED, truncation=1,
+                      m2l_variant=v).eval(m2)
+        assert rel_rms(Hm, H64) <= 1e-5, v

@@ -33,3 +33,12 @@ def test_fit_of_c_in_s_equals_c_p_squared():
     recs[0]["s_opt"] = 99.0  # orders up to 3 are not fitted (Eq. (so) sets 8 there)
     recs[1]["s_opt"] = 99.0
     assert study.fit_c(recs) == pytest.approx(1.3)
+
+
+def test_error_estimate_reproduces_table_ii():
+    """Sec. 3 estimate e = [theta/(2-theta)]^p at Table II's (p, alpha) pairs:
+    about 0.05 for every pair (printed there as 0.048 ... 0.053)."""
+    pairs = {(2, 0.36): 0.048, (3, 0.54): 0.051, (4, 0.64): 0.049, (5, 0.71): 0.050, (6, 0.76): 0.053,
+             (7, 0.79): 0.051, (8, 0.81): 0.046}
+    for (p, a), e in pairs.items():
+        assert abs(study.paper_error_estimate(p, a) - e) <= 0.0006, (p, a)
