@@ -118,8 +118,12 @@ def pass_work(info, n, nb, order):
         "p2m": {"kernel": "k_permute_moments+k_p2m<float,%d>" % order, "bound": "hbm",
                 "bytes": n * nb * 24.0 + n * 12.0 + leaves * exp_b, "flops": 6.0 * NP * n * nb},
         "m2m": {"kernel": "k_m2m<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
+        # the method's own M2L products: 2 NP^2 per pair and configuration, NP = (p+1)(p+2)(p+3)/6 - 1 in the
+        # full form, p (p + 2) in the traceless form (the fold and fill are per-cell work)
         "m2l": {"kernel": m2l_kernel_name(info["m2l_variant"], order),
-                "bound": "mfma", "bytes": 2.0 * cells * exp_b, "flops": info["m2l_flops_per_config"] * nb},
+                "bound": "mfma", "bytes": 2.0 * cells * exp_b,
+                "flops": (2.0 * (order * (order + 2)) ** 2 * info["n_m2l_pairs"] * nb
+                          if m2l_traceless_active(info["m2l_variant"], order) else info["m2l_flops_per_config"] * nb)},
         "l2l": {"kernel": "k_l2l<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
         # each input read once: FP32 position and residual (24 B), moment (12 B per configuration), caller
         # index (4 B), the smallest cells' local expansions when L2P is fused; FP64 field written (24 B)
@@ -137,10 +141,18 @@ def pass_work(info, n, nb, order):
     return out
 
 
+def m2l_traceless_active(variant, order):
+    """Whether the M2L pass runs in the traceless form (the default for the
+    mixed-precision wide kernels, orders <= 6)."""
+    return variant in (2, 3, 4) and order <= 6
+
+
 def m2l_kernel_name(variant, order):
-    """The M2L kernel a plan's variant launches (FP32)."""
-    return {0: "k_m2l<float,%d>" % order, 1: "k_m2l_wave<float,%d>" % order, 2: "k_m2l_wide<%d,4>" % order,
-            3: "k_m2l_wide<%d,2>" % order, 4: "k_m2l_wide<%d,1>" % order}[variant]
+    """The M2L kernel a plan's variant launches (FP32; the wide kernels in the
+    traceless form)."""
+    return {0: "k_m2l<float,%d>" % order, 1: "k_m2l_wave<float,%d>" % order,
+            2: "k_m2l_wide<%d,4,true>" % order, 3: "k_m2l_wide<%d,2,true>" % order,
+            4: "k_m2l_wide<%d,1,true>" % order}[variant]
 
 
 # the source file that defines each kernel family

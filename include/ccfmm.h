@@ -85,6 +85,10 @@ typedef struct {
   int32_t truncation;     /* 0 (default): multipoles and locals each to order p, M2L with D up to
                              order 2p (the reading of Sec. 3); 1: total degree, M2L keeps only the
                              terms with |n| + |q| <= p (D_k = 0 for |k| > p) */
+  int32_t m2l_traceless;  /* 1 (default): the mixed-precision wide M2L kernels contract folded
+                             moments over their 2l+1 components per degree and fill the rest of
+                             V from the Laplace equation (D and V are harmonic; the same sums,
+                             rounded differently); 0: the full 83 x 84 operator at p = 6 */
 } ccfmm_params;
 
 /* One timed M2L configuration of ccfmm_plan_autotune. */

@@ -29,7 +29,7 @@ class ccfmm_params(C.Structure):
                 ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
                 ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32), ("m2l_variant", C.c_int32),
                 ("use_graph", C.c_int32), ("overlap_near", C.c_int32), ("keep_lists", C.c_int32),
-                ("truncation", C.c_int32)]
+                ("truncation", C.c_int32), ("m2l_traceless", C.c_int32)]
 
 
 class ccfmm_tune_entry(C.Structure):
@@ -153,7 +153,7 @@ def _check(rc):
 
 def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64, selector=0,
            err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=0, use_graph=1, overlap_near=1,
-           keep_lists=1, truncation=0):
+           keep_lists=1, truncation=0, m2l_traceless=1):
     p = ccfmm_params()
     _check(lib().ccfmm_params_default(C.byref(p)))
     p.order = int(order)
@@ -175,6 +175,7 @@ def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64
     p.overlap_near = int(overlap_near)
     p.keep_lists = int(keep_lists)
     p.truncation = int(truncation)
+    p.m2l_traceless = int(m2l_traceless)
     return p
 
 

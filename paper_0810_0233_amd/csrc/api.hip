@@ -220,6 +220,8 @@ static void size_expansions(Plan& P, int nb) {
   const size_t es = P.precision == CCFMM_PREC_FP64 ? sizeof(double) : sizeof(float);
   P.Q.ensure(es * std::max<int64_t>(1, off));
   P.V.ensure(es * std::max<int64_t>(1, off));
+  if (P.precision != CCFMM_PREC_FP64 && P.p <= 6 && P.prm.m2l_traceless)
+    P.Qr.ensure(sizeof(float) * std::max<int64_t>(1, off / NS * ((P.p * (P.p + 2) + 3) & ~3)));
   P.m_sorted.ensure(es * 3 * (size_t)P.n * nb);
   if (nb >= P.batched_min) P.m_sorted_t.ensure(es * 3 * (size_t)P.n * nb);
   P.qv_batch = nb;
@@ -355,6 +357,7 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
     fail(CCFMM_EINVAL, "selector must be 0 at plan creation (apply learned parameters with ccfmm_plan_select)");
   if (prm->max_batch < 1 || prm->max_batch > 4096) fail(CCFMM_EINVAL, "max_batch must be in 1..4096");
   if (prm->truncation != 0 && prm->truncation != 1) fail(CCFMM_EINVAL, "truncation must be 0 or 1");
+  if (prm->m2l_traceless != 0 && prm->m2l_traceless != 1) fail(CCFMM_EINVAL, "m2l_traceless must be 0 or 1");
   if (prm->has_box)
     for (int a = 0; a < 3; a++)
       if (!std::isfinite(prm->box_lo[a]) || !std::isfinite(prm->box_hi[a])) fail(CCFMM_EINVAL, "box not finite");
@@ -602,6 +605,7 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->overlap_near = 1;
   prm->keep_lists = 1;
   prm->truncation = 0;
+  prm->m2l_traceless = 1;
   prm->has_box = 0;
   prm->max_batch = 1;
   prm->m2l_class_bits = 3;

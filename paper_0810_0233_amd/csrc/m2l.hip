@@ -329,11 +329,6 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
 // keeps the loads free of consumers until the products that need them.
 __device__ const float g_zero_row[128] = {};
 
-template <int P>
-__device__ __forceinline__ int op_index_kperm(int m, int kq, int ks) {
-  constexpr int KS = nstride(P) / 4;
-  return op_index<P>(m, kq * KS + ks);
-}
 
 // Operator layout of the wide kernels: slot e of row block mb holds, for
 // steps 4 k4 .. 4 k4 + 3 of lane l, the float4 at k4 * 256 + 4 l (so a lane
@@ -347,9 +342,115 @@ __device__ __forceinline__ int op_index_kperm(int m, int kq, int ks) {
 // float4s so the four groups sit in different banks).
 // Row length padded to a multiple of 256 words (whole 16-byte loads of one
 // wavefront).
+// Traceless form.  D is harmonic (sum_a D_{k+2e_a} = 0), so in the M2L sum
+// every moment with q_z >= 2 can be moved onto q - 2e_z + 2e_x and
+// q - 2e_z + 2e_y with a minus sign (highest q_z first) without changing any
+// V_n, and the sum then runs over the q_z <= 1 components only, 2l + 1 per
+// degree.  V is harmonic too, so only its n_z <= 1 components need the
+// product; the others follow from V_{m+2e_z} = -V_{m+2e_x} - V_{m+2e_y}
+// (lowest n_z first).  At p = 6 the operator shrinks from 83 x 84 to 48 x 48.
+__host__ __device__ constexpr int nred(int p) { return p * (p + 2); }  // sum over l = 1..p of 2l + 1
+__host__ __device__ constexpr int nred_stride(int p) { return (nred(p) + 3) & ~3; }
+
+// Reduced index r -> full index f (expansion position f - 1): the f with
+// f_z <= 1 in increasing order.  The multi-indices are graded by degree, so
+// the list for order p is a prefix of this one for every p <= 6.
+struct RedFull {
+  int8_t full[nred(6)];
+  constexpr RedFull() : full{} {
+    MultiIndexTable<6> mi;
+    int r = 0;
+    for (int f = 1; f < ncoef(6); f++)
+      if (mi.z[f] <= 1) full[r++] = (int8_t)f;
+  }
+};
+__device__ constexpr RedFull kRedFull{};
+
+// Moves of the fold, highest z first: the moment at src goes, negated, onto
+// d1 (two more in x, two less in z) and d2 (two more in y).
 template <int P>
+struct FoldTable {
+  static constexpr int NF = nact(P) - nred(P) > 0 ? nact(P) - nred(P) : 1;
+  int src[NF], d1[NF], d2[NF];
+  constexpr FoldTable() : src{}, d1{}, d2{} {
+    MultiIndexTable<P> mi;
+    int t = 0;
+    for (int z = P; z >= 2; z--)
+      for (int f = 1; f < ncoef(P); f++)
+        if (mi.z[f] == z) {
+          src[t] = f;
+          d1[t] = midx(mi.x[f] + 2, mi.y[f], z - 2);
+          d2[t] = midx(mi.x[f], mi.y[f] + 2, z - 2);
+          t++;
+        }
+  }
+};
+
+// Folded moments Qr[row][nred_stride(P)] from the full moments (one thread per
+// expansion row, FP32).
+template <int P>
+__global__ void k_fold_moments(int64_t rows, const float* __restrict__ Q, float* __restrict__ Qr) {
+  constexpr int NSF = nstride(P), NR = nred(P), NRS = nred_stride(P), NF = nact(P) - nred(P);
+  constexpr FoldTable<P> F{};
+  constexpr RedFull R{};
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float q[NSF];
+  const f32x4* in = reinterpret_cast<const f32x4*>(Q + r * NSF);
+#pragma unroll
+  for (int i = 0; i < NSF / 4; i++) {
+    const f32x4 v = in[i];
+    q[4 * i] = v[0];
+    q[4 * i + 1] = v[1];
+    q[4 * i + 2] = v[2];
+    q[4 * i + 3] = v[3];
+  }
+#pragma unroll
+  for (int i = 0; i < NF; i++) {
+    const float v = q[F.src[i] - 1];
+    q[F.d1[i] - 1] -= v;
+    q[F.d2[i] - 1] -= v;
+  }
+  f32x4* out = reinterpret_cast<f32x4*>(Qr + r * NRS);
+#pragma unroll
+  for (int i = 0; i < NRS / 4; i++) {
+    f32x4 v;
+#pragma unroll
+    for (int u = 0; u < 4; u++) v[u] = 4 * i + u < NR ? q[R.full[4 * i + u] - 1] : 0.f;
+    out[i] = v;
+  }
+}
+
+// The n_z >= 2 components of local expansions whose n_z <= 1 components the
+// traceless M2L wrote (lowest z first); padding positions set to zero.
+template <int P>
+__global__ void k_fill_locals(int64_t rows, float* __restrict__ V) {
+  constexpr int NSF = nstride(P), NA = nact(P), NF = nact(P) - nred(P);
+  constexpr FoldTable<P> F{};
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float v[NSF];
+  f32x4* row = reinterpret_cast<f32x4*>(V + r * NSF);
+#pragma unroll
+  for (int i = 0; i < NSF / 4; i++) {
+    const f32x4 a = row[i];
+    v[4 * i] = a[0];
+    v[4 * i + 1] = a[1];
+    v[4 * i + 2] = a[2];
+    v[4 * i + 3] = a[3];
+  }
+#pragma unroll
+  for (int i = NF - 1; i >= 0; i--) v[F.src[i] - 1] = -v[F.d1[i] - 1] - v[F.d2[i] - 1];
+#pragma unroll
+  for (int i = NA; i < NSF; i++) v[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < NSF / 4; i++) row[i] = f32x4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
+}
+
+template <int P, bool RED = false>
 struct WideOp {
-  static constexpr int NP = nact(P), NS = nstride(P), KS = NS / 4, ND = ncoef(2 * P);
+  static constexpr int NP = RED ? nred(P) : nact(P), NS = RED ? nred_stride(P) : nstride(P), KS = NS / 4,
+                       ND = ncoef(2 * P);
   static constexpr int MF = NP / 16, RF = NP % 16;
   static constexpr bool VROWS = MF >= 1 && RF > 0 && RF <= 8;
   static constexpr int MB = VROWS ? MF : (NP + 15) / 16;  // matrix-core row blocks
@@ -362,15 +463,28 @@ struct WideOp {
   static constexpr int NEP = (NE + 255) / 256 * 256;     // padded row length
 };
 
+// operator entry (row m, column k) of the wide layout: the full form's
+// op_index, or in the traceless form D_{n+q} over the reduced rows and columns
+template <int P, bool RED>
+__device__ __forceinline__ int wide_op_index(int m, int k) {
+  if constexpr (RED) {
+    if (m >= nred(P) || k >= nred(P)) return ncoef(2 * P);
+    const int a = kRedFull.full[m], b = kRedFull.full[k];
+    return midx(kMI.x[a] + kMI.x[b], kMI.y[a] + kMI.y[b], kMI.z[a] + kMI.z[b]);
+  } else {
+    return op_index<P>(m, k);
+  }
+}
+
 // derivative-tensor index of slot e (ND, the row's trailing zero, for padding)
-template <int P>
+template <int P, bool RED = false>
 __device__ __forceinline__ int wide_slot_dindex(int e) {
-  using W = WideOp<P>;
+  using W = WideOp<P, RED>;
   if (e >= W::NE) return W::ND;
   if (e >= W::NEM) {
     const int kq = (e - W::NEM) / W::KSTR, r = (e - W::NEM) % W::KSTR;
     if (r >= W::RV * W::KS) return W::ND;
-    return op_index_kperm<P>(16 * W::MB + r % W::RV, kq, r / W::RV);
+    return wide_op_index<P, RED>(16 * W::MB + r % W::RV, kq * W::KS + r / W::RV);
   }
   const int mb = e / (W::KS * 64), r0 = e % (W::KS * 64);
   int ks, l;
@@ -381,28 +495,36 @@ __device__ __forceinline__ int wide_slot_dindex(int e) {
     ks = 4 * W::K4 + (r0 - W::K4 * 256) / 64;
     l = r0 & 63;
   }
-  return op_index_kperm<P>(16 * mb + (l & 15), l >> 4, ks);
+  return wide_op_index<P, RED>(16 * mb + (l & 15), (l >> 4) * W::KS + ks);
 }
 
 // Every derivative-table row expanded into that layout (FP32), once per
 // table: a step's operator is then one contiguous block of memory.
-template <int P>
+template <int P, bool RED>
 __global__ void k_expand_ops(int64_t nrows, const float* __restrict__ Df, float* __restrict__ Dx) {
-  using W = WideOp<P>;
+  using W = WideOp<P, RED>;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows * W::NEP) return;
   const int64_t r = t / W::NEP;
   const int e = (int)(t % W::NEP);
-  Dx[t] = Df[r * drow_stride(P) + wide_slot_dindex<P>(e)];
+  Dx[t] = Df[r * drow_stride(P) + wide_slot_dindex<P, RED>(e)];
+}
+
+template <int P, bool RED>
+static void expand_ops_red(Plan& P_, hipStream_t st) {
+  using W = WideOp<P, RED>;
+  float* Dx = reinterpret_cast<float*>(P_.Dx.ensure(sizeof(float) * (size_t)P_.nrows * W::NEP));
+  const int64_t nt = P_.nrows * W::NEP;
+  k_expand_ops<P, RED><<<ceil_div(nt, 256), 256, 0, st>>>(P_.nrows, P_.Df.as<float>(), Dx);
+  CCFMM_HIP(hipGetLastError());
 }
 
 template <int P>
 static void expand_ops_impl(Plan& P_, hipStream_t st) {
-  using W = WideOp<P>;
-  float* Dx = reinterpret_cast<float*>(P_.Dx.ensure(sizeof(float) * (size_t)P_.nrows * W::NEP));
-  const int64_t nt = P_.nrows * W::NEP;
-  k_expand_ops<P><<<ceil_div(nt, 256), 256, 0, st>>>(P_.nrows, P_.Df.as<float>(), Dx);
-  CCFMM_HIP(hipGetLastError());
+  if (P_.prm.m2l_traceless)
+    expand_ops_red<P, true>(P_, st);
+  else
+    expand_ops_red<P, false>(P_, st);
 }
 
 void build_wide_ops(Plan& P, hipStream_t st) {
@@ -417,7 +539,9 @@ void build_wide_ops(Plan& P, hipStream_t st) {
   }
 }
 
-template <int P, int CB>
+// RED: the traceless form (Q holds the folded moments, nred_stride(P) per
+// row; only the n_z <= 1 rows of V are written, k_fill_locals does the rest).
+template <int P, int CB, bool RED>
 __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile* __restrict__ tiles,
                                                    const int32_t* __restrict__ tile_order, int64_t ntiles,
                                                    const int32_t* __restrict__ tile_tgt,
@@ -425,8 +549,9 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
                                                    const int32_t* __restrict__ step_src,
                                                    const float* __restrict__ Dop, const float* __restrict__ Q,
                                                    float* __restrict__ V, LevelOffsets lo, int nb, int TB, int TC) {
-  using W = WideOp<P>;
+  using W = WideOp<P, RED>;
   constexpr int NS = W::NS, KS = W::KS, MB = W::MB, NP = W::NP, RV = W::RV;
+  constexpr int NSV = nstride(P);  // row stride of V (and of Q in the full form)
   constexpr int K4 = W::K4, KT = W::KT;  // full groups of 4 steps, steps left over
   constexpr int NEP = W::NEP;             // operator words per step (padded)
   __shared__ __attribute__((aligned(16))) float sT[2][NEP];
@@ -435,7 +560,7 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   // tiles are launched longest first (greedy balance over the compute units)
   if ((int64_t)blockIdx.x >= ntiles) return;
   const M2LTile tl = tiles[tile_order[blockIdx.x]];
-  const float* Ql = Q + lo.qoff[tl.level];
+  const float* Ql = Q + (RED ? lo.qoff[tl.level] / NSV * NS : lo.qoff[tl.level]);
   const int nsteps = tl.nsteps;
 
   // this lane's columns: 16 CB w + 16 cb + lane % 16, fragment rows kq KS .. kq KS + KS - 1
@@ -568,20 +693,18 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     if (ctc[cb] < 0) continue;
     const int tgt = tile_tgt[tl.tgt0 + ctc[cb]];
     if (tgt < 0) continue;
-    float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NS;
+    float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NSV;
 #pragma unroll
     for (int mb = 0; mb < MB; mb++) {
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         const int m = 16 * mb + acc_row<float>(kq, r);
-        if (m < NS) {
-          float v = 0.f;
-          if (m < NP) {
-            const int f = m + 1;
-            const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
-            v = (deg & 1) ? -acc[mb][cb][r] : acc[mb][cb][r];
-          }
-          out[m] = v;
+        if (m < NP) {
+          const int f = RED ? (int)kRedFull.full[m] : m + 1;
+          const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
+          out[f - 1] = (deg & 1) ? -acc[mb][cb][r] : acc[mb][cb][r];
+        } else if (!RED && m < NS) {
+          out[m] = 0.f;
         }
       }
     }
@@ -602,20 +725,23 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
       if (ctc[cb] < 0) continue;
       const int tgt = tile_tgt[tl.tgt0 + ctc[cb]];
       if (tgt < 0) continue;
-      float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NS;
+      float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NSV;
+      // the traceless form writes the RV rows only (the fill writes the rest)
+      constexpr int NW = RED ? RV : NS - 16 * MB;
 #pragma unroll
-      for (int j0 = 0; j0 < NS - 16 * MB; j0 += 4) {
+      for (int j0 = 0; j0 < NW; j0 += 4) {
         const int j = j0 + kq;
-        if (j < NS - 16 * MB) {
+        if (j < NW) {
           float v = 0.f;
+          int f = 16 * MB + j + 1;
 #pragma unroll
           for (int jj = 0; jj < RV; jj++)
             if (jj == j) {
-              const int f = 16 * MB + jj + 1;
+              f = RED ? (int)kRedFull.full[16 * MB + jj] : 16 * MB + jj + 1;
               const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
               v = (deg & 1) ? -pv[cb][jj] : pv[cb][jj];
             }
-          out[16 * MB + j] = v;
+          out[f - 1] = v;
         }
       }
     }
@@ -631,19 +757,30 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value && PP <= 6) {
     if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1) {
       const unsigned nblk = (unsigned)P.ntiles;
-#define CCFMM_WIDE(CB)                                                                                               \
-  k_m2l_wide<PP, CB><<<nblk, 256, 0, st>>>(P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles,            \
-                                           P.tile_tgt.as<int32_t>(), P.step_delta.as<int32_t>(),                    \
-                                           P.step_src.as<int32_t>(), P.Dx.as<float>(), P.Q.as<T>(), P.V.as<T>(), lo,   \
-                                           nb, P.TB, P.TC)
-      if (P.tiles_variant == kM2LWide4)
-        CCFMM_WIDE(4);
-      else if (P.tiles_variant == kM2LWide2)
-        CCFMM_WIDE(2);
-      else
-        CCFMM_WIDE(1);
+      const bool red = P.prm.m2l_traceless != 0;
+      const int64_t rows = P.qv_elems / nstride(PP);
+      if (red) {
+        k_fold_moments<PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.Q.as<float>(), P.Qr.as<float>());
+        CCFMM_HIP(hipGetLastError());
+      }
+#define CCFMM_WIDE(CB, RED)                                                                                          \
+  k_m2l_wide<PP, CB, RED><<<nblk, 256, 0, st>>>(                                                                     \
+      P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(),                        \
+      P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), P.Dx.as<float>(), RED ? P.Qr.as<T>() : P.Q.as<T>(),     \
+      P.V.as<T>(), lo, nb, P.TB, P.TC)
+      if (P.tiles_variant == kM2LWide4) {
+        if (red) CCFMM_WIDE(4, true); else CCFMM_WIDE(4, false);
+      } else if (P.tiles_variant == kM2LWide2) {
+        if (red) CCFMM_WIDE(2, true); else CCFMM_WIDE(2, false);
+      } else {
+        if (red) CCFMM_WIDE(1, true); else CCFMM_WIDE(1, false);
+      }
 #undef CCFMM_WIDE
       CCFMM_HIP(hipGetLastError());
+      if (red) {
+        k_fill_locals<PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.V.as<float>());
+        CCFMM_HIP(hipGetLastError());
+      }
       return;
     }
   }

@@ -32,11 +32,12 @@ def test_status_strings_and_defaults():
     assert ccfmm.status_string(ccfmm.EINVAL) == "invalid argument"
     p = ccfmm.params()
     assert p.order == 4 and p.theta == 0.5 and p.max_batch == 1
-    assert p.keep_lists == 1 and p.truncation == 0
+    assert p.keep_lists == 1 and p.truncation == 0 and p.m2l_traceless == 1
 
 
 @pytest.mark.parametrize("bad", [dict(order=0), dict(order=9), dict(theta=0.0), dict(theta=1.0),
-                                 dict(max_batch=0), dict(precision=7), dict(truncation=2)])
+                                 dict(max_batch=0), dict(precision=7), dict(truncation=2),
+                                 dict(m2l_traceless=3)])
 def test_invalid_params_rejected_without_gpu(bad):
     prm = ccfmm.params(**bad)
     with pytest.raises(ccfmm.CCFMMError) as e:

@@ -250,6 +250,15 @@ def test_wide_m2l_variants(order):
     print("order %d wide-vs-block %s" % (order, errs), flush=True)
     for variant in (2, 3, 4):
         assert errs[variant] <= 1e-6
+    # the full (83 x 84 at p = 6) operator in the wide kernels: the same sums,
+    # rounded differently from the traceless (folded) form used by default
+    for variant in (2, 4):
+        pl = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=nb, m2l_variant=variant,
+                      m2l_class_bits=3, m2l_traceless=0)
+        e = rel_rms(pl.eval(m), H[variant])
+        print("order %d variant %d traceless-vs-full %.3e" % (order, variant, e), flush=True)
+        assert e <= 1e-6
+        pl.destroy()
     p64 = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_FP64, max_batch=nb, m2l_variant=2)
     assert p64.info()["m2l_variant"] == 0
     assert rel_rms(H[2], p64.eval(m)) <= MIXED_BAR
