@@ -156,7 +156,8 @@ def m2l_kernel_name(variant, order):
 
 
 # the source file that defines each kernel family
-KERNEL_SRC = (("k_p2p", "p2p.hip"), ("k_l2p", "p2p.hip"), ("k_m2l", "m2l.hip"), ("k_p2m", "expansions.hip"),
+KERNEL_SRC = (("k_p2p", "p2p.hip"), ("k_l2p", "p2p.hip"), ("k_m2l", "m2l.hip"), ("k_fold", "m2l.hip"),
+              ("k_fill", "m2l.hip"), ("k_p2m", "expansions.hip"),
               ("k_m2m", "expansions.hip"), ("k_l2l", "expansions.hip"), ("k_permute", "expansions.hip"))
 
 

@@ -601,3 +601,37 @@ def test_total_degree_fmm_converges_to_bruteforce(ref):
     # at the same order the total-degree form keeps fewer terms: never more accurate here
     e_sep = ref.rel_rms(ref.fmm(pos, m, 4, 0.5, leaf_target=8, box=box), Hd)
     assert errs[1] > e_sep
+
+
+def test_traceless_fold_and_fill_reproduce_m2l(ref):
+    """D is harmonic (sum_a D_{k+2e_a} = 0).  Hence moving every moment with
+    q_z >= 2 onto q - 2e_z + 2e_x and q - 2e_z + 2e_y with a minus sign
+    (highest q_z first) leaves every V_n of M2L unchanged while the sum runs
+    over the 2l+1 components with q_z <= 1 only, and V's n_z >= 2 components
+    follow from V_{m+2e_z} = -V_{m+2e_x} - V_{m+2e_y}.  Checked here against
+    the oracle's M2L and derivative tensor for random moments."""
+    for p in (2, 3, 4, 5, 6):
+        rng = np.random.default_rng(60 + p)
+        full = [(x, y, d - x - y) for d in range(1, p + 1) for x in range(d, -1, -1) for y in range(d - x, -1, -1)]
+        Q = np.zeros((p + 1,) * 3)
+        for c in full:
+            Q[c] = rng.normal()
+        cvec = np.array([2.0, -3.0, 1.0]) + rng.uniform(-0.2, 0.2, 3)
+        V = ref.m2l(p, cvec, Q)
+        D = ref.dtensor(2 * p, cvec)
+        Qf = Q.copy()
+        for z in range(p, 1, -1):
+            for x, y, zz in full:
+                if zz == z:
+                    Qf[x + 2, y, z - 2] -= Qf[x, y, z]
+                    Qf[x, y + 2, z - 2] -= Qf[x, y, z]
+        red = [c for c in full if c[2] <= 1]
+        assert len(red) == p * (p + 2)
+        Vr = np.zeros_like(V)
+        for n in [(0, 0, 0)] + red:
+            Vr[n] = (-1) ** sum(n) * sum(D[n[0] + q[0], n[1] + q[1], n[2] + q[2]] * Qf[q] for q in red)
+        for z in range(2, p + 1):
+            for x, y, zz in full:
+                if zz == z:
+                    Vr[x, y, z] = -Vr[x + 2, y, z - 2] - Vr[x, y + 2, z - 2]
+        assert np.max(np.abs(Vr - V)) <= 1e-12 * np.max(np.abs(V)), p
