@@ -498,20 +498,16 @@ static void ensure_side_stream(Plan& P) {
 }
 
 // The passes of one evaluation.  With overlap, the near field (VALU-bound)
-// runs on the plan's side stream while M2L (MFMA-bound) and L2L run on the
-// caller's stream; the smooth field is added after the join.  The side
-// stream forks after M2M, so the near field and M2L are queued together
-// (forked before P2M, the near field fills the GPU first and M2L waits).  Timing
+// runs on the plan's side stream while P2M, M2M, M2L (MFMA-bound) and L2L run
+// on the caller's stream; the smooth field is added after the join.  The side
+// stream forks as soon as the moments are in tree order: the near field needs
+// nothing else, and it is the longest pass.  Timing
 // events (ev, 9 of them): [0] start, [1] after P2M, [2] after M2M, [3] after
 // M2L, [4] after L2L, [8] L2P start, [5] end, all on the caller's stream;
 // [6], [7] around the near field.
 static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev) {
   if (ev) CCFMM_HIP(hipEventRecord(ev[0], st));
   run_permute(P, nb, d_m, st);
-  run_p2m(P, nb, d_m, st);
-  if (ev) CCFMM_HIP(hipEventRecord(ev[1], st));
-  run_m2m(P, nb, st);
-  if (ev) CCFMM_HIP(hipEventRecord(ev[2], st));
   if (P.overlap) {
     ensure_side_stream(P);
     CCFMM_HIP(hipEventRecord(P.ev_fork, st));
@@ -521,6 +517,10 @@ static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStre
     if (ev) CCFMM_HIP(hipEventRecord(ev[7], P.side));
     CCFMM_HIP(hipEventRecord(P.ev_join, P.side));
   }
+  run_p2m(P, nb, d_m, st);
+  if (ev) CCFMM_HIP(hipEventRecord(ev[1], st));
+  run_m2m(P, nb, st);
+  if (ev) CCFMM_HIP(hipEventRecord(ev[2], st));
   run_m2l(P, nb, st);
   if (ev) CCFMM_HIP(hipEventRecord(ev[3], st));
   run_l2l(P, nb, st);
