@@ -90,6 +90,22 @@ struct P2PTgt {
   T x, y, z, lx, ly, lz;
 };
 
+// Blocks of a launch go to the 8 XCDs in turn, each XCD with its own L2.
+// Chunks in key order that are close in the list are close in space and share
+// source cells, so each XCD is given runs of kXcdRun consecutive block slots:
+// XCD x runs block slots x, x + 8, ... of the remapped order, i.e. runs x,
+// x + 8, x + 16, ... of kXcdRun chunks-blocks each.  Within a run the sources
+// stay in one L2; every XCD still draws runs from the whole domain, which
+// keeps uneven work (clustered dipoles) balanced across the XCDs.  Blocks
+// past the last whole group of 8 runs keep their order.
+constexpr int kXcdRun = 32;
+__device__ __forceinline__ int64_t xcd_run_block(int nblk, int bid) {
+  const int full = nblk / (8 * kXcdRun) * (8 * kXcdRun);
+  if (bid >= full) return bid;
+  const int x = bid & 7, s = bid >> 3;
+  return ((int64_t)(s / kXcdRun) * 8 + x) * kXcdRun + s % kXcdRun;
+}
+
 // One source on one target: f += (3 (m.r) r / r^2 - m) / r^3, written as
 // inv3 * (k r - m) with k = 3 (m.r) / r^2.  Only the target's own cell can
 // hold a source at zero separation (a position determines its cell), so only
@@ -205,10 +221,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
   // the wave index is uniform: say so, so chunk data, counts and loop bounds
   // live in scalar registers and branch on scalar conditions
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  // blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
-  // range of chunks, so neighbouring cells (shared sources) share an L2
-  const int nblk = gridDim.x, bid = blockIdx.x;
-  const int64_t blk = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  const int64_t blk = xcd_run_block(gridDim.x, blockIdx.x);
   const int64_t item = blk * kP2PWaves + w;
   const int b = blockIdx.y;
   if (item >= a.nchunks) return;
@@ -913,9 +926,7 @@ __global__ void __launch_bounds__(256, 2) k_p2p_mfma(P2PArgs a, const P2PChunk* 
                                                      int64_t nchunks, const float* __restrict__ y,
                                                      const float* __restrict__ mt, double* __restrict__ H) {
   __shared__ __attribute__((aligned(16))) float sA[2][kMNA];
-  // blocks are dealt round-robin to the 8 XCDs: give each a contiguous range
-  const int nblk = gridDim.x, bid = blockIdx.x;
-  const int64_t item = (nblk % 8 == 0) ? (int64_t)(bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  const int64_t item = xcd_run_block(gridDim.x, blockIdx.x);
   if (item >= nchunks) return;
   const P2PChunk ch = chunks[item];
   switch ((3 * ch.count + 15) / 16) {  // row blocks in use (uniform over the block)
