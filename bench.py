@@ -35,6 +35,9 @@ network trained on two smaller films of the same recipe).
 its captured evaluation replayed after every in-place precession step of the
 moments, the energy taken on the GPU every step (and the same loop in FP64).
 
+`--workload leaffit`: the paper's fit of s_o(p) over many system sizes (Fig. 2)
+on the GPU: 30 cubic lattices of side 16 to 132, p = 4, 5, 6.
+
 `--workload truncation`: both readings of the paper's truncation (each index to
 order p, or total degree |n| + |q| <= p): errors against the direct sum, energy
 errors and times on the 32^3 lattice and the ferrofluid.
@@ -43,7 +46,7 @@ errors and times on the 32^3 lattice and the ferrofluid.
 the GPU path: trees two levels either side of s_o(p) for Table II's (p, alpha)
 pairs, on 32^3 and 128^3 lattices and the ferrofluid.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|film|dynamics|leafsweep|truncation]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|film|dynamics|leafsweep|leaffit|truncation]
                        [--skip-cpu] [--skip-fp64] [--calib-copy]
 """
 import argparse
@@ -445,6 +448,30 @@ def bench_leafsweep(args, torch, ccfmm, inputs):
     print(json.dumps(res), flush=True)
 
 
+def bench_leaffit(args, torch, ccfmm, inputs):
+    """The paper's fit of s_o = c p^2 over many system sizes (Fig. 2), on the
+    GPU: 30 cubic lattices of side 16 ... 132, Table II's (p, alpha) pairs for
+    p = 4, 5, 6, one level either side of the paper's tree; mixed precision.
+    One JSON line; value = evals/s of the 132^3 lattice at p = 6 on its
+    fastest tree (full step)."""
+    from paper_0810_0233_amd import study
+
+    pairs = [(4, 0.64), (5, 0.71), (6, 0.76)]
+    sides = list(range(16, 133, 4))
+    fit = study.lattice_size_fit(sides, pairs, progress=log)
+    log("c in s_o = c p^2 over %d sizes: %.3f (paper 0.74); mean s_opt %s" % (
+        len(sides), fit["c_fit"], {p: round(v, 1) for p, v in fit["s_opt_mean"].items()}))
+    last = fit["sides"][-1]
+    r6 = next(r for r in last["records"] if r["order"] == 6)
+    best = min(r6["points"], key=lambda q: q["step_ms"])
+    res = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "steps": 5, "warmup": 1,
+           "value": last["n"] / (best["step_ms"] * 1e-3), "ms_per_step": best["step_ms"],
+           "config": {"workload": "leaffit", "sides": [sides[0], sides[-1], len(sides)]},
+           "study": fit, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(res), flush=True)
+
+
 def bench_truncation(args, torch, ccfmm, inputs):
     """Both readings of the paper's truncation (Sec. 3) on the GPU path: each
     index to order p (the default) against total degree |n| + |q| <= p.  On the
@@ -512,6 +539,9 @@ def main():
         return
     if args.workload == "truncation":
         bench_truncation(args, torch, ccfmm, inputs)
+        return
+    if args.workload == "leaffit":
+        bench_leaffit(args, torch, ccfmm, inputs)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()

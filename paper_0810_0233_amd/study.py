@@ -100,6 +100,32 @@ def leaf_sweep(pos, box, m, pairs, dL=(-2, -1, 0, 1, 2), precision=None, reps=7,
     return out
 
 
+def lattice_size_fit(sides, pairs, seed=6100, progress=None):
+    """The paper's fit of s_o(p) over many system sizes (its Fig. 2) redone on
+    the GPU: for every cubic lattice side in sides and every (p, theta) in
+    pairs, a sweep of one level either side of the paper's tree gives the
+    GPU-optimal s (parabola in log2 s through the three points).  Returns the
+    records per side and the least-squares c in s_o = c p^2 over all of them
+    (orders above 3)."""
+    from . import inputs
+
+    per_side = []
+    for side in sides:
+        pos, box = inputs.lattice(side, side, side)
+        m = inputs.random_moments(pos.shape[0], seed + side)
+        recs = leaf_sweep(pos, box, m, pairs, dL=(-1, 0, 1), reps=5, samples=256)
+        per_side.append({"side": side, "n": int(pos.shape[0]), "records": recs})
+        if progress:
+            progress("lattice %d^3: %s" % (side, ", ".join("p=%d s_opt %.1f" % (r["order"], r["s_opt"]) for r in recs)))
+    allrec = [r for ps in per_side for r in ps["records"]]
+    by_p = {}
+    for r in allrec:
+        by_p.setdefault(r["order"], []).append(r["s_opt"])
+    return {"sides": per_side, "c_fit": fit_c(allrec),
+            "s_opt_mean": {p: float(np.mean(v)) for p, v in by_p.items()},
+            "s_opt_median": {p: float(np.median(v)) for p, v in by_p.items()}}
+
+
 def optimum_s(pts, key):
     """s at the minimum of a parabola through the fastest point and its two
     neighbours in log2 s (the fastest point itself at an end of the sweep)."""
