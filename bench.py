@@ -38,6 +38,9 @@ moments, the energy taken on the GPU every step (and the same loop in FP64).
 `--workload leaffit`: the paper's fit of s_o(p) over many system sizes (Fig. 2)
 on the GPU: 30 cubic lattices of side 16 to 132, p = 4, 5, 6.
 
+`--workload params`: the paper's choice of (p, alpha) per error level (Table II,
+Fig. 3) on the GPU, on 32^3 and 128^3 lattices.
+
 `--workload truncation`: both readings of the paper's truncation (each index to
 order p, or total degree |n| + |q| <= p): errors against the direct sum, energy
 errors and times on the 32^3 lattice and the ferrofluid.
@@ -46,7 +49,7 @@ errors and times on the 32^3 lattice and the ferrofluid.
 the GPU path: trees two levels either side of s_o(p) for Table II's (p, alpha)
 pairs, on 32^3 and 128^3 lattices and the ferrofluid.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|film|dynamics|leafsweep|leaffit|truncation]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ferrofluid|sphere|clusters|film|dynamics|leafsweep|leaffit|params|truncation]
                        [--skip-cpu] [--skip-fp64] [--calib-copy]
 """
 import argparse
@@ -472,6 +475,36 @@ def bench_leaffit(args, torch, ccfmm, inputs):
     print(json.dumps(res), flush=True)
 
 
+def bench_params(args, torch, ccfmm, inputs):
+    """The paper's choice of (p, alpha) per error level (Table II and Fig. 3) on
+    the GPU: for e = 0.1 ... 0.001 and p = 2 ... 8, alpha from
+    [alpha/(2-alpha)]^p = e, the paper's tree, one timed full step and the
+    measured error, on the 32^3 lattice (the paper's size) and a 128^3
+    lattice.  One JSON line; value = evals/s of the 128^3 lattice at e = 0.05
+    with its fastest (p, alpha)."""
+    from paper_0810_0233_amd import study
+
+    errors = [0.1, 0.05, 0.02, 0.01, 0.005, 0.002, 0.001]
+    out = {}
+    for side in (32, 128):
+        pos, box = inputs.lattice(side, side, side)
+        m = inputs.random_moments(pos.shape[0], 7000 + side)
+        log("parameter sweep: %d^3 lattice" % side)
+        out["lattice_%d" % side] = study.param_sweep(pos, box, m, errors, list(range(2, 9)),
+                                                     samples=0 if side <= 32 else 4096, progress=log)
+        for e, b in out["lattice_%d" % side]["best"].items():
+            log("  e=%s: fastest p=%d alpha=%.3f, %.3f ms, eps_abs %.2e" % (e, b["order"], b["alpha"], b["step_ms"],
+                                                                              b["eps_abs"]))
+    b = out["lattice_128"]["best"]["0.05"]
+    n = 128 ** 3
+    res = {"metric": METRIC, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic", "steps": 5, "warmup": 1,
+           "value": n / (b["step_ms"] * 1e-3), "ms_per_step": b["step_ms"],
+           "config": {"workload": "params", "order": b["order"], "alpha": b["alpha"], "e": 0.05},
+           "study": out, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(res), flush=True)
+
+
 def bench_truncation(args, torch, ccfmm, inputs):
     """Both readings of the paper's truncation (Sec. 3) on the GPU path: each
     index to order p (the default) against total degree |n| + |q| <= p.  On the
@@ -542,6 +575,9 @@ def main():
         return
     if args.workload == "leaffit":
         bench_leaffit(args, torch, ccfmm, inputs)
+        return
+    if args.workload == "params":
+        bench_params(args, torch, ccfmm, inputs)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()

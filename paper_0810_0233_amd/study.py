@@ -126,6 +126,71 @@ def lattice_size_fit(sides, pairs, seed=6100, progress=None):
             "s_opt_median": {p: float(np.median(v)) for p, v in by_p.items()}}
 
 
+def alpha_for_error(p, e):
+    """The opening angle at which Sec. 3's estimate [alpha/(2-alpha)]^p equals e."""
+    r = e ** (1.0 / p)
+    return 2.0 * r / (1.0 + r)
+
+
+def param_sweep(pos, box, m, errors, orders, reps=5, samples=0, seed=17, min_alpha=0.25, progress=None):
+    """The paper's choice of (p, alpha) per error level (Table II, Fig. 3) on
+    the GPU: for every estimate e in errors and order p in orders, alpha is set
+    so that [alpha/(2-alpha)]^p = e, the tree follows the paper's s_o(p), and
+    one full step (update for the positions + evaluation, mixed precision,
+    M2L autotuned) is timed; the field error against the FP64 direct sum is
+    measured.  Angles below min_alpha are skipped, and a plan the library
+    refuses (lists beyond its limits) is recorded as such.  Returns the
+    points and, per e, the fastest (p, alpha)."""
+    import torch
+
+    from . import ccfmm
+
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    n = pos.shape[0]
+    d_pos = torch.from_numpy(np.ascontiguousarray(pos)).to(dev)
+    d_m = torch.from_numpy(np.ascontiguousarray(m[None])).to(dev)
+    d_H = torch.empty_like(d_m)
+    idx = np.arange(n) if not samples or samples >= n else np.sort(
+        np.random.default_rng(seed).choice(n, samples, replace=False))
+    d_idx = torch.from_numpy(idx.astype(np.int64)).to(dev)
+    d_Hd = torch.empty((idx.size, 3), dtype=torch.float64, device=dev)
+    ccfmm.direct_targets_device(n, d_pos.data_ptr(), d_m[0].data_ptr(), idx.size, d_idx.data_ptr(), d_Hd.data_ptr(),
+                                st)
+    pts = []
+    for e in errors:
+        for p in orders:
+            a = alpha_for_error(p, e)
+            if not min_alpha <= a < 1.0:  # tiny angles: near lists of whole regions, never the fastest
+                continue
+            prm = ccfmm.params(order=p, theta=a, box=box, precision=ccfmm.PREC_MIXED, max_batch=1)
+            try:
+                pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+            except ccfmm.CCFMMError as err:  # lists beyond the plan's limits at this size
+                pts.append({"e": e, "order": p, "alpha": a, "refused": str(err)})
+                continue
+            pl.autotune(1, d_m.data_ptr(), d_H.data_ptr(), st)
+
+            def step():
+                pl.update_positions_device(d_pos.data_ptr(), st)
+                pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+
+            t = _timed(step, reps, torch)
+            H = d_H[0][d_idx]
+            err = float(torch.sqrt(torch.sum((H - d_Hd) ** 2) / torch.sum(d_Hd ** 2)))
+            pl.destroy()
+            pts.append({"e": e, "order": p, "alpha": a, "step_ms": 1e3 * t, "eps_abs": err})
+            if progress:
+                progress("e=%.3g p=%d alpha=%.3f: step %.3f ms, eps_abs %.2e" % (e, p, a, 1e3 * t, err))
+    best = {}
+    for e in errors:
+        cand = [q for q in pts if q["e"] == e and "step_ms" in q]
+        if cand:
+            b = min(cand, key=lambda q: q["step_ms"])
+            best[str(e)] = {"order": b["order"], "alpha": b["alpha"], "step_ms": b["step_ms"], "eps_abs": b["eps_abs"]}
+    return {"points": pts, "best": best}
+
+
 def optimum_s(pts, key):
     """s at the minimum of a parabola through the fastest point and its two
     neighbours in log2 s (the fastest point itself at an end of the sweep)."""

@@ -42,3 +42,15 @@ def test_error_estimate_reproduces_table_ii():
              (7, 0.79): 0.051, (8, 0.81): 0.046}
     for (p, a), e in pairs.items():
         assert abs(study.paper_error_estimate(p, a) - e) <= 0.0006, (p, a)
+
+
+def test_alpha_for_error_inverts_the_estimate():
+    """alpha(p, e) solves [alpha/(2-alpha)]^p = e; Table II's pairs come back
+    at e = 0.05 to the two printed digits of alpha."""
+    for p in range(1, 9):
+        for e in (0.1, 0.05, 0.001):
+            a = study.alpha_for_error(p, e)
+            assert 0 < a < 1 and abs(study.paper_error_estimate(p, a) - e) <= 1e-12 * e
+    table = {2: 0.36, 3: 0.54, 4: 0.64, 5: 0.71, 6: 0.76, 7: 0.79, 8: 0.81}
+    for p, a in table.items():
+        assert abs(study.alpha_for_error(p, 0.05) - a) <= 0.01, p
