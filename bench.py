@@ -150,7 +150,7 @@ def pass_work(info, n, nb, order):
 def m2l_traceless_active(variant, order):
     """Whether the M2L pass runs in the traceless form (the default for the
     mixed-precision wide kernels, orders <= 6)."""
-    return variant in (2, 3, 4) and order <= 6
+    return variant in (2, 3, 4) and order <= 8
 
 
 def m2l_kernel_name(variant, order):

@@ -70,7 +70,8 @@ typedef struct {
   int32_t m2l_variant;    /* M2L kernel: 0 = block of 4 wavefronts sharing one operator per
                              step (64-column tiles), 1 = independent wavefronts (16 columns,
                              orders <= 6), 2 / 3 / 4 = wide blocks with a double-buffered
-                             operator (256 / 128 / 64 columns; mixed precision, orders <= 6).
+                             operator (256 / 128 / 64 columns; mixed precision, orders <= 6,
+                             <= 8 with m2l_traceless).
                              A variant the order or precision cannot use falls back to 0;
                              ccfmm_plan_autotune can choose */
   int32_t use_graph;      /* 1: evaluations are captured once into a HIP graph (per batch size

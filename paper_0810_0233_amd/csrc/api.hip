@@ -220,7 +220,7 @@ static void size_expansions(Plan& P, int nb) {
   const size_t es = P.precision == CCFMM_PREC_FP64 ? sizeof(double) : sizeof(float);
   P.Q.ensure(es * std::max<int64_t>(1, off));
   P.V.ensure(es * std::max<int64_t>(1, off));
-  if (P.precision != CCFMM_PREC_FP64 && P.p <= 6 && P.prm.m2l_traceless)
+  if (P.precision != CCFMM_PREC_FP64 && P.prm.m2l_traceless && P.p <= wide_max_order(true))
     P.Qr.ensure(sizeof(float) * std::max<int64_t>(1, off / NS * ((P.p * (P.p + 2) + 3) & ~3)));
   P.m_sorted.ensure(es * 3 * (size_t)P.n * nb);
   if (nb >= P.batched_min) P.m_sorted_t.ensure(es * 3 * (size_t)P.n * nb);
@@ -631,7 +631,8 @@ static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const 
       P.precision = prm->precision;
       P.nbmax = prm->max_batch;
       P.class_bits = prm->m2l_class_bits < 0 ? 3 : std::min(prm->m2l_class_bits, 12);
-      P.m2l_variant = m2l_variant_ok(prm->m2l_variant, prm->order, prm->precision == CCFMM_PREC_FP64)
+      P.m2l_variant = m2l_variant_ok(prm->m2l_variant, prm->order, prm->precision == CCFMM_PREC_FP64,
+                                   prm->m2l_traceless != 0)
                           ? prm->m2l_variant
                           : kM2LBlock;
       P.use_graph = prm->use_graph != 0;
@@ -791,7 +792,7 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
     const int variants[5] = {kM2LBlock, kM2LWave, kM2LWide4, kM2LWide2, kM2LWide1};
     const int bits[3] = {0, 3, 6};
     for (int v : variants) {
-      if (!m2l_variant_ok(v, P.p, P.precision == CCFMM_PREC_FP64)) continue;
+      if (!m2l_variant_ok(v, P.p, P.precision == CCFMM_PREC_FP64, P.prm.m2l_traceless != 0)) continue;
       for (int cb : bits) {
         P.m2l_variant = v;
         P.class_bits = cb;

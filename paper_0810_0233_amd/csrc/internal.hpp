@@ -32,11 +32,15 @@ constexpr int kM2LWide1 = 4;  // FP32, 64-column tiles
 inline int m2l_tile_cols(int variant) {
   return variant == kM2LWave ? 16 : variant == kM2LWide4 ? 256 : variant == kM2LWide2 ? 128 : 64;
 }
-// whether an M2L kernel variant exists for this order and precision
-inline bool m2l_variant_ok(int variant, int order, bool fp64) {
+// the wide (FP32) M2L kernels serve orders up to 6 in the full form and up
+// to 8 in the traceless form (its operator is p(p+2) square: 80 rows at p = 8)
+inline int wide_max_order(bool traceless) { return traceless ? 8 : 6; }
+// whether an M2L kernel variant exists for this order, precision and form
+inline bool m2l_variant_ok(int variant, int order, bool fp64, bool traceless) {
   if (variant == kM2LBlock) return true;
   if (variant == kM2LWave) return order <= 6;
-  if (variant == kM2LWide4 || variant == kM2LWide2 || variant == kM2LWide1) return order <= 6 && !fp64;
+  if (variant == kM2LWide4 || variant == kM2LWide2 || variant == kM2LWide1)
+    return order <= wide_max_order(traceless) && !fp64;
   return false;
 }
 

@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
   }
 }
 
-// Wide variant (FP32, orders <= 6): a block of four wavefronts owns a tile of
+// Wide variant (FP32; orders <= 6, <= 8 in the traceless form): a block of four wavefronts owns a tile of
 // 4 x 16 CB columns (16 CB per wavefront); each wavefront keeps MB x CB accumulator blocks, so every
 // operator fragment it reads from LDS feeds CB matrix products.  The contraction
 // index is permuted so lane group kq = lane / 16 holds k = kq KS + ks: a lane's
@@ -354,14 +354,14 @@ __host__ __device__ constexpr int nred_stride(int p) { return (nred(p) + 3) & ~3
 
 // Reduced index r -> full index f (expansion position f - 1): the f with
 // f_z <= 1 in increasing order.  The multi-indices are graded by degree, so
-// the list for order p is a prefix of this one for every p <= 6.
+// the list for order p is a prefix of this one for every p <= 8.
 struct RedFull {
-  int8_t full[nred(6)];
+  uint8_t full[nred(8)];
   constexpr RedFull() : full{} {
-    MultiIndexTable<6> mi;
+    MultiIndexTable<8> mi;
     int r = 0;
-    for (int f = 1; f < ncoef(6); f++)
-      if (mi.z[f] <= 1) full[r++] = (int8_t)f;
+    for (int f = 1; f < ncoef(8); f++)
+      if (mi.z[f] <= 1) full[r++] = (uint8_t)f;
   }
 };
 __device__ constexpr RedFull kRedFull{};
@@ -521,10 +521,11 @@ static void expand_ops_red(Plan& P_, hipStream_t st) {
 
 template <int P>
 static void expand_ops_impl(Plan& P_, hipStream_t st) {
-  if (P_.prm.m2l_traceless)
+  if (P_.prm.m2l_traceless) {
     expand_ops_red<P, true>(P_, st);
-  else
-    expand_ops_red<P, false>(P_, st);
+  } else {
+    if constexpr (P <= 6) expand_ops_red<P, false>(P_, st);
+  }
 }
 
 void build_wide_ops(Plan& P, hipStream_t st) {
@@ -535,7 +536,9 @@ void build_wide_ops(Plan& P, hipStream_t st) {
     case 4: expand_ops_impl<4>(P, st); break;
     case 5: expand_ops_impl<5>(P, st); break;
     case 6: expand_ops_impl<6>(P, st); break;
-    default: break;  // the wide kernels serve orders up to 6
+    case 7: expand_ops_impl<7>(P, st); break;
+    case 8: expand_ops_impl<8>(P, st); break;
+    default: break;
   }
 }
 
@@ -754,10 +757,11 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
   for (int l = 0; l <= P.L; l++) lo.qoff[l] = P.lev[l]->qoff;
   const T* D = std::is_same<T, double>::value ? (const T*)P.Dd.p : (const T*)P.Df.p;
   if (P.ntiles == 0) return;
-  if constexpr (std::is_same<T, float>::value && PP <= 6) {
-    if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1) {
+  if constexpr (std::is_same<T, float>::value && PP <= 8) {
+    const bool red = P.prm.m2l_traceless != 0;
+    if ((P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1) &&
+        PP <= wide_max_order(red)) {
       const unsigned nblk = (unsigned)P.ntiles;
-      const bool red = P.prm.m2l_traceless != 0;
       const int64_t rows = P.qv_elems / nstride(PP);
       if (red) {
         k_fold_moments<PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.Q.as<float>(), P.Qr.as<float>());
@@ -768,12 +772,22 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
       P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(),                        \
       P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), P.Dx.as<float>(), RED ? P.Qr.as<T>() : P.Q.as<T>(),     \
       P.V.as<T>(), lo, nb, P.TB, P.TC)
-      if (P.tiles_variant == kM2LWide4) {
-        if (red) CCFMM_WIDE(4, true); else CCFMM_WIDE(4, false);
-      } else if (P.tiles_variant == kM2LWide2) {
-        if (red) CCFMM_WIDE(2, true); else CCFMM_WIDE(2, false);
+      if (red) {
+        if (P.tiles_variant == kM2LWide4)
+          CCFMM_WIDE(4, true);
+        else if (P.tiles_variant == kM2LWide2)
+          CCFMM_WIDE(2, true);
+        else
+          CCFMM_WIDE(1, true);
       } else {
-        if (red) CCFMM_WIDE(1, true); else CCFMM_WIDE(1, false);
+        if constexpr (PP <= 6) {  // the full form's operator fits up to order 6
+          if (P.tiles_variant == kM2LWide4)
+            CCFMM_WIDE(4, false);
+          else if (P.tiles_variant == kM2LWide2)
+            CCFMM_WIDE(2, false);
+          else
+            CCFMM_WIDE(1, false);
+        }
       }
 #undef CCFMM_WIDE
       CCFMM_HIP(hipGetLastError());
@@ -785,7 +799,7 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
     }
   }
   if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1)
-    fail(CCFMM_EINVAL, "wide M2L variants need mixed precision and order <= 6");
+    fail(CCFMM_EINVAL, "wide M2L variants need mixed precision and order <= 6 (8 in the traceless form)");
   if (P.tiles_variant == kM2LWave) {
     if constexpr (PP <= 6) {
       k_m2l_wave<T, PP><<<ceil_div(P.ntiles, 4), 256, 0, st>>>(

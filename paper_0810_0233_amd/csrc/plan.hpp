@@ -79,8 +79,8 @@ struct Plan {
   // kept across rebuilds while the keys do not change
   int64_t nrows = 0;
   DevBuf Dd, Df;
-  DevBuf Dx;
-  DevBuf Qr;  // folded (traceless-form) moments, nred_stride(p) per row, for the wide M2L kernels  // FP32 rows expanded into the wide M2L kernels' LDS order (mixed precision, p <= 6)
+  DevBuf Dx;  // FP32 rows expanded into the wide M2L kernels' LDS order (mixed precision)
+  DevBuf Qr;  // folded (traceless-form) moments, nred_stride(p) per row, for the wide M2L kernels
   int dtab_p = 0;
   std::vector<std::array<double, 6>> dtab_keys;
   // M2L tiles

@@ -230,7 +230,7 @@ def test_m2l_variants_and_autotune_agree(ref, precision):
     assert rel_rms(d_H.cpu().numpy(), base) <= (1e-14 if precision == ccfmm.PREC_FP64 else 1e-6)
 
 
-@pytest.mark.parametrize("order", [2, 4, 5, 6])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7, 8])
 def test_wide_m2l_variants(order):
     """The wide FP32 M2L kernels (128- and 256-column tiles, permuted
     contraction order) equal the block kernel for several orders and a batch
@@ -252,7 +252,7 @@ def test_wide_m2l_variants(order):
         assert errs[variant] <= 1e-6
     # the full (83 x 84 at p = 6) operator in the wide kernels: the same sums,
     # rounded differently from the traceless (folded) form used by default
-    for variant in (2, 4):
+    for variant in ((2, 4) if order <= 6 else ()):  # the full form's wide kernels stop at order 6
         pl = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=nb, m2l_variant=variant,
                       m2l_class_bits=3, m2l_traceless=0)
         e = rel_rms(pl.eval(m), H[variant])
@@ -261,6 +261,11 @@ def test_wide_m2l_variants(order):
         pl.destroy()
     p64 = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_FP64, max_batch=nb, m2l_variant=2)
     assert p64.info()["m2l_variant"] == 0
+    if order > 6:  # the full form's wide kernels stop at order 6: such a plan gets the block kernel
+        pf = plan_for(pos, order, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=nb, m2l_variant=2,
+                      m2l_traceless=0)
+        assert pf.info()["m2l_variant"] == 0
+        pf.destroy()
     assert rel_rms(H[2], p64.eval(m)) <= MIXED_BAR
     p64.destroy()
 
