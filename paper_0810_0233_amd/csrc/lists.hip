@@ -727,6 +727,15 @@ __global__ void k_chunk_fill32(int32_t nl, const int32_t* lstart, const int32_t*
   for (int k = 0; k < lcount[i]; k++) dleaf[lstart[i] + k] = i;
 }
 
+// dipole -> smallest cell (tree order) alone, for plans that never run the
+// batched near field; the 32-chunk total is then zero
+__global__ void k_dleaf(int32_t nl, const int32_t* lstart, const int32_t* lcount, int32_t* dleaf, int32_t* total32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *total32 = 0;
+  if (i >= nl) return;
+  for (int k = 0; k < lcount[i]; k++) dleaf[lstart[i] + k] = i;
+}
+
 void build_p2p_chunks(Plan& P, hipStream_t st) {
   const int nl = P.lev[P.L]->ncells;
   P.nchunks_cap = (int64_t)nl + P.n / 64 + 1;
@@ -741,12 +750,18 @@ void build_p2p_chunks(Plan& P, hipStream_t st) {
   P2PChunk* ch = reinterpret_cast<P2PChunk*>(P.chunks.ensure(sizeof(P2PChunk) * P.nchunks_cap));
   k_chunk_fill<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), off, ch);
   CCFMM_HIP(hipGetLastError());
+  int32_t* dleaf = reinterpret_cast<int32_t*>(P.dleaf.ensure(sizeof(int32_t) * P.n));
+  if (P.nbmax < P.batched_min) {  // no batch of this plan reaches the matrix-core near field
+    k_dleaf<<<ceil_div(std::max(nl, 1), 256), 256, 0, st>>>(nl, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), dleaf,
+                                                            off32 + nl);
+    CCFMM_HIP(hipGetLastError());
+    return;
+  }
   k_chunk_count32<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lcount.as<int32_t>(), cnt32);
   CCFMM_HIP(hipGetLastError());
   scan_exclusive(cnt32, off32, nl, P.scratch, st);
   P2PChunk* ch32 =
       reinterpret_cast<P2PChunk*>(P.chunks32.ensure(sizeof(P2PChunk) * ((int64_t)nl + P.n / 32 + 1)));
-  int32_t* dleaf = reinterpret_cast<int32_t*>(P.dleaf.ensure(sizeof(int32_t) * P.n));
   k_chunk_fill32<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), off32, ch32,
                                                     dleaf);
   CCFMM_HIP(hipGetLastError());
