@@ -377,7 +377,6 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
   const TreeGeom geo0 = P.geo;
   const int L0 = P.L;
   const uint64_t allocs0 = devbuf_allocs();
-  const int64_t nch0 = P.nchunks, nch32_0 = P.nchunks32;
   double mn[3], mx[3];
   // With the caller's box and the paper's level rule the bounds are only a
   // check: it runs on the device and comes back with the level sizes (the
@@ -422,10 +421,15 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
   if (check[0]) fail(CCFMM_EINVAL, "non-finite position");
   if (check[1]) fail(CCFMM_EINVAL, "a dipole lies outside the box");
   if (same_geo && same_cells) {
+    // nothing to wait for: the near-field launches cover the chunk lists'
+    // capacity (unchanged with the cells) and read their lengths on the GPU;
+    // the plan statistics are those of the same lists, the direct-pair count
+    // is taken at the next ccfmm_plan_info
     build_p2p_chunks(P, st);
     P.n_rebuilds_kept++;
-    fill_info(P, st, false);
-    if (devbuf_allocs() != allocs0 || P.nchunks != nch0 || P.nchunks32 != nch32_0) P.drop_graph();
+    P.info.n_rebuilds_kept = P.n_rebuilds_kept;
+    P.pairs_stale = true;
+    if (devbuf_allocs() != allocs0) P.drop_graph();
     P.built = P.ever_built = true;
     return;
   }

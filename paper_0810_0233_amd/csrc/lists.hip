@@ -760,8 +760,8 @@ void build_p2p_chunks(Plan& P, hipStream_t st) {
   k_chunk_count32<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lcount.as<int32_t>(), cnt32);
   CCFMM_HIP(hipGetLastError());
   scan_exclusive(cnt32, off32, nl, P.scratch, st);
-  P2PChunk* ch32 =
-      reinterpret_cast<P2PChunk*>(P.chunks32.ensure(sizeof(P2PChunk) * ((int64_t)nl + P.n / 32 + 1)));
+  P.nchunks32_cap = (int64_t)nl + P.n / 32 + 1;
+  P2PChunk* ch32 = reinterpret_cast<P2PChunk*>(P.chunks32.ensure(sizeof(P2PChunk) * P.nchunks32_cap));
   k_chunk_fill32<<<ceil_div(nl, 256), 256, 0, st>>>(nl, P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), off32, ch32,
                                                     dleaf);
   CCFMM_HIP(hipGetLastError());

@@ -46,7 +46,7 @@ constexpr int kP2PWaves = 4;
 
 struct P2PArgs {
   const P2PChunk* chunks;
-  int64_t nchunks;
+  const int32_t* nchunks;    // device: the number of chunks (the launch covers the capacity)
   const int32_t* near_ptr;   // level L, compact leaves
   const int32_t* near_idx;
   const int32_t* coord;      // level L, compact leaves
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_
   const int64_t blk = xcd_run_block(gridDim.x, blockIdx.x);
   const int64_t item = blk * kP2PWaves + w;
   const int b = blockIdx.y;
-  if (item >= a.nchunks) return;
+  if (item >= *a.nchunks) return;
   const P2PChunk ch = a.chunks[item];
   const int n = (int)a.n;
   const int c = ch.count;
@@ -497,7 +497,8 @@ constexpr int kBT = 32;  // targets per chunk
 constexpr int kBS = 16;  // sources per step
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* __restrict__ chunks, int64_t nchunks,
+__global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* __restrict__ chunks,
+                                                      const int32_t* __restrict__ nchunks,
                                                      const T* __restrict__ y, const T* __restrict__ mt,
                                                      double* __restrict__ H) {
   constexpr int MB = 3 * kBT / 16;  // 6 row blocks
@@ -508,7 +509,7 @@ __global__ void __launch_bounds__(256) k_p2p_batched(P2PArgs a, const P2PChunk* 
   __shared__ T ss[kBS][6];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int64_t item = blockIdx.x;
-  if (item >= nchunks) return;
+  if (item >= *nchunks) return;
   const P2PChunk ch = chunks[item];
   const int nb = a.nb;
   const int cfg0 = blockIdx.y * 64;
@@ -923,11 +924,11 @@ __device__ __forceinline__ void p2p_mfma_chunk(const P2PArgs& a, const P2PChunk&
 }
 
 __global__ void __launch_bounds__(256, 2) k_p2p_mfma(P2PArgs a, const P2PChunk* __restrict__ chunks,
-                                                     int64_t nchunks, const float* __restrict__ y,
+                                                     const int32_t* __restrict__ nchunks, const float* __restrict__ y,
                                                      const float* __restrict__ mt, double* __restrict__ H) {
   __shared__ __attribute__((aligned(16))) float sA[2][kMNA];
   const int64_t item = xcd_run_block(gridDim.x, blockIdx.x);
-  if (item >= nchunks) return;
+  if (item >= *nchunks) return;
   const P2PChunk ch = chunks[item];
   switch ((3 * ch.count + 15) / 16) {  // row blocks in use (uniform over the block)
     case 1: p2p_mfma_chunk<1>(a, ch, y, mt, H, sA); break;
@@ -943,7 +944,7 @@ static P2PArgs p2p_args(Plan& P, int nb, bool fp64) {
   LevelData& D = *P.lev[P.L];
   P2PArgs a;
   a.chunks = P.chunks.as<P2PChunk>();
-  a.nchunks = P.nchunks;
+  a.nchunks = P.chunk_cnt.as<int32_t>() + (P.lev[P.L]->ncells + 1) + P.lev[P.L]->ncells;  // off[nl]
   a.near_ptr = D.near_ptr.as<int32_t>();
   a.near_idx = D.near_idx.as<int32_t>();
   a.coord = D.coord.as<int32_t>();
@@ -968,15 +969,16 @@ static void near_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const T* y = fp64 ? (const T*)P.yd.p : (const T*)P.yf.p;
   P2PArgs a = p2p_args(P, nb, fp64);
   if (nb >= P.batched_min) {
-    if (P.nchunks32 == 0) return;
-    dim3 grid((unsigned)P.nchunks32, ceil_div(nb, 64));
+    const int nl = P.lev[P.L]->ncells;
+    const int32_t* n32 = P.chunk_cnt.as<int32_t>() + 3 * (nl + 1) + nl;  // off32[nl]
+    dim3 grid((unsigned)P.nchunks32_cap, ceil_div(nb, 64));
     if constexpr (std::is_same<T, float>::value)
-      k_p2p_mfma<<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<float>(), d_H);
+      k_p2p_mfma<<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), n32, y, P.m_sorted_t.as<float>(), d_H);
     else
-      k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), P.nchunks32, y, P.m_sorted_t.as<T>(),
+      k_p2p_batched<T><<<grid, 256, 0, st>>>(a, P.chunks32.as<P2PChunk>(), n32, y, P.m_sorted_t.as<T>(),
                                              d_H);
   } else {
-    dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
+    dim3 grid(ceil_div(P.nchunks_cap, kP2PWaves), nb);
     k_p2p_l2p<T, PP, false><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
   }
   CCFMM_HIP(hipGetLastError());
@@ -1004,7 +1006,7 @@ static void fused_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const bool fp64 = std::is_same<T, double>::value;
   const T* y = fp64 ? (const T*)P.yd.p : (const T*)P.yf.p;
   P2PArgs a = p2p_args(P, nb, fp64);
-  dim3 grid(ceil_div(P.nchunks, kP2PWaves), nb);
+  dim3 grid(ceil_div(P.nchunks_cap, kP2PWaves), nb);
   k_p2p_l2p<T, PP, true><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
   CCFMM_HIP(hipGetLastError());
 }

@@ -107,6 +107,7 @@ struct Plan {
   DevBuf m_sorted_t;
   DevBuf chunks32, dleaf;
   int64_t nchunks32 = 0;
+  int64_t nchunks32_cap = 0;  // capacity of the 32-chunk list (launch size of the batched near field)
   int batched_min = 32;  // nbatch from which the near field runs on the matrix cores
   DevBuf scratch;    // scan/sort temporaries
   DevBuf scratch2;
