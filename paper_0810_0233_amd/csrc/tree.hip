@@ -547,6 +547,22 @@ void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells, 
     k_zero_i32<<<1, 64, 0, st>>>(g + L + 2, 1);
     k_flags_differ<<<ceil_div(nheap, T), T, 0, st>>>(flag, P.heap_flag_prev.as<int32_t>(), nheap, g + L + 2);
     CCFMM_HIP(hipGetLastError());
+    // the verdict first: with every cell's occupancy as before, the compact
+    // cells, their links, coordinates and level sizes are those of the
+    // previous build, and only the dipole ranges of the smallest cells change
+    int32_t differ = 1;
+    CCFMM_HIP(hipMemcpyAsync(&differ, g + L + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (d_check) CCFMM_HIP(hipMemcpyAsync(h_check, d_check, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st));
+    CCFMM_HIP(hipStreamSynchronize(st));
+    d_check = nullptr;  // read
+    if (differ == 0) {
+      *same_cells = true;
+      const int32_t nl = P.lev[L]->ncells;
+      k_leaf_ranges<<<ceil_div(nl, T), T, 0, st>>>(P.lev[L]->key.as<int32_t>(), ls, nl, P.lstart.as<int32_t>(),
+                                                    P.lcount.as<int32_t>());
+      CCFMM_HIP(hipGetLastError());
+      return;
+    }
   }
   int32_t* prev = reinterpret_cast<int32_t*>(P.heap_flag_prev.ensure(sizeof(int32_t) * nheap));
   CCFMM_HIP(hipMemcpyAsync(prev, flag, sizeof(int32_t) * nheap, hipMemcpyDeviceToDevice, st));
@@ -562,7 +578,7 @@ void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells, 
     if (d_check) CCFMM_HIP(hipMemcpyAsync(h_check, d_check, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st));
     CCFMM_HIP(hipStreamSynchronize(st));
   }
-  if (same_cells) *same_cells = compare && starts[L + 2] == 0;
+  if (same_cells) *same_cells = false;  // a kept tree returned above
   LevelPtrs lp{};
   for (int l = 0; l <= L; l++) {
     LevelData& D = *P.lev[l];
