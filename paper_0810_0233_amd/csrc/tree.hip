@@ -405,8 +405,9 @@ __global__ void k_leaf_start(const uint32_t* key, int64_t n, int64_t nleaf, int3
   start[k] = (int32_t)lo;
 }
 
+// yd (FP64 coordinates) only for FP64 plans: null skips it
 __global__ void k_gather_sorted(const double* __restrict__ pos, const uint32_t* __restrict__ key,
-                                const int32_t* __restrict__ perm, int64_t n, TreeGeom G, double* yd,
+                                const int32_t* __restrict__ perm, int64_t n, TreeGeom G, double inv_s, double* yd,
                                 float* yf) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -414,11 +415,10 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const uint32_t* 
   int32_t c[3];
   cell_coords(G, L, key[i], c);
   const int64_t src = perm[i];
-  const double inv_s = 1.0 / G.lev[L].s;
   for (int a = 0; a < 3; a++) {
     const double center = G.lo[a] + ((double)c[a] + 0.5) * G.lev[L].h[a];
     const double y = (pos[3 * src + a] - center) * inv_s;
-    yd[a * n + i] = y;
+    if (yd) yd[a * n + i] = y;
     const float hi = (float)y;
     yf[a * n + i] = hi;
     yf[(3 + a) * n + i] = (float)(y - (double)hi);  // residual: y = hi + lo to ~1e-16
@@ -532,8 +532,9 @@ void build_tree(Plan& P, const double* d_pos, hipStream_t st, bool* same_cells, 
   CCFMM_HIP(hipGetLastError());
   // sorted -> input order is the sorted val array
   CCFMM_HIP(hipMemcpyAsync(P.perm.p, val, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
-  k_gather_sorted<<<ceil_div(n, T), T, 0, st>>>(d_pos, key, P.perm.as<int32_t>(), n, G,
-                                                P.yd.as<double>(), P.yf.as<float>());
+  k_gather_sorted<<<ceil_div(n, T), T, 0, st>>>(d_pos, key, P.perm.as<int32_t>(), n, G, 1.0 / G.lev[L].s,
+                                                P.precision == CCFMM_PREC_FP64 ? P.yd.as<double>() : nullptr,
+                                                P.yf.as<float>());
   CCFMM_HIP(hipGetLastError());
 
   const int64_t nheap = (2ll << L) - 1;
