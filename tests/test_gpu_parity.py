@@ -537,8 +537,8 @@ def test_leaf_sweep_points_match_oracle(ref, order, theta, dl):
     pl.destroy()
 
 
-@pytest.mark.parametrize("precision", [ccfmm.PREC_FP64, ccfmm.PREC_MIXED])
-def test_rebuild_keeps_lists_when_cells_stay_occupied(precision):
+@pytest.mark.parametrize("precision,nb", [(ccfmm.PREC_FP64, 1), (ccfmm.PREC_MIXED, 1), (ccfmm.PREC_MIXED, 40)])
+def test_rebuild_keeps_lists_when_cells_stay_occupied(precision, nb):
     """A position update that moves dipoles without emptying or filling any
     cell (same geometry, same occupied cells at every level) keeps the cell
     lists, the M2L tiles and the captured evaluation; the replayed evaluation
@@ -555,33 +555,33 @@ def test_rebuild_keeps_lists_when_cells_stay_occupied(precision):
     W = hi - lo
     slab = pos2[:, 0] < lo[0] + 0.25 * W[0]
     pos2[slab, 0] += 0.5 * W[0]  # the slab x < 1/4 emptied: its cells are no longer occupied
-    m = inputs.random_moments(n, 53)[None]
+    m = np.stack([inputs.random_moments(n, 53 + b) for b in range(nb)])  # 40: the matrix-core near field
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream().cuda_stream
     d_m = torch.from_numpy(m).to(dev)
 
     def fresh(pos, with_info=False):
         d_pos = torch.from_numpy(pos).to(dev)
-        prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1)
+        prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=nb)
         pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
         d_H = torch.empty_like(d_m)
-        pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+        pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
         torch.cuda.synchronize()
         inf = pl.info()
         pl.destroy()
         return (d_H.cpu().numpy(), inf) if with_info else d_H.cpu().numpy()
 
     d_pos = torch.from_numpy(pos0.copy()).to(dev)
-    prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1)
+    prm = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=nb)
     pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
     d_H = torch.empty_like(d_m)
-    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)  # captured
+    pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)  # captured
     tol = 1e-13 if precision == ccfmm.PREC_FP64 else 1e-6
     for k, (pos, kept) in enumerate([(pos1, 1), (pos1, 2), (pos2, 2), (pos0, 2)]):
         print("case rebuild %d, kept so far %d" % (k, kept), flush=True)
         d_pos.copy_(torch.from_numpy(pos))
         pl.update_positions_device(d_pos.data_ptr(), st)
-        pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+        pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
         torch.cuda.synchronize()
         H_new, inf_new = fresh(pos, with_info=True)
         inf = pl.info()  # the direct-pair count of a kept update is taken here
@@ -592,12 +592,12 @@ def test_rebuild_keeps_lists_when_cells_stay_occupied(precision):
     pl.destroy()
     # keep_lists = 0: every update rebuilds everything, with the same field
     d_pos.copy_(torch.from_numpy(pos0))
-    prm0 = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=1, keep_lists=0)
+    prm0 = ccfmm.params(order=5, theta=0.5, box=box, precision=precision, max_batch=nb, keep_lists=0)
     p0 = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm0, st)
     d_pos.copy_(torch.from_numpy(pos1))
     p0.update_positions_device(d_pos.data_ptr(), st)
     assert p0.info()["n_rebuilds_kept"] == 0
-    p0.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    p0.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
     torch.cuda.synchronize()
     assert rel_rms(d_H.cpu().numpy(), fresh(pos1)) <= tol
     p0.destroy()
