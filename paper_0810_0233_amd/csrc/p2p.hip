@@ -212,7 +212,7 @@ __device__ __forceinline__ void l2p_write(const T* __restrict__ v, int pl, T yx,
 // without it the kernel writes the near field alone and the smooth part is
 // added later by k_l2p_batched (so the near field can run beside M2L).
 template <typename T, int P, bool kL2P>
-__global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 5 : 2) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
+__global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 6 : 2) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
                                                            const T* __restrict__ msort, const T* __restrict__ V,
                                                            double* __restrict__ H) {
   constexpr int NS = nstride(P);
