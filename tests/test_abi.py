@@ -45,6 +45,14 @@ def test_invalid_params_rejected_without_gpu(bad):
     assert e.value.status == ccfmm.EINVAL
 
 
+def test_empty_input_rejected():
+    # no dipoles: nothing to build a tree on; refused before any device call
+    with pytest.raises(ccfmm.CCFMMError) as e:
+        ccfmm.Plan.create(np.zeros((0, 3)), ccfmm.params())
+    assert e.value.status == ccfmm.EINVAL
+    assert "n must be >= 1" in ccfmm.last_error()
+
+
 def test_nonfinite_positions_rejected():
     pos = np.zeros((4, 3))
     pos[2, 1] = np.nan
