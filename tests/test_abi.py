@@ -37,7 +37,8 @@ def test_status_strings_and_defaults():
 
 @pytest.mark.parametrize("bad", [dict(order=0), dict(order=9), dict(theta=0.0), dict(theta=1.0),
                                  dict(max_batch=0), dict(precision=7), dict(truncation=2),
-                                 dict(m2l_traceless=3)])
+                                 dict(m2l_traceless=3), dict(max_batch=4097), dict(leaf_rule=2),
+                                 dict(selector=1), dict(leaf_target=float("inf"))])
 def test_invalid_params_rejected_without_gpu(bad):
     prm = ccfmm.params(**bad)
     with pytest.raises(ccfmm.CCFMMError) as e:
