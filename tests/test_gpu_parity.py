@@ -126,6 +126,33 @@ def test_batched_equals_single(ref):
             assert rel_rms(Hb[b], ref.fmm(pos, mb[b], 5, 0.5, box=box)) <= FP64_BAR
 
 
+def test_maximum_batch(ref):
+    """The largest batch a plan accepts, 4096 configurations in one launch:
+    FP64 configurations equal the same configuration evaluated alone (to
+    summation order) and the oracle at the first and last; the mixed plan
+    (matrix-core near field over 64 column blocks) stays within the mixed bar
+    of FP64 on every configuration."""
+    n, nb = 1500, 4096
+    pos, box = inputs.sphere_cut(n, 16)
+    mb = inputs.aligned_moments(n, nb, 4100)
+    print("case maximum batch fp64 n=%d nb=%d" % (n, nb), flush=True)
+    pl = plan_for(pos, 4, 0.5, 0.0, box, max_batch=nb)
+    Hb = pl.eval(mb)
+    for b in (0, 1, 2047, nb - 1):
+        Hs = pl.eval(mb[b:b + 1])[0]
+        assert rel_rms(Hb[b], Hs) <= 1e-14
+    for b in (0, nb - 1):
+        assert rel_rms(Hb[b], ref.fmm(pos, mb[b], 4, 0.5, box=box)) <= FP64_BAR
+    pl.destroy()
+    print("case maximum batch mixed n=%d nb=%d" % (n, nb), flush=True)
+    pm = plan_for(pos, 4, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=nb)
+    Hm = pm.eval(mb)
+    pm.destroy()
+    err = np.sqrt(np.sum((Hm - Hb) ** 2, axis=(1, 2)) / np.sum(Hb ** 2, axis=(1, 2)))
+    print("maximum batch: worst mixed vs fp64 %.3e" % err.max(), flush=True)
+    assert err.max() <= MIXED_BAR
+
+
 def test_edge_cases(ref):
     # one dipole: no field
     pl = plan_for(np.array([[0.3, 0.2, 0.1]]), 3, 0.5)
