@@ -67,7 +67,9 @@ typedef struct {
   int32_t max_batch;    /* largest nbatch the plan will evaluate (device buffers sized) */
   int32_t m2l_class_bits; /* M2L target ordering: cells grouped by their low key bits
                              (position inside their ancestors) before tiling; 0..12 */
-  int32_t m2l_variant;    /* M2L kernel: 0 = block of 4 wavefronts sharing one operator per
+  int32_t m2l_variant;    /* M2L kernel: -1 (default) = chosen at plan creation: 4 where the
+                             order, precision and form allow it, else 0; 0 = block of 4
+                             wavefronts sharing one operator per
                              step (64-column tiles), 1 = independent wavefronts (16 columns,
                              orders <= 6), 2 / 3 / 4 = wide blocks with a double-buffered
                              operator (256 / 128 / 64 columns; mixed precision, orders <= 6,

@@ -152,7 +152,7 @@ def _check(rc):
 
 
 def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64, selector=0,
-           err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=0, use_graph=1, overlap_near=1,
+           err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=-1, use_graph=1, overlap_near=1,
            keep_lists=1, truncation=0, m2l_traceless=1):
     p = ccfmm_params()
     _check(lib().ccfmm_params_default(C.byref(p)))

@@ -613,7 +613,7 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->has_box = 0;
   prm->max_batch = 1;
   prm->m2l_class_bits = 3;
-  prm->m2l_variant = kM2LBlock;
+  prm->m2l_variant = kM2LAuto;
   prm->use_graph = 1;
   return CCFMM_OK;
 }
@@ -635,10 +635,12 @@ static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const 
       P.precision = prm->precision;
       P.nbmax = prm->max_batch;
       P.class_bits = prm->m2l_class_bits < 0 ? 3 : std::min(prm->m2l_class_bits, 12);
-      P.m2l_variant = m2l_variant_ok(prm->m2l_variant, prm->order, prm->precision == CCFMM_PREC_FP64,
-                                   prm->m2l_traceless != 0)
-                          ? prm->m2l_variant
-                          : kM2LBlock;
+      const bool fp64 = prm->precision == CCFMM_PREC_FP64, traceless = prm->m2l_traceless != 0;
+      if (prm->m2l_variant == kM2LAuto)
+        P.m2l_variant = m2l_default_variant(prm->order, fp64, traceless);
+      else
+        P.m2l_variant = m2l_variant_ok(prm->m2l_variant, prm->order, fp64, traceless) ? prm->m2l_variant
+                                                                                       : kM2LBlock;
       P.use_graph = prm->use_graph != 0;
       P.overlap = prm->overlap_near != 0;
       if (own) {

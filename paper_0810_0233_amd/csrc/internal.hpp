@@ -24,6 +24,7 @@ constexpr int kKMax = 2 * kPMax;  // derivative tensors up to order 2p
 // M2L kernel variants and their tile widths in (target cell, configuration)
 // columns: a block of 4 wavefronts sharing one operator per step (64), or
 // independent wavefronts gathering operator entries themselves (16)
+constexpr int kM2LAuto = -1;  // the default: chosen from order, precision and form at plan creation
 constexpr int kM2LBlock = 0;
 constexpr int kM2LWave = 1;
 constexpr int kM2LWide4 = 2;  // FP32, 256-column tiles
@@ -42,6 +43,12 @@ inline bool m2l_variant_ok(int variant, int order, bool fp64, bool traceless) {
   if (variant == kM2LWide4 || variant == kM2LWide2 || variant == kM2LWide1)
     return order <= wide_max_order(traceless) && !fp64;
   return false;
+}
+// the variant a plan gets when the caller names none: the 64-column wide
+// kernel wherever it exists (the fastest one measured, single configurations
+// and batches of 64 alike), else the block kernel
+inline int m2l_default_variant(int order, bool fp64, bool traceless) {
+  return m2l_variant_ok(kM2LWide1, order, fp64, traceless) ? kM2LWide1 : kM2LBlock;
 }
 
 // configurations per M2L tile for a batch of nb: the next power of two, at

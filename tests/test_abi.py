@@ -33,6 +33,7 @@ def test_status_strings_and_defaults():
     p = ccfmm.params()
     assert p.order == 4 and p.theta == 0.5 and p.max_batch == 1
     assert p.keep_lists == 1 and p.truncation == 0 and p.m2l_traceless == 1
+    assert p.m2l_variant == -1  # chosen at plan creation
 
 
 @pytest.mark.parametrize("bad", [dict(order=0), dict(order=9), dict(theta=0.0), dict(theta=1.0),

@@ -153,6 +153,27 @@ def test_maximum_batch(ref):
     assert err.max() <= MIXED_BAR
 
 
+def test_default_m2l_variant_is_chosen_per_plan(ref):
+    """With no variant named, a plan gets the 64-column wide kernel where the
+    order, precision and form allow it (mixed, p <= 8 traceless, p <= 6 full
+    form) and the block kernel elsewhere (FP64), and the field is that of the
+    named variant."""
+    pos, box = inputs.ferrofluid(3000, 77)
+    m = inputs.random_moments(3000, 78)
+    cases = ((ccfmm.PREC_MIXED, 6, 1, 4), (ccfmm.PREC_MIXED, 8, 1, 4), (ccfmm.PREC_MIXED, 8, 0, 0),
+             (ccfmm.PREC_FP64, 6, 1, 0))
+    for prec, order, red, want in cases:
+        print("case default variant precision=%d order=%d traceless=%d" % (prec, order, red), flush=True)
+        pd = plan_for(pos, order, 0.5, 0.0, box, precision=prec, m2l_traceless=red)
+        assert pd.info()["m2l_variant"] == want
+        Hd = pd.eval(m)
+        pd.destroy()
+        pn = plan_for(pos, order, 0.5, 0.0, box, precision=prec, m2l_traceless=red, m2l_variant=want)
+        Hn = pn.eval(m)
+        pn.destroy()
+        assert rel_rms(Hd, Hn) <= 1e-14
+
+
 def test_edge_cases(ref):
     # one dipole: no field
     pl = plan_for(np.array([[0.3, 0.2, 0.1]]), 3, 0.5)
