@@ -56,6 +56,49 @@ def test_bruteforce_is_minus_grad_potential(ref):
         np.testing.assert_allclose(H[i], fd, rtol=1e-7, atol=1e-9)
 
 
+def test_energy_closed_form_pairs(ref):
+    """Energy of two dipoles (Sec. 3 with the Appendix's factor 1/2): the
+    interaction energy of a pair is counted once.  Coaxial parallel unit
+    dipoles at distance r: E = -2/r^3; coaxial antiparallel: +2/r^3; parallel
+    side by side (moments perpendicular to the separation): +1/r^3.  Dropping
+    the 1/2 doubles these and flipping the sign negates them."""
+    r = 1.7
+    z = np.array([0.0, 0.0, 1.0])
+    cases = [
+        (np.array([[0.0, 0, 0], [0, 0, r]]), np.array([z, z]), -2.0 / r**3),
+        (np.array([[0.0, 0, 0], [0, 0, r]]), np.array([z, -z]), 2.0 / r**3),
+        (np.array([[0.0, 0, 0], [r, 0, 0]]), np.array([z, z]), 1.0 / r**3),
+        (np.array([[0.0, 0, 0], [0, r, 0]]), np.array([z, z]), 1.0 / r**3),
+    ]
+    for pos, m, e in cases:
+        assert abs(ref.energy(m, ref.bruteforce(pos, m)) - e) <= 1e-14 * abs(e)
+    # the same from fields written by hand: on the axis each dipole sees
+    # 2m/r^3, beside each other -m/r^3
+    H_axis = np.array([2 * z / r**3, 2 * z / r**3])
+    assert abs(ref.energy(np.array([z, z]), H_axis) + 2.0 / r**3) <= 1e-15
+    H_side = np.array([-z / r**3, -z / r**3])
+    assert abs(ref.energy(np.array([z, z]), H_side) - 1.0 / r**3) <= 1e-15
+
+
+def test_energy_is_sum_of_pair_interactions(ref):
+    """Three (and more) dipoles: the energy equals the sum over unordered pairs
+    of the pair interaction energy (m_i.m_j - 3 (m_i.u)(m_j.u)) / r^3, a sum
+    that never forms a field."""
+    rng = np.random.default_rng(11)
+    for n in (3, 7):
+        pos = rng.random((n, 3)) * 4
+        m = rng.standard_normal((n, 3))
+        e_pairs = 0.0
+        for i in range(n):
+            for j in range(i + 1, n):
+                d = pos[i] - pos[j]
+                rr = float(np.sqrt(d @ d))
+                u = d / rr
+                e_pairs += (m[i] @ m[j] - 3.0 * (m[i] @ u) * (m[j] @ u)) / rr**3
+        e = ref.energy(m, ref.bruteforce(pos, m))
+        assert abs(e - e_pairs) <= 1e-12 * max(1.0, abs(e_pairs))
+
+
 def test_bruteforce_coincident_points_do_not_interact(ref):
     pos = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 0, 0]])
     m = np.array([[0, 0, 1.0], [0, 1.0, 0], [1.0, 0, 0]])
