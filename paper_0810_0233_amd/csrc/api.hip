@@ -1039,6 +1039,8 @@ int ccfmm_plan_select(ccfmm_plan plan, const float* d_params, double err_bound, 
     if (!d_params || !d_m || !(err_bound > 0.0) || !(cost_far >= 0.0)) fail(CCFMM_EINVAL, "invalid argument");
     Plan& P = plan->P;
     if (nbatch < 1 || nbatch > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
+    // the candidate orders are 2..6: a plan of order 1 has none
+    if (P.p < 2) fail(CCFMM_EINVAL, "learned selection needs a plan of order >= 2");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
     if (P.has_leaf) apply_leaf_params(P, nullptr, nullptr, st);

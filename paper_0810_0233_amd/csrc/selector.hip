@@ -333,7 +333,8 @@ __global__ void k_select(SelectArgs a, TreeGeom G, const float* __restrict__ pre
   }
   out_p[c] = best_p;
   out_theta[c] = kThetaSet[best_t];
-  atomicAdd(&hist[(best_p - 2) * 5 + best_t], 1);
+  // the histogram covers orders 2..6 (the caller refuses plans of order 1)
+  atomicAdd(&hist[(max(best_p, 2) - 2) * 5 + best_t], 1);
 }
 
 __global__ void k_diff_sums(int64_t count, const double* __restrict__ A, const double* __restrict__ B, double* part) {

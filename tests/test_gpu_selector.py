@@ -241,6 +241,12 @@ def test_select_extremes_and_fallback():
     assert pl.info()["fallback"] == 1
     assert np.array_equal(pl.eval(m), H_fixed)
     pl.destroy()
+    # a plan of order 1 has no candidate order (2..6): refused before any launch
+    p1 = plan_for(pos, 1, 0.4, box, precision=ccfmm.PREC_MIXED)
+    with pytest.raises(ccfmm.CCFMMError) as ei:
+        p1.select(dP.data_ptr(), 1e-2, 0.0, 0.0, 1, dm.data_ptr(), judge=False, stream=stream())
+    assert ei.value.status == ccfmm.EINVAL and "order >= 2" in str(ei.value)
+    p1.destroy()
 
 
 def test_trained_selector_beats_fixed_parameters():
