@@ -195,6 +195,21 @@ int ccfmm_energy(int64_t n, int32_t nbatch, const double* m, const double* H, do
  * calls on one plan must not overlap. */
 int ccfmm_plan_energy_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, const double* d_H, double* d_E,
                              void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy
+ * of ccfmm_plan_energy_device with no plan and no allocation.  d_m, d_H:
+ * device [nbatch][n][3] FP64 (caller-owned, any dipole order, the same in
+ * both); d_E: device [nbatch] FP64.  Runs on the calling thread's current
+ * device, ordered on stream; same kernels and summation order as
+ * ccfmm_plan_energy_device (bitwise the same result).  The partial sums live
+ * in a fixed library array of CCFMM_NOALLOC_MAX_BATCH x 256 doubles (8 MiB)
+ * that every GPU the library runs on holds until the process ends.  Errors:
+ * EINVAL for n < 1, NULL pointers or nbatch outside 1..CCFMM_NOALLOC_MAX_BATCH
+ * (checked before any device call).  Calls that overlap on one GPU share the
+ * array and race: order them on one stream. */
+#define CCFMM_NOALLOC_MAX_BATCH 4096
+int ccfmm_energy_device_noalloc(int64_t n, int32_t nbatch, const double* d_m, const double* d_H, double* d_E,
+                                void* stream);
 /* NULL-safe. */
 void ccfmm_plan_destroy(ccfmm_plan plan);
 

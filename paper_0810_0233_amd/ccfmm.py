@@ -63,8 +63,10 @@ EXPORTS = [
     "ccfmm_direct_targets_device", "ccfmm_selftest_mfma",
     "ccfmm_plan_set_leaf_params", "ccfmm_plan_get_leaf_params", "ccfmm_plan_leaf_ids", "ccfmm_plan_leaf_features",
     "ccfmm_plan_leaf_errors", "ccfmm_mlp_forward", "ccfmm_mlp_loss_grad", "ccfmm_mlp_adam", "ccfmm_plan_select",
+    "ccfmm_energy_device_noalloc",
 ]
 
+NOALLOC_MAX_BATCH = 4096
 MLP_IN, MLP_HIDDEN, MLP_OUT = 8, 64, 25
 MLP_PARAMS = 64 * 8 + 64 + 64 * 64 + 64 + 25 * 64 + 25
 SEL_P = (2, 3, 4, 5, 6)
@@ -122,6 +124,8 @@ def lib():
         L.ccfmm_direct_targets_device.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                                   C.c_void_p, C.c_void_p]
         L.ccfmm_selftest_mfma.argtypes = [C.c_int32]
+        L.ccfmm_energy_device_noalloc.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                  C.c_void_p]
         vp = C.c_void_p
         L.ccfmm_plan_set_leaf_params.argtypes = [vp, vp, vp, vp]
         L.ccfmm_plan_get_leaf_params.argtypes = [vp, vp, vp, C.POINTER(C.c_int32)]
@@ -305,6 +309,13 @@ def energy(m, H):
     E = np.zeros(nb)
     _check(lib().ccfmm_energy(n, nb, m.reshape(-1), H.reshape(-1), E))
     return E
+
+
+def energy_device_noalloc(n, nbatch, d_m, d_H, d_E, stream=0):
+    """Energy per configuration from device arrays with no allocation (fixed
+    library scratch); nbatch <= NOALLOC_MAX_BATCH."""
+    _check(lib().ccfmm_energy_device_noalloc(int(n), int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H),
+                                             C.c_void_p(d_E), C.c_void_p(stream)))
 
 
 def direct_targets_device(n, d_pos, d_m, nt, d_idx, d_H, stream=0):

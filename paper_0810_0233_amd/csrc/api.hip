@@ -1102,6 +1102,15 @@ int ccfmm_plan_energy_device(ccfmm_plan plan, int32_t nbatch, const double* d_m,
   });
 }
 
+int ccfmm_energy_device_noalloc(int64_t n, int32_t nbatch, const double* d_m, const double* d_H, double* d_E,
+                                void* stream) {
+  return guarded([&] {
+    if (n < 1 || !d_m || !d_H || !d_E) fail(CCFMM_EINVAL, "invalid argument");
+    run_energy_noalloc(n, nbatch, d_m, d_H, d_E, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
 int ccfmm_direct_targets_device(int64_t n, const double* d_pos, const double* d_m, int64_t nt, const int64_t* d_idx,
                                 double* d_H, void* stream) {
   return guarded([&] {

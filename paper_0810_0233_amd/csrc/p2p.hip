@@ -14,6 +14,7 @@
 // cell so all coordinates stay cell-relative) and padded with null sources
 // (zero moment, far away) that add exactly zero, so every lane runs the same
 // trip count; the next batch is loaded while the current one is summed.
+#include <mutex>
 #include <type_traits>
 
 #include "mfma.hpp"
@@ -1136,6 +1137,47 @@ __global__ void __launch_bounds__(256) k_energy_final(const double* __restrict__
 void run_energy(Plan& P, int nb, const double* d_m, const double* d_H, double* d_E, hipStream_t st) {
   double* part = reinterpret_cast<double*>(P.energy_part.ensure(sizeof(double) * (size_t)kEnergyBlocks * nb));
   k_energy_part<<<dim3(kEnergyBlocks, nb), 256, 0, st>>>(3 * P.n, d_m, d_H, part);
+  CCFMM_HIP(hipGetLastError());
+  k_energy_final<<<nb, 256, 0, st>>>(part, d_E);
+  CCFMM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ energy, no allocation
+// The same energy with its partial sums in a fixed device array instead of a
+// plan buffer, for callers that cannot allocate device memory (graph capture,
+// serving loops).  Every GPU the library runs on holds its own copy of the
+// array until the process ends.  Host code never passes the array's name to
+// a kernel (that is a host-side stand-in); it looks up the device address
+// once per device and passes that.  k_energy_part writes every slot that
+// k_energy_final reads, so nothing needs clearing; overlapping calls on one
+// GPU share the array and race.
+static __device__ __align__(256) double scratch[kEnergyBlocks * CCFMM_NOALLOC_MAX_BATCH];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array (looked up on first use)
+static double* scratch_for_current_device() {
+  int dev = -1;
+  CCFMM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(CCFMM_EINVAL, "device ordinal beyond the supported 64");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    CCFMM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(CCFMM_EHIP, "no device address for the energy scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<double*>(g_scratch_ptr[dev]);
+}
+
+void run_energy_noalloc(int64_t n, int nb, const double* d_m, const double* d_H, double* d_E, hipStream_t st) {
+  if (nb < 1 || nb > CCFMM_NOALLOC_MAX_BATCH)
+    fail(CCFMM_EINVAL, "nbatch must be in 1.." + std::to_string(CCFMM_NOALLOC_MAX_BATCH) +
+                           " (the fixed partial-sum array holds that many configurations)");
+  double* part = scratch_for_current_device();
+  k_energy_part<<<dim3(kEnergyBlocks, nb), 256, 0, st>>>(3 * n, d_m, d_H, part);
   CCFMM_HIP(hipGetLastError());
   k_energy_final<<<nb, 256, 0, st>>>(part, d_E);
   CCFMM_HIP(hipGetLastError());

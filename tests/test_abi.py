@@ -70,3 +70,12 @@ def test_energy_helper_matches_definition():
     H = rng.normal(size=(2, 10, 3))
     E = ccfmm.energy(m, H)
     np.testing.assert_allclose(E, -0.5 * np.sum(m * H, axis=(1, 2)), rtol=1e-14)
+
+
+def test_noalloc_energy_rejects_sizes_without_gpu():
+    # argument checks come before any device call
+    for n, nb in ((0, 1), (10, 0), (10, ccfmm.NOALLOC_MAX_BATCH + 1)):
+        with pytest.raises(ccfmm.CCFMMError) as e:
+            ccfmm.energy_device_noalloc(n, nb, 8, 8, 8)
+        assert e.value.status == ccfmm.EINVAL
+    assert "nbatch must be in 1..%d" % ccfmm.NOALLOC_MAX_BATCH in ccfmm.last_error()
