@@ -533,7 +533,7 @@ static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStre
     CCFMM_HIP(hipStreamWaitEvent(st, P.ev_join, 0));
     if (ev) CCFMM_HIP(hipEventRecord(ev[8], st));
     run_l2p(P, nb, d_H, st);
-  } else if (nb >= P.batched_min) {  // batched: two kernels, timed apart
+  } else if (nb >= 2) {  // several configurations: two kernels, timed apart
     if (ev) CCFMM_HIP(hipEventRecord(ev[6], st));
     run_near(P, nb, d_H, st);
     if (ev) {

@@ -440,6 +440,307 @@ __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 6 : 2) k_p2p_
   }
 }
 
+// ------------------------------------------------------------ a few configurations
+// Near field for 2..31 configurations on the vector units.  The geometry of a
+// pair -- separation, reciprocal distance, r^-2 and r^-3 -- is the same for
+// every configuration, so it is formed once and applied to KB configurations
+// held by the same lane: about 13 + 10 KB operations per pair instead of
+// 23 KB.  One wavefront per chunk of <= 64 target dipoles of one smallest
+// cell; the c targets get G = floor(64/c) lanes each (the lanes of a target
+// split the sources; a chunk of a full 32-dipole cell uses every lane), and
+// blockIdx.y runs over groups of KB configurations.  Sources are staged 64 at
+// a time in LDS with their moments for the group (zero for configurations
+// past the batch), packed from consecutive near cells and padded with null
+// sources as in k_p2p_l2p; the next batch is loaded while the current one is
+// summed.  FP32 partial fields of a batch are added into FP64 accumulators.
+
+// words of one staged source: position (x, y, z, unused), then m[KB][3],
+// rounded up to whole 16-byte LDS reads
+template <typename T, int KB>
+constexpr int p2pk_words() {
+  return ((4 + 3 * KB) * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
+}
+
+// a staged source in registers: whole 16-byte LDS reads (4 floats or 2
+// doubles each); element i of the record is v[i / W][i % W]
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int W = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int W = 2;
+};
+template <typename T, int KB>
+struct SrcRegs {
+  static constexpr int W = Vec16<T>::W;
+  static constexpr int NV = p2pk_words<T, KB>() / W;
+  typename Vec16<T>::type v[NV];
+  __device__ __forceinline__ T at(int i) const { return v[i / W][i % W]; }
+};
+template <typename T, int KB>
+__device__ __forceinline__ SrcRegs<T, KB> load_regs(const typename Vec16<T>::type* __restrict__ p) {
+  SrcRegs<T, KB> r;
+#pragma unroll
+  for (int i = 0; i < SrcRegs<T, KB>::NV; i++) r.v[i] = p[i];
+  return r;
+}
+
+// one source on one target for KB configurations; kSelf: the pair may be at
+// zero separation (target's own cell); kAcc: separations formed from the
+// FP32 residuals too (own and adjacent cells, where pairs can be close)
+template <typename T, int KB, bool kSelf, bool kAcc>
+__device__ __forceinline__ void p2pk_pair(const SrcRegs<T, KB>& q, const P2PLo<T>& lo, const P2PTgt<T>& t,
+                                          T (&f)[KB][3]) {
+  T rx = t.x - q.at(0), ry = t.y - q.at(1), rz = t.z - q.at(2);
+  if (kAcc) {
+    rx += t.lx - lo.x;
+    ry += t.ly - lo.y;
+    rz += t.lz - lo.z;
+  }
+  const T r2 = rx * rx + ry * ry + rz * rz;
+  T inv = rsqrt_t<T>(r2);
+  if (kSelf) inv = (r2 > (T)0) ? inv : (T)0;
+  const T inv2 = inv * inv;
+  const T inv3 = inv2 * inv;
+  const T c3 = (T)3 * inv2;
+#pragma unroll
+  for (int b = 0; b < KB; b++) {
+    const T mx = q.at(4 + 3 * b), my = q.at(5 + 3 * b), mz = q.at(6 + 3 * b);
+    const T k = c3 * (mx * rx + my * ry + mz * rz);
+    f[b][0] += inv3 * (k * rx - mx);
+    f[b][1] += inv3 * (k * ry - my);
+    f[b][2] += inv3 * (k * rz - mz);
+  }
+}
+
+// the slots sub, sub + G, ... (K >= 1 of them) of the staged batch; the
+// next slot's record is read while the current one is summed (the last
+// iteration re-reads its own slot rather than pass the batch)
+template <typename T, int KB, bool kSelf, bool kAcc>
+__device__ __forceinline__ void p2pk_run(const T* __restrict__ src, const P2PLo<T>* __restrict__ lo, int G,
+                                         int sub, int K, const P2PTgt<T>& t, T (&f)[KB][3]) {
+  using V = typename Vec16<T>::type;
+  constexpr int NV = SrcRegs<T, KB>::NV;
+  const V* q = reinterpret_cast<const V*>(src) + sub * NV;
+  const P2PLo<T>* ql = lo + sub;
+  const int step = G * NV;
+  SrcRegs<T, KB> cur = load_regs<T, KB>(q);
+  P2PLo<T> lcur{(T)0, (T)0, (T)0, (T)0};
+  if (kAcc) lcur = ql[0];
+  for (int k = 0; k < K; k++) {
+    const int kn = min(k + 1, K - 1);
+    const SrcRegs<T, KB> nxt = load_regs<T, KB>(q + kn * step);
+    P2PLo<T> lnxt{(T)0, (T)0, (T)0, (T)0};
+    if (kAcc) lnxt = ql[kn * G];
+    p2pk_pair<T, KB, kSelf, kAcc>(cur, lcur, t, f);
+    cur = nxt;
+    lcur = lnxt;
+  }
+}
+
+template <typename T, int KB>
+__global__ void __launch_bounds__(64 * kP2PWaves, 3) k_p2p_multi(P2PArgs a, const T* __restrict__ y,
+                                                                 const T* __restrict__ msort, double* __restrict__ H) {
+  constexpr int NW = p2pk_words<T, KB>();
+  constexpr int kSlots = 64 + kP2PPad;
+  __shared__ __attribute__((aligned(16))) T sS[kP2PWaves][kSlots * NW];
+  __shared__ P2PLo<T> sL[kP2PWaves][kSlots];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t blk = xcd_run_block(gridDim.x, blockIdx.x);
+  const int64_t item = blk * kP2PWaves + w;
+  if (item >= *a.nchunks) return;
+  const int cfg0 = blockIdx.y * KB;
+  const int ncfg = min(KB, a.nb - cfg0);  // configurations of this group inside the batch
+  const P2PChunk ch = a.chunks[item];
+  const int n = (int)a.n;
+  const int c = ch.count;
+  const int G = 64 / c;  // lanes per target
+  const int tt = lane / G, sub = lane % G;
+  const bool act = tt < c;
+  const int64_t it = ch.first + (act ? tt : 0);
+  constexpr bool kLo = std::is_same<T, float>::value;  // FP32 keeps residuals for close pairs
+  P2PTgt<T> tg{y[it], y[n + it], y[2 * n + it], (T)0, (T)0, (T)0};
+  if constexpr (kLo) {
+    tg.lx = (T)a.ylo[it];
+    tg.ly = (T)a.ylo[n + it];
+    tg.lz = (T)a.ylo[2 * n + it];
+  }
+  const int cx = a.coord[3 * ch.leaf], cy = a.coord[3 * ch.leaf + 1], cz = a.coord[3 * ch.leaf + 2];
+  T* src = sS[w];
+  P2PLo<T>* srclo = sL[w];
+  if (lane < kP2PPad) {  // null sources past the batch (read by strides that do not divide 64)
+    T* z = src + (64 + lane) * NW;
+    z[0] = z[1] = z[2] = (T)1e4;
+    for (int q = 3; q < NW; q++) z[q] = (T)0;
+    P2PLo<T> zl;
+    zl.x = zl.y = zl.z = zl.p = (T)0;
+    srclo[64 + lane] = zl;
+  }
+  const int e0 = a.near_ptr[ch.leaf], e1 = a.near_ptr[ch.leaf + 1];
+  // near-list metadata, 64 entries at a time (first dipole, count, own cell,
+  // adjacent cell, offset in cell-relative units), read back with readlane
+  int wb = e0;
+  int mstart = 0, mcnt = 0, mself = 0, madj = 0;
+  T mox = (T)0, moy = (T)0, moz = (T)0;
+  auto load_meta = [&](int base) {
+    const int e = base + lane;
+    mcnt = 0;
+    mself = 0;
+    madj = 0;
+    if (e < e1) {
+      const int S = a.near_idx[e];
+      mstart = a.lstart[S];
+      mcnt = a.lcount[S];
+      mself = S == ch.leaf;
+      madj = abs(a.coord[3 * S] - cx) <= 1 && abs(a.coord[3 * S + 1] - cy) <= 1 && abs(a.coord[3 * S + 2] - cz) <= 1;
+      mox = (T)((a.coord[3 * S] - cx) * a.g[0]);
+      moy = (T)((a.coord[3 * S + 1] - cy) * a.g[1]);
+      moz = (T)((a.coord[3 * S + 2] - cz) * a.g[2]);
+    }
+  };
+  load_meta(wb);
+  int e = e0, off = 0;
+  struct Batch {
+    int filled;
+    bool self, adj, valid;
+    int64_t j;
+    T ox, oy, oz;
+  };
+  auto next_batch = [&]() -> Batch {
+    Batch bt;
+    bt.filled = 0;
+    bt.self = bt.adj = bt.valid = false;
+    bt.j = 0;
+    bt.ox = bt.oy = bt.oz = (T)0;
+    while (bt.filled < 64 && e < e1) {
+      if (e - wb >= 64) {
+        wb = e;
+        load_meta(wb);
+      }
+      const int k = e - wb;
+      const int cnt = __builtin_amdgcn_readlane(mcnt, k);
+      const int st = __builtin_amdgcn_readlane(mstart, k);
+      const int take = min(64 - bt.filled, cnt - off);
+      if (lane >= bt.filled && lane < bt.filled + take) {
+        bt.valid = true;
+        bt.j = st + off + (lane - bt.filled);
+        bt.ox = __builtin_bit_cast(T, readlane_t(mox, k));
+        bt.oy = __builtin_bit_cast(T, readlane_t(moy, k));
+        bt.oz = __builtin_bit_cast(T, readlane_t(moz, k));
+      }
+      bt.self = bt.self || __builtin_amdgcn_readlane(mself, k);
+      bt.adj = bt.adj || __builtin_amdgcn_readlane(madj, k);
+      bt.filled += take;
+      off += take;
+      if (off == cnt) {
+        e++;
+        off = 0;
+      }
+    }
+    return bt;
+  };
+  // this lane's source of a batch: shifted position, its exact rounding
+  // error joined to the stored residual (adjacent batches only), moments
+  struct Src {
+    T v[4 + 3 * KB];
+    P2PLo<T> l;
+  };
+  auto load_src = [&](const Batch& bt) -> Src {
+    Src q;
+    q.l.x = q.l.y = q.l.z = q.l.p = (T)0;
+    q.v[3] = (T)0;
+    if (bt.valid) {
+      const int64_t j = bt.j;
+      const T hx = y[j], hy = y[n + j], hz = y[2 * n + j];
+      q.v[0] = hx + bt.ox;
+      q.v[1] = hy + bt.oy;
+      q.v[2] = hz + bt.oz;
+      if (kLo && bt.adj) {
+        q.l.x = (hx - (q.v[0] - bt.ox)) + (T)a.ylo[j];
+        q.l.y = (hy - (q.v[1] - bt.oy)) + (T)a.ylo[n + j];
+        q.l.z = (hz - (q.v[2] - bt.oz)) + (T)a.ylo[2 * n + j];
+      }
+#pragma unroll
+      for (int b = 0; b < KB; b++) {
+        const bool in = b < ncfg;
+        const T* mb = msort + (int64_t)(in ? cfg0 + b : 0) * 3 * n;
+        q.v[4 + 3 * b] = in ? mb[j] : (T)0;
+        q.v[5 + 3 * b] = in ? mb[n + j] : (T)0;
+        q.v[6 + 3 * b] = in ? mb[2 * n + j] : (T)0;
+      }
+    } else {  // null source: zero moments, far from every target
+      q.v[0] = q.v[1] = q.v[2] = (T)1e4;
+#pragma unroll
+      for (int b = 0; b < 3 * KB; b++) q.v[4 + b] = (T)0;
+    }
+    return q;
+  };
+  double h[KB][3];
+#pragma unroll
+  for (int b = 0; b < KB; b++) h[b][0] = h[b][1] = h[b][2] = 0.0;
+  Batch cur = next_batch();
+  Src qc = load_src(cur);
+  while (cur.filled > 0) {
+    T* slot = src + lane * NW;
+#pragma unroll
+    for (int q = 0; q < 4 + 3 * KB; q++) slot[q] = qc.v[q];
+    if (kLo && cur.adj) srclo[lane] = qc.l;
+    wave_lds_sync();
+    const Batch nxt = next_batch();
+    const Src qn = load_src(nxt);
+    const int K = (cur.filled + G - 1) / G;
+    T f[KB][3];
+#pragma unroll
+    for (int b = 0; b < KB; b++) f[b][0] = f[b][1] = f[b][2] = (T)0;
+    if (cur.self)
+      p2pk_run<T, KB, true, kLo>(src, srclo, G, sub, K, tg, f);
+    else if (kLo && cur.adj)
+      p2pk_run<T, KB, false, kLo>(src, srclo, G, sub, K, tg, f);
+    else
+      p2pk_run<T, KB, false, false>(src, srclo, G, sub, K, tg, f);
+    wave_lds_sync();
+#pragma unroll
+    for (int b = 0; b < KB; b++) {
+      h[b][0] += (double)f[b][0];
+      h[b][1] += (double)f[b][1];
+      h[b][2] += (double)f[b][2];
+    }
+    cur = nxt;
+    qc = qn;
+  }
+  // the G lanes of a target are contiguous (lane = t G + sub), G need not be
+  // a power of two: a segmented tree leaves each sum in the lane with sub = 0
+  for (int o = 1; o < G; o <<= 1) {
+#pragma unroll
+    for (int b = 0; b < KB; b++) {
+      const double ox = __shfl_down(h[b][0], o), oy = __shfl_down(h[b][1], o), oz = __shfl_down(h[b][2], o);
+      if (sub + o < G) {
+        h[b][0] += ox;
+        h[b][1] += oy;
+        h[b][2] += oz;
+      }
+    }
+  }
+  if (act && sub == 0) {
+    const double s3 = a.inv_s3;
+    const int64_t pi = a.perm[it];
+#pragma unroll
+    for (int b = 0; b < KB; b++) {
+      if (b < ncfg) {
+        double* o = H + ((int64_t)(cfg0 + b) * n + pi) * 3;
+        o[0] = s3 * h[b][0];
+        o[1] = s3 * h[b][1];
+        o[2] = s3 * h[b][2];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ batched form
 // Smooth field for many configurations: one thread per (dipole, configuration),
 // written (FP64, caller order) before the batched near field adds to it.
@@ -963,13 +1264,44 @@ static P2PArgs p2p_args(Plan& P, int nb, bool fp64) {
   return a;
 }
 
+// configurations per lane of the few-configuration near field: the group
+// size with the fewest vector operations, ceil(nb / KB) (13 + 10 KB) per
+// pair (FP64 stops at 4, its registers being twice as wide)
+static int multi_group(int nb, bool fp64) {
+  int best = 2;
+  double best_ops = 1e300;
+  for (int kb : {2, 4, 8}) {
+    if (fp64 && kb > 4) continue;
+    const double ops = (double)ceil_div(nb, kb) * (13.0 + 10.0 * kb);
+    if (ops < best_ops) {
+      best_ops = ops;
+      best = kb;
+    }
+  }
+  return best;
+}
+
+template <typename T, int KB>
+static void multi_launch(Plan& P, const P2PArgs& a, const T* y, int nb, double* d_H, hipStream_t st) {
+  dim3 grid(ceil_div(P.nchunks_cap, kP2PWaves), ceil_div(nb, KB));
+  k_p2p_multi<T, KB><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), d_H);
+}
+
 // near field alone: written (not added) to H in the caller's order
 template <typename T, int PP>
 static void near_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const bool fp64 = std::is_same<T, double>::value;
   const T* y = fp64 ? (const T*)P.yd.p : (const T*)P.yf.p;
   P2PArgs a = p2p_args(P, nb, fp64);
-  if (nb >= P.batched_min) {
+  if (nb >= 2 && nb < P.batched_min) {
+    const int kb = multi_group(nb, fp64);
+    if (kb == 2)
+      multi_launch<T, 2>(P, a, y, nb, d_H, st);
+    else if (kb == 4)
+      multi_launch<T, 4>(P, a, y, nb, d_H, st);
+    else if constexpr (!std::is_same<T, double>::value)
+      multi_launch<T, 8>(P, a, y, nb, d_H, st);
+  } else if (nb >= P.batched_min) {
     const int nl = P.lev[P.L]->ncells;
     const int32_t* n32 = P.chunk_cnt.as<int32_t>() + 3 * (nl + 1) + nl;  // off32[nl]
     dim3 grid((unsigned)P.nchunks32_cap, ceil_div(nb, 64));
@@ -999,7 +1331,7 @@ static void l2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
 // both in one pass (single stream, one configuration at a time)
 template <typename T, int PP>
 static void fused_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
-  if (nb >= P.batched_min) {
+  if (nb >= 2) {  // near field for several configurations, then the smooth field added
     near_impl<T, PP>(P, nb, d_H, st);
     l2p_impl<T, PP>(P, nb, d_H, st);
     return;
