@@ -42,6 +42,7 @@ extern "C" {
 #define CCFMM_EHIP (-3)       /* HIP runtime error (message in ccfmm_last_error) */
 #define CCFMM_ESTATE (-4)     /* call not valid in the plan's state */
 #define CCFMM_W_FALLBACK 1    /* learned selector rejected, fixed-parameter result returned */
+#define CCFMM_W_NOWEIGHTS 2   /* selector weights file missing: nothing loaded, fixed parameters kept */
 
 #define CCFMM_PREC_FP64 0     /* every pass in FP64 */
 #define CCFMM_PREC_MIXED 1    /* FP32 bulk arithmetic; FP64 derivative tensors and final sums */
@@ -58,10 +59,16 @@ typedef struct {
   int32_t leaf_rule;    /* 0: levels L = argmin_L |N/2^L - s| (Sec. 4);
                            1: same with N/2^L replaced by the mean over occupied cells */
   int32_t precision;    /* CCFMM_PREC_FP64 or CCFMM_PREC_MIXED */
-  int32_t selector;     /* must be 0 at plan creation: a plan starts with the fixed (order,
-                           theta); learned per-cell parameters are applied afterwards with
-                           ccfmm_plan_select (which takes the weights and the error bound) */
-  double err_bound;     /* reserved (the bound is an argument of ccfmm_plan_select) */
+  int32_t selector;     /* 0: fixed (order, theta) everywhere.  1: learned per smallest cell:
+                           once the plan holds selector weights (ccfmm_selector_load / _set),
+                           the first evaluation after the plan is built, or after a position
+                           update that changed the occupied cells, chooses (p, theta) per cell
+                           from that call's moments, has the fixed-parameter FMM judge the
+                           choice against err_bound and keeps it, or falls back to the fixed
+                           parameters (that call returns CCFMM_W_FALLBACK).  Needs order >= 2.
+                           Without weights the plan evaluates with the fixed parameters. */
+  double err_bound;     /* selector = 1: bound on the relative RMS difference between the
+                           learned and the fixed-parameter field (e.g. 1e-5), > 0 */
   int32_t has_box;      /* 1: root cell is [box_lo, box_hi]; 0: tight bounding box */
   double box_lo[3], box_hi[3];
   int32_t max_batch;    /* largest nbatch the plan will evaluate (device buffers sized) */
@@ -92,6 +99,11 @@ typedef struct {
                              moments over their 2l+1 components per degree and fill the rest of
                              V from the Laplace equation (D and V are harmonic; the same sums,
                              rounded differently); 0: the full 83 x 84 operator at p = 6 */
+  double sel_margin;      /* selector = 1: a cell takes the cheapest (p, theta) whose predicted
+                             log10 error is <= log10(err_bound) - sel_margin (default 0.3, >= 0) */
+  double sel_cost_far;    /* selector = 1: cost of one far cell relative to one direct dipole
+                             pair in the selection; <= 0 (default): measured on the plan (M2L and
+                             near-field times of one evaluation, each pass alone) */
 } ccfmm_params;
 
 /* One timed M2L configuration of ccfmm_plan_autotune. */
@@ -124,6 +136,9 @@ typedef struct {
   int64_t n_rebuilds_kept;              /* position updates that kept the cell lists, M2L tiles and the
                                            captured evaluation's structure: same geometry and the same
                                            occupied cells at every level (only the dipoles moved) */
+  int32_t learned;                      /* per-cell parameters of the learned selector in use */
+  double judge_err;                     /* the judge's relative RMS difference at the last selection */
+  double sel_cost_far;                  /* far-cell cost used at the last selection */
 } ccfmm_info;
 
 /* Per-pass device times (milliseconds) of one evaluation, from HIP events.
@@ -237,6 +252,7 @@ typedef struct {
   int32_t hist[CCFMM_MLP_OUT];  /* cells per chosen (p, theta), index as the network output */
   double judge_err;             /* relative RMS of the learned vs the fixed-parameter field */
   int32_t fallback;             /* 1: learned choice rejected, plan back on fixed parameters */
+  double pred_err;              /* the network's prediction of the chosen field's relative RMS error */
 } ccfmm_select_info;
 
 /* Set (d_p, d_theta: device arrays of n_leaves int32 / FP64, compact leaf
@@ -265,15 +281,77 @@ int ccfmm_mlp_loss_grad(const float* d_params, int64_t rows, const float* d_x, c
 /* One Adam step (beta 0.9 / 0.999, bias-corrected; step counts from 1). */
 int ccfmm_mlp_adam(float* d_params, const float* d_grad, float* d_m1, float* d_m2, int32_t step, float lr,
                    void* stream);
-/* Learned selection: features of the current moments -> network -> for every
- * cell the cheapest (p, theta) whose predicted log10 error is at most
- * log10(err_bound) - margin (cost = own dipoles x near source dipoles +
- * cost_far x far cells), then set as the plan's per-cell parameters.  With
- * judge != 0 the learned field of these moments is compared with the
- * fixed-parameter field; above err_bound the plan returns to fixed parameters
- * and the call returns CCFMM_W_FALLBACK.  Synchronises the stream. */
+/* Learned selection on the current moments: the fixed-parameter field gives
+ * each cell's squared field F_c; features -> network -> predicted log10
+ * relative error y_c(p, theta) per cell and candidate; the choice minimises
+ * the total cost (own dipoles x near source dipoles + cost_far x far cells +
+ * the smooth field's work at order p, per cell) subject to the predicted
+ * global relative RMS error sqrt(sum F_c 10^(2 y_c) / sum F_c) being at most
+ * err_bound x 10^-margin (Lagrange multiplier found by bisection), and is set
+ * as the plan's per-cell parameters.  With judge != 0 the learned field of
+ * these moments is compared with the fixed-parameter field; above err_bound
+ * the plan returns to fixed parameters and the call returns
+ * CCFMM_W_FALLBACK.  Synchronises the stream. */
 int ccfmm_plan_select(ccfmm_plan plan, const float* d_params, double err_bound, double margin, double cost_far,
                       int32_t nbatch, const double* d_m, int32_t judge, void* stream, ccfmm_select_info* out);
+
+/* Selector weights files.  Format (little-endian): "CCFMMSEL", uint32
+ * version (1), uint32 inputs, hidden width, outputs, parameter count
+ * (8, 64, 25, CCFMM_MLP_PARAMS), uint32 lowest and highest candidate order
+ * (2, 6), FP64 candidate angles [5] (0.3 .. 0.7), FP32 parameters (packed as
+ * for ccfmm_mlp_forward), uint64 FNV-1a hash of all preceding bytes.
+ * Reading checks every field: a mismatch (other network shape, candidate
+ * set or version, truncated or altered file) is CCFMM_EINVAL; a file that
+ * does not exist gives the warning CCFMM_W_NOWEIGHTS and leaves h_params or
+ * the plan unchanged (the plan keeps its fixed parameters). */
+int ccfmm_selector_write(const char* path, const float* h_params);  /* h_params: host [CCFMM_MLP_PARAMS] */
+int ccfmm_selector_read(const char* path, float* h_params);
+/* The plan's selector weights (device copy owned by the plan): from a file,
+ * from device memory d_params [CCFMM_MLP_PARAMS] (stream-ordered), or to a
+ * file (ESTATE if the plan holds none).  Loading or setting weights makes the
+ * next evaluation of a selector = 1 plan choose the per-cell parameters anew. */
+int ccfmm_selector_load(ccfmm_plan plan, const char* path);
+int ccfmm_selector_set(ccfmm_plan plan, const float* d_params, void* stream);
+int ccfmm_selector_save(ccfmm_plan plan, const char* path);
+
+/* Training of the selector network on the GPU (the precursor is the
+ * parameter study of Sec. 4: error estimate and timings per (p, alpha)).
+ * Labels: for each geometry, every candidate (p, theta) in {2..6} x
+ * {0.3..0.7} is applied to all smallest cells, the FMM (fixed order and angle
+ * above the smallest cells) is evaluated, and each labelled cell gets log10 of
+ * its relative RMS field error against the FP64 direct sum at its dipoles
+ * (computed on the GPU).  Features: those of ccfmm_plan_leaf_features.  Then
+ * `steps` full-batch Adam steps on the masked squared error from seeded
+ * He-normal weights.  All arithmetic runs in the library's kernels; the host
+ * only sequences them.  The weights go to out_path (a weights file, if not
+ * NULL) and to h_params_out (host [CCFMM_MLP_PARAMS], if not NULL). */
+typedef struct {
+  int64_t n;             /* dipoles */
+  const double* pos;     /* host [n][3] positions */
+  const double* m;       /* host [n][3] moments (one configuration) */
+  int32_t has_box;       /* 1: root cell [box_lo, box_hi]; 0: the tight bounding box */
+  double box_lo[3], box_hi[3];
+} ccfmm_train_geometry;
+typedef struct {
+  int32_t device;
+  int32_t n_geom;
+  const ccfmm_train_geometry* geom;
+  int32_t order;         /* fixed order above the smallest cells, 2..CCFMM_PMAX */
+  double theta;          /* fixed opening angle above the smallest cells */
+  double leaf_target;    /* s (<= 0: Eq. so) */
+  int32_t precision;     /* precision of the labelling evaluations */
+  int32_t sample_cells;  /* smallest cells labelled per geometry (<= 0: all of them) */
+  int32_t steps;         /* Adam steps, >= 1 */
+  float lr;              /* Adam step size, > 0 */
+  uint64_t seed;         /* initial weights and cell sample */
+} ccfmm_train_spec;
+typedef struct {
+  int64_t rows;          /* labelled cells over all geometries */
+  float loss_first, loss_last;  /* masked loss at the first and the last step */
+  double label_seconds, train_seconds;
+} ccfmm_train_info;
+int ccfmm_selector_train(const ccfmm_train_spec* spec, const char* out_path, float* h_params_out,
+                         ccfmm_train_info* info);
 
 /* Direct O(N^2) FP64 field on the GPU at nt sampled targets (error reference at
  * scale): d_pos [n][3], d_m [n][3], d_idx [nt] int64, d_H [nt][3]; stream-ordered. */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libccfmm.so")
 
 PMAX = 8
 LMAX = 24
-OK, EINVAL, ENOMEM, EHIP, ESTATE, W_FALLBACK = 0, -1, -2, -3, -4, 1
+OK, EINVAL, ENOMEM, EHIP, ESTATE, W_FALLBACK, W_NOWEIGHTS = 0, -1, -2, -3, -4, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -29,7 +29,8 @@ class ccfmm_params(C.Structure):
                 ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
                 ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32), ("m2l_variant", C.c_int32),
                 ("use_graph", C.c_int32), ("overlap_near", C.c_int32), ("keep_lists", C.c_int32),
-                ("truncation", C.c_int32), ("m2l_traceless", C.c_int32)]
+                ("truncation", C.c_int32), ("m2l_traceless", C.c_int32),
+                ("sel_margin", C.c_double), ("sel_cost_far", C.c_double)]
 
 
 class ccfmm_tune_entry(C.Structure):
@@ -47,7 +48,25 @@ class ccfmm_info(C.Structure):
                 ("n_m2l_tiles", C.c_int64), ("n_m2l_steps", C.c_int64), ("n_delta", C.c_int64),
                 ("m2l_class_bits", C.c_int32), ("fallback", C.c_int32),
                 ("m2l_flops_per_config", C.c_double), ("p2p_pairs_per_config", C.c_double),
-                ("m2l_variant", C.c_int32), ("n_rebuilds_kept", C.c_int64)]
+                ("m2l_variant", C.c_int32), ("n_rebuilds_kept", C.c_int64),
+                ("learned", C.c_int32), ("judge_err", C.c_double), ("sel_cost_far", C.c_double)]
+
+
+class ccfmm_train_geometry(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.c_void_p), ("m", C.c_void_p), ("has_box", C.c_int32),
+                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
+
+
+class ccfmm_train_spec(C.Structure):
+    _fields_ = [("device", C.c_int32), ("n_geom", C.c_int32), ("geom", C.POINTER(ccfmm_train_geometry)),
+                ("order", C.c_int32), ("theta", C.c_double), ("leaf_target", C.c_double),
+                ("precision", C.c_int32), ("sample_cells", C.c_int32), ("steps", C.c_int32),
+                ("lr", C.c_float), ("seed", C.c_uint64)]
+
+
+class ccfmm_train_info(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("loss_first", C.c_float), ("loss_last", C.c_float),
+                ("label_seconds", C.c_double), ("train_seconds", C.c_double)]
 
 
 class ccfmm_pass_times(C.Structure):
@@ -63,7 +82,8 @@ EXPORTS = [
     "ccfmm_direct_targets_device", "ccfmm_selftest_mfma",
     "ccfmm_plan_set_leaf_params", "ccfmm_plan_get_leaf_params", "ccfmm_plan_leaf_ids", "ccfmm_plan_leaf_features",
     "ccfmm_plan_leaf_errors", "ccfmm_mlp_forward", "ccfmm_mlp_loss_grad", "ccfmm_mlp_adam", "ccfmm_plan_select",
-    "ccfmm_energy_device_noalloc",
+    "ccfmm_energy_device_noalloc", "ccfmm_selector_write", "ccfmm_selector_read", "ccfmm_selector_load",
+    "ccfmm_selector_set", "ccfmm_selector_save", "ccfmm_selector_train",
 ]
 
 NOALLOC_MAX_BATCH = 4096
@@ -75,7 +95,7 @@ SEL_THETA = (0.3, 0.4, 0.5, 0.6, 0.7)
 
 class ccfmm_select_info(C.Structure):
     _fields_ = [("n_leaves", C.c_int32), ("hist", C.c_int32 * MLP_OUT), ("judge_err", C.c_double),
-                ("fallback", C.c_int32)]
+                ("fallback", C.c_int32), ("pred_err", C.c_double)]
 
 _lib = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -127,6 +147,13 @@ def lib():
         L.ccfmm_energy_device_noalloc.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                                   C.c_void_p]
         vp = C.c_void_p
+        L.ccfmm_selector_write.argtypes = [C.c_char_p, vp]
+        L.ccfmm_selector_read.argtypes = [C.c_char_p, vp]
+        L.ccfmm_selector_load.argtypes = [vp, C.c_char_p]
+        L.ccfmm_selector_set.argtypes = [vp, vp, vp]
+        L.ccfmm_selector_save.argtypes = [vp, C.c_char_p]
+        L.ccfmm_selector_train.argtypes = [C.POINTER(ccfmm_train_spec), C.c_char_p, vp,
+                                           C.POINTER(ccfmm_train_info)]
         L.ccfmm_plan_set_leaf_params.argtypes = [vp, vp, vp, vp]
         L.ccfmm_plan_get_leaf_params.argtypes = [vp, vp, vp, C.POINTER(C.c_int32)]
         L.ccfmm_plan_leaf_ids.argtypes = [vp, vp, vp]
@@ -157,7 +184,7 @@ def _check(rc):
 
 def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64, selector=0,
            err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=-1, use_graph=1, overlap_near=1,
-           keep_lists=1, truncation=0, m2l_traceless=1):
+           keep_lists=1, truncation=0, m2l_traceless=1, sel_margin=0.3, sel_cost_far=0.0):
     p = ccfmm_params()
     _check(lib().ccfmm_params_default(C.byref(p)))
     p.order = int(order)
@@ -180,6 +207,8 @@ def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64
     p.keep_lists = int(keep_lists)
     p.truncation = int(truncation)
     p.m2l_traceless = int(m2l_traceless)
+    p.sel_margin = float(sel_margin)
+    p.sel_cost_far = float(sel_cost_far)
     return p
 
 
@@ -224,11 +253,24 @@ class Plan:
         shape = m.shape
         m3 = m.reshape(-1, self.info()["n"], 3)
         H = np.empty_like(m3)
-        _check(lib().ccfmm_eval(self.h, m3.shape[0], m3, H))
+        self.last_status = _check(lib().ccfmm_eval(self.h, m3.shape[0], m3, H))
         return H.reshape(shape)
 
     def eval_device(self, nbatch, d_m, d_H, stream=0):
-        _check(lib().ccfmm_eval_device(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H), C.c_void_p(stream)))
+        """Returns the status (OK, or W_FALLBACK when a learned plan's choice was rejected)."""
+        self.last_status = _check(lib().ccfmm_eval_device(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H),
+                                                          C.c_void_p(stream)))
+        return self.last_status
+
+    def selector_load(self, path):
+        """Weights from a file; returns OK or W_NOWEIGHTS (file missing: fixed parameters kept)."""
+        return _check(lib().ccfmm_selector_load(self.h, os.fsencode(path)))
+
+    def selector_set(self, d_params, stream=0):
+        _check(lib().ccfmm_selector_set(self.h, C.c_void_p(d_params), C.c_void_p(stream)))
+
+    def selector_save(self, path):
+        _check(lib().ccfmm_selector_save(self.h, os.fsencode(path)))
 
     def energy_device(self, nbatch, d_m, d_H, d_E, stream=0):
         """E_b = -1/2 sum_i m_i . H_i on the GPU into d_E [nbatch] (FP64)."""
@@ -282,7 +324,7 @@ class Plan:
                                             float(cost_far), int(nbatch), C.c_void_p(d_m), int(bool(judge)),
                                             C.c_void_p(stream), C.byref(out)))
         return rc, {"n_leaves": out.n_leaves, "hist": list(out.hist), "judge_err": out.judge_err,
-                    "fallback": out.fallback}
+                    "fallback": out.fallback, "pred_err": out.pred_err}
 
     def info(self):
         inf = ccfmm_info()
@@ -309,6 +351,50 @@ def energy(m, H):
     E = np.zeros(nb)
     _check(lib().ccfmm_energy(n, nb, m.reshape(-1), H.reshape(-1), E))
     return E
+
+
+def selector_write(path, params):
+    P = np.ascontiguousarray(params, dtype=np.float32)
+    if P.size != MLP_PARAMS:
+        raise ValueError("expected %d parameters" % MLP_PARAMS)
+    _check(lib().ccfmm_selector_write(os.fsencode(path), P.ctypes.data_as(C.c_void_p)))
+
+
+def selector_read(path):
+    """Weights from a file, or None if the file does not exist."""
+    P = np.zeros(MLP_PARAMS, dtype=np.float32)
+    rc = _check(lib().ccfmm_selector_read(os.fsencode(path), P.ctypes.data_as(C.c_void_p)))
+    return None if rc == W_NOWEIGHTS else P
+
+
+def selector_train(geoms, order=6, theta=0.4, leaf_target=0.0, precision=PREC_MIXED, sample_cells=0, steps=600,
+                   lr=3e-3, seed=1, out_path=None, device=0):
+    """GPU training of the selector network (labels, features and Adam in the
+    library).  geoms: list of dicts with pos [n][3], m [n][3] and box (or
+    None).  Returns (params, info dict)."""
+    keep = []
+    G = (ccfmm_train_geometry * len(geoms))()
+    for i, g in enumerate(geoms):
+        pos = np.ascontiguousarray(g["pos"], dtype=np.float64).reshape(-1, 3)
+        m = np.ascontiguousarray(g["m"], dtype=np.float64).reshape(-1, 3)
+        keep += [pos, m]
+        G[i].n = pos.shape[0]
+        G[i].pos = pos.ctypes.data
+        G[i].m = m.ctypes.data
+        box = g.get("box")
+        if box is not None:
+            G[i].has_box = 1
+            for a in range(3):
+                G[i].box_lo[a] = float(box[0][a])
+                G[i].box_hi[a] = float(box[1][a])
+    sp = ccfmm_train_spec(device=device, n_geom=len(geoms), geom=G, order=order, theta=theta,
+                          leaf_target=leaf_target, precision=precision, sample_cells=sample_cells, steps=steps,
+                          lr=lr, seed=seed)
+    P = np.zeros(MLP_PARAMS, dtype=np.float32)
+    inf = ccfmm_train_info()
+    _check(lib().ccfmm_selector_train(C.byref(sp), None if out_path is None else os.fsencode(out_path),
+                                      P.ctypes.data_as(C.c_void_p), C.byref(inf)))
+    return P, {f: getattr(inf, f) for f, _ in ccfmm_train_info._fields_}
 
 
 def energy_device_noalloc(n, nbatch, d_m, d_H, d_E, stream=0):

@@ -353,8 +353,15 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
   if (prm->leaf_rule != 0 && prm->leaf_rule != 1) fail(CCFMM_EINVAL, "leaf_rule must be 0 or 1");
   if (prm->precision != CCFMM_PREC_FP64 && prm->precision != CCFMM_PREC_MIXED)
     fail(CCFMM_EINVAL, "precision must be FP64 or MIXED");
-  if (prm->selector != 0)
-    fail(CCFMM_EINVAL, "selector must be 0 at plan creation (apply learned parameters with ccfmm_plan_select)");
+  if (prm->selector != 0 && prm->selector != 1) fail(CCFMM_EINVAL, "selector must be 0 or 1");
+  if (prm->selector == 1) {
+    if (prm->order < 2) fail(CCFMM_EINVAL, "the learned selector needs order >= 2 (candidate orders 2..6)");
+    if (!(prm->err_bound > 0.0) || !std::isfinite(prm->err_bound))
+      fail(CCFMM_EINVAL, "err_bound must be finite and > 0 with the selector");
+    if (!(prm->sel_margin >= 0.0) || !std::isfinite(prm->sel_margin))
+      fail(CCFMM_EINVAL, "sel_margin must be finite and >= 0");
+    if (!std::isfinite(prm->sel_cost_far)) fail(CCFMM_EINVAL, "sel_cost_far not finite");
+  }
   if (prm->max_batch < 1 || prm->max_batch > 4096) fail(CCFMM_EINVAL, "max_batch must be in 1..4096");
   if (prm->truncation != 0 && prm->truncation != 1) fail(CCFMM_EINVAL, "truncation must be 0 or 1");
   if (prm->m2l_traceless != 0 && prm->m2l_traceless != 1) fail(CCFMM_EINVAL, "m2l_traceless must be 0 or 1");
@@ -371,9 +378,10 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
 // reads was reallocated and its launch sizes stand.  This is the usual case
 // of a time step in a dense system (dipoles move, cells stay occupied).
 static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_built = false) {
-  // the current lists were built for the fixed (order, theta)
-  const bool prev_fixed = was_built && !P.has_leaf && P.prm.keep_lists != 0;
-  P.has_leaf = false;  // per-cell parameters belong to the previous cells
+  // the current lists (fixed, or with per-cell parameters) can be kept if the
+  // cells stay: per-cell parameters are in compact leaf order, which the same
+  // occupied cells leave unchanged
+  const bool prev_kept_ok = was_built && P.prm.keep_lists != 0;
   const TreeGeom geo0 = P.geo;
   const int L0 = P.L;
   const uint64_t allocs0 = devbuf_allocs();
@@ -400,7 +408,7 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
     if (bad) fail(CCFMM_EINVAL, "non-finite position");
   }
   setup_geometry(P, mn, mx, d_pos, st);
-  const bool same_geo = prev_fixed && P.L == L0 && std::memcmp(&geo0, &P.geo, sizeof(TreeGeom)) == 0;
+  const bool same_geo = prev_kept_ok && P.L == L0 && std::memcmp(&geo0, &P.geo, sizeof(TreeGeom)) == 0;
   const int64_t n = P.n;
   P.key.ensure(sizeof(uint32_t) * n);
   P.val.ensure(sizeof(int32_t) * n);
@@ -433,6 +441,12 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
     P.built = P.ever_built = true;
     return;
   }
+  // new cells: per-cell parameters belong to the previous ones; a learned
+  // plan chooses again at its next evaluation
+  P.has_leaf = false;
+  P.h_leaf_p.clear();
+  P.h_leaf_theta.clear();
+  P.sel_stale = true;
   P.drop_graph();
   build_lists(P, st);
   build_dtensors(P, st);
@@ -440,6 +454,7 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
   build_m2l_tiles(P, P.nbmax, st);
   P.qv_batch = 0;
   fill_info(P, st);
+  P.info.learned = 0;
   P.built = P.ever_built = true;
 }
 
@@ -464,11 +479,17 @@ static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStre
 // One evaluation.  With graphs on (and a capturable stream), the pass sequence
 // is captured once per (nbatch, moments, fields) and replayed; the capture
 // holds kernel launches only.
-static void eval_run(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st) {
+int auto_select(Plan& P, int nb, const double* d_m, hipStream_t st);
+
+// Returns CCFMM_OK, or CCFMM_W_FALLBACK when this call made the learned choice
+// and the judge rejected it.
+static int eval_run(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st) {
+  if (nb < 1 || nb > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
+  const int rc = auto_select(P, nb, d_m, st);
   prepare_batch(P, nb, st);
   if (!P.use_graph || st == nullptr) {
     eval_passes(P, nb, d_m, d_H, st, nullptr);
-    return;
+    return rc;
   }
   if (!P.gexec || P.g_nb != nb || P.g_m != d_m || P.g_H != d_H) {
     P.drop_graph();
@@ -492,6 +513,7 @@ static void eval_run(Plan& P, int nb, const double* d_m, double* d_H, hipStream_
     P.g_H = d_H;
   }
   CCFMM_HIP(hipGraphLaunch(P.gexec, st));
+  return rc;
 }
 
 static void ensure_side_stream(Plan& P) {
@@ -552,6 +574,12 @@ static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStre
   if (ev) CCFMM_HIP(hipEventRecord(ev[5], st));
 }
 
+// one evaluation, plain stream launches (no capture, no learned choice)
+void eval_once(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st) {
+  prepare_batch(P, nb, st);
+  eval_passes(P, nb, d_m, d_H, st, nullptr);
+}
+
 template <typename F>
 static int guarded(F&& f) {
   try {
@@ -576,10 +604,6 @@ static int guarded(F&& f) {
 
 using namespace ccfmm;
 
-struct ccfmm_plan_s {
-  Plan P;
-};
-
 extern "C" {
 
 const char* ccfmm_status_string(int status) {
@@ -590,6 +614,7 @@ const char* ccfmm_status_string(int status) {
     case CCFMM_EHIP: return "HIP runtime error";
     case CCFMM_ESTATE: return "invalid plan state";
     case CCFMM_W_FALLBACK: return "learned selector fell back to fixed parameters";
+    case CCFMM_W_NOWEIGHTS: return "selector weights file missing, fixed parameters kept";
     default: return "unknown status";
   }
 }
@@ -606,6 +631,8 @@ int ccfmm_params_default(ccfmm_params* prm) {
   prm->precision = CCFMM_PREC_FP64;
   prm->selector = 0;
   prm->err_bound = 1e-5;
+  prm->sel_margin = 0.3;
+  prm->sel_cost_far = 0.0;
   prm->overlap_near = 1;
   prm->keep_lists = 1;
   prm->truncation = 0;
@@ -707,8 +734,7 @@ int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double
     Plan& P = plan->P;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
-    eval_run(P, nbatch, d_m, d_H, st);
-    return CCFMM_OK;
+    return eval_run(P, nbatch, d_m, d_H, st);
   });
 }
 
@@ -720,6 +746,8 @@ int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, 
     Plan& P = plan->P;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
+    if (nbatch < 1 || nbatch > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
+    const int rc = auto_select(P, nbatch, d_m, st);
     prepare_batch(P, nbatch, st);
     hipEvent_t ev[9];
     for (int i = 0; i < 9; i++) CCFMM_HIP(hipEventCreate(&ev[i]));
@@ -749,7 +777,7 @@ int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, 
     times->p2p = near;
     times->l2p = l2p;
     times->total = tot;
-    return CCFMM_OK;
+    return rc;
   });
 }
 
@@ -771,10 +799,10 @@ int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H) {
     P.host_m.ensure(cap);
     P.host_H.ensure(cap);
     CCFMM_HIP(hipMemcpyAsync(P.host_m.p, m, bytes, hipMemcpyHostToDevice, st));
-    eval_run(P, nbatch, P.host_m.as<double>(), P.host_H.as<double>(), st);
+    const int rc = eval_run(P, nbatch, P.host_m.as<double>(), P.host_H.as<double>(), st);
     CCFMM_HIP(hipMemcpyAsync(H, P.host_H.p, bytes, hipMemcpyDeviceToHost, st));
     CCFMM_HIP(hipStreamSynchronize(st));
-    return CCFMM_OK;
+    return rc;
   });
 }
 
@@ -893,7 +921,7 @@ void ccfmm_plan_destroy(ccfmm_plan plan) {
 namespace ccfmm {
 // Install (or clear) per-cell parameters given on the host and rebuild every
 // list, tile and count that depends on them (the tree is unchanged).
-static void apply_leaf_params(Plan& P, const int32_t* hp, const double* hth, hipStream_t st) {
+void apply_leaf_params(Plan& P, const int32_t* hp, const double* hth, hipStream_t st) {
   const int nl = P.lev[P.L]->ncells;
   if (hp && hth) {
     std::vector<double> th2(nl);
@@ -923,6 +951,124 @@ static void apply_leaf_params(Plan& P, const int32_t* hp, const double* hth, hip
   build_dtensors(P, st);
   build_m2l_tiles(P, P.tiles_nb, st);
   fill_info(P, st);
+}
+
+// The learned choice: features of these moments -> network -> per cell the
+// cheapest (p, theta) predicted to meet the bound.  With judge, the fixed-
+// parameter field and the learned field of these moments are compared; above
+// the bound the plan returns to the fixed parameters (CCFMM_W_FALLBACK).
+// The learned choice on these moments: the fixed-parameter field gives each
+// cell's squared field F_c; features -> network -> per-cell (p, theta) with
+// the least cost whose predicted global relative RMS error is within
+// err_bound x 10^-margin.  With judge, the learned field is compared with the
+// fixed one; above the bound the plan returns to the fixed parameters
+// (CCFMM_W_FALLBACK).
+int select_impl(Plan& P, const float* d_params, double err_bound, double margin, double cost_far, int nbatch,
+                const double* d_m, bool judge, hipStream_t st, ccfmm_select_info* out) {
+  if (P.has_leaf) apply_leaf_params(P, nullptr, nullptr, st);
+  const int nl = P.lev[P.L]->ncells;
+  const size_t bytes = sizeof(double) * 3 * (size_t)P.n * nbatch;
+  double* Hf = reinterpret_cast<double*>(P.judge_a.ensure(bytes));
+  prepare_batch(P, nbatch, st);
+  eval_passes(P, nbatch, d_m, Hf, st, nullptr);
+  DevBuf dp, dt, dnum, dF;
+  dp.ensure(sizeof(int32_t) * nl);
+  dt.ensure(sizeof(double) * nl);
+  dnum.ensure(sizeof(double) * nl);
+  dF.ensure(sizeof(double) * nl);
+  run_leaf_errors(P, nbatch, Hf, Hf, dnum.as<double>(), dF.as<double>(), st);
+  std::vector<int32_t> hist;
+  double pred_err = 0.0;
+  run_select(P, d_params, std::log10(err_bound) - margin, cost_far, nbatch, d_m, dF.as<double>(), dp.as<int32_t>(),
+             dt.as<double>(), hist, &pred_err, st);
+  std::vector<int32_t> hp(nl);
+  std::vector<double> ht(nl);
+  CCFMM_HIP(hipMemcpyAsync(hp.data(), dp.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipMemcpyAsync(ht.data(), dt.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  apply_leaf_params(P, hp.data(), ht.data(), st);
+  int rc = CCFMM_OK;
+  double jerr = 0.0;
+  int fb = 0;
+  if (judge) {
+    double* Hl = reinterpret_cast<double*>(P.judge_b.ensure(bytes));
+    prepare_batch(P, nbatch, st);
+    eval_passes(P, nbatch, d_m, Hl, st, nullptr);
+    jerr = run_rel_rms(Hl, Hf, (int64_t)3 * P.n * nbatch, P.scratch, st);
+    if (!(jerr <= err_bound)) {
+      apply_leaf_params(P, nullptr, nullptr, st);
+      fb = 1;
+      rc = CCFMM_W_FALLBACK;
+    }
+  }
+  P.info.fallback = fb;
+  P.info.learned = fb ? 0 : 1;
+  P.info.judge_err = jerr;
+  P.info.sel_cost_far = cost_far;
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->n_leaves = nl;
+    for (int i = 0; i < CCFMM_MLP_OUT && i < (int)hist.size(); i++) out->hist[i] = hist[i];
+    out->judge_err = jerr;
+    out->fallback = fb;
+    out->pred_err = pred_err;
+  }
+  return rc;
+}
+
+// direct pairs of the current lists, if the last update left them uncounted
+static void refresh_pair_count(Plan& P) {
+  if (!P.pairs_stale) return;
+  CCFMM_HIP(hipDeviceSynchronize());
+  unsigned long long* dcnt = reinterpret_cast<unsigned long long*>(P.scratch2.ensure(64));
+  CCFMM_HIP(hipMemsetAsync(dcnt, 0, sizeof(unsigned long long), nullptr));
+  launch_pair_count(P, dcnt, nullptr);
+  unsigned long long npairs = 0;
+  CCFMM_HIP(hipMemcpy(&npairs, dcnt, sizeof(npairs), hipMemcpyDeviceToHost));
+  P.info.n_p2p_pairs = (int64_t)npairs;
+  P.info.p2p_pairs_per_config = (double)npairs;
+  P.pairs_stale = false;
+}
+
+// Cost of one far cell (M2L pair) relative to one direct dipole pair, from
+// one evaluation of these moments on the fixed-parameter lists with every
+// pass alone on the stream (the second of two, the first warming up).
+static double measure_cost_far(Plan& P, int nb, const double* d_m, hipStream_t st) {
+  if (P.has_leaf) apply_leaf_params(P, nullptr, nullptr, st);
+  refresh_pair_count(P);
+  prepare_batch(P, nb, st);
+  double* Hs = reinterpret_cast<double*>(P.judge_a.ensure(sizeof(double) * 3 * (size_t)P.n * nb));
+  hipEvent_t ev[9];
+  for (int i = 0; i < 9; i++) CCFMM_HIP(hipEventCreate(&ev[i]));
+  const bool overlap = P.overlap;
+  P.overlap = false;
+  float m2l = 0.f, near = 0.f;
+  try {
+    for (int rep = 0; rep < 2; rep++) eval_passes(P, nb, d_m, Hs, st, ev);
+    CCFMM_HIP(hipEventSynchronize(ev[5]));
+    CCFMM_HIP(hipEventElapsedTime(&m2l, ev[2], ev[3]));
+    CCFMM_HIP(hipEventElapsedTime(&near, ev[6], ev[7]));
+  } catch (...) {
+    P.overlap = overlap;
+    for (int i = 0; i < 9; i++) (void)hipEventDestroy(ev[i]);
+    throw;
+  }
+  P.overlap = overlap;
+  for (int i = 0; i < 9; i++) (void)hipEventDestroy(ev[i]);
+  const double per_m2l = (double)m2l / (double)std::max<int64_t>(1, P.info.n_m2l_pairs);
+  const double per_near = (double)near / std::max(1.0, P.info.p2p_pairs_per_config);
+  return per_near > 0.0 ? per_m2l / per_near : 1.0;
+}
+
+// Learned mode: choose per-cell parameters when the plan has weights and the
+// current choice is stale (first evaluation of the cells, new weights).
+int auto_select(Plan& P, int nb, const double* d_m, hipStream_t st) {
+  if (P.prm.selector != 1 || !P.has_sel_w || !P.sel_stale) return CCFMM_OK;
+  const double cf = P.prm.sel_cost_far > 0.0 ? P.prm.sel_cost_far : measure_cost_far(P, nb, d_m, st);
+  const int rc = select_impl(P, P.sel_w.as<float>(), P.prm.err_bound, P.prm.sel_margin, cf, nb, d_m, true, st,
+                             nullptr);
+  P.sel_stale = false;
+  return rc;
 }
 }  // namespace ccfmm
 
@@ -1043,50 +1189,81 @@ int ccfmm_plan_select(ccfmm_plan plan, const float* d_params, double err_bound, 
     if (P.p < 2) fail(CCFMM_EINVAL, "learned selection needs a plan of order >= 2");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
-    if (P.has_leaf) apply_leaf_params(P, nullptr, nullptr, st);
-    const int nl = P.lev[P.L]->ncells;
-    DevBuf dp, dt;
-    dp.ensure(sizeof(int32_t) * nl);
-    dt.ensure(sizeof(double) * nl);
-    std::vector<int32_t> hist;
-    run_select(P, d_params, std::log10(err_bound) - margin, cost_far, nbatch, d_m, dp.as<int32_t>(),
-               dt.as<double>(), hist, st);
-    std::vector<int32_t> hp(nl);
-    std::vector<double> ht(nl);
-    CCFMM_HIP(hipMemcpyAsync(hp.data(), dp.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
-    CCFMM_HIP(hipMemcpyAsync(ht.data(), dt.p, sizeof(double) * nl, hipMemcpyDeviceToHost, st));
-    CCFMM_HIP(hipStreamSynchronize(st));
-    int rc = CCFMM_OK;
-    double jerr = 0.0;
-    int fb = 0;
-    if (judge) {
-      // fixed-parameter field, then the learned one, on these moments
-      const size_t bytes = sizeof(double) * 3 * (size_t)P.n * nbatch;
-      double* Hf = reinterpret_cast<double*>(P.judge_a.ensure(bytes));
-      double* Hl = reinterpret_cast<double*>(P.judge_b.ensure(bytes));
-      prepare_batch(P, nbatch, st);
-      eval_passes(P, nbatch, d_m, Hf, st, nullptr);
-      apply_leaf_params(P, hp.data(), ht.data(), st);
-      prepare_batch(P, nbatch, st);
-      eval_passes(P, nbatch, d_m, Hl, st, nullptr);
-      jerr = run_rel_rms(Hl, Hf, (int64_t)3 * P.n * nbatch, P.scratch, st);
-      if (!(jerr <= err_bound)) {
-        apply_leaf_params(P, nullptr, nullptr, st);
-        fb = 1;
-        rc = CCFMM_W_FALLBACK;
-      }
-    } else {
-      apply_leaf_params(P, hp.data(), ht.data(), st);
+    return select_impl(P, d_params, err_bound, margin, cost_far, nbatch, d_m, judge != 0, st, out);
+  });
+}
+
+int ccfmm_selector_write(const char* path, const float* h_params) {
+  return guarded([&] {
+    selector_file_write(path, h_params);
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_selector_read(const char* path, float* h_params) {
+  return guarded([&] {
+    std::vector<float> h(CCFMM_MLP_PARAMS);
+    if (!selector_file_read(path, h.data())) {
+      g_last_error = std::string("selector weights file not found: ") + (path ? path : "");
+      return CCFMM_W_NOWEIGHTS;
     }
-    P.info.fallback = fb;
-    if (out) {
-      std::memset(out, 0, sizeof(*out));
-      out->n_leaves = nl;
-      for (int i = 0; i < CCFMM_MLP_OUT && i < (int)hist.size(); i++) out->hist[i] = hist[i];
-      out->judge_err = jerr;
-      out->fallback = fb;
+    std::copy(h.begin(), h.end(), h_params);
+    return CCFMM_OK;
+  });
+}
+
+// new weights in the plan: a learned plan chooses again at its next evaluation
+static void install_weights(Plan& P, const void* src, hipMemcpyKind kind, hipStream_t st) {
+  P.sel_w.ensure(sizeof(float) * CCFMM_MLP_PARAMS);
+  CCFMM_HIP(hipMemcpyAsync(P.sel_w.p, src, sizeof(float) * CCFMM_MLP_PARAMS, kind, st));
+  CCFMM_HIP(hipStreamSynchronize(st));
+  P.has_sel_w = true;
+  P.sel_stale = true;
+}
+
+int ccfmm_selector_load(ccfmm_plan plan, const char* path) {
+  return guarded([&] {
+    if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
+    Plan& P = plan->P;
+    std::vector<float> h(CCFMM_MLP_PARAMS);
+    if (!selector_file_read(path, h.data())) {
+      g_last_error = std::string("selector weights file not found, fixed parameters kept: ") + (path ? path : "");
+      return CCFMM_W_NOWEIGHTS;
     }
-    return rc;
+    CCFMM_HIP(hipSetDevice(P.device));
+    install_weights(P, h.data(), hipMemcpyHostToDevice, nullptr);
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_selector_set(ccfmm_plan plan, const float* d_params, void* stream) {
+  return guarded([&] {
+    if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
+    if (!d_params) fail(CCFMM_EINVAL, "parameters are NULL");
+    CCFMM_HIP(hipSetDevice(plan->P.device));
+    install_weights(plan->P, d_params, hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_selector_save(ccfmm_plan plan, const char* path) {
+  return guarded([&] {
+    if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
+    Plan& P = plan->P;
+    if (!P.has_sel_w) fail(CCFMM_ESTATE, "the plan holds no selector weights");
+    CCFMM_HIP(hipSetDevice(P.device));
+    std::vector<float> h(CCFMM_MLP_PARAMS);
+    CCFMM_HIP(hipMemcpy(h.data(), P.sel_w.p, sizeof(float) * CCFMM_MLP_PARAMS, hipMemcpyDeviceToHost));
+    selector_file_write(path, h.data());
+    return CCFMM_OK;
+  });
+}
+
+int ccfmm_selector_train(const ccfmm_train_spec* spec, const char* out_path, float* h_params_out,
+                         ccfmm_train_info* info) {
+  return guarded([&] {
+    train_selector(spec, out_path, h_params_out, info);
+    return CCFMM_OK;
   });
 }
 

@@ -194,15 +194,21 @@ __device__ __forceinline__ void l2p_write(const T* __restrict__ v, int pl, T yx,
     py[j] = py[j - 1] * yy * inv;
     pz[j] = pz[j - 1] * yz * inv;
   }
+  (void)NM;
   T ex = (T)0, ey = (T)0, ez = (T)0;
-#pragma unroll 4
-  for (int k = 0; k < NM; k++) {
-    const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
-    // a smallest cell with its own order pl keeps |n| <= pl, i.e. |k| <= pl - 1
-    const T mono = (kx + ky + kz < pl) ? px[kx] * py[ky] * pz[kz] : (T)0;
-    ex += v[midx(kx + 1, ky, kz) - 1] * mono;
-    ey += v[midx(kx, ky + 1, kz) - 1] * mono;
-    ez += v[midx(kx, ky, kz + 1) - 1] * mono;
+  // degree by degree (the monomials are ordered by degree): a smallest cell
+  // with its own order pl keeps |n| <= pl, i.e. |k| <= pl - 1, and stops there
+#pragma unroll
+  for (int d = 0; d < P; d++) {
+    if (d >= pl) break;
+#pragma unroll
+    for (int k = ncoef(d - 1); k < ncoef(d); k++) {
+      const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
+      const T mono = px[kx] * py[ky] * pz[kz];
+      ex += v[midx(kx + 1, ky, kz) - 1] * mono;
+      ey += v[midx(kx, ky + 1, kz) - 1] * mono;
+      ez += v[midx(kx, ky, kz + 1) - 1] * mono;
+    }
   }
   Ho[0] = s3 * (hx - (double)ex);
   Ho[1] = s3 * (hy - (double)ey);
@@ -766,14 +772,19 @@ __global__ void k_l2p_batched(int64_t n, int nb, const int32_t* __restrict__ dle
     pz[j] = pz[j - 1] * yz * inv;
   }
   const int pl = leaf_p ? leaf_p[dleaf[i]] : P;
+  (void)NM;
   T ex = (T)0, ey = (T)0, ez = (T)0;
 #pragma unroll
-  for (int k = 0; k < NM; k++) {
-    const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
-    const T mono = (kx + ky + kz < pl) ? px[kx] * py[ky] * pz[kz] : (T)0;
-    ex += v[midx(kx + 1, ky, kz) - 1] * mono;
-    ey += v[midx(kx, ky + 1, kz) - 1] * mono;
-    ez += v[midx(kx, ky, kz + 1) - 1] * mono;
+  for (int d = 0; d < P; d++) {  // degree by degree, stopping at the cell's order
+    if (d >= pl) break;
+#pragma unroll
+    for (int k = ncoef(d - 1); k < ncoef(d); k++) {
+      const int kx = kMI.x[k], ky = kMI.y[k], kz = kMI.z[k];
+      const T mono = px[kx] * py[ky] * pz[kz];
+      ex += v[midx(kx + 1, ky, kz) - 1] * mono;
+      ey += v[midx(kx, ky + 1, kz) - 1] * mono;
+      ez += v[midx(kx, ky, kz + 1) - 1] * mono;
+    }
   }
   const int64_t o = ((int64_t)b * n + perm[i]) * 3;
   if (kAdd) {  // the near field is already there

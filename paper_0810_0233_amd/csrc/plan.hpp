@@ -121,6 +121,12 @@ struct Plan {
   double leaf_theta_min = 1.0;
   int tiles_nb = 1;                 // nbatch the M2L tiles were built for
   DevBuf judge_a, judge_b;          // field buffers of the selector's judge
+  // learned mode (selector = 1): network weights, and whether the per-cell
+  // choice must be made at the next evaluation (new plan, new weights, or an
+  // update that changed the occupied cells)
+  DevBuf sel_w;
+  bool has_sel_w = false;
+  bool sel_stale = true;
   // captured evaluation graph, valid for (g_nb, g_m, g_H) until the next rebuild
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
@@ -179,8 +185,21 @@ void run_mlp_loss_grad(const float* d_params, int64_t rows, const float* d_x, co
 void run_mlp_adam(float* d_params, const float* d_grad, float* d_m1, float* d_m2, int step, float lr,
                   hipStream_t st);
 void run_select(Plan& P, const float* d_params, double log_bound, double cost_far, int nb, const double* d_m,
-                int32_t* d_p, double* d_theta, std::vector<int32_t>& hist, hipStream_t st);
+                const double* d_F, int32_t* d_p, double* d_theta, std::vector<int32_t>& hist, double* pred_err,
+                hipStream_t st);
 double run_rel_rms(const double* d_A, const double* d_B, int64_t count, DevBuf& tmp, hipStream_t st);
+void run_scatter_rows(int64_t nt, const int64_t* d_idx, const double* d_src, double* d_dst, hipStream_t st);
+
+// plan-level steps shared by the C ABI and the selector trainer (api.hip)
+void apply_leaf_params(Plan& P, const int32_t* hp, const double* hth, hipStream_t st);
+void eval_once(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st);
+int select_impl(Plan& P, const float* d_params, double err_bound, double margin, double cost_far, int nbatch,
+                const double* d_m, bool judge, hipStream_t st, ccfmm_select_info* out);
+// selector weights files (train.hip): write, and read (false if the file
+// does not exist; any other problem throws CCFMM_EINVAL)
+void selector_file_write(const char* path, const float* h_params);
+bool selector_file_read(const char* path, float* h_params);
+void train_selector(const ccfmm_train_spec* spec, const char* out_path, float* h_out, ccfmm_train_info* info);
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -190,3 +209,8 @@ __host__ __device__ inline int64_t box_index(const int w[3], int dx, int dy, int
 }
 
 }  // namespace ccfmm
+
+// the opaque plan handle of the C ABI
+struct ccfmm_plan_s {
+  ccfmm::Plan P;
+};

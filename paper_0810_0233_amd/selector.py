@@ -149,28 +149,23 @@ def cost_ratio(plan, d_m, d_H, stream, repeats=3, nbatch=1):
     return per_m2l / per_p2p
 
 
-def train_on(configs, order=6, theta=0.4, steps=600, lr=3e-3, seed=1, dev="cuda:0", log_every=0, sample_cells=0):
+def train_on(configs, order=6, theta=0.4, steps=600, lr=3e-3, seed=1, dev="cuda:0", log_every=0, sample_cells=0,
+             out_path=None):
     """Labels from every training configuration (each a dict with pos, box and
-    m[0]; all cells, or sample_cells of each), then training; returns (params,
-    losses, number of cells)."""
-    feats, labs, masks = [], [], []
-    for i, c in enumerate(configs):
-        f, y, k = cell_labels(c["pos"], c["box"], c["m"][0], order=order, theta=theta, dev=dev,
-                              sample_cells=sample_cells, seed=seed + i)
-        feats.append(f)
-        labs.append(y)
-        masks.append(k)
-    F, Y, K = np.concatenate(feats), np.concatenate(labs), np.concatenate(masks)
-    params, losses = train(F, Y, K, steps=steps, lr=lr, seed=seed, dev=dev, log_every=log_every)
-    return params, losses, F.shape[0]
+    m[0]; all cells, or sample_cells of each) and training, all inside the
+    library (ccfmm_selector_train); returns (params, losses, number of cells)."""
+    geoms = [dict(pos=c["pos"], m=c["m"][0], box=c["box"]) for c in configs]
+    params, inf = ccfmm.selector_train(geoms, order=order, theta=theta, precision=ccfmm.PREC_MIXED,
+                                       sample_cells=sample_cells, steps=steps, lr=lr, seed=seed, out_path=out_path)
+    losses = [(1, inf["loss_first"]), (steps, inf["loss_last"])]
+    return params, losses, int(inf["rows"])
 
 
 def save(path, params):
-    np.save(path, np.asarray(params, dtype=np.float32), allow_pickle=False)
+    """Weights to a selector weights file (the library's format)."""
+    ccfmm.selector_write(path, params)
 
 
 def load(path):
-    p = np.load(path, allow_pickle=False)
-    if p.dtype != np.float32 or p.size != ccfmm.MLP_PARAMS:
-        raise ValueError("not a selector weight file")
-    return p
+    """Weights from a selector weights file; None if the file does not exist."""
+    return ccfmm.selector_read(path)

@@ -39,7 +39,8 @@ def test_status_strings_and_defaults():
 @pytest.mark.parametrize("bad", [dict(order=0), dict(order=9), dict(theta=0.0), dict(theta=1.0),
                                  dict(max_batch=0), dict(precision=7), dict(truncation=2),
                                  dict(m2l_traceless=3), dict(max_batch=4097), dict(leaf_rule=2),
-                                 dict(selector=1), dict(leaf_target=float("inf"))])
+                                 dict(selector=2), dict(selector=1, order=1), dict(selector=1, err_bound=0.0),
+                                 dict(selector=1, sel_margin=-0.1), dict(leaf_target=float("inf"))])
 def test_invalid_params_rejected_without_gpu(bad):
     prm = ccfmm.params(**bad)
     with pytest.raises(ccfmm.CCFMMError) as e:
@@ -79,3 +80,55 @@ def test_noalloc_energy_rejects_sizes_without_gpu():
             ccfmm.energy_device_noalloc(n, nb, 8, 8, 8)
         assert e.value.status == ccfmm.EINVAL
     assert "nbatch must be in 1..%d" % ccfmm.NOALLOC_MAX_BATCH in ccfmm.last_error()
+
+
+def fnv1a64(b):
+    h = 14695981039346656037
+    for x in b:
+        h = ((h ^ x) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_selector_file_format_and_checks(tmp_path):
+    """The weights file has the documented little-endian layout, reads back
+    bit for bit, a missing file is a warning, and any altered, truncated or
+    foreign file is refused."""
+    import struct
+
+    rng = np.random.default_rng(5)
+    P = rng.standard_normal(ccfmm.MLP_PARAMS).astype(np.float32)
+    f = tmp_path / "w.ccsel"
+    ccfmm.selector_write(str(f), P)
+    b = f.read_bytes()
+    assert len(b) == 8 + 7 * 4 + 5 * 8 + 4 * ccfmm.MLP_PARAMS + 8
+    assert b[:8] == b"CCFMMSEL"
+    assert struct.unpack_from("<7I", b, 8) == (1, 8, 64, 25, ccfmm.MLP_PARAMS, 2, 6)
+    assert struct.unpack_from("<5d", b, 36) == (0.3, 0.4, 0.5, 0.6, 0.7)
+    assert np.array_equal(np.frombuffer(b, dtype="<f4", count=ccfmm.MLP_PARAMS, offset=76), P)
+    assert struct.unpack_from("<Q", b, len(b) - 8)[0] == fnv1a64(b[:-8])
+    assert np.array_equal(ccfmm.selector_read(str(f)), P)
+    # missing file: warning, nothing read
+    assert ccfmm.selector_read(str(tmp_path / "absent.ccsel")) is None
+    assert ccfmm.lib().ccfmm_selector_read(str(tmp_path / "absent.ccsel").encode(), None) == ccfmm.W_NOWEIGHTS
+    # one parameter bit flipped, truncated, foreign header: refused
+    bad = bytearray(b)
+    bad[100] ^= 1
+    for name, data in (("flip", bytes(bad)), ("short", b[:-1]), ("magic", b"CCFMMSEX" + b[8:]),
+                       ("version", b[:8] + struct.pack("<I", 2) + b[12:])):
+        g = tmp_path / (name + ".ccsel")
+        g.write_bytes(data)
+        with pytest.raises(ccfmm.CCFMMError) as e:
+            ccfmm.selector_read(str(g))
+        assert e.value.status == ccfmm.EINVAL
+
+
+def test_selector_train_rejects_bad_specs_without_gpu():
+    pos = np.zeros((4, 3))
+    g = [dict(pos=pos, m=pos, box=None)]
+    for kw in (dict(order=1), dict(theta=1.0), dict(steps=0), dict(lr=0.0)):
+        with pytest.raises(ccfmm.CCFMMError) as e:
+            ccfmm.selector_train(g, **kw)
+        assert e.value.status == ccfmm.EINVAL
+    with pytest.raises(ccfmm.CCFMMError) as e:
+        ccfmm.selector_train([])
+    assert e.value.status == ccfmm.EINVAL

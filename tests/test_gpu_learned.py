@@ -1,0 +1,208 @@
+"""GPU tests of the learned mode through the C ABI: the selector trained by
+ccfmm_selector_train, its weights file written and read back, a plan created
+with selector = 1 choosing per-cell parameters at its first evaluation with
+the fixed-parameter FMM as judge, the missing-file warning, the forced
+fallback, and the choice kept across position updates that keep the cells.
+
+Bars: learned field within err_bound (relative RMS) of the fixed-parameter
+field (the judge's criterion) and of the oracle FMM's fixed field; FP64 plans
+with the chosen per-cell parameters against the oracle's per-cell FMM
+(ccref_fmm_leaf) <= 1e-10; fallback results equal the fixed ones bit for bit.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_0810_0233_amd import ccfmm, inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-10
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def torch_mod():
+    import torch
+
+    return torch
+
+
+def stream():
+    return torch_mod().cuda.current_stream().cuda_stream
+
+
+def cluster_case(seed, ncl=16, per=600):
+    pos, box = inputs.clusters(ncl, per, seed, sigma=6.0, box_side=256.0, margin=16.0)
+    m = inputs.random_moments(pos.shape[0], seed + 1)
+    return pos, box, m
+
+
+@pytest.fixture(scope="module")
+def trained(tmp_path_factory):
+    """Weights trained in the library on three cluster geometries (every
+    cell labelled), written to a file."""
+    path = str(tmp_path_factory.mktemp("sel") / "clusters.ccsel")
+    geoms = []
+    for seed in (4211, 4213, 4215):
+        pos, box, m = cluster_case(seed)
+        geoms.append(dict(pos=pos, m=m, box=box))
+    print("case train 3 cluster geometries", flush=True)
+    P, info = ccfmm.selector_train(geoms, order=6, theta=0.4, precision=ccfmm.PREC_MIXED, steps=600, lr=3e-3,
+                                   seed=3, out_path=path)
+    print("trained rows %d loss %.4f -> %.4f (labels %.1f s, training %.2f s)" % (
+        info["rows"], info["loss_first"], info["loss_last"], info["label_seconds"], info["train_seconds"]),
+        flush=True)
+    return path, P, info
+
+
+def test_training_reduces_loss_and_writes_file(trained):
+    path, P, info = trained
+    assert info["rows"] > 100
+    assert info["loss_last"] < 0.25 * info["loss_first"]
+    assert np.array_equal(ccfmm.selector_read(path), P)
+
+
+def learned_plan(pos, box, precision, bound, max_batch=1, **kw):
+    prm = ccfmm.params(order=6, theta=0.4, box=box, precision=precision, max_batch=max_batch, selector=1,
+                       err_bound=bound, **kw)
+    return ccfmm.Plan.create(pos, prm)
+
+
+def test_selector_at_plan_creation(trained, ref, tmp_path):
+    """A selector = 1 plan given the weights file chooses per-cell parameters
+    at its first evaluation (judged against the fixed field), keeps them
+    afterwards, saves the same weights back; the FP64 form with those
+    parameters equals the oracle's per-cell FMM."""
+    path, P, _ = trained
+    pos, box, m = cluster_case(4311)
+    n = pos.shape[0]
+    bound = 1e-4
+    fixed = ccfmm.Plan.create(pos, ccfmm.params(order=6, theta=0.4, box=box, precision=ccfmm.PREC_MIXED))
+    H_fixed = fixed.eval(m)
+    fixed.destroy()
+    pl = learned_plan(pos, box, ccfmm.PREC_MIXED, bound)
+    assert pl.info()["learned"] == 0
+    assert pl.selector_load(path) == ccfmm.OK
+    H = pl.eval(m)
+    inf = pl.info()
+    print("learned: status %d judge %.3e cost_far %.1f m2l pairs %d near pairs %.4e" % (
+        pl.last_status, inf["judge_err"], inf["sel_cost_far"], inf["n_m2l_pairs"], inf["p2p_pairs_per_config"]),
+        flush=True)
+    assert pl.last_status == ccfmm.OK and inf["learned"] == 1 and inf["fallback"] == 0
+    assert 0 < inf["judge_err"] <= bound and inf["sel_cost_far"] > 0
+    assert rel_rms(H, H_fixed) <= bound
+    p, th = pl.get_leaf_params()
+    assert len(np.unique(th)) > 1 or th[0] != 0.4  # the choice departs from the fixed parameters
+    # the second evaluation reuses the choice: same field, no new judge
+    assert np.array_equal(pl.eval(m), H)
+    saved = tmp_path / "again.ccsel"
+    pl.selector_save(str(saved))
+    assert saved.read_bytes() == open(path, "rb").read()
+    # FP64 with the chosen per-cell parameters against the oracle's per-cell FMM
+    p64 = ccfmm.Plan.create(pos, ccfmm.params(order=6, theta=0.4, box=box))
+    torch = torch_mod()
+    dp = torch.from_numpy(p.astype(np.int32)).cuda()
+    dt = torch.from_numpy(th.astype(np.float64)).cuda()
+    p64.set_leaf_params(dp.data_ptr(), dt.data_ptr(), stream())
+    torch.cuda.synchronize()
+    ids = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    p64.leaf_ids(ids.data_ptr(), stream())
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy()
+    H_ref, st = ref.fmm_leaf(pos, m, 6, 0.4, leaf_p=p[ids], leaf_theta=th[ids], box=box, return_stats=True)
+    assert p64.info()["m2l_pairs_per_level"] == st["m2l_pairs_per_level"]
+    assert rel_rms(p64.eval(m), H_ref) <= FP64_BAR
+    p64.destroy()
+    pl.destroy()
+
+
+def test_missing_weights_file_keeps_fixed_parameters(tmp_path):
+    pos, box, m = cluster_case(4312, ncl=8, per=400)
+    pl = learned_plan(pos, box, ccfmm.PREC_FP64, 1e-5)
+    assert pl.selector_load(str(tmp_path / "absent.ccsel")) == ccfmm.W_NOWEIGHTS
+    assert "not found" in ccfmm.last_error()
+    H = pl.eval(m)
+    assert pl.info()["learned"] == 0
+    fixed = ccfmm.Plan.create(pos, ccfmm.params(order=6, theta=0.4, box=box))
+    assert np.array_equal(H, fixed.eval(m))
+    with pytest.raises(ccfmm.CCFMMError) as e:
+        pl.selector_save(str(tmp_path / "none.ccsel"))  # the plan holds no weights
+    assert e.value.status == ccfmm.ESTATE
+    fixed.destroy()
+    pl.destroy()
+
+
+def constant_net(level):
+    P = np.zeros(ccfmm.MLP_PARAMS, dtype=np.float32)
+    P[-ccfmm.MLP_OUT:] = level
+    return P
+
+
+def test_forced_fallback_returns_fixed_field():
+    """Weights that predict negligible errors everywhere make every cell take
+    the widest angle; with a bound below what that costs, the judge rejects:
+    that evaluation returns W_FALLBACK and the fixed field bit for bit, and
+    the plan stays on fixed parameters."""
+    torch = torch_mod()
+    pos, box, m = cluster_case(4313, ncl=8, per=400)
+    pl = learned_plan(pos, box, ccfmm.PREC_FP64, 1e-9, sel_cost_far=1.0)
+    dP = torch.from_numpy(constant_net(-20.0)).cuda()
+    pl.selector_set(dP.data_ptr(), stream())
+    H = pl.eval(m)
+    inf = pl.info()
+    assert pl.last_status == ccfmm.W_FALLBACK and inf["fallback"] == 1 and inf["learned"] == 0
+    assert inf["judge_err"] > 1e-9
+    fixed = ccfmm.Plan.create(pos, ccfmm.params(order=6, theta=0.4, box=box))
+    H_fixed = fixed.eval(m)
+    assert np.array_equal(H, H_fixed)
+    assert np.array_equal(pl.eval(m), H_fixed) and pl.last_status == ccfmm.OK
+    fixed.destroy()
+    pl.destroy()
+
+
+def test_learned_choice_kept_across_updates_that_keep_the_cells(trained):
+    """Position updates that leave every occupied cell occupied keep the
+    per-cell choice (compact cell order unchanged) and its lists; an update
+    that changes the cells makes the next evaluation choose again."""
+    import torch
+
+    path, _, _ = trained
+    pos, box, m = cluster_case(4314)
+    n = pos.shape[0]
+    dev = torch.device("cuda:0")
+    st = stream()
+    d_pos = torch.from_numpy(pos).to(dev)
+    d_m = torch.from_numpy(m).to(dev)
+    d_H = torch.empty_like(d_m)
+    prm = ccfmm.params(order=6, theta=0.4, box=box, precision=ccfmm.PREC_MIXED, selector=1, err_bound=1e-4)
+    pl = ccfmm.Plan.create_device(n, d_pos.data_ptr(), prm, st)
+    assert pl.selector_load(path) == ccfmm.OK
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    H0 = d_H.cpu().numpy()
+    p0, th0 = pl.get_leaf_params()
+    kept0 = pl.info()["n_rebuilds_kept"]
+    pl.update_positions_device(d_pos.data_ptr(), st)  # same positions: same cells
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    inf = pl.info()
+    assert inf["n_rebuilds_kept"] == kept0 + 1 and inf["learned"] == 1
+    p1, th1 = pl.get_leaf_params()
+    assert np.array_equal(p0, p1) and np.array_equal(th0, th1)
+    assert np.array_equal(d_H.cpu().numpy(), H0)
+    # move one dipole into an empty corner cell: the cells change, the choice is made again
+    moved = pos.copy()
+    moved[0] = np.asarray(box[1]) - 1e-3
+    d_pos2 = torch.from_numpy(moved).to(dev)
+    pl.update_positions_device(d_pos2.data_ptr(), st)
+    assert pl.info()["learned"] == 0
+    pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+    torch.cuda.synchronize()
+    inf = pl.info()
+    assert inf["learned"] == 1 or inf["fallback"] == 1
+    assert inf["n_leaves"] == len(pl.get_leaf_params()[0])
+    pl.destroy()

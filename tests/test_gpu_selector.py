@@ -223,18 +223,22 @@ def test_select_extremes_and_fallback():
     nl = pl.info()["n_leaves"]
     H_fixed = pl.eval(m)
     dm = dev_t(m)
-    # nothing meets the bound -> every cell takes (pmax, 0.3)
+    # nothing can meet the bound (every prediction 10^5): the most accurate
+    # candidate, which for equal predictions is (pmax, 0.3)
     dP = dev_t(constant_net(5.0))
     rc, si = pl.select(dP.data_ptr(), 1e-4, 0.0, 30.0, 1, dm.data_ptr(), judge=False, stream=stream())
     assert rc == ccfmm.OK and si["n_leaves"] == nl
     assert si["hist"][4 * 5 + 0] == nl and sum(si["hist"]) == nl
     p, th = pl.get_leaf_params()
     assert np.all(p == 6) and np.all(th == 0.3)
-    # everything meets a loose bound with no far cost -> the largest angle, top order
+    # everything meets a loose bound with no far cost: the cheapest candidate,
+    # the largest angle (fewest near sources) at the lowest order (least
+    # smooth-field work)
     dP = dev_t(constant_net(-20.0))
     rc, si = pl.select(dP.data_ptr(), 1e-2, 0.0, 0.0, 1, dm.data_ptr(), judge=False, stream=stream())
     p, th = pl.get_leaf_params()
-    assert np.all(p == 6) and np.all(th == 0.7)
+    assert np.all(p == 2) and np.all(th == 0.7)
+    assert si["pred_err"] <= 1e-2
     # a judge with an unreachable bound rejects -> fixed parameters, bit for bit
     rc, si = pl.select(dP.data_ptr(), 1e-13, 0.0, 0.0, 1, dm.data_ptr(), judge=True, stream=stream())
     assert rc == ccfmm.W_FALLBACK and si["fallback"] == 1 and si["judge_err"] > 1e-13
@@ -249,58 +253,82 @@ def test_select_extremes_and_fallback():
     p1.destroy()
 
 
+def uniform_sweep(pl, m, err_of, timed=None):
+    """Every uniform (p, theta) of the candidate grid on this plan: its error
+    (err_of(field)), the plan statistics and, with timed, a measured
+    evaluation time (median of three, every pass alone)."""
+    nl = pl.info()["n_leaves"]
+    out = []
+    for p in ccfmm.SEL_P:
+        for th in ccfmm.SEL_THETA:
+            set_params(pl, np.full(nl, p), np.full(nl, th))
+            row = {"p": p, "theta": th, "err": err_of(pl.eval(m)), "info": pl.info()}
+            if timed is not None:
+                row["ms"] = timed()
+            out.append(row)
+    pl.set_leaf_params(0, 0, stream())
+    return out
+
+
 def test_trained_selector_beats_fixed_parameters():
-    """Labels from the library (25 uniform (p, theta) runs vs the GPU direct
-    sum per cell) on four training geometries, Adam on the GPU, then selection
-    with judge on a held-out geometry with a different seed."""
+    """Weights trained by the library (ccfmm_selector_train: 25 uniform
+    (p, theta) runs per cell against the GPU direct sum, Adam on the GPU) on
+    four training geometries; on a held-out geometry the judged learned choice
+    meets the bound at a lower modelled cost (near pairs + cost_far x M2L
+    pairs) than fixed (6, 0.4) and than the cheapest uniform (p, theta) of the
+    grid that meets the same bound on the same geometry."""
     torch = torch_mod()
-    feats, labs, masks = [], [], []
+    geoms = []
     for seed in (4201, 4203, 4205, 4207):
         pos, box, m = cluster_case(seed)
-        f, y, k = selector.cell_labels(pos, box, m, order=6, theta=0.4)
-        feats.append(f)
-        labs.append(y)
-        masks.append(k)
-        print("labels seed=%d cells=%d" % (seed, f.shape[0]), flush=True)
-    F, Y, K = np.concatenate(feats), np.concatenate(labs), np.concatenate(masks)
-    params, losses = selector.train(F, Y, K, steps=600, lr=3e-3, seed=1, log_every=200)
-    print("loss", losses, flush=True)
-    assert losses[-1][1] < 0.25 * losses[0][1]
+        geoms.append(dict(pos=pos, m=m, box=box))
+    params, tinfo = ccfmm.selector_train(geoms, order=6, theta=0.4, steps=600, lr=3e-3, seed=1)
+    print("trained rows %d loss %.4f -> %.4f" % (tinfo["rows"], tinfo["loss_first"], tinfo["loss_last"]), flush=True)
+    assert tinfo["loss_last"] < 0.25 * tinfo["loss_first"]
 
     pos, box, m = cluster_case(4301)
     Hd = selector.direct_field(pos, m, "cuda:0")
     torch.cuda.synchronize()
     H_direct = Hd.cpu().numpy()
     bound, cost_far = 1e-4, 30.0
+    cost = lambda inf: inf["p2p_pairs_per_config"] + cost_far * inf["n_m2l_pairs"]  # noqa: E731
 
     fixed = plan_for(pos, 6, 0.4, box, precision=ccfmm.PREC_MIXED)
     fi = fixed.info()
     err_fixed = rel_rms(fixed.eval(m), H_direct)
+    sweep = uniform_sweep(fixed, m, lambda H: rel_rms(H, H_direct))
+    ok = [r for r in sweep if r["err"] <= bound]
+    best = min(ok, key=lambda r: cost(r["info"]))
     dP = dev_t(params)
     dm = dev_t(m)
     rc, si = fixed.select(dP.data_ptr(), bound, 0.3, cost_far, 1, dm.data_ptr(), judge=True, stream=stream())
     li = fixed.info()
     err_learned = rel_rms(fixed.eval(m), H_direct)
-    cost = lambda inf: inf["p2p_pairs_per_config"] + cost_far * inf["n_m2l_pairs"]  # noqa: E731
-    print("fixed err %.3e cost %.4e | learned err %.3e cost %.4e judge %.3e rc %d hist %s" %
-          (err_fixed, cost(fi), err_learned, cost(li), si["judge_err"], rc, si["hist"]), flush=True)
+    print("fixed err %.3e cost %.4e | best uniform (%d, %.1f) err %.3e cost %.4e | learned err %.3e cost %.4e "
+          "judge %.3e rc %d hist %s" % (err_fixed, cost(fi), best["p"], best["theta"], best["err"],
+                                         cost(best["info"]), err_learned, cost(li), si["judge_err"], rc, si["hist"]),
+          flush=True)
     assert rc == ccfmm.OK
     assert err_learned <= bound
     assert cost(li) < 0.8 * cost(fi)
+    # the learned choice is made against the bound with a margin; it may not
+    # cost more than the cheapest uniform setting that meets the bound itself
+    assert cost(li) <= 1.02 * cost(best["info"])
     fixed.destroy()
 
 
 def test_selector_clusters_full_scale(ref):
-    """2^21 dipoles in 256 Gaussian clusters (sigma 8, box 512^3): a network
-    trained on the GPU on two training geometries of the same recipe (seeds
-    4101, 4102) picks per-cell (p, theta) for a 1e-5 bound; the fixed
+    """2^21 dipoles in 256 Gaussian clusters (sigma 8, box 512^3): weights
+    trained by the library on two training geometries of the same recipe
+    (seeds 4101, 4102) pick per-cell (p, theta) for a 1e-5 bound; the fixed
     (6, 0.4) FMM judges it.  Against the oracle's direct sum at sampled
-    dipoles the learned field meets the bound, at a lower modelled cost
-    (near pairs + measured M2L/P2P cost ratio x M2L pairs) than the fixed one."""
+    dipoles the learned field meets the bound; its measured evaluation is well
+    below that of fixed (6, 0.4) and matches (within 5%) the fastest uniform
+    (p, theta) of the grid that meets the same bound on the same dipoles."""
     torch = torch_mod()
     st = stream()
     train = [inputs.config_clusters_training(4101), inputs.config_clusters_training(4102)]
-    params, losses, ncells = selector.train_on(train, steps=600, log_every=200)
+    params, losses, ncells = selector.train_on(train, steps=600)
     print("trained on %d cells, loss %s" % (ncells, losses), flush=True)
     c = inputs.config_clusters()
     pos, box, m = c["pos"], c["box"], c["m"][0]
@@ -310,26 +338,40 @@ def test_selector_clusters_full_scale(ref):
     dH = torch.empty_like(dm)
     pl.autotune(1, dm.data_ptr(), dH.data_ptr(), st)
     cf = selector.cost_ratio(pl, dm.data_ptr(), dH.data_ptr(), st)
+
+    def timed():
+        return float(np.median([pl.eval_device_timed(1, dm.data_ptr(), dH.data_ptr(), st)["total"]
+                                for _ in range(3)]))
+
     fi = pl.info()
-    t_fixed = pl.eval_device_timed(1, dm.data_ptr(), dH.data_ptr(), st)["total"]
+    t_fixed = timed()
     torch.cuda.synchronize()
     H_fixed = dH.cpu().numpy()
     idx = np.sort(np.random.default_rng(11).choice(n, 512, replace=False)).astype(np.int64)
     Hd = ref.bruteforce_targets(pos, m, idx)
     err_fixed = rel_rms(H_fixed[idx], Hd)
+    sweep = uniform_sweep(pl, m, lambda H: rel_rms(H[idx], Hd), timed=timed)
+    ok = [r for r in sweep if r["err"] <= 1e-5]
+    for r in sweep:
+        print("uniform (%d, %.1f): err %.3e eval %.2f ms" % (r["p"], r["theta"], r["err"], r["ms"]), flush=True)
+    best = min(ok, key=lambda r: r["ms"])
     dP = dev_t(params)
     rc, si = pl.select(dP.data_ptr(), 1e-5, 0.3, cf, 1, dm.data_ptr(), judge=True, stream=st)
     li = pl.info()
-    t_learned = pl.eval_device_timed(1, dm.data_ptr(), dH.data_ptr(), st)["total"]
+    t_learned = timed()
     torch.cuda.synchronize()
     err_learned = rel_rms(dH.cpu().numpy()[idx], Hd)
-    cost = lambda inf: inf["p2p_pairs_per_config"] + cf * inf["n_m2l_pairs"]  # noqa: E731
-    print("n=%d cells=%d cost ratio %.1f | fixed: err %.3e cost %.4e eval %.2f ms | learned: err %.3e cost %.4e "
-          "eval %.2f ms judge %.3e rc %d hist %s" % (n, fi["n_leaves"], cf, err_fixed, cost(fi), t_fixed, err_learned,
-                                                     cost(li), t_learned, si["judge_err"], rc, si["hist"]), flush=True)
+    print("n=%d cells=%d cost ratio %.1f | fixed: err %.3e eval %.2f ms | best uniform (%d, %.1f): err %.3e eval "
+          "%.2f ms | learned: err %.3e eval %.2f ms judge %.3e rc %d hist %s" % (
+              n, fi["n_leaves"], cf, err_fixed, t_fixed, best["p"], best["theta"], best["err"], best["ms"],
+              err_learned, t_learned, si["judge_err"], rc, si["hist"]), flush=True)
     assert rc == ccfmm.OK
     assert err_learned <= 1e-5
-    assert cost(li) < cost(fi)
+    assert t_learned < 0.7 * t_fixed
+    # On these clusters the cheapest corner of the grid already meets 1e-5
+    # (close pairs dominate |H|), so the learned choice can at best match the
+    # fastest uniform setting: within 5% of its measured time
+    assert t_learned <= 1.05 * best["ms"]
     pl.destroy()
 
 
