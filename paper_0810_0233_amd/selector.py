@@ -13,6 +13,8 @@ predicted to meet the bound is taken per cell, and the fixed-parameter FMM
 judges the result (fallback if the learned field differs from it by more
 than the bound).
 """
+import os
+
 import numpy as np
 
 from . import ccfmm
@@ -169,3 +171,38 @@ def save(path, params):
 def load(path):
     """Weights from a selector weights file; None if the file does not exist."""
     return ccfmm.selector_read(path)
+
+
+# Weights shipped with the package (trained by train_film below).
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+FILM_WEIGHTS = "film_1024x1024x16_p6_t04.ccsel"
+FILM_TRAIN_SEEDS = (5101, 5103)
+FILM_SAMPLE_CELLS = 4096
+
+
+def train_film(out_path, steps=600, seed=1):
+    """Selector weights for the thin-film workload: two full-size films of the
+    same recipe with other hole and moment seeds (same tree depth and
+    smallest-cell shape as the film they serve), FILM_SAMPLE_CELLS labelled
+    cells each, fixed (p, theta) = (6, 0.4) above the smallest cells."""
+    from . import inputs
+
+    train_cfgs = [inputs.config_film_training(s) for s in FILM_TRAIN_SEEDS]
+    return train_on(train_cfgs, order=6, theta=0.4, steps=steps, seed=seed, sample_cells=FILM_SAMPLE_CELLS,
+                    out_path=out_path)
+
+
+if __name__ == "__main__":
+    import argparse
+    import time
+
+    ap = argparse.ArgumentParser(description="train the selector network on the GPU and write its weights file")
+    ap.add_argument("--workload", choices=["film"], default="film")
+    ap.add_argument("--out", default=os.path.join(WEIGHTS_DIR, FILM_WEIGHTS))
+    ap.add_argument("--steps", type=int, default=600)
+    a = ap.parse_args()
+    import torch  # noqa: F401  (the library binds to torch's HIP runtime)
+
+    t = time.time()
+    params, losses, rows = train_film(a.out, steps=a.steps)
+    print("trained on %d cells in %.1f s, loss %s -> %s" % (rows, time.time() - t, losses, a.out), flush=True)
