@@ -119,6 +119,7 @@ def pass_work(info, n, nb, order):
     pairs = info["n_p2p_pairs"]
     batched = nb >= 32
     exp_b = 4.0 * NS * nb
+    l2p_flops = 6.0 * (order * (order + 1) * (order + 2) // 6) * n * nb
     out = {
         "p2m": {"kernel": "k_permute_moments+k_p2m<float,%d>" % order, "bound": "hbm",
                 "bytes": n * nb * 24.0 + n * 12.0 + leaves * exp_b, "flops": 6.0 * NP * n * nb},
@@ -134,12 +135,12 @@ def pass_work(info, n, nb, order):
         # index (4 B), the smallest cells' local expansions when L2P is fused; FP64 field written (24 B)
         "p2p": {"kernel": near_kernel_name(nb, order),
                 "bound": "mfma" if batched else "alu",
-                "bytes": n * 28.0 + n * nb * 36.0 + (0.0 if nb > 1 else leaves * exp_b),
-                "flops": near_flops(pairs, nb)},
-        "l2p": {"kernel": ("k_l2p_batched<float,%d,true>" % order if nb > 1
-                           else "fused into k_p2p_l2p<float,%d,true>" % order), "bound": "hbm",
+                "bytes": n * 28.0 + n * nb * 36.0 + (0.0 if batched else leaves * exp_b),
+                "flops": near_flops(pairs, nb) + (0.0 if batched else l2p_flops)},
+        "l2p": {"kernel": ("k_l2p_batched<float,%d,true>" % order if batched
+                           else "fused into " + near_kernel_name(nb, order)), "bound": "hbm",
                 "bytes": leaves * exp_b + n * 12.0 + n * nb * 48.0,
-                "flops": 6.0 * (order * (order + 1) * (order + 2) // 6) * n * nb},
+                "flops": l2p_flops},
     }
     for v in out.values():
         v["peak"] = PEAK_FP32_MFMA if v["bound"] == "mfma" else PEAK_FP32_VALU
@@ -154,10 +155,12 @@ def multi_group(nb):
 
 
 def near_kernel_name(nb, order):
+    """The near-field kernel of a pass timed alone (single stream): the smooth
+    field is fused into it below the matrix-core size."""
     if nb >= 32:
         return "k_p2p_mfma"
     if nb >= 2:
-        return "k_p2p_multi<float,%d>" % multi_group(nb)
+        return "k_p2p_multi<float,%d,%d>" % (multi_group(nb), order)
     return "k_p2p_l2p<float,%d,true>" % order
 
 
@@ -240,12 +243,15 @@ def read_counter_csv(d):
     out = {}
     with open(files[0]) as fh:
         for row in csv.DictReader(fh):
-            out.setdefault((row["Kernel_Name"], row["Dispatch_Id"]), 0.0)
-            out[(row["Kernel_Name"], row["Dispatch_Id"])] += float(row["Counter_Value"])
+            key = (row["Kernel_Name"], int(row["Dispatch_Id"]))
+            out[key] = out.get(key, 0.0) + float(row["Counter_Value"])
     per = {}
-    for (name, _), v in out.items():
+    for (name, did), v in sorted(out.items(), key=lambda kv: kv[0][1]):
         per.setdefault(name, []).append(v)
-    return per
+    # the run's closing calibration copy: its last copy dispatch
+    copies = [(did, v) for (name, did), v in out.items() if "copy" in name.lower()]
+    calib = max(copies)[1] if copies else None
+    return per, calib
 
 
 def short_kernel_name(name):
@@ -259,15 +265,10 @@ def write_traffic_record(workload_name, fetch_dir, write_dir, summary_path):
     dispatch) into the traffic record of one workload: bytes per launch,
     each counter scaled by what it reads for the run's closing 256 MiB device
     copy (the calibration: a copy fetches and writes 256 MiB)."""
-    fetch, write = read_counter_csv(fetch_dir), read_counter_csv(write_dir)
-
-    def calib(per, key):
-        v = [x for k, xs in per.items() if "copy" in k.lower() or "Copy" in k for x in xs]
-        if not v:
-            raise SystemExit("no calibration copy in the %s run" % key)
-        return (256 << 10) / max(v)
-
-    fs, ws = calib(fetch, "FETCH_SIZE"), calib(write, "WRITE_SIZE")
+    (fetch, cf), (write, cw) = read_counter_csv(fetch_dir), read_counter_csv(write_dir)
+    if not cf or not cw:
+        raise SystemExit("no calibration copy in the counter runs")
+    fs, ws = (256 << 10) / cf, (256 << 10) / cw
     try:
         with open(TRAFFIC_PATH) as fh:
             rec = json.load(fh)
@@ -654,6 +655,8 @@ def bench_film(args, torch, ccfmm, inputs):
     # ---- roofline of the dominant pass (the near field), times from HIP
     # events the library records on the launch stream, every pass alone
     kern = pass_work(li, n, nb, 6)
+    if nb < 32:
+        pt["l2p"] = 0.0  # fused into the near-field kernel (the timer brackets nothing)
     for k, v in kern.items():
         v["ms"] = pt[k]
         if pt[k] <= 0.0:

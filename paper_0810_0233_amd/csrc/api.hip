@@ -474,7 +474,8 @@ static void prepare_batch(Plan& P, int nb, hipStream_t st) {
   }
 }
 
-static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev);
+static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev,
+                        bool fuse_near = true);
 
 // One evaluation.  With graphs on (and a capturable stream), the pass sequence
 // is captured once per (nbatch, moments, fields) and replayed; the capture
@@ -531,7 +532,8 @@ static void ensure_side_stream(Plan& P) {
 // events (ev, 9 of them): [0] start, [1] after P2M, [2] after M2M, [3] after
 // M2L, [4] after L2L, [8] L2P start, [5] end, all on the caller's stream;
 // [6], [7] around the near field.
-static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev) {
+static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t* ev,
+                        bool fuse_near) {
   if (ev) CCFMM_HIP(hipEventRecord(ev[0], st));
   run_permute(P, nb, d_m, st);
   if (P.overlap) {
@@ -555,7 +557,7 @@ static void eval_passes(Plan& P, int nb, const double* d_m, double* d_H, hipStre
     CCFMM_HIP(hipStreamWaitEvent(st, P.ev_join, 0));
     if (ev) CCFMM_HIP(hipEventRecord(ev[8], st));
     run_l2p(P, nb, d_H, st);
-  } else if (nb >= 2) {  // several configurations: two kernels, timed apart
+  } else if (nb >= P.batched_min || (nb >= 2 && !fuse_near)) {  // two kernels, timed apart
     if (ev) CCFMM_HIP(hipEventRecord(ev[6], st));
     run_near(P, nb, d_H, st);
     if (ev) {
@@ -1044,7 +1046,8 @@ static double measure_cost_far(Plan& P, int nb, const double* d_m, hipStream_t s
   P.overlap = false;
   float m2l = 0.f, near = 0.f;
   try {
-    for (int rep = 0; rep < 2; rep++) eval_passes(P, nb, d_m, Hs, st, ev);
+    // the near field alone (not fused with the smooth field): the per-pair cost
+    for (int rep = 0; rep < 2; rep++) eval_passes(P, nb, d_m, Hs, st, ev, false);
     CCFMM_HIP(hipEventSynchronize(ev[5]));
     CCFMM_HIP(hipEventElapsedTime(&m2l, ev[2], ev[3]));
     CCFMM_HIP(hipEventElapsedTime(&near, ev[6], ev[7]));

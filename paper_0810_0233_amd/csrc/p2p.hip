@@ -549,9 +549,13 @@ __device__ __forceinline__ void p2pk_run(const T* __restrict__ src, const P2PLo<
   }
 }
 
-template <typename T, int KB>
+// PL > 0: also add the smooth field of the cell's local expansion (order PL),
+// the single-stream form; PL = 0: the near field alone (written, not added),
+// the form that runs beside the expansion passes
+template <typename T, int KB, int PL>
 __global__ void __launch_bounds__(64 * kP2PWaves, 3) k_p2p_multi(P2PArgs a, const T* __restrict__ y,
-                                                                 const T* __restrict__ msort, double* __restrict__ H) {
+                                                                 const T* __restrict__ msort, const T* __restrict__ V,
+                                                                 double* __restrict__ H) {
   constexpr int NW = p2pk_words<T, KB>();
   constexpr int kSlots = 64 + kP2PPad;
   __shared__ __attribute__((aligned(16))) T sS[kP2PWaves][kSlots * NW];
@@ -735,13 +739,24 @@ __global__ void __launch_bounds__(64 * kP2PWaves, 3) k_p2p_multi(P2PArgs a, cons
   if (act && sub == 0) {
     const double s3 = a.inv_s3;
     const int64_t pi = a.perm[it];
+    if constexpr (PL > 0) {
+      constexpr int NS = nstride(PL);
+      const int pl = a.leaf_p ? a.leaf_p[ch.leaf] : PL;
 #pragma unroll
-    for (int b = 0; b < KB; b++) {
-      if (b < ncfg) {
-        double* o = H + ((int64_t)(cfg0 + b) * n + pi) * 3;
-        o[0] = s3 * h[b][0];
-        o[1] = s3 * h[b][1];
-        o[2] = s3 * h[b][2];
+      for (int b = 0; b < KB; b++)
+        if (b < ncfg)
+          l2p_write<T, PL>(V + a.voff + ((int64_t)ch.leaf * a.nb + cfg0 + b) * NS, pl, tg.x, tg.y, tg.z, h[b][0],
+                           h[b][1], h[b][2], s3, H + ((int64_t)(cfg0 + b) * n + pi) * 3);
+    } else {
+      (void)V;
+#pragma unroll
+      for (int b = 0; b < KB; b++) {
+        if (b < ncfg) {
+          double* o = H + ((int64_t)(cfg0 + b) * n + pi) * 3;
+          o[0] = s3 * h[b][0];
+          o[1] = s3 * h[b][1];
+          o[2] = s3 * h[b][2];
+        }
       }
     }
   }
@@ -1292,10 +1307,23 @@ static int multi_group(int nb, bool fp64) {
   return best;
 }
 
-template <typename T, int KB>
+template <typename T, int KB, int PL>
 static void multi_launch(Plan& P, const P2PArgs& a, const T* y, int nb, double* d_H, hipStream_t st) {
   dim3 grid(ceil_div(P.nchunks_cap, kP2PWaves), ceil_div(nb, KB));
-  k_p2p_multi<T, KB><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), d_H);
+  k_p2p_multi<T, KB, PL><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
+}
+
+// the few-configuration near field in groups of multi_group(nb); PL > 0 adds
+// the smooth field of order PL
+template <typename T, int PL>
+static void multi_dispatch(Plan& P, const P2PArgs& a, const T* y, int nb, double* d_H, hipStream_t st) {
+  const int kb = multi_group(nb, std::is_same<T, double>::value);
+  if (kb == 2)
+    multi_launch<T, 2, PL>(P, a, y, nb, d_H, st);
+  else if (kb == 4)
+    multi_launch<T, 4, PL>(P, a, y, nb, d_H, st);
+  else if constexpr (!std::is_same<T, double>::value)
+    multi_launch<T, 8, PL>(P, a, y, nb, d_H, st);
 }
 
 // near field alone: written (not added) to H in the caller's order
@@ -1305,13 +1333,7 @@ static void near_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const T* y = fp64 ? (const T*)P.yd.p : (const T*)P.yf.p;
   P2PArgs a = p2p_args(P, nb, fp64);
   if (nb >= 2 && nb < P.batched_min) {
-    const int kb = multi_group(nb, fp64);
-    if (kb == 2)
-      multi_launch<T, 2>(P, a, y, nb, d_H, st);
-    else if (kb == 4)
-      multi_launch<T, 4>(P, a, y, nb, d_H, st);
-    else if constexpr (!std::is_same<T, double>::value)
-      multi_launch<T, 8>(P, a, y, nb, d_H, st);
+    multi_dispatch<T, 0>(P, a, y, nb, d_H, st);
   } else if (nb >= P.batched_min) {
     const int nl = P.lev[P.L]->ncells;
     const int32_t* n32 = P.chunk_cnt.as<int32_t>() + 3 * (nl + 1) + nl;  // off32[nl]
@@ -1339,10 +1361,11 @@ static void l2p_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   CCFMM_HIP(hipGetLastError());
 }
 
-// both in one pass (single stream, one configuration at a time)
+// both in one pass (single stream): one configuration, or 2..31 configurations
+// sharing each pair's geometry; from the matrix-core size, two kernels
 template <typename T, int PP>
 static void fused_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
-  if (nb >= 2) {  // near field for several configurations, then the smooth field added
+  if (nb >= P.batched_min) {  // matrix-core near field, then the smooth field added
     near_impl<T, PP>(P, nb, d_H, st);
     l2p_impl<T, PP>(P, nb, d_H, st);
     return;
@@ -1350,6 +1373,11 @@ static void fused_impl(Plan& P, int nb, double* d_H, hipStream_t st) {
   const bool fp64 = std::is_same<T, double>::value;
   const T* y = fp64 ? (const T*)P.yd.p : (const T*)P.yf.p;
   P2PArgs a = p2p_args(P, nb, fp64);
+  if (nb >= 2) {
+    multi_dispatch<T, PP>(P, a, y, nb, d_H, st);
+    CCFMM_HIP(hipGetLastError());
+    return;
+  }
   dim3 grid(ceil_div(P.nchunks_cap, kP2PWaves), nb);
   k_p2p_l2p<T, PP, true><<<grid, 64 * kP2PWaves, 0, st>>>(a, y, P.m_sorted.as<T>(), P.V.as<T>(), d_H);
   CCFMM_HIP(hipGetLastError());

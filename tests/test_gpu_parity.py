@@ -766,6 +766,12 @@ def test_few_configuration_near_field(ref, precision, nb):
     pl = plan_for(pos, 5, 0.5, 12.0, box, precision=precision, max_batch=nb)
     Hb = pl.eval(mb)
     pl.destroy()
+    # one stream: the near field and the smooth field in one kernel
+    one = plan_for(pos, 5, 0.5, 12.0, box, precision=precision, max_batch=nb, overlap_near=0)
+    e = rel_rms(one.eval(mb), Hb)
+    print("nb=%d single-stream (fused) vs overlapped %.3e" % (nb, e), flush=True)
+    assert e <= (1e-13 if precision == ccfmm.PREC_FP64 else 2e-6)
+    one.destroy()
     single = plan_for(pos, 5, 0.5, 12.0, box, precision=precision, max_batch=1)
     for b in sorted({0, nb // 2, nb - 1}):
         e = rel_rms(Hb[b], single.eval(mb[b:b + 1])[0])
