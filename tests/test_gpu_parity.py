@@ -13,35 +13,14 @@ import numpy as np
 import pytest
 
 from paper_0810_0233_amd import ccfmm, inputs
+from parity_bars import check_per_dipole
 
 pytestmark = pytest.mark.gpu
 
 FP64_BAR = 1e-10
 MIXED_BAR = 1e-5
-# per-dipole bars of the mixed form against the oracle (design notes, parity
-# bars): the 1e-5 bound held by 99% of the dipoles one by one, and no dipole's
-# error above 1e-4 of the RMS field
-P99_BAR = 1e-5
-MAXN_BAR = 1e-4
-
-
 def rel_rms(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
-
-
-def per_dipole(H, Href):
-    """Median and 99th percentile of |dH_i| / |H_i| over dipoles (and
-    configurations), and the largest |dH_i| over the RMS of |H|."""
-    d = np.linalg.norm(np.asarray(H) - np.asarray(Href), axis=-1).ravel()
-    r = np.linalg.norm(np.asarray(Href), axis=-1).ravel()
-    e = d[r > 0] / r[r > 0]
-    return float(np.median(e)), float(np.percentile(e, 99)), float(d.max() / np.sqrt(np.mean(r * r)))
-
-
-def check_per_dipole(H, Href, label):
-    med, p99, mx = per_dipole(H, Href)
-    print("%s per dipole vs oracle: median %.2e p99 %.2e max/rms %.2e" % (label, med, p99, mx), flush=True)
-    assert p99 <= P99_BAR and mx <= MAXN_BAR, (med, p99, mx)
 
 
 @pytest.fixture(scope="module")
@@ -124,7 +103,7 @@ def test_bounding_box_and_clusters(ref):
     assert rel_rms(pl.eval(m), H_ref) <= FP64_BAR
 
 
-def test_mixed_precision_vs_fp64():
+def test_mixed_precision_vs_fp64(ref):
     pos, box = inputs.ferrofluid(20000, 2001)
     m = inputs.random_moments(20000, 2002)
     H64 = plan_for(pos, 6, 0.5, 0.0, box).eval(m)
@@ -132,6 +111,9 @@ def test_mixed_precision_vs_fp64():
     e = rel_rms(H32, H64)
     print("mixed vs fp64 rel rms = %.3e" % e, flush=True)
     assert e <= MIXED_BAR
+    H_ref = ref.fmm(pos, m, 6, 0.5, box=box)
+    assert rel_rms(H64, H_ref) <= FP64_BAR
+    check_per_dipole(H32, H_ref, "ferrofluid 20000 mixed")
 
 
 def test_batched_equals_single(ref):
@@ -353,8 +335,12 @@ def test_batched_matrix_core_near_field(ref, precision):
         e = rel_rms(Hb[b], Hs)
         print("batched vs single b=%d: %.3e" % (b, e), flush=True)
         assert e <= (1e-13 if precision == ccfmm.PREC_FP64 else 2e-6)
-        if precision == ccfmm.PREC_FP64 and b != 7:
-            assert rel_rms(Hb[b], ref.fmm(pos, mb[b], 5, 0.5, box=box)) <= FP64_BAR
+        if b != 7:
+            H_ref = ref.fmm(pos, mb[b], 5, 0.5, box=box)
+            if precision == ccfmm.PREC_FP64:
+                assert rel_rms(Hb[b], H_ref) <= FP64_BAR
+            else:
+                check_per_dipole(Hb[b], H_ref, "matrix-core near field b=%d" % b)
 
 
 @pytest.mark.parametrize("leaf_target", [0.0, 90.0])

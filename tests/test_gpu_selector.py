@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from paper_0810_0233_amd import ccfmm, inputs, selector
+from parity_bars import check_per_dipole
 
 pytestmark = pytest.mark.gpu
 
@@ -135,7 +136,10 @@ def test_random_leaf_params_fp64_match_oracle(ref, seed):
     pl.destroy()
 
 
-def test_leaf_params_mixed_match_fp64():
+def test_leaf_params_mixed_match_fp64(ref):
+    """Random per-cell parameters in mixed precision: within 1e-5 of the FP64
+    plan, and per dipole within the mixed-precision bars of the oracle's
+    per-cell FMM given the same parameters."""
     pos, box, m = cluster_case(711, ncl=8, per=400)
     out = []
     for prec in (ccfmm.PREC_FP64, ccfmm.PREC_MIXED):
@@ -144,8 +148,12 @@ def test_leaf_params_mixed_match_fp64():
         r = np.random.default_rng(12)
         set_params(pl, r.integers(2, 7, nl), r.choice(np.asarray(ccfmm.SEL_THETA), nl))
         out.append(pl.eval(m))
+        ids, pd, thd = per_dipole(pl, pos.shape[0])
         pl.destroy()
     assert rel_rms(out[1], out[0]) <= 1e-5
+    H_ref = ref.fmm_leaf(pos, m, 6, 0.5, leaf_p=pd, leaf_theta=thd, box=box)
+    assert rel_rms(out[0], H_ref) <= FP64_BAR
+    check_per_dipole(out[1], H_ref, "per-cell parameters mixed")
 
 
 def test_invalid_leaf_params_rejected():
