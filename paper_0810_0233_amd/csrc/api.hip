@@ -220,8 +220,8 @@ static void size_expansions(Plan& P, int nb) {
   const size_t es = P.precision == CCFMM_PREC_FP64 ? sizeof(double) : sizeof(float);
   P.Q.ensure(es * std::max<int64_t>(1, off));
   P.V.ensure(es * std::max<int64_t>(1, off));
-  if (P.precision != CCFMM_PREC_FP64 && P.prm.m2l_traceless && P.p <= wide_max_order(true))
-    P.Qr.ensure(sizeof(float) * std::max<int64_t>(1, off / NS * ((P.p * (P.p + 2) + 3) & ~3)));
+  if (P.prm.m2l_traceless && P.p <= wide_max_order(true))
+    P.Qr.ensure(es * std::max<int64_t>(1, off / NS * ((P.p * (P.p + 2) + 3) & ~3)));
   P.m_sorted.ensure(es * 3 * (size_t)P.n * nb);
   if (nb >= P.batched_min) P.m_sorted_t.ensure(es * 3 * (size_t)P.n * nb);
   P.qv_batch = nb;

@@ -187,7 +187,8 @@ void build_dtensors(Plan& P, hipStream_t st) {
                                                  Df);
     CCFMM_HIP(hipGetLastError());
   }
-  if (P.precision != CCFMM_PREC_FP64 && P.p <= wide_max_order(P.prm.m2l_traceless != 0)) build_wide_ops(P, st);
+  if (P.p <= wide_max_order(P.prm.m2l_traceless != 0) && (P.precision != CCFMM_PREC_FP64 || P.prm.m2l_traceless))
+    build_wide_ops(P, st);
   CCFMM_HIP(hipStreamSynchronize(st));  // the host table copies above must finish before scratch2 is reused
   P.dtab_p = P.p;
   P.dtab_keys = keys;

@@ -41,7 +41,7 @@ inline bool m2l_variant_ok(int variant, int order, bool fp64, bool traceless) {
   if (variant == kM2LBlock) return true;
   if (variant == kM2LWave) return order <= 6;
   if (variant == kM2LWide4 || variant == kM2LWide2 || variant == kM2LWide1)
-    return order <= wide_max_order(traceless) && !fp64;
+    return order <= wide_max_order(traceless) && (traceless || !fp64);  // FP64: traceless form only
   return false;
 }
 // the variant a plan gets when the caller names none: the 64-column wide

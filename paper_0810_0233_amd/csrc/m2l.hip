@@ -327,7 +327,21 @@ __global__ void __launch_bounds__(256, 2) k_m2l_wave(const M2LTile* __restrict__
 // and two blocks fit on a compute unit.
 // Zeros read by empty columns: selecting an address instead of a loaded value
 // keeps the loads free of consumers until the products that need them.
-__device__ const float g_zero_row[128] = {};
+// (128 doubles: zero words for either element type)
+__device__ const double g_zero_row[128] = {};
+
+// four consecutive expansion or operator entries: one 16-byte (FP32) or two
+// 16-byte (FP64) accesses
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef f32x4 type;
+};
+template <>
+struct Vec4<double> {
+  typedef f64x4 type;
+};
 
 
 // Operator layout of the wide kernels: slot e of row block mb holds, for
@@ -387,19 +401,20 @@ struct FoldTable {
 };
 
 // Folded moments Qr[row][nred_stride(P)] from the full moments (one thread per
-// expansion row, FP32).
-template <int P>
-__global__ void k_fold_moments(int64_t rows, const float* __restrict__ Q, float* __restrict__ Qr) {
+// expansion row).
+template <typename T, int P>
+__global__ void k_fold_moments(int64_t rows, const T* __restrict__ Q, T* __restrict__ Qr) {
+  using V4 = typename Vec4<T>::type;
   constexpr int NSF = nstride(P), NR = nred(P), NRS = nred_stride(P), NF = nact(P) - nred(P);
   constexpr FoldTable<P> F{};
   constexpr RedFull R{};
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  float q[NSF];
-  const f32x4* in = reinterpret_cast<const f32x4*>(Q + r * NSF);
+  T q[NSF];
+  const V4* in = reinterpret_cast<const V4*>(Q + r * NSF);
 #pragma unroll
   for (int i = 0; i < NSF / 4; i++) {
-    const f32x4 v = in[i];
+    const V4 v = in[i];
     q[4 * i] = v[0];
     q[4 * i + 1] = v[1];
     q[4 * i + 2] = v[2];
@@ -407,33 +422,34 @@ __global__ void k_fold_moments(int64_t rows, const float* __restrict__ Q, float*
   }
 #pragma unroll
   for (int i = 0; i < NF; i++) {
-    const float v = q[F.src[i] - 1];
+    const T v = q[F.src[i] - 1];
     q[F.d1[i] - 1] -= v;
     q[F.d2[i] - 1] -= v;
   }
-  f32x4* out = reinterpret_cast<f32x4*>(Qr + r * NRS);
+  V4* out = reinterpret_cast<V4*>(Qr + r * NRS);
 #pragma unroll
   for (int i = 0; i < NRS / 4; i++) {
-    f32x4 v;
+    V4 v;
 #pragma unroll
-    for (int u = 0; u < 4; u++) v[u] = 4 * i + u < NR ? q[R.full[4 * i + u] - 1] : 0.f;
+    for (int u = 0; u < 4; u++) v[u] = 4 * i + u < NR ? q[R.full[4 * i + u] - 1] : (T)0;
     out[i] = v;
   }
 }
 
 // The n_z >= 2 components of local expansions whose n_z <= 1 components the
 // traceless M2L wrote (lowest z first); padding positions set to zero.
-template <int P>
-__global__ void k_fill_locals(int64_t rows, float* __restrict__ V) {
+template <typename T, int P>
+__global__ void k_fill_locals(int64_t rows, T* __restrict__ V) {
+  using V4 = typename Vec4<T>::type;
   constexpr int NSF = nstride(P), NA = nact(P), NF = nact(P) - nred(P);
   constexpr FoldTable<P> F{};
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  float v[NSF];
-  f32x4* row = reinterpret_cast<f32x4*>(V + r * NSF);
+  T v[NSF];
+  V4* row = reinterpret_cast<V4*>(V + r * NSF);
 #pragma unroll
   for (int i = 0; i < NSF / 4; i++) {
-    const f32x4 a = row[i];
+    const V4 a = row[i];
     v[4 * i] = a[0];
     v[4 * i + 1] = a[1];
     v[4 * i + 2] = a[2];
@@ -442,9 +458,9 @@ __global__ void k_fill_locals(int64_t rows, float* __restrict__ V) {
 #pragma unroll
   for (int i = NF - 1; i >= 0; i--) v[F.src[i] - 1] = -v[F.d1[i] - 1] - v[F.d2[i] - 1];
 #pragma unroll
-  for (int i = NA; i < NSF; i++) v[i] = 0.f;
+  for (int i = NA; i < NSF; i++) v[i] = (T)0;
 #pragma unroll
-  for (int i = 0; i < NSF / 4; i++) row[i] = f32x4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
+  for (int i = 0; i < NSF / 4; i++) row[i] = V4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
 }
 
 template <int P, bool RED = false>
@@ -498,10 +514,11 @@ __device__ __forceinline__ int wide_slot_dindex(int e) {
   return wide_op_index<P, RED>(16 * mb + (l & 15), (l >> 4) * W::KS + ks);
 }
 
-// Every derivative-table row expanded into that layout (FP32), once per
-// table: a step's operator is then one contiguous block of memory.
-template <int P, bool RED>
-__global__ void k_expand_ops(int64_t nrows, const float* __restrict__ Df, float* __restrict__ Dx) {
+// Every derivative-table row expanded into that layout (in the plan's
+// precision), once per table: a step's operator is then one contiguous block
+// of memory.
+template <typename T, int P, bool RED>
+__global__ void k_expand_ops(int64_t nrows, const T* __restrict__ Df, T* __restrict__ Dx) {
   using W = WideOp<P, RED>;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows * W::NEP) return;
@@ -510,21 +527,24 @@ __global__ void k_expand_ops(int64_t nrows, const float* __restrict__ Df, float*
   Dx[t] = Df[r * drow_stride(P) + wide_slot_dindex<P, RED>(e)];
 }
 
-template <int P, bool RED>
-static void expand_ops_red(Plan& P_, hipStream_t st) {
+template <typename T, int P, bool RED>
+static void expand_ops_red(Plan& P_, const T* D, hipStream_t st) {
   using W = WideOp<P, RED>;
-  float* Dx = reinterpret_cast<float*>(P_.Dx.ensure(sizeof(float) * (size_t)P_.nrows * W::NEP));
+  T* Dx = reinterpret_cast<T*>(P_.Dx.ensure(sizeof(T) * (size_t)P_.nrows * W::NEP));
   const int64_t nt = P_.nrows * W::NEP;
-  k_expand_ops<P, RED><<<ceil_div(nt, 256), 256, 0, st>>>(P_.nrows, P_.Df.as<float>(), Dx);
+  k_expand_ops<T, P, RED><<<ceil_div(nt, 256), 256, 0, st>>>(P_.nrows, D, Dx);
   CCFMM_HIP(hipGetLastError());
 }
 
+// FP64 plans use the wide kernels in the traceless form only
 template <int P>
 static void expand_ops_impl(Plan& P_, hipStream_t st) {
-  if (P_.prm.m2l_traceless) {
-    expand_ops_red<P, true>(P_, st);
+  if (P_.precision == CCFMM_PREC_FP64) {
+    if (P_.prm.m2l_traceless) expand_ops_red<double, P, true>(P_, P_.Dd.as<double>(), st);
+  } else if (P_.prm.m2l_traceless) {
+    expand_ops_red<float, P, true>(P_, P_.Df.as<float>(), st);
   } else {
-    if constexpr (P <= 6) expand_ops_red<P, false>(P_, st);
+    if constexpr (P <= 6) expand_ops_red<float, P, false>(P_, P_.Df.as<float>(), st);
   }
 }
 
@@ -544,26 +564,29 @@ void build_wide_ops(Plan& P, hipStream_t st) {
 
 // RED: the traceless form (Q holds the folded moments, nred_stride(P) per
 // row; only the n_z <= 1 rows of V are written, k_fill_locals does the rest).
-template <int P, int CB, bool RED>
+template <typename T, int P, int CB, bool RED>
 __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile* __restrict__ tiles,
                                                    const int32_t* __restrict__ tile_order, int64_t ntiles,
                                                    const int32_t* __restrict__ tile_tgt,
                                                    const int32_t* __restrict__ step_delta,
                                                    const int32_t* __restrict__ step_src,
-                                                   const float* __restrict__ Dop, const float* __restrict__ Q,
-                                                   float* __restrict__ V, LevelOffsets lo, int nb, int TB, int TC) {
+                                                   const T* __restrict__ Dop, const T* __restrict__ Q,
+                                                   T* __restrict__ V, LevelOffsets lo, int nb, int TB, int TC) {
   using W = WideOp<P, RED>;
+  using V4 = typename Vec4<T>::type;
+  using AccT = typename Acc<T>::type;
   constexpr int NS = W::NS, KS = W::KS, MB = W::MB, NP = W::NP, RV = W::RV;
   constexpr int NSV = nstride(P);  // row stride of V (and of Q in the full form)
   constexpr int K4 = W::K4, KT = W::KT;  // full groups of 4 steps, steps left over
   constexpr int NEP = W::NEP;             // operator words per step (padded)
-  __shared__ __attribute__((aligned(16))) float sT[2][NEP];
+  __shared__ __attribute__((aligned(32))) T sT[2][NEP];
+  constexpr int kOpBytes = NEP * (int)sizeof(T);  // a multiple of 1024 (rows padded to 256 entries)
   const int t = threadIdx.x, lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   // tiles are launched longest first (greedy balance over the compute units)
   if ((int64_t)blockIdx.x >= ntiles) return;
   const M2LTile tl = tiles[tile_order[blockIdx.x]];
-  const float* Ql = Q + (RED ? lo.qoff[tl.level] / NSV * NS : lo.qoff[tl.level]);
+  const T* Ql = Q + (RED ? lo.qoff[tl.level] / NSV * NS : lo.qoff[tl.level]);
   const int nsteps = tl.nsteps;
 
   // this lane's columns: 16 CB w + 16 cb + lane % 16, fragment rows kq KS .. kq KS + KS - 1
@@ -584,14 +607,14 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
 #pragma unroll
     for (int cb = 0; cb < CB; cb++) src[cb] = step_src[st * TC + (ctc[cb] >= 0 ? ctc[cb] : 0)];
   };
-  auto load_b = [&](const int (&src)[CB], float (&B)[CB][KS]) {
+  auto load_b = [&](const int (&src)[CB], T (&B)[CB][KS]) {
 #pragma unroll
     for (int cb = 0; cb < CB; cb++) {
       const bool ok = ctc[cb] >= 0 && src[cb] >= 0;
       // both candidates in the global address space: a generic pointer would
       // make these flat loads, which the LDS wait counter also tracks, so
       // every wait for an operator fragment would wait for them too
-      typedef const __attribute__((address_space(1))) float* gptr;
+      typedef const __attribute__((address_space(1))) T* gptr;
       const gptr q = ok ? (gptr)(Ql + ((int64_t)src[cb] * nb + cb_b[cb]) * NS + kq * KS) : (gptr)g_zero_row;
 #pragma unroll
       for (int ks = 0; ks < KS; ks++) B[cb][ks] = q[ks];
@@ -599,33 +622,34 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   };
   // the operator of step s (its expanded row, already in LDS order) goes from
   // memory straight into sT[buf] (no registers): 16-byte loads, lane l of
-  // wavefront w covering words 1024 r + 256 w + 4 l .. + 3
+  // wavefront w covering bytes 4096 r + 1024 w + 16 l .. + 15
   auto load_op = [&](int s, int buf) {
-    const float* orow = Dop + (int64_t)step_delta[tl.step0 + s] * NEP;
+    const char* orow = reinterpret_cast<const char*>(Dop + (int64_t)step_delta[tl.step0 + s] * NEP);
+    char* dst = reinterpret_cast<char*>(&sT[buf][0]);
 #pragma unroll
-    for (int r = 0; r < (NEP + 1023) / 1024; r++) {
-      const int o = 1024 * r + 256 * w;
-      if (NEP % 1024 == 0 || o < NEP)  // uniform over the wavefront
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(orow + o + 4 * lane),
-                                         (__attribute__((address_space(3))) void*)&sT[buf][o], 16, 0, 0);
+    for (int r = 0; r < (kOpBytes + 4095) / 4096; r++) {
+      const int o = 4096 * r + 1024 * w;
+      if (kOpBytes % 4096 == 0 || o < kOpBytes)  // uniform over the wavefront
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(orow + o + 16 * lane),
+                                         (__attribute__((address_space(3))) void*)(dst + o), 16, 0, 0);
     }
   };
   // all of this wavefront's memory loads have landed (vmcnt = 0)
   auto wait_loads = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
 
-  f32x4 acc[MB][CB];
+  AccT acc[MB][CB];
 #pragma unroll
   for (int mb = 0; mb < MB; mb++)
 #pragma unroll
-    for (int cb = 0; cb < CB; cb++) acc[mb][cb] = f32x4{0, 0, 0, 0};
+    for (int cb = 0; cb < CB; cb++) acc[mb][cb] = AccT{0, 0, 0, 0};
   // vector-unit rows: this lane's partial sums over its lane group's k range
-  float pv[CB][RV > 0 ? RV : 1];
+  T pv[CB][RV > 0 ? RV : 1];
 #pragma unroll
   for (int cb = 0; cb < CB; cb++)
 #pragma unroll
-    for (int j = 0; j < (RV > 0 ? RV : 1); j++) pv[cb][j] = 0.f;
+    for (int j = 0; j < (RV > 0 ? RV : 1); j++) pv[cb][j] = (T)0;
 
-  float B0[CB][KS], B1[CB][KS];
+  T B0[CB][KS], B1[CB][KS];
   int srcA[CB], srcB[CB];
   if (nsteps > 0) {
     load_op(0, 0);
@@ -636,7 +660,7 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   wait_loads();
   __syncthreads();
   // one step: products on sT[cur] x Bc while the next operator and B arrive
-  auto step = [&](int s, int cur, float (&Bc)[CB][KS], float (&Bn)[CB][KS], int (&srcN)[CB], int (&srcN2)[CB]) {
+  auto step = [&](int s, int cur, T (&Bc)[CB][KS], T (&Bn)[CB][KS], int (&srcN)[CB], int (&srcN2)[CB]) {
     const bool more = s + 1 < nsteps;
     if (more) {
       load_op(s + 1, cur ^ 1);
@@ -644,13 +668,13 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
       if (s + 2 < nsteps) load_src(s + 2, srcN2);
     }
     __builtin_amdgcn_sched_barrier(0);  // issue the loads before the products
-    const float* T0 = sT[cur];
+    const T* T0 = sT[cur];
 #pragma unroll
     for (int k4 = 0; k4 < K4; k4++) {
-      f32x4 av[MB];
+      V4 av[MB];
 #pragma unroll
       for (int mb = 0; mb < MB; mb++)
-        av[mb] = *reinterpret_cast<const f32x4*>(T0 + mb * KS * 64 + k4 * 256 + 4 * lane);
+        av[mb] = *reinterpret_cast<const V4*>(T0 + mb * KS * 64 + k4 * 256 + 4 * lane);
 #pragma unroll
       for (int ku = 0; ku < 4; ku++)
 #pragma unroll
@@ -662,22 +686,22 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     for (int t = 0; t < KT; t++) {
 #pragma unroll
       for (int mb = 0; mb < MB; mb++) {
-        const float a = T0[mb * KS * 64 + K4 * 256 + t * 64 + lane];
+        const T a = T0[mb * KS * 64 + K4 * 256 + t * 64 + lane];
 #pragma unroll
         for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(a, Bc[cb][4 * K4 + t], acc[mb][cb]);
       }
     }
     if constexpr (RV > 0) {
-      const float* Tv = T0 + W::NEM + kq * W::KSTR;
+      const T* Tv = T0 + W::NEM + kq * W::KSTR;
 #pragma unroll
       for (int i = 0; i < W::KSTR / 4; i++) {
-        const f32x4 tv = *reinterpret_cast<const f32x4*>(Tv + 4 * i);
+        const V4 tv = *reinterpret_cast<const V4*>(Tv + 4 * i);
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           const int r = 4 * i + u;
           if (r < RV * KS) {
 #pragma unroll
-            for (int cb = 0; cb < CB; cb++) pv[cb][r % RV] = fmaf(tv[u], Bc[cb][r / RV], pv[cb][r % RV]);
+            for (int cb = 0; cb < CB; cb++) pv[cb][r % RV] = fma(tv[u], Bc[cb][r / RV], pv[cb][r % RV]);
           }
         }
       }
@@ -696,18 +720,18 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     if (ctc[cb] < 0) continue;
     const int tgt = tile_tgt[tl.tgt0 + ctc[cb]];
     if (tgt < 0) continue;
-    float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NSV;
+    T* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NSV;
 #pragma unroll
     for (int mb = 0; mb < MB; mb++) {
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int m = 16 * mb + acc_row<float>(kq, r);
+        const int m = 16 * mb + acc_row<T>(kq, r);
         if (m < NP) {
           const int f = RED ? (int)kRedFull.full[m] : m + 1;
           const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
           out[f - 1] = (deg & 1) ? -acc[mb][cb][r] : acc[mb][cb][r];
         } else if (!RED && m < NS) {
-          out[m] = 0.f;
+          out[m] = (T)0;
         }
       }
     }
@@ -728,14 +752,14 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
       if (ctc[cb] < 0) continue;
       const int tgt = tile_tgt[tl.tgt0 + ctc[cb]];
       if (tgt < 0) continue;
-      float* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NSV;
+      T* out = V + lo.qoff[tl.level] + ((int64_t)tgt * nb + cb_b[cb]) * NSV;
       // the traceless form writes the RV rows only (the fill writes the rest)
       constexpr int NW = RED ? RV : NS - 16 * MB;
 #pragma unroll
       for (int j0 = 0; j0 < NW; j0 += 4) {
         const int j = j0 + kq;
         if (j < NW) {
-          float v = 0.f;
+          T v = (T)0;
           int f = 16 * MB + j + 1;
 #pragma unroll
           for (int jj = 0; jj < RV; jj++)
@@ -757,20 +781,21 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
   for (int l = 0; l <= P.L; l++) lo.qoff[l] = P.lev[l]->qoff;
   const T* D = std::is_same<T, double>::value ? (const T*)P.Dd.p : (const T*)P.Df.p;
   if (P.ntiles == 0) return;
-  if constexpr (std::is_same<T, float>::value && PP <= 8) {
+  constexpr bool kFP64 = std::is_same<T, double>::value;
+  if constexpr (PP <= 8) {
     const bool red = P.prm.m2l_traceless != 0;
     if ((P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1) &&
-        PP <= wide_max_order(red)) {
+        PP <= wide_max_order(red) && (red || !kFP64)) {
       const unsigned nblk = (unsigned)P.ntiles;
       const int64_t rows = P.qv_elems / nstride(PP);
       if (red) {
-        k_fold_moments<PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.Q.as<float>(), P.Qr.as<float>());
+        k_fold_moments<T, PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.Q.as<T>(), P.Qr.as<T>());
         CCFMM_HIP(hipGetLastError());
       }
 #define CCFMM_WIDE(CB, RED)                                                                                          \
-  k_m2l_wide<PP, CB, RED><<<nblk, 256, 0, st>>>(                                                                     \
+  k_m2l_wide<T, PP, CB, RED><<<nblk, 256, 0, st>>>(                                                                  \
       P.tiles.as<M2LTile>(), P.tile_order.as<int32_t>(), P.ntiles, P.tile_tgt.as<int32_t>(),                        \
-      P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), P.Dx.as<float>(), RED ? P.Qr.as<T>() : P.Q.as<T>(),     \
+      P.step_delta.as<int32_t>(), P.step_src.as<int32_t>(), P.Dx.as<T>(), RED ? P.Qr.as<T>() : P.Q.as<T>(),         \
       P.V.as<T>(), lo, nb, P.TB, P.TC)
       if (red) {
         if (P.tiles_variant == kM2LWide4)
@@ -780,7 +805,7 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
         else
           CCFMM_WIDE(1, true);
       } else {
-        if constexpr (PP <= 6) {  // the full form's operator fits up to order 6
+        if constexpr (PP <= 6 && !kFP64) {  // the full form's operator fits up to order 6
           if (P.tiles_variant == kM2LWide4)
             CCFMM_WIDE(4, false);
           else if (P.tiles_variant == kM2LWide2)
@@ -792,14 +817,15 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
 #undef CCFMM_WIDE
       CCFMM_HIP(hipGetLastError());
       if (red) {
-        k_fill_locals<PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.V.as<float>());
+        k_fill_locals<T, PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.V.as<T>());
         CCFMM_HIP(hipGetLastError());
       }
       return;
     }
   }
   if (P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1)
-    fail(CCFMM_EINVAL, "wide M2L variants need mixed precision and order <= 6 (8 in the traceless form)");
+    fail(CCFMM_EINVAL, "wide M2L variants need order <= 8 in the traceless form (mixed precision: <= 6 in the "
+                       "full form)");
   if (P.tiles_variant == kM2LWave) {
     if constexpr (PP <= 6) {
       k_m2l_wave<T, PP><<<ceil_div(P.ntiles, 4), 256, 0, st>>>(
