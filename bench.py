@@ -637,12 +637,15 @@ def bench_film(args, torch, ccfmm, inputs):
             out["speedup_learned_eval_vs_best_uniform"] = best["eval_ms"] / (1e3 * t_learned_eval)
     fixed.destroy()
 
-    # ---- the plain FP64 GPU FMM, fixed (6, 0.4): the same step
+    # ---- the plain FP64 GPU FMM, fixed (6, 0.4): the same step, with the
+    # same forms as the mixed plans (traceless M2L on the FP64 matrix cores,
+    # near field beside the expansion passes)
     if not args.skip_fp64:
         p64 = make(ccfmm.PREC_FP64)
         p64.autotune(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
         t64 = timed(step(p64), max(2, args.steps // 5), 1)
         out["fp64_full_step_ms"] = 1e3 * t64
+        out["fp64_m2l_variant"] = p64.info()["m2l_variant"]
         out["fp64_passes_ms"] = p64.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
         out["speedup_vs_fp64_step"] = t64 / t_learned
         out["eps_prec_fixed_mixed"] = dev_rel_rms(H_fixed, d_H)
@@ -1069,7 +1072,9 @@ def main():
     out = {}
     # ---- plain FP64 GPU FMM
     if not args.skip_fp64:
-        plan64 = make(ccfmm.PREC_FP64, overlap_near=0)  # the plain form: one stream
+        # the FP64 plan with the same forms as the mixed one (traceless M2L on
+        # the FP64 matrix cores, near field beside the expansion passes)
+        plan64 = make(ccfmm.PREC_FP64)
         plan64.autotune(nb, d_m.data_ptr(), d_H64.data_ptr(), sh)
         t_step64 = time_steps(plan64, d_H64, True, max(2, args.steps // 2), 1)
         t_eval64 = time_steps(plan64, d_H64, False, max(2, args.steps // 2), 1)
@@ -1079,11 +1084,19 @@ def main():
         out["fp64_full_step_ms"] = 1e3 * t_step64
         out["fp64_eval_ms"] = 1e3 * t_eval64
         out["fp64_passes_ms"] = passes64
+        out["fp64_m2l_variant"] = plan64.info()["m2l_variant"]
         out["speedup_vs_fp64_step"] = t_step64 / t_step
         out["speedup_vs_fp64_eval"] = t_eval64 / t_eval
         out["eps_prec"] = rel_rms(H_mixed, H64)
         log("fp64 step %.3f ms eval %.3f ms; eps_prec %.3e" % (1e3 * t_step64, 1e3 * t_eval64, out["eps_prec"]))
         plan64.destroy()
+        # beside it, the plain form: one stream, full (dense) M2L operator
+        plan64b = make(ccfmm.PREC_FP64, overlap_near=0, m2l_traceless=0)
+        t_step64b = time_steps(plan64b, d_H64, True, max(2, args.steps // 2), 1)
+        out["fp64_one_stream_full_operator_step_ms"] = 1e3 * t_step64b
+        out["speedup_vs_fp64_one_stream_full_operator_step"] = t_step64b / t_step
+        log("fp64 one stream, full operator: step %.3f ms" % (1e3 * t_step64b))
+        plan64b.destroy()
     # ---- error against the direct sum at sampled dipoles (FP64 on the GPU), configuration 0
     rng = np.random.default_rng(7)
     idx = np.sort(rng.choice(n, size=min(args.samples, n), replace=False)).astype(np.int64)

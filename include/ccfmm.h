@@ -79,8 +79,8 @@ typedef struct {
                              wavefronts sharing one operator per
                              step (64-column tiles), 1 = independent wavefronts (16 columns,
                              orders <= 6), 2 / 3 / 4 = wide blocks with a double-buffered
-                             operator (256 / 128 / 64 columns; mixed precision, orders <= 6,
-                             <= 8 with m2l_traceless).
+                             operator (256 / 128 / 64 columns; orders <= 8 with m2l_traceless,
+                             FP64 included; mixed precision only and orders <= 6 without).
                              A variant the order or precision cannot use falls back to 0;
                              ccfmm_plan_autotune can choose */
   int32_t use_graph;      /* 1: evaluations are captured once into a HIP graph (per batch size
@@ -193,8 +193,10 @@ int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, 
 /* M2L autotuner: times every (kernel variant, class bits) combination on this
  * plan's tiles for nbatch configurations of the device moments d_m (d_H is a
  * scratch field buffer of the same shape), keeps the fastest in the plan and
- * writes up to max_out timings to out (*n_out = number written).  Synchronises
- * the stream.  The field values do not depend on the choice. */
+ * writes up to max_out timings to out (*n_out = number written): the median of
+ * three launches, or a single launch for a combination whose first launch took
+ * more than twice the best median so far.  Synchronises the stream.  The field
+ * values do not depend on the choice (beyond rounding). */
 int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream,
                         ccfmm_tune_entry* out, int32_t max_out, int32_t* n_out);
 

@@ -825,27 +825,38 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
     CCFMM_HIP(hipEventCreate(&e0));
     CCFMM_HIP(hipEventCreate(&e1));
     std::vector<ccfmm_tune_entry> res;
-    const int variants[5] = {kM2LBlock, kM2LWave, kM2LWide4, kM2LWide2, kM2LWide1};
+    // the wide kernels first (usually the fastest); a combination whose first
+    // timed launch takes more than twice the best median so far keeps that
+    // one timing and is not repeated (on large batches the others cost
+    // several times the best per launch)
+    const int variants[5] = {kM2LWide1, kM2LWide2, kM2LWide4, kM2LBlock, kM2LWave};
     const int bits[3] = {0, 3, 6};
+    double best_ms = INFINITY;
+    auto time_m2l = [&]() {
+      CCFMM_HIP(hipEventRecord(e0, st));
+      run_m2l(P, nbatch, st);
+      CCFMM_HIP(hipEventRecord(e1, st));
+      CCFMM_HIP(hipEventSynchronize(e1));
+      float t;
+      CCFMM_HIP(hipEventElapsedTime(&t, e0, e1));
+      return t;
+    };
     for (int v : variants) {
       if (!m2l_variant_ok(v, P.p, P.precision == CCFMM_PREC_FP64, P.prm.m2l_traceless != 0)) continue;
       for (int cb : bits) {
         P.m2l_variant = v;
         P.class_bits = cb;
         prepare_batch(P, nbatch, st);
-        run_m2l(P, nbatch, st);  // warm-up
-        std::vector<float> ms;
-        for (int r = 0; r < 3; r++) {
-          CCFMM_HIP(hipEventRecord(e0, st));
-          run_m2l(P, nbatch, st);
-          CCFMM_HIP(hipEventRecord(e1, st));
-          CCFMM_HIP(hipEventSynchronize(e1));
-          float t;
-          CCFMM_HIP(hipEventElapsedTime(&t, e0, e1));
-          ms.push_back(t);
+        const float first = time_m2l();  // also the warm-up
+        if ((double)first > 2.0 * best_ms) {
+          res.push_back(ccfmm_tune_entry{v, cb, (double)first, P.nsteps});
+          continue;
         }
+        std::vector<float> ms;
+        for (int r = 0; r < 3; r++) ms.push_back(time_m2l());
         std::sort(ms.begin(), ms.end());
         res.push_back(ccfmm_tune_entry{v, cb, (double)ms[1], P.nsteps});
+        best_ms = std::min(best_ms, (double)ms[1]);
       }
     }
     (void)hipEventDestroy(e0);
