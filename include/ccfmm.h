@@ -104,6 +104,10 @@ typedef struct {
   double sel_cost_far;    /* selector = 1: cost of one far cell relative to one direct dipole
                              pair in the selection; <= 0 (default): measured on the plan (M2L and
                              near-field times of one evaluation, each pass alone) */
+  int64_t device_mem_cap; /* bytes of device memory the plan may hold (its buffers and the
+                             temporaries of its calls); 0 (default): no cap.  A call that would
+                             pass it fails with CCFMM_ENOMEM; the plan stays destroyable, and
+                             after a failed evaluation it evaluates again at sizes that fit */
 } ccfmm_params;
 
 /* One timed M2L configuration of ccfmm_plan_autotune. */
@@ -139,6 +143,7 @@ typedef struct {
   int32_t learned;                      /* per-cell parameters of the learned selector in use */
   double judge_err;                     /* the judge's relative RMS difference at the last selection */
   double sel_cost_far;                  /* far-cell cost used at the last selection */
+  int64_t device_bytes;                 /* device memory the plan holds now */
 } ccfmm_info;
 
 /* Per-pass device times (milliseconds) of one evaluation, from HIP events.

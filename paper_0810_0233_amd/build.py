@@ -18,7 +18,8 @@ FLAGS = [
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+    """The HIP kernels and runtime (*.hip) and the host-only parts (*.cpp)."""
+    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) + glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
 
 
 def build(jobs=8, verbose=False):

@@ -30,7 +30,7 @@ class ccfmm_params(C.Structure):
                 ("max_batch", C.c_int32), ("m2l_class_bits", C.c_int32), ("m2l_variant", C.c_int32),
                 ("use_graph", C.c_int32), ("overlap_near", C.c_int32), ("keep_lists", C.c_int32),
                 ("truncation", C.c_int32), ("m2l_traceless", C.c_int32),
-                ("sel_margin", C.c_double), ("sel_cost_far", C.c_double)]
+                ("sel_margin", C.c_double), ("sel_cost_far", C.c_double), ("device_mem_cap", C.c_int64)]
 
 
 class ccfmm_tune_entry(C.Structure):
@@ -49,7 +49,8 @@ class ccfmm_info(C.Structure):
                 ("m2l_class_bits", C.c_int32), ("fallback", C.c_int32),
                 ("m2l_flops_per_config", C.c_double), ("p2p_pairs_per_config", C.c_double),
                 ("m2l_variant", C.c_int32), ("n_rebuilds_kept", C.c_int64),
-                ("learned", C.c_int32), ("judge_err", C.c_double), ("sel_cost_far", C.c_double)]
+                ("learned", C.c_int32), ("judge_err", C.c_double), ("sel_cost_far", C.c_double),
+                ("device_bytes", C.c_int64)]
 
 
 class ccfmm_train_geometry(C.Structure):
@@ -184,7 +185,7 @@ def _check(rc):
 
 def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64, selector=0,
            err_bound=1e-5, box=None, max_batch=1, m2l_class_bits=3, m2l_variant=-1, use_graph=1, overlap_near=1,
-           keep_lists=1, truncation=0, m2l_traceless=1, sel_margin=0.3, sel_cost_far=0.0):
+           keep_lists=1, truncation=0, m2l_traceless=1, sel_margin=0.3, sel_cost_far=0.0, device_mem_cap=0):
     p = ccfmm_params()
     _check(lib().ccfmm_params_default(C.byref(p)))
     p.order = int(order)
@@ -209,6 +210,7 @@ def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64
     p.m2l_traceless = int(m2l_traceless)
     p.sel_margin = float(sel_margin)
     p.sel_cost_far = float(sel_cost_far)
+    p.device_mem_cap = int(device_mem_cap)
     return p
 
 

@@ -16,9 +16,22 @@ static thread_local std::string g_last_error;
 static std::atomic<uint64_t> g_devbuf_allocs{0};
 uint64_t devbuf_allocs() { return g_devbuf_allocs.load(); }
 
+MemBudget*& current_budget() {
+  static thread_local MemBudget* b = nullptr;
+  return b;
+}
+
 void* DevBuf::ensure(size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (bytes <= cap) return p;
+  MemBudget* b = current_budget();
+  if (b && b->cap > 0) {
+    const int64_t after = b->used - (budget == b ? (int64_t)cap : 0) + (int64_t)bytes;
+    if (after > b->cap)
+      throw StatusError{CCFMM_ENOMEM, "plan device-memory cap of " + std::to_string(b->cap) + " bytes: holding " +
+                                          std::to_string(b->used) + ", a buffer of " + std::to_string(bytes) +
+                                          " bytes does not fit"};
+  }
   release();
   g_devbuf_allocs.fetch_add(1);
   void* q = nullptr;
@@ -29,6 +42,8 @@ void* DevBuf::ensure(size_t bytes) {
   }
   p = q;
   cap = bytes;
+  budget = b;
+  if (b) b->used += (int64_t)bytes;
   return p;
 }
 
@@ -39,6 +54,8 @@ void DevBuf::release() {
     (void)hipDeviceSynchronize();
     (void)hipFree(p);
   }
+  if (budget) budget->used -= (int64_t)cap;
+  budget = nullptr;
   p = nullptr;
   cap = 0;
 }
@@ -209,14 +226,17 @@ static void setup_geometry(Plan& P, const double mn[3], const double mx[3], cons
   make_geometry(lo, W, P.L, P.geo);
 }
 
+// Expansion and moment buffers for nb configurations; the level offsets are
+// committed only once every buffer has its size (a failed allocation leaves
+// the previous layout in place).
 static void size_expansions(Plan& P, int nb) {
   const int NS = nstride(P.p);
   int64_t off = 0;
+  std::vector<int64_t> qoff(P.L + 1);
   for (int l = 0; l <= P.L; l++) {
-    P.lev[l]->qoff = off;
+    qoff[l] = off;
     off += (int64_t)P.lev[l]->ncells * nb * NS;
   }
-  P.qv_elems = off;
   const size_t es = P.precision == CCFMM_PREC_FP64 ? sizeof(double) : sizeof(float);
   P.Q.ensure(es * std::max<int64_t>(1, off));
   P.V.ensure(es * std::max<int64_t>(1, off));
@@ -224,6 +244,8 @@ static void size_expansions(Plan& P, int nb) {
     P.Qr.ensure(es * std::max<int64_t>(1, off / NS * ((P.p * (P.p + 2) + 3) & ~3)));
   P.m_sorted.ensure(es * 3 * (size_t)P.n * nb);
   if (nb >= P.batched_min) P.m_sorted_t.ensure(es * 3 * (size_t)P.n * nb);
+  for (int l = 0; l <= P.L; l++) P.lev[l]->qoff = qoff[l];
+  P.qv_elems = off;
   P.qv_batch = nb;
 }
 
@@ -365,6 +387,7 @@ static void validate_params(const ccfmm_params* prm, int64_t n) {
   if (prm->max_batch < 1 || prm->max_batch > 4096) fail(CCFMM_EINVAL, "max_batch must be in 1..4096");
   if (prm->truncation != 0 && prm->truncation != 1) fail(CCFMM_EINVAL, "truncation must be 0 or 1");
   if (prm->m2l_traceless != 0 && prm->m2l_traceless != 1) fail(CCFMM_EINVAL, "m2l_traceless must be 0 or 1");
+  if (prm->device_mem_cap < 0) fail(CCFMM_EINVAL, "device_mem_cap must be >= 0");
   if (prm->has_box)
     for (int a = 0; a < 3; a++)
       if (!std::isfinite(prm->box_lo[a]) || !std::isfinite(prm->box_hi[a])) fail(CCFMM_EINVAL, "box not finite");
@@ -458,7 +481,22 @@ static void build_all(Plan& P, const double* d_pos, hipStream_t st, bool was_bui
   P.built = P.ever_built = true;
 }
 
+static void prepare_batch_impl(Plan& P, int nb, hipStream_t st);
+
+// On failure (an allocation past the plan's cap, say) the batch layout and
+// the tiles are marked stale, so the next call lays them out anew.
 static void prepare_batch(Plan& P, int nb, hipStream_t st) {
+  try {
+    prepare_batch_impl(P, nb, st);
+  } catch (...) {
+    P.qv_batch = 0;
+    P.tiles_variant = -1;
+    P.drop_graph();
+    throw;
+  }
+}
+
+static void prepare_batch_impl(Plan& P, int nb, hipStream_t st) {
   if (nb < 1 || nb > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
   const int tb = tile_batch(nb, m2l_tile_cols(P.m2l_variant));
   if (tb != P.TB || ceil_div(nb, tb) != P.ncg || P.tiles_variant != P.m2l_variant ||
@@ -656,7 +694,9 @@ static int create_common(ccfmm_plan* out, int64_t n, const double* d_pos, const 
     if (!d_pos) fail(CCFMM_EINVAL, "positions are NULL");
     ccfmm_plan pl = new ccfmm_plan_s();
     Plan& P = pl->P;
+    P.mem.cap = prm->device_mem_cap;
     try {
+      BudgetScope bs(&P.mem);
       CCFMM_HIP(hipGetDevice(&P.device));
       P.n = n;
       P.prm = *prm;
@@ -701,9 +741,19 @@ int ccfmm_plan_create(ccfmm_plan* out, int32_t device, int64_t n, const double* 
     CCFMM_HIP(hipMemcpy(dpos.p, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
     int rc = create_common(out, n, dpos.as<double>(), prm, nullptr, true);
     if (rc == CCFMM_OK) {
-      // keep the device copy: the host-pointer plan owns its positions
-      std::swap((*out)->P.pos.p, dpos.p);
-      std::swap((*out)->P.pos.cap, dpos.cap);
+      // keep the device copy: the host-pointer plan owns its positions (and
+      // they count against its budget)
+      Plan& P = (*out)->P;
+      std::swap(P.pos.p, dpos.p);
+      std::swap(P.pos.cap, dpos.cap);
+      P.pos.budget = &P.mem;
+      P.mem.used += (int64_t)P.pos.cap;
+      if (P.mem.cap > 0 && P.mem.used > P.mem.cap) {
+        ccfmm_plan_destroy(*out);
+        *out = nullptr;
+        fail(CCFMM_ENOMEM, "plan device-memory cap of " + std::to_string(prm->device_mem_cap) +
+                               " bytes: the positions do not fit beside the plan");
+      }
       CCFMM_HIP(hipStreamSynchronize((*out)->P.own_stream));
     }
     return rc;  // on failure the message set by create_common stands
@@ -720,6 +770,7 @@ int ccfmm_plan_update_positions_device(ccfmm_plan plan, const double* d_pos, voi
     if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_pos) fail(CCFMM_EINVAL, "positions are NULL");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     CCFMM_HIP(hipSetDevice(P.device));
     // after a failed update only a full rebuild is trusted
     const bool was_built = P.built;
@@ -734,6 +785,7 @@ int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_m || !d_H) fail(CCFMM_EINVAL, "moment or field pointer is NULL");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
     return eval_run(P, nbatch, d_m, d_H, st);
@@ -746,6 +798,7 @@ int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, 
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_m || !d_H || !times) fail(CCFMM_EINVAL, "NULL argument");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
     if (nbatch < 1 || nbatch > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
@@ -788,6 +841,7 @@ int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H) {
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!m || !H) fail(CCFMM_EINVAL, "moment or field pointer is NULL");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     if (nbatch < 1 || nbatch > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
     for (int64_t i = 0; i < (int64_t)3 * P.n * nbatch; i++)
       if (!std::isfinite(m[i])) fail(CCFMM_EINVAL, "non-finite moment");
@@ -814,6 +868,7 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_m || !d_H) fail(CCFMM_EINVAL, "moment or field pointer is NULL");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
     prepare_batch(P, nbatch, st);
@@ -885,6 +940,7 @@ int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out) {
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!out) fail(CCFMM_EINVAL, "out is NULL");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     if (P.pairs_stale) {
       // the direct-pair count after an update that kept the lists: taken now,
       // once every stream's work on the plan has finished
@@ -900,6 +956,7 @@ int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out) {
       P.pairs_stale = false;
     }
     *out = P.info;
+    out->device_bytes = P.mem.used;
     return CCFMM_OK;
   });
 }
@@ -1093,6 +1150,7 @@ int ccfmm_plan_set_leaf_params(ccfmm_plan plan, const int32_t* d_p, const double
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if ((d_p == nullptr) != (d_theta == nullptr)) fail(CCFMM_EINVAL, "give both per-cell arrays or neither");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
     if (!d_p) {
@@ -1114,6 +1172,7 @@ int ccfmm_plan_get_leaf_params(ccfmm_plan plan, int32_t* h_p, double* h_theta, i
   return guarded([&] {
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     const int nl = P.lev[P.L]->ncells;
     if (n_leaves) *n_leaves = nl;
     for (int i = 0; i < nl; i++) {
@@ -1128,6 +1187,7 @@ int ccfmm_plan_leaf_ids(ccfmm_plan plan, int32_t* d_out, void* stream) {
   return guarded([&] {
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_out) fail(CCFMM_EINVAL, "output is NULL");
+    BudgetScope bs(&plan->P.mem);
     CCFMM_HIP(hipSetDevice(plan->P.device));
     run_leaf_ids(plan->P, d_out, reinterpret_cast<hipStream_t>(stream));
     return CCFMM_OK;
@@ -1139,6 +1199,7 @@ int ccfmm_plan_leaf_features(ccfmm_plan plan, int32_t nbatch, const double* d_m,
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_m || !d_feat || nbatch < 1) fail(CCFMM_EINVAL, "invalid argument");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CCFMM_HIP(hipSetDevice(P.device));
     if (P.has_leaf) apply_leaf_params(P, nullptr, nullptr, st);  // features use the fixed lists
@@ -1152,6 +1213,7 @@ int ccfmm_plan_leaf_errors(ccfmm_plan plan, int32_t nbatch, const double* d_H, c
   return guarded([&] {
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_H || !d_Href || !d_num || !d_den || nbatch < 1) fail(CCFMM_EINVAL, "invalid argument");
+    BudgetScope bs(&plan->P.mem);
     CCFMM_HIP(hipSetDevice(plan->P.device));
     run_leaf_errors(plan->P, nbatch, d_H, d_Href, d_num, d_den, reinterpret_cast<hipStream_t>(stream));
     return CCFMM_OK;
@@ -1198,6 +1260,7 @@ int ccfmm_plan_select(ccfmm_plan plan, const float* d_params, double err_bound, 
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_params || !d_m || !(err_bound > 0.0) || !(cost_far >= 0.0)) fail(CCFMM_EINVAL, "invalid argument");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     if (nbatch < 1 || nbatch > P.nbmax) fail(CCFMM_EINVAL, "nbatch must be in 1..max_batch");
     // the candidate orders are 2..6: a plan of order 1 has none
     if (P.p < 2) fail(CCFMM_EINVAL, "learned selection needs a plan of order >= 2");
@@ -1239,6 +1302,7 @@ int ccfmm_selector_load(ccfmm_plan plan, const char* path) {
   return guarded([&] {
     if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     std::vector<float> h(CCFMM_MLP_PARAMS);
     if (!selector_file_read(path, h.data())) {
       g_last_error = std::string("selector weights file not found, fixed parameters kept: ") + (path ? path : "");
@@ -1254,6 +1318,7 @@ int ccfmm_selector_set(ccfmm_plan plan, const float* d_params, void* stream) {
   return guarded([&] {
     if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
     if (!d_params) fail(CCFMM_EINVAL, "parameters are NULL");
+    BudgetScope bs(&plan->P.mem);
     CCFMM_HIP(hipSetDevice(plan->P.device));
     install_weights(plan->P, d_params, hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(stream));
     return CCFMM_OK;
@@ -1264,6 +1329,7 @@ int ccfmm_selector_save(ccfmm_plan plan, const char* path) {
   return guarded([&] {
     if (!plan || !plan->P.ever_built) fail(CCFMM_ESTATE, "plan not built");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     if (!P.has_sel_w) fail(CCFMM_ESTATE, "the plan holds no selector weights");
     CCFMM_HIP(hipSetDevice(P.device));
     std::vector<float> h(CCFMM_MLP_PARAMS);
@@ -1287,6 +1353,7 @@ int ccfmm_plan_energy_device(ccfmm_plan plan, int32_t nbatch, const double* d_m,
     if (!plan || !plan->P.built) fail(CCFMM_ESTATE, "plan not built");
     if (nbatch < 1 || !d_m || !d_H || !d_E) fail(CCFMM_EINVAL, "invalid argument");
     Plan& P = plan->P;
+    BudgetScope bs(&P.mem);
     CCFMM_HIP(hipSetDevice(P.device));
     run_energy(P, nbatch, d_m, d_H, d_E, reinterpret_cast<hipStream_t>(stream));
     return CCFMM_OK;

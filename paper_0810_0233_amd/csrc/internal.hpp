@@ -141,11 +141,32 @@ struct P2PChunk {
 };
 
 // ---------------------------------------------------------------------------
-// Device buffer with grow-only capacity.
+// Device memory budget of one plan: the bytes its buffers hold and an optional
+// cap.  Buffers allocated while a plan's call runs are charged to its budget
+// (current_budget) and uncharged when they release their memory.
+// ---------------------------------------------------------------------------
+struct MemBudget {
+  int64_t cap = 0;   // 0: no cap
+  int64_t used = 0;
+};
+MemBudget*& current_budget();  // per thread; null outside plan calls
+struct BudgetScope {
+  MemBudget* prev;
+  explicit BudgetScope(MemBudget* b) : prev(current_budget()) { current_budget() = b; }
+  ~BudgetScope() { current_budget() = prev; }
+  BudgetScope(const BudgetScope&) = delete;
+  BudgetScope& operator=(const BudgetScope&) = delete;
+};
+
+// ---------------------------------------------------------------------------
+// Device buffer with grow-only capacity.  Growing past the current budget's
+// cap throws CCFMM_ENOMEM before the old memory is released (the buffer keeps
+// its contents).
 // ---------------------------------------------------------------------------
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  MemBudget* budget = nullptr;  // the budget this buffer's memory counts against
   void* ensure(size_t bytes);
   void release();
   template <typename T>

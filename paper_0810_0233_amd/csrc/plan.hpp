@@ -42,6 +42,7 @@ struct LevelData {
 };
 
 struct Plan {
+  MemBudget mem;  // first member: destroyed after every buffer charged to it
   int device = 0;
   int64_t n = 0;
   ccfmm_params prm{};

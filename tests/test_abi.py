@@ -40,7 +40,8 @@ def test_status_strings_and_defaults():
                                  dict(max_batch=0), dict(precision=7), dict(truncation=2),
                                  dict(m2l_traceless=3), dict(max_batch=4097), dict(leaf_rule=2),
                                  dict(selector=2), dict(selector=1, order=1), dict(selector=1, err_bound=0.0),
-                                 dict(selector=1, sel_margin=-0.1), dict(leaf_target=float("inf"))])
+                                 dict(selector=1, sel_margin=-0.1), dict(leaf_target=float("inf")),
+                                 dict(device_mem_cap=-1)])
 def test_invalid_params_rejected_without_gpu(bad):
     prm = ccfmm.params(**bad)
     with pytest.raises(ccfmm.CCFMMError) as e:

@@ -788,3 +788,34 @@ def test_few_configuration_near_field(ref, precision, nb):
         else:
             assert rel_rms(Hb[b], H_ref) <= MIXED_BAR
             check_per_dipole(Hb[b], H_ref, "nb=%d b=%d mixed" % (nb, b))
+
+
+def test_device_memory_cap_gives_enomem(ref):
+    """A plan-level device-memory cap: creation that cannot fit fails with
+    CCFMM_ENOMEM (nothing left behind); a plan created within its cap reports
+    what it holds; an evaluation whose larger batch would pass the cap fails
+    with CCFMM_ENOMEM, and the plan then still evaluates the batch sizes that
+    fit (same field as before) and is destroyed normally."""
+    pos, box = inputs.ferrofluid(20000, 2001)
+    m = np.stack([inputs.random_moments(20000, 2101 + b) for b in range(8)])
+    with pytest.raises(ccfmm.CCFMMError) as e:
+        plan_for(pos, 6, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=8, device_mem_cap=1 << 20)
+    assert e.value.status == ccfmm.ENOMEM and "cap" in str(e.value)
+    free = plan_for(pos, 6, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=8)
+    H1 = free.eval(m[:1])
+    need1 = free.info()["device_bytes"]
+    H8 = free.eval(m)
+    need8 = free.info()["device_bytes"]
+    free.destroy()
+    print("device bytes: one configuration %d, eight %d" % (need1, need8), flush=True)
+    assert 0 < need1 < need8
+    capped = plan_for(pos, 6, 0.5, 0.0, box, precision=ccfmm.PREC_MIXED, max_batch=8,
+                      device_mem_cap=(need1 + need8) // 2)
+    assert np.array_equal(capped.eval(m[:1]), H1)
+    assert capped.info()["device_bytes"] <= (need1 + need8) // 2
+    with pytest.raises(ccfmm.CCFMMError) as e:
+        capped.eval(m)
+    assert e.value.status == ccfmm.ENOMEM
+    assert np.array_equal(capped.eval(m[:1]), H1)  # the sizes that fit still evaluate
+    assert rel_rms(H8[0], H1[0]) <= 1e-6
+    capped.destroy()
