@@ -82,7 +82,9 @@ typedef struct {
                              operator (256 / 128 / 64 columns; orders <= 8 with m2l_traceless,
                              FP64 included; mixed precision only and orders <= 6 without).
                              A variant the order or precision cannot use falls back to 0;
-                             ccfmm_plan_autotune can choose */
+                             ccfmm_plan_autotune can choose.  With per-cell orders, the
+                             wide traceless kernels compute for a tile of smallest cells
+                             only the local rows of the largest order among its targets */
   int32_t use_graph;      /* 1: evaluations are captured once into a HIP graph (per batch size
                              and buffer pair) and replayed; 0: plain stream launches */
   int32_t overlap_near;   /* 1 (default): the near field runs on a plan-owned second stream
@@ -95,12 +97,13 @@ typedef struct {
   int32_t truncation;     /* 0 (default): multipoles and locals each to order p, M2L with D up to
                              order 2p (the reading of Sec. 3); 1: total degree, M2L keeps only the
                              terms with |n| + |q| <= p (D_k = 0 for |k| > p) */
-  int32_t m2l_traceless;  /* 1 (default): the mixed-precision wide M2L kernels contract folded
+  int32_t m2l_traceless;  /* 1 (default): the wide M2L kernels (mixed and FP64) contract folded
                              moments over their 2l+1 components per degree and fill the rest of
                              V from the Laplace equation (D and V are harmonic; the same sums,
                              rounded differently); 0: the full 83 x 84 operator at p = 6 */
-  double sel_margin;      /* selector = 1: a cell takes the cheapest (p, theta) whose predicted
-                             log10 error is <= log10(err_bound) - sel_margin (default 0.3, >= 0) */
+  double sel_margin;      /* selector = 1: the choice keeps the predicted global relative RMS
+                             error within err_bound x 10^-sel_margin (default 0.3, >= 0);
+                             see ccfmm_plan_select */
   double sel_cost_far;    /* selector = 1: cost of one far cell relative to one direct dipole
                              pair in the selection; <= 0 (default): measured on the plan (M2L and
                              near-field times of one evaluation, each pass alone) */
@@ -264,6 +267,9 @@ typedef struct {
 
 /* Set (d_p, d_theta: device arrays of n_leaves int32 / FP64, compact leaf
  * order) or clear (both NULL) the per-cell parameters; rebuilds the lists.
+ * A cell's order truncates its local expansion for the smooth field (and the
+ * M2L rows computed for it); its theta sets the opening test of its
+ * neighbour candidates at the smallest level.
  * EINVAL if a p is outside 1..order or a theta outside (0,1). */
 int ccfmm_plan_set_leaf_params(ccfmm_plan plan, const int32_t* d_p, const double* d_theta, void* stream);
 /* Current per-cell parameters into host arrays of n_leaves (p, theta); with no
@@ -291,8 +297,9 @@ int ccfmm_mlp_adam(float* d_params, const float* d_grad, float* d_m1, float* d_m
 /* Learned selection on the current moments: the fixed-parameter field gives
  * each cell's squared field F_c; features -> network -> predicted log10
  * relative error y_c(p, theta) per cell and candidate; the choice minimises
- * the total cost (own dipoles x near source dipoles + cost_far x far cells +
- * the smooth field's work at order p, per cell) subject to the predicted
+ * the total cost (own dipoles x near source dipoles + cost_far x far cells x
+ * the share of the M2L rows order p needs + the smooth field's work at order
+ * p, per cell) subject to the predicted
  * global relative RMS error sqrt(sum F_c 10^(2 y_c) / sum F_c) being at most
  * err_bound x 10^-margin (Lagrange multiplier found by bisection), and is set
  * as the plan's per-cell parameters.  With judge != 0 the learned field of

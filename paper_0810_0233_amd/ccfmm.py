@@ -20,6 +20,8 @@ PMAX = 8
 LMAX = 24
 OK, EINVAL, ENOMEM, EHIP, ESTATE, W_FALLBACK, W_NOWEIGHTS = 0, -1, -2, -3, -4, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
+# M2L kernel variants (ccfmm_params.m2l_variant)
+M2L_AUTO, M2L_BLOCK, M2L_WAVE, M2L_WIDE4, M2L_WIDE2, M2L_WIDE1 = -1, 0, 1, 2, 3, 4
 
 
 class ccfmm_params(C.Structure):

@@ -1023,10 +1023,6 @@ void apply_leaf_params(Plan& P, const int32_t* hp, const double* hth, hipStream_
   fill_info(P, st);
 }
 
-// The learned choice: features of these moments -> network -> per cell the
-// cheapest (p, theta) predicted to meet the bound.  With judge, the fixed-
-// parameter field and the learned field of these moments are compared; above
-// the bound the plan returns to the fixed parameters (CCFMM_W_FALLBACK).
 // The learned choice on these moments: the fixed-parameter field gives each
 // cell's squared field F_c; features -> network -> per-cell (p, theta) with
 // the least cost whose predicted global relative RMS error is within

@@ -129,7 +129,8 @@ struct M2LTile {
   int32_t nsteps;
   int32_t tgt0;     // first entry in tile_tgt (16 entries, -1 = unused column group)
   int32_t b0;       // first configuration of the tile
-  int32_t pad[3];
+  int32_t rows;     // local rows its targets need (smallest cells of a lower order: fewer)
+  int32_t pad[2];
 };
 
 // P2P / L2P work chunk: up to 64 consecutive sorted dipoles of one leaf.

@@ -348,7 +348,16 @@ struct TileLevels {
   TileLevel lv[kLMax + 1];
   int32_t nlev;
   int32_t TC;
+  // per-cell orders of the smallest cells (compact order; null: none): their
+  // tiles are grouped by order and compute the local rows of that order only
+  const int32_t* leaf_p;
+  int32_t L;
+  int32_t red;    // traceless rows (q (q + 2) for order q) or full rows (N(q) - 1)
+  int32_t pbits;  // order bits in the sort key
 };
+
+// local-expansion rows of order q, a prefix of the row order in either form
+__device__ __forceinline__ int local_rows(int q, int red) { return red ? q * (q + 2) : ncoef(q) - 1; }
 
 __device__ __forceinline__ int level_of_cell(const TileLevels& T, int64_t i) {
   int l = 0;
@@ -401,7 +410,9 @@ __global__ void __launch_bounds__(256) k_tile_class_keys(TileLevels T, int64_t n
     const int cbl = min(cb, l);
     const uint32_t cls = (uint32_t)lv.key[c] & ((1u << cbl) - 1u);
     const uint32_t sig = sigbits ? h >> (32 - sigbits) : 0u;
-    key[i] = ((((uint32_t)l << cb) | cls) << sigbits) | sig;
+    // smallest cells with their own order: grouped by it (orders 1..8 -> 0..7)
+    const uint32_t pg = (T.pbits && l == T.L && T.leaf_p) ? (uint32_t)(T.leaf_p[c] - 1) : 0u;
+    key[i] = ((((((uint32_t)l << T.pbits) | pg) << cb) | cls) << sigbits) | sig;
     val[i] = (int32_t)i;
   }
 }
@@ -564,10 +575,22 @@ __global__ void k_tile_tgt(TileLevels T, int64_t ncol, const int32_t* sorted, in
   tgt[j] = pos < lv.nc ? sorted[lv.cell0 + pos] - (int32_t)lv.cell0 : -1;
 }
 
-__global__ void k_tiles(TileLevels T, int64_t ngroups, int TB, int ncg, const int32_t* goff, M2LTile* tiles) {
+// full_rows: the local rows of the plan's order.  A tile of smallest cells
+// with their own orders needs the rows of the largest of them.
+__global__ void k_tiles(TileLevels T, int64_t ngroups, int TB, int ncg, const int32_t* goff,
+                        const int32_t* tile_tgt, int full_rows, M2LTile* tiles) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= ngroups) return;
   const int l = level_of_group(T, b);
+  int rows = full_rows;
+  if (l == T.L && T.leaf_p) {
+    int q = 0;
+    for (int j = 0; j < T.TC; j++) {
+      const int c = tile_tgt[b * T.TC + j];
+      if (c >= 0) q = max(q, T.leaf_p[c]);
+    }
+    rows = q > 0 ? min(full_rows, local_rows(q, T.red)) : full_rows;
+  }
   for (int cg = 0; cg < ncg; cg++) {
     M2LTile t;
     t.level = l;
@@ -575,7 +598,8 @@ __global__ void k_tiles(TileLevels T, int64_t ngroups, int TB, int ncg, const in
     t.nsteps = goff[b + 1] - goff[b];
     t.tgt0 = (int32_t)(b * T.TC);
     t.b0 = cg * TB;
-    t.pad[0] = t.pad[1] = t.pad[2] = 0;
+    t.rows = rows;
+    t.pad[0] = t.pad[1] = 0;
     tiles[b * ncg + cg] = t;
   }
 }
@@ -602,6 +626,12 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   TileLevels TL{};
   TL.nlev = L + 1;
   TL.TC = TC;
+  TL.L = L;
+  const bool red = P.prm.m2l_traceless != 0 && P.p <= wide_max_order(true) &&
+                   (P.m2l_variant == kM2LWide4 || P.m2l_variant == kM2LWide2 || P.m2l_variant == kM2LWide1);
+  TL.red = red ? 1 : 0;
+  TL.leaf_p = P.has_leaf ? P.leaf_p.as<int32_t>() : nullptr;
+  TL.pbits = P.has_leaf ? 3 : 0;
   int64_t ncell = 0, ngroups = 0, nbm = 0;
   int maxwords = 1;
   for (int l = 0; l <= L; l++) {
@@ -634,10 +664,12 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   int32_t* sorted = sbuf + ncell;
   uint32_t* skey2 = reinterpret_cast<uint32_t*>(sbuf + 2 * ncell);
   int32_t* sval2 = sbuf + 3 * ncell;
-  const int sigbits = P.tile_signature ? 16 : 0;
+  // the sort key is (level, order group, class bits, signature) in 32 bits:
+  // the signature gives way when the other fields need its bits
+  const int sigbits = P.tile_signature ? std::min(16, 32 - (cb + lbits + TL.pbits)) : 0;
   k_tile_class_keys<<<ceil_div(ncell, 4), T, 0, st>>>(TL, ncell, cb, sigbits, skey, sorted);
   CCFMM_HIP(hipGetLastError());
-  radix_sort_pairs(skey, sorted, skey2, sval2, ncell, cb + lbits + sigbits, P.scratch, st);
+  radix_sort_pairs(skey, sorted, skey2, sval2, ncell, cb + lbits + TL.pbits + sigbits, P.scratch, st);
   // bitmaps, ranks and step counts of every group; global step offsets
   uint32_t* bitmap = reinterpret_cast<uint32_t*>(P.bitmap.ensure(sizeof(uint32_t) * 2 * std::max<int64_t>(1, nbm)));
   int32_t* wpre = reinterpret_cast<int32_t*>(bitmap + std::max<int64_t>(1, nbm));
@@ -669,7 +701,8 @@ void build_m2l_tiles(Plan& P, int nbatch, hipStream_t st) {
   }
   k_tile_tgt<<<ceil_div(ngroups * TC, T), T, 0, st>>>(TL, ngroups * TC, sorted, tile_tgt);
   CCFMM_HIP(hipGetLastError());
-  k_tiles<<<ceil_div(ngroups, T), T, 0, st>>>(TL, ngroups, P.TB, P.ncg, goff, tiles);
+  k_tiles<<<ceil_div(ngroups, T), T, 0, st>>>(TL, ngroups, P.TB, P.ncg, goff, tile_tgt,
+                                              red ? P.p * (P.p + 2) : nact(P.p), tiles);
   CCFMM_HIP(hipGetLastError());
   // launch order: longest step lists first, so the dispatcher's greedy,
   // round-robin placement balances the XCDs and their compute units

@@ -564,6 +564,32 @@ void build_wide_ops(Plan& P, hipStream_t st) {
 
 // RED: the traceless form (Q holds the folded moments, nred_stride(P) per
 // row; only the n_z <= 1 rows of V are written, k_fill_locals does the rest).
+// Share of a full-order M2L tile's work that a tile of smallest cells of
+// order q takes in the wide traceless kernels: the matrix-core row blocks its
+// rows need (a tile needing the vector-unit rows takes the full form).
+double m2l_row_share(const Plan& P, int q) {
+  const bool wide = P.m2l_variant == kM2LWide4 || P.m2l_variant == kM2LWide2 || P.m2l_variant == kM2LWide1;
+  if (!wide || P.prm.m2l_traceless == 0 || q >= P.p) return 1.0;
+  const int np = nred(P.p), mf = np / 16, rf = np % 16;
+  const int mb = (mf >= 1 && rf > 0 && rf <= 8) ? mf : (np + 15) / 16;
+  const int rows = nred(q);
+  if (rows > 16 * mb) return 1.0;
+  return (double)((rows + 15) / 16) / (double)mb;
+}
+
+// f(std::integral_constant<int, k>) for the k = mbu in 1..MB (uniform per block)
+template <int MB, int K = 1, typename F>
+__device__ __forceinline__ void with_row_blocks(int mbu, F& f) {
+  if constexpr (K >= MB) {
+    f(std::integral_constant<int, MB>{});
+  } else {
+    if (mbu <= K)
+      f(std::integral_constant<int, K>{});
+    else
+      with_row_blocks<MB, K + 1>(mbu, f);
+  }
+}
+
 template <typename T, int P, int CB, bool RED>
 __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile* __restrict__ tiles,
                                                    const int32_t* __restrict__ tile_order, int64_t ntiles,
@@ -623,13 +649,14 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   // the operator of step s (its expanded row, already in LDS order) goes from
   // memory straight into sT[buf] (no registers): 16-byte loads, lane l of
   // wavefront w covering bytes 4096 r + 1024 w + 16 l .. + 15
-  auto load_op = [&](int s, int buf) {
+  // (the first nbytes of the row: the row blocks in use)
+  auto load_op = [&](int s, int buf, int nbytes) {
     const char* orow = reinterpret_cast<const char*>(Dop + (int64_t)step_delta[tl.step0 + s] * NEP);
     char* dst = reinterpret_cast<char*>(&sT[buf][0]);
 #pragma unroll
     for (int r = 0; r < (kOpBytes + 4095) / 4096; r++) {
       const int o = 4096 * r + 1024 * w;
-      if (kOpBytes % 4096 == 0 || o < kOpBytes)  // uniform over the wavefront
+      if (o < nbytes)  // uniform over the wavefront
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(orow + o + 16 * lane),
                                          (__attribute__((address_space(3))) void*)(dst + o), 16, 0, 0);
     }
@@ -637,6 +664,13 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   // all of this wavefront's memory loads have landed (vmcnt = 0)
   auto wait_loads = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
 
+  // The products for the first MBU row blocks (MBU = MB: all rows, the vector
+  // rows included); tiles of smallest cells with a lower order of their own
+  // need fewer rows, and write zeros past them (their L2P reads none of those).
+  auto body = [&](auto mbu_c) {
+  constexpr int MBU = decltype(mbu_c)::value;
+  constexpr bool kAllRows = MBU == MB;
+  constexpr int kOpUsed = kAllRows ? kOpBytes : (MBU * KS * 64 * (int)sizeof(T) + 1023) / 1024 * 1024;
   AccT acc[MB][CB];
 #pragma unroll
   for (int mb = 0; mb < MB; mb++)
@@ -652,7 +686,7 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   T B0[CB][KS], B1[CB][KS];
   int srcA[CB], srcB[CB];
   if (nsteps > 0) {
-    load_op(0, 0);
+    load_op(0, 0, kOpUsed);
     load_src(0, srcA);
     load_b(srcA, B0);
     if (nsteps > 1) load_src(1, srcB);
@@ -663,7 +697,7 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
   auto step = [&](int s, int cur, T (&Bc)[CB][KS], T (&Bn)[CB][KS], int (&srcN)[CB], int (&srcN2)[CB]) {
     const bool more = s + 1 < nsteps;
     if (more) {
-      load_op(s + 1, cur ^ 1);
+      load_op(s + 1, cur ^ 1, kOpUsed);
       load_b(srcN, Bn);
       if (s + 2 < nsteps) load_src(s + 2, srcN2);
     }
@@ -671,27 +705,27 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
     const T* T0 = sT[cur];
 #pragma unroll
     for (int k4 = 0; k4 < K4; k4++) {
-      V4 av[MB];
+      V4 av[MBU];
 #pragma unroll
-      for (int mb = 0; mb < MB; mb++)
+      for (int mb = 0; mb < MBU; mb++)
         av[mb] = *reinterpret_cast<const V4*>(T0 + mb * KS * 64 + k4 * 256 + 4 * lane);
 #pragma unroll
       for (int ku = 0; ku < 4; ku++)
 #pragma unroll
-        for (int mb = 0; mb < MB; mb++)
+        for (int mb = 0; mb < MBU; mb++)
 #pragma unroll
           for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(av[mb][ku], Bc[cb][4 * k4 + ku], acc[mb][cb]);
     }
 #pragma unroll
     for (int t = 0; t < KT; t++) {
 #pragma unroll
-      for (int mb = 0; mb < MB; mb++) {
+      for (int mb = 0; mb < MBU; mb++) {
         const T a = T0[mb * KS * 64 + K4 * 256 + t * 64 + lane];
 #pragma unroll
         for (int cb = 0; cb < CB; cb++) acc[mb][cb] = mfma16x16x4(a, Bc[cb][4 * K4 + t], acc[mb][cb]);
       }
     }
-    if constexpr (RV > 0) {
+    if constexpr (RV > 0 && kAllRows) {
       const T* Tv = T0 + W::NEM + kq * W::KSTR;
 #pragma unroll
       for (int i = 0; i < W::KSTR / 4; i++) {
@@ -729,7 +763,8 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
         if (m < NP) {
           const int f = RED ? (int)kRedFull.full[m] : m + 1;
           const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
-          out[f - 1] = (deg & 1) ? -acc[mb][cb][r] : acc[mb][cb][r];
+          const T v = mb < MBU ? acc[mb][cb][r] : (T)0;
+          out[f - 1] = (deg & 1) ? -v : v;
         } else if (!RED && m < NS) {
           out[m] = (T)0;
         }
@@ -766,13 +801,20 @@ __global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile
             if (jj == j) {
               f = RED ? (int)kRedFull.full[16 * MB + jj] : 16 * MB + jj + 1;
               const int deg = kMI.x[f] + kMI.y[f] + kMI.z[f];
-              v = (deg & 1) ? -pv[cb][jj] : pv[cb][jj];
+              const T pj = kAllRows ? pv[cb][jj] : (T)0;
+              v = (deg & 1) ? -pj : pj;
             }
           out[f - 1] = v;
         }
       }
     }
   }
+  };
+  // row blocks in use: a tile needing rows past the matrix-core blocks (the
+  // vector rows) or all of them takes the full form
+  const int rows = tl.rows > 0 ? tl.rows : NP;
+  const int mbu = rows > 16 * MB ? MB : (rows + 15) / 16;
+  with_row_blocks<MB>(mbu, body);
 }
 
 template <typename T, int PP>

@@ -170,6 +170,7 @@ void run_near(Plan& P, int nb, double* d_H, hipStream_t st);     // near field w
 void run_l2p(Plan& P, int nb, double* d_H, hipStream_t st);      // smooth field added to H
 void run_permute(Plan& P, int nb, const double* d_m, hipStream_t st);
 void build_wide_ops(Plan& P, hipStream_t st);  // expanded operator rows (Dx) from Df
+double m2l_row_share(const Plan& P, int q);  // smallest-level M2L tile work at order q (0..1]
 void run_energy(Plan& P, int nb, const double* d_m, const double* d_H, double* d_E, hipStream_t st);
 void run_energy_noalloc(int64_t n, int nb, const double* d_m, const double* d_H, double* d_E, hipStream_t st);
 void run_direct_targets(int64_t n, const double* d_pos, const double* d_m, int64_t nt,

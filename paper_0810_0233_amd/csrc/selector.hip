@@ -266,6 +266,7 @@ struct SelectArgs {
   int L;
   double log_bound;           // log10(err_bound) - margin
   double cost_far;            // cost of one far (M2L) cell relative to one dipole pair
+  double far_share[5];        // share of that cost a cell of order 2..6 takes (its M2L rows)
   int pmax;
 };
 
@@ -285,7 +286,7 @@ __device__ __forceinline__ bool near_test(const LevelGeom& lg, double th2, int d
 
 // Per cell and candidate (p, theta): the work it costs, in direct-pair
 // units: own dipoles x near source dipoles at that angle, plus cost_far per
-// far cell, plus the smooth field at order p (an FMA triple per monomial of
+// far cell (scaled by the share of the M2L rows order p needs), plus the smooth field at order p (an FMA triple per monomial of
 // degree <= p-1 and own dipole, weighed against the ~23 vector operations of
 // one pair).  Candidates above the plan's order cost +inf (never chosen).
 constexpr double kL2PPairFrac = 3.0 / 23.0;
@@ -317,7 +318,7 @@ __global__ void k_cand_costs(SelectArgs a, TreeGeom G, double* __restrict__ cost
     for (int q = 0; q < 5; q++) {
       const double l2p = own * kL2PPairFrac * (double)ncoef(p - 1);
       cost[(int64_t)c * kOut + (p - 2) * 5 + q] =
-          p > a.pmax ? INFINITY : own * near_src[q] + a.cost_far * far_cells[q] + l2p;
+          p > a.pmax ? INFINITY : own * near_src[q] + a.cost_far * a.far_share[p - 2] * far_cells[q] + l2p;
     }
 }
 
@@ -522,6 +523,7 @@ void run_select(Plan& P, const float* d_params, double log_bound, double cost_fa
   a.log_bound = log_bound;
   a.cost_far = cost_far;
   a.pmax = std::min(P.p, 6);
+  for (int q = 2; q <= 6; q++) a.far_share[q - 2] = m2l_row_share(P, q);
   k_cand_costs<<<ceil_div(nl, 128), 128, 0, st>>>(a, P.geo, cost);
   CCFMM_HIP(hipGetLastError());
   std::vector<double> hF(nl);

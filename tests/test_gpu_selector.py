@@ -156,6 +156,36 @@ def test_leaf_params_mixed_match_fp64(ref):
     check_per_dipole(out[1], H_ref, "per-cell parameters mixed")
 
 
+@pytest.mark.parametrize("order,precision", [(6, ccfmm.PREC_FP64), (8, ccfmm.PREC_FP64), (5, ccfmm.PREC_FP64),
+                                             (6, ccfmm.PREC_MIXED)])
+def test_per_cell_orders_truncate_wide_m2l_rows(order, precision):
+    """Smallest cells of orders below the plan's: the wide traceless M2L
+    kernel computes only the local rows of the largest order in each tile
+    (zeros past them, which that tile's smooth field never reads); the field
+    equals the block kernel's, which computes every row.  Orders 1..order
+    cover tiles of one, some and all row blocks, and at order 5 the
+    vector-unit rows."""
+    pos, box, m = cluster_case(731, ncl=8, per=400)
+    r = np.random.default_rng(order)
+    out = {}
+    for variant in (ccfmm.M2L_BLOCK, ccfmm.M2L_WIDE1):
+        prm = ccfmm.params(order=order, theta=0.5, box=box, precision=precision, m2l_variant=variant, max_batch=1)
+        pl = ccfmm.Plan.create(pos, prm)
+        assert pl.info()["m2l_variant"] == variant
+        nl = pl.info()["n_leaves"]
+        rr = np.random.default_rng(order)
+        # half the cells at low orders, so that whole tiles fall below the plan's order
+        p = np.where(rr.random(nl) < 0.5, rr.integers(1, 3, nl), rr.integers(1, order + 1, nl))
+        set_params(pl, p, np.full(nl, 0.5))
+        out[variant] = pl.eval(m)
+        pl.destroy()
+    del r
+    bar = 1e-13 if precision == ccfmm.PREC_FP64 else 2e-6
+    err = rel_rms(out[ccfmm.M2L_WIDE1], out[ccfmm.M2L_BLOCK])
+    print("order %d precision %d wide vs block %.3e" % (order, precision, err), flush=True)
+    assert err <= bar
+
+
 def test_invalid_leaf_params_rejected():
     pos, box = inputs.lattice(8, 8, 8)
     pl = plan_for(pos, 4, 0.5, box, leaf_target=8)
