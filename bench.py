@@ -539,7 +539,7 @@ def bench_film(args, torch, ccfmm, inputs):
 
     # ---- the learned plan: weights, then the choice at its first evaluation
     out = {}
-    plan = make(ccfmm.PREC_MIXED, selector=1, err_bound=bound)
+    plan = make(ccfmm.PREC_MIXED, selector=1, err_bound=bound, sel_margin=selector.FILM_MARGIN)
     wpath = os.path.join(selector.WEIGHTS_DIR, selector.FILM_WEIGHTS)
     rc = plan.selector_load(wpath)
     if rc == ccfmm.W_NOWEIGHTS:
@@ -725,7 +725,8 @@ def bench_film(args, torch, ccfmm, inputs):
         "config": {"workload": c["name"], "n": n, "batch": nb, "order": 6, "theta": 0.4, "precision": "mixed",
                    "selector": "learned", "err_bound": bound, "levels": li["levels"],
                    "step": "position update (lists and choice kept) + evaluation of the 8 configurations",
-                   "selection": "once per geometry at the first evaluation, with its judge (selection_ms)"},
+                   "selection": "once per geometry at the first evaluation, with its judge (selection_ms)",
+                   "sel_margin": selector.FILM_MARGIN},
         "selection_ms": 1e3 * t_select,
         "selection_status": status,
         "learned": li["learned"],

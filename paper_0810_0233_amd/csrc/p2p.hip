@@ -218,6 +218,9 @@ __device__ __forceinline__ void l2p_write(const T* __restrict__ v, int pl, T yx,
 // kL2P: also add the smooth field of the cell's local expansion (one pass);
 // without it the kernel writes the near field alone and the smooth part is
 // added later by k_l2p_batched (so the near field can run beside M2L).
+// FP32 asks for 6 waves per SIMD, which spills a few registers (44 bytes a
+// lane, held in the caches); at 5 waves nothing spills but the 2^20-dipole
+// ferrofluid's near field took 3.15 ms instead of 3.03.
 template <typename T, int P, bool kL2P>
 __global__ void __launch_bounds__(64 * kP2PWaves, sizeof(T) == 4 ? 6 : 2) k_p2p_l2p(P2PArgs a, const T* __restrict__ y,
                                                            const T* __restrict__ msort, const T* __restrict__ V,
@@ -552,8 +555,21 @@ __device__ __forceinline__ void p2pk_run(const T* __restrict__ src, const P2PLo<
 // PL > 0: also add the smooth field of the cell's local expansion (order PL),
 // the single-stream form; PL = 0: the near field alone (written, not added),
 // the form that runs beside the expansion passes
+// Waves per SIMD asked of the compiler: 3, except in FP64 with four
+// configurations a block (the LDS records allow 2 blocks per CU, 1 with the
+// smooth field) and with the smooth field at the highest orders, whose
+// registers would spill at 3.
 template <typename T, int KB, int PL>
-__global__ void __launch_bounds__(64 * kP2PWaves, 3) k_p2p_multi(P2PArgs a, const T* __restrict__ y,
+constexpr int multi_waves() {
+  if (sizeof(T) == 8 && KB >= 4) return PL > 0 ? 1 : 2;
+  if (sizeof(T) == 8 && PL >= 8) return 1;  // the smooth field's registers at high orders
+  if (sizeof(T) == 8 && PL >= 7) return 2;
+  if (KB >= 8 && PL >= 8) return 2;
+  return 3;
+}
+
+template <typename T, int KB, int PL>
+__global__ void __launch_bounds__(64 * kP2PWaves, (multi_waves<T, KB, PL>())) k_p2p_multi(P2PArgs a, const T* __restrict__ y,
                                                                  const T* __restrict__ msort, const T* __restrict__ V,
                                                                  double* __restrict__ H) {
   constexpr int NW = p2pk_words<T, KB>();

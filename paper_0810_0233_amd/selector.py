@@ -178,6 +178,11 @@ WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights"
 FILM_WEIGHTS = "film_1024x1024x16_p6_t04.ccsel"
 FILM_TRAIN_SEEDS = (5101, 5103)
 FILM_SAMPLE_CELLS = 4096
+# Selection margin for films (log10 units below the bound): the smallest of
+# 0.3, 0.2, 0.15, 0.1, 0.05 whose judged error on the training film of seed
+# 5101 (8 configurations, bound 1e-5) stayed within 0.85 of the bound
+# (0.1: 8.26e-6; 0.05 reached 9.23e-6).
+FILM_MARGIN = 0.1
 
 
 def train_film(out_path, steps=600, seed=1):
