@@ -134,7 +134,6 @@ __global__ void k_dtensor(int64_t nbox, int w0, int w1, int w2, double g0, doubl
 // rebuilds as long as order, shapes and boxes do not change.
 void build_dtensors(Plan& P, hipStream_t st) {
   const int K = 2 * P.p;
-  const int NK = ncoef(K);
   std::vector<std::array<double, 6>> keys;
   std::vector<int64_t> key_row, key_nbox;
   std::vector<int> lev_key(P.L + 1, -1);
@@ -225,14 +224,17 @@ __global__ void k_permute_moments_t(const double* __restrict__ m, const int32_t*
 }
 
 // ------------------------------------------------------------ P2M
-// One wavefront per (occupied smallest cell, configuration).  Eq.
-// (multipolemoments) in scaled units: Qt_n = sum_i sum_{a: n_a>0} m_ia yt^(n-e_a)/(n-e_a)!.
-// Lanes first tabulate yt^k/k! (|k| <= p-1) of kP2MChunk dipoles in LDS, then
-// each lane sums whole coefficients over those dipoles.
+// One wavefront per (occupied smallest cell, group of up to CG
+// configurations; CG = 1 for a single configuration, else kP2MConfigs).  Eq. (multipolemoments) in scaled units:
+// Qt_n = sum_i sum_{a: n_a>0} m_ia yt^(n-e_a)/(n-e_a)!.  Lanes first tabulate
+// yt^k/k! (|k| <= p-1) of kP2MChunk dipoles in LDS (once for the whole group:
+// the monomials do not depend on the moments), then each lane sums whole
+// coefficients over those dipoles for every configuration of the group.
 constexpr int kP2MWaves = 4;
 constexpr int kP2MChunk = 16;
+constexpr int kP2MConfigs = 8;
 
-template <typename T, int P>
+template <typename T, int P, int CG>
 __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restrict__ lstart,
                                                        const int32_t* __restrict__ lcount, int32_t nleaf,
                                                        const T* __restrict__ y, const T* __restrict__ msort,
@@ -242,19 +244,22 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
   constexpr int NS = nstride(P);
   constexpr int NR = (NP + 63) / 64;
   __shared__ T mono[kP2MWaves][kP2MChunk][NM + 1];
-  __shared__ T mm[kP2MWaves][kP2MChunk][3];
+  __shared__ T mm[kP2MWaves][kP2MChunk][CG][3];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ngrp = (nb + CG - 1) / CG;
   const int64_t item = (int64_t)blockIdx.x * kP2MWaves + w;
-  if (item >= (int64_t)nleaf * nb) return;
-  const int leaf = (int)(item / nb), b = (int)(item % nb);
+  if (item >= (int64_t)nleaf * ngrp) return;
+  const int leaf = (int)(item / ngrp), b0 = (int)(item % ngrp) * CG;
+  const int nbg = min(CG, nb - b0);
   const int first = lstart[leaf], cnt = lcount[leaf];
   // source indices of coefficient n - e_a for this lane's coefficients
   int srcx[NR], srcy[NR], srcz[NR];
-  T acc[NR];
+  T acc[CG][NR];
 #pragma unroll
   for (int r = 0; r < NR; r++) {
     const int t = lane + 64 * r + 1;  // flat index, |n| >= 1
-    acc[r] = (T)0;
+#pragma unroll
+    for (int c = 0; c < CG; c++) acc[c][r] = (T)0;
     srcx[r] = srcy[r] = srcz[r] = -1;
     if (t <= NP) {
       const int x = kMI.x[t], yy = kMI.y[t], z = kMI.z[t];
@@ -263,7 +268,6 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
       if (z > 0) srcz[r] = midx(x, yy, z - 1);
     }
   }
-  const T* mb = msort + (int64_t)b * 3 * n;
   for (int base = 0; base < cnt; base += kP2MChunk) {
     const int nchunk = min(kP2MChunk, cnt - base);
     if (lane < nchunk) {
@@ -280,33 +284,57 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
       }
 #pragma unroll
       for (int t = 0; t < NM; t++) mono[w][lane][t] = px[kMI.x[t]] * py[kMI.y[t]] * pz[kMI.z[t]];
-      mm[w][lane][0] = mb[i];
-      mm[w][lane][1] = mb[n + i];
-      mm[w][lane][2] = mb[2 * n + i];
+    }
+    // the group's moments of these dipoles, one (dipole, configuration) per lane
+    for (int q = lane; q < nchunk * nbg; q += 64) {
+      const int j = q / nbg, c = q - j * nbg;
+      const int64_t i = first + base + j;
+      const T* mb = msort + (int64_t)(b0 + c) * 3 * n;
+      mm[w][j][c][0] = mb[i];
+      mm[w][j][c][1] = mb[n + i];
+      mm[w][j][c][2] = mb[2 * n + i];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int j = 0; j < nchunk; j++) {
-      const T m0 = mm[w][j][0], m1 = mm[w][j][1], m2 = mm[w][j][2];
+      // this lane's monomials of dipole j (zero where the term is absent)
+      T vx[NR], vy[NR], vz[NR];
 #pragma unroll
       for (int r = 0; r < NR; r++) {
-        T s = acc[r];
-        if (srcx[r] >= 0) s += m0 * mono[w][j][srcx[r]];
-        if (srcy[r] >= 0) s += m1 * mono[w][j][srcy[r]];
-        if (srcz[r] >= 0) s += m2 * mono[w][j][srcz[r]];
-        acc[r] = s;
+        vx[r] = srcx[r] >= 0 ? mono[w][j][srcx[r]] : (T)0;
+        vy[r] = srcy[r] >= 0 ? mono[w][j][srcy[r]] : (T)0;
+        vz[r] = srcz[r] >= 0 ? mono[w][j][srcz[r]] : (T)0;
+      }
+#pragma unroll
+      for (int c = 0; c < CG; c++) {
+        if (c < nbg) {
+          const T m0 = mm[w][j][c][0], m1 = mm[w][j][c][1], m2 = mm[w][j][c][2];
+#pragma unroll
+          for (int r = 0; r < NR; r++) {
+            T s = acc[c][r];
+            s += m0 * vx[r];
+            s += m1 * vy[r];
+            s += m2 * vz[r];
+            acc[c][r] = s;
+          }
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  T* q = Q + ((int64_t)leaf * nb + b) * NS;
 #pragma unroll
-  for (int r = 0; r < NR; r++) {
-    const int a = lane + 64 * r;
-    if (a < NS) q[a] = (a < NP) ? acc[r] : (T)0;
+  for (int c = 0; c < CG; c++) {
+    if (c < nbg) {
+      T* q = Q + ((int64_t)leaf * nb + b0 + c) * NS;
+#pragma unroll
+      for (int r = 0; r < NR; r++) {
+        const int a = lane + 64 * r;
+        if (a < NS) q[a] = (a < NP) ? acc[c][r] : (T)0;
+      }
+    }
   }
 }
 
@@ -315,77 +343,202 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
 // the parent centre along the halved axis a only, so Q_n(P) sums Q_{n-k e_a}(C)
 // over k; in scaled units the weight is gamma^k/k! rho^(|n|-k-1) with
 // gamma = (child centre - parent centre)_a / s_l and rho = s_{l+1}/s_l.
+// The weights of a level are tabulated on the host (ShiftW): w[k][d] =
+// gamma^k/k! rho^(d-1) for the child at +gamma; the child at -gamma takes
+// (-1)^k of it.
+struct ShiftW {
+  double w[kPMax + 1][kPMax + 1];
+};
+
+static ShiftW m2m_weights(double gam, double rho, int p) {
+  ShiftW W{};
+  double gk = 1.0;  // gamma^k / k!
+  for (int k = 0; k <= p; k++) {
+    for (int d = 1; d <= p; d++) {
+      double w = gk;
+      for (int j = 0; j < d - 1; j++) w *= rho;
+      W.w[k][d] = w;
+    }
+    gk = gk * gam / (double)(k + 1);
+  }
+  return W;
+}
+
+// Along the halved axis the shift acts on lines of coefficients: the two
+// other components (u, v) of n fixed, n_a = t running over 0..p-u-v.  One
+// lane per (line, configuration): Q_n(P) at n_a = t sums the children's
+// Q at n_a = t - k, k = 0..t, so a lane needs no per-term index search and
+// every lane of a line runs the same loop.  A wavefront takes LPW = 64 / lines
+// configurations of one parent cell; rows move through LDS whole (coalesced).
+constexpr int kShiftWaves = 4;
+
+// line l (0 .. (p+1)(p+2)/2 - 1) -> the two other components (u, v), by u + v
+__device__ __forceinline__ void line_uv(int l, int& u, int& v) {
+  int q = 0;
+  while (l > q) {
+    l -= q + 1;
+    q++;
+  }
+  u = q - l;
+  v = l;
+}
+// active index of the multi-index with component t on axis ax and (u, v) on
+// the other two (in x, y, z order)
+__device__ __forceinline__ int line_index(int ax, int u, int v, int t) {
+  return ax == 0 ? midx(t, u, v) - 1 : ax == 1 ? midx(u, t, v) - 1 : midx(u, v, t) - 1;
+}
+template <int P>
+constexpr int shift_lines() {
+  return (P + 1) * (P + 2) / 2;
+}
+template <int P>
+constexpr int shift_cpw() {
+  return 64 / shift_lines<P>() >= 1 ? 64 / shift_lines<P>() : 1;
+}
+
 template <typename T, int P>
-__global__ void k_m2m(int32_t ncells, const int32_t* __restrict__ child, int axis, double gam, double rho, int nb,
-                      const T* __restrict__ Qc, T* __restrict__ Qp) {
+__global__ void __launch_bounds__(64 * kShiftWaves) k_m2m(int32_t ncells, const int32_t* __restrict__ child, int axis,
+                                                          ShiftW W, int nb, const T* __restrict__ Qc,
+                                                          T* __restrict__ Qp) {
   constexpr int NP = nact(P);
   constexpr int NS = nstride(P);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)ncells * nb * NS) return;
-  const int a = (int)(t % NS);
-  const int64_t cb = t / NS;
-  const int b = (int)(cb % nb);
-  const int c = (int)(cb / nb);
-  T* out = Qp + ((int64_t)c * nb + b) * NS;
-  if (a >= NP) {
-    out[a] = (T)0;
-    return;
+  constexpr int NL = shift_lines<P>();
+  constexpr int CPW = shift_cpw<P>();
+  __shared__ double sw[(P + 1) * (P + 1)];  // the weights, read at per-lane indices
+  __shared__ T sq[kShiftWaves][CPW][2][NS];
+  __shared__ T so[kShiftWaves][CPW][NS];
+  for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += blockDim.x) sw[i] = W.w[i / (P + 1)][i % (P + 1)];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ngrp = (nb + CPW - 1) / CPW;
+  const int64_t item = (int64_t)blockIdx.x * kShiftWaves + w;
+  if (item >= (int64_t)ncells * ngrp) return;
+  const int c = (int)(item / ngrp), b0 = (int)(item % ngrp) * CPW;
+  const int nbg = min(CPW, nb - b0);
+  const int ch[2] = {child[2 * c], child[2 * c + 1]};
+  for (int i = lane; i < nbg * 2 * NS; i += 64) {  // an absent child reads as a zero row
+    const int cf = i / (2 * NS), e = (i / NS) & 1, a = i % NS;
+    sq[w][cf][e][a] = ch[e] >= 0 ? Qc[((int64_t)ch[e] * nb + b0 + cf) * NS + a] : (T)0;
   }
-  const int f = a + 1;
-  int n[3] = {kMI.x[f], kMI.y[f], kMI.z[f]};
-  const int deg = n[0] + n[1] + n[2];
-  double s = 0.0;
-  for (int e = 0; e < 2; e++) {
-    const int ch = child[2 * c + e];
-    if (ch < 0) continue;
-    const double g = (e == 0) ? -gam : gam;
-    const T* qc = Qc + ((int64_t)ch * nb + b) * NS;
-    double gk = 1.0;  // gamma^k / k!
-    for (int k = 0; k <= n[axis]; k++) {
-      int m[3] = {n[0], n[1], n[2]};
-      m[axis] -= k;
-      const int dm = deg - k;
-      if (dm >= 1) {
-        double w = gk;
-        for (int j = 0; j < dm - 1; j++) w *= rho;
-        s += w * (double)qc[midx(m[0], m[1], m[2]) - 1];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int cf = lane / NL;
+  if (cf < nbg) {
+    int u, v;
+    line_uv(lane % NL, u, v);
+    const int q = u + v;
+    // the line of both children in registers (zero past its end and at the
+    // monopole), read together; then every loop below is unrolled with the
+    // line's bounds as predicates
+    double x0[P + 1], x1[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; j++) {
+      const bool ok = j <= P - q && j + q >= 1;
+      const int idx = ok ? line_index(axis, u, v, j) : 0;
+      x0[j] = ok ? (double)sq[w][cf][0][idx] : 0.0;
+      x1[j] = ok ? (double)sq[w][cf][1][idx] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t <= P; t++) {
+      if (t <= P - q && t + q >= 1) {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+#pragma unroll
+          for (int k = 0; k <= t; k++) {
+            const int j = t - k;  // the child's component on the axis; its degree is j + q
+            if (j + q >= 1) {     // (Q_0 = 0: no monopole term)
+              const double wv = sw[k * (P + 1) + j + q];
+              const double wk = (e == 0 && (k & 1)) ? -wv : wv;
+              s += wk * (e == 0 ? x0[j] : x1[j]);
+            }
+          }
+        }
+        so[w][cf][line_index(axis, u, v, t)] = (T)s;
       }
-      gk = gk * g / (double)(k + 1);
     }
   }
-  out[a] = (T)s;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int i = lane; i < nbg * NS; i += 64) {
+    const int f = i / NS, a = i % NS;
+    Qp[((int64_t)c * nb + b0 + f) * NS + a] = a < NP ? so[w][f][a] : (T)0;
+  }
 }
 
 // ------------------------------------------------------------ L2L
 // Eq.(taylorshift) from level l to l+1 along the halved axis:
-// Vt_n(C) += sum_k gamma^k/k! rho^(|n|+2) Vt_{n+k e_a}(P).
+// Vt_n(C) += sum_k gamma^k/k! rho^(|n|+2) Vt_{n+k e_a}(P).  Tabulated on the
+// host per level: g[k] = gamma^k/k! (the child at -gamma takes (-1)^k of it)
+// and r[d] = rho^(d+2).
+struct TaylorW {
+  double g[kPMax + 1];
+  double r[kPMax + 1];
+};
+
+static TaylorW l2l_weights(double gam, double rho, int p) {
+  TaylorW W{};
+  double gk = 1.0;
+  for (int k = 0; k <= p; k++) {
+    W.g[k] = gk;
+    gk = gk * gam / (double)(k + 1);
+  }
+  for (int d = 0; d <= p; d++) {
+    double rp = 1.0;
+    for (int j = 0; j < d + 2; j++) rp *= rho;
+    W.r[d] = rp;
+  }
+  return W;
+}
+
+// One wavefront per (child cell, configuration): the parent's row is read
+// whole (coalesced) into LDS, then each lane adds its coefficients.  (The
+// line form of M2M measured slower here: a child's row is read and written
+// besides the parent's, and each line has half the terms.)
 template <typename T, int P>
-__global__ void k_l2l(int32_t ncells, const int32_t* __restrict__ parent, const int32_t* __restrict__ key, int axis,
-                      double gam, double rho, int nb, const T* __restrict__ Vp, T* __restrict__ Vc) {
+__global__ void __launch_bounds__(64 * kShiftWaves) k_l2l(int32_t ncells, const int32_t* __restrict__ parent,
+                                                          const int32_t* __restrict__ key, int axis, TaylorW W,
+                                                          int nb, const T* __restrict__ Vp, T* __restrict__ Vc) {
   constexpr int NP = nact(P);
   constexpr int NS = nstride(P);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)ncells * nb * NP) return;
-  const int a = (int)(t % NP);
-  const int64_t cb = t / NP;
-  const int b = (int)(cb % nb);
-  const int c = (int)(cb / nb);
-  const int f = a + 1;
-  const int n[3] = {kMI.x[f], kMI.y[f], kMI.z[f]};
-  const int deg = n[0] + n[1] + n[2];
-  const double g = (key[c] & 1) ? gam : -gam;
+  constexpr int NR = (NS + 63) / 64;
+  __shared__ T sv[kShiftWaves][NS];
+  __shared__ double sg[2 * (P + 1)];  // the weights, read at per-lane indices
+  for (int i = threadIdx.x; i < 2 * (P + 1); i += blockDim.x) sg[i] = i <= P ? W.g[i] : W.r[i - (P + 1)];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * kShiftWaves + w;
+  if (item >= (int64_t)ncells * nb) return;
+  const int c = (int)(item / nb), b = (int)(item % nb);
   const T* vp = Vp + ((int64_t)parent[c] * nb + b) * NS;
-  double rp = 1.0;
-  for (int j = 0; j < deg + 2; j++) rp *= rho;
-  double s = 0.0, gk = 1.0;
-  for (int k = 0; deg + k <= P; k++) {
-    int m[3] = {n[0], n[1], n[2]};
-    m[axis] += k;
-    s += gk * (double)vp[midx(m[0], m[1], m[2]) - 1];
-    gk = gk * g / (double)(k + 1);
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int a = lane + 64 * r;
+    if (a < NS) sv[w][a] = vp[a];
   }
-  T* out = Vc + ((int64_t)c * nb + b) * NS + a;
-  *out = (T)((double)*out + rp * s);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const bool neg = (key[c] & 1) == 0;  // the child at -gamma
+  T* out = Vc + item * NS;
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int a = lane + 64 * r;
+    if (a >= NP) continue;
+    const int f = a + 1;
+    const int n[3] = {kMI.x[f], kMI.y[f], kMI.z[f]};
+    const int deg = n[0] + n[1] + n[2];
+    double s = 0.0;
+    for (int k = 0; deg + k <= P; k++) {
+      int m[3] = {n[0], n[1], n[2]};
+      m[axis] += k;
+      const double gk = (neg && (k & 1)) ? -sg[k] : sg[k];
+      s += gk * (double)sv[w][midx(m[0], m[1], m[2]) - 1];
+    }
+    out[a] = (T)((double)out[a] + sg[P + 1 + deg] * s);
+  }
 }
 
 // ------------------------------------------------------------ launchers
@@ -400,22 +553,27 @@ static void p2m_impl(Plan& P, int nb, const double* d_m, hipStream_t st) {
   T* ms = P.m_sorted.as<T>();
   const int nl = P.lev[P.L]->ncells;
   const T* y = std::is_same<T, double>::value ? (const T*)P.yd.p : (const T*)P.yf.p;
-  const int64_t items = (int64_t)nl * nb;
-  k_p2m<T, PP><<<ceil_div(items, kP2MWaves), 64 * kP2MWaves, 0, st>>>(P.lstart.as<int32_t>(), P.lcount.as<int32_t>(),
-                                                                    nl, y, ms, P.n, nb, qptr<T>(P, P.Q, P.L));
+  if (nb == 1) {
+    k_p2m<T, PP, 1><<<ceil_div(nl, kP2MWaves), 64 * kP2MWaves, 0, st>>>(P.lstart.as<int32_t>(), P.lcount.as<int32_t>(),
+                                                                       nl, y, ms, P.n, nb, qptr<T>(P, P.Q, P.L));
+  } else {
+    const int64_t items = (int64_t)nl * ceil_div(nb, kP2MConfigs);
+    k_p2m<T, PP, kP2MConfigs><<<ceil_div(items, kP2MWaves), 64 * kP2MWaves, 0, st>>>(
+        P.lstart.as<int32_t>(), P.lcount.as<int32_t>(), nl, y, ms, P.n, nb, qptr<T>(P, P.Q, P.L));
+  }
   CCFMM_HIP(hipGetLastError());
 }
 
 template <typename T, int PP>
 static void m2m_impl(Plan& P, int nb, hipStream_t st) {
-  constexpr int NS = nstride(PP);
   for (int l = P.L - 1; l >= 1; l--) {
     const LevelData& D = *P.lev[l];
     const int a = P.geo.lev[l + 1].axis;
     const double gam = 0.5 * P.geo.lev[l + 1].h[a] / P.geo.lev[l].s;
     const double rho = P.geo.lev[l + 1].s / P.geo.lev[l].s;
-    const int64_t nt = (int64_t)D.ncells * nb * NS;
-    k_m2m<T, PP><<<ceil_div(nt, 256), 256, 0, st>>>(D.ncells, D.child.as<int32_t>(), a, gam, rho, nb,
+    const int64_t nt = (int64_t)D.ncells * ceil_div(nb, shift_cpw<PP>());
+    k_m2m<T, PP><<<ceil_div(nt, kShiftWaves), 64 * kShiftWaves, 0, st>>>(D.ncells, D.child.as<int32_t>(), a,
+                                                                          m2m_weights(gam, rho, PP), nb,
                                                     qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l));
     CCFMM_HIP(hipGetLastError());
   }
@@ -423,15 +581,15 @@ static void m2m_impl(Plan& P, int nb, hipStream_t st) {
 
 template <typename T, int PP>
 static void l2l_impl(Plan& P, int nb, hipStream_t st) {
-  constexpr int NP = nact(PP);
   for (int l = 1; l < P.L; l++) {
     const LevelData& C = *P.lev[l + 1];
     const int a = P.geo.lev[l + 1].axis;
     const double gam = 0.5 * P.geo.lev[l + 1].h[a] / P.geo.lev[l].s;
     const double rho = P.geo.lev[l + 1].s / P.geo.lev[l].s;
-    const int64_t nt = (int64_t)C.ncells * nb * NP;
-    k_l2l<T, PP><<<ceil_div(nt, 256), 256, 0, st>>>(C.ncells, C.parent.as<int32_t>(), C.key.as<int32_t>(), a, gam,
-                                                    rho, nb, qptr<T>(P, P.V, l), qptr<T>(P, P.V, l + 1));
+    const int64_t nt = (int64_t)C.ncells * nb;
+    k_l2l<T, PP><<<ceil_div(nt, kShiftWaves), 64 * kShiftWaves, 0, st>>>(C.ncells, C.parent.as<int32_t>(), C.key.as<int32_t>(), a,
+                                                    l2l_weights(gam, rho, PP), nb, qptr<T>(P, P.V, l),
+                                                    qptr<T>(P, P.V, l + 1));
     CCFMM_HIP(hipGetLastError());
   }
 }
