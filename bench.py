@@ -565,6 +565,8 @@ def bench_film(args, torch, ccfmm, inputs):
     li = plan.info()
     log("learned choice: status %d learned %d judge %.3e cost_far %.1f (%.1f ms with its judge)" % (
         status, li["learned"], li["judge_err"], li["sel_cost_far"], 1e3 * t_select))
+    log("evaluation form: %s (tuned: near field beside %.3f ms, one stream %.3f ms)" % (
+        "near field beside the expansion passes" if li["overlap_near"] else "one stream", *li["tune_eval_ms"]))
 
     def step(pl):
         def f():
@@ -730,7 +732,8 @@ def bench_film(args, torch, ccfmm, inputs):
                    "selector": "learned", "err_bound": bound, "levels": li["levels"],
                    "step": "position update (lists and choice kept) + evaluation of the 8 configurations",
                    "selection": "once per geometry at the first evaluation, with its judge (selection_ms)",
-                   "sel_margin": selector.FILM_MARGIN},
+                   "sel_margin": selector.FILM_MARGIN, "overlap_near": li["overlap_near"]},
+        "tune_eval_ms": {"near_field_beside": li["tune_eval_ms"][0], "one_stream": li["tune_eval_ms"][1]},
         "selection_ms": 1e3 * t_select,
         "selection_status": status,
         "learned": li["learned"],
@@ -1048,6 +1051,8 @@ def main():
     plan = make(ccfmm.PREC_MIXED)
     tune = plan.autotune(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
     info = plan.info()
+    log("evaluation form: %s (tuned: near field beside %.3f ms, one stream %.3f ms)" % (
+        "near field beside the expansion passes" if info["overlap_near"] else "one stream", *info["tune_eval_ms"]))
     log("m2l autotune: %s -> variant %d class_bits %d" % (
         json.dumps([(t["variant"], t["class_bits"], round(t["m2l_ms"], 3)) for t in tune]),
         info["m2l_variant"], info["m2l_class_bits"]))
@@ -1148,12 +1153,17 @@ def main():
         ns = n
         threads = min(os.cpu_count() or 1, 16)
         t = time.perf_counter()
-        oracle.fmm(pos, m[0], order, theta, box=box, nthreads=threads)
+        H_ref = oracle.fmm(pos, m[0], order, theta, box=box, nthreads=threads)
         dt = time.perf_counter() - t
         cpu = {"value": ns / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": "FP64 recursive CPU FMM (same p, theta, s rule and root box) on the whole workload, "
-                         "configuration 0 only (n=%d), %.1f s" % (ns, dt)}
+                         "configuration 0 only (n=%d), %.1f s" % (ns, dt), "cpu_model": cpu_model()}
         log("cpu oracle: %.3e evals/s on %d threads" % (ns / dt, threads))
+        # the timed oracle field is also the reference of the mixed field at the
+        # same (p, theta, s): every dipole, configuration 0
+        out["eps_vs_oracle_fmm"] = rel_rms(H_mixed[0], H_ref)
+        out["per_dipole_vs_oracle_fmm"] = per_dipole_stats(H_mixed[0], H_ref)
+        log("mixed vs oracle FMM %.3e, per dipole %s" % (out["eps_vs_oracle_fmm"], out["per_dipole_vs_oracle_fmm"]))
 
     res = {
         "metric": METRIC,
@@ -1172,7 +1182,9 @@ def main():
                    "leaf_target": info["s_used"], "levels": info["levels"], "precision": "mixed",
                    "step": "rebuild for moved dipoles (tree; lists and tiles unless the occupied cells are the "
                            "same) + eval",
-                   "m2l_variant": info["m2l_variant"], "m2l_class_bits": info["m2l_class_bits"]},
+                   "m2l_variant": info["m2l_variant"], "m2l_class_bits": info["m2l_class_bits"],
+                   "overlap_near": info["overlap_near"]},
+        "tune_eval_ms": {"near_field_beside": info["tune_eval_ms"][0], "one_stream": info["tune_eval_ms"][1]},
         "rebuilds_keeping_lists": kept,
         "step_lists_always_rebuilt_ms": 1e3 * t_step_full,
         "eval_only_evals_per_s": n * nb / t_eval,

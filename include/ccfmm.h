@@ -147,6 +147,9 @@ typedef struct {
   double judge_err;                     /* the judge's relative RMS difference at the last selection */
   double sel_cost_far;                  /* far-cell cost used at the last selection */
   int64_t device_bytes;                 /* device memory the plan holds now */
+  int32_t overlap_near;                 /* evaluation form in use (see ccfmm_params; the autotuner chooses) */
+  double tune_eval_ms[2];               /* the last autotune's evaluation times: [0] near field beside the
+                                           expansion passes, [1] one stream; 0 before any autotune */
 } ccfmm_info;
 
 /* Per-pass device times (milliseconds) of one evaluation, from HIP events.
@@ -203,8 +206,13 @@ int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, 
  * scratch field buffer of the same shape), keeps the fastest in the plan and
  * writes up to max_out timings to out (*n_out = number written): the median of
  * three launches, or a single launch for a combination whose first launch took
- * more than twice the best median so far.  Synchronises the stream.  The field
- * values do not depend on the choice (beyond rounding). */
+ * more than twice the best median so far.  Then it times whole evaluations in
+ * both forms (near field beside the expansion passes, and everything on one
+ * stream; per evaluation, the better of two runs of four queued back to back,
+ * replayed from a graph when the plan uses graphs) and keeps the faster as the
+ * plan's overlap_near (reported with both times in ccfmm_plan_info).
+ * Synchronises the stream.  The field values do not depend on the choices
+ * (beyond rounding). */
 int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream,
                         ccfmm_tune_entry* out, int32_t max_out, int32_t* n_out);
 

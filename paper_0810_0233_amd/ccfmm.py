@@ -52,7 +52,7 @@ class ccfmm_info(C.Structure):
                 ("m2l_flops_per_config", C.c_double), ("p2p_pairs_per_config", C.c_double),
                 ("m2l_variant", C.c_int32), ("n_rebuilds_kept", C.c_int64),
                 ("learned", C.c_int32), ("judge_err", C.c_double), ("sel_cost_far", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("overlap_near", C.c_int32), ("tune_eval_ms", C.c_double * 2)]
 
 
 class ccfmm_train_geometry(C.Structure):
@@ -219,7 +219,8 @@ def params(order=4, theta=0.5, leaf_target=0.0, leaf_rule=0, precision=PREC_FP64
 def info_dict(inf):
     L = inf.levels
     d = {f: getattr(inf, f) for f, _ in ccfmm_info._fields_
-         if f not in ("split_axis", "box_lo", "box_hi", "leaf_side", "m2l_pairs_per_level")}
+         if f not in ("split_axis", "box_lo", "box_hi", "leaf_side", "m2l_pairs_per_level", "tune_eval_ms")}
+    d["tune_eval_ms"] = list(inf.tune_eval_ms)
     d["split_axis"] = [inf.split_axis[l] for l in range(1, L + 1)]
     d["box_lo"] = list(inf.box_lo)
     d["box_hi"] = list(inf.box_hi)
@@ -288,7 +289,10 @@ class Plan:
         return {f: getattr(t, f) for f, _ in ccfmm_pass_times._fields_}
 
     def autotune(self, nbatch, d_m, d_H, stream=0):
-        """Time the M2L variants on this plan, keep the fastest; returns the timings."""
+        """Time the M2L variants on this plan and keep the fastest, then the two
+        evaluation forms (near field beside the expansion passes, or one stream)
+        and keep the faster; returns the M2L timings (the forms' times are in
+        info()["tune_eval_ms"])."""
         out = (ccfmm_tune_entry * 32)()
         n = C.c_int32(0)
         _check(lib().ccfmm_plan_autotune(self.h, int(nbatch), C.c_void_p(d_m), C.c_void_p(d_H),

@@ -862,6 +862,59 @@ int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H) {
   });
 }
 
+// Time per evaluation in the plan's current form: after a warm-up, the
+// better of two runs of four evaluations queued back to back (as a caller's
+// loop runs them: per-evaluation start-up overlaps the previous one), replayed
+// from a graph captured here when the plan's evaluations use one, else plain
+// launches.
+static double time_eval_form(Plan& P, int nb, const double* d_m, double* d_H, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1) {
+  const bool graph = P.use_graph && st != nullptr;
+  hipGraphExec_t gx = nullptr;
+  if (graph) {
+    CCFMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      eval_passes(P, nb, d_m, d_H, st, nullptr);
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(st, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    hipGraph_t g = nullptr;
+    CCFMM_HIP(hipStreamEndCapture(st, &g));
+    const hipError_t e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) gx = nullptr;
+    CCFMM_HIP(e);
+  }
+  constexpr int kRun = 4;
+  auto launch = [&]() {
+    if (graph)
+      CCFMM_HIP(hipGraphLaunch(gx, st));
+    else
+      eval_passes(P, nb, d_m, d_H, st, nullptr);
+  };
+  double best = INFINITY;
+  try {
+    launch();  // warm-up
+    for (int r = 0; r < 2; r++) {
+      CCFMM_HIP(hipEventRecord(e0, st));
+      for (int i = 0; i < kRun; i++) launch();
+      CCFMM_HIP(hipEventRecord(e1, st));
+      CCFMM_HIP(hipEventSynchronize(e1));
+      float t;
+      CCFMM_HIP(hipEventElapsedTime(&t, e0, e1));
+      best = std::min(best, (double)t / kRun);
+    }
+  } catch (...) {
+    if (gx) (void)hipGraphExecDestroy(gx);
+    throw;
+  }
+  if (gx) (void)hipGraphExecDestroy(gx);
+  return best;
+}
+
 int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream,
                         ccfmm_tune_entry* out, int32_t max_out, int32_t* n_out) {
   return guarded([&] {
@@ -914,8 +967,6 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
         best_ms = std::min(best_ms, (double)ms[1]);
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     size_t best = 0;
     for (size_t i = 1; i < res.size(); i++)
       if (res[i].m2l_ms < res[best].m2l_ms) best = i;
@@ -924,13 +975,24 @@ int ccfmm_plan_autotune(ccfmm_plan plan, int32_t nbatch, const double* d_m, doub
     prepare_batch(P, nbatch, st);
     P.info.m2l_class_bits = P.class_bits;
     P.info.m2l_variant = P.m2l_variant;
+    // the evaluation form: the near field beside the expansion passes (the
+    // plan's second stream) or everything on the caller's stream.  Which is
+    // faster depends on the workload: where the near field's blocks fill
+    // every compute unit, the passes beside it only slow it down.
+    P.drop_graph();
+    for (int f = 0; f < 2; f++) {
+      P.overlap = f == 0;
+      P.tune_eval_ms[f] = time_eval_form(P, nbatch, d_m, d_H, st, e0, e1);
+    }
+    P.overlap = P.tune_eval_ms[0] <= P.tune_eval_ms[1];
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (n_out) *n_out = 0;
     if (out && max_out > 0) {
       const int k = std::min<int>(max_out, (int)res.size());
       for (int i = 0; i < k; i++) out[i] = res[i];
       if (n_out) *n_out = k;
     }
-    (void)d_H;
     return CCFMM_OK;
   });
 }
@@ -957,6 +1019,9 @@ int ccfmm_plan_info(ccfmm_plan plan, ccfmm_info* out) {
     }
     *out = P.info;
     out->device_bytes = P.mem.used;
+    out->overlap_near = P.overlap ? 1 : 0;
+    out->tune_eval_ms[0] = P.tune_eval_ms[0];
+    out->tune_eval_ms[1] = P.tune_eval_ms[1];
     return CCFMM_OK;
   });
 }

@@ -56,6 +56,7 @@ struct Plan {
   // the near field runs on a second stream beside the expansion passes
   // (forked after the moment permutation, joined before L2P)
   bool overlap = true;
+  double tune_eval_ms[2] = {0.0, 0.0};  // the last autotune's evaluation times: [0] overlapped, [1] one stream
   DevBuf heap_flag_prev;       // occupancy of every heap cell at the previous build
   DevBuf pos_check;            // [0] a position is not finite, [1] one lies outside the caller's box
   bool pairs_stale = false;    // info's direct-pair count not yet taken for the current cells

@@ -250,8 +250,8 @@ def test_direct_targets_matches_oracle(ref):
 def test_m2l_variants_and_autotune_agree(ref, precision):
     """Every M2L kernel (the block and wavefront kernels on the full operator,
     the wide kernels on the traceless one, in FP64 too), every target
-    grouping and the autotuner's pick give the same fields; FP64 matches the
-    oracle.  FP64 bar between variants 1e-13: the traceless form adds folded
+    grouping and the autotuner's pick (kernel, grouping and evaluation form)
+    give the same fields; FP64 matches the oracle.  FP64 bar between variants 1e-13: the traceless form adds folded
     moments and sums 48 instead of 83 terms per row, a different rounding of
     the same sums (1e-16 per operation)."""
     import torch
@@ -282,6 +282,10 @@ def test_m2l_variants_and_autotune_agree(ref, precision):
     inf = pl.info()
     best = min(res, key=lambda r: r["m2l_ms"])
     assert (inf["m2l_variant"], inf["m2l_class_bits"]) == (best["variant"], best["class_bits"])
+    # the evaluation form: both timed, the faster kept
+    t_beside, t_one = inf["tune_eval_ms"]
+    assert t_beside > 0 and t_one > 0
+    assert inf["overlap_near"] == (1 if t_beside <= t_one else 0)
     pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
     torch.cuda.synchronize()
     assert rel_rms(d_H.cpu().numpy(), base) <= (1e-13 if precision == ccfmm.PREC_FP64 else 1e-6)
