@@ -54,7 +54,7 @@ the GPU path: trees two levels either side of s_o(p) for Table II's (p, alpha)
 pairs, on 32^3 and 128^3 lattices and the ferrofluid.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload film|ferrofluid|sphere|clusters|dynamics|leafsweep|leaffit|params|truncation]
-                       [--skip-cpu] [--skip-fp64] [--skip-sweep] [--calib-copy]
+                       [--skip-cpu] [--skip-fp64] [--skip-sweep] [--roofline-only] [--calib-copy]
 """
 import argparse
 import json
@@ -497,6 +497,43 @@ def per_dipole_stats(H, Href):
             "max_over_rms_field": float(d.max() / np.sqrt(np.mean(r * r)))}
 
 
+def calibration_copy(torch, dev):
+    """One plain 256 MiB device-to-device copy: the counter runs' scale (its
+    FETCH_SIZE and WRITE_SIZE readings against the bytes it moves)."""
+    a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+    b = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    a.copy_(b)
+    torch.cuda.synchronize()
+    return 256 << 20
+
+
+def film_roofline(li, pt, n, nb, name):
+    """Per-pass work of the film's learned plan and the roofline of its
+    dominant pass (times: HIP events the library records on the launch
+    stream, every pass alone)."""
+    kern = pass_work(li, n, nb, 6)
+    if nb < 32:
+        pt["l2p"] = 0.0  # fused into the near-field kernel (the timer brackets nothing)
+    for k, v in kern.items():
+        v["ms"] = pt[k]
+        if pt[k] <= 0.0:
+            continue
+        sec = pt[k] * 1e-3
+        v["gb_s"] = v["bytes"] / sec / 1e9
+        v["hbm_frac"] = v["bytes"] / sec / PEAK_HBM
+        if v["flops"]:
+            v["tflop_s"] = v["flops"] / sec / 1e12
+            v["flop_frac"] = v["flops"] / sec / v["peak"]
+    dom = max(("m2l", "p2p"), key=lambda k: pt[k])
+    d = kern[dom]
+    ach = d["flops"] / (pt[dom] * 1e-3)
+    roof = {"kernel": d["kernel"], "bound": d["bound"], "achieved": ach / 1e12, "peak": d["peak"] / 1e12,
+            "unit": "TFLOP/s", "frac": ach / d["peak"], "traffic": counted_traffic(d["kernel"], name),
+            "algorithmic_bytes": d["bytes"]}
+    return {k: {q: v[q] for q in v if q != "peak"} for k, v in kern.items()}, roof
+
+
 def bench_film(args, torch, ccfmm, inputs):
     """The thin-film workload: 1024 x 1024 x 16 lattice with 16 circular holes
     (14,482,960 sites), 8 magnetisation configurations evaluated together,
@@ -556,7 +593,8 @@ def bench_film(args, torch, ccfmm, inputs):
         out["selector_weights"] = "trained in this run on %d cells, loss %s" % (rows, losses)
     else:
         out["selector_weights"] = os.path.relpath(wpath, ROOT)
-    plan.autotune(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
+    if not args.roofline_only:
+        plan.autotune(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
     torch.cuda.synchronize()
     t = time.perf_counter()
     status = plan.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), sh)
@@ -587,6 +625,17 @@ def bench_film(args, torch, ccfmm, inputs):
     log("learned step %.2f ms, eval %.2f ms; passes (one stream) %s; choice %s" % (
         1e3 * t_learned, 1e3 * t_learned_eval, json.dumps({k: round(v, 2) for k, v in pt.items()}), hist))
     plan.destroy()
+    if args.roofline_only:
+        # counter runs: the learned plan alone, untuned (the near field beside
+        # the expansion passes), so the fused near-field kernel of the roofline
+        # runs only in the three timed evaluations
+        kern, roof = film_roofline(li, pt, n, nb, c["name"])
+        res = {"metric": METRIC, "workload": c["name"], "roofline_only": True, "passes_ms": pt, "roofline": roof,
+               "kernels": kern}
+        if args.calib_copy:
+            res["calib_copy_bytes"] = calibration_copy(torch, dev)
+        print(json.dumps(res), flush=True)
+        return
 
     # ---- fixed (6, 0.4), the same step
     fixed = make(ccfmm.PREC_MIXED)
@@ -661,28 +710,8 @@ def bench_film(args, torch, ccfmm, inputs):
             1e3 * t64, out["eps_prec_fixed_mixed"], out["eps_learned_vs_fp64_fixed"]))
         p64.destroy()
 
-    # ---- roofline of the dominant pass (the near field), times from HIP
-    # events the library records on the launch stream, every pass alone
-    kern = pass_work(li, n, nb, 6)
-    if nb < 32:
-        pt["l2p"] = 0.0  # fused into the near-field kernel (the timer brackets nothing)
-    for k, v in kern.items():
-        v["ms"] = pt[k]
-        if pt[k] <= 0.0:
-            continue
-        sec = pt[k] * 1e-3
-        v["gb_s"] = v["bytes"] / sec / 1e9
-        v["hbm_frac"] = v["bytes"] / sec / PEAK_HBM
-        if v["flops"]:
-            v["tflop_s"] = v["flops"] / sec / 1e12
-            v["flop_frac"] = v["flops"] / sec / v["peak"]
-    dom = max(("m2l", "p2p"), key=lambda k: pt[k])
-    d = kern[dom]
-    ach = d["flops"] / (pt[dom] * 1e-3)
-    roof = {"kernel": d["kernel"], "bound": d["bound"], "achieved": ach / 1e12, "peak": d["peak"] / 1e12,
-            "unit": "TFLOP/s", "frac": ach / d["peak"], "traffic": counted_traffic(d["kernel"], c["name"]),
-            "algorithmic_bytes": d["bytes"]}
-    out["kernels"] = {k: {q: v[q] for q in v if q != "peak"} for k, v in kern.items()}
+    # ---- roofline of the dominant pass (the near field)
+    out["kernels"], roof = film_roofline(li, pt, n, nb, c["name"])
 
     # ---- CPU oracle on a bounded sample of the same workload
     cpu = None
@@ -751,12 +780,7 @@ def bench_film(args, torch, ccfmm, inputs):
     }
     res.update(out)
     if args.calib_copy:
-        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
-        b = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        torch.cuda.synchronize()
-        a.copy_(b)
-        torch.cuda.synchronize()
-        res["calib_copy_bytes"] = 256 << 20
+        res["calib_copy_bytes"] = calibration_copy(torch, dev)
     print(json.dumps(res), flush=True)
 
 
@@ -958,6 +982,8 @@ def main():
     ap.add_argument("--samples", type=int, default=0, help="sampled dipoles for the error against the direct sum "
                     "(default 4096; 1024 on the film)")
     ap.add_argument("--skip-sweep", action="store_true", help="film: skip the uniform (p, theta) grid")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="film: the learned plan alone, untuned, then the roofline (for counter runs)")
     ap.add_argument("--traffic-record", nargs=3, metavar=("WORKLOAD", "FETCH_DIR", "WRITE_DIR"),
                     help="write the counter record of WORKLOAD from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--traffic-summary", default="", help="with --traffic-record: the summary file it cites")
@@ -1195,12 +1221,7 @@ def main():
     }
     res.update(out)
     if args.calib_copy:
-        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
-        b = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        torch.cuda.synchronize()
-        a.copy_(b)
-        torch.cuda.synchronize()
-        res["calib_copy_bytes"] = 256 << 20
+        res["calib_copy_bytes"] = calibration_copy(torch, dev)
     print(json.dumps(res), flush=True)
 
 
