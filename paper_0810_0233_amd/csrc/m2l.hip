@@ -497,10 +497,12 @@ template <int P, bool RED = false>
 __device__ __forceinline__ int wide_slot_dindex(int e) {
   using W = WideOp<P, RED>;
   if (e >= W::NE) return W::ND;
-  if (e >= W::NEM) {
-    const int kq = (e - W::NEM) / W::KSTR, r = (e - W::NEM) % W::KSTR;
-    if (r >= W::RV * W::KS) return W::ND;
-    return wide_op_index<P, RED>(16 * W::MB + r % W::RV, kq * W::KS + r / W::RV);
+  if constexpr (W::RV > 0) {  // the vector-unit rows (none when every row is in a matrix-core block)
+    if (e >= W::NEM) {
+      const int kq = (e - W::NEM) / W::KSTR, r = (e - W::NEM) % W::KSTR;
+      if (r >= W::RV * W::KS) return W::ND;
+      return wide_op_index<P, RED>(16 * W::MB + r % W::RV, kq * W::KS + r / W::RV);
+    }
   }
   const int mb = e / (W::KS * 64), r0 = e % (W::KS * 64);
   int ks, l;
@@ -590,8 +592,10 @@ __device__ __forceinline__ void with_row_blocks(int mbu, F& f) {
   }
 }
 
+// two blocks per CU where the double-buffered operator leaves room for them
+// (FP64 at order 8 holds 100 KB of LDS: one)
 template <typename T, int P, int CB, bool RED>
-__global__ void __launch_bounds__(256, CB <= 2 ? 2 : 1) k_m2l_wide(const M2LTile* __restrict__ tiles,
+__global__ void __launch_bounds__(256, (CB <= 2 && !(sizeof(T) == 8 && P >= 8)) ? 2 : 1) k_m2l_wide(const M2LTile* __restrict__ tiles,
                                                    const int32_t* __restrict__ tile_order, int64_t ntiles,
                                                    const int32_t* __restrict__ tile_tgt,
                                                    const int32_t* __restrict__ step_delta,
