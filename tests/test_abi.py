@@ -133,3 +133,38 @@ def test_selector_train_rejects_bad_specs_without_gpu():
     with pytest.raises(ccfmm.CCFMMError) as e:
         ccfmm.selector_train([])
     assert e.value.status == ccfmm.EINVAL
+
+
+STRUCTS = ("ccfmm_params", "ccfmm_tune_entry", "ccfmm_info", "ccfmm_train_geometry", "ccfmm_train_spec",
+           "ccfmm_train_info", "ccfmm_pass_times", "ccfmm_select_info")
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Every struct of the binding has the size and field offsets the C
+    compiler gives the header's struct (a C program built against
+    include/ccfmm.h prints them)."""
+    import ctypes
+    import subprocess
+
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ccfmm.h"', "int main(void) {"]
+    for sname in STRUCTS:
+        S = getattr(ccfmm, sname)
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (sname, sname))
+        for fname, _ in S._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (sname, fname, sname, fname))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            a, b, v = ln.split()
+            got[(a, b)] = int(v)
+    for sname in STRUCTS:
+        S = getattr(ccfmm, sname)
+        assert got[(sname, "size")] == ctypes.sizeof(S), sname
+        for fname, _ in S._fields_:
+            assert got[(sname, fname)] == getattr(S, fname).offset, (sname, fname)
