@@ -89,7 +89,8 @@ typedef struct {
                              and buffer pair) and replayed; 0: plain stream launches */
   int32_t overlap_near;   /* 1 (default): the near field runs on a plan-owned second stream
                              (default priority) beside P2M..L2L, joined before L2P;
-                             0: everything on the caller's stream, near field and L2P fused */
+                             0: everything on the caller's stream, near field and L2P fused.
+                             ccfmm_plan_autotune times both and keeps the faster */
   int32_t keep_lists;     /* 1 (default): a position update with the same geometry and the same
                              occupied cells keeps the cell lists, M2L tiles and captured
                              evaluation (exactly what a full rebuild would produce);
