@@ -206,3 +206,43 @@ def test_learned_choice_kept_across_updates_that_keep_the_cells(trained):
     assert inf["learned"] == 1 or inf["fallback"] == 1
     assert inf["n_leaves"] == len(pl.get_leaf_params()[0])
     pl.destroy()
+
+
+def test_autotune_before_the_choice(trained):
+    """Autotuning a learned plan before its first evaluation (M2L kernel and
+    evaluation form timed on the fixed parameters) leaves the choice to that
+    evaluation. With the far-field cost given (a measured one differs from
+    run to run), the tuned plan chooses as an untuned one does: the same
+    parameters in all but the odd cell that sits at the Lagrangian's edge
+    (the tuned M2L kernel may round the fixed field F_c differently), and
+    both judged fields within the bound of each other."""
+    import torch
+
+    path, _, _ = trained
+    pos, box, m = cluster_case(4315)
+    bound = 1e-4
+    st = stream()
+    d_m = torch.from_numpy(m).cuda()
+    d_H = torch.empty_like(d_m)
+    out = []
+    for tune in (False, True):
+        pl = learned_plan(pos, box, ccfmm.PREC_MIXED, bound, sel_cost_far=200.0)
+        assert pl.selector_load(path) == ccfmm.OK
+        if tune:
+            pl.autotune(1, d_m.data_ptr(), d_H.data_ptr(), st)
+            inf = pl.info()
+            assert inf["learned"] == 0 and min(inf["tune_eval_ms"]) > 0
+        pl.eval_device(1, d_m.data_ptr(), d_H.data_ptr(), st)
+        torch.cuda.synchronize()
+        inf = pl.info()
+        assert pl.last_status == ccfmm.OK and inf["learned"] == 1
+        assert 0 < inf["judge_err"] <= bound
+        out.append((pl.get_leaf_params(), d_H.cpu().numpy().copy()))
+        pl.destroy()
+    (p0, th0), H0 = out[0]
+    (p1, th1), H1 = out[1]
+    same = np.mean((p0 == p1) & (th0 == th1))
+    print("cells with the same choice: %.5f of %d; fields differ by %.3e" % (same, p0.size, rel_rms(H1, H0)),
+          flush=True)
+    assert same >= 0.99
+    assert rel_rms(H1, H0) <= 2 * bound
