@@ -493,51 +493,165 @@ static TaylorW l2l_weights(double gam, double rho, int p) {
   return W;
 }
 
-// One wavefront per (child cell, configuration): the parent's row is read
-// whole (coalesced) into LDS, then each lane adds its coefficients.  (The
-// line form of M2M measured slower here: a child's row is read and written
-// besides the parent's, and each line has half the terms.)
-template <typename T, int P>
-__global__ void __launch_bounds__(64 * kShiftWaves) k_l2l(int32_t ncells, const int32_t* __restrict__ parent,
-                                                          const int32_t* __restrict__ key, int axis, TaylorW W,
-                                                          int nb, const T* __restrict__ Vp, T* __restrict__ Vc) {
-  constexpr int NP = nact(P);
-  constexpr int NS = nstride(P);
-  constexpr int NR = (NS + 63) / 64;
-  __shared__ T sv[kShiftWaves][NS];
-  __shared__ double sg[2 * (P + 1)];  // the weights, read at per-lane indices
-  for (int i = threadIdx.x; i < 2 * (P + 1); i += blockDim.x) sg[i] = i <= P ? W.g[i] : W.r[i - (P + 1)];
-  __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * kShiftWaves + w;
-  if (item >= (int64_t)ncells * nb) return;
-  const int c = (int)(item / nb), b = (int)(item % nb);
-  const T* vp = Vp + ((int64_t)parent[c] * nb + b) * NS;
-#pragma unroll
-  for (int r = 0; r < NR; r++) {
-    const int a = lane + 64 * r;
-    if (a < NS) sv[w][a] = vp[a];
+// Multi-index (x, y, z) of coefficient f in the graded order of midx, at
+// compile time: degree d, then s = y + z and z from f - ncoef(d - 1) =
+// s (s + 1) / 2 + z.
+constexpr int mi_deg(int f) {
+  int d = 0;
+  while (ncoef(d) <= f) d++;
+  return d;
+}
+constexpr int mi_s(int f) {
+  const int r = f - ncoef(mi_deg(f) - 1);
+  int s = 0;
+  while ((s + 1) * (s + 2) / 2 <= r) s++;
+  return s;
+}
+constexpr int mi_z(int f) { return f - ncoef(mi_deg(f) - 1) - mi_s(f) * (mi_s(f) + 1) / 2; }
+constexpr int mi_x(int f) { return mi_deg(f) - mi_s(f); }
+constexpr int mi_y(int f) { return mi_s(f) - mi_z(f); }
+constexpr int binom(int n, int k) {
+  int r = 1;
+  for (int i = 0; i < k; i++) r = r * (n - i) / (i + 1);
+  return r;
+}
+
+template <int A, int B, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (A < B) {
+    f(std::integral_constant<int, A>{});
+    static_for<A + 1, B>(f);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const bool neg = (key[c] & 1) == 0;  // the child at -gamma
-  T* out = Vc + item * NS;
-#pragma unroll
-  for (int r = 0; r < NR; r++) {
-    const int a = lane + 64 * r;
-    if (a >= NP) continue;
-    const int f = a + 1;
-    const int n[3] = {kMI.x[f], kMI.y[f], kMI.z[f]};
-    const int deg = n[0] + n[1] + n[2];
-    double s = 0.0;
-    for (int k = 0; deg + k <= P; k++) {
-      int m[3] = {n[0], n[1], n[2]};
-      m[axis] += k;
-      const double gk = (neg && (k & 1)) ? -sg[k] : sg[k];
-      s += gk * (double)sv[w][midx(m[0], m[1], m[2]) - 1];
+}
+
+typedef float l2l_f4 __attribute__((ext_vector_type(4)));
+typedef double l2l_d4 __attribute__((ext_vector_type(4)));
+template <typename T>
+using RowVec4 = typename std::conditional<std::is_same<T, float>::value, l2l_f4, l2l_d4>::type;
+
+// (child cell, configuration) rows per L2L block: two rows of LDS per row
+// (parent and child), 43.5 KB at order 6 in either precision
+constexpr int kL2LThreads = 256;
+template <typename T>
+constexpr int l2l_rows() {
+  return sizeof(T) == 4 ? 64 : 32;
+}
+
+// Coefficients C0 <= a < C1 of one child row: pr and cr are the parent's and
+// the child's rows in LDS, gs the signed weights gamma^k/k! of this child.
+// FOLDED: the child's row holds only its n_z <= 1 components (the traceless
+// M2L's output).  A local expansion satisfies the Laplace equation, so its
+// other components follow from those: unrolling
+// V(x, y, z) = -V(x + 2, y, z - 2) - V(x, y + 2, z - 2) gives, for z = 2k + e,
+// V(x, y, z) = (-1)^k sum_j C(k, j) V(x + 2j, y + 2(k - j), e).  They are formed
+// here before the shifted parent is added, so the row is read and written once.
+template <typename T, int P, bool FOLDED, int AX, int C0, int C1>
+__device__ __forceinline__ void l2l_coefs(const T* __restrict__ pr, const T* __restrict__ cr, const double* gs,
+                                          const TaylorW& W, T* res) {
+  static_for<C0, C1>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    constexpr int f = a + 1, x = mi_x(f), y = mi_y(f), z = mi_z(f), deg = x + y + z;
+    double base;
+    if constexpr (FOLDED && z >= 2) {
+      constexpr int kz = z / 2, e = z % 2;
+      double t = 0.0;
+      static_for<0, kz + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int src = midx(x + 2 * j, y + 2 * (kz - j), e) - 1;
+        t += (double)binom(kz, j) * (double)cr[src];
+      });
+      base = (kz & 1) ? -t : t;
+    } else {
+      base = (double)cr[a];
     }
-    out[a] = (T)((double)out[a] + sg[P + 1 + deg] * s);
+    double sh = 0.0;
+    static_for<0, P - deg + 1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int src = midx(x + (AX == 0 ? k : 0), y + (AX == 1 ? k : 0), z + (AX == 2 ? k : 0)) - 1;
+      sh = fma(gs[k], (double)pr[src], sh);
+    });
+    res[a - C0] = (T)(base + W.r[deg] * sh);
+  });
+}
+
+// Eq.(taylorshift) from level l to l+1 along the halved axis AX, one block per
+// l2l_rows() consecutive (child cell, configuration) rows.  The child rows
+// (contiguous) and each one's parent row are read with coalesced vector loads
+// into LDS (rows padded to an odd stride), each thread forms one share of one
+// row's coefficients with compile-time indices, and the finished rows go back
+// through LDS with coalesced stores.
+template <typename T, int P, bool FOLDED, int AX>
+__global__ void __launch_bounds__(kL2LThreads) k_l2l(int64_t nitems, const int32_t* __restrict__ parent,
+                                                     const int32_t* __restrict__ key, TaylorW W, int nb,
+                                                     const T* __restrict__ Vp, T* __restrict__ Vc) {
+  using V4 = RowVec4<T>;
+  constexpr int NP = nact(P), NS = nstride(P), NQ = NS / 4, LS = NS + 1;
+  constexpr int R = l2l_rows<T>();
+  constexpr int CH = kL2LThreads / R;     // shares of a row
+  constexpr int CW = (NP + CH - 1) / CH;  // coefficients per share
+  constexpr int QU = (R * NQ + kL2LThreads - 1) / kL2LThreads;  // vector loads per thread and row kind
+  __shared__ T sp[R * LS], sc[R * LS];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * R;
+  const int nr = (int)(nitems - i0 < R ? nitems - i0 : R);
+  // row i0 + r is (cell c0 + (b0 + r) / nb, configuration (b0 + r) % nb)
+  const int64_t c0 = i0 / nb;
+  const int b0 = (int)(i0 - c0 * nb);
+  const V4* cin = reinterpret_cast<const V4*>(Vc + i0 * NS);
+  V4 cv[QU], pv[QU];
+#pragma unroll
+  for (int u = 0; u < QU; u++) {
+    const int q = tid + u * kL2LThreads;
+    if (q < nr * NQ) {
+      const int t = b0 + q / NQ, dc = t / nb;
+      const int64_t prow = (int64_t)parent[c0 + dc] * nb + (t - dc * nb);
+      cv[u] = cin[q];
+      pv[u] = reinterpret_cast<const V4*>(Vp + prow * NS)[q % NQ];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < QU; u++) {
+    const int q = tid + u * kL2LThreads;
+    if (q < nr * NQ) {
+      const int o = (q / NQ) * LS + 4 * (q % NQ);
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        sc[o + e] = cv[u][e];
+        sp[o + e] = pv[u][e];
+      }
+    }
+  }
+  __syncthreads();
+  const int r = tid % R, share = tid / R;
+  T res[CW];
+  if (r < nr) {
+    const int64_t c = c0 + (b0 + r) / nb;
+    const bool neg = (key[c] & 1) == 0;  // the child at -gamma
+    double gs[P + 1];
+#pragma unroll
+    for (int k = 0; k <= P; k++) gs[k] = (neg && (k & 1)) ? -W.g[k] : W.g[k];
+    const T* pr = sp + r * LS;
+    const T* cr = sc + r * LS;
+    static_for<0, CH>([&](auto hc) {
+      constexpr int h = decltype(hc)::value;
+      if (share == h) l2l_coefs<T, P, FOLDED, AX, h * CW, (h + 1) * CW < NP ? (h + 1) * CW : NP>(pr, cr, gs, W, res);
+    });
+  }
+  __syncthreads();
+  if (r < nr) {
+#pragma unroll
+    for (int i = 0; i < CW; i++) {
+      const int a = share * CW + i;
+      if (a < NP) sp[r * LS + a] = res[i];
+    }
+    if (share == 0)
+      for (int a = NP; a < NS; a++) sp[r * LS + a] = (T)0;
+  }
+  __syncthreads();
+  V4* cout = reinterpret_cast<V4*>(Vc + i0 * NS);
+  for (int q = tid; q < nr * NQ; q += kL2LThreads) {
+    const T* d = sp + (q / NQ) * LS + 4 * (q % NQ);
+    cout[q] = V4{d[0], d[1], d[2], d[3]};
   }
 }
 
@@ -579,6 +693,18 @@ static void m2m_impl(Plan& P, int nb, hipStream_t st) {
   }
 }
 
+template <typename T, int PP, bool FOLDED>
+static void l2l_level(int axis, int64_t nitems, const int32_t* parent, const int32_t* key, const TaylorW& W, int nb,
+                      const T* Vp, T* Vc, hipStream_t st) {
+  const unsigned grid = (unsigned)ceil_div(nitems, l2l_rows<T>());
+  if (axis == 0)
+    k_l2l<T, PP, FOLDED, 0><<<grid, kL2LThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
+  else if (axis == 1)
+    k_l2l<T, PP, FOLDED, 1><<<grid, kL2LThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
+  else
+    k_l2l<T, PP, FOLDED, 2><<<grid, kL2LThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
+}
+
 template <typename T, int PP>
 static void l2l_impl(Plan& P, int nb, hipStream_t st) {
   for (int l = 1; l < P.L; l++) {
@@ -587,9 +713,14 @@ static void l2l_impl(Plan& P, int nb, hipStream_t st) {
     const double gam = 0.5 * P.geo.lev[l + 1].h[a] / P.geo.lev[l].s;
     const double rho = P.geo.lev[l + 1].s / P.geo.lev[l].s;
     const int64_t nt = (int64_t)C.ncells * nb;
-    k_l2l<T, PP><<<ceil_div(nt, kShiftWaves), 64 * kShiftWaves, 0, st>>>(C.ncells, C.parent.as<int32_t>(), C.key.as<int32_t>(), a,
-                                                    l2l_weights(gam, rho, PP), nb, qptr<T>(P, P.V, l),
-                                                    qptr<T>(P, P.V, l + 1));
+    if (nt == 0) continue;
+    const TaylorW W = l2l_weights(gam, rho, PP);
+    if (P.v_folded)
+      l2l_level<T, PP, true>(a, nt, C.parent.as<int32_t>(), C.key.as<int32_t>(), W, nb, qptr<T>(P, P.V, l),
+                             qptr<T>(P, P.V, l + 1), st);
+    else
+      l2l_level<T, PP, false>(a, nt, C.parent.as<int32_t>(), C.key.as<int32_t>(), W, nb, qptr<T>(P, P.V, l),
+                              qptr<T>(P, P.V, l + 1), st);
     CCFMM_HIP(hipGetLastError());
   }
 }

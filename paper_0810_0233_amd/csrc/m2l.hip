@@ -437,7 +437,9 @@ __global__ void k_fold_moments(int64_t rows, const T* __restrict__ Q, T* __restr
 }
 
 // The n_z >= 2 components of local expansions whose n_z <= 1 components the
-// traceless M2L wrote (lowest z first); padding positions set to zero.
+// traceless M2L wrote (lowest z first); padding positions set to zero.  Runs
+// on the rows of levels 0 and 1 (the first parents of L2L); L2L forms the same
+// components of every deeper level.
 template <typename T, int P>
 __global__ void k_fill_locals(int64_t rows, T* __restrict__ V) {
   using V4 = typename Vec4<T>::type;
@@ -565,7 +567,8 @@ void build_wide_ops(Plan& P, hipStream_t st) {
 }
 
 // RED: the traceless form (Q holds the folded moments, nred_stride(P) per
-// row; only the n_z <= 1 rows of V are written, k_fill_locals does the rest).
+// row; only the n_z <= 1 rows of V are written: k_fill_locals completes levels
+// 0 and 1, L2L the deeper levels).
 // Share of a full-order M2L tile's work that a tile of smallest cells of
 // order q takes in the wide traceless kernels: the matrix-core row blocks its
 // rows need (a tile needing the vector-unit rows takes the full form).
@@ -826,6 +829,7 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
   LevelOffsets lo{};
   for (int l = 0; l <= P.L; l++) lo.qoff[l] = P.lev[l]->qoff;
   const T* D = std::is_same<T, double>::value ? (const T*)P.Dd.p : (const T*)P.Df.p;
+  P.v_folded = false;
   if (P.ntiles == 0) return;
   constexpr bool kFP64 = std::is_same<T, double>::value;
   if constexpr (PP <= 8) {
@@ -863,8 +867,12 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
 #undef CCFMM_WIDE
       CCFMM_HIP(hipGetLastError());
       if (red) {
-        k_fill_locals<T, PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.V.as<T>());
+        // levels 0 and 1 completed here; L2L completes each deeper level as it
+        // adds the parent's shifted expansion (one pass over those rows)
+        const int64_t top = P.L >= 2 ? P.lev[2]->qoff / nstride(PP) : rows;
+        k_fill_locals<T, PP><<<ceil_div(top, 256), 256, 0, st>>>(top, P.V.as<T>());
         CCFMM_HIP(hipGetLastError());
+        P.v_folded = P.L >= 2;
       }
       return;
     }

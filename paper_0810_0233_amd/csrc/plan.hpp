@@ -88,6 +88,9 @@ struct Plan {
   // M2L tiles
   int TB = 64, TC = 1, ncg = 1;  // configs per tile, targets per tile, config groups
   int m2l_variant = kM2LBlock;    // kernel used by run_m2l
+  // the last M2L left the local rows of levels >= 2 folded (their n_z <= 1
+  // components only); L2L completes them
+  bool v_folded = false;
   int tiles_variant = -1, tiles_class_bits = -1;  // what the current tiles were built for
   DevBuf tiles, tile_tgt, step_delta, step_src, bitmap, gcount;
   DevBuf tile_order;  // launch order of the M2L tiles: longest step list first (+ sort temporaries)
