@@ -364,107 +364,204 @@ static ShiftW m2m_weights(double gam, double rho, int p) {
   return W;
 }
 
-// Along the halved axis the shift acts on lines of coefficients: the two
-// other components (u, v) of n fixed, n_a = t running over 0..p-u-v.  One
-// lane per (line, configuration): Q_n(P) at n_a = t sums the children's
-// Q at n_a = t - k, k = 0..t, so a lane needs no per-term index search and
-// every lane of a line runs the same loop.  A wavefront takes LPW = 64 / lines
-// configurations of one parent cell; rows move through LDS whole (coalesced).
-constexpr int kShiftWaves = 4;
-
-// line l (0 .. (p+1)(p+2)/2 - 1) -> the two other components (u, v), by u + v
-__device__ __forceinline__ void line_uv(int l, int& u, int& v) {
-  int q = 0;
-  while (l > q) {
-    l -= q + 1;
-    q++;
-  }
-  u = q - l;
-  v = l;
+// Multi-index (x, y, z) of coefficient f in the graded order of midx, at
+// compile time: degree d, then s = y + z and z from f - ncoef(d - 1) =
+// s (s + 1) / 2 + z.
+constexpr int mi_deg(int f) {
+  int d = 0;
+  while (ncoef(d) <= f) d++;
+  return d;
 }
-// active index of the multi-index with component t on axis ax and (u, v) on
-// the other two (in x, y, z order)
-__device__ __forceinline__ int line_index(int ax, int u, int v, int t) {
-  return ax == 0 ? midx(t, u, v) - 1 : ax == 1 ? midx(u, t, v) - 1 : midx(u, v, t) - 1;
+constexpr int mi_s(int f) {
+  const int r = f - ncoef(mi_deg(f) - 1);
+  int s = 0;
+  while ((s + 1) * (s + 2) / 2 <= r) s++;
+  return s;
 }
-template <int P>
-constexpr int shift_lines() {
-  return (P + 1) * (P + 2) / 2;
+constexpr int mi_z(int f) { return f - ncoef(mi_deg(f) - 1) - mi_s(f) * (mi_s(f) + 1) / 2; }
+constexpr int mi_x(int f) { return mi_deg(f) - mi_s(f); }
+constexpr int mi_y(int f) { return mi_s(f) - mi_z(f); }
+// i-th f with f_z <= 1 (the traceless rows' order)
+constexpr int red_full(int i) {
+  int f = 1;
+  for (;; f++)
+    if (mi_z(f) <= 1 && i-- == 0) return f;
 }
-template <int P>
-constexpr int shift_cpw() {
-  return 64 / shift_lines<P>() >= 1 ? 64 / shift_lines<P>() : 1;
+constexpr int binom(int n, int k) {
+  int r = 1;
+  for (int i = 0; i < k; i++) r = r * (n - i) / (i + 1);
+  return r;
 }
 
-template <typename T, int P>
-__global__ void __launch_bounds__(64 * kShiftWaves) k_m2m(int32_t ncells, const int32_t* __restrict__ child, int axis,
-                                                          ShiftW W, int nb, const T* __restrict__ Qc,
-                                                          T* __restrict__ Qp) {
-  constexpr int NP = nact(P);
-  constexpr int NS = nstride(P);
-  constexpr int NL = shift_lines<P>();
-  constexpr int CPW = shift_cpw<P>();
-  __shared__ double sw[(P + 1) * (P + 1)];  // the weights, read at per-lane indices
-  __shared__ T sq[kShiftWaves][CPW][2][NS];
-  __shared__ T so[kShiftWaves][CPW][NS];
-  for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += blockDim.x) sw[i] = W.w[i / (P + 1)][i % (P + 1)];
-  __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ngrp = (nb + CPW - 1) / CPW;
-  const int64_t item = (int64_t)blockIdx.x * kShiftWaves + w;
-  if (item >= (int64_t)ncells * ngrp) return;
-  const int c = (int)(item / ngrp), b0 = (int)(item % ngrp) * CPW;
-  const int nbg = min(CPW, nb - b0);
-  const int ch[2] = {child[2 * c], child[2 * c + 1]};
-  for (int i = lane; i < nbg * 2 * NS; i += 64) {  // an absent child reads as a zero row
-    const int cf = i / (2 * NS), e = (i / NS) & 1, a = i % NS;
-    sq[w][cf][e][a] = ch[e] >= 0 ? Qc[((int64_t)ch[e] * nb + b0 + cf) * NS + a] : (T)0;
+template <int A, int B, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (A < B) {
+    f(std::integral_constant<int, A>{});
+    static_for<A + 1, B>(f);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int cf = lane / NL;
-  if (cf < nbg) {
-    int u, v;
-    line_uv(lane % NL, u, v);
-    const int q = u + v;
-    // the line of both children in registers (zero past its end and at the
-    // monopole), read together; then every loop below is unrolled with the
-    // line's bounds as predicates
-    double x0[P + 1], x1[P + 1];
-#pragma unroll
-    for (int j = 0; j <= P; j++) {
-      const bool ok = j <= P - q && j + q >= 1;
-      const int idx = ok ? line_index(axis, u, v, j) : 0;
-      x0[j] = ok ? (double)sq[w][cf][0][idx] : 0.0;
-      x1[j] = ok ? (double)sq[w][cf][1][idx] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t <= P; t++) {
-      if (t <= P - q && t + q >= 1) {
-        double s = 0.0;
-#pragma unroll
-        for (int e = 0; e < 2; e++) {
-#pragma unroll
-          for (int k = 0; k <= t; k++) {
-            const int j = t - k;  // the child's component on the axis; its degree is j + q
-            if (j + q >= 1) {     // (Q_0 = 0: no monopole term)
-              const double wv = sw[k * (P + 1) + j + q];
-              const double wk = (e == 0 && (k & 1)) ? -wv : wv;
-              s += wk * (e == 0 ? x0[j] : x1[j]);
-            }
-          }
+}
+
+typedef float l2l_f4 __attribute__((ext_vector_type(4)));
+typedef double l2l_d4 __attribute__((ext_vector_type(4)));
+template <typename T>
+using RowVec4 = typename std::conditional<std::is_same<T, float>::value, l2l_f4, l2l_d4>::type;
+
+// Expansion rows per M2M and L2L block: two rows of LDS per row (the two
+// children, or parent and child), 43.5 KB at order 6 in either precision
+constexpr int kShiftThreads = 256;
+template <typename T>
+constexpr int shift_rows() {
+  return sizeof(T) == 4 ? 64 : 32;
+}
+
+// The two child rows of every parent row are read with coalesced vector loads
+// into LDS (rows padded to an odd stride); each thread forms one share of one
+// parent row's coefficients with compile-time indices, and the rows go back
+// through LDS with coalesced stores.
+// FOLD: the children's folded (traceless-form) rows, which the wide M2L
+// kernels read, are written from the same LDS rows.  Moving each moment with
+// q_z >= 2 onto q - 2e_z + 2e_x and q - 2e_z + 2e_y with a minus sign, highest
+// q_z first, adds (-1)^k C(k, j) Q(x - 2j, y - 2(k - j), e + 2k) onto the
+// position (x, y, e), e <= 1 (the transpose of the local rows' completion).
+template <typename T, int P, int AX, int C0, int C1>
+__device__ __forceinline__ void m2m_coefs(const T* __restrict__ c0r, const T* __restrict__ c1r, const ShiftW& W,
+                                          T* res) {
+  static_for<C0, C1>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    constexpr int f = a + 1, x = mi_x(f), y = mi_y(f), z = mi_z(f), deg = x + y + z;
+    constexpr int na = AX == 0 ? x : AX == 1 ? y : z;
+    double s = 0.0;
+    static_for<0, na + 1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if constexpr (deg - k >= 1) {  // (Q_0 = 0: no monopole term)
+        constexpr int src = midx(x - (AX == 0 ? k : 0), y - (AX == 1 ? k : 0), z - (AX == 2 ? k : 0)) - 1;
+        const double c1 = (double)c1r[src], c0 = (double)c0r[src];  // the child at +gamma, at -gamma
+        s = fma(W.w[k][deg - k], (k & 1) ? c1 - c0 : c1 + c0, s);
+      }
+    });
+    res[a - C0] = (T)s;
+  });
+}
+
+template <typename T, int P, int R0, int R1>
+__device__ __forceinline__ void fold_coefs(const T* __restrict__ q, T* res) {
+  static_for<R0, R1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int f = red_full(i), x = mi_x(f), y = mi_y(f), e = mi_z(f);
+    double s = (double)q[f - 1];
+    static_for<1, (x + y) / 2 + 1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      static_for<0, k + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (x - 2 * j >= 0 && y - 2 * (k - j) >= 0) {
+          constexpr int src = midx(x - 2 * j, y - 2 * (k - j), e + 2 * k) - 1;
+          constexpr double cf = (k & 1) ? -(double)binom(k, j) : (double)binom(k, j);
+          s = fma(cf, (double)q[src], s);
         }
-        so[w][cf][line_index(axis, u, v, t)] = (T)s;
+      });
+    });
+    res[i - R0] = (T)s;
+  });
+}
+
+template <typename T, int P, int AX, bool FOLD>
+__global__ void __launch_bounds__(kShiftThreads) k_m2m(int64_t nitems, const int32_t* __restrict__ child, ShiftW W,
+                                                      int nb, const T* __restrict__ Qc, T* __restrict__ Qp,
+                                                      T* __restrict__ Qrc) {
+  using V4 = RowVec4<T>;
+  constexpr int NP = nact(P), NS = nstride(P), NQ = NS / 4, LS = NS + 1;
+  constexpr int NR = nred(P), NRS = nred_stride(P), NRQ = NRS / 4, LR = NRS + 1;
+  constexpr int R = shift_rows<T>();
+  constexpr int CH = kShiftThreads / R;     // shares of a row
+  constexpr int CW = (NP + CH - 1) / CH;    // parent coefficients per share
+  constexpr int CWR = (NR + CH - 1) / CH;   // folded child coefficients per share
+  constexpr int QU = (2 * R * NQ + kShiftThreads - 1) / kShiftThreads;
+  __shared__ T sc[2 * R * LS];  // child rows 2 r + e of parent row r
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * R;
+  const int nr = (int)(nitems - i0 < R ? nitems - i0 : R);
+  // parent row i0 + r is (cell c0 + (b0 + r) / nb, configuration (b0 + r) % nb)
+  const int64_t c0 = i0 / nb;
+  const int b0 = (int)(i0 - c0 * nb);
+  V4 cv[QU];
+#pragma unroll
+  for (int u = 0; u < QU; u++) {
+    const int q = tid + u * kShiftThreads;
+    if (q < 2 * nr * NQ) {
+      const int row2 = q / NQ, t = b0 + (row2 >> 1), dc = t / nb;
+      const int32_t ch = child[2 * (c0 + dc) + (row2 & 1)];
+      cv[u] = ch >= 0 ? reinterpret_cast<const V4*>(Qc + ((int64_t)ch * nb + (t - dc * nb)) * NS)[q % NQ]
+                      : V4{(T)0, (T)0, (T)0, (T)0};  // an absent child reads as a zero row
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < QU; u++) {
+    const int q = tid + u * kShiftThreads;
+    if (q < 2 * nr * NQ) {
+      T* d = sc + (q / NQ) * LS + 4 * (q % NQ);
+#pragma unroll
+      for (int e = 0; e < 4; e++) d[e] = cv[u][e];
+    }
+  }
+  __syncthreads();
+  const int r = tid % R, share = tid / R;
+  T res[CW];
+  T fr[2][CWR];
+  if (r < nr) {
+    const T* c0r = sc + (2 * r) * LS;
+    const T* c1r = sc + (2 * r + 1) * LS;
+    static_for<0, CH>([&](auto hc) {
+      constexpr int h = decltype(hc)::value;
+      if (share == h) {
+        m2m_coefs<T, P, AX, h * CW, (h + 1) * CW < NP ? (h + 1) * CW : NP>(c0r, c1r, W, res);
+        if constexpr (FOLD) {
+          constexpr int F0 = h * CWR, F1 = (h + 1) * CWR < NR ? (h + 1) * CWR : NR;
+          fold_coefs<T, P, F0, F1>(c0r, fr[0]);
+          fold_coefs<T, P, F0, F1>(c1r, fr[1]);
+        }
+      }
+    });
+  }
+  __syncthreads();
+  if constexpr (FOLD) {
+    // the children's folded rows, stride LR in LDS
+    if (r < nr) {
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+#pragma unroll
+        for (int i = 0; i < CWR; i++) {
+          const int a = share * CWR + i;
+          if (a < NR) sc[(2 * r + e) * LR + a] = fr[e][i];
+        }
+        if (share == 0)
+          for (int a = NR; a < NRS; a++) sc[(2 * r + e) * LR + a] = (T)0;
       }
     }
+    __syncthreads();
+    for (int q = tid; q < 2 * nr * NRQ; q += kShiftThreads) {
+      const int row2 = q / NRQ, t = b0 + (row2 >> 1), dc = t / nb;
+      const int32_t ch = child[2 * (c0 + dc) + (row2 & 1)];
+      if (ch >= 0) {
+        const T* d = sc + row2 * LR + 4 * (q % NRQ);
+        reinterpret_cast<V4*>(Qrc + ((int64_t)ch * nb + (t - dc * nb)) * NRS)[q % NRQ] = V4{d[0], d[1], d[2], d[3]};
+      }
+    }
+    __syncthreads();
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int i = lane; i < nbg * NS; i += 64) {
-    const int f = i / NS, a = i % NS;
-    Qp[((int64_t)c * nb + b0 + f) * NS + a] = a < NP ? so[w][f][a] : (T)0;
+  if (r < nr) {
+#pragma unroll
+    for (int i = 0; i < CW; i++) {
+      const int a = share * CW + i;
+      if (a < NP) sc[r * LS + a] = res[i];
+    }
+    if (share == 0)
+      for (int a = NP; a < NS; a++) sc[r * LS + a] = (T)0;
+  }
+  __syncthreads();
+  V4* out = reinterpret_cast<V4*>(Qp + i0 * NS);
+  for (int q = tid; q < nr * NQ; q += kShiftThreads) {
+    const T* d = sc + (q / NQ) * LS + 4 * (q % NQ);
+    out[q] = V4{d[0], d[1], d[2], d[3]};
   }
 }
 
@@ -491,50 +588,6 @@ static TaylorW l2l_weights(double gam, double rho, int p) {
     W.r[d] = rp;
   }
   return W;
-}
-
-// Multi-index (x, y, z) of coefficient f in the graded order of midx, at
-// compile time: degree d, then s = y + z and z from f - ncoef(d - 1) =
-// s (s + 1) / 2 + z.
-constexpr int mi_deg(int f) {
-  int d = 0;
-  while (ncoef(d) <= f) d++;
-  return d;
-}
-constexpr int mi_s(int f) {
-  const int r = f - ncoef(mi_deg(f) - 1);
-  int s = 0;
-  while ((s + 1) * (s + 2) / 2 <= r) s++;
-  return s;
-}
-constexpr int mi_z(int f) { return f - ncoef(mi_deg(f) - 1) - mi_s(f) * (mi_s(f) + 1) / 2; }
-constexpr int mi_x(int f) { return mi_deg(f) - mi_s(f); }
-constexpr int mi_y(int f) { return mi_s(f) - mi_z(f); }
-constexpr int binom(int n, int k) {
-  int r = 1;
-  for (int i = 0; i < k; i++) r = r * (n - i) / (i + 1);
-  return r;
-}
-
-template <int A, int B, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (A < B) {
-    f(std::integral_constant<int, A>{});
-    static_for<A + 1, B>(f);
-  }
-}
-
-typedef float l2l_f4 __attribute__((ext_vector_type(4)));
-typedef double l2l_d4 __attribute__((ext_vector_type(4)));
-template <typename T>
-using RowVec4 = typename std::conditional<std::is_same<T, float>::value, l2l_f4, l2l_d4>::type;
-
-// (child cell, configuration) rows per L2L block: two rows of LDS per row
-// (parent and child), 43.5 KB at order 6 in either precision
-constexpr int kL2LThreads = 256;
-template <typename T>
-constexpr int l2l_rows() {
-  return sizeof(T) == 4 ? 64 : 32;
 }
 
 // Coefficients C0 <= a < C1 of one child row: pr and cr are the parent's and
@@ -581,15 +634,15 @@ __device__ __forceinline__ void l2l_coefs(const T* __restrict__ pr, const T* __r
 // row's coefficients with compile-time indices, and the finished rows go back
 // through LDS with coalesced stores.
 template <typename T, int P, bool FOLDED, int AX>
-__global__ void __launch_bounds__(kL2LThreads) k_l2l(int64_t nitems, const int32_t* __restrict__ parent,
+__global__ void __launch_bounds__(kShiftThreads) k_l2l(int64_t nitems, const int32_t* __restrict__ parent,
                                                      const int32_t* __restrict__ key, TaylorW W, int nb,
                                                      const T* __restrict__ Vp, T* __restrict__ Vc) {
   using V4 = RowVec4<T>;
   constexpr int NP = nact(P), NS = nstride(P), NQ = NS / 4, LS = NS + 1;
-  constexpr int R = l2l_rows<T>();
-  constexpr int CH = kL2LThreads / R;     // shares of a row
+  constexpr int R = shift_rows<T>();
+  constexpr int CH = kShiftThreads / R;     // shares of a row
   constexpr int CW = (NP + CH - 1) / CH;  // coefficients per share
-  constexpr int QU = (R * NQ + kL2LThreads - 1) / kL2LThreads;  // vector loads per thread and row kind
+  constexpr int QU = (R * NQ + kShiftThreads - 1) / kShiftThreads;  // vector loads per thread and row kind
   __shared__ T sp[R * LS], sc[R * LS];
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * R;
@@ -601,7 +654,7 @@ __global__ void __launch_bounds__(kL2LThreads) k_l2l(int64_t nitems, const int32
   V4 cv[QU], pv[QU];
 #pragma unroll
   for (int u = 0; u < QU; u++) {
-    const int q = tid + u * kL2LThreads;
+    const int q = tid + u * kShiftThreads;
     if (q < nr * NQ) {
       const int t = b0 + q / NQ, dc = t / nb;
       const int64_t prow = (int64_t)parent[c0 + dc] * nb + (t - dc * nb);
@@ -611,7 +664,7 @@ __global__ void __launch_bounds__(kL2LThreads) k_l2l(int64_t nitems, const int32
   }
 #pragma unroll
   for (int u = 0; u < QU; u++) {
-    const int q = tid + u * kL2LThreads;
+    const int q = tid + u * kShiftThreads;
     if (q < nr * NQ) {
       const int o = (q / NQ) * LS + 4 * (q % NQ);
 #pragma unroll
@@ -649,7 +702,7 @@ __global__ void __launch_bounds__(kL2LThreads) k_l2l(int64_t nitems, const int32
   }
   __syncthreads();
   V4* cout = reinterpret_cast<V4*>(Vc + i0 * NS);
-  for (int q = tid; q < nr * NQ; q += kL2LThreads) {
+  for (int q = tid; q < nr * NQ; q += kShiftThreads) {
     const T* d = sp + (q / NQ) * LS + 4 * (q % NQ);
     cout[q] = V4{d[0], d[1], d[2], d[3]};
   }
@@ -678,31 +731,52 @@ static void p2m_impl(Plan& P, int nb, const double* d_m, hipStream_t st) {
   CCFMM_HIP(hipGetLastError());
 }
 
+template <typename T, int PP, bool FOLD>
+static void m2m_level(int axis, int64_t nitems, const int32_t* child, const ShiftW& W, int nb, const T* Qc, T* Qp,
+                      T* Qrc, hipStream_t st) {
+  const unsigned grid = (unsigned)ceil_div(nitems, shift_rows<T>());
+  if (axis == 0)
+    k_m2m<T, PP, 0, FOLD><<<grid, kShiftThreads, 0, st>>>(nitems, child, W, nb, Qc, Qp, Qrc);
+  else if (axis == 1)
+    k_m2m<T, PP, 1, FOLD><<<grid, kShiftThreads, 0, st>>>(nitems, child, W, nb, Qc, Qp, Qrc);
+  else
+    k_m2m<T, PP, 2, FOLD><<<grid, kShiftThreads, 0, st>>>(nitems, child, W, nb, Qc, Qp, Qrc);
+}
+
 template <typename T, int PP>
 static void m2m_impl(Plan& P, int nb, hipStream_t st) {
+  // the wide traceless M2L kernels read folded moments: M2M writes those of
+  // levels >= 2 (every child it reads), the M2L pass folds levels 0 and 1
+  const bool fold = P.prm.m2l_traceless && PP <= wide_max_order(true) && P.L >= 2;
   for (int l = P.L - 1; l >= 1; l--) {
     const LevelData& D = *P.lev[l];
     const int a = P.geo.lev[l + 1].axis;
     const double gam = 0.5 * P.geo.lev[l + 1].h[a] / P.geo.lev[l].s;
     const double rho = P.geo.lev[l + 1].s / P.geo.lev[l].s;
-    const int64_t nt = (int64_t)D.ncells * ceil_div(nb, shift_cpw<PP>());
-    k_m2m<T, PP><<<ceil_div(nt, kShiftWaves), 64 * kShiftWaves, 0, st>>>(D.ncells, D.child.as<int32_t>(), a,
-                                                                          m2m_weights(gam, rho, PP), nb,
-                                                    qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l));
+    const int64_t nt = (int64_t)D.ncells * nb;
+    if (nt == 0) continue;
+    const ShiftW W = m2m_weights(gam, rho, PP);
+    if (fold)
+      m2m_level<T, PP, true>(a, nt, D.child.as<int32_t>(), W, nb, qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l),
+                                 P.Qr.as<T>() + P.lev[l + 1]->qoff / nstride(PP) * nred_stride(PP), st);
+    else
+      m2m_level<T, PP, false>(a, nt, D.child.as<int32_t>(), W, nb, qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l),
+                              nullptr, st);
     CCFMM_HIP(hipGetLastError());
   }
+  P.q_folded = fold;
 }
 
 template <typename T, int PP, bool FOLDED>
 static void l2l_level(int axis, int64_t nitems, const int32_t* parent, const int32_t* key, const TaylorW& W, int nb,
                       const T* Vp, T* Vc, hipStream_t st) {
-  const unsigned grid = (unsigned)ceil_div(nitems, l2l_rows<T>());
+  const unsigned grid = (unsigned)ceil_div(nitems, shift_rows<T>());
   if (axis == 0)
-    k_l2l<T, PP, FOLDED, 0><<<grid, kL2LThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
+    k_l2l<T, PP, FOLDED, 0><<<grid, kShiftThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
   else if (axis == 1)
-    k_l2l<T, PP, FOLDED, 1><<<grid, kL2LThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
+    k_l2l<T, PP, FOLDED, 1><<<grid, kShiftThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
   else
-    k_l2l<T, PP, FOLDED, 2><<<grid, kL2LThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
+    k_l2l<T, PP, FOLDED, 2><<<grid, kShiftThreads, 0, st>>>(nitems, parent, key, W, nb, Vp, Vc);
 }
 
 template <typename T, int PP>

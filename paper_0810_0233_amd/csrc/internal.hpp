@@ -66,6 +66,10 @@ __host__ __device__ constexpr int midx(int a, int b, int c) {
 // active coefficients of order p, and the padded stride of one expansion
 __host__ __device__ constexpr int nact(int p) { return ncoef(p) - 1; }
 __host__ __device__ constexpr int nstride(int p) { return (nact(p) + 3) & ~3; }
+// traceless (folded) rows: the n_z <= 1 components, 2l + 1 of degree l, and
+// their padded stride
+__host__ __device__ constexpr int nred(int p) { return p * (p + 2); }
+__host__ __device__ constexpr int nred_stride(int p) { return (nred(p) + 3) & ~3; }
 // A row of the derivative table: the ncoef(2p) entries D_k of one offset, then
 // one zero (read by the padding entries of the M2L operator)
 __host__ __device__ constexpr int drow_stride(int p) { return ncoef(2 * p) + 1; }

@@ -363,8 +363,6 @@ struct Vec4<double> {
 // degree.  V is harmonic too, so only its n_z <= 1 components need the
 // product; the others follow from V_{m+2e_z} = -V_{m+2e_x} - V_{m+2e_y}
 // (lowest n_z first).  At p = 6 the operator shrinks from 83 x 84 to 48 x 48.
-__host__ __device__ constexpr int nred(int p) { return p * (p + 2); }  // sum over l = 1..p of 2l + 1
-__host__ __device__ constexpr int nred_stride(int p) { return (nred(p) + 3) & ~3; }
 
 // Reduced index r -> full index f (expansion position f - 1): the f with
 // f_z <= 1 in increasing order.  The multi-indices are graded by degree, so
@@ -401,7 +399,8 @@ struct FoldTable {
 };
 
 // Folded moments Qr[row][nred_stride(P)] from the full moments (one thread per
-// expansion row).
+// expansion row): the rows of levels 0 and 1 after M2M wrote the deeper levels'
+// folded rows, or every row.
 template <typename T, int P>
 __global__ void k_fold_moments(int64_t rows, const T* __restrict__ Q, T* __restrict__ Qr) {
   using V4 = typename Vec4<T>::type;
@@ -839,7 +838,9 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
       const unsigned nblk = (unsigned)P.ntiles;
       const int64_t rows = P.qv_elems / nstride(PP);
       if (red) {
-        k_fold_moments<T, PP><<<ceil_div(rows, 256), 256, 0, st>>>(rows, P.Q.as<T>(), P.Qr.as<T>());
+        // levels 0 and 1 folded here when M2M folded the deeper ones
+        const int64_t ftop = P.q_folded ? P.lev[2]->qoff / nstride(PP) : rows;
+        k_fold_moments<T, PP><<<ceil_div(ftop, 256), 256, 0, st>>>(ftop, P.Q.as<T>(), P.Qr.as<T>());
         CCFMM_HIP(hipGetLastError());
       }
 #define CCFMM_WIDE(CB, RED)                                                                                          \

@@ -91,6 +91,9 @@ struct Plan {
   // the last M2L left the local rows of levels >= 2 folded (their n_z <= 1
   // components only); L2L completes them
   bool v_folded = false;
+  // the last M2M wrote the folded moments of levels >= 2 (the M2L pass folds
+  // levels 0 and 1)
+  bool q_folded = false;
   int tiles_variant = -1, tiles_class_bits = -1;  // what the current tiles were built for
   DevBuf tiles, tile_tgt, step_delta, step_src, bitmap, gcount;
   DevBuf tile_order;  // launch order of the M2L tiles: longest step list first (+ sort temporaries)
