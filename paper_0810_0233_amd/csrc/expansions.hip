@@ -565,6 +565,112 @@ __global__ void __launch_bounds__(kShiftThreads) k_m2m(int64_t nitems, const int
   }
 }
 
+// The form beside the near field (few registers, one wavefront per parent and
+// group of configurations; it fits beside the near field's waves where the
+// LDS-staged form above waits for room).  Along the halved axis the shift acts
+// on lines of coefficients: the two other components (u, v) of n fixed, n_a = t running over 0..p-u-v.  One
+// lane per (line, configuration): Q_n(P) at n_a = t sums the children's
+// Q at n_a = t - k, k = 0..t, so a lane needs no per-term index search and
+// every lane of a line runs the same loop.  A wavefront takes LPW = 64 / lines
+// configurations of one parent cell; rows move through LDS whole (coalesced).
+constexpr int kShiftWaves = 4;
+
+// line l (0 .. (p+1)(p+2)/2 - 1) -> the two other components (u, v), by u + v
+__device__ __forceinline__ void line_uv(int l, int& u, int& v) {
+  int q = 0;
+  while (l > q) {
+    l -= q + 1;
+    q++;
+  }
+  u = q - l;
+  v = l;
+}
+// active index of the multi-index with component t on axis ax and (u, v) on
+// the other two (in x, y, z order)
+__device__ __forceinline__ int line_index(int ax, int u, int v, int t) {
+  return ax == 0 ? midx(t, u, v) - 1 : ax == 1 ? midx(u, t, v) - 1 : midx(u, v, t) - 1;
+}
+template <int P>
+constexpr int shift_lines() {
+  return (P + 1) * (P + 2) / 2;
+}
+template <int P>
+constexpr int shift_cpw() {
+  return 64 / shift_lines<P>() >= 1 ? 64 / shift_lines<P>() : 1;
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(64 * kShiftWaves) k_m2m_lines(int32_t ncells, const int32_t* __restrict__ child, int axis,
+                                                          ShiftW W, int nb, const T* __restrict__ Qc,
+                                                          T* __restrict__ Qp) {
+  constexpr int NP = nact(P);
+  constexpr int NS = nstride(P);
+  constexpr int NL = shift_lines<P>();
+  constexpr int CPW = shift_cpw<P>();
+  __shared__ double sw[(P + 1) * (P + 1)];  // the weights, read at per-lane indices
+  __shared__ T sq[kShiftWaves][CPW][2][NS];
+  __shared__ T so[kShiftWaves][CPW][NS];
+  for (int i = threadIdx.x; i < (P + 1) * (P + 1); i += blockDim.x) sw[i] = W.w[i / (P + 1)][i % (P + 1)];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ngrp = (nb + CPW - 1) / CPW;
+  const int64_t item = (int64_t)blockIdx.x * kShiftWaves + w;
+  if (item >= (int64_t)ncells * ngrp) return;
+  const int c = (int)(item / ngrp), b0 = (int)(item % ngrp) * CPW;
+  const int nbg = min(CPW, nb - b0);
+  const int ch[2] = {child[2 * c], child[2 * c + 1]};
+  for (int i = lane; i < nbg * 2 * NS; i += 64) {  // an absent child reads as a zero row
+    const int cf = i / (2 * NS), e = (i / NS) & 1, a = i % NS;
+    sq[w][cf][e][a] = ch[e] >= 0 ? Qc[((int64_t)ch[e] * nb + b0 + cf) * NS + a] : (T)0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int cf = lane / NL;
+  if (cf < nbg) {
+    int u, v;
+    line_uv(lane % NL, u, v);
+    const int q = u + v;
+    // the line of both children in registers (zero past its end and at the
+    // monopole), read together; then every loop below is unrolled with the
+    // line's bounds as predicates
+    double x0[P + 1], x1[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; j++) {
+      const bool ok = j <= P - q && j + q >= 1;
+      const int idx = ok ? line_index(axis, u, v, j) : 0;
+      x0[j] = ok ? (double)sq[w][cf][0][idx] : 0.0;
+      x1[j] = ok ? (double)sq[w][cf][1][idx] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t <= P; t++) {
+      if (t <= P - q && t + q >= 1) {
+        double s = 0.0;
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+#pragma unroll
+          for (int k = 0; k <= t; k++) {
+            const int j = t - k;  // the child's component on the axis; its degree is j + q
+            if (j + q >= 1) {     // (Q_0 = 0: no monopole term)
+              const double wv = sw[k * (P + 1) + j + q];
+              const double wk = (e == 0 && (k & 1)) ? -wv : wv;
+              s += wk * (e == 0 ? x0[j] : x1[j]);
+            }
+          }
+        }
+        so[w][cf][line_index(axis, u, v, t)] = (T)s;
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int i = lane; i < nbg * NS; i += 64) {
+    const int f = i / NS, a = i % NS;
+    Qp[((int64_t)c * nb + b0 + f) * NS + a] = a < NP ? so[w][f][a] : (T)0;
+  }
+}
+
 // ------------------------------------------------------------ L2L
 // Eq.(taylorshift) from level l to l+1 along the halved axis:
 // Vt_n(C) += sum_k gamma^k/k! rho^(|n|+2) Vt_{n+k e_a}(P).  Tabulated on the
@@ -708,6 +814,55 @@ __global__ void __launch_bounds__(kShiftThreads) k_l2l(int64_t nitems, const int
   }
 }
 
+// The form beside the near field (few registers; the local rows arrive
+// complete): one wavefront per (child cell, configuration), the parent's row
+// read whole (coalesced) into LDS, then each lane adds its coefficients.  (The
+// line form of M2M measured slower here: a child's row is read and written
+// besides the parent's, and each line has half the terms.)
+template <typename T, int P>
+__global__ void __launch_bounds__(64 * kShiftWaves) k_l2l_lanes(int32_t ncells, const int32_t* __restrict__ parent,
+                                                          const int32_t* __restrict__ key, int axis, TaylorW W,
+                                                          int nb, const T* __restrict__ Vp, T* __restrict__ Vc) {
+  constexpr int NP = nact(P);
+  constexpr int NS = nstride(P);
+  constexpr int NR = (NS + 63) / 64;
+  __shared__ T sv[kShiftWaves][NS];
+  __shared__ double sg[2 * (P + 1)];  // the weights, read at per-lane indices
+  for (int i = threadIdx.x; i < 2 * (P + 1); i += blockDim.x) sg[i] = i <= P ? W.g[i] : W.r[i - (P + 1)];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * kShiftWaves + w;
+  if (item >= (int64_t)ncells * nb) return;
+  const int c = (int)(item / nb), b = (int)(item % nb);
+  const T* vp = Vp + ((int64_t)parent[c] * nb + b) * NS;
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int a = lane + 64 * r;
+    if (a < NS) sv[w][a] = vp[a];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const bool neg = (key[c] & 1) == 0;  // the child at -gamma
+  T* out = Vc + item * NS;
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int a = lane + 64 * r;
+    if (a >= NP) continue;
+    const int f = a + 1;
+    const int n[3] = {kMI.x[f], kMI.y[f], kMI.z[f]};
+    const int deg = n[0] + n[1] + n[2];
+    double s = 0.0;
+    for (int k = 0; deg + k <= P; k++) {
+      int m[3] = {n[0], n[1], n[2]};
+      m[axis] += k;
+      const double gk = (neg && (k & 1)) ? -sg[k] : sg[k];
+      s += gk * (double)sv[w][midx(m[0], m[1], m[2]) - 1];
+    }
+    out[a] = (T)((double)out[a] + sg[P + 1 + deg] * s);
+  }
+}
+
 // ------------------------------------------------------------ launchers
 template <typename T>
 static T* qptr(Plan& P, DevBuf& buf, int l) {
@@ -745,20 +900,28 @@ static void m2m_level(int axis, int64_t nitems, const int32_t* child, const Shif
 
 template <typename T, int PP>
 static void m2m_impl(Plan& P, int nb, hipStream_t st) {
-  // the wide traceless M2L kernels read folded moments: M2M writes those of
-  // levels >= 2 (every child it reads), the M2L pass folds levels 0 and 1
-  const bool fold = P.prm.m2l_traceless && PP <= wide_max_order(true) && P.L >= 2;
+  const bool staged = shifts_staged(P);
+  // the wide traceless M2L kernels read folded moments: the staged M2M writes
+  // those of levels >= 2 (every child it reads), the M2L pass folds the rest
+  const bool fold = staged && P.prm.m2l_traceless && PP <= wide_max_order(true) && P.L >= 2;
   for (int l = P.L - 1; l >= 1; l--) {
     const LevelData& D = *P.lev[l];
     const int a = P.geo.lev[l + 1].axis;
     const double gam = 0.5 * P.geo.lev[l + 1].h[a] / P.geo.lev[l].s;
     const double rho = P.geo.lev[l + 1].s / P.geo.lev[l].s;
+    const ShiftW W = m2m_weights(gam, rho, PP);
+    if (!staged) {
+      const int64_t nt = (int64_t)D.ncells * ceil_div(nb, shift_cpw<PP>());
+      k_m2m_lines<T, PP><<<ceil_div(nt, kShiftWaves), 64 * kShiftWaves, 0, st>>>(
+          D.ncells, D.child.as<int32_t>(), a, W, nb, qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l));
+      CCFMM_HIP(hipGetLastError());
+      continue;
+    }
     const int64_t nt = (int64_t)D.ncells * nb;
     if (nt == 0) continue;
-    const ShiftW W = m2m_weights(gam, rho, PP);
     if (fold)
       m2m_level<T, PP, true>(a, nt, D.child.as<int32_t>(), W, nb, qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l),
-                                 P.Qr.as<T>() + P.lev[l + 1]->qoff / nstride(PP) * nred_stride(PP), st);
+                             P.Qr.as<T>() + P.lev[l + 1]->qoff / nstride(PP) * nred_stride(PP), st);
     else
       m2m_level<T, PP, false>(a, nt, D.child.as<int32_t>(), W, nb, qptr<T>(P, P.Q, l + 1), qptr<T>(P, P.Q, l),
                               nullptr, st);
@@ -781,6 +944,7 @@ static void l2l_level(int axis, int64_t nitems, const int32_t* parent, const int
 
 template <typename T, int PP>
 static void l2l_impl(Plan& P, int nb, hipStream_t st) {
+  const bool staged = shifts_staged(P);
   for (int l = 1; l < P.L; l++) {
     const LevelData& C = *P.lev[l + 1];
     const int a = P.geo.lev[l + 1].axis;
@@ -789,7 +953,11 @@ static void l2l_impl(Plan& P, int nb, hipStream_t st) {
     const int64_t nt = (int64_t)C.ncells * nb;
     if (nt == 0) continue;
     const TaylorW W = l2l_weights(gam, rho, PP);
-    if (P.v_folded)
+    if (!staged)
+      k_l2l_lanes<T, PP><<<ceil_div(nt, kShiftWaves), 64 * kShiftWaves, 0, st>>>(
+          C.ncells, C.parent.as<int32_t>(), C.key.as<int32_t>(), a, W, nb, qptr<T>(P, P.V, l),
+          qptr<T>(P, P.V, l + 1));
+    else if (P.v_folded)
       l2l_level<T, PP, true>(a, nt, C.parent.as<int32_t>(), C.key.as<int32_t>(), W, nb, qptr<T>(P, P.V, l),
                              qptr<T>(P, P.V, l + 1), st);
     else

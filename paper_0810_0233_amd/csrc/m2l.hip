@@ -870,10 +870,12 @@ static void m2l_impl(Plan& P, int nb, hipStream_t st) {
       if (red) {
         // levels 0 and 1 completed here; L2L completes each deeper level as it
         // adds the parent's shifted expansion (one pass over those rows)
-        const int64_t top = P.L >= 2 ? P.lev[2]->qoff / nstride(PP) : rows;
+        // (the staged L2L only: the form beside the near field takes complete rows)
+        const bool deep = shifts_staged(P) && P.L >= 2;
+        const int64_t top = deep ? P.lev[2]->qoff / nstride(PP) : rows;
         k_fill_locals<T, PP><<<ceil_div(top, 256), 256, 0, st>>>(top, P.V.as<T>());
         CCFMM_HIP(hipGetLastError());
-        P.v_folded = P.L >= 2;
+        P.v_folded = deep;
       }
       return;
     }

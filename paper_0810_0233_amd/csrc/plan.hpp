@@ -170,6 +170,10 @@ void build_p2p_chunks(Plan& P, hipStream_t st);
 // evaluation passes
 void run_p2m(Plan& P, int nb, const double* d_m, hipStream_t st);
 void run_m2m(Plan& P, int nb, hipStream_t st);
+// M2M and L2L in their LDS-staged form (the fastest alone, with the fold and
+// the local rows' completion fused in), or, while the near field runs beside
+// them, the form with few registers that fits beside the near field's waves
+inline bool shifts_staged(const Plan& P) { return !P.overlap; }
 void run_m2l(Plan& P, int nb, hipStream_t st);
 void run_l2l(Plan& P, int nb, hipStream_t st);
 void run_p2p_l2p(Plan& P, int nb, double* d_H, hipStream_t st);  // near + smooth field, one stream

@@ -487,6 +487,32 @@ def test_leaf_rule_occupied_mean(ref, geom):
     pl.destroy()
 
 
+@pytest.mark.parametrize("order", [3, 6, 8])
+def test_shift_forms_agree(ref, order):
+    """M2M and L2L in their two forms: staged through LDS with the moment fold
+    and the completion of the local rows fused in (single-stream evaluations),
+    and the form with few registers beside the near field (overlapped
+    evaluations).  FP64: the two agree to rounding and the staged form equals
+    the oracle FMM; mixed: within the FP32 variant bar; one configuration and
+    three (rows of a block that straddle cells)."""
+    n = 6000
+    pos, box = inputs.ferrofluid(n, 43)
+    for nb in (1, 3):
+        m = np.stack([inputs.random_moments(n, 500 + b) for b in range(nb)])
+        for prec, bar in ((ccfmm.PREC_FP64, 1e-13), (ccfmm.PREC_MIXED, 2e-6)):
+            H = {}
+            for ov in (0, 1):
+                print("case order=%d nb=%d precision=%d overlap_near=%d" % (order, nb, prec, ov), flush=True)
+                pl = plan_for(pos, order, 0.5, 0.0, box, precision=prec, max_batch=nb, overlap_near=ov)
+                H[ov] = pl.eval(m)
+                pl.destroy()
+            e = rel_rms(H[0], H[1])
+            print("order=%d nb=%d precision=%d staged vs beside %.3e" % (order, nb, prec, e), flush=True)
+            assert e <= bar
+            if prec == ccfmm.PREC_FP64 and nb == 1:
+                assert rel_rms(H[0][0], ref.fmm(pos, m[0], order, 0.5, box=box)) <= FP64_BAR
+
+
 @pytest.mark.parametrize("nb", [1, 8, 40])
 def test_overlapped_near_field_equals_single_stream(nb):
     """The near field on the side stream beside the expansion passes (joined
@@ -508,11 +534,13 @@ def test_overlapped_near_field_equals_single_stream(nb):
             pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
             torch.cuda.synchronize()
             res.append(d_H.cpu().numpy().copy())
-        # the timed evaluation runs every pass alone on one stream, with the same field
+        # the timed evaluation runs every pass alone on one stream, with the same
+        # field (the single-stream form's M2M and L2L: FP32 rounding apart from
+        # the overlapped form's)
         t = pl.eval_device_timed(nb, d_m.data_ptr(), d_H.data_ptr(), st)
         torch.cuda.synchronize()
         assert t["p2p"] > 0 and t["total"] > 0
-        assert rel_rms(d_H.cpu().numpy(), res[0]) <= 1e-12
+        assert rel_rms(d_H.cpu().numpy(), res[0]) <= (1e-12 if ov == 0 else 2e-6)
         # and leaves the plan's own (overlapped, graph-replayed) evaluation as it was
         pl.eval_device(nb, d_m.data_ptr(), d_H.data_ptr(), st)
         torch.cuda.synchronize()
@@ -520,7 +548,8 @@ def test_overlapped_near_field_equals_single_stream(nb):
         assert all(np.array_equal(r, res[0]) for r in res[1:])
         out[ov] = res[0]
         pl.destroy()
-    assert rel_rms(out[1], out[0]) <= 1e-12
+    # the two forms run different M2M and L2L kernels: FP32 rounding apart
+    assert rel_rms(out[1], out[0]) <= 2e-6
 
 
 def test_energy_device_matches_oracle(ref):
