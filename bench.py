@@ -127,14 +127,18 @@ def pass_work(info, n, nb, order):
     out = {
         "p2m": {"kernel": "k_permute_moments+k_p2m<float,%d>" % order, "bound": "hbm",
                 "bytes": n * nb * 24.0 + n * 12.0 + leaves * exp_b, "flops": 6.0 * NP * n * nb},
-        "m2m": {"kernel": "k_m2m<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
+        # (the passes are timed on one stream: M2M and L2L in their staged form, one launch per level and halved
+        # axis; M2M also writes the folded moments, L2L completes the local rows)
+        "m2m": {"kernel": "k_m2m<float,%d,axis,true>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b,
+                "flops": 0.0},
         # the method's own M2L products: 2 NP^2 per pair and configuration, NP = (p+1)(p+2)(p+3)/6 - 1 in the
         # full form, p (p + 2) in the traceless form (the fold and fill are per-cell work)
         "m2l": {"kernel": m2l_kernel_name(info["m2l_variant"], order),
                 "bound": "mfma", "bytes": 2.0 * cells * exp_b,
                 "flops": (2.0 * (order * (order + 2)) ** 2 * info["n_m2l_pairs"] * nb
                           if m2l_traceless_active(info["m2l_variant"], order) else info["m2l_flops_per_config"] * nb)},
-        "l2l": {"kernel": "k_l2l<float,%d>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b, "flops": 0.0},
+        "l2l": {"kernel": "k_l2l<float,%d,true,axis>" % order, "bound": "hbm", "bytes": 2.0 * cells * exp_b,
+                "flops": 0.0},
         # each input read once: FP32 position and residual (24 B), moment (12 B per configuration), caller
         # index (4 B), the smallest cells' local expansions when L2P is fused; FP64 field written (24 B)
         "p2p": {"kernel": near_kernel_name(nb, order),
