@@ -487,14 +487,17 @@ def test_leaf_rule_occupied_mean(ref, geom):
     pl.destroy()
 
 
-@pytest.mark.parametrize("order", [3, 6, 8])
-def test_shift_forms_agree(ref, order):
-    """M2M and L2L in their two forms: staged through LDS with the moment fold
-    and the completion of the local rows fused in (single-stream evaluations),
-    and the form with few registers beside the near field (overlapped
-    evaluations).  FP64: the two agree to rounding and the staged form equals
-    the oracle FMM; mixed: within the FP32 variant bar; one configuration and
-    three (rows of a block that straddle cells)."""
+@pytest.mark.parametrize("order,traceless,variant", [(3, 1, ccfmm.M2L_AUTO), (6, 1, ccfmm.M2L_AUTO),
+                                                     (8, 1, ccfmm.M2L_AUTO), (6, 0, ccfmm.M2L_AUTO),
+                                                     (5, 1, ccfmm.M2L_BLOCK)])
+def test_shift_forms_agree(ref, order, traceless, variant):
+    """M2M and L2L in their two forms: staged through LDS (single-stream
+    evaluations; with the wide traceless M2L the moment fold and the
+    completion of the local rows are fused in, with the full operator or the
+    block kernel they are not needed), and the form with few registers beside
+    the near field (overlapped evaluations).  FP64: the two agree to rounding
+    and the staged form equals the oracle FMM; mixed: within the FP32 variant
+    bar; one configuration and three (rows of a block that straddle cells)."""
     n = 6000
     pos, box = inputs.ferrofluid(n, 43)
     for nb in (1, 3):
@@ -502,8 +505,10 @@ def test_shift_forms_agree(ref, order):
         for prec, bar in ((ccfmm.PREC_FP64, 1e-13), (ccfmm.PREC_MIXED, 2e-6)):
             H = {}
             for ov in (0, 1):
-                print("case order=%d nb=%d precision=%d overlap_near=%d" % (order, nb, prec, ov), flush=True)
-                pl = plan_for(pos, order, 0.5, 0.0, box, precision=prec, max_batch=nb, overlap_near=ov)
+                print("case order=%d traceless=%d variant=%d nb=%d precision=%d overlap_near=%d" % (
+                    order, traceless, variant, nb, prec, ov), flush=True)
+                pl = plan_for(pos, order, 0.5, 0.0, box, precision=prec, max_batch=nb, overlap_near=ov,
+                              m2l_traceless=traceless, m2l_variant=variant)
                 H[ov] = pl.eval(m)
                 pl.destroy()
             e = rel_rms(H[0], H[1])
