@@ -401,10 +401,10 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-typedef float l2l_f4 __attribute__((ext_vector_type(4)));
-typedef double l2l_d4 __attribute__((ext_vector_type(4)));
+typedef float shift_f4 __attribute__((ext_vector_type(4)));
+typedef double shift_d4 __attribute__((ext_vector_type(4)));
 template <typename T>
-using RowVec4 = typename std::conditional<std::is_same<T, float>::value, l2l_f4, l2l_d4>::type;
+using RowVec4 = typename std::conditional<std::is_same<T, float>::value, shift_f4, shift_d4>::type;
 
 // Expansion rows per M2M and L2L block: two rows of LDS per row (the two
 // children, or parent and child), 43.5 KB at order 6 in either precision
