@@ -487,7 +487,9 @@ def test_leaf_rule_occupied_mean(ref, geom):
     pl.destroy()
 
 
-@pytest.mark.parametrize("order,traceless,variant", [(3, 1, ccfmm.M2L_AUTO), (6, 1, ccfmm.M2L_AUTO),
+@pytest.mark.parametrize("order,traceless,variant", [(1, 1, ccfmm.M2L_AUTO), (2, 1, ccfmm.M2L_AUTO),
+                                                     (3, 1, ccfmm.M2L_AUTO), (4, 1, ccfmm.M2L_AUTO),
+                                                     (6, 1, ccfmm.M2L_AUTO), (7, 1, ccfmm.M2L_AUTO),
                                                      (8, 1, ccfmm.M2L_AUTO), (6, 0, ccfmm.M2L_AUTO),
                                                      (5, 1, ccfmm.M2L_BLOCK)])
 def test_shift_forms_agree(ref, order, traceless, variant):
