@@ -285,14 +285,17 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
 #pragma unroll
       for (int t = 0; t < NM; t++) mono[w][lane][t] = px[kMI.x[t]] * py[kMI.y[t]] * pz[kMI.z[t]];
     }
-    // the group's moments of these dipoles, one (dipole, configuration) per lane
-    for (int q = lane; q < nchunk * nbg; q += 64) {
-      const int j = q / nbg, c = q - j * nbg;
+    // the group's moments of these dipoles, one (dipole, configuration) per
+    // lane; zeros past the group's last configuration, so the sums below run
+    // over all CG without a test per configuration (those sums are not stored)
+    for (int q = lane; q < nchunk * CG; q += 64) {
+      const int j = q / CG, c = q % CG;
       const int64_t i = first + base + j;
-      const T* mb = msort + (int64_t)(b0 + c) * 3 * n;
-      mm[w][j][c][0] = mb[i];
-      mm[w][j][c][1] = mb[n + i];
-      mm[w][j][c][2] = mb[2 * n + i];
+      const bool ok = c < nbg;
+      const T* mb = msort + (int64_t)(b0 + (ok ? c : 0)) * 3 * n;
+      mm[w][j][c][0] = ok ? mb[i] : (T)0;
+      mm[w][j][c][1] = ok ? mb[n + i] : (T)0;
+      mm[w][j][c][2] = ok ? mb[2 * n + i] : (T)0;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -308,16 +311,14 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
       }
 #pragma unroll
       for (int c = 0; c < CG; c++) {
-        if (c < nbg) {
-          const T m0 = mm[w][j][c][0], m1 = mm[w][j][c][1], m2 = mm[w][j][c][2];
+        const T m0 = mm[w][j][c][0], m1 = mm[w][j][c][1], m2 = mm[w][j][c][2];
 #pragma unroll
-          for (int r = 0; r < NR; r++) {
-            T s = acc[c][r];
-            s += m0 * vx[r];
-            s += m1 * vy[r];
-            s += m2 * vz[r];
-            acc[c][r] = s;
-          }
+        for (int r = 0; r < NR; r++) {
+          T s = acc[c][r];
+          s += m0 * vx[r];
+          s += m1 * vy[r];
+          s += m2 * vz[r];
+          acc[c][r] = s;
         }
       }
     }
