@@ -252,7 +252,8 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
   const int leaf = (int)(item / ngrp), b0 = (int)(item % ngrp) * CG;
   const int nbg = min(CG, nb - b0);
   const int first = lstart[leaf], cnt = lcount[leaf];
-  // source indices of coefficient n - e_a for this lane's coefficients
+  // source indices of coefficient n - e_a for this lane's coefficients (NM,
+  // a slot kept zero, where the term is absent)
   int srcx[NR], srcy[NR], srcz[NR];
   T acc[CG][NR];
 #pragma unroll
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
     const int t = lane + 64 * r + 1;  // flat index, |n| >= 1
 #pragma unroll
     for (int c = 0; c < CG; c++) acc[c][r] = (T)0;
-    srcx[r] = srcy[r] = srcz[r] = -1;
+    srcx[r] = srcy[r] = srcz[r] = NM;
     if (t <= NP) {
       const int x = kMI.x[t], yy = kMI.y[t], z = kMI.z[t];
       if (x > 0) srcx[r] = midx(x - 1, yy, z);
@@ -268,6 +269,7 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
       if (z > 0) srcz[r] = midx(x, yy, z - 1);
     }
   }
+  if (lane < kP2MChunk) mono[w][lane][NM] = (T)0;
   for (int base = 0; base < cnt; base += kP2MChunk) {
     const int nchunk = min(kP2MChunk, cnt - base);
     if (lane < nchunk) {
@@ -305,9 +307,9 @@ __global__ void __launch_bounds__(64 * kP2MWaves) k_p2m(const int32_t* __restric
       T vx[NR], vy[NR], vz[NR];
 #pragma unroll
       for (int r = 0; r < NR; r++) {
-        vx[r] = srcx[r] >= 0 ? mono[w][j][srcx[r]] : (T)0;
-        vy[r] = srcy[r] >= 0 ? mono[w][j][srcy[r]] : (T)0;
-        vz[r] = srcz[r] >= 0 ? mono[w][j][srcz[r]] : (T)0;
+        vx[r] = mono[w][j][srcx[r]];
+        vy[r] = mono[w][j][srcy[r]];
+        vz[r] = mono[w][j][srcz[r]];
       }
 #pragma unroll
       for (int c = 0; c < CG; c++) {
