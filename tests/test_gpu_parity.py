@@ -499,10 +499,12 @@ def test_shift_forms_agree(ref, order, traceless, variant):
     block kernel they are not needed), and the form with few registers beside
     the near field (overlapped evaluations).  FP64: the two agree to rounding
     and the staged form equals the oracle FMM; mixed: within the FP32 variant
-    bar; one configuration and three (rows of a block that straddle cells)."""
+    bar; one configuration, three (rows of a block that straddle cells) and,
+    at order 5, seventy (a cell's rows spread over two blocks)."""
     n = 6000
     pos, box = inputs.ferrofluid(n, 43)
-    for nb in (1, 3):
+    # 70 configurations: a cell's rows span two blocks of either precision
+    for nb in ((1, 3, 70) if order == 5 else (1, 3)):
         m = np.stack([inputs.random_moments(n, 500 + b) for b in range(nb)])
         for prec, bar in ((ccfmm.PREC_FP64, 1e-13), (ccfmm.PREC_MIXED, 2e-6)):
             H = {}
