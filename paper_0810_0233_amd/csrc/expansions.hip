@@ -906,7 +906,9 @@ static void m2m_impl(Plan& P, int nb, hipStream_t st) {
   const bool staged = shifts_staged(P);
   // the wide traceless M2L kernels read folded moments: the staged M2M writes
   // those of levels >= 2 (every child it reads), the M2L pass folds the rest
-  const bool fold = staged && P.prm.m2l_traceless && PP <= wide_max_order(true) && P.L >= 2;
+  // (all of them if M2M did not)
+  const bool wide = P.tiles_variant == kM2LWide4 || P.tiles_variant == kM2LWide2 || P.tiles_variant == kM2LWide1;
+  const bool fold = staged && wide && P.prm.m2l_traceless && PP <= wide_max_order(true) && P.L >= 2;
   for (int l = P.L - 1; l >= 1; l--) {
     const LevelData& D = *P.lev[l];
     const int a = P.geo.lev[l + 1].axis;
