@@ -101,7 +101,9 @@ typedef struct {
   int32_t m2l_traceless;  /* 1 (default): the wide M2L kernels (mixed and FP64) contract folded
                              moments over their 2l+1 components per degree and fill the rest of
                              V from the Laplace equation (D and V are harmonic; the same sums,
-                             rounded differently); 0: the full 83 x 84 operator at p = 6 */
+                             rounded differently; on one stream M2M folds the moments and L2L
+                             completes the local rows as they shift); 0: the full 83 x 84
+                             operator at p = 6 */
   double sel_margin;      /* selector = 1: the choice keeps the predicted global relative RMS
                              error within err_bound x 10^-sel_margin (default 0.3, >= 0);
                              see ccfmm_plan_select */
@@ -197,8 +199,10 @@ int ccfmm_eval(ccfmm_plan plan, int32_t nbatch, const double* m, double* H);
 int ccfmm_eval_device(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H, void* stream);
 /* As ccfmm_eval_device, with HIP events between the passes (synchronises).
  * The passes run one after another on the caller's stream whatever the
- * plan's overlap_near, so each time is that pass alone; below the batched
- * size the near field and L2P are one fused kernel (timed as p2p, l2p 0). */
+ * plan's overlap_near, so each time is that pass alone (M2M and L2L in their
+ * single-stream form, with the moment fold and the completion of the local
+ * rows of the traceless M2L inside them); below the batched size the near
+ * field and L2P are one fused kernel (timed as p2p, l2p 0). */
 int ccfmm_eval_device_timed(ccfmm_plan plan, int32_t nbatch, const double* d_m, double* d_H,
                             void* stream, ccfmm_pass_times* times);
 
